@@ -1,0 +1,169 @@
+"""CPU oracle for the exact greedy permutation (TEST INFRASTRUCTURE ONLY).
+
+Only ``tests/``, ``__graft_entry__.smoke()`` and the CPU-baseline leg of
+``bench.py`` may import this package.  The product library never links or
+calls it, and it shares no code with the HIP path.
+
+The arithmetic lives in ``bs_oracle.c`` (plain C, binary32 without FP
+contraction, compiled here with gcc).  This module only marshals numpy
+arrays through ctypes.  See the C file's header for the passages of the
+paper each function follows (Sec. 3.2 progressive sampling, Sec. 3.3 greedy
+permutation, Sec. 4.1 r-nets) and for the readings taken where the paper is
+silent.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "bs_oracle.c")
+_LIB_PATH = os.path.join(_HERE, "_bs_oracle.so")
+
+# -O2 with contraction off: binary32 ops stay single correctly rounded ops.
+CFLAGS = ["-O2", "-std=c11", "-ffp-contract=off", "-fno-fast-math",
+          "-fPIC", "-shared", "-Wall", "-Wextra"]
+
+_lib = None
+
+
+def build(force: bool = True) -> str:
+    """Compile the oracle with gcc into ``oracle/_bs_oracle.so``."""
+    if force or not os.path.exists(_LIB_PATH):
+        tmp = _LIB_PATH + ".tmp%d" % os.getpid()
+        subprocess.check_call(["gcc", *CFLAGS, "-o", tmp, _SRC, "-lm"])
+        os.replace(tmp, _LIB_PATH)
+    return _LIB_PATH
+
+
+def _bind(path: str):
+    lib = ctypes.CDLL(path)
+    i64, u64 = ctypes.c_int64, ctypes.c_uint64
+    vp = ctypes.c_void_p
+    lib.oracle_splitmix64_first.argtypes = [u64]
+    lib.oracle_splitmix64_first.restype = u64
+    lib.oracle_start_index.argtypes = [u64, i64]
+    lib.oracle_start_index.restype = i64
+    lib.oracle_greedy32.argtypes = [vp, i64, i64, i64, vp, vp, vp, vp, vp]
+    lib.oracle_greedy32.restype = ctypes.c_int
+    lib.oracle_greedy64.argtypes = [vp, i64, i64, i64, vp, vp]
+    lib.oracle_greedy64.restype = ctypes.c_int
+    lib.oracle_along_order64.argtypes = [vp, i64, vp, i64, vp]
+    lib.oracle_along_order64.restype = ctypes.c_int
+    lib.oracle_greedy32_grid.argtypes = [vp, i64, i64, i64, vp, vp, ctypes.c_double, vp]
+    lib.oracle_greedy32_grid.restype = ctypes.c_int
+    return lib
+
+
+def _load():
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(_LIB_PATH) or os.path.getmtime(_LIB_PATH) < os.path.getmtime(_SRC):
+        build(force=True)
+    _lib = _bind(_LIB_PATH)
+    return _lib
+
+
+def _ptr(a):
+    return None if a is None else a.ctypes.data_as(ctypes.c_void_p)
+
+
+def _points32(points) -> np.ndarray:
+    p = np.ascontiguousarray(np.asarray(points, dtype=np.float32))
+    if p.ndim != 2 or p.shape[1] != 3:
+        raise ValueError("points must have shape [n, 3]")
+    return p
+
+
+def splitmix64_first(seed: int, lib=None) -> int:
+    """First SplitMix64 output for ``seed`` (Steele, Lea and Flood 2014)."""
+    return int((lib or _load()).oracle_splitmix64_first(ctypes.c_uint64(seed & (2**64 - 1))))
+
+
+def start_index(seed: int, n: int, lib=None) -> int:
+    """The random starting surfel (Sec. 3.2): SplitMix64(seed) mod n."""
+    return int((lib or _load()).oracle_start_index(ctypes.c_uint64(seed & (2**64 - 1)), n))
+
+
+class OracleError(RuntimeError):
+    pass
+
+
+def _check(rc: int, allow_nonfinite: bool = True):
+    if rc == 0 or (rc == 1 and allow_nonfinite):
+        return rc
+    raise OracleError("oracle returned %d" % rc)
+
+
+def greedy32(points, k: int, start: int, stats: bool = False, lib=None):
+    """Plain binary32 greedy permutation (Sec. 3.2/3.3).
+
+    Returns ``(order int32[k], radius float32[k])`` and, with ``stats``, a
+    dict of per-update arrays ``n_live``, ``n_ball``, ``n_dec`` (length k-1).
+    """
+    p = _points32(points)
+    n = p.shape[0]
+    order = np.empty(max(k, 0), dtype=np.int32)
+    radius = np.empty(max(k, 0), dtype=np.float32)
+    st = {}
+    if stats:
+        for key in ("n_live", "n_ball", "n_dec"):
+            st[key] = np.zeros(max(k - 1, 0), dtype=np.int64)
+    rc = (lib or _load()).oracle_greedy32(_ptr(p), n, k, start, _ptr(order), _ptr(radius),
+                                 _ptr(st.get("n_live")), _ptr(st.get("n_ball")),
+                                 _ptr(st.get("n_dec")))
+    _check(rc)
+    return (order, radius, st) if stats else (order, radius)
+
+
+def greedy32_grid(points, k: int, start: int, target: float = 12.0, stats: bool = False, lib=None):
+    """Exact grid-accelerated binary32 greedy; equal to :func:`greedy32`."""
+    p = _points32(points)
+    n = p.shape[0]
+    order = np.empty(max(k, 0), dtype=np.int32)
+    radius = np.empty(max(k, 0), dtype=np.float32)
+    ball = np.zeros(max(k - 1, 0), dtype=np.int64) if stats else None
+    rc = (lib or _load()).oracle_greedy32_grid(_ptr(p), n, k, start, _ptr(order), _ptr(radius),
+                                      float(target), _ptr(ball))
+    _check(rc)
+    return (order, radius, {"n_ball": ball}) if stats else (order, radius)
+
+
+def greedy64(points, k: int, start: int, lib=None):
+    """The same greedy in binary64 on exactly widened coordinates."""
+    p = np.ascontiguousarray(_points32(points).astype(np.float64))
+    n = p.shape[0]
+    order = np.empty(max(k, 0), dtype=np.int32)
+    radius = np.empty(max(k, 0), dtype=np.float64)
+    _check((lib or _load()).oracle_greedy64(_ptr(p), n, k, start, _ptr(order), _ptr(radius)), False)
+    return order, radius
+
+
+def along_order64(points, order, lib=None) -> np.ndarray:
+    """Binary64 distance of each ``order[t]`` to its nearest earlier pick."""
+    p = _points32(points)
+    o = np.ascontiguousarray(np.asarray(order, dtype=np.int32))
+    r = np.empty(o.shape[0], dtype=np.float64)
+    _check((lib or _load()).oracle_along_order64(_ptr(p), p.shape[0], _ptr(o), o.shape[0], _ptr(r)), False)
+    return r
+
+
+def compile_variant(src_text: str, out_path: str):
+    """Compile a (mutated) copy of the oracle source and bind it.
+
+    Used only by the test that checks that planted mistakes in the oracle
+    are caught by its pins."""
+    c_path = out_path + ".c"
+    with open(c_path, "w") as f:
+        f.write(src_text)
+    subprocess.check_call(["gcc", *CFLAGS, "-o", out_path, c_path, "-lm"])
+    return _bind(out_path)
+
+
+def source_text() -> str:
+    with open(_SRC) as f:
+        return f.read()

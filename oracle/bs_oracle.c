@@ -1,0 +1,470 @@
+/*
+ * bs_oracle.c -- CPU oracle for the exact greedy permutation of surfel
+ * candidates ("Progressive Blue Surfels", Brandt, Jaehn, Fischer and
+ * Meyer auf der Heide, arXiv 1904.08225).
+ *
+ * TEST INFRASTRUCTURE ONLY.  Nothing in the product library links, loads or
+ * calls this file; only the test suite, the package's smoke check and the
+ * benchmark's CPU-baseline leg do.  It shares no code, header, table or
+ * helper with the HIP path.
+ *
+ * What it computes (paper, Sec. 3.2 "Progressive Sampling" and Sec. 3.3):
+ *   The goal sequence is a greedy permutation (farthest-first traversal,
+ *   Related Work paragraph citing Eppstein et al. and Eldar et al.): start
+ *   from a random surfel, then repeatedly append the remaining candidate
+ *   whose distance to all previously chosen surfels is largest, and remove
+ *   it from the candidate set; stop after the desired count or when the set
+ *   is exhausted.  "Distance to all chosen surfels" is read as the distance
+ *   to the NEAREST chosen surfel (max-min, the r-net reading of Sec. 4.1).
+ *
+ * Readings where the paper is silent (each listed in the design notes):
+ *   - arithmetic is IEEE binary32, round to nearest even, no contraction:
+ *       d2(a,b) = ((dx*dx + dy*dy) + dz*dz),  dx = a.x - b.x, ...
+ *     compiled with -ffp-contract=off on SSE2 (no x87 excess precision);
+ *   - the argmax runs on d2 (not on its square root), lowest index wins ties;
+ *   - radius[t] = sqrtf(d2 of order[t] to its nearest earlier pick), the
+ *     covering radius of the t-prefix; radius[0] = +inf;
+ *   - a picked candidate is never picked again, even at distance 0;
+ *   - the random start is the first output of SplitMix64 (Steele, Lea and
+ *     Flood, OOPSLA 2014) seeded with `seed`, reduced modulo n;
+ *   - non-finite coordinates: order[:] = -1, radius[:] = NaN.
+ *
+ * Functions:
+ *   oracle_splitmix64_first  SplitMix64 first output, from its definition.
+ *   oracle_start_index       start = first output mod n.
+ *   oracle_greedy32          plain O(n k) FP32 greedy (the oracle proper).
+ *   oracle_greedy64          the same algorithm in binary64.
+ *   oracle_along_order64     binary64 nearest-earlier distance along a given
+ *                            order (for the FP64 error bound).
+ *   oracle_greedy32_grid     an exact, faster variant of oracle_greedy32 that
+ *                            skips provably unaffected candidates using a
+ *                            uniform grid with a conservative binary64 bound
+ *                            and a max segment tree over cells.  It is pinned
+ *                            bit-exact to oracle_greedy32 by the test suite
+ *                            and exists only so that large inputs can be
+ *                            checked in seconds.
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+#define ORACLE_OK 0
+#define ORACLE_BAD_ARG -1
+#define ORACLE_NO_MEM -2
+#define ORACLE_NONFINITE 1
+
+/* ---------------------------------------------------------------- start */
+
+uint64_t oracle_splitmix64_first(uint64_t seed)
+{
+    /* SplitMix64: state advances by the golden-ratio increment, the output
+     * is the advanced state passed through the variant-13 mix. */
+    uint64_t z = seed + 0x9E3779B97F4A7C15ull;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+}
+
+int64_t oracle_start_index(uint64_t seed, int64_t n)
+{
+    if (n <= 0) return -1;
+    return (int64_t)(oracle_splitmix64_first(seed) % (uint64_t)n);
+}
+
+/* ------------------------------------------------------------ distances */
+
+static float d2_f32(const float* a, const float* b)
+{
+    float dx = a[0] - b[0];
+    float dy = a[1] - b[1];
+    float dz = a[2] - b[2];
+    float xx = dx * dx;
+    float yy = dy * dy;
+    float zz = dz * dz;
+    float s = xx + yy;
+    return s + zz;
+}
+
+static double d2_f64(const double* a, const double* b)
+{
+    double dx = a[0] - b[0];
+    double dy = a[1] - b[1];
+    double dz = a[2] - b[2];
+    return (dx * dx + dy * dy) + dz * dz;
+}
+
+static int all_finite(const float* P, int64_t n)
+{
+    for (int64_t i = 0; i < 3 * n; ++i)
+        if (!isfinite(P[i])) return 0;
+    return 1;
+}
+
+static void fill_nonfinite(int32_t* order, float* radius, int64_t k)
+{
+    for (int64_t t = 0; t < k; ++t) {
+        order[t] = -1;
+        if (radius) radius[t] = NAN;
+    }
+}
+
+/* ------------------------------------------------------ plain FP32 greedy */
+
+/*
+ * Plain greedy permutation in binary32.  P is AoS [n][3].  Writes k entries
+ * of order and (optionally) radius.  Optional per-update statistics, each
+ * of length k-1 (entry u describes the update with the u-th pick, u=0..k-2):
+ *   n_live[u]  live candidates after that pick,
+ *   n_ball[u]  live candidates strictly closer to the pick than the pick's
+ *              own covering radius (d2 < m(pick)),
+ *   n_dec[u]   min-distances that strictly decreased.
+ */
+int oracle_greedy32(const float* P, int64_t n, int64_t k, int64_t start,
+                    int32_t* order, float* radius,
+                    int64_t* n_live, int64_t* n_ball, int64_t* n_dec)
+{
+    if (k == 0) return ORACLE_OK;
+    if (!P || !order || n < 1 || k < 0 || k > n || start < 0 || start >= n)
+        return ORACLE_BAD_ARG;
+    if (!all_finite(P, n)) {
+        fill_nonfinite(order, radius, k);
+        return ORACLE_NONFINITE;
+    }
+    float* m = (float*)malloc(sizeof(float) * (size_t)n);
+    unsigned char* sel = (unsigned char*)calloc((size_t)n, 1);
+    if (!m || !sel) { free(m); free(sel); return ORACLE_NO_MEM; }
+
+    int64_t c = start;
+    float mc = INFINITY;            /* covering radius^2 of the pick */
+    sel[c] = 1;
+    order[0] = (int32_t)c;
+    if (radius) radius[0] = INFINITY;
+    for (int64_t i = 0; i < n; ++i) m[i] = INFINITY;
+
+    for (int64_t t = 1; t <= k; ++t) {
+        /* update every live candidate with the newest pick c */
+        if (t < k) {
+            int64_t live = 0, ball = 0, dec = 0;
+            for (int64_t i = 0; i < n; ++i) {
+                if (sel[i]) continue;
+                float d = d2_f32(P + 3 * i, P + 3 * c);
+                ++live;
+                if (d < mc) ++ball;
+                if (d < m[i]) { m[i] = d; ++dec; }
+            }
+            if (n_live) n_live[t - 1] = live;
+            if (n_ball) n_ball[t - 1] = ball;
+            if (n_dec) n_dec[t - 1] = dec;
+        }
+        if (t == k) break;
+        /* select: largest min-distance, lowest index on ties */
+        int64_t best = -1;
+        for (int64_t i = 0; i < n; ++i) {
+            if (sel[i]) continue;
+            if (best < 0 || m[i] > m[best]) best = i;
+        }
+        c = best;
+        mc = m[c];
+        sel[c] = 1;
+        order[t] = (int32_t)c;
+        if (radius) radius[t] = sqrtf(mc);
+    }
+    free(m);
+    free(sel);
+    return ORACLE_OK;
+}
+
+/* ------------------------------------------------------------ FP64 greedy */
+
+int oracle_greedy64(const double* P, int64_t n, int64_t k, int64_t start,
+                    int32_t* order, double* radius)
+{
+    if (k == 0) return ORACLE_OK;
+    if (!P || !order || n < 1 || k < 0 || k > n || start < 0 || start >= n)
+        return ORACLE_BAD_ARG;
+    double* m = (double*)malloc(sizeof(double) * (size_t)n);
+    unsigned char* sel = (unsigned char*)calloc((size_t)n, 1);
+    if (!m || !sel) { free(m); free(sel); return ORACLE_NO_MEM; }
+    int64_t c = start;
+    sel[c] = 1;
+    order[0] = (int32_t)c;
+    if (radius) radius[0] = INFINITY;
+    for (int64_t i = 0; i < n; ++i) m[i] = INFINITY;
+    for (int64_t t = 1; t < k; ++t) {
+        for (int64_t i = 0; i < n; ++i) {
+            if (sel[i]) continue;
+            double d = d2_f64(P + 3 * i, P + 3 * c);
+            if (d < m[i]) m[i] = d;
+        }
+        int64_t best = -1;
+        for (int64_t i = 0; i < n; ++i) {
+            if (sel[i]) continue;
+            if (best < 0 || m[i] > m[best]) best = i;
+        }
+        c = best;
+        sel[c] = 1;
+        order[t] = (int32_t)c;
+        if (radius) radius[t] = sqrt(m[c]);
+    }
+    free(m);
+    free(sel);
+    return ORACLE_OK;
+}
+
+/*
+ * r64[t] = sqrt(min_{j<t} d2_64(P[order[t]], P[order[j]])), r64[0] = +inf,
+ * evaluated in binary64 on coordinates widened exactly from binary32.
+ */
+int oracle_along_order64(const float* P, int64_t n, const int32_t* order,
+                         int64_t k, double* r64)
+{
+    if (k == 0) return ORACLE_OK;
+    if (!P || !order || !r64 || k < 0 || k > n) return ORACLE_BAD_ARG;
+    double* Q = (double*)malloc(sizeof(double) * 3 * (size_t)k);
+    if (!Q) return ORACLE_NO_MEM;
+    for (int64_t t = 0; t < k; ++t) {
+        int64_t o = order[t];
+        if (o < 0 || o >= n) { free(Q); return ORACLE_BAD_ARG; }
+        Q[3 * t + 0] = (double)P[3 * o + 0];
+        Q[3 * t + 1] = (double)P[3 * o + 1];
+        Q[3 * t + 2] = (double)P[3 * o + 2];
+    }
+    r64[0] = INFINITY;
+    for (int64_t t = 1; t < k; ++t) {
+        double best = INFINITY;
+        for (int64_t j = 0; j < t; ++j) {
+            double d = d2_f64(Q + 3 * t, Q + 3 * j);
+            if (d < best) best = d;
+        }
+        r64[t] = sqrt(best);
+    }
+    free(Q);
+    return ORACLE_OK;
+}
+
+/* ------------------------------------------ exact grid-accelerated greedy */
+
+typedef struct {
+    int64_t begin, end;      /* range in the cell-sorted index list */
+    double lo[3], hi[3];     /* exact box of the member coordinates */
+    int64_t gx, gy, gz;      /* integer cell coordinates */
+} ocell;
+
+static uint64_t cell_hash_key(int64_t gx, int64_t gy, int64_t gz)
+{
+    return ((uint64_t)(gx & 0x1FFFFF) << 42) | ((uint64_t)(gy & 0x1FFFFF) << 21) |
+           (uint64_t)(gz & 0x1FFFFF);
+}
+
+static uint64_t mix64(uint64_t z)
+{
+    z = (z ^ (z >> 33)) * 0xff51afd7ed558ccdull;
+    z = (z ^ (z >> 33)) * 0xc4ceb9fe1a85ec53ull;
+    return z ^ (z >> 33);
+}
+
+typedef struct { uint64_t key; int64_t cell; int64_t i; } osort_rec;
+
+static int cmp_rec(const void* a, const void* b)
+{
+    const osort_rec* x = (const osort_rec*)a;
+    const osort_rec* y = (const osort_rec*)b;
+    if (x->key != y->key) return x->key < y->key ? -1 : 1;
+    return x->i < y->i ? -1 : (x->i > y->i);
+}
+
+/* selection key: larger d2 first, then lower index; 0 = no live member */
+static uint64_t sel_key(float d2, int64_t i)
+{
+    uint32_t b;
+    memcpy(&b, &d2, 4);
+    return ((uint64_t)b << 32) | (uint64_t)(0xFFFFFFFFu - (uint32_t)i);
+}
+
+/*
+ * Same result as oracle_greedy32 (bit for bit), faster on large inputs.
+ * A candidate's min-distance can only drop if its binary32 distance to the
+ * pick is below its own min-distance, which is at most the pick's m(c).  A
+ * cell is skipped when the binary64 distance from the pick to the cell's
+ * exact member box, shrunk by a relative margin of 1e-5 (binary32 rounding
+ * of d2 is within 5 * 2^-24 relative, plus underflow of order 1e-38), is at
+ * least m(c).  `target` is the desired mean number of points per cell.
+ */
+int oracle_greedy32_grid(const float* P, int64_t n, int64_t k, int64_t start,
+                         int32_t* order, float* radius, double target,
+                         int64_t* n_ball)
+{
+    if (k == 0) return ORACLE_OK;
+    if (!P || !order || n < 1 || k < 0 || k > n || start < 0 || start >= n)
+        return ORACLE_BAD_ARG;
+    if (!all_finite(P, n)) {
+        fill_nonfinite(order, radius, k);
+        return ORACLE_NONFINITE;
+    }
+    if (!(target >= 1.0)) target = 12.0;
+
+    double lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
+    for (int64_t i = 0; i < n; ++i)
+        for (int a = 0; a < 3; ++a) {
+            double v = P[3 * i + a];
+            if (v < lo[a]) lo[a] = v;
+            if (v > hi[a]) hi[a] = v;
+        }
+    double ext = 0.0;
+    for (int a = 0; a < 3; ++a) if (hi[a] - lo[a] > ext) ext = hi[a] - lo[a];
+    if (!(ext > 0.0)) ext = 1.0;
+
+    osort_rec* rec = (osort_rec*)malloc(sizeof(osort_rec) * (size_t)n);
+    if (!rec) return ORACLE_NO_MEM;
+
+    /* pick the cell side h: start from a volume-filling guess and refine by
+     * the observed occupancy (surfaces occupy far fewer cells) */
+    double h = ext / cbrt((double)n / target);
+    int64_t ncell = 0;
+    for (int iter = 0; iter < 3; ++iter) {
+        if (ext / h > 1.0e6) h = ext / 1.0e6;
+        for (int64_t i = 0; i < n; ++i) {
+            int64_t g[3];
+            for (int a = 0; a < 3; ++a) g[a] = (int64_t)floor(((double)P[3 * i + a] - lo[a]) / h);
+            rec[i].key = cell_hash_key(g[0], g[1], g[2]);
+            rec[i].i = i;
+        }
+        qsort(rec, (size_t)n, sizeof(osort_rec), cmp_rec);
+        ncell = 0;
+        for (int64_t i = 0; i < n; ++i)
+            if (i == 0 || rec[i].key != rec[i - 1].key) ++ncell;
+        double per = (double)n / (double)ncell;
+        if (iter == 2 || (per > 0.5 * target && per < 2.0 * target)) break;
+        h *= sqrt(target / per);
+    }
+
+    ocell* cells = (ocell*)malloc(sizeof(ocell) * (size_t)ncell);
+    int64_t* cell_of = (int64_t*)malloc(sizeof(int64_t) * (size_t)n);
+    int64_t* members = (int64_t*)malloc(sizeof(int64_t) * (size_t)n);
+    int64_t hcap = 1;
+    while (hcap < 2 * ncell) hcap <<= 1;
+    int64_t* htab = (int64_t*)malloc(sizeof(int64_t) * (size_t)hcap);
+    uint64_t* hkey = (uint64_t*)malloc(sizeof(uint64_t) * (size_t)hcap);
+    int64_t tsize = 1;
+    while (tsize < ncell) tsize <<= 1;
+    uint64_t* tree = (uint64_t*)calloc(2 * (size_t)tsize, sizeof(uint64_t));
+    float* m = (float*)malloc(sizeof(float) * (size_t)n);
+    unsigned char* sel = (unsigned char*)calloc((size_t)n, 1);
+    int64_t* visit = (int64_t*)malloc(sizeof(int64_t) * (size_t)ncell);
+    if (!cells || !cell_of || !members || !htab || !hkey || !tree || !m || !sel || !visit) {
+        free(rec); free(cells); free(cell_of); free(members); free(htab); free(hkey);
+        free(tree); free(m); free(sel); free(visit);
+        return ORACLE_NO_MEM;
+    }
+    for (int64_t i = 0; i < hcap; ++i) htab[i] = -1;
+
+    int64_t ci = -1;
+    for (int64_t r = 0; r < n; ++r) {
+        int64_t i = rec[r].i;
+        if (r == 0 || rec[r].key != rec[r - 1].key) {
+            ++ci;
+            ocell* C = &cells[ci];
+            C->begin = r;
+            for (int a = 0; a < 3; ++a) { C->lo[a] = INFINITY; C->hi[a] = -INFINITY; }
+            C->gx = (int64_t)floor(((double)P[3 * i + 0] - lo[0]) / h);
+            C->gy = (int64_t)floor(((double)P[3 * i + 1] - lo[1]) / h);
+            C->gz = (int64_t)floor(((double)P[3 * i + 2] - lo[2]) / h);
+            uint64_t key = rec[r].key;
+            uint64_t s = mix64(key) & (uint64_t)(hcap - 1);
+            while (htab[s] >= 0) s = (s + 1) & (uint64_t)(hcap - 1);
+            htab[s] = ci;
+            hkey[s] = key;
+        }
+        ocell* C = &cells[ci];
+        C->end = r + 1;
+        members[r] = i;
+        cell_of[i] = ci;
+        for (int a = 0; a < 3; ++a) {
+            double v = P[3 * i + a];
+            if (v < C->lo[a]) C->lo[a] = v;
+            if (v > C->hi[a]) C->hi[a] = v;
+        }
+    }
+    free(rec);
+
+    for (int64_t i = 0; i < n; ++i) m[i] = INFINITY;
+
+    int64_t c = start;
+    float mc = INFINITY;
+    sel[c] = 1;
+    order[0] = (int32_t)c;
+    if (radius) radius[0] = INFINITY;
+
+    for (int64_t t = 1; t < k; ++t) {
+        const float* pc = P + 3 * c;
+        double pcd[3] = {pc[0], pc[1], pc[2]};
+        /* gather the cells that may contain an affected candidate */
+        int64_t nvisit = 0;
+        double rr = sqrt((double)mc);
+        int64_t span = isinf(rr) ? INT64_MAX : (int64_t)floor(rr / h) + 1;
+        double boxes = (double)(2 * (double)span + 1);
+        boxes = boxes * boxes * boxes;
+        if (isinf(rr) || boxes >= (double)ncell) {
+            for (int64_t q = 0; q < ncell; ++q) visit[nvisit++] = q;
+        } else {
+            int64_t g0 = (int64_t)floor((pcd[0] - lo[0]) / h);
+            int64_t g1 = (int64_t)floor((pcd[1] - lo[1]) / h);
+            int64_t g2 = (int64_t)floor((pcd[2] - lo[2]) / h);
+            for (int64_t a = g0 - span; a <= g0 + span; ++a)
+                for (int64_t b = g1 - span; b <= g1 + span; ++b)
+                    for (int64_t e = g2 - span; e <= g2 + span; ++e) {
+                        if (a < 0 || b < 0 || e < 0) continue;
+                        uint64_t key = cell_hash_key(a, b, e);
+                        uint64_t s = mix64(key) & (uint64_t)(hcap - 1);
+                        while (htab[s] >= 0) {
+                            if (hkey[s] == key) { visit[nvisit++] = htab[s]; break; }
+                            s = (s + 1) & (uint64_t)(hcap - 1);
+                        }
+                    }
+        }
+        int64_t ball = 0;
+        int64_t own = cell_of[c];
+        for (int64_t v = 0; v < nvisit; ++v) {
+            int64_t q = visit[v];
+            ocell* C = &cells[q];
+            if (q != own && !isinf(rr)) {
+                double bd = 0.0;
+                for (int a = 0; a < 3; ++a) {
+                    double g = 0.0;
+                    if (pcd[a] < C->lo[a]) g = C->lo[a] - pcd[a];
+                    else if (pcd[a] > C->hi[a]) g = pcd[a] - C->hi[a];
+                    bd += g * g;
+                }
+                if (bd * (1.0 - 1e-5) - 1e-37 >= (double)mc) continue;
+            }
+            uint64_t best = 0;
+            for (int64_t r = C->begin; r < C->end; ++r) {
+                int64_t i = members[r];
+                if (sel[i]) continue;
+                float d = d2_f32(P + 3 * i, pc);
+                if (d < mc) ++ball;
+                if (d < m[i]) m[i] = d;
+                uint64_t kk = sel_key(m[i], i);
+                if (kk > best) best = kk;
+            }
+            int64_t node = tsize + q;
+            tree[node] = best;
+            for (node >>= 1; node >= 1; node >>= 1) {
+                uint64_t l = tree[2 * node], rgt = tree[2 * node + 1];
+                tree[node] = l > rgt ? l : rgt;
+            }
+        }
+        if (n_ball) n_ball[t - 1] = ball;
+        uint64_t top = tree[1];
+        c = (int64_t)(0xFFFFFFFFu - (uint32_t)(top & 0xFFFFFFFFu));
+        mc = m[c];
+        sel[c] = 1;
+        order[t] = (int32_t)c;
+        if (radius) radius[t] = sqrtf(mc);
+    }
+
+    free(cells); free(cell_of); free(members); free(htab); free(hkey);
+    free(tree); free(m); free(sel); free(visit);
+    return ORACLE_OK;
+}

@@ -1,0 +1,49 @@
+"""Planted mistakes in copies of the oracle must fail its pins (CPU only).
+
+Each mutant is the oracle source with one plausible slip (a dropped term, a
+wrong sign, a wrong tie-break, the other reading of "largest distance to all
+chosen surfels", a wrong operand, ...), compiled with the oracle's own flags
+into a temporary library.  The pin battery must reject every one of them;
+the unmodified source must pass it.
+"""
+import pytest
+
+import oracle
+from tests import pins
+
+MUTANTS = {
+    "dropped_dz_term": ("    float s = xx + yy;\n    return s + zz;",
+                        "    float s = xx + yy;\n    (void)zz;\n    return s;"),
+    "wrong_sign_dz": ("    float dz = a[2] - b[2];", "    float dz = a[2] + b[2];"),
+    "highest_index_tie": ("            if (best < 0 || m[i] > m[best]) best = i;\n        }\n        c = best;\n        mc = m[c];",
+                          "            if (best < 0 || m[i] >= m[best]) best = i;\n        }\n        c = best;\n        mc = m[c];"),
+    "max_sum_reading": ("                if (d < m[i]) { m[i] = d; ++dec; }",
+                        "                { m[i] = isinf(m[i]) ? d : m[i] + d; ++dec; }"),
+    "distance_to_start_only": ("                float d = d2_f32(P + 3 * i, P + 3 * c);\n                ++live;",
+                               "                float d = d2_f32(P + 3 * i, P + 3 * start);\n                ++live;"),
+    "radius_is_d2": ("        if (radius) radius[t] = sqrtf(mc);\n    }\n    free(m);",
+                     "        if (radius) radius[t] = mc;\n    }\n    free(m);"),
+    "reselect_picked": ("        for (int64_t i = 0; i < n; ++i) {\n            if (sel[i]) continue;\n            if (best < 0 || m[i] > m[best]) best = i;\n        }\n        c = best;\n        mc",
+                        "        for (int64_t i = 0; i < n; ++i) {\n            if (best < 0 || m[i] > m[best]) best = i;\n        }\n        c = best;\n        mc"),
+    "grid_prunes_too_much": ("if (bd * (1.0 - 1e-5) - 1e-37 >= (double)mc) continue;",
+                             "if (bd * 4.0 >= (double)mc) continue;"),
+    "splitmix_constant": ("z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;",
+                          "z = (z ^ (z >> 27)) * 0x94D049BB133111EAull;"),
+    "fp64_dropped_dz": ("    double dz = a[2] - b[2];", "    double dz = 0.0 * (a[2] - b[2]);"),
+    "along_order_max": ("            if (d < best) best = d;\n        }\n        r64[t] = sqrt(best);",
+                        "            if (d > best || isinf(best)) best = d;\n        }\n        r64[t] = sqrt(best);"),
+}
+
+
+def test_unmodified_passes_battery():
+    pins.pin_battery()
+
+
+@pytest.mark.parametrize("name", sorted(MUTANTS))
+def test_mutant_is_caught(name, tmp_path):
+    old, new = MUTANTS[name]
+    src = oracle.source_text()
+    assert src.count(old) == 1, "mutation target not unique: " + name
+    lib = oracle.compile_variant(src.replace(old, new), str(tmp_path / ("m_%s.so" % name)))
+    with pytest.raises((AssertionError, oracle.OracleError)):
+        pins.pin_battery(lib)
