@@ -1,0 +1,148 @@
+/*
+ * bluesurfels.h -- C ABI of the MI355X (gfx950) greedy blue-noise surfel
+ * ordering library (libbluesurfels.so).
+ *
+ * The operation is the progressive ordering of candidate surfels from
+ * "Rendering of Complex Heterogenous Scenes using Progressive Blue Surfels"
+ * (Brandt, Jaehn, Fischer, Meyer auf der Heide; arXiv 1904.08225), Sec. 3.2
+ * and Sec. 3.3: start at a random candidate, then repeatedly append the
+ * remaining candidate whose distance to its nearest already chosen surfel is
+ * largest, and remove it, until k surfels are chosen.  The result is a
+ * greedy permutation (farthest-first traversal): every prefix of the
+ * ordered array is an r-net of the candidates (Sec. 4.1), so a renderer
+ * picks a level of detail by drawing a prefix.
+ *
+ * Exactness contract (the paper does not fix the arithmetic; these are the
+ * library's readings):
+ *   - distances are squared Euclidean in binary32 with a fixed association
+ *     and no contraction:  d2 = ((dx*dx + dy*dy) + dz*dz),  dx = a.x - b.x;
+ *   - the selection compares d2 values; ties go to the lowest index;
+ *   - out_radius[t] = sqrtf(d2 of out_order[t] to its nearest earlier pick),
+ *     correctly rounded; out_radius[0] = +inf;
+ *   - a chosen candidate is never chosen again, also at distance 0;
+ *   - the start is SplitMix64(seed) mod n (first output of SplitMix64,
+ *     Steele, Lea and Flood 2014) unless an explicit start is given.
+ * Every entry point returns the same orders and radii, bit for bit, for the
+ * same (points, k, start), whichever kernel or tiling it uses.
+ *
+ * Conventions for every entry point:
+ *   - pointers named d_* or documented as device pointers are device memory
+ *     (hipMalloc / PyTorch CUDA tensors) on the current HIP device; h_*
+ *     pointers are host memory;
+ *   - the caller owns every input, output and workspace buffer; the library
+ *     never frees them;
+ *   - `stream` is a hipStream_t (NULL = the null stream).  Calls enqueue
+ *     work and return without waiting; errors that the host can detect
+ *     (null pointers, bad sizes, too small workspace) are returned
+ *     synchronously and nothing is enqueued;
+ *   - candidates with a non-finite coordinate are detected on the device;
+ *     the outputs are then out_order[:] = -1 and out_radius[:] = NaN.
+ *   - normals and colours are accepted for interface completeness (a surfel
+ *     is position + normal + material, Sec. 3.1) but the selection ignores
+ *     them, as the paper's sampling does (Sec. 5 limitations); they may be
+ *     NULL.
+ * All functions are thread-safe except where a handle is shared without
+ * external locking.
+ */
+#ifndef BLUESURFELS_H
+#define BLUESURFELS_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---------------------------------------------------------------- status */
+typedef enum {
+    BS_OK = 0,
+    BS_ERR_INVALID_ARG = -1,   /* bad pointer / size / argument */
+    BS_ERR_OUT_OF_MEMORY = -2, /* device allocation failed */
+    BS_ERR_HIP = -3,           /* a HIP runtime call failed */
+    BS_ERR_OVER_BUDGET = -4,   /* server: job exceeds the HBM budget */
+    BS_ERR_NOT_READY = -5,     /* server: job not finished yet */
+    BS_ERR_UNSUPPORTED = -6,   /* no kernel for this size / device */
+    BS_ERR_TIMEOUT = -7,       /* a wait exceeded its deadline */
+    BS_ERR_DEVICE = -8         /* a kernel reported an internal error */
+} bs_status;
+
+/* Human readable name of a status code (static string). */
+const char* bs_error_string(int code);
+/* Detail message of the last error on the calling thread (static storage
+ * per thread, valid until the next call on that thread). */
+const char* bs_last_error_message(void);
+/* Library version as "major.minor.patch". */
+const char* bs_version(void);
+
+/* ---------------------------------------------------------------- tuning */
+typedef enum {
+    BS_KERNEL_AUTO = 0,  /* library picks (autotuned table) */
+    BS_KERNEL_WG = 1,    /* one workgroup, candidates resident in registers */
+    BS_KERNEL_COOP = 2,  /* cooperative workgroups, resident, full scan */
+    BS_KERNEL_GRID = 3   /* uniform-grid radius-pruned kernel */
+} bs_kernel;
+
+typedef struct {
+    int32_t kernel;        /* bs_kernel */
+    int32_t block;         /* threads per workgroup (0 = auto) */
+    int32_t per_thread;    /* candidates per thread for resident kernels (0 = auto) */
+    int32_t groups;        /* workgroups of a cooperative launch (0 = auto) */
+    float cell_points;     /* grid kernel: target mean candidates per cell (0 = auto) */
+    int32_t reserved[7];   /* must be zero */
+} bs_tuning;
+
+/* ------------------------------------------------------- single instance */
+
+/*
+ * Greedy permutation of n candidates (paper Sec. 3.2, 3.3).
+ *   d_points   device float[n][3] (AoS, row-major, 12-byte stride)
+ *   d_normals  device float[n][3] or NULL (not read by the ordering)
+ *   d_colors   device uint8[n][3] or NULL (not read by the ordering)
+ *   n          number of candidates, 1 <= n < 2^31 (n may be 0 when k == 0)
+ *   k          number of surfels to order, 0 <= k <= n (k == 0: no-op)
+ *   seed       start = SplitMix64(seed) mod n
+ *   d_out_order   device int32[k]: candidate indices in greedy order
+ *   d_out_radius  device float[k] or NULL: distance of each pick to its
+ *                 nearest earlier pick (covering radius of the prefix)
+ * The library allocates its workspace from a stream-ordered pool
+ * (hipMallocAsync) and frees it stream-ordered.  Errors: BS_ERR_INVALID_ARG
+ * (null pointers, k < 0, k > n, n >= 2^31), BS_ERR_OUT_OF_MEMORY, BS_ERR_HIP.
+ */
+int bs_order(const float* d_points, const float* d_normals, const uint8_t* d_colors,
+             int64_t n, int64_t k, uint64_t seed,
+             int32_t* d_out_order, float* d_out_radius, void* stream);
+
+/*
+ * As bs_order with an explicit start, a caller-owned workspace and an
+ * optional tuning override.
+ *   start_index   0 <= start_index < n, or -1 to derive it from `seed`
+ *   d_workspace   device buffer of at least bs_workspace_size(n, k, tuning)
+ *                 bytes, 256-byte aligned; its contents on entry do not
+ *                 matter; concurrent calls must not share it
+ *   tuning        NULL = automatic choice
+ * Errors: as bs_order, plus BS_ERR_INVALID_ARG for a too small or
+ * misaligned workspace and BS_ERR_UNSUPPORTED if the forced kernel cannot
+ * hold n candidates.
+ */
+int bs_order_ex(const float* d_points, const float* d_normals, const uint8_t* d_colors,
+                int64_t n, int64_t k, uint64_t seed, int64_t start_index,
+                int32_t* d_out_order, float* d_out_radius,
+                void* d_workspace, size_t workspace_bytes,
+                const bs_tuning* tuning, void* stream);
+
+/* Workspace bytes bs_order_ex needs for (n, k, tuning); 0 if unsupported. */
+size_t bs_workspace_size(int64_t n, int64_t k, const bs_tuning* tuning);
+
+/* The start index bs_order uses for (seed, n): SplitMix64(seed) mod n;
+ * -1 if n < 1. */
+int64_t bs_start_index(uint64_t seed, int64_t n);
+
+/* Which kernel the automatic choice uses for (n, k) (a bs_kernel value). */
+int bs_auto_kernel(int64_t n, int64_t k);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* BLUESURFELS_H */

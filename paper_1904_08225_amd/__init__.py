@@ -1,0 +1,182 @@
+"""Python binding of libbluesurfels (MI355X greedy blue-noise surfel ordering).
+
+Argument marshalling only: every step of the ordering runs in the HIP
+kernels of ``libbluesurfels.so`` (built in-tree by
+``python -m paper_1904_08225_amd.build``).  There is no CPU fallback; if the
+library is missing, :func:`load` raises.
+
+The ordering is the greedy permutation of the paper's progressive sampling
+(Sec. 3.2) whose exact form Sec. 3.3 names as the goal: start at a random
+candidate, then repeatedly append the remaining candidate farthest from its
+nearest chosen surfel.  See ``include/bluesurfels.h`` for the exact
+arithmetic contract.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import re
+from typing import Optional, Tuple
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libbluesurfels.so")
+HEADER = os.path.join(os.path.dirname(_HERE), "include", "bluesurfels.h")
+
+BS_OK = 0
+BS_ERR_INVALID_ARG = -1
+BS_ERR_OUT_OF_MEMORY = -2
+BS_ERR_HIP = -3
+BS_ERR_OVER_BUDGET = -4
+BS_ERR_NOT_READY = -5
+BS_ERR_UNSUPPORTED = -6
+BS_ERR_TIMEOUT = -7
+BS_ERR_DEVICE = -8
+
+KERNEL_AUTO, KERNEL_WG, KERNEL_COOP, KERNEL_GRID = 0, 1, 2, 3
+
+_lib = None
+
+
+class BSError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__("%s: %s" % (error_string(code) if _lib else code, msg))
+        self.code = code
+
+
+class Tuning(ctypes.Structure):
+    _fields_ = [("kernel", ctypes.c_int32), ("block", ctypes.c_int32),
+                ("per_thread", ctypes.c_int32), ("groups", ctypes.c_int32),
+                ("cell_points", ctypes.c_float), ("reserved", ctypes.c_int32 * 7)]
+
+
+def tuning(kernel: int = 0, block: int = 0, per_thread: int = 0, groups: int = 0,
+           cell_points: float = 0.0) -> Tuning:
+    return Tuning(kernel, block, per_thread, groups, cell_points)
+
+
+def header_functions():
+    """Names of the functions declared in include/bluesurfels.h."""
+    with open(HEADER) as f:
+        text = f.read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(bs_[a-z0-9_]+)\s*\(", text)))
+
+
+def load():
+    """Load libbluesurfels.so; raise if it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError("libbluesurfels.so is not built (run: python -m paper_1904_08225_amd.build)")
+    lib = ctypes.CDLL(LIB_PATH)
+    i32, i64, u64, vp, sz = ctypes.c_int, ctypes.c_int64, ctypes.c_uint64, ctypes.c_void_p, ctypes.c_size_t
+    tp = ctypes.POINTER(Tuning)
+    lib.bs_error_string.argtypes = [i32]
+    lib.bs_error_string.restype = ctypes.c_char_p
+    lib.bs_last_error_message.argtypes = []
+    lib.bs_last_error_message.restype = ctypes.c_char_p
+    lib.bs_version.restype = ctypes.c_char_p
+    lib.bs_start_index.argtypes = [u64, i64]
+    lib.bs_start_index.restype = i64
+    lib.bs_auto_kernel.argtypes = [i64, i64]
+    lib.bs_auto_kernel.restype = i32
+    lib.bs_workspace_size.argtypes = [i64, i64, tp]
+    lib.bs_workspace_size.restype = sz
+    lib.bs_order.argtypes = [vp, vp, vp, i64, i64, u64, vp, vp, vp]
+    lib.bs_order.restype = i32
+    lib.bs_order_ex.argtypes = [vp, vp, vp, i64, i64, u64, i64, vp, vp, vp, sz, tp, vp]
+    lib.bs_order_ex.restype = i32
+    _lib = lib
+    return lib
+
+
+def error_string(code: int) -> str:
+    return load().bs_error_string(code).decode()
+
+
+def last_error() -> str:
+    return load().bs_last_error_message().decode()
+
+
+def _check(rc: int):
+    if rc != BS_OK:
+        raise BSError(rc, last_error())
+
+
+def start_index(seed: int, n: int) -> int:
+    return int(load().bs_start_index(ctypes.c_uint64(seed & (2**64 - 1)), n))
+
+
+def auto_kernel(n: int, k: int) -> int:
+    return int(load().bs_auto_kernel(n, k))
+
+
+def workspace_size(n: int, k: int, tune: Optional[Tuning] = None) -> int:
+    return int(load().bs_workspace_size(n, k, ctypes.byref(tune) if tune is not None else None))
+
+
+def _ptr(t):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+def _stream_handle(stream):
+    import torch
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def _prep_points(points):
+    import torch
+    if not isinstance(points, torch.Tensor) or not points.is_cuda:
+        raise TypeError("points must be a CUDA (HIP) torch tensor")
+    if points.dtype != torch.float32 or points.dim() != 2 or points.shape[1] != 3:
+        raise TypeError("points must be float32 [n, 3]")
+    if not points.is_contiguous():
+        raise ValueError("points must be contiguous")
+    return points
+
+
+def order(points, k: Optional[int] = None, seed: int = 0, *, normals=None, colors=None,
+          start: Optional[int] = None, tune: Optional[Tuning] = None, workspace=None,
+          out_order=None, out_radius=None, stream=None, check: bool = True
+          ) -> Tuple["torch.Tensor", "torch.Tensor"]:
+    """Greedy permutation of ``points`` (float32 [n, 3] on the GPU).
+
+    Returns ``(order int32[k], radius float32[k])`` on the same device.  With
+    ``start`` or ``tune`` or ``workspace`` given, calls ``bs_order_ex`` with a
+    torch-allocated workspace; otherwise ``bs_order``.  ``check`` synchronises
+    and raises ValueError if the device flagged non-finite coordinates.
+    """
+    import torch
+    lib = load()
+    points = _prep_points(points)
+    n = int(points.shape[0])
+    k = n if k is None else int(k)
+    dev = points.device
+    if out_order is None:
+        out_order = torch.empty(max(k, 0), dtype=torch.int32, device=dev)
+    if out_radius is None:
+        out_radius = torch.empty(max(k, 0), dtype=torch.float32, device=dev)
+    st = _stream_handle(stream)
+    if start is None and tune is None and workspace is None:
+        rc = lib.bs_order(_ptr(points), _ptr(normals), _ptr(colors), n, k,
+                          ctypes.c_uint64(seed & (2**64 - 1)), _ptr(out_order), _ptr(out_radius), st)
+    else:
+        tp = ctypes.byref(tune) if tune is not None else None
+        if workspace is None:
+            need = int(lib.bs_workspace_size(n, k, tp)) if k > 0 else 0
+            if k > 0 and need == 0:
+                _check(lib.bs_order_ex(_ptr(points), None, None, n, k, 0, -1 if start is None else start,
+                                       _ptr(out_order), _ptr(out_radius), None, 0, tp, st))
+            workspace = torch.empty(max(need, 1), dtype=torch.uint8, device=dev)
+        rc = lib.bs_order_ex(_ptr(points), _ptr(normals), _ptr(colors), n, k,
+                             ctypes.c_uint64(seed & (2**64 - 1)), -1 if start is None else int(start),
+                             _ptr(out_order), _ptr(out_radius), _ptr(workspace),
+                             int(workspace.numel()), tp, st)
+    _check(rc)
+    if check and k > 0:
+        torch.cuda.current_stream().synchronize() if stream is None else stream.synchronize()
+        if int(out_order[0]) == -1:
+            raise ValueError("non-finite candidate coordinates")
+    return out_order, out_radius

@@ -1,0 +1,194 @@
+// bs_api.cpp -- C ABI of libbluesurfels: argument validation, workspace
+// sizing, kernel choice and enqueueing.  See include/bluesurfels.h.
+#include <hip/hip_runtime.h>
+
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <mutex>
+
+#include "bs_internal.h"
+
+namespace bs {
+
+namespace {
+thread_local char g_msg[512] = "";
+
+struct DeviceInfo {
+    int cus = 0;
+};
+std::mutex g_dev_mu;
+DeviceInfo g_dev[64];
+
+int device_cus() {
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return 0;
+    std::lock_guard<std::mutex> lk(g_dev_mu);
+    if (g_dev[dev].cus == 0) {
+        hipDeviceProp_t p;
+        if (hipGetDeviceProperties(&p, dev) != hipSuccess) return 0;
+        g_dev[dev].cus = p.multiProcessorCount;
+    }
+    return g_dev[dev].cus;
+}
+
+bool tuning_clean(const bs_tuning* t) {
+    if (!t) return true;
+    for (int r : t->reserved)
+        if (r != 0) return false;
+    return t->kernel >= BS_KERNEL_AUTO && t->kernel <= BS_KERNEL_GRID;
+}
+
+// Resolve the kernel and, for resident kernels, the launch shape.
+int plan_single(int64_t n, int64_t k, const bs_tuning* t, int* kernel, ScanShape* shape) {
+    const int cus = device_cus() > 0 ? device_cus() : 256;
+    int want = t ? t->kernel : BS_KERNEL_AUTO;
+    const int wb = t ? t->block : 0, wp = t ? t->per_thread : 0, wg = t ? t->groups : 0;
+    (void)k;
+    if (want == BS_KERNEL_AUTO) {
+        if (choose_scan_shape(n, cus, wb, wp, wg, shape)) {
+            *kernel = shape->groups > 1 ? BS_KERNEL_COOP : BS_KERNEL_WG;
+            return BS_OK;
+        }
+        return set_error(BS_ERR_UNSUPPORTED, "no kernel holds n=%lld candidates", (long long)n);
+    }
+    if (want == BS_KERNEL_WG || want == BS_KERNEL_COOP) {
+        if (!choose_scan_shape(n, cus, wb, wp, want == BS_KERNEL_WG ? 1 : wg, shape))
+            return set_error(BS_ERR_UNSUPPORTED, "resident kernel cannot hold n=%lld with this tuning",
+                             (long long)n);
+        if (want == BS_KERNEL_WG && shape->groups != 1)
+            return set_error(BS_ERR_UNSUPPORTED, "n=%lld does not fit one workgroup", (long long)n);
+        if (want == BS_KERNEL_COOP && shape->groups > cus * 2)
+            return set_error(BS_ERR_UNSUPPORTED, "cooperative grid of %d groups too large", shape->groups);
+        *kernel = want;
+        return BS_OK;
+    }
+    return set_error(BS_ERR_UNSUPPORTED, "kernel %d not available", want);
+}
+
+size_t workspace_for(int kernel, const ScanShape& s) {
+    (void)kernel;
+    return scan_workspace_bytes(s);
+}
+
+}  // namespace
+
+int set_error(int code, const char* fmt, ...) {
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(g_msg, sizeof(g_msg), fmt, ap);
+    va_end(ap);
+    return code;
+}
+
+}  // namespace bs
+
+using namespace bs;
+
+extern "C" {
+
+const char* bs_error_string(int code) {
+    switch (code) {
+        case BS_OK: return "BS_OK";
+        case BS_ERR_INVALID_ARG: return "BS_ERR_INVALID_ARG";
+        case BS_ERR_OUT_OF_MEMORY: return "BS_ERR_OUT_OF_MEMORY";
+        case BS_ERR_HIP: return "BS_ERR_HIP";
+        case BS_ERR_OVER_BUDGET: return "BS_ERR_OVER_BUDGET";
+        case BS_ERR_NOT_READY: return "BS_ERR_NOT_READY";
+        case BS_ERR_UNSUPPORTED: return "BS_ERR_UNSUPPORTED";
+        case BS_ERR_TIMEOUT: return "BS_ERR_TIMEOUT";
+        case BS_ERR_DEVICE: return "BS_ERR_DEVICE";
+        default: return "BS_ERR_UNKNOWN";
+    }
+}
+
+const char* bs_last_error_message(void) { return g_msg; }
+
+const char* bs_version(void) { return "0.1.0"; }
+
+int64_t bs_start_index(uint64_t seed, int64_t n) {
+    if (n < 1) return -1;
+    // first output of SplitMix64 seeded with `seed`
+    uint64_t z = seed + 0x9E3779B97F4A7C15ull;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    z ^= z >> 31;
+    return int64_t(z % uint64_t(n));
+}
+
+int bs_auto_kernel(int64_t n, int64_t k) {
+    int kernel = 0;
+    ScanShape s;
+    if (n < 1 || n >= (int64_t(1) << 31)) return -1;
+    if (plan_single(n, k, nullptr, &kernel, &s) != BS_OK) return -1;
+    return kernel;
+}
+
+size_t bs_workspace_size(int64_t n, int64_t k, const bs_tuning* tuning) {
+    if (n < 1 || n >= (int64_t(1) << 31) || k < 0 || k > n || !tuning_clean(tuning)) return 0;
+    int kernel = 0;
+    ScanShape s;
+    if (plan_single(n, k, tuning, &kernel, &s) != BS_OK) return 0;
+    return workspace_for(kernel, s);
+}
+
+int bs_order_ex(const float* d_points, const float* d_normals, const uint8_t* d_colors,
+                int64_t n, int64_t k, uint64_t seed, int64_t start_index,
+                int32_t* d_out_order, float* d_out_radius, void* d_workspace,
+                size_t workspace_bytes, const bs_tuning* tuning, void* stream) {
+    (void)d_normals;
+    (void)d_colors;
+    if (k < 0) return set_error(BS_ERR_INVALID_ARG, "k=%lld < 0", (long long)k);
+    if (k == 0) return BS_OK;
+    if (n < 1 || n >= (int64_t(1) << 31))
+        return set_error(BS_ERR_INVALID_ARG, "n=%lld outside [1, 2^31)", (long long)n);
+    if (k > n) return set_error(BS_ERR_INVALID_ARG, "k=%lld > n=%lld", (long long)k, (long long)n);
+    if (!d_points || !d_out_order) return set_error(BS_ERR_INVALID_ARG, "null points or output");
+    if (!tuning_clean(tuning)) return set_error(BS_ERR_INVALID_ARG, "bad tuning struct");
+    if (start_index < -1 || start_index >= n)
+        return set_error(BS_ERR_INVALID_ARG, "start_index=%lld outside [-1, n)", (long long)start_index);
+    const int64_t start = start_index >= 0 ? start_index : bs_start_index(seed, n);
+
+    int kernel = 0;
+    ScanShape shape;
+    int rc = plan_single(n, k, tuning, &kernel, &shape);
+    if (rc != BS_OK) return rc;
+    const size_t need = workspace_for(kernel, shape);
+    if (!d_workspace || workspace_bytes < need)
+        return set_error(BS_ERR_INVALID_ARG, "workspace %zu bytes < %zu needed", workspace_bytes, need);
+    if (reinterpret_cast<uintptr_t>(d_workspace) % kAlign != 0)
+        return set_error(BS_ERR_INVALID_ARG, "workspace not %zu-byte aligned", kAlign);
+
+    hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+    DevHeader* hdr = reinterpret_cast<DevHeader*>(d_workspace);
+    void* scratch = static_cast<char*>(d_workspace) + align_up(sizeof(DevHeader));
+    hipError_t e = launch_init_header(hdr, st);
+    if (e == hipSuccess) e = launch_validate(d_points, n, hdr, st);
+    if (e == hipSuccess)
+        e = launch_scan(shape, d_points, int(n), int(k), int(start), d_out_order, d_out_radius, hdr,
+                        scratch, st);
+    if (e != hipSuccess) return set_error(BS_ERR_HIP, "launch failed: %s", hipGetErrorString(e));
+    return BS_OK;
+}
+
+int bs_order(const float* d_points, const float* d_normals, const uint8_t* d_colors, int64_t n,
+             int64_t k, uint64_t seed, int32_t* d_out_order, float* d_out_radius, void* stream) {
+    if (k < 0) return set_error(BS_ERR_INVALID_ARG, "k=%lld < 0", (long long)k);
+    if (k == 0) return BS_OK;
+    const size_t need = bs_workspace_size(n, k, nullptr);
+    if (need == 0) {
+        if (n < 1 || n >= (int64_t(1) << 31) || k > n)
+            return set_error(BS_ERR_INVALID_ARG, "bad sizes n=%lld k=%lld", (long long)n, (long long)k);
+        return set_error(BS_ERR_UNSUPPORTED, "no kernel for n=%lld", (long long)n);
+    }
+    hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+    void* ws = nullptr;
+    hipError_t e = hipMallocAsync(&ws, need, st);
+    if (e != hipSuccess || !ws) return set_error(BS_ERR_OUT_OF_MEMORY, "workspace of %zu bytes", need);
+    int rc = bs_order_ex(d_points, d_normals, d_colors, n, k, seed, -1, d_out_order, d_out_radius,
+                         ws, need, nullptr, stream);
+    hipFreeAsync(ws, st);
+    return rc;
+}
+
+}  // extern "C"

@@ -1,0 +1,53 @@
+// bs_internal.h -- declarations shared by the HIP sources of libbluesurfels.
+// Not part of the public ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+#include "../../include/bluesurfels.h"
+
+namespace bs {
+
+// Per-call device header at the start of every workspace (256 bytes).
+struct DevHeader {
+    uint32_t nonfinite;  // set by the validate kernel if any coordinate is not finite
+    uint32_t error;      // set by a kernel whose bounded wait gave up
+    uint32_t bbox[6];    // order-preserving uint encodings: min x,y,z then max x,y,z
+    uint32_t pad[56];
+};
+static_assert(sizeof(DevHeader) == 256, "header size");
+
+constexpr size_t kAlign = 256;
+inline size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
+
+// Resident-scan launch shape.
+struct ScanShape {
+    int block = 0;       // threads per workgroup
+    int per_thread = 0;  // candidates per thread
+    int groups = 0;      // workgroups (1 = single-workgroup kernel)
+};
+
+// Largest cooperative grid this library launches for the resident scan.
+constexpr int kMaxCoopGroups = 1024;
+
+// Supported (block, per_thread) instantiations of the resident scan.
+bool scan_shape_supported(int block, int per_thread);
+// Choose a resident-scan shape for n candidates on a device with `cus`
+// compute units; returns false if n does not fit in registers.
+bool choose_scan_shape(int64_t n, int cus, int want_block, int want_pt, int want_groups,
+                       ScanShape* out);
+size_t scan_workspace_bytes(const ScanShape& s);
+
+// Kernel launchers (bs_scan.hip).  All return hipError_t of the launch.
+hipError_t launch_init_header(DevHeader* hdr, hipStream_t st);
+hipError_t launch_validate(const float* pts, int64_t n, DevHeader* hdr, hipStream_t st);
+hipError_t launch_scan(const ScanShape& s, const float* pts, int n, int k, int start,
+                       int32_t* order, float* radius, DevHeader* hdr, void* scratch,
+                       hipStream_t st);
+
+// Error reporting (bs_api.cpp).
+int set_error(int code, const char* fmt, ...);
+
+}  // namespace bs

@@ -1,0 +1,53 @@
+"""The C-ABI library loads and exports what include/bluesurfels.h declares;
+host-side logic (start index, argument validation) works without a GPU."""
+import ctypes
+import os
+
+import pytest
+
+import oracle
+import paper_1904_08225_amd as bs
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(bs.LIB_PATH):
+        from paper_1904_08225_amd import build
+        build.build()
+    return bs.load()
+
+
+def test_exports_every_declared_function(lib):
+    names = bs.header_functions()
+    assert "bs_order" in names and "bs_order_ex" in names
+    missing = [n for n in names if not hasattr(lib, n)]
+    assert not missing, missing
+
+
+def test_start_index_matches_splitmix64(lib):
+    for n in (1, 2, 3, 1000, 16384, 4194304, 2**31 - 1):
+        for seed in (0, 1, 2, 3, 99, 2**63, 2**64 - 1):
+            assert bs.start_index(seed, n) == oracle.start_index(seed, n)
+    assert bs.start_index(5, 0) == -1
+
+
+def test_argument_validation_without_device(lib):
+    vp = ctypes.c_void_p
+    fake = vp(0x1000)
+    # k == 0 is a no-op even with null pointers
+    assert lib.bs_order(None, None, None, 10, 0, 0, None, None, None) == bs.BS_OK
+    assert lib.bs_order(fake, None, None, 10, -1, 0, fake, None, None) == bs.BS_ERR_INVALID_ARG
+    assert lib.bs_order_ex(fake, None, None, 10, 11, 0, -1, fake, None, fake, 1 << 20, None, None) == bs.BS_ERR_INVALID_ARG
+    assert "k=11 > n=10" in bs.last_error()
+    assert lib.bs_order_ex(None, None, None, 10, 5, 0, -1, fake, None, fake, 1 << 20, None, None) == bs.BS_ERR_INVALID_ARG
+    assert lib.bs_order_ex(fake, None, None, 10, 5, 0, 10, fake, None, fake, 1 << 20, None, None) == bs.BS_ERR_INVALID_ARG
+    assert lib.bs_order_ex(fake, None, None, 0, 5, 0, -1, fake, None, fake, 1 << 20, None, None) == bs.BS_ERR_INVALID_ARG
+    assert lib.bs_order_ex(fake, None, None, 2**31, 5, 0, -1, fake, None, fake, 1 << 20, None, None) == bs.BS_ERR_INVALID_ARG
+    bad = bs.Tuning()
+    bad.reserved[0] = 1
+    assert lib.bs_order_ex(fake, None, None, 10, 5, 0, -1, fake, None, fake, 1 << 20, ctypes.byref(bad), None) == bs.BS_ERR_INVALID_ARG
+    # too small workspace is rejected before anything is enqueued
+    assert lib.bs_order_ex(fake, None, None, 10, 5, 0, -1, fake, None, fake, 16, None, None) == bs.BS_ERR_INVALID_ARG
+    assert lib.bs_workspace_size(10, 11, None) == 0
+    assert lib.bs_workspace_size(16384, 16384, None) > 0
+    assert bs.error_string(bs.BS_ERR_OVER_BUDGET) == "BS_ERR_OVER_BUDGET"

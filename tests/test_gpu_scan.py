@@ -1,0 +1,155 @@
+"""GPU parity of the resident full-scan kernels against the CPU oracle.
+
+Orders and radii must match bit for bit (the radii are the binary32
+square roots of the selected squared distances on both sides).
+"""
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from tests import cases, pins
+
+pytestmark = pytest.mark.gpu
+
+
+def run(hip, P_np, k, start=None, tune=None, seed=0):
+    import torch
+    P = torch.from_numpy(np.ascontiguousarray(P_np, dtype=np.float32)).cuda()
+    o, r = hip.order(P, k, seed=seed, start=start, tune=tune)
+    torch.cuda.synchronize()
+    return o.cpu().numpy(), r.cpu().numpy()
+
+
+def assert_parity(o, r, eo, er, label=""):
+    if not np.array_equal(o, eo):
+        i = int(np.argmax(o != eo))
+        raise AssertionError("%s: order differs first at %d: gpu %d oracle %d" % (label, i, o[i], eo[i]))
+    assert pins.same_f32(r, er), label + ": radius bits differ"
+
+
+def test_sphere_box_full_order(hip):
+    s = synth.sphere_and_box(n=16384, seed=1)
+    P = s.points.numpy()
+    st = oracle.start_index(1, P.shape[0])
+    eo, er = oracle.greedy32(P, 16384, st)
+    o, r = run(hip, P, 16384, start=st)
+    assert_parity(o, r, eo, er, "sphere_and_box")
+    # radius within 1e-6 relative of the binary64 recomputation along the order
+    r64 = oracle.along_order64(P, o)
+    assert np.all(np.abs(r[1:].astype(np.float64) - r64[1:]) <= 1e-6 * r64[1:])
+
+
+@pytest.mark.parametrize("name", sorted(cases.ADVERSARIAL))
+def test_adversarial_single_workgroup(hip, name):
+    for n in (1, 2, 3, 64, 65, 1000, 1025, 4097):
+        P = cases.ADVERSARIAL[name](n, 31 + n)
+        st = (7 * n) // 11
+        eo, er = oracle.greedy32(P, n, st)
+        o, r = run(hip, P, n, start=st, tune=hip.tuning(kernel=hip.KERNEL_WG))
+        assert_parity(o, r, eo, er, "%s n=%d" % (name, n))
+
+
+@pytest.mark.parametrize("pt", [1, 2, 4, 8, 12, 16])
+def test_single_workgroup_tilings(hip, pt):
+    n = min(1024 * pt, 9000)
+    P = synth.cad_part(n, seed=5).points.numpy()
+    eo, er = oracle.greedy32(P, n, 3)
+    o, r = run(hip, P, n, start=3, tune=hip.tuning(kernel=hip.KERNEL_WG, block=1024, per_thread=pt))
+    assert_parity(o, r, eo, er, "pt=%d" % pt)
+
+
+@pytest.mark.parametrize("pt", [1, 4, 8, 16])
+def test_cooperative_tilings(hip, pt):
+    n = 40000
+    P = synth.cad_part(n, seed=6).points.numpy()
+    k = 6000
+    eo, er = oracle.greedy32_grid(P, k, 11)
+    o, r = run(hip, P, k, start=11, tune=hip.tuning(kernel=hip.KERNEL_COOP, block=1024, per_thread=pt))
+    assert_parity(o, r, eo, er, "coop pt=%d" % pt)
+
+
+def test_cooperative_512_threads(hip):
+    n = 70000
+    P = synth.cad_part(n, seed=7).points.numpy()
+    eo, er = oracle.greedy32_grid(P, 3000, 0)
+    for pt in (24, 32):
+        o, r = run(hip, P, 3000, start=0, tune=hip.tuning(kernel=hip.KERNEL_COOP, block=512, per_thread=pt))
+        assert_parity(o, r, eo, er, "coop512 pt=%d" % pt)
+
+
+@pytest.mark.parametrize("name", ["duplicates", "lattice", "subnormal", "huge", "mixed_scale"])
+def test_cooperative_adversarial(hip, name):
+    n = 20000
+    P = cases.ADVERSARIAL[name](n, 77)
+    k = n // 2
+    eo, er = oracle.greedy32_grid(P, k, 123)
+    o, r = run(hip, P, k, start=123, tune=hip.tuning(kernel=hip.KERNEL_COOP, block=1024, per_thread=4))
+    assert_parity(o, r, eo, er, name)
+
+
+def test_all_kernels_agree_and_repeat(hip):
+    n = 12000
+    P = synth.sphere_and_box(n=n, seed=9).points.numpy()
+    base = run(hip, P, n, start=5, tune=hip.tuning(kernel=hip.KERNEL_WG))
+    for tune in (hip.tuning(kernel=hip.KERNEL_COOP, per_thread=1),
+                 hip.tuning(kernel=hip.KERNEL_COOP, per_thread=4),
+                 hip.tuning(kernel=hip.KERNEL_WG, per_thread=16),
+                 None):
+        for _ in range(2):
+            o, r = run(hip, P, n, start=5, tune=tune)
+            assert_parity(o, r, base[0], base[1], "tiling")
+
+
+def test_seeded_start_and_prefix_stability(hip):
+    import torch
+    n = 5000
+    P = cases.random_cloud(n, 3)
+    Pt = torch.from_numpy(P).cuda()
+    for seed in (0, 1, 2, 2**63 + 5):
+        o, r = hip.order(Pt, 300, seed=seed)
+        o = o.cpu().numpy()
+        assert o[0] == oracle.start_index(seed, n)
+        eo, er = oracle.greedy32(P, 300, int(o[0]))
+        assert_parity(o, r.cpu().numpy(), eo, er, "seed")
+        o2, _ = hip.order(Pt, 40, seed=seed)
+        assert np.array_equal(o2.cpu().numpy(), o[:40])
+
+
+def test_k_edges(hip):
+    import torch
+    P = cases.random_cloud(100, 1)
+    Pt = torch.from_numpy(P).cuda()
+    o, r = hip.order(Pt, 0)
+    assert o.numel() == 0
+    o, r = run(hip, P, 1, start=42)
+    assert o.tolist() == [42] and np.isinf(r[0])
+    eo, er = oracle.greedy32(P, 100, 42)
+    o, r = run(hip, P, 100, start=42)
+    assert_parity(o, r, eo, er, "k=n")
+    with pytest.raises(hip.BSError):
+        hip.order(Pt, 101)
+
+
+def test_nonfinite_input(hip):
+    import torch
+    for tune in (hip.tuning(kernel=hip.KERNEL_WG), hip.tuning(kernel=hip.KERNEL_COOP, per_thread=1)):
+        P = cases.random_cloud(3000, 2)
+        P[1234, 2] = np.nan
+        Pt = torch.from_numpy(P).cuda()
+        with pytest.raises(ValueError):
+            hip.order(Pt, 50, start=0, tune=tune)
+        o, r = hip.order(Pt, 50, start=0, tune=tune, check=False)
+        torch.cuda.synchronize()
+        assert (o.cpu().numpy() == -1).all() and np.isnan(r.cpu().numpy()).all()
+
+
+def test_cad_part_full_size(hip):
+    """4,194,304 candidates ordered to k = 262,144 (the bench's launch shape)."""
+    import torch
+    n, k = 4194304, 262144
+    P = synth.cad_part(n, seed=2).points.numpy()
+    st = oracle.start_index(2, n)
+    o, r = run(hip, P, k, seed=2)
+    eo, er = oracle.greedy32_grid(P, k, st)
+    assert_parity(o, r, eo, er, "cad_part full")
