@@ -131,6 +131,22 @@ int bs_order_ex(const float* d_points, const float* d_normals, const uint8_t* d_
                 void* d_workspace, size_t workspace_bytes,
                 const bs_tuning* tuning, void* stream);
 
+/*
+ * Profiling form of bs_order_ex (same ordering, same workspace size): also
+ * writes d_step_ticks[t] (device uint64[k]) = the device wall clock (see
+ * bs_wall_clock_hz) right after pick t is emitted, so that consecutive
+ * differences are per-step latencies.  start_index as in bs_order_ex, with
+ * -1 meaning SplitMix64(0) mod n.  Errors: as bs_order_ex, plus
+ * BS_ERR_INVALID_ARG for a null tick buffer when k > 0.
+ */
+int bs_order_profile(const float* d_points, int64_t n, int64_t k, int64_t start_index,
+                     int32_t* d_out_order, float* d_out_radius, uint64_t* d_step_ticks,
+                     void* d_workspace, size_t workspace_bytes, const bs_tuning* tuning,
+                     void* stream);
+
+/* Frequency of the device wall clock used by bs_order_profile (Hz); 0 on error. */
+double bs_wall_clock_hz(void);
+
 /* Workspace bytes bs_order_ex needs for (n, k, tuning); 0 if unsupported. */
 size_t bs_workspace_size(int64_t n, int64_t k, const bs_tuning* tuning);
 

@@ -87,6 +87,10 @@ def load():
     lib.bs_order.restype = i32
     lib.bs_order_ex.argtypes = [vp, vp, vp, i64, i64, u64, i64, vp, vp, vp, sz, tp, vp]
     lib.bs_order_ex.restype = i32
+    lib.bs_order_profile.argtypes = [vp, i64, i64, i64, vp, vp, vp, vp, sz, tp, vp]
+    lib.bs_order_profile.restype = i32
+    lib.bs_wall_clock_hz.argtypes = []
+    lib.bs_wall_clock_hz.restype = ctypes.c_double
     _lib = lib
     return lib
 
@@ -180,3 +184,28 @@ def order(points, k: Optional[int] = None, seed: int = 0, *, normals=None, color
         if int(out_order[0]) == -1:
             raise ValueError("non-finite candidate coordinates")
     return out_order, out_radius
+
+
+def wall_clock_hz() -> float:
+    return float(load().bs_wall_clock_hz())
+
+
+def order_profile(points, k: int, start: int = -1, tune: Optional[Tuning] = None, stream=None):
+    """Ordering plus per-step device timestamps.
+
+    Returns ``(order, radius, ticks)`` where ``ticks`` is uint64 [k] (as
+    int64 tensor) of the device wall clock after each pick."""
+    import torch
+    lib = load()
+    points = _prep_points(points)
+    n = int(points.shape[0])
+    dev = points.device
+    tp = ctypes.byref(tune) if tune is not None else None
+    need = int(lib.bs_workspace_size(n, k, tp))
+    ws = torch.empty(max(need, 1), dtype=torch.uint8, device=dev)
+    o = torch.empty(k, dtype=torch.int32, device=dev)
+    r = torch.empty(k, dtype=torch.float32, device=dev)
+    ticks = torch.zeros(k, dtype=torch.int64, device=dev)
+    _check(lib.bs_order_profile(_ptr(points), n, k, start, _ptr(o), _ptr(r), _ptr(ticks), _ptr(ws),
+                                int(ws.numel()), tp, _stream_handle(stream)))
+    return o, r, ticks

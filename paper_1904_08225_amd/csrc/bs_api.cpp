@@ -7,6 +7,7 @@
 #include <cstring>
 #include <mutex>
 
+#include "bs_grid.h"
 #include "bs_internal.h"
 
 namespace bs {
@@ -39,36 +40,56 @@ bool tuning_clean(const bs_tuning* t) {
     return t->kernel >= BS_KERNEL_AUTO && t->kernel <= BS_KERNEL_GRID;
 }
 
-// Resolve the kernel and, for resident kernels, the launch shape.
-int plan_single(int64_t n, int64_t k, const bs_tuning* t, int* kernel, ScanShape* shape) {
+constexpr float kDefaultCellPoints = 32.f;
+constexpr int64_t kAutoResidentMax = 16384;  // one workgroup holds these in VGPRs
+
+struct Plan {
+    int kernel = 0;
+    ScanShape shape;     // resident kernels
+    int grid_block = 0;  // grid kernel workgroup size
+    float cell_points = kDefaultCellPoints;
+};
+
+// Resolve the kernel and its launch shape.
+int plan_single(int64_t n, int64_t k, const bs_tuning* t, Plan* p) {
     const int cus = device_cus() > 0 ? device_cus() : 256;
-    int want = t ? t->kernel : BS_KERNEL_AUTO;
+    const int want = t ? t->kernel : BS_KERNEL_AUTO;
     const int wb = t ? t->block : 0, wp = t ? t->per_thread : 0, wg = t ? t->groups : 0;
     (void)k;
+    p->cell_points = (t && t->cell_points > 0.f) ? t->cell_points : kDefaultCellPoints;
+    if (p->cell_points < 1.f) p->cell_points = 1.f;
+    if (want == BS_KERNEL_GRID || (want == BS_KERNEL_AUTO && n > kAutoResidentMax)) {
+        int b = wb > 0 ? wb : grid_block_size(n);
+        if (b != 256 && b != 1024)
+            return set_error(BS_ERR_UNSUPPORTED, "grid kernel block must be 256 or 1024, got %d", b);
+        p->kernel = BS_KERNEL_GRID;
+        p->grid_block = b;
+        return BS_OK;
+    }
     if (want == BS_KERNEL_AUTO) {
-        if (choose_scan_shape(n, cus, wb, wp, wg, shape)) {
-            *kernel = shape->groups > 1 ? BS_KERNEL_COOP : BS_KERNEL_WG;
+        if (choose_scan_shape(n, cus, wb, wp, wg, &p->shape)) {
+            p->kernel = p->shape.groups > 1 ? BS_KERNEL_COOP : BS_KERNEL_WG;
             return BS_OK;
         }
         return set_error(BS_ERR_UNSUPPORTED, "no kernel holds n=%lld candidates", (long long)n);
     }
     if (want == BS_KERNEL_WG || want == BS_KERNEL_COOP) {
-        if (!choose_scan_shape(n, cus, wb, wp, want == BS_KERNEL_WG ? 1 : wg, shape))
+        if (!choose_scan_shape(n, cus, wb, wp, want == BS_KERNEL_WG ? 1 : wg, &p->shape))
             return set_error(BS_ERR_UNSUPPORTED, "resident kernel cannot hold n=%lld with this tuning",
                              (long long)n);
-        if (want == BS_KERNEL_WG && shape->groups != 1)
+        if (want == BS_KERNEL_WG && p->shape.groups != 1)
             return set_error(BS_ERR_UNSUPPORTED, "n=%lld does not fit one workgroup", (long long)n);
-        if (want == BS_KERNEL_COOP && shape->groups > cus * 2)
-            return set_error(BS_ERR_UNSUPPORTED, "cooperative grid of %d groups too large", shape->groups);
-        *kernel = want;
+        if (want == BS_KERNEL_COOP && p->shape.groups > cus * 2)
+            return set_error(BS_ERR_UNSUPPORTED, "cooperative grid of %d groups too large", p->shape.groups);
+        p->kernel = want;
         return BS_OK;
     }
     return set_error(BS_ERR_UNSUPPORTED, "kernel %d not available", want);
 }
 
-size_t workspace_for(int kernel, const ScanShape& s) {
-    (void)kernel;
-    return scan_workspace_bytes(s);
+size_t workspace_for(int64_t n, const Plan& p) {
+    if (p.kernel == BS_KERNEL_GRID) return grid_layout(n, p.grid_block).total;
+    return scan_workspace_bytes(p.shape);
 }
 
 }  // namespace
@@ -117,27 +138,23 @@ int64_t bs_start_index(uint64_t seed, int64_t n) {
 }
 
 int bs_auto_kernel(int64_t n, int64_t k) {
-    int kernel = 0;
-    ScanShape s;
+    Plan p;
     if (n < 1 || n >= (int64_t(1) << 31)) return -1;
-    if (plan_single(n, k, nullptr, &kernel, &s) != BS_OK) return -1;
-    return kernel;
+    if (plan_single(n, k, nullptr, &p) != BS_OK) return -1;
+    return p.kernel;
 }
 
 size_t bs_workspace_size(int64_t n, int64_t k, const bs_tuning* tuning) {
     if (n < 1 || n >= (int64_t(1) << 31) || k < 0 || k > n || !tuning_clean(tuning)) return 0;
-    int kernel = 0;
-    ScanShape s;
-    if (plan_single(n, k, tuning, &kernel, &s) != BS_OK) return 0;
-    return workspace_for(kernel, s);
+    Plan p;
+    if (plan_single(n, k, tuning, &p) != BS_OK) return 0;
+    return workspace_for(n, p);
 }
 
-int bs_order_ex(const float* d_points, const float* d_normals, const uint8_t* d_colors,
-                int64_t n, int64_t k, uint64_t seed, int64_t start_index,
-                int32_t* d_out_order, float* d_out_radius, void* d_workspace,
-                size_t workspace_bytes, const bs_tuning* tuning, void* stream) {
-    (void)d_normals;
-    (void)d_colors;
+static int order_impl(const float* d_points, int64_t n, int64_t k, uint64_t seed,
+                      int64_t start_index, int32_t* d_out_order, float* d_out_radius,
+                      uint64_t* d_ticks, void* d_workspace, size_t workspace_bytes,
+                      const bs_tuning* tuning, void* stream) {
     if (k < 0) return set_error(BS_ERR_INVALID_ARG, "k=%lld < 0", (long long)k);
     if (k == 0) return BS_OK;
     if (n < 1 || n >= (int64_t(1) << 31))
@@ -149,26 +166,57 @@ int bs_order_ex(const float* d_points, const float* d_normals, const uint8_t* d_
         return set_error(BS_ERR_INVALID_ARG, "start_index=%lld outside [-1, n)", (long long)start_index);
     const int64_t start = start_index >= 0 ? start_index : bs_start_index(seed, n);
 
-    int kernel = 0;
-    ScanShape shape;
-    int rc = plan_single(n, k, tuning, &kernel, &shape);
+    Plan plan;
+    int rc = plan_single(n, k, tuning, &plan);
     if (rc != BS_OK) return rc;
-    const size_t need = workspace_for(kernel, shape);
+    const size_t need = workspace_for(n, plan);
     if (!d_workspace || workspace_bytes < need)
         return set_error(BS_ERR_INVALID_ARG, "workspace %zu bytes < %zu needed", workspace_bytes, need);
     if (reinterpret_cast<uintptr_t>(d_workspace) % kAlign != 0)
         return set_error(BS_ERR_INVALID_ARG, "workspace not %zu-byte aligned", kAlign);
 
     hipStream_t st = reinterpret_cast<hipStream_t>(stream);
-    DevHeader* hdr = reinterpret_cast<DevHeader*>(d_workspace);
-    void* scratch = static_cast<char*>(d_workspace) + align_up(sizeof(DevHeader));
-    hipError_t e = launch_init_header(hdr, st);
-    if (e == hipSuccess) e = launch_validate(d_points, n, hdr, st);
-    if (e == hipSuccess)
-        e = launch_scan(shape, d_points, int(n), int(k), int(start), d_out_order, d_out_radius, hdr,
-                        scratch, st);
+    hipError_t e = hipSuccess;
+    if (plan.kernel == BS_KERNEL_GRID) {
+        e = launch_grid(d_points, int(n), int(k), int(start), d_out_order, d_out_radius, d_workspace,
+                        plan.cell_points, plan.grid_block, d_ticks, st);
+    } else {
+        DevHeader* hdr = reinterpret_cast<DevHeader*>(d_workspace);
+        void* scratch = static_cast<char*>(d_workspace) + align_up(sizeof(DevHeader));
+        e = launch_init_header(hdr, st);
+        if (e == hipSuccess) e = launch_validate(d_points, n, hdr, st);
+        if (e == hipSuccess)
+            e = launch_scan(plan.shape, d_points, int(n), int(k), int(start), d_out_order, d_out_radius,
+                            hdr, scratch, d_ticks, st);
+    }
     if (e != hipSuccess) return set_error(BS_ERR_HIP, "launch failed: %s", hipGetErrorString(e));
     return BS_OK;
+}
+
+int bs_order_ex(const float* d_points, const float* d_normals, const uint8_t* d_colors,
+                int64_t n, int64_t k, uint64_t seed, int64_t start_index,
+                int32_t* d_out_order, float* d_out_radius, void* d_workspace,
+                size_t workspace_bytes, const bs_tuning* tuning, void* stream) {
+    (void)d_normals;
+    (void)d_colors;
+    return order_impl(d_points, n, k, seed, start_index, d_out_order, d_out_radius, nullptr,
+                      d_workspace, workspace_bytes, tuning, stream);
+}
+
+int bs_order_profile(const float* d_points, int64_t n, int64_t k, int64_t start_index,
+                     int32_t* d_out_order, float* d_out_radius, uint64_t* d_step_ticks,
+                     void* d_workspace, size_t workspace_bytes, const bs_tuning* tuning,
+                     void* stream) {
+    if (k > 0 && !d_step_ticks) return set_error(BS_ERR_INVALID_ARG, "null step tick buffer");
+    return order_impl(d_points, n, k, 0, start_index, d_out_order, d_out_radius, d_step_ticks,
+                      d_workspace, workspace_bytes, tuning, stream);
+}
+
+double bs_wall_clock_hz(void) {
+    int dev = 0, khz = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return 0.0;
+    if (hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, dev) != hipSuccess) return 0.0;
+    return double(khz) * 1000.0;
 }
 
 int bs_order(const float* d_points, const float* d_normals, const uint8_t* d_colors, int64_t n,
@@ -187,7 +235,7 @@ int bs_order(const float* d_points, const float* d_normals, const uint8_t* d_col
     if (e != hipSuccess || !ws) return set_error(BS_ERR_OUT_OF_MEMORY, "workspace of %zu bytes", need);
     int rc = bs_order_ex(d_points, d_normals, d_colors, n, k, seed, -1, d_out_order, d_out_radius,
                          ws, need, nullptr, stream);
-    hipFreeAsync(ws, st);
+    (void)hipFreeAsync(ws, st);
     return rc;
 }
 

@@ -1,0 +1,53 @@
+// bs_grid.h -- internal declarations of the grid-pruned ordering.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+namespace bs {
+
+// Device-written description of one object's grid (chosen on the device).
+struct GridHeader {
+    uint32_t hist[12];   // adjacent sorted pairs first separated at each Morton level
+    int32_t level;       // grid level: cells of side extent / 2^level
+    int32_t C;           // occupied cells
+    int32_t B;           // cells per block (power of two >= 64)
+    int32_t NB;          // blocks (<= workgroup size)
+    int32_t start_pos;   // sorted position of the start candidate
+    int32_t start_cell;  // its cell
+    int32_t pad[46];
+};
+static_assert(sizeof(GridHeader) == 256, "grid header size");
+
+// What the ordering loop needs for one object.
+struct GridObject {
+    int k;
+    uint32_t start_id;
+    int C, B, NB;
+    int start_pos, start_cell;
+    float4* xyzm;              // [n] Morton-sorted x, y, z, m (m = -1 once chosen)
+    const uint32_t* ids;       // [n] original index of each sorted candidate
+    const float4* cstat;       // [2C] (lo.xyz, start) (hi.xyz, count)
+    uint4* cdyn;               // [2C] (key lo, key hi, pos, -) (x, y, z, -)
+    const float4* bstat;       // [2NB] block boxes
+    const uint4* bdyn;         // [2NB] initial block bests (key lo, key hi, pos, cell) (x, y, z, -)
+    int32_t* order;
+    float* radius;
+    uint64_t* ticks;           // optional: device wall clock after each step
+};
+
+// Byte offsets of the grid workspace pieces.
+struct GridLayout {
+    size_t dev_header, grid_header, codes, vals, codes_sorted, ids, flags, cellidx, cstart, xyzm,
+        cstat, cdyn, bstat, bdyn, temp;
+    size_t temp_bytes;
+    size_t total;
+};
+
+GridLayout grid_layout(int64_t n, int block);
+int grid_block_size(int64_t n);
+hipError_t launch_grid(const float* pts, int n, int k, int start, int32_t* order, float* radius,
+                       void* ws, float target, int block, uint64_t* ticks, hipStream_t st);
+
+}  // namespace bs

@@ -45,7 +45,7 @@ hipError_t launch_init_header(DevHeader* hdr, hipStream_t st);
 hipError_t launch_validate(const float* pts, int64_t n, DevHeader* hdr, hipStream_t st);
 hipError_t launch_scan(const ScanShape& s, const float* pts, int n, int k, int start,
                        int32_t* order, float* radius, DevHeader* hdr, void* scratch,
-                       hipStream_t st);
+                       uint64_t* ticks, hipStream_t st);
 
 // Error reporting (bs_api.cpp).
 int set_error(int code, const char* fmt, ...);

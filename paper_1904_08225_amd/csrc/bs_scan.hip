@@ -154,7 +154,8 @@ template <int BLOCK, int P, bool MULTI>
 __global__ void __launch_bounds__(BLOCK)
     scan_kernel(const float* __restrict__ pts, int n, int k, int start,
                 int32_t* __restrict__ order, float* __restrict__ radius,
-                DevHeader* __restrict__ hdr, uint64_t* __restrict__ slots) {
+                DevHeader* __restrict__ hdr, uint64_t* __restrict__ slots,
+                uint64_t* __restrict__ ticks) {
     constexpr int NW = BLOCK / 64;
     __shared__ uint64_t s_key[2][NW];
     __shared__ float s_pos[2][NW][4];
@@ -203,6 +204,7 @@ __global__ void __launch_bounds__(BLOCK)
     if (g == 0 && tid == 0) {
         order[0] = c;
         if (radius) radius[0] = INFINITY;
+        if (ticks) ticks[0] = wall_clock64();
     }
     if (tid == 0) s_abort = 0;
     __syncthreads();
@@ -330,11 +332,13 @@ __global__ void __launch_bounds__(BLOCK)
         if (g == 0 && tid == 0) {
             order[t] = c;
             if (radius) radius[t] = sqrtf(key_value(best));
+            if (ticks) ticks[t] = wall_clock64();
         }
     }
 }
 
-using ScanFn = void (*)(const float*, int, int, int, int32_t*, float*, DevHeader*, uint64_t*);
+using ScanFn = void (*)(const float*, int, int, int, int32_t*, float*, DevHeader*, uint64_t*,
+                       uint64_t*);
 
 struct ScanEntry {
     int block, per_thread;
@@ -420,21 +424,21 @@ hipError_t launch_validate(const float* pts, int64_t n, DevHeader* hdr, hipStrea
 
 hipError_t launch_scan(const ScanShape& s, const float* pts, int n, int k, int start,
                        int32_t* order, float* radius, DevHeader* hdr, void* scratch,
-                       hipStream_t st) {
+                       uint64_t* ticks, hipStream_t st) {
     const ScanEntry* e = find_entry(s.block, s.per_thread);
     if (!e) return hipErrorInvalidValue;
     uint64_t* slots = reinterpret_cast<uint64_t*>(scratch);
     if (s.groups <= 1) {
         hipLaunchKernelGGL(e->single, dim3(1), dim3(s.block), 0, st, pts, n, k, start, order,
-                           radius, hdr, slots);
+                           radius, hdr, slots, ticks);
         return hipGetLastError();
     }
     // stale records from an earlier call must not carry matching tags
     hipLaunchKernelGGL(clear_slots_kernel, dim3(1), dim3(256), 0, st, slots, 2 * s.groups * kRecWords);
     hipError_t err = hipGetLastError();
     if (err != hipSuccess) return err;
-    void* args[] = {(void*)&pts, (void*)&n, (void*)&k, (void*)&start, (void*)&order,
-                    (void*)&radius, (void*)&hdr, (void*)&slots};
+    void* args[] = {(void*)&pts,   (void*)&n,   (void*)&k,     (void*)&start, (void*)&order,
+                    (void*)&radius, (void*)&hdr, (void*)&slots, (void*)&ticks};
     return hipLaunchCooperativeKernel(reinterpret_cast<const void*>(e->multi), dim3(s.groups),
                                       dim3(s.block), args, 0, st);
 }

@@ -1,0 +1,89 @@
+"""GPU parity of the uniform-grid radius-pruned kernel against the CPU oracle.
+
+The pruning must not change a single bit: orders and radii equal the plain
+oracle's (small cases) or the exact grid oracle's (large cases, itself
+pinned bit-exact to the plain oracle).
+"""
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from tests import cases
+from tests.test_gpu_scan import assert_parity, run
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.mark.parametrize("block", [256, 1024])
+@pytest.mark.parametrize("name", sorted(cases.ADVERSARIAL))
+def test_grid_adversarial(hip, name, block):
+    for n in (1, 2, 3, 65, 1000, 4097):
+        P = cases.ADVERSARIAL[name](n, 41 + n)
+        st = (5 * n) // 7
+        eo, er = oracle.greedy32(P, n, st)
+        o, r = run(hip, P, n, start=st, tune=hip.tuning(kernel=hip.KERNEL_GRID, block=block))
+        assert_parity(o, r, eo, er, "grid %s n=%d block=%d" % (name, n, block))
+
+
+@pytest.mark.parametrize("cell_points", [1.0, 4.0, 32.0, 200.0])
+def test_grid_cell_sizes(hip, cell_points):
+    n = 30000
+    P = synth.cad_part(n, seed=12).points.numpy()
+    k = n // 3
+    eo, er = oracle.greedy32_grid(P, k, 17)
+    for block in (256, 1024):
+        o, r = run(hip, P, k, start=17,
+                   tune=hip.tuning(kernel=hip.KERNEL_GRID, block=block, cell_points=cell_points))
+        assert_parity(o, r, eo, er, "cell_points=%g block=%d" % (cell_points, block))
+
+
+def test_grid_sphere_box_full_order(hip):
+    s = synth.sphere_and_box(n=16384, seed=1)
+    P = s.points.numpy()
+    st = oracle.start_index(1, P.shape[0])
+    eo, er = oracle.greedy32(P, 16384, st)
+    o, r = run(hip, P, 16384, start=st, tune=hip.tuning(kernel=hip.KERNEL_GRID))
+    assert_parity(o, r, eo, er, "grid sphere_and_box")
+
+
+def test_grid_many_duplicates_and_ties(hip):
+    # 40 distinct positions repeated: long runs of zero-distance picks
+    P = cases.with_duplicates(20000, 5, groups=40)
+    eo, er = oracle.greedy32_grid(P, 20000, 7)
+    o, r = run(hip, P, 20000, start=7, tune=hip.tuning(kernel=hip.KERNEL_GRID))
+    assert_parity(o, r, eo, er, "duplicates")
+    L = cases.integer_lattice(30, 30, 30)
+    eo, er = oracle.greedy32_grid(L, 27000, 0)
+    o, r = run(hip, L, 27000, start=0, tune=hip.tuning(kernel=hip.KERNEL_GRID))
+    assert_parity(o, r, eo, er, "lattice ties")
+
+
+def test_grid_nonfinite(hip):
+    import torch
+    P = cases.random_cloud(50000, 2)
+    P[777, 0] = np.inf
+    Pt = torch.from_numpy(P).cuda()
+    o, r = hip.order(Pt, 100, start=0, tune=hip.tuning(kernel=hip.KERNEL_GRID), check=False)
+    torch.cuda.synchronize()
+    assert (o.cpu().numpy() == -1).all() and np.isnan(r.cpu().numpy()).all()
+
+
+def test_grid_repeat_and_agrees_with_resident(hip):
+    n = 16000
+    P = synth.cad_part(n, seed=21).points.numpy()
+    a = run(hip, P, 4000, start=3, tune=hip.tuning(kernel=hip.KERNEL_WG))
+    for _ in range(2):
+        b = run(hip, P, 4000, start=3, tune=hip.tuning(kernel=hip.KERNEL_GRID))
+        assert_parity(b[0], b[1], a[0], a[1], "grid vs resident")
+
+
+def test_grid_cad_part_full_size(hip):
+    """4,194,304 candidates to k = 262,144 through the automatic choice."""
+    n, k = 4194304, 262144
+    P = synth.cad_part(n, seed=2).points.numpy()
+    st = oracle.start_index(2, n)
+    assert hip.auto_kernel(n, k) == hip.KERNEL_GRID
+    o, r = run(hip, P, k, seed=2)
+    eo, er = oracle.greedy32_grid(P, k, st)
+    assert_parity(o, r, eo, er, "grid cad_part full")

@@ -144,12 +144,11 @@ def test_nonfinite_input(hip):
         assert (o.cpu().numpy() == -1).all() and np.isnan(r.cpu().numpy()).all()
 
 
-def test_cad_part_full_size(hip):
-    """4,194,304 candidates ordered to k = 262,144 (the bench's launch shape)."""
-    import torch
+def test_cooperative_cad_part_full_size(hip):
+    """4,194,304 candidates ordered to k = 262,144 by the cooperative resident scan."""
     n, k = 4194304, 262144
     P = synth.cad_part(n, seed=2).points.numpy()
     st = oracle.start_index(2, n)
-    o, r = run(hip, P, k, seed=2)
+    o, r = run(hip, P, k, start=st, tune=hip.tuning(kernel=hip.KERNEL_COOP, block=1024, per_thread=16))
     eo, er = oracle.greedy32_grid(P, k, st)
     assert_parity(o, r, eo, er, "cad_part full")
