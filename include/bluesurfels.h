@@ -157,6 +157,54 @@ int64_t bs_start_index(uint64_t seed, int64_t n);
 /* Which kernel the automatic choice uses for (n, k) (a bs_kernel value). */
 int bs_auto_kernel(int64_t n, int64_t k);
 
+/* -------------------------------------------------------------- batched */
+
+/*
+ * Batched ordering of many independent objects (the per-node approximations
+ * of a scene, paper Sec. 3.4 and Sec. 5: the sampling parallelises over the
+ * objects of a scene).  Every object's result is bit-identical to ordering
+ * it alone with bs_order(seed = h_seed[j]).
+ *
+ * Candidates of all objects lie in one device array in CSR form: object j
+ * owns rows h_offsets[j] .. h_offsets[j+1]-1 of d_points (float[N][3]).
+ * Its k_j = h_k[j] picks are written to rows out_off[j] .. out_off[j]+k_j-1
+ * of d_out_order / d_out_radius, where out_off is the exclusive prefix sum
+ * of h_k (bs_batch_out_offsets); indices are local to the object
+ * (0 .. n_j-1).
+ *
+ * The plan copies its host arrays; it owns a few small device arrays and,
+ * after the first execute, a captured hipGraph of the ordering launch (a
+ * queue reset and one persistent work-queue kernel whose workgroups order
+ * objects largest-k first).  Preprocessing (per-object grids) is enqueued
+ * as ordinary launches before the graph.
+ *
+ *   h_offsets  host int64[m+1], non-decreasing, h_offsets[0] = 0, total < 2^31
+ *   h_k        host int64[m], 0 <= k_j <= n_j
+ *   h_seed     host uint64[m] or NULL (all 0): start_j = SplitMix64(seed_j) mod n_j
+ *   tuning     NULL or cell_points (target candidates per grid cell, >= 8)
+ * Errors: BS_ERR_INVALID_ARG (bad sizes), BS_ERR_OUT_OF_MEMORY, BS_ERR_HIP.
+ */
+typedef struct bs_batch_plan bs_batch_plan;
+int bs_batch_plan_create(const int64_t* h_offsets, const int64_t* h_k, const uint64_t* h_seed,
+                         int32_t m, const bs_tuning* tuning, bs_batch_plan** out_plan);
+/* Device workspace bytes bs_batch_plan_execute needs (256-byte aligned). */
+size_t bs_batch_workspace_size(const bs_batch_plan* plan);
+/* Sum of k over the objects (length of the output arrays). */
+int64_t bs_batch_total_k(const bs_batch_plan* plan);
+/* Writes the m+1 output offsets (exclusive prefix sum of h_k) to host memory. */
+int bs_batch_out_offsets(const bs_batch_plan* plan, int64_t* h_out_offsets);
+/*
+ * Enqueue the batched ordering on `stream`.  d_out_radius may be NULL.
+ * Objects whose candidates contain a non-finite coordinate get order -1 and
+ * radius NaN; the others are unaffected.  Calls with the same plan are
+ * serialised by the plan; distinct plans may run concurrently on distinct
+ * workspaces.
+ */
+int bs_batch_plan_execute(bs_batch_plan* plan, const float* d_points, int32_t* d_out_order,
+                          float* d_out_radius, void* d_workspace, size_t workspace_bytes,
+                          void* stream);
+void bs_batch_plan_destroy(bs_batch_plan* plan);
+
 #ifdef __cplusplus
 }
 #endif

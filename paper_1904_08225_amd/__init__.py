@@ -91,6 +91,18 @@ def load():
     lib.bs_order_profile.restype = i32
     lib.bs_wall_clock_hz.argtypes = []
     lib.bs_wall_clock_hz.restype = ctypes.c_double
+    lib.bs_batch_plan_create.argtypes = [vp, vp, vp, ctypes.c_int32, tp, ctypes.POINTER(vp)]
+    lib.bs_batch_plan_create.restype = i32
+    lib.bs_batch_workspace_size.argtypes = [vp]
+    lib.bs_batch_workspace_size.restype = sz
+    lib.bs_batch_total_k.argtypes = [vp]
+    lib.bs_batch_total_k.restype = i64
+    lib.bs_batch_out_offsets.argtypes = [vp, vp]
+    lib.bs_batch_out_offsets.restype = i32
+    lib.bs_batch_plan_execute.argtypes = [vp, vp, vp, vp, vp, sz, vp]
+    lib.bs_batch_plan_execute.restype = i32
+    lib.bs_batch_plan_destroy.argtypes = [vp]
+    lib.bs_batch_plan_destroy.restype = None
     _lib = lib
     return lib
 
@@ -209,3 +221,65 @@ def order_profile(points, k: int, start: int = -1, tune: Optional[Tuning] = None
     _check(lib.bs_order_profile(_ptr(points), n, k, start, _ptr(o), _ptr(r), _ptr(ticks), _ptr(ws),
                                 int(ws.numel()), tp, _stream_handle(stream)))
     return o, r, ticks
+
+
+class BatchPlan:
+    """Batched ordering of many objects in CSR form (``bs_batch_plan_*``).
+
+    ``offsets``: int sequence [m+1] of candidate row offsets, ``ks``: [m]
+    picks per object, ``seeds``: [m] start seeds (default 0).  ``execute``
+    takes the concatenated float32 [N, 3] candidates on the GPU and returns
+    ``(order, radius)`` of length ``total_k``; object j's picks are
+    ``order[out_offsets[j]:out_offsets[j+1]]`` (local indices).
+    """
+
+    def __init__(self, offsets, ks, seeds=None, tune: Optional[Tuning] = None):
+        import numpy as np
+        lib = load()
+        self._lib = lib
+        offs = np.ascontiguousarray(np.asarray(offsets, dtype=np.int64))
+        kk = np.ascontiguousarray(np.asarray(ks, dtype=np.int64))
+        m = int(kk.shape[0])
+        if offs.shape[0] != m + 1:
+            raise ValueError("offsets must have m + 1 entries")
+        sd = None if seeds is None else np.ascontiguousarray(
+            np.asarray([int(s) & (2**64 - 1) for s in seeds], dtype=np.uint64))
+        self.m = m
+        self._plan = ctypes.c_void_p()
+        tp = ctypes.byref(tune) if tune is not None else None
+        _check(lib.bs_batch_plan_create(offs.ctypes.data_as(ctypes.c_void_p), kk.ctypes.data_as(ctypes.c_void_p),
+                                        None if sd is None else sd.ctypes.data_as(ctypes.c_void_p),
+                                        m, tp, ctypes.byref(self._plan)))
+        self.total_k = int(lib.bs_batch_total_k(self._plan))
+        self.workspace_bytes = int(lib.bs_batch_workspace_size(self._plan))
+        oo = np.zeros(m + 1, dtype=np.int64)
+        _check(lib.bs_batch_out_offsets(self._plan, oo.ctypes.data_as(ctypes.c_void_p)))
+        self.out_offsets = oo
+        self._ws = None
+
+    def execute(self, points, out_order=None, out_radius=None, workspace=None, stream=None):
+        import torch
+        points = _prep_points(points) if points.shape[0] > 0 else points
+        dev = points.device
+        if out_order is None:
+            out_order = torch.empty(max(self.total_k, 1), dtype=torch.int32, device=dev)
+        if out_radius is None:
+            out_radius = torch.empty(max(self.total_k, 1), dtype=torch.float32, device=dev)
+        if workspace is None:
+            if self._ws is None or self._ws.numel() < self.workspace_bytes:
+                self._ws = torch.empty(max(self.workspace_bytes, 1), dtype=torch.uint8, device=dev)
+            workspace = self._ws
+        _check(self._lib.bs_batch_plan_execute(self._plan, _ptr(points), _ptr(out_order), _ptr(out_radius),
+                                               _ptr(workspace), int(workspace.numel()), _stream_handle(stream)))
+        return out_order[: self.total_k], out_radius[: self.total_k]
+
+    def close(self):
+        if getattr(self, "_plan", None):
+            self._lib.bs_batch_plan_destroy(self._plan)
+            self._plan = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

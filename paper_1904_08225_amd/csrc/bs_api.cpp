@@ -60,8 +60,8 @@ int plan_single(int64_t n, int64_t k, const bs_tuning* t, Plan* p) {
     if (p->cell_points < 1.f) p->cell_points = 1.f;
     if (want == BS_KERNEL_GRID || (want == BS_KERNEL_AUTO && n > kAutoResidentMax)) {
         int b = wb > 0 ? wb : grid_block_size(n);
-        if (b != 256 && b != 1024)
-            return set_error(BS_ERR_UNSUPPORTED, "grid kernel block must be 256 or 1024, got %d", b);
+        if (b != 256 && b != 512 && b != 1024)
+            return set_error(BS_ERR_UNSUPPORTED, "grid kernel block must be 256, 512 or 1024, got %d", b);
         p->kernel = BS_KERNEL_GRID;
         p->grid_block = b;
         return BS_OK;
@@ -237,6 +237,51 @@ int bs_order(const float* d_points, const float* d_normals, const uint8_t* d_col
                          ws, need, nullptr, stream);
     (void)hipFreeAsync(ws, st);
     return rc;
+}
+
+struct bs_batch_plan {
+    bs::BatchPlan* p;
+    int32_t m_all;
+};
+
+int bs_batch_plan_create(const int64_t* h_offsets, const int64_t* h_k, const uint64_t* h_seed,
+                         int32_t m, const bs_tuning* tuning, bs_batch_plan** out_plan) {
+    if (!out_plan) return set_error(BS_ERR_INVALID_ARG, "null plan pointer");
+    *out_plan = nullptr;
+    if (!tuning_clean(tuning)) return set_error(BS_ERR_INVALID_ARG, "bad tuning struct");
+    const float target = (tuning && tuning->cell_points > 0.f) ? tuning->cell_points : kDefaultCellPoints;
+    bs::BatchPlan* p = nullptr;
+    const int rc = batch_plan_create(h_offsets, h_k, h_seed, m, target, &p);
+    if (rc != BS_OK) return rc;
+    *out_plan = new bs_batch_plan{p, m};
+    return BS_OK;
+}
+
+size_t bs_batch_workspace_size(const bs_batch_plan* plan) {
+    return plan ? batch_workspace_bytes(plan->p) : 0;
+}
+
+int64_t bs_batch_total_k(const bs_batch_plan* plan) { return plan ? batch_total_k(plan->p) : 0; }
+
+int bs_batch_out_offsets(const bs_batch_plan* plan, int64_t* h_out_offsets) {
+    if (!plan || !h_out_offsets) return set_error(BS_ERR_INVALID_ARG, "null argument");
+    const int64_t* o = batch_out_offsets(plan->p);
+    for (int32_t j = 0; j <= plan->m_all; ++j) h_out_offsets[j] = o[j];
+    return BS_OK;
+}
+
+int bs_batch_plan_execute(bs_batch_plan* plan, const float* d_points, int32_t* d_out_order,
+                          float* d_out_radius, void* d_workspace, size_t workspace_bytes,
+                          void* stream) {
+    if (!plan) return set_error(BS_ERR_INVALID_ARG, "null plan");
+    return batch_plan_execute(plan->p, d_points, d_out_order, d_out_radius, d_workspace,
+                              workspace_bytes, reinterpret_cast<hipStream_t>(stream));
+}
+
+void bs_batch_plan_destroy(bs_batch_plan* plan) {
+    if (!plan) return;
+    batch_plan_free(plan->p);
+    delete plan;
 }
 
 }  // extern "C"

@@ -1,0 +1,753 @@
+// bs_batch.hip -- batched ordering: thousands of objects in one persistent
+// work-queue launch captured in a hipGraph.
+//
+// The paper generates one approximation per scene-graph node and notes that
+// the sampling is easily parallelised over the objects of a scene (Sec. 3.4
+// hierarchical generation, Sec. 5 preprocessing).  Here every object is an
+// independent greedy permutation (same result, bit for bit, as ordering it
+// alone): the grid of every object is built by segmented preprocessing
+// kernels over all candidates at once (sort key = object id : Morton code),
+// then a persistent kernel whose workgroups pop objects from a device queue,
+// largest k first, runs the grid-pruned ordering loop of each object.
+#pragma clang fp contract(off)
+
+#include <hip/hip_runtime.h>
+#include <hipcub/hipcub.hpp>
+
+#include <algorithm>
+#include <cstring>
+#include <mutex>
+#include <numeric>
+#include <vector>
+
+#include "bs_grid.h"
+#include "bs_grid_device.h"
+#include "bs_internal.h"
+
+namespace bs {
+
+namespace {
+
+constexpr int kBatchBlock = 256;         // threads per ordering workgroup
+constexpr int kBatchMaxBlocks = 1024;    // blocks of 64 cells per object
+constexpr int kObjBits = 30;             // Morton bits below the object id
+
+// Per-object device state of the batched preprocessing (128 bytes).
+struct ObjHdr {
+    uint32_t bbox[6];  // order-preserving encodings: min x,y,z, max x,y,z
+    uint32_t nonfinite;
+    uint32_t hist[11];
+    int32_t level, cell_base, C, NB, block_base, nsb, sb_base, start_pos, start_cell;
+    int32_t pad[5];
+};
+static_assert(sizeof(ObjHdr) == 128, "object header size");
+
+__device__ __forceinline__ uint32_t ord_encode_f(float f) {
+    const uint32_t u = __float_as_uint(f);
+    return (u & 0x80000000u) ? ~u : (u | 0x80000000u);
+}
+
+// object of global candidate i: largest j with offs[j] <= i
+__device__ __forceinline__ int find_obj(const int32_t* __restrict__ offs, int m, int i) {
+    int lo = 0, hi = m - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (offs[mid] <= i) lo = mid;
+        else hi = mid - 1;
+    }
+    return lo;
+}
+
+__global__ void bobj_init_kernel(int m, ObjHdr* __restrict__ hd) {
+    const int j = blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= m) return;
+    ObjHdr h{};
+    for (int a = 0; a < 3; ++a) {
+        h.bbox[a] = 0xFFFFFFFFu;
+        h.bbox[3 + a] = 0u;
+    }
+    h.start_pos = -1;
+    hd[j] = h;
+}
+
+template <bool UMAX>
+__device__ __forceinline__ uint32_t wave_minmax_u32(uint32_t v) {
+    for (int off = 32; off > 0; off >>= 1) {
+        const uint32_t o = uint32_t(__shfl_xor(int(v), off, 64));
+        v = UMAX ? (o > v ? o : v) : (o < v ? o : v);
+    }
+    return v;
+}
+
+// finiteness flag and box of every object
+__global__ void bvalidate_kernel(const float* __restrict__ pts, int N, const int32_t* __restrict__ offs,
+                                 int m, ObjHdr* __restrict__ hd) {
+    const int stride = gridDim.x * blockDim.x;
+    for (int base = blockIdx.x * blockDim.x; base < N; base += stride) {
+        const int i = base + threadIdx.x;
+        const bool in = i < N;
+        const int obj = in ? find_obj(offs, m, i) : -1;
+        uint32_t lo[3], hi[3];
+        bool bad = false;
+        for (int a = 0; a < 3; ++a) {
+            const float v = in ? pts[3 * size_t(i) + a] : 0.f;
+            bad |= in && !isfinite(v);
+            const uint32_t e = ord_encode_f(v);
+            lo[a] = in ? e : 0xFFFFFFFFu;
+            hi[a] = in ? e : 0u;
+        }
+        const int o0 = __builtin_amdgcn_readfirstlane(obj);
+        const bool uniform = __ballot(in && obj != o0) == 0 && o0 >= 0;
+        if (uniform) {
+            for (int a = 0; a < 3; ++a) {
+                lo[a] = wave_minmax_u32<false>(lo[a]);
+                hi[a] = wave_minmax_u32<true>(hi[a]);
+            }
+            const bool anybad = __ballot(bad) != 0;
+            if ((threadIdx.x & 63) == 0) {
+                for (int a = 0; a < 3; ++a) {
+                    atomicMin(&hd[o0].bbox[a], lo[a]);
+                    atomicMax(&hd[o0].bbox[3 + a], hi[a]);
+                }
+                if (anybad) atomicOr(&hd[o0].nonfinite, 1u);
+            }
+        } else if (in) {
+            for (int a = 0; a < 3; ++a) {
+                atomicMin(&hd[obj].bbox[a], lo[a]);
+                atomicMax(&hd[obj].bbox[3 + a], hi[a]);
+            }
+            if (bad) atomicOr(&hd[obj].nonfinite, 1u);
+        }
+    }
+}
+
+__global__ void bmorton_kernel(const float* __restrict__ pts, int N, const int32_t* __restrict__ offs,
+                               int m, const ObjHdr* __restrict__ hd, uint64_t* __restrict__ keys,
+                               uint32_t* __restrict__ vals) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= N) return;
+    const int obj = find_obj(offs, m, i);
+    const ObjHdr& h = hd[obj];
+    float lo[3], ext = 0.f;
+    for (int a = 0; a < 3; ++a) {
+        lo[a] = ord_decode(h.bbox[a]);
+        ext = fmaxf(ext, ord_decode(h.bbox[3 + a]) - lo[a]);
+    }
+    const float scale = (ext > 0.f && isfinite(ext)) ? float(1 << kMortonBits) / ext : 0.f;
+    uint32_t q[3];
+    for (int a = 0; a < 3; ++a) {
+        const float f = (pts[3 * size_t(i) + a] - lo[a]) * scale;
+        int v = isfinite(f) ? int(f) : 0;
+        v = v < 0 ? 0 : (v > (1 << kMortonBits) - 1 ? (1 << kMortonBits) - 1 : v);
+        q[a] = uint32_t(v);
+    }
+    const uint32_t code = spread3(q[0]) | (spread3(q[1]) << 1) | (spread3(q[2]) << 2);
+    keys[i] = (uint64_t(obj) << kObjBits) | code;
+    vals[i] = uint32_t(i);
+}
+
+// per object: adjacent sorted pairs first separated at each Morton level
+__global__ void bhist_kernel(const uint64_t* __restrict__ keys, int N, ObjHdr* __restrict__ hd) {
+    __shared__ uint32_t h[kMortonBits + 1];
+    const int first = blockIdx.x * blockDim.x;
+    if (first >= N) return;
+    const int obj0 = int(keys[first] >> kObjBits);
+    if (threadIdx.x <= kMortonBits) h[threadIdx.x] = 0;
+    __syncthreads();
+    const int i = first + threadIdx.x;
+    if (i >= 1 && i < N) {
+        const uint64_t a = keys[i], b = keys[i - 1];
+        if ((a >> kObjBits) == (b >> kObjBits)) {
+            const uint32_t d = uint32_t(a ^ b) & ((1u << kObjBits) - 1u);
+            if (d) {
+                const int l = kMortonBits - (31 - __clz(d)) / 3;
+                const int obj = int(a >> kObjBits);
+                if (obj == obj0) atomicAdd(&h[l], 1u);
+                else atomicAdd(&hd[obj].hist[l], 1u);
+            }
+        }
+    }
+    __syncthreads();
+    if (threadIdx.x <= kMortonBits && h[threadIdx.x]) atomicAdd(&hd[obj0].hist[threadIdx.x], h[threadIdx.x]);
+}
+
+__global__ void blevel_kernel(int m, const int32_t* __restrict__ offs, ObjHdr* __restrict__ hd,
+                              float target, int max_blocks) {
+    const int j = blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= m) return;
+    const int n = offs[j + 1] - offs[j];
+    const double cap = fmin(fmax(1.0, double(n) / double(target)), double(64 * max_blocks));
+    int level = 0;
+    uint32_t acc = 1;
+    for (int l = 1; l <= kMortonBits; ++l) {
+        acc += hd[j].hist[l];
+        if (double(acc) <= cap) level = l;
+    }
+    hd[j].level = level;
+}
+
+__global__ void bflag_kernel(const uint64_t* __restrict__ keys, int N, const ObjHdr* __restrict__ hd,
+                             uint32_t* __restrict__ flags) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= N) return;
+    const uint64_t a = keys[i];
+    if (i == 0) {
+        flags[i] = 1u;
+        return;
+    }
+    const uint64_t b = keys[i - 1];
+    const int obj = int(a >> kObjBits);
+    const int s = 3 * (kMortonBits - hd[obj].level);
+    const uint32_t ca = uint32_t(a) & ((1u << kObjBits) - 1u), cb = uint32_t(b) & ((1u << kObjBits) - 1u);
+    flags[i] = ((a >> kObjBits) != (b >> kObjBits) || (ca >> s) != (cb >> s)) ? 1u : 0u;
+}
+
+__global__ void bgather_kernel(const float* __restrict__ pts, const uint64_t* __restrict__ keys,
+                               const uint32_t* __restrict__ vals, const uint32_t* __restrict__ flags,
+                               const uint32_t* __restrict__ cellidx, int N,
+                               const int32_t* __restrict__ offs, const int32_t* __restrict__ starts,
+                               ObjHdr* __restrict__ hd, float4* __restrict__ xyzm,
+                               uint32_t* __restrict__ ids, int32_t* __restrict__ cstart) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= N) return;
+    const uint32_t g = vals[i];
+    const int obj = int(keys[i] >> kObjBits);
+    const uint32_t local = g - uint32_t(offs[obj]);
+    xyzm[i] = make_float4(pts[3 * size_t(g) + 0], pts[3 * size_t(g) + 1], pts[3 * size_t(g) + 2], INFINITY);
+    ids[i] = local;
+    const int cell = int(cellidx[i]) - 1;
+    if (flags[i]) cstart[cell] = i;
+    if (i == 0 || (keys[i - 1] >> kObjBits) != uint64_t(obj)) hd[obj].cell_base = cell;
+    if (int(local) == starts[obj]) {
+        hd[obj].start_pos = i;
+        hd[obj].start_cell = cell;
+    }
+}
+
+// one workgroup: per-object cell / block / superblock counts and bases
+__global__ void bobj_fin_kernel(int m, const uint32_t* __restrict__ cellidx, int N,
+                                ObjHdr* __restrict__ hd, int32_t* __restrict__ totals) {
+    __shared__ int32_t s_carry[2];
+    __shared__ int32_t s_w[2][16];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int total_cells = int(cellidx[N - 1]);
+    if (tid == 0) {
+        s_carry[0] = 0;
+        s_carry[1] = 0;
+    }
+    __syncthreads();
+    for (int base = 0; base < m; base += blockDim.x) {
+        const int j = base + tid;
+        int nb = 0, ns = 0;
+        if (j < m) {
+            const int cb = hd[j].cell_base;
+            const int ce = (j + 1 < m) ? hd[j + 1].cell_base : total_cells;
+            const int C = ce - cb;
+            nb = (C + 63) / 64;
+            ns = (nb + 63) / 64;
+            hd[j].C = C;
+            hd[j].NB = nb;
+            hd[j].nsb = ns;
+            hd[j].start_cell -= cb;
+        }
+        // block-wide exclusive scans of nb and ns
+        int xb = nb, xs = ns;
+        for (int off = 1; off < 64; off <<= 1) {
+            const int yb = __shfl_up(xb, off, 64), ys = __shfl_up(xs, off, 64);
+            if (lane >= off) {
+                xb += yb;
+                xs += ys;
+            }
+        }
+        if (lane == 63) {
+            s_w[0][wave] = xb;
+            s_w[1][wave] = xs;
+        }
+        __syncthreads();
+        int ob = s_carry[0], os = s_carry[1];
+        const int nw = blockDim.x / 64;
+        int tb = 0, ts = 0;
+        for (int w = 0; w < nw; ++w) {
+            if (w < wave) {
+                ob += s_w[0][w];
+                os += s_w[1][w];
+            }
+            tb += s_w[0][w];
+            ts += s_w[1][w];
+        }
+        if (j < m) {
+            hd[j].block_base = ob + xb - nb;
+            hd[j].sb_base = os + xs - ns;
+        }
+        __syncthreads();
+        if (tid == 0) {
+            s_carry[0] += tb;
+            s_carry[1] += ts;
+        }
+        __syncthreads();
+    }
+    if (tid == 0) {
+        totals[0] = total_cells;
+        totals[1] = s_carry[0];
+        totals[2] = s_carry[1];
+    }
+}
+
+__global__ void bcells_kernel(const int32_t* __restrict__ cstart, int N, const int32_t* __restrict__ totals,
+                              const float4* __restrict__ xyzm, const uint32_t* __restrict__ ids,
+                              float4* __restrict__ cstat, uint4* __restrict__ cdyn) {
+    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    const int C = totals[0];
+    if (c >= C) return;
+    const int s = cstart[c];
+    const int e = (c + 1 < C) ? cstart[c + 1] : N;
+    float lx = INFINITY, ly = INFINITY, lz = INFINITY, hx = -INFINITY, hy = -INFINITY, hz = -INFINITY;
+    uint32_t best_id = 0xFFFFFFFFu;
+    int best_pos = s;
+    for (int i = s; i < e; ++i) {
+        const float4 p = xyzm[i];
+        lx = fminf(lx, p.x);
+        ly = fminf(ly, p.y);
+        lz = fminf(lz, p.z);
+        hx = fmaxf(hx, p.x);
+        hy = fmaxf(hy, p.y);
+        hz = fmaxf(hz, p.z);
+        if (ids[i] < best_id) {
+            best_id = ids[i];
+            best_pos = i;
+        }
+    }
+    cstat[2 * size_t(c) + 0] = make_float4(lx, ly, lz, __int_as_float(s));
+    cstat[2 * size_t(c) + 1] = make_float4(hx, hy, hz, __int_as_float(e - s));
+    const uint64_t key = make_key(INFINITY, best_id);
+    const float4 w = xyzm[best_pos];
+    cdyn[2 * size_t(c) + 0] = make_uint4(uint32_t(key), uint32_t(key >> 32), uint32_t(best_pos), 0u);
+    cdyn[2 * size_t(c) + 1] = make_uint4(__float_as_uint(w.x), __float_as_uint(w.y), __float_as_uint(w.z), 0u);
+}
+
+// object owning global block / superblock b: largest j with base(j) <= b
+template <int FIELD>
+__device__ __forceinline__ int find_obj_by_base(const ObjHdr* __restrict__ hd, int m, int b) {
+    int lo = 0, hi = m - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        const int base = FIELD == 0 ? hd[mid].block_base : hd[mid].sb_base;
+        if (base <= b) lo = mid;
+        else hi = mid - 1;
+    }
+    // skip objects with no blocks that share the same base
+    while (lo + 1 < m && (FIELD == 0 ? hd[lo + 1].block_base : hd[lo + 1].sb_base) <= b) ++lo;
+    return lo;
+}
+
+__global__ void bblocks_kernel(int m, const ObjHdr* __restrict__ hd, const int32_t* __restrict__ totals,
+                               const float4* __restrict__ cstat, const uint4* __restrict__ cdyn,
+                               float4* __restrict__ bstat, uint4* __restrict__ bdyn) {
+    const int b = blockIdx.x * blockDim.x + threadIdx.x;
+    if (b >= totals[1]) return;
+    const int j = find_obj_by_base<0>(hd, m, b);
+    const int lb = b - hd[j].block_base;
+    const int cb = hd[j].cell_base, C = hd[j].C;
+    float lx = INFINITY, ly = INFINITY, lz = INFINITY, hx = -INFINITY, hy = -INFINITY, hz = -INFINITY;
+    uint64_t best = 0;
+    int bc = lb * 64;
+    for (int c = lb * 64; c < C && c < (lb + 1) * 64; ++c) {
+        const size_t g = size_t(cb) + c;
+        const float4 lo = cstat[2 * g], hi = cstat[2 * g + 1];
+        lx = fminf(lx, lo.x);
+        ly = fminf(ly, lo.y);
+        lz = fminf(lz, lo.z);
+        hx = fmaxf(hx, hi.x);
+        hy = fmaxf(hy, hi.y);
+        hz = fmaxf(hz, hi.z);
+        const uint4 d = cdyn[2 * g];
+        const uint64_t key = (uint64_t(d.y) << 32) | d.x;
+        if (key > best) {
+            best = key;
+            bc = c;
+        }
+    }
+    bstat[2 * size_t(b) + 0] = make_float4(lx, ly, lz, 0.f);
+    bstat[2 * size_t(b) + 1] = make_float4(hx, hy, hz, 0.f);
+    const size_t g = size_t(cb) + bc;
+    const uint4 d0 = cdyn[2 * g], d1 = cdyn[2 * g + 1];
+    bdyn[2 * size_t(b) + 0] = make_uint4(d0.x, d0.y, d0.z, uint32_t(bc));
+    bdyn[2 * size_t(b) + 1] = d1;
+}
+
+__global__ void bsuper_kernel(int m, const ObjHdr* __restrict__ hd, const int32_t* __restrict__ totals,
+                              const float4* __restrict__ bstat, float4* __restrict__ sbstat) {
+    const int s = blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= totals[2]) return;
+    const int j = find_obj_by_base<1>(hd, m, s);
+    const int ls = s - hd[j].sb_base;
+    const int bb = hd[j].block_base, NB = hd[j].NB;
+    float lx = INFINITY, ly = INFINITY, lz = INFINITY, hx = -INFINITY, hy = -INFINITY, hz = -INFINITY;
+    for (int b = ls * 64; b < NB && b < (ls + 1) * 64; ++b) {
+        const float4 lo = bstat[2 * (size_t(bb) + b)], hi = bstat[2 * (size_t(bb) + b) + 1];
+        lx = fminf(lx, lo.x);
+        ly = fminf(ly, lo.y);
+        lz = fminf(lz, lo.z);
+        hx = fmaxf(hx, hi.x);
+        hy = fmaxf(hy, hi.y);
+        hz = fmaxf(hz, hi.z);
+    }
+    sbstat[2 * size_t(s) + 0] = make_float4(lx, ly, lz, 0.f);
+    sbstat[2 * size_t(s) + 1] = make_float4(hx, hy, hz, 0.f);
+}
+
+struct ObjDesc {
+    GridObject o;
+    int nonfinite;
+    int pad[3];
+};
+
+__global__ void bdesc_kernel(int m, const ObjHdr* __restrict__ hd, const int32_t* __restrict__ ks,
+                             const int32_t* __restrict__ starts, const int64_t* __restrict__ out_offs,
+                             float4* xyzm, const uint32_t* ids, const float4* cstat, uint4* cdyn,
+                             const float4* bstat, const uint4* bdyn, const float4* sbstat,
+                             int32_t* out_order, float* out_radius, ObjDesc* __restrict__ desc) {
+    const int j = blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= m) return;
+    const ObjHdr& h = hd[j];
+    ObjDesc d{};
+    GridObject& o = d.o;
+    o.k = ks[j];
+    o.start_id = uint32_t(starts[j]);
+    o.C = h.C;
+    o.B = 64;
+    o.NB = h.NB;
+    o.start_pos = h.start_pos;
+    o.start_cell = h.start_cell;
+    o.xyzm = xyzm;
+    o.ids = ids;
+    o.cstat = cstat + 2 * size_t(h.cell_base);
+    o.cdyn = cdyn + 2 * size_t(h.cell_base);
+    o.bstat = bstat + 2 * size_t(h.block_base);
+    o.bdyn = bdyn + 2 * size_t(h.block_base);
+    o.sbstat = sbstat + 2 * size_t(h.sb_base);
+    o.order = out_order + out_offs[j];
+    o.radius = out_radius ? out_radius + out_offs[j] : nullptr;
+    o.ticks = nullptr;
+    d.nonfinite = int(h.nonfinite);
+    desc[j] = d;
+}
+
+__global__ void queue_reset_kernel(uint32_t* q) {
+    if (threadIdx.x == 0) q[0] = 0u;
+}
+
+// Persistent work queue: each workgroup pops objects (largest k first) until
+// the queue is drained; every pop ends the loop for all its waves alike.
+__global__ void __launch_bounds__(kBatchBlock)
+    batch_order_kernel(const ObjDesc* __restrict__ desc, const int32_t* __restrict__ lpt, int mwork,
+                       uint32_t* __restrict__ queue) {
+    __shared__ GridLds<kBatchBlock / 64, kBatchMaxBlocks> L;
+    __shared__ int s_item;
+    for (;;) {
+        if (threadIdx.x == 0) s_item = int(atomicAdd(queue, 1u));
+        __syncthreads();
+        const int item = s_item;
+        __syncthreads();
+        if (item >= mwork) return;
+        const int j = lpt[item];
+        const GridObject o = desc[j].o;
+        if (o.k <= 0) continue;
+        if (desc[j].nonfinite) {
+            for (int t = threadIdx.x; t < o.k; t += kBatchBlock) {
+                o.order[t] = -1;
+                if (o.radius) o.radius[t] = __builtin_nanf("");
+            }
+            continue;
+        }
+        grid_order_object<kBatchBlock, kBatchMaxBlocks>(o, L);
+        __syncthreads();
+    }
+}
+
+template <class T>
+T* carve(char* base, size_t& off, size_t count) {
+    T* p = reinterpret_cast<T*>(base + off);
+    off += align_up(count * sizeof(T));
+    return p;
+}
+
+}  // namespace
+
+struct BatchPlan {
+    int m = 0;                      // objects with n >= 1
+    int N = 0;                      // total candidates
+    int64_t total_k = 0;
+    float target = 32.f;
+    std::vector<int32_t> h_offs;    // m + 1
+    std::vector<int32_t> h_k, h_start, h_lpt;
+    std::vector<int64_t> h_out_offs;  // m + 1
+    int mwork = 0;                  // objects with k > 0
+    size_t maxC = 0, maxB = 0, maxS = 0;
+    size_t sort_bytes = 0, scan_bytes = 0;
+    size_t ws_bytes = 0;
+    int device = 0;
+    int slots = 0;                  // persistent workgroups
+    // small device arrays owned by the plan
+    int32_t* d_offs = nullptr;
+    int32_t* d_k = nullptr;
+    int32_t* d_start = nullptr;
+    int32_t* d_lpt = nullptr;
+    int64_t* d_out_offs = nullptr;
+    // the captured ordering graph, valid for one workspace address
+    hipGraphExec_t exec = nullptr;
+    hipGraph_t graph = nullptr;
+    void* graph_ws = nullptr;
+    std::mutex mu;
+};
+
+namespace {
+
+struct BatchWs {
+    ObjHdr* hd;
+    uint64_t* keys;
+    uint64_t* keys_s;
+    uint32_t* vals;
+    uint32_t* vals_s;
+    uint32_t* flags;
+    uint32_t* cellidx;
+    int32_t* cstart;
+    float4* xyzm;
+    uint32_t* ids;
+    float4* cstat;
+    uint4* cdyn;
+    float4* bstat;
+    uint4* bdyn;
+    float4* sbstat;
+    ObjDesc* desc;
+    int32_t* totals;
+    uint32_t* queue;
+    void* temp;
+    size_t total;
+};
+
+BatchWs batch_layout(const BatchPlan& p, char* base) {
+    BatchWs w{};
+    size_t off = 0;
+    const size_t N = size_t(p.N), m = size_t(p.m);
+    w.hd = carve<ObjHdr>(base, off, m);
+    w.keys = carve<uint64_t>(base, off, N);
+    w.keys_s = carve<uint64_t>(base, off, N);
+    w.vals = carve<uint32_t>(base, off, N);
+    w.vals_s = carve<uint32_t>(base, off, N);
+    w.flags = carve<uint32_t>(base, off, N);
+    w.cellidx = carve<uint32_t>(base, off, N);
+    w.cstart = carve<int32_t>(base, off, p.maxC);
+    w.xyzm = carve<float4>(base, off, N);
+    w.ids = carve<uint32_t>(base, off, N);
+    w.cstat = carve<float4>(base, off, 2 * p.maxC);
+    w.cdyn = carve<uint4>(base, off, 2 * p.maxC);
+    w.bstat = carve<float4>(base, off, 2 * p.maxB);
+    w.bdyn = carve<uint4>(base, off, 2 * p.maxB);
+    w.sbstat = carve<float4>(base, off, 2 * p.maxS);
+    w.desc = carve<ObjDesc>(base, off, m);
+    w.totals = carve<int32_t>(base, off, 4);
+    w.queue = carve<uint32_t>(base, off, 4);
+    w.temp = base + off;
+    off += align_up(std::max(p.sort_bytes, p.scan_bytes));
+    w.total = off;
+    return w;
+}
+
+int end_bit_for(int m) {
+    int b = 1;
+    while ((1 << b) < m + 1) ++b;
+    return kObjBits + b;
+}
+
+hipError_t capture_order_graph(BatchPlan& p, const BatchWs& w) {
+    if (p.exec) {
+        (void)hipGraphExecDestroy(p.exec);
+        p.exec = nullptr;
+    }
+    if (p.graph) {
+        (void)hipGraphDestroy(p.graph);
+        p.graph = nullptr;
+    }
+    hipStream_t cap = nullptr;
+    hipError_t e = hipStreamCreateWithFlags(&cap, hipStreamNonBlocking);
+    if (e != hipSuccess) return e;
+    e = hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal);
+    if (e == hipSuccess) {
+        hipLaunchKernelGGL(queue_reset_kernel, dim3(1), dim3(64), 0, cap, w.queue);
+        hipLaunchKernelGGL(batch_order_kernel, dim3(p.slots), dim3(kBatchBlock), 0, cap, w.desc,
+                           p.d_lpt, p.mwork, w.queue);
+        hipError_t e2 = hipStreamEndCapture(cap, &p.graph);
+        e = (e2 != hipSuccess) ? e2 : hipGetLastError();
+    }
+    if (e == hipSuccess) e = hipGraphInstantiate(&p.exec, p.graph, nullptr, nullptr, 0);
+    (void)hipStreamDestroy(cap);
+    return e;
+}
+
+}  // namespace
+
+void batch_plan_free(BatchPlan* p) {
+    if (!p) return;
+    if (p->exec) (void)hipGraphExecDestroy(p->exec);
+    if (p->graph) (void)hipGraphDestroy(p->graph);
+    (void)hipFree(p->d_offs);
+    (void)hipFree(p->d_k);
+    (void)hipFree(p->d_start);
+    (void)hipFree(p->d_lpt);
+    (void)hipFree(p->d_out_offs);
+    delete p;
+}
+
+int batch_plan_create(const int64_t* h_offsets, const int64_t* h_k, const uint64_t* h_seed, int32_t m,
+                      float target, BatchPlan** out) {
+    if (!out || m < 0 || (m > 0 && (!h_offsets || !h_k)))
+        return set_error(BS_ERR_INVALID_ARG, "null plan arguments");
+    if (h_offsets && h_offsets[0] != 0) return set_error(BS_ERR_INVALID_ARG, "offsets[0] must be 0");
+    for (int j = 0; j < m; ++j) {
+        const int64_t n = h_offsets[j + 1] - h_offsets[j];
+        if (n < 0) return set_error(BS_ERR_INVALID_ARG, "offsets decrease at object %d", j);
+        if (h_k[j] < 0 || h_k[j] > n)
+            return set_error(BS_ERR_INVALID_ARG, "object %d: k=%lld outside [0, n=%lld]", j,
+                             (long long)h_k[j], (long long)n);
+    }
+    if (m > 0 && h_offsets[m] >= (int64_t(1) << 31))
+        return set_error(BS_ERR_INVALID_ARG, "total candidates %lld >= 2^31", (long long)h_offsets[m]);
+    BatchPlan* p = new BatchPlan();
+    p->target = target < 8.f ? 8.f : target;
+    // objects without candidates have k = 0 and take no part
+    std::vector<int> keep;
+    for (int j = 0; j < m; ++j)
+        if (h_offsets[j + 1] > h_offsets[j]) keep.push_back(j);
+    p->h_out_offs.assign(size_t(m) + 1, 0);
+    for (int j = 0; j < m; ++j) p->h_out_offs[j + 1] = p->h_out_offs[j] + h_k[j];
+    p->total_k = p->h_out_offs[m];
+    p->m = int(keep.size());
+    p->N = m > 0 ? int(h_offsets[m]) : 0;
+    p->h_offs.resize(size_t(p->m) + 1);
+    p->h_k.resize(p->m);
+    p->h_start.resize(p->m);
+    std::vector<int64_t> outo(size_t(p->m) + 1);
+    size_t maxC = 0, maxB = 0, maxS = 0;
+    for (int i = 0; i < p->m; ++i) {
+        const int j = keep[i];
+        const int64_t n = h_offsets[j + 1] - h_offsets[j];
+        p->h_offs[i] = int32_t(h_offsets[j]);
+        p->h_k[i] = int32_t(h_k[j]);
+        p->h_start[i] = int32_t(bs_start_index(h_seed ? h_seed[j] : 0, n));
+        outo[i] = p->h_out_offs[j];
+        const double cap = std::min(std::max(1.0, double(n) / double(p->target)), double(64 * kBatchMaxBlocks));
+        const size_t c = size_t(cap);
+        maxC += c;
+        const size_t nb = (c + 63) / 64;
+        maxB += nb;
+        maxS += (nb + 63) / 64;
+    }
+    p->h_offs[p->m] = p->N;
+    outo[p->m] = p->total_k;
+    p->maxC = std::max<size_t>(maxC, 1);
+    p->maxB = std::max<size_t>(maxB, 1);
+    p->maxS = std::max<size_t>(maxS, 1);
+    // largest chains first (longest-processing-time order)
+    p->h_lpt.clear();
+    for (int i = 0; i < p->m; ++i)
+        if (p->h_k[i] > 0) p->h_lpt.push_back(i);
+    std::stable_sort(p->h_lpt.begin(), p->h_lpt.end(),
+                     [&](int a, int b) { return p->h_k[a] > p->h_k[b]; });
+    p->mwork = int(p->h_lpt.size());
+    if (p->N > 0) {
+        hipcub::DeviceRadixSort::SortPairs(nullptr, p->sort_bytes, (const uint64_t*)nullptr,
+                                           (uint64_t*)nullptr, (const uint32_t*)nullptr,
+                                           (uint32_t*)nullptr, p->N, 0, end_bit_for(p->m));
+        hipcub::DeviceScan::InclusiveSum(nullptr, p->scan_bytes, (const uint32_t*)nullptr,
+                                         (uint32_t*)nullptr, p->N);
+    }
+    p->ws_bytes = batch_layout(*p, nullptr).total;
+    (void)hipGetDevice(&p->device);
+    int cus = 0, per = 0;
+    (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, p->device);
+    (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, reinterpret_cast<const void*>(batch_order_kernel),
+                                                       kBatchBlock, 0);
+    if (cus <= 0) cus = 256;
+    if (per <= 0) per = 1;
+    p->slots = std::max(1, std::min(cus * per, std::max(p->mwork, 1)));
+    auto up = [&](void** dst, const void* src, size_t bytes) -> hipError_t {
+        hipError_t e = hipMalloc(dst, std::max<size_t>(bytes, 8));
+        if (e == hipSuccess && bytes) e = hipMemcpy(*dst, src, bytes, hipMemcpyHostToDevice);
+        return e;
+    };
+    hipError_t e = up((void**)&p->d_offs, p->h_offs.data(), p->h_offs.size() * 4);
+    if (e == hipSuccess) e = up((void**)&p->d_k, p->h_k.data(), p->h_k.size() * 4);
+    if (e == hipSuccess) e = up((void**)&p->d_start, p->h_start.data(), p->h_start.size() * 4);
+    if (e == hipSuccess) e = up((void**)&p->d_lpt, p->h_lpt.data(), p->h_lpt.size() * 4);
+    if (e == hipSuccess) e = up((void**)&p->d_out_offs, outo.data(), outo.size() * 8);
+    if (e != hipSuccess) {
+        batch_plan_free(p);
+        return set_error(e == hipErrorOutOfMemory ? BS_ERR_OUT_OF_MEMORY : BS_ERR_HIP,
+                         "plan upload: %s", hipGetErrorString(e));
+    }
+    *out = p;
+    return BS_OK;
+}
+
+size_t batch_workspace_bytes(const BatchPlan* p) { return p ? p->ws_bytes : 0; }
+int64_t batch_total_k(const BatchPlan* p) { return p ? p->total_k : 0; }
+const int64_t* batch_out_offsets(const BatchPlan* p) { return p->h_out_offs.data(); }
+int batch_slots(const BatchPlan* p) { return p ? p->slots : 0; }
+
+int batch_plan_execute(BatchPlan* p, const float* pts, int32_t* out_order, float* out_radius, void* ws,
+                       size_t ws_bytes, hipStream_t st) {
+    if (!p) return set_error(BS_ERR_INVALID_ARG, "null plan");
+    if (p->mwork == 0) return BS_OK;
+    if (!pts || !out_order) return set_error(BS_ERR_INVALID_ARG, "null points or output");
+    if (!ws || ws_bytes < p->ws_bytes)
+        return set_error(BS_ERR_INVALID_ARG, "workspace %zu bytes < %zu needed", ws_bytes, p->ws_bytes);
+    if (reinterpret_cast<uintptr_t>(ws) % kAlign)
+        return set_error(BS_ERR_INVALID_ARG, "workspace not %zu-byte aligned", kAlign);
+    std::lock_guard<std::mutex> lk(p->mu);
+    const BatchWs w = batch_layout(*p, static_cast<char*>(ws));
+    const int N = p->N, m = p->m;
+    const int tb = 256;
+    const int nblk = (N + tb - 1) / tb;
+    const int mblk = (m + tb - 1) / tb;
+    hipError_t e;
+    hipLaunchKernelGGL(bobj_init_kernel, dim3(mblk), dim3(tb), 0, st, m, w.hd);
+    hipLaunchKernelGGL(bvalidate_kernel, dim3(std::min(nblk, 8192)), dim3(tb), 0, st, pts, N, p->d_offs, m, w.hd);
+    hipLaunchKernelGGL(bmorton_kernel, dim3(nblk), dim3(tb), 0, st, pts, N, p->d_offs, m, w.hd, w.keys, w.vals);
+    if ((e = hipGetLastError()) != hipSuccess) return set_error(BS_ERR_HIP, "%s", hipGetErrorString(e));
+    size_t tbytes = std::max(p->sort_bytes, p->scan_bytes);
+    e = hipcub::DeviceRadixSort::SortPairs(w.temp, tbytes, w.keys, w.keys_s, w.vals, w.vals_s, N, 0,
+                                           end_bit_for(m), st);
+    if (e != hipSuccess) return set_error(BS_ERR_HIP, "sort: %s", hipGetErrorString(e));
+    hipLaunchKernelGGL(bhist_kernel, dim3(nblk), dim3(tb), 0, st, w.keys_s, N, w.hd);
+    hipLaunchKernelGGL(blevel_kernel, dim3(mblk), dim3(tb), 0, st, m, p->d_offs, w.hd, p->target,
+                       kBatchMaxBlocks);
+    hipLaunchKernelGGL(bflag_kernel, dim3(nblk), dim3(tb), 0, st, w.keys_s, N, w.hd, w.flags);
+    tbytes = std::max(p->sort_bytes, p->scan_bytes);
+    e = hipcub::DeviceScan::InclusiveSum(w.temp, tbytes, w.flags, w.cellidx, N, st);
+    if (e != hipSuccess) return set_error(BS_ERR_HIP, "scan: %s", hipGetErrorString(e));
+    hipLaunchKernelGGL(bgather_kernel, dim3(nblk), dim3(tb), 0, st, pts, w.keys_s, w.vals_s, w.flags,
+                       w.cellidx, N, p->d_offs, p->d_start, w.hd, w.xyzm, w.ids, w.cstart);
+    hipLaunchKernelGGL(bobj_fin_kernel, dim3(1), dim3(1024), 0, st, m, w.cellidx, N, w.hd, w.totals);
+    const int cblk = int((p->maxC + tb - 1) / tb);
+    hipLaunchKernelGGL(bcells_kernel, dim3(cblk), dim3(tb), 0, st, w.cstart, N, w.totals, w.xyzm, w.ids,
+                       w.cstat, w.cdyn);
+    hipLaunchKernelGGL(bblocks_kernel, dim3(int((p->maxB + tb - 1) / tb)), dim3(tb), 0, st, m, w.hd,
+                       w.totals, w.cstat, w.cdyn, w.bstat, w.bdyn);
+    hipLaunchKernelGGL(bsuper_kernel, dim3(int((p->maxS + tb - 1) / tb)), dim3(tb), 0, st, m, w.hd,
+                       w.totals, w.bstat, w.sbstat);
+    hipLaunchKernelGGL(bdesc_kernel, dim3(mblk), dim3(tb), 0, st, m, w.hd, p->d_k, p->d_start,
+                       p->d_out_offs, w.xyzm, w.ids, w.cstat, w.cdyn, w.bstat, w.bdyn, w.sbstat,
+                       out_order, out_radius, w.desc);
+    if ((e = hipGetLastError()) != hipSuccess) return set_error(BS_ERR_HIP, "%s", hipGetErrorString(e));
+    if (!p->exec || p->graph_ws != ws) {
+        e = capture_order_graph(*p, w);
+        if (e != hipSuccess) return set_error(BS_ERR_HIP, "graph capture: %s", hipGetErrorString(e));
+        p->graph_ws = ws;
+    }
+    e = hipGraphLaunch(p->exec, st);
+    if (e != hipSuccess) return set_error(BS_ERR_HIP, "graph launch: %s", hipGetErrorString(e));
+    return BS_OK;
+}
+
+}  // namespace bs

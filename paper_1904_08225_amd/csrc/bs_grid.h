@@ -32,6 +32,7 @@ struct GridObject {
     uint4* cdyn;               // [2C] (key lo, key hi, pos, -) (x, y, z, -)
     const float4* bstat;       // [2NB] block boxes
     const uint4* bdyn;         // [2NB] initial block bests (key lo, key hi, pos, cell) (x, y, z, -)
+    const float4* sbstat;      // [2 ceil(NB/64)] superblock boxes
     int32_t* order;
     float* radius;
     uint64_t* ticks;           // optional: device wall clock after each step
@@ -40,13 +41,14 @@ struct GridObject {
 // Byte offsets of the grid workspace pieces.
 struct GridLayout {
     size_t dev_header, grid_header, codes, vals, codes_sorted, ids, flags, cellidx, cstart, xyzm,
-        cstat, cdyn, bstat, bdyn, temp;
+        cstat, cdyn, bstat, bdyn, sbstat, temp;
     size_t temp_bytes;
     size_t total;
 };
 
 GridLayout grid_layout(int64_t n, int block);
 int grid_block_size(int64_t n);
+int grid_max_blocks(int block);
 hipError_t launch_grid(const float* pts, int n, int k, int start, int32_t* order, float* radius,
                        void* ws, float target, int block, uint64_t* ticks, hipStream_t st);
 

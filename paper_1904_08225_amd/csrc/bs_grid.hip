@@ -29,84 +29,11 @@
 #include <stdint.h>
 
 #include "bs_grid.h"
+#include "bs_grid_device.h"
 #include "bs_internal.h"
 
 namespace bs {
 namespace {
-
-constexpr int kMortonBits = 10;  // per axis
-constexpr int kMaxBlocks = 1024; // blocks of 64 cells per object (LDS-resident maxima)
-
-__device__ __forceinline__ float dist2(float ax, float ay, float az, float bx, float by,
-                                       float bz) {
-    const float dx = ax - bx;
-    const float dy = ay - by;
-    const float dz = az - bz;
-    const float xx = dx * dx;
-    const float yy = dy * dy;
-    const float zz = dz * dz;
-    const float s = xx + yy;
-    return s + zz;
-}
-
-// Lower bound of d2(p, c) over p in the box [lo, hi] (see file comment).
-__device__ __forceinline__ float box_lower(float lx, float ly, float lz, float hx, float hy,
-                                           float hz, float cx, float cy, float cz) {
-    const float gx = cx < lx ? lx - cx : (cx > hx ? cx - hx : 0.f);
-    const float gy = cy < ly ? ly - cy : (cy > hy ? cy - hy : 0.f);
-    const float gz = cz < lz ? lz - cz : (cz > hz ? cz - hz : 0.f);
-    const float xx = gx * gx;
-    const float yy = gy * gy;
-    const float zz = gz * gz;
-    const float s = xx + yy;
-    return s + zz;
-}
-
-__device__ __forceinline__ uint64_t make_key(float m, uint32_t id) {
-    return (uint64_t(__float_as_uint(m)) << 32) | uint64_t(0x7FFFFFFFu - id);
-}
-__device__ __forceinline__ uint32_t key_id(uint64_t key) {
-    return 0x7FFFFFFFu - uint32_t(key & 0x7FFFFFFFull);
-}
-__device__ __forceinline__ float key_value(uint64_t key) {
-    return __uint_as_float(uint32_t(key >> 32));
-}
-
-template <int CTRL, int ROWS>
-__device__ __forceinline__ uint64_t dpp_max_step(uint64_t v) {
-    const int lo = int(uint32_t(v));
-    const int hi = int(uint32_t(v >> 32));
-    const uint32_t olo = uint32_t(__builtin_amdgcn_update_dpp(lo, lo, CTRL, ROWS, 0xF, false));
-    const uint32_t ohi = uint32_t(__builtin_amdgcn_update_dpp(hi, hi, CTRL, ROWS, 0xF, false));
-    const uint64_t o = (uint64_t(ohi) << 32) | olo;
-    return o > v ? o : v;
-}
-
-__device__ __forceinline__ uint64_t wave_max_u64(uint64_t v) {
-    v = dpp_max_step<0xB1, 0xF>(v);
-    v = dpp_max_step<0x4E, 0xF>(v);
-    v = dpp_max_step<0x141, 0xF>(v);
-    v = dpp_max_step<0x140, 0xF>(v);
-    v = dpp_max_step<0x142, 0xA>(v);
-    v = dpp_max_step<0x143, 0xC>(v);
-    const uint32_t lo = uint32_t(__builtin_amdgcn_readlane(int(uint32_t(v)), 63));
-    const uint32_t hi = uint32_t(__builtin_amdgcn_readlane(int(uint32_t(v >> 32)), 63));
-    return (uint64_t(hi) << 32) | lo;
-}
-
-__device__ __forceinline__ float ord_decode(uint32_t e) {
-    const uint32_t u = (e & 0x80000000u) ? (e & 0x7FFFFFFFu) : ~e;
-    return __uint_as_float(u);
-}
-
-__device__ __forceinline__ uint32_t spread3(uint32_t v) {
-    v &= 0x3FFu;
-    v = (v | (v << 16)) & 0x030000FFu;
-    v = (v | (v << 8)) & 0x0300F00Fu;
-    v = (v | (v << 4)) & 0x030C30C3u;
-    v = (v | (v << 2)) & 0x09249249u;
-    return v;
-}
 
 // ------------------------------------------------------------ preprocessing
 
@@ -154,9 +81,9 @@ __global__ void level_hist_kernel(const uint32_t* __restrict__ codes, int n, Gri
     if (threadIdx.x <= kMortonBits && h[threadIdx.x]) atomicAdd(&gh->hist[threadIdx.x], h[threadIdx.x]);
 }
 
-__global__ void choose_level_kernel(int n, GridHeader* gh, float target) {
+__global__ void choose_level_kernel(int n, GridHeader* gh, float target, int max_blocks) {
     if (threadIdx.x != 0) return;
-    const double cap = fmin(fmax(1.0, double(n) / double(target)), double(64 * kMaxBlocks));
+    const double cap = fmin(fmax(1.0, double(n) / double(target)), double(64 * max_blocks));
     int level = 0;
     uint32_t cells = 1, acc = 1;
     for (int l = 1; l <= kMortonBits; ++l) {
@@ -266,326 +193,35 @@ __global__ void block_build_kernel(const GridHeader* gh, const float4* __restric
     bdyn[2 * b + 1] = d1;
 }
 
+// One thread per superblock (64 consecutive blocks): union box.
+__global__ void superblock_build_kernel(const GridHeader* gh, const float4* __restrict__ bstat,
+                                        float4* __restrict__ sbstat) {
+    const int s = blockIdx.x * blockDim.x + threadIdx.x;
+    const int NB = gh->NB;
+    if (s * 64 >= NB) return;
+    float lx = INFINITY, ly = INFINITY, lz = INFINITY, hx = -INFINITY, hy = -INFINITY,
+          hz = -INFINITY;
+    for (int b = s * 64; b < NB && b < (s + 1) * 64; ++b) {
+        const float4 lo = bstat[2 * b], hi = bstat[2 * b + 1];
+        lx = fminf(lx, lo.x);
+        ly = fminf(ly, lo.y);
+        lz = fminf(lz, lo.z);
+        hx = fmaxf(hx, hi.x);
+        hy = fmaxf(hy, hi.y);
+        hz = fmaxf(hz, hi.z);
+    }
+    sbstat[2 * s + 0] = make_float4(lx, ly, lz, 0.f);
+    sbstat[2 * s + 1] = make_float4(hx, hy, hz, 0.f);
+}
+
 }  // namespace
-
-// ---------------------------------------------------------------- ordering
-
-// Per-wavefront scratch for one block: hit-cell table and per-cell bests.
-struct WaveScratch {
-    int2 tab[64];        // (start, count) of the r-th hit cell
-    uint64_t gkey[64];   // its new best key
-    float4 gwin[64];     // x, y, z, sorted position of that best
-};
-
-// LDS state of one object's ordering: per-block best key, its coordinates
-// and sorted position, its cell, the per-step touched-block masks, and the
-// wavefront scratch.
-template <int NW>
-struct GridLds {
-    uint64_t mask[kMaxBlocks / 64];
-    uint64_t bkey[kMaxBlocks];
-    float4 bwin[kMaxBlocks];
-    int bcell[kMaxBlocks];
-    WaveScratch ws[NW];
-};
-
-// LDS writes by some lanes become visible to reads by other lanes of the
-// same wavefront once they have completed; also a compiler memory barrier.
-__device__ __forceinline__ void wave_lds_sync() { asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory"); }
-
-// Max over aligned groups of 2^steps lanes: afterwards the last lane of each
-// group holds the group's maximum (steps = 6: lane 63 holds the wave max).
-// `steps` must be wave-uniform.
-__device__ __forceinline__ uint64_t group_max_u64(uint64_t v, int steps) {
-    if (steps >= 1) v = dpp_max_step<0xB1, 0xF>(v);
-    if (steps >= 2) v = dpp_max_step<0x4E, 0xF>(v);
-    if (steps >= 3) v = dpp_max_step<0x141, 0xF>(v);
-    if (steps >= 4) v = dpp_max_step<0x140, 0xF>(v);
-    if (steps >= 5) v = dpp_max_step<0x142, 0xA>(v);
-    if (steps >= 6) v = dpp_max_step<0x143, 0xC>(v);
-    return v;
-}
-
-constexpr int kUnroll = 8;  // members per lane in flight
-
-#ifdef BS_PHASE_PROF
-#define BS_PROF(slot) \
-    do { if (o.ticks && threadIdx.x == 0) o.ticks[size_t(prof_t) * 16 + (slot)] = wall_clock64(); } while (0)
-#else
-#define BS_PROF(slot) do { } while (0)
-#endif
-
-// One wavefront updates every candidate of block b that the pick can reach
-// and rewrites the block's best into LDS.  The nh hit cells each get an
-// aligned group of 64 / 2^ceil(log2 nh) lanes.  Wave-local: no barrier.
-// Loads are issued unconditionally (clamped to a valid address) so that a
-// batch of them is in flight together.
-template <int NW>
-__device__ void process_block(const GridObject& o, GridLds<NW>& L, int b, int c_pos, int c_cell,
-                              float cx, float cy, float cz, float mc, int prof_t) {
-    (void)prof_t;
-    const int lane = threadIdx.x & 63;
-    WaveScratch& W = L.ws[threadIdx.x >> 6];
-    float4* __restrict__ xyzm = o.xyzm;
-    const uint32_t* __restrict__ ids = o.ids;
-    const int cell = b * 64 + lane;
-    const bool valid = cell < o.C;
-    const int ci = valid ? cell : o.C - 1;
-    const float4 lo = o.cstat[2 * ci], hi = o.cstat[2 * ci + 1];
-    const uint4 d0 = o.cdyn[2 * ci], d1 = o.cdyn[2 * ci + 1];
-    uint64_t ckey = valid ? ((uint64_t(d0.y) << 32) | d0.x) : 0ull;
-    float4 cwin = make_float4(__uint_as_float(d1.x), __uint_as_float(d1.y), __uint_as_float(d1.z),
-                              __int_as_float(int(d0.z)));
-    const bool hit = valid && (cell == c_cell ||
-                               box_lower(lo.x, lo.y, lo.z, hi.x, hi.y, hi.z, cx, cy, cz) < mc);
-    const uint64_t hm = __ballot(hit);
-    const int nh = __popcll(hm);
-    BS_PROF(8);
-    if (nh == 0) return;  // nothing in reach: the block's best is unchanged
-
-    // lanes -> (hit cell r, sub-lane s)
-    int start, count, G, gshift, r;
-    if (nh == 1) {
-        const int h = __builtin_ctzll(hm);
-        start = __builtin_amdgcn_readlane(__float_as_int(lo.w), h);
-        count = __builtin_amdgcn_readlane(__float_as_int(hi.w), h);
-        gshift = 6;
-        G = 64;
-        r = 0;
-    } else {
-        const int rank = __popcll(hm & ((1ull << lane) - 1));
-        if (hit) W.tab[rank] = make_int2(__float_as_int(lo.w), __float_as_int(hi.w));
-        int steps = 0;
-        while ((1 << steps) < nh) ++steps;
-        gshift = 6 - steps;
-        G = 1 << gshift;
-        r = lane >> gshift;
-        wave_lds_sync();
-        const int2 my = W.tab[r < nh ? r : 0];
-        start = my.x;
-        count = r < nh ? my.y : 0;
-    }
-    const int s = lane & (G - 1);
-
-    uint64_t lk = 0;
-    float4 lw = make_float4(0.f, 0.f, 0.f, 0.f);
-    for (int q0 = s; q0 < count; q0 += G * kUnroll) {
-        int pos[kUnroll];
-        bool ok[kUnroll];
-#pragma unroll
-        for (int u = 0; u < kUnroll; ++u) {
-            const int q = q0 + u * G;
-            ok[u] = q < count;
-            pos[u] = start + (ok[u] ? q : 0);
-        }
-        float4 p[kUnroll];
-        uint32_t id[kUnroll];
-#pragma unroll
-        for (int u = 0; u < kUnroll; ++u) p[u] = xyzm[pos[u]];
-#pragma unroll
-        for (int u = 0; u < kUnroll; ++u) id[u] = ids[pos[u]];
-#pragma unroll
-        for (int u = 0; u < kUnroll; ++u) {
-            const bool pick = ok[u] && pos[u] == c_pos;
-            const bool live = ok[u] && !pick && p[u].w >= 0.f;
-            const float d = dist2(p[u].x, p[u].y, p[u].z, cx, cy, cz);
-            const bool dec = live && d < p[u].w;
-            const float m = dec ? d : p[u].w;
-            if (dec || (pick && p[u].w != -1.f)) xyzm[pos[u]].w = pick ? -1.f : d;
-            const uint64_t kk = live ? make_key(m, id[u]) : 0ull;
-            const bool better = kk > lk;
-            lk = better ? kk : lk;
-            lw = better ? make_float4(p[u].x, p[u].y, p[u].z, __int_as_float(pos[u])) : lw;
-        }
-    }
-    BS_PROF(9);
-
-    if (nh == 1) {
-        const int h = __builtin_ctzll(hm);
-        const uint64_t wk = wave_max_u64(lk);
-        const int wl = __builtin_ctzll(__ballot(lk == wk) | (1ull << 63));
-        const float wx = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(lw.x), wl));
-        const float wy = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(lw.y), wl));
-        const float wz = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(lw.z), wl));
-        const float wp = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(lw.w), wl));
-        if (lane == h) {
-            ckey = wk;
-            cwin = make_float4(wx, wy, wz, wp);
-        }
-    } else {
-        const uint64_t gm = group_max_u64(lk, gshift);
-        if (s == G - 1 && r < nh) W.gkey[r] = gm;
-        wave_lds_sync();
-        if (r < nh && lk != 0 && lk == W.gkey[r]) W.gwin[r] = lw;
-        wave_lds_sync();
-        if (hit) {
-            const int rank = __popcll(hm & ((1ull << lane) - 1));
-            ckey = W.gkey[rank];
-            cwin = W.gwin[rank];
-        }
-    }
-    if (hit) {
-        o.cdyn[2 * cell + 0] = make_uint4(uint32_t(ckey), uint32_t(ckey >> 32),
-                                          uint32_t(__float_as_int(cwin.w)), 0u);
-        o.cdyn[2 * cell + 1] = make_uint4(__float_as_uint(cwin.x), __float_as_uint(cwin.y),
-                                          __float_as_uint(cwin.z), 0u);
-    }
-    const uint64_t bk = wave_max_u64(ckey);
-    if (bk != 0 && ckey == bk) {
-        L.bwin[b] = cwin;
-        L.bcell[b] = cell;
-    }
-    if (lane == 0) L.bkey[b] = bk;
-    wave_lds_sync();
-    BS_PROF(10);
-}
-
-// Best block of superblock sb (64 consecutive blocks), computed by one
-// wavefront from LDS: (key, block).
-template <int NW>
-__device__ __forceinline__ void superblock_best(GridLds<NW>& L, int sb, uint64_t& key, int& blk) {
-    const int lane = threadIdx.x & 63;
-    const uint64_t v = L.bkey[sb * 64 + lane];
-    key = wave_max_u64(v);
-    blk = sb * 64 + __builtin_ctzll(__ballot(v == key) | (1ull << 63));
-}
-
-// Whole ordering of one object by one workgroup (steps 1 .. k-1).
-template <int BLOCK>
-__device__ void grid_order_object(const GridObject& o, GridLds<BLOCK / 64>& L) {
-    constexpr int NW = BLOCK / 64;
-    constexpr int BPT = kMaxBlocks / BLOCK;  // block boxes held per thread
-    const int tid = threadIdx.x;
-    const int lane = tid & 63;
-    const int wave = tid >> 6;
-    const int k = o.k;
-    const int NB = o.NB;
-    const int nsb = (NB + 63) / 64;
-
-    float blx[BPT], bly[BPT], blz[BPT], bhx[BPT], bhy[BPT], bhz[BPT];
-#pragma unroll
-    for (int j = 0; j < BPT; ++j) {
-        const int b = j * BLOCK + tid;
-        if (b < NB) {
-            const float4 lo = o.bstat[2 * b], hi = o.bstat[2 * b + 1];
-            blx[j] = lo.x; bly[j] = lo.y; blz[j] = lo.z;
-            bhx[j] = hi.x; bhy[j] = hi.y; bhz[j] = hi.z;
-            const uint4 d0 = o.bdyn[2 * b], d1 = o.bdyn[2 * b + 1];
-            L.bkey[b] = (uint64_t(d0.y) << 32) | d0.x;
-            L.bwin[b] = make_float4(__uint_as_float(d1.x), __uint_as_float(d1.y),
-                                    __uint_as_float(d1.z), __int_as_float(int(d0.z)));
-            L.bcell[b] = int(d0.w);
-        } else {
-            blx[j] = bly[j] = blz[j] = INFINITY;  // empty box: never touched
-            bhx[j] = bhy[j] = bhz[j] = -INFINITY;
-            L.bkey[b] = 0;
-        }
-    }
-
-    int c_pos = o.start_pos, c_cell = o.start_cell;
-    const float4 sp = o.xyzm[c_pos];
-    float cx = sp.x, cy = sp.y, cz = sp.z;
-    float mc = INFINITY;
-    if (tid == 0) {
-        o.order[0] = int32_t(o.start_id);
-        if (o.radius) o.radius[0] = INFINITY;
-#ifndef BS_PHASE_PROF
-        if (o.ticks) o.ticks[0] = wall_clock64();
-#endif
-    }
-    __syncthreads();
-
-    // superblock bests, kept redundantly by every wavefront: lane j holds superblock j
-    uint64_t sbk = 0;
-    int sbb = 0;
-    for (int sb = 0; sb < nsb; ++sb) {
-        uint64_t kk;
-        int bb;
-        superblock_best(L, sb, kk, bb);
-        if (lane == sb) {
-            sbk = kk;
-            sbb = bb;
-        }
-    }
-
-    for (int t = 1; t < k; ++t) {
-        const int prof_t = t;
-        (void)prof_t;
-        BS_PROF(0);
-        // blocks that may hold a candidate whose m can drop, or the pick
-        const int cb = c_cell >> 6;
-#pragma unroll
-        for (int j = 0; j < BPT; ++j) {
-            const int b = j * BLOCK + tid;
-            const bool touch =
-                b == cb || box_lower(blx[j], bly[j], blz[j], bhx[j], bhy[j], bhz[j], cx, cy, cz) < mc;
-            const uint64_t m = __ballot(touch);
-            if (lane == 0) L.mask[j * NW + wave] = m;
-        }
-        BS_PROF(1);
-        __syncthreads();
-        BS_PROF(2);
-
-        // wavefront w takes the touched blocks of rank w, w + NW, ...
-        const uint64_t mword = lane < nsb ? L.mask[lane] : 0ull;
-        const uint64_t nz = __ballot(mword != 0);
-        int rank = 0;
-        for (uint64_t zs = nz; zs;) {
-            const int mi = __builtin_ctzll(zs);
-            zs &= zs - 1;
-            const uint32_t mlo = uint32_t(__builtin_amdgcn_readlane(int(uint32_t(mword)), mi));
-            const uint32_t mhi = uint32_t(__builtin_amdgcn_readlane(int(uint32_t(mword >> 32)), mi));
-            for (uint64_t mk = (uint64_t(mhi) << 32) | mlo; mk;) {
-                const int b = mi * 64 + __builtin_ctzll(mk);
-                mk &= mk - 1;
-                if (rank % NW == wave) process_block(o, L, b, c_pos, c_cell, cx, cy, cz, mc, t);
-                ++rank;
-            }
-        }
-        BS_PROF(3);
-        __syncthreads();
-        BS_PROF(4);
-
-        // refresh the touched superblocks, then the argmax over superblocks
-        for (uint64_t zs = nz; zs;) {
-            const int mi = __builtin_ctzll(zs);
-            zs &= zs - 1;
-            uint64_t kk;
-            int bb;
-            superblock_best(L, mi, kk, bb);
-            if (lane == mi) {
-                sbk = kk;
-                sbb = bb;
-            }
-        }
-        BS_PROF(5);
-        const uint64_t best = wave_max_u64(sbk);
-        const int wl = __builtin_ctzll(__ballot(sbk == best) | (1ull << 63));
-        const int bb = __builtin_amdgcn_readlane(sbb, wl);
-        const float4 win = L.bwin[bb];
-        c_cell = L.bcell[bb];
-        c_pos = __float_as_int(win.w);
-        cx = win.x;
-        cy = win.y;
-        cz = win.z;
-        mc = key_value(best);
-        BS_PROF(6);
-        if (tid == 0) {
-            o.order[t] = int32_t(key_id(best));
-            if (o.radius) o.radius[t] = sqrtf(mc);
-#ifndef BS_PHASE_PROF
-            if (o.ticks) o.ticks[t] = wall_clock64();
-#endif
-        }
-    }
-}
 
 namespace {
 
-template <int BLOCK>
+template <int BLOCK, int MAXB>
 __global__ void __launch_bounds__(BLOCK) grid_single_kernel(GridObject o, const DevHeader* hdr,
                                                             const GridHeader* gh) {
-    __shared__ GridLds<BLOCK / 64> L;
+    __shared__ GridLds<BLOCK / 64, MAXB> L;
     GridObject obj = o;
     if (o.k <= 0) return;
     if (hdr->nonfinite) {
@@ -600,7 +236,7 @@ __global__ void __launch_bounds__(BLOCK) grid_single_kernel(GridObject o, const 
     obj.NB = gh->NB;
     obj.start_pos = gh->start_pos;
     obj.start_cell = gh->start_cell;
-    grid_order_object<BLOCK>(obj, L);
+    grid_order_object<BLOCK, MAXB>(obj, L);
 }
 
 }  // namespace
@@ -629,8 +265,9 @@ GridLayout grid_layout(int64_t n, int block) {
     g.xyzm = take(N * 16);
     g.cstat = take(maxC * 32);
     g.cdyn = take(maxC * 32);
-    g.bstat = take(size_t(kMaxBlocks) * 32);
-    g.bdyn = take(size_t(kMaxBlocks) * 32);
+    g.bstat = take(size_t(kMaxBlocksAny) * 32);
+    g.bdyn = take(size_t(kMaxBlocksAny) * 32);
+    g.sbstat = take(size_t(kMaxBlocksAny / 64) * 32);
     size_t sort_bytes = 0, scan_bytes = 0;
     hipcub::DeviceRadixSort::SortPairs(nullptr, sort_bytes, (const uint32_t*)nullptr, (uint32_t*)nullptr,
                                        (const uint32_t*)nullptr, (uint32_t*)nullptr, int(n), 0,
@@ -643,7 +280,9 @@ GridLayout grid_layout(int64_t n, int block) {
     return g;
 }
 
-int grid_block_size(int64_t n) { return n > (int64_t(1) << 16) ? 1024 : 256; }
+int grid_block_size(int64_t n) { return n > (int64_t(1) << 16) ? 512 : 256; }
+
+int grid_max_blocks(int block) { return block == 512 ? 4096 : 1024; }
 
 hipError_t launch_grid(const float* pts, int n, int k, int start, int32_t* order, float* radius,
                        void* ws, float target, int block, uint64_t* ticks, hipStream_t st) {
@@ -663,6 +302,7 @@ hipError_t launch_grid(const float* pts, int n, int k, int start, int32_t* order
     uint4* cdyn = reinterpret_cast<uint4*>(base + g.cdyn);
     float4* bstat = reinterpret_cast<float4*>(base + g.bstat);
     uint4* bdyn = reinterpret_cast<uint4*>(base + g.bdyn);
+    float4* sbstat = reinterpret_cast<float4*>(base + g.sbstat);
     void* temp = base + g.temp;
 
     hipError_t e = launch_init_header(hdr, st);
@@ -680,7 +320,8 @@ hipError_t launch_grid(const float* pts, int n, int k, int start, int32_t* order
     if (e != hipSuccess) return e;
     const int hblk = nblk < 1024 ? nblk : 1024;
     hipLaunchKernelGGL(level_hist_kernel, dim3(hblk), dim3(tb), 0, st, codes_s, n, gh);
-    hipLaunchKernelGGL(choose_level_kernel, dim3(1), dim3(64), 0, st, n, gh, target);
+    hipLaunchKernelGGL(choose_level_kernel, dim3(1), dim3(64), 0, st, n, gh, target,
+                       grid_max_blocks(block));
     hipLaunchKernelGGL(cell_flag_kernel, dim3(nblk), dim3(tb), 0, st, codes_s, n, gh, flags);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     tbytes = g.temp_bytes;
@@ -690,8 +331,9 @@ hipError_t launch_grid(const float* pts, int n, int k, int start, int32_t* order
                        gh, xyzm, cstart);
     hipLaunchKernelGGL(cell_build_kernel, dim3(nblk), dim3(tb), 0, st, cstart, n, gh, xyzm, ids, cstat,
                        cdyn);
-    hipLaunchKernelGGL(block_build_kernel, dim3((kMaxBlocks + tb - 1) / tb), dim3(tb), 0, st, gh, cstat,
-                       cdyn, bstat, bdyn);
+    hipLaunchKernelGGL(block_build_kernel, dim3((kMaxBlocksAny + tb - 1) / tb), dim3(tb), 0, st, gh,
+                       cstat, cdyn, bstat, bdyn);
+    hipLaunchKernelGGL(superblock_build_kernel, dim3(1), dim3(64), 0, st, gh, bstat, sbstat);
     if ((e = hipGetLastError()) != hipSuccess) return e;
 
     GridObject o{};
@@ -703,13 +345,16 @@ hipError_t launch_grid(const float* pts, int n, int k, int start, int32_t* order
     o.cdyn = cdyn;
     o.bstat = bstat;
     o.bdyn = bdyn;
+    o.sbstat = sbstat;
     o.order = order;
     o.radius = radius;
     o.ticks = ticks;
-    if (block == 1024)
-        hipLaunchKernelGGL(grid_single_kernel<1024>, dim3(1), dim3(1024), 0, st, o, hdr, gh);
+    if (block == 512)
+        hipLaunchKernelGGL((grid_single_kernel<512, 4096>), dim3(1), dim3(512), 0, st, o, hdr, gh);
+    else if (block == 1024)
+        hipLaunchKernelGGL((grid_single_kernel<1024, 1024>), dim3(1), dim3(1024), 0, st, o, hdr, gh);
     else
-        hipLaunchKernelGGL(grid_single_kernel<256>, dim3(1), dim3(256), 0, st, o, hdr, gh);
+        hipLaunchKernelGGL((grid_single_kernel<256, 1024>), dim3(1), dim3(256), 0, st, o, hdr, gh);
     return hipGetLastError();
 }
 

@@ -47,6 +47,18 @@ hipError_t launch_scan(const ScanShape& s, const float* pts, int n, int k, int s
                        int32_t* order, float* radius, DevHeader* hdr, void* scratch,
                        uint64_t* ticks, hipStream_t st);
 
+// Batched plans (bs_batch.hip).
+struct BatchPlan;
+int batch_plan_create(const int64_t* h_offsets, const int64_t* h_k, const uint64_t* h_seed, int32_t m,
+                      float target, BatchPlan** out);
+void batch_plan_free(BatchPlan* p);
+size_t batch_workspace_bytes(const BatchPlan* p);
+int64_t batch_total_k(const BatchPlan* p);
+const int64_t* batch_out_offsets(const BatchPlan* p);
+int batch_slots(const BatchPlan* p);
+int batch_plan_execute(BatchPlan* p, const float* pts, int32_t* out_order, float* out_radius, void* ws,
+                       size_t ws_bytes, hipStream_t st);
+
 // Error reporting (bs_api.cpp).
 int set_error(int code, const char* fmt, ...);
 

@@ -51,3 +51,21 @@ def test_argument_validation_without_device(lib):
     assert lib.bs_workspace_size(10, 11, None) == 0
     assert lib.bs_workspace_size(16384, 16384, None) > 0
     assert bs.error_string(bs.BS_ERR_OVER_BUDGET) == "BS_ERR_OVER_BUDGET"
+
+
+def test_batch_plan_validation_without_device(lib):
+    import numpy as np
+    plan = ctypes.c_void_p()
+    offs = np.array([0, 5, 3], dtype=np.int64)   # decreasing
+    ks = np.array([1, 1], dtype=np.int64)
+    vp = ctypes.c_void_p
+    rc = lib.bs_batch_plan_create(offs.ctypes.data_as(vp), ks.ctypes.data_as(vp), None, 2, None, ctypes.byref(plan))
+    assert rc == bs.BS_ERR_INVALID_ARG
+    offs = np.array([0, 5, 9], dtype=np.int64)
+    ks = np.array([6, 1], dtype=np.int64)         # k > n
+    rc = lib.bs_batch_plan_create(offs.ctypes.data_as(vp), ks.ctypes.data_as(vp), None, 2, None, ctypes.byref(plan))
+    assert rc == bs.BS_ERR_INVALID_ARG and "k=6" in bs.last_error()
+    offs = np.array([1, 5], dtype=np.int64)       # offsets[0] != 0
+    ks = np.array([1], dtype=np.int64)
+    rc = lib.bs_batch_plan_create(offs.ctypes.data_as(vp), ks.ctypes.data_as(vp), None, 1, None, ctypes.byref(plan))
+    assert rc == bs.BS_ERR_INVALID_ARG

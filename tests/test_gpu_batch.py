@@ -1,0 +1,110 @@
+"""Batched ordering: every object bit-identical to the oracle and to ordering
+it alone (the same result in the batch as alone)."""
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from tests import cases, pins
+from tests.test_gpu_scan import assert_parity
+
+pytestmark = pytest.mark.gpu
+
+
+def make_batch(seed, count=40):
+    rng = np.random.default_rng(seed)
+    objs, ks, seeds = [], [], []
+    kinds = sorted(cases.ADVERSARIAL)
+    for j in range(count):
+        r = j % 5
+        if r == 0:
+            n = int(rng.integers(1, 5))
+            P = cases.random_cloud(n, 1000 + j)
+        elif r == 1:
+            n = int(rng.integers(100, 3000))
+            P = cases.ADVERSARIAL[kinds[j % len(kinds)]](n, 2000 + j)
+        elif r == 2:
+            n = int(rng.integers(2000, 30000))
+            P = synth.cad_part(n, seed=3000 + j, count=20).points.numpy()
+        elif r == 3:
+            n = int(rng.integers(500, 9000))
+            P = synth.scene_object(j % 3, n, seed=4000 + j).points.numpy()
+        else:
+            n = 0 if j % 10 == 4 else int(rng.integers(1, 400))
+            P = cases.random_cloud(max(n, 0), 5000 + j)[:n]
+        k = 0 if n == 0 else int(rng.integers(0, n + 1)) if j % 7 else n
+        objs.append(np.asarray(P, dtype=np.float32).reshape(-1, 3))
+        ks.append(k)
+        seeds.append(int(rng.integers(0, 2**63)))
+    offs = np.concatenate([[0], np.cumsum([o.shape[0] for o in objs])]).astype(np.int64)
+    return objs, ks, seeds, offs
+
+
+def test_batch_matches_oracle_and_alone(hip):
+    import torch
+    objs, ks, seeds, offs = make_batch(7)
+    plan = hip.BatchPlan(offs, ks, seeds)
+    allp = torch.from_numpy(np.concatenate(objs)).cuda()
+    o, r = plan.execute(allp)
+    torch.cuda.synchronize()
+    o = o.cpu().numpy()
+    r = r.cpu().numpy()
+    for j, P in enumerate(objs):
+        a, b = plan.out_offsets[j], plan.out_offsets[j + 1]
+        assert b - a == ks[j]
+        if ks[j] == 0:
+            continue
+        st = oracle.start_index(seeds[j], P.shape[0])
+        eo, er = oracle.greedy32_grid(P, ks[j], st)
+        assert_parity(o[a:b], r[a:b], eo, er, "batch object %d (n=%d k=%d)" % (j, P.shape[0], ks[j]))
+        # alone through the single-object entry point
+        so, sr = hip.order(torch.from_numpy(P).cuda(), ks[j], seed=seeds[j])
+        assert_parity(o[a:b], r[a:b], so.cpu().numpy(), sr.cpu().numpy(), "alone vs batch %d" % j)
+    plan.close()
+
+
+def test_batch_replay_and_nonfinite(hip):
+    import torch
+    objs, ks, seeds, offs = make_batch(11, count=25)
+    objs[3] = objs[3].copy()
+    if objs[3].shape[0] > 0:
+        objs[3][0, 1] = np.nan
+    plan = hip.BatchPlan(offs, ks, seeds)
+    allp = torch.from_numpy(np.concatenate(objs)).cuda()
+    first = [x.cpu().numpy().copy() for x in plan.execute(allp)]
+    for rep in range(3):
+        o, r = plan.execute(allp)
+        torch.cuda.synchronize()
+        assert np.array_equal(o.cpu().numpy(), first[0]), "replay %d order" % rep
+        assert pins.same_f32(r.cpu().numpy(), first[1]), "replay %d radius" % rep
+    for j, P in enumerate(objs):
+        a, b = plan.out_offsets[j], plan.out_offsets[j + 1]
+        if ks[j] == 0:
+            continue
+        if j == 3 and P.shape[0] > 0:
+            assert (first[0][a:b] == -1).all() and np.isnan(first[1][a:b]).all()
+        else:
+            st = oracle.start_index(seeds[j], P.shape[0])
+            eo, er = oracle.greedy32_grid(P, ks[j], st)
+            assert_parity(first[0][a:b], first[1][a:b], eo, er, "object %d" % j)
+    plan.close()
+
+
+def test_batch_many_small_objects(hip):
+    import torch
+    sizes = synth.log_uniform_sizes(600, 64, 4096, seed=5)
+    objs = [synth.cad_part(n, seed=9000 + j, count=8).points.numpy() if j % 50 == 0
+            else cases.random_cloud(n, 9000 + j) for j, n in enumerate(sizes)]
+    ks = [n // 4 for n in sizes]
+    seeds = list(range(len(sizes)))
+    offs = np.concatenate([[0], np.cumsum(sizes)]).astype(np.int64)
+    plan = hip.BatchPlan(offs, ks, seeds)
+    o, r = plan.execute(torch.from_numpy(np.concatenate(objs)).cuda())
+    torch.cuda.synchronize()
+    o = o.cpu().numpy()
+    r = r.cpu().numpy()
+    for j in range(0, len(sizes), 7):
+        a, b = plan.out_offsets[j], plan.out_offsets[j + 1]
+        eo, er = oracle.greedy32(objs[j], ks[j], oracle.start_index(seeds[j], sizes[j]))
+        assert_parity(o[a:b], r[a:b], eo, er, "small object %d" % j)
+    plan.close()

@@ -15,7 +15,7 @@ from tests.test_gpu_scan import assert_parity, run
 pytestmark = pytest.mark.gpu
 
 
-@pytest.mark.parametrize("block", [256, 1024])
+@pytest.mark.parametrize("block", [256, 512, 1024])
 @pytest.mark.parametrize("name", sorted(cases.ADVERSARIAL))
 def test_grid_adversarial(hip, name, block):
     for n in (1, 2, 3, 65, 1000, 4097):
@@ -32,7 +32,7 @@ def test_grid_cell_sizes(hip, cell_points):
     P = synth.cad_part(n, seed=12).points.numpy()
     k = n // 3
     eo, er = oracle.greedy32_grid(P, k, 17)
-    for block in (256, 1024):
+    for block in (256, 512, 1024):
         o, r = run(hip, P, k, start=17,
                    tune=hip.tuning(kernel=hip.KERNEL_GRID, block=block, cell_points=cell_points))
         assert_parity(o, r, eo, er, "cell_points=%g block=%d" % (cell_points, block))
