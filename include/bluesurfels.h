@@ -205,6 +205,66 @@ int bs_batch_plan_execute(bs_batch_plan* plan, const float* d_points, int32_t* d
                           void* stream);
 void bs_batch_plan_destroy(bs_batch_plan* plan);
 
+/* -------------------------------------------------------------- serving */
+
+/*
+ * A serving loop with continuous batching under an HBM budget.  Jobs are
+ * submitted from any host thread; a dispatcher thread admits pending jobs,
+ * in arrival order, into micro-batches whenever one of `max_inflight`
+ * streams is free and the job fits the remaining budget; micro-batches run
+ * concurrently on the device, one workgroup per job (the batched ordering
+ * above).  Each job is timed from submit to the moment its completion flag
+ * (written by the device into pinned host memory) is observed.  Results
+ * are bit-identical to bs_order on the same job.
+ */
+typedef struct {
+    size_t hbm_budget_bytes;     /* device bytes the server may hold at once (> 0) */
+    int32_t device;              /* HIP device ordinal */
+    int32_t max_inflight;        /* concurrent micro-batches (streams); 0 = 4 */
+    int32_t max_jobs_per_batch;  /* 0 = 512 */
+    int32_t poll_us;             /* dispatcher polling period while busy; 0 = 50 */
+    float cell_points;           /* grid cell target, 0 = 32 */
+    int32_t reserved[7];         /* must be zero */
+} bs_server_config;
+
+typedef struct {
+    const float* d_points;   /* device float[n][3]; must stay valid until the job is done */
+    int64_t n;
+    int64_t k;               /* 0 <= k <= n */
+    uint64_t seed;           /* start = SplitMix64(seed) mod n */
+    int32_t* d_out_order;    /* device int32[k] */
+    float* d_out_radius;     /* device float[k] or NULL */
+} bs_job;
+
+typedef struct {
+    int64_t submitted, admitted, completed, rejected;
+    int64_t queued;            /* waiting for admission now */
+    int64_t inflight_batches;  /* micro-batches on the device now */
+    int64_t batches;           /* micro-batches launched so far */
+    int64_t ordered_surfels;   /* sum of k over completed jobs */
+    double p50_us, p99_us, mean_us, max_us;  /* submit -> done latency */
+    double elapsed_s;          /* first submit -> last completion */
+    double surfels_per_s;      /* ordered_surfels / elapsed_s */
+    size_t hbm_in_use, hbm_peak;
+} bs_serving_stats;
+
+typedef struct bs_server bs_server;
+/* Errors: BS_ERR_INVALID_ARG, BS_ERR_HIP. */
+int bs_server_create(const bs_server_config* cfg, bs_server** out_server);
+/* Enqueue a job; returns a ticket.  BS_ERR_OVER_BUDGET if the job alone can
+ * never fit the budget (it is then not queued). */
+int bs_server_submit(bs_server* server, const bs_job* job, uint64_t* ticket);
+/* *done = 1 once the job's outputs are complete (returns the job's status). */
+int bs_server_poll(bs_server* server, uint64_t ticket, int* done);
+/* Block until the job is done or timeout_us passes (< 0: no limit);
+ * BS_ERR_TIMEOUT on timeout. */
+int bs_server_wait(bs_server* server, uint64_t ticket, int64_t timeout_us);
+/* Block until no job is queued or in flight. */
+int bs_server_drain(bs_server* server, int64_t timeout_us);
+int bs_server_stats(bs_server* server, bs_serving_stats* out);
+/* Finishes the jobs still queued or in flight, then releases everything. */
+void bs_server_destroy(bs_server* server);
+
 #ifdef __cplusplus
 }
 #endif

@@ -103,6 +103,20 @@ def load():
     lib.bs_batch_plan_execute.restype = i32
     lib.bs_batch_plan_destroy.argtypes = [vp]
     lib.bs_batch_plan_destroy.restype = None
+    lib.bs_server_create.argtypes = [vp, ctypes.POINTER(vp)]
+    lib.bs_server_create.restype = i32
+    lib.bs_server_submit.argtypes = [vp, vp, ctypes.POINTER(u64)]
+    lib.bs_server_submit.restype = i32
+    lib.bs_server_poll.argtypes = [vp, u64, ctypes.POINTER(ctypes.c_int)]
+    lib.bs_server_poll.restype = i32
+    lib.bs_server_wait.argtypes = [vp, u64, i64]
+    lib.bs_server_wait.restype = i32
+    lib.bs_server_drain.argtypes = [vp, i64]
+    lib.bs_server_drain.restype = i32
+    lib.bs_server_stats.argtypes = [vp, vp]
+    lib.bs_server_stats.restype = i32
+    lib.bs_server_destroy.argtypes = [vp]
+    lib.bs_server_destroy.restype = None
     _lib = lib
     return lib
 
@@ -277,6 +291,84 @@ class BatchPlan:
         if getattr(self, "_plan", None):
             self._lib.bs_batch_plan_destroy(self._plan)
             self._plan = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class ServerConfig(ctypes.Structure):
+    _fields_ = [("hbm_budget_bytes", ctypes.c_size_t), ("device", ctypes.c_int32),
+                ("max_inflight", ctypes.c_int32), ("max_jobs_per_batch", ctypes.c_int32),
+                ("poll_us", ctypes.c_int32), ("cell_points", ctypes.c_float),
+                ("reserved", ctypes.c_int32 * 7)]
+
+
+class Job(ctypes.Structure):
+    _fields_ = [("d_points", ctypes.c_void_p), ("n", ctypes.c_int64), ("k", ctypes.c_int64),
+                ("seed", ctypes.c_uint64), ("d_out_order", ctypes.c_void_p), ("d_out_radius", ctypes.c_void_p)]
+
+
+class ServingStats(ctypes.Structure):
+    _fields_ = [("submitted", ctypes.c_int64), ("admitted", ctypes.c_int64), ("completed", ctypes.c_int64),
+                ("rejected", ctypes.c_int64), ("queued", ctypes.c_int64), ("inflight_batches", ctypes.c_int64),
+                ("batches", ctypes.c_int64), ("ordered_surfels", ctypes.c_int64),
+                ("p50_us", ctypes.c_double), ("p99_us", ctypes.c_double), ("mean_us", ctypes.c_double),
+                ("max_us", ctypes.c_double), ("elapsed_s", ctypes.c_double), ("surfels_per_s", ctypes.c_double),
+                ("hbm_in_use", ctypes.c_size_t), ("hbm_peak", ctypes.c_size_t)]
+
+    def as_dict(self):
+        return {f[0]: getattr(self, f[0]) for f in self._fields_}
+
+
+class Server:
+    """Serving loop with continuous batching (``bs_server_*``).
+
+    ``submit`` takes device tensors (points float32 [n, 3], order int32 [k],
+    radius float32 [k]) which must stay alive until the job is done."""
+
+    def __init__(self, hbm_budget_bytes: int, device: int = 0, max_inflight: int = 4,
+                 max_jobs_per_batch: int = 512, poll_us: int = 50, cell_points: float = 0.0):
+        lib = load()
+        self._lib = lib
+        cfg = ServerConfig(int(hbm_budget_bytes), device, max_inflight, max_jobs_per_batch, poll_us, cell_points)
+        self._srv = ctypes.c_void_p()
+        _check(lib.bs_server_create(ctypes.byref(cfg), ctypes.byref(self._srv)))
+        self._keep = {}
+
+    def submit(self, points, k: int, seed: int, out_order, out_radius=None) -> int:
+        n = int(points.shape[0])
+        job = Job(ctypes.c_void_p(points.data_ptr()) if n else None, n, int(k), seed & (2**64 - 1),
+                  _ptr(out_order) if k else None, _ptr(out_radius) if (out_radius is not None and k) else None)
+        t = ctypes.c_uint64()
+        _check(self._lib.bs_server_submit(self._srv, ctypes.byref(job), ctypes.byref(t)))
+        self._keep[t.value] = (points, out_order, out_radius)
+        return t.value
+
+    def wait(self, ticket: int, timeout_us: int = -1):
+        _check(self._lib.bs_server_wait(self._srv, ctypes.c_uint64(ticket), timeout_us))
+        self._keep.pop(ticket, None)
+
+    def poll(self, ticket: int) -> bool:
+        d = ctypes.c_int()
+        _check(self._lib.bs_server_poll(self._srv, ctypes.c_uint64(ticket), ctypes.byref(d)))
+        return bool(d.value)
+
+    def drain(self, timeout_us: int = -1):
+        _check(self._lib.bs_server_drain(self._srv, timeout_us))
+
+    def stats(self) -> dict:
+        st = ServingStats()
+        _check(self._lib.bs_server_stats(self._srv, ctypes.byref(st)))
+        return st.as_dict()
+
+    def close(self):
+        if getattr(self, "_srv", None):
+            self._lib.bs_server_destroy(self._srv)
+            self._srv = None
+            self._keep.clear()
 
     def __del__(self):
         try:

@@ -398,15 +398,25 @@ __global__ void bsuper_kernel(int m, const ObjHdr* __restrict__ hd, const int32_
 
 struct ObjDesc {
     GridObject o;
+    uint32_t* done;    // optional completion flag (host-visible memory), set to 1 at the end
     int nonfinite;
-    int pad[3];
+    int pad;
+};
+
+// Optional per-object outputs (served jobs write straight into their own buffers).
+struct JobIo {
+    int32_t* order;
+    float* radius;
+    uint32_t* done;
+    void* pad;
 };
 
 __global__ void bdesc_kernel(int m, const ObjHdr* __restrict__ hd, const int32_t* __restrict__ ks,
                              const int32_t* __restrict__ starts, const int64_t* __restrict__ out_offs,
                              float4* xyzm, const uint32_t* ids, const float4* cstat, uint4* cdyn,
                              const float4* bstat, const uint4* bdyn, const float4* sbstat,
-                             int32_t* out_order, float* out_radius, ObjDesc* __restrict__ desc) {
+                             int32_t* out_order, float* out_radius, const JobIo* __restrict__ io,
+                             ObjDesc* __restrict__ desc) {
     const int j = blockIdx.x * blockDim.x + threadIdx.x;
     if (j >= m) return;
     const ObjHdr& h = hd[j];
@@ -426,8 +436,15 @@ __global__ void bdesc_kernel(int m, const ObjHdr* __restrict__ hd, const int32_t
     o.bstat = bstat + 2 * size_t(h.block_base);
     o.bdyn = bdyn + 2 * size_t(h.block_base);
     o.sbstat = sbstat + 2 * size_t(h.sb_base);
-    o.order = out_order + out_offs[j];
-    o.radius = out_radius ? out_radius + out_offs[j] : nullptr;
+    if (io) {
+        o.order = io[j].order;
+        o.radius = io[j].radius;
+        d.done = io[j].done;
+    } else {
+        o.order = out_order + out_offs[j];
+        o.radius = out_radius ? out_radius + out_offs[j] : nullptr;
+        d.done = nullptr;
+    }
     o.ticks = nullptr;
     d.nonfinite = int(h.nonfinite);
     desc[j] = d;
@@ -452,16 +469,23 @@ __global__ void __launch_bounds__(kBatchBlock)
         if (item >= mwork) return;
         const int j = lpt[item];
         const GridObject o = desc[j].o;
-        if (o.k <= 0) continue;
-        if (desc[j].nonfinite) {
-            for (int t = threadIdx.x; t < o.k; t += kBatchBlock) {
-                o.order[t] = -1;
-                if (o.radius) o.radius[t] = __builtin_nanf("");
+        uint32_t* done = desc[j].done;
+        if (o.k > 0) {
+            if (desc[j].nonfinite) {
+                for (int t = threadIdx.x; t < o.k; t += kBatchBlock) {
+                    o.order[t] = -1;
+                    if (o.radius) o.radius[t] = __builtin_nanf("");
+                }
+            } else {
+                grid_order_object<kBatchBlock, kBatchMaxBlocks>(o, L);
             }
-            continue;
         }
-        grid_order_object<kBatchBlock, kBatchMaxBlocks>(o, L);
         __syncthreads();
+        if (done && threadIdx.x == 0) {
+            // outputs of this object happen-before the flag, at system scope
+            __atomic_thread_fence(__ATOMIC_RELEASE);
+            __hip_atomic_store(done, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
+        }
     }
 }
 
@@ -476,24 +500,22 @@ T* carve(char* base, size_t& off, size_t count) {
 
 struct BatchPlan {
     int m = 0;                      // objects with n >= 1
+    int m_all = 0;                  // objects as given
     int N = 0;                      // total candidates
     int64_t total_k = 0;
     float target = 32.f;
     std::vector<int32_t> h_offs;    // m + 1
     std::vector<int32_t> h_k, h_start, h_lpt;
-    std::vector<int64_t> h_out_offs;  // m + 1
+    std::vector<int64_t> h_out_offs;  // m_all + 1 (caller's object numbering)
+    std::vector<int64_t> h_outo;      // m + 1 (kept objects)
+    std::vector<JobIo> h_io;          // optional per-object outputs (kept objects)
+    std::vector<int> kept;            // caller object number of each kept object
     int mwork = 0;                  // objects with k > 0
     size_t maxC = 0, maxB = 0, maxS = 0;
     size_t sort_bytes = 0, scan_bytes = 0;
     size_t ws_bytes = 0;
-    int device = 0;
     int slots = 0;                  // persistent workgroups
-    // small device arrays owned by the plan
-    int32_t* d_offs = nullptr;
-    int32_t* d_k = nullptr;
-    int32_t* d_start = nullptr;
-    int32_t* d_lpt = nullptr;
-    int64_t* d_out_offs = nullptr;
+    bool use_graph = true;
     // the captured ordering graph, valid for one workspace address
     hipGraphExec_t exec = nullptr;
     hipGraph_t graph = nullptr;
@@ -522,6 +544,12 @@ struct BatchWs {
     ObjDesc* desc;
     int32_t* totals;
     uint32_t* queue;
+    int32_t* offs;
+    int32_t* ks;
+    int32_t* starts;
+    int32_t* lpt;
+    int64_t* outo;
+    JobIo* io;
     void* temp;
     size_t total;
 };
@@ -548,6 +576,12 @@ BatchWs batch_layout(const BatchPlan& p, char* base) {
     w.desc = carve<ObjDesc>(base, off, m);
     w.totals = carve<int32_t>(base, off, 4);
     w.queue = carve<uint32_t>(base, off, 4);
+    w.offs = carve<int32_t>(base, off, m + 1);
+    w.ks = carve<int32_t>(base, off, m + 1);
+    w.starts = carve<int32_t>(base, off, m + 1);
+    w.lpt = carve<int32_t>(base, off, m + 1);
+    w.outo = carve<int64_t>(base, off, m + 1);
+    w.io = carve<JobIo>(base, off, m + 1);
     w.temp = base + off;
     off += align_up(std::max(p.sort_bytes, p.scan_bytes));
     w.total = off;
@@ -576,7 +610,7 @@ hipError_t capture_order_graph(BatchPlan& p, const BatchWs& w) {
     if (e == hipSuccess) {
         hipLaunchKernelGGL(queue_reset_kernel, dim3(1), dim3(64), 0, cap, w.queue);
         hipLaunchKernelGGL(batch_order_kernel, dim3(p.slots), dim3(kBatchBlock), 0, cap, w.desc,
-                           p.d_lpt, p.mwork, w.queue);
+                           w.lpt, p.mwork, w.queue);
         hipError_t e2 = hipStreamEndCapture(cap, &p.graph);
         e = (e2 != hipSuccess) ? e2 : hipGetLastError();
     }
@@ -591,11 +625,6 @@ void batch_plan_free(BatchPlan* p) {
     if (!p) return;
     if (p->exec) (void)hipGraphExecDestroy(p->exec);
     if (p->graph) (void)hipGraphDestroy(p->graph);
-    (void)hipFree(p->d_offs);
-    (void)hipFree(p->d_k);
-    (void)hipFree(p->d_start);
-    (void)hipFree(p->d_lpt);
-    (void)hipFree(p->d_out_offs);
     delete p;
 }
 
@@ -614,6 +643,7 @@ int batch_plan_create(const int64_t* h_offsets, const int64_t* h_k, const uint64
     if (m > 0 && h_offsets[m] >= (int64_t(1) << 31))
         return set_error(BS_ERR_INVALID_ARG, "total candidates %lld >= 2^31", (long long)h_offsets[m]);
     BatchPlan* p = new BatchPlan();
+    p->m_all = m;
     p->target = target < 8.f ? 8.f : target;
     // objects without candidates have k = 0 and take no part
     std::vector<int> keep;
@@ -623,6 +653,7 @@ int batch_plan_create(const int64_t* h_offsets, const int64_t* h_k, const uint64
     for (int j = 0; j < m; ++j) p->h_out_offs[j + 1] = p->h_out_offs[j] + h_k[j];
     p->total_k = p->h_out_offs[m];
     p->m = int(keep.size());
+    p->kept = keep;
     p->N = m > 0 ? int(h_offsets[m]) : 0;
     p->h_offs.resize(size_t(p->m) + 1);
     p->h_k.resize(p->m);
@@ -662,32 +693,30 @@ int batch_plan_create(const int64_t* h_offsets, const int64_t* h_k, const uint64
         hipcub::DeviceScan::InclusiveSum(nullptr, p->scan_bytes, (const uint32_t*)nullptr,
                                          (uint32_t*)nullptr, p->N);
     }
+    p->h_outo = outo;
     p->ws_bytes = batch_layout(*p, nullptr).total;
-    (void)hipGetDevice(&p->device);
-    int cus = 0, per = 0;
-    (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, p->device);
+    int dev = 0, cus = 0, per = 0;
+    (void)hipGetDevice(&dev);
+    (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
     (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, reinterpret_cast<const void*>(batch_order_kernel),
                                                        kBatchBlock, 0);
     if (cus <= 0) cus = 256;
     if (per <= 0) per = 1;
     p->slots = std::max(1, std::min(cus * per, std::max(p->mwork, 1)));
-    auto up = [&](void** dst, const void* src, size_t bytes) -> hipError_t {
-        hipError_t e = hipMalloc(dst, std::max<size_t>(bytes, 8));
-        if (e == hipSuccess && bytes) e = hipMemcpy(*dst, src, bytes, hipMemcpyHostToDevice);
-        return e;
-    };
-    hipError_t e = up((void**)&p->d_offs, p->h_offs.data(), p->h_offs.size() * 4);
-    if (e == hipSuccess) e = up((void**)&p->d_k, p->h_k.data(), p->h_k.size() * 4);
-    if (e == hipSuccess) e = up((void**)&p->d_start, p->h_start.data(), p->h_start.size() * 4);
-    if (e == hipSuccess) e = up((void**)&p->d_lpt, p->h_lpt.data(), p->h_lpt.size() * 4);
-    if (e == hipSuccess) e = up((void**)&p->d_out_offs, outo.data(), outo.size() * 8);
-    if (e != hipSuccess) {
-        batch_plan_free(p);
-        return set_error(e == hipErrorOutOfMemory ? BS_ERR_OUT_OF_MEMORY : BS_ERR_HIP,
-                         "plan upload: %s", hipGetErrorString(e));
-    }
     *out = p;
     return BS_OK;
+}
+
+// Served micro-batches: per-object output buffers and completion flags
+// (index = caller object number), plain launches instead of a graph.
+void batch_set_job_io(BatchPlan* p, const std::vector<int32_t*>& order, const std::vector<float*>& radius,
+                      const std::vector<uint32_t*>& done) {
+    p->h_io.resize(size_t(p->m) + 1);
+    for (int i = 0; i < p->m; ++i) {
+        const int j = p->kept[i];
+        p->h_io[i] = JobIo{order[j], radius[j], done[j], nullptr};
+    }
+    p->use_graph = false;
 }
 
 size_t batch_workspace_bytes(const BatchPlan* p) { return p ? p->ws_bytes : 0; }
@@ -699,7 +728,7 @@ int batch_plan_execute(BatchPlan* p, const float* pts, int32_t* out_order, float
                        size_t ws_bytes, hipStream_t st) {
     if (!p) return set_error(BS_ERR_INVALID_ARG, "null plan");
     if (p->mwork == 0) return BS_OK;
-    if (!pts || !out_order) return set_error(BS_ERR_INVALID_ARG, "null points or output");
+    if (!pts || (!out_order && p->h_io.empty())) return set_error(BS_ERR_INVALID_ARG, "null points or output");
     if (!ws || ws_bytes < p->ws_bytes)
         return set_error(BS_ERR_INVALID_ARG, "workspace %zu bytes < %zu needed", ws_bytes, p->ws_bytes);
     if (reinterpret_cast<uintptr_t>(ws) % kAlign)
@@ -707,27 +736,39 @@ int batch_plan_execute(BatchPlan* p, const float* pts, int32_t* out_order, float
     std::lock_guard<std::mutex> lk(p->mu);
     const BatchWs w = batch_layout(*p, static_cast<char*>(ws));
     const int N = p->N, m = p->m;
+    hipError_t e = hipMemcpyAsync(w.offs, p->h_offs.data(), p->h_offs.size() * 4, hipMemcpyHostToDevice, st);
+    if (e == hipSuccess && m)
+        e = hipMemcpyAsync(w.ks, p->h_k.data(), p->h_k.size() * 4, hipMemcpyHostToDevice, st);
+    if (e == hipSuccess && m)
+        e = hipMemcpyAsync(w.starts, p->h_start.data(), p->h_start.size() * 4, hipMemcpyHostToDevice, st);
+    if (e == hipSuccess && p->mwork)
+        e = hipMemcpyAsync(w.lpt, p->h_lpt.data(), p->h_lpt.size() * 4, hipMemcpyHostToDevice, st);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(w.outo, p->h_outo.data(), p->h_outo.size() * 8, hipMemcpyHostToDevice, st);
+    const bool use_io = !p->h_io.empty();
+    if (e == hipSuccess && use_io)
+        e = hipMemcpyAsync(w.io, p->h_io.data(), p->h_io.size() * sizeof(JobIo), hipMemcpyHostToDevice, st);
+    if (e != hipSuccess) return set_error(BS_ERR_HIP, "plan upload: %s", hipGetErrorString(e));
     const int tb = 256;
     const int nblk = (N + tb - 1) / tb;
     const int mblk = (m + tb - 1) / tb;
-    hipError_t e;
     hipLaunchKernelGGL(bobj_init_kernel, dim3(mblk), dim3(tb), 0, st, m, w.hd);
-    hipLaunchKernelGGL(bvalidate_kernel, dim3(std::min(nblk, 8192)), dim3(tb), 0, st, pts, N, p->d_offs, m, w.hd);
-    hipLaunchKernelGGL(bmorton_kernel, dim3(nblk), dim3(tb), 0, st, pts, N, p->d_offs, m, w.hd, w.keys, w.vals);
+    hipLaunchKernelGGL(bvalidate_kernel, dim3(std::min(nblk, 8192)), dim3(tb), 0, st, pts, N, w.offs, m, w.hd);
+    hipLaunchKernelGGL(bmorton_kernel, dim3(nblk), dim3(tb), 0, st, pts, N, w.offs, m, w.hd, w.keys, w.vals);
     if ((e = hipGetLastError()) != hipSuccess) return set_error(BS_ERR_HIP, "%s", hipGetErrorString(e));
     size_t tbytes = std::max(p->sort_bytes, p->scan_bytes);
     e = hipcub::DeviceRadixSort::SortPairs(w.temp, tbytes, w.keys, w.keys_s, w.vals, w.vals_s, N, 0,
                                            end_bit_for(m), st);
     if (e != hipSuccess) return set_error(BS_ERR_HIP, "sort: %s", hipGetErrorString(e));
     hipLaunchKernelGGL(bhist_kernel, dim3(nblk), dim3(tb), 0, st, w.keys_s, N, w.hd);
-    hipLaunchKernelGGL(blevel_kernel, dim3(mblk), dim3(tb), 0, st, m, p->d_offs, w.hd, p->target,
+    hipLaunchKernelGGL(blevel_kernel, dim3(mblk), dim3(tb), 0, st, m, w.offs, w.hd, p->target,
                        kBatchMaxBlocks);
     hipLaunchKernelGGL(bflag_kernel, dim3(nblk), dim3(tb), 0, st, w.keys_s, N, w.hd, w.flags);
     tbytes = std::max(p->sort_bytes, p->scan_bytes);
     e = hipcub::DeviceScan::InclusiveSum(w.temp, tbytes, w.flags, w.cellidx, N, st);
     if (e != hipSuccess) return set_error(BS_ERR_HIP, "scan: %s", hipGetErrorString(e));
     hipLaunchKernelGGL(bgather_kernel, dim3(nblk), dim3(tb), 0, st, pts, w.keys_s, w.vals_s, w.flags,
-                       w.cellidx, N, p->d_offs, p->d_start, w.hd, w.xyzm, w.ids, w.cstart);
+                       w.cellidx, N, w.offs, w.starts, w.hd, w.xyzm, w.ids, w.cstart);
     hipLaunchKernelGGL(bobj_fin_kernel, dim3(1), dim3(1024), 0, st, m, w.cellidx, N, w.hd, w.totals);
     const int cblk = int((p->maxC + tb - 1) / tb);
     hipLaunchKernelGGL(bcells_kernel, dim3(cblk), dim3(tb), 0, st, w.cstart, N, w.totals, w.xyzm, w.ids,
@@ -736,10 +777,18 @@ int batch_plan_execute(BatchPlan* p, const float* pts, int32_t* out_order, float
                        w.totals, w.cstat, w.cdyn, w.bstat, w.bdyn);
     hipLaunchKernelGGL(bsuper_kernel, dim3(int((p->maxS + tb - 1) / tb)), dim3(tb), 0, st, m, w.hd,
                        w.totals, w.bstat, w.sbstat);
-    hipLaunchKernelGGL(bdesc_kernel, dim3(mblk), dim3(tb), 0, st, m, w.hd, p->d_k, p->d_start,
-                       p->d_out_offs, w.xyzm, w.ids, w.cstat, w.cdyn, w.bstat, w.bdyn, w.sbstat,
-                       out_order, out_radius, w.desc);
+    hipLaunchKernelGGL(bdesc_kernel, dim3(mblk), dim3(tb), 0, st, m, w.hd, w.ks, w.starts,
+                       w.outo, w.xyzm, w.ids, w.cstat, w.cdyn, w.bstat, w.bdyn, w.sbstat,
+                       out_order, out_radius, use_io ? w.io : nullptr, w.desc);
     if ((e = hipGetLastError()) != hipSuccess) return set_error(BS_ERR_HIP, "%s", hipGetErrorString(e));
+    if (!p->use_graph) {
+        hipLaunchKernelGGL(queue_reset_kernel, dim3(1), dim3(64), 0, st, w.queue);
+        hipLaunchKernelGGL(batch_order_kernel, dim3(p->slots), dim3(kBatchBlock), 0, st, w.desc, w.lpt,
+                           p->mwork, w.queue);
+        e = hipGetLastError();
+        if (e != hipSuccess) return set_error(BS_ERR_HIP, "order launch: %s", hipGetErrorString(e));
+        return BS_OK;
+    }
     if (!p->exec || p->graph_ws != ws) {
         e = capture_order_graph(*p, w);
         if (e != hipSuccess) return set_error(BS_ERR_HIP, "graph capture: %s", hipGetErrorString(e));

@@ -6,6 +6,8 @@
 #include <stddef.h>
 #include <stdint.h>
 
+#include <vector>
+
 #include "../../include/bluesurfels.h"
 
 namespace bs {
@@ -56,6 +58,8 @@ size_t batch_workspace_bytes(const BatchPlan* p);
 int64_t batch_total_k(const BatchPlan* p);
 const int64_t* batch_out_offsets(const BatchPlan* p);
 int batch_slots(const BatchPlan* p);
+void batch_set_job_io(BatchPlan* p, const std::vector<int32_t*>& order, const std::vector<float*>& radius,
+                      const std::vector<uint32_t*>& done);
 int batch_plan_execute(BatchPlan* p, const float* pts, int32_t* out_order, float* out_radius, void* ws,
                        size_t ws_bytes, hipStream_t st);
 

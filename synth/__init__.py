@@ -323,3 +323,98 @@ def concat(objs: List[Surfels]):
     nrm = torch.cat([o.normals for o in objs]) if objs else torch.zeros((0, 3))
     col = torch.cat([o.colors for o in objs]) if objs else torch.zeros((0, 3), dtype=torch.uint8)
     return pts, nrm, col, offs
+
+
+def _inside_batched(kind, prm, center, rot, pts):
+    """Strictly-inside test of points against one primitive each (batched):
+    kind [S], prm [S,3], center [S,3], rot [S,3,3], pts [S,3]."""
+    q = torch.einsum("sji,sj->si", rot, pts - center)  # rot^T (p - c)
+    x, y, z = q.unbind(1)
+    a, b, c = prm.unbind(1)
+    sphere = x * x + y * y + z * z < a * a
+    box = (x.abs() < a) & (y.abs() < b) & (z.abs() < c)
+    cyl = (x * x + y * y < a * a) & (z.abs() < b)
+    rr = torch.sqrt(x * x + y * y) - a
+    tor = rr * rr + z * z < b * b
+    return torch.where(kind == SPHERE, sphere, torch.where(kind == BOX, box,
+                       torch.where(kind == CYLINDER, cyl, tor)))
+
+
+def cad_parts_batch(sizes: List[int], seed: int = 3, count: int = 200, device="cpu",
+                    chunk: int = 1 << 24):
+    """Many CAD-like parts at once: object j is the union boundary of its own
+    `count` random boxes/cylinders (the recipe of :func:`cad_part`), with
+    sizes[j] area-uniform samples.  Returns (points [N,3] float32, offsets
+    list of m+1).  Vectorised over objects and processed in chunks of
+    samples, so thousands of objects take seconds on a GPU."""
+    device = torch.device(device)
+    m = len(sizes)
+    g = _gen(seed * 7919 + 29, device)
+    kind = torch.where(_rand(g, (m, count), device) < 0.5, BOX, CYLINDER)
+    dims = _log_uniform(g, (m, count, 3), 0.01, 1.0, device)
+    prm = torch.where((kind == BOX)[..., None], dims / 2,
+                      torch.stack([dims[..., 0] / 2, dims[..., 1] / 2, torch.zeros_like(dims[..., 0])], -1))
+    center = 2 * _rand(g, (m, count, 3), device)
+    rot = _random_rotations(g, m * count, device).view(m, count, 3, 3)
+    flat = Primitives(kind.reshape(-1), center.reshape(-1, 3), rot.reshape(-1, 3, 3), prm.reshape(-1, 3),
+                      torch.zeros((m * count, 3), dtype=torch.uint8, device=device))
+    area = _area(flat).view(m, count)
+    cdf = torch.cumsum(area, 1) / area.sum(1, keepdim=True)
+    cdf[:, -1] = 1.0
+    flat_cdf = (cdf + torch.arange(m, device=device, dtype=torch.float64)[:, None]).reshape(-1)
+    bound = _bound_radius(flat).view(m, count)
+    sizes_t = torch.tensor(sizes, dtype=torch.int64, device=device)
+    need = sizes_t.clone()
+    got: List[List[torch.Tensor]] = [[] for _ in range(m)]
+    have = torch.zeros(m, dtype=torch.int64, device=device)
+    over = 1.35
+    rounds = 0
+    while bool((need > 0).any()) and rounds < 12:
+        rounds += 1
+        want = torch.clamp((need.double() * over).ceil().long() + 16, min=0) * (need > 0)
+        obj_all = torch.repeat_interleave(torch.arange(m, device=device), want)
+        for s0 in range(0, int(obj_all.numel()), chunk):
+            obj = obj_all[s0:s0 + chunk]
+            u = _rand(g, (obj.numel(),), device) * 0.999999999 + obj.double()
+            pid_flat = torch.searchsorted(flat_cdf, u, right=True).clamp(max=m * count - 1)
+            pid_flat = torch.maximum(pid_flat, obj * count)
+            q, nrm, ok = _sample_local(g, flat, pid_flat, device)
+            r = flat.rot[pid_flat]
+            pts = torch.einsum("mij,mj->mi", r, q) + flat.center[pid_flat]
+            keep = ok.clone()
+            own = pid_flat - obj * count
+            for p in range(count):
+                fp = obj * count + p
+                near = keep & (own != p) & ((pts - flat.center[fp]).pow(2).sum(1) < bound.view(-1)[fp] ** 2)
+                idx = near.nonzero().squeeze(1)
+                if idx.numel():
+                    f = fp[idx]
+                    ins = _inside_batched(flat.kind[f], flat.prm[f], flat.center[f], flat.rot[f], pts[idx])
+                    keep[idx[ins]] = False
+            kept = keep.nonzero().squeeze(1)
+            ko = obj[kept]
+            kp = pts[kept].to(torch.float32)
+            # take at most `need` more per object, in sample order
+            order = torch.argsort(ko, stable=True)
+            ko = ko[order]
+            kp = kp[order]
+            counts = torch.bincount(ko, minlength=m)
+            starts = torch.cumsum(counts, 0) - counts
+            rank = torch.arange(ko.numel(), device=device) - starts[ko]
+            take = rank < (sizes_t - have)[ko]
+            ko = ko[take]
+            kp = kp[take]
+            taken = torch.bincount(ko, minlength=m)
+            if ko.numel():
+                for j, part in enumerate(torch.split(kp, taken.tolist())):
+                    if part.shape[0]:
+                        got[j].append(part)
+            have += taken
+        need = sizes_t - have
+        over *= 1.5
+    pts = torch.cat([torch.cat(gj) if gj else torch.zeros((0, 3), device=device) for gj in got]).contiguous()
+    offs = [0]
+    for n in sizes:
+        offs.append(offs[-1] + n)
+    assert pts.shape[0] == offs[-1], "generator did not reach the requested sizes"
+    return pts, offs

@@ -69,3 +69,12 @@ def test_batch_plan_validation_without_device(lib):
     ks = np.array([1], dtype=np.int64)
     rc = lib.bs_batch_plan_create(offs.ctypes.data_as(vp), ks.ctypes.data_as(vp), None, 1, None, ctypes.byref(plan))
     assert rc == bs.BS_ERR_INVALID_ARG
+
+
+def test_server_config_validation_without_device(lib):
+    cfg = bs.ServerConfig(0, 0, 4, 16, 50, 0.0)
+    srv = ctypes.c_void_p()
+    assert lib.bs_server_create(ctypes.byref(cfg), ctypes.byref(srv)) == bs.BS_ERR_INVALID_ARG
+    cfg = bs.ServerConfig(1 << 30, 0, 4, 16, 50, 0.0)
+    cfg.reserved[2] = 5
+    assert lib.bs_server_create(ctypes.byref(cfg), ctypes.byref(srv)) == bs.BS_ERR_INVALID_ARG
