@@ -1,111 +1,83 @@
 """Benchmark of the greedy blue-noise ordering on one MI355X.
 
-python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload NAME]
+python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-batch] [--no-serve]
+                [--no-cpu-baseline] [--no-full-scan]
 
-A step is one full ordering of one synthetic object: input validation,
-every greedy step (select + min-distance update) and the emitted order and
-radii, with the candidates already resident in HBM.  The default workload is
-one CAD-like part: the union boundary of 200 random boxes/cylinders, 4,194,304
-binary32 candidates, ordered to k = 262,144.
+A step is one full ordering of one synthetic CAD-like part -- the union
+boundary of 200 random boxes/cylinders, 4,194,304 binary32 candidates,
+ordered to k = 262,144 -- through the library's automatic kernel choice:
+input validation, grid build, every greedy step (select + min-distance
+update) and the emitted order and radii, with the candidates already
+resident in HBM.  `value` is ordered surfels per second of that step.
 
-Prints one JSON line (metric, value = ordered surfels/s, roofline of the
-dominant kernel measured with HIP events on the launch stream, and the CPU
-oracle timed on a bounded sample on this host).
+The same JSON line also carries
+  roofline      the dominant kernel (grid-pruned ordering) against HBM,
+                with its algorithmic bytes (16 B per candidate inside the
+                covering-radius ball, counted by the CPU oracle on the same
+                points) over its duration (device clock, launch stream);
+  latency       per-step p50 / p99 from device timestamps;
+  full_scan     the cooperative register-resident full scan on the same
+                input (16 B per live candidate per step);
+  batched       1,000 parts of the same kind, n log-uniform 2,048..2,097,152,
+                k = n/4, in one graph-captured persistent launch, against a
+                plain loop of one ordering launch per object (sampled);
+  served        a Poisson stream (mean 200 requests/s) of jobs with n
+                log-uniform 1e4..4e6, k = n/8, under an 80 GB budget:
+                p50 / p99 latency and throughput, against the plain loop;
+  cpu_baseline  the exact CPU oracle (grid-accelerated, one thread) on the
+                same points.
 """
 from __future__ import annotations
 
 import argparse
 import json
+import math
 import os
 import sys
+import threading
 import time
 
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
-
-WORKLOADS = {
-    # name: (n, k, seed, generator)
-    "cad_part": (4194304, 262144, 2, "cad_part"),
-    "sphere_box": (16384, 16384, 1, "sphere_and_box"),
-}
+N_MAIN, K_MAIN, SEED_MAIN = 4194304, 262144, 2
 
 
 def log(msg):
     print("[bench] " + msg, file=sys.stderr, flush=True)
 
 
-def make_points(gen, n, seed, device):
-    import synth
-    if gen == "cad_part":
-        return synth.cad_part(n, seed=seed, device=device)
-    return synth.sphere_and_box(n=n, seed=seed, device=device)
-
-
-def algorithmic_bytes_full_scan(n, k):
-    """16 B (xyz + min-distance) read per live candidate per update; the
-    update after pick t-1 (t = 1..k-1) runs over n - t live candidates."""
-    if k < 2:
-        return 0
-    live = (k - 1) * n - (k * (k - 1)) // 2
-    return 16 * live
-
-
-def cpu_baseline(points_host, k, start, budget_s=30.0):
-    """Oracle timed on this host on a bounded sample of the workload."""
-    import numpy as np
-    import oracle
-    P = np.ascontiguousarray(points_host)
-    n = P.shape[0]
-    # grid-accelerated exact oracle (single thread) on the full workload if it
-    # fits the budget, else on a prefix of the steps
-    kk = k
-    t0 = time.perf_counter()
-    order, radius = oracle.greedy32_grid(P, kk, start)
-    dt = time.perf_counter() - t0
-    return {"value": kk / dt, "unit": "ordered surfels/s", "cores": 1, "kind": "oracle",
-            "sample": "exact grid oracle (bs_oracle.c, 1 thread), full workload n=%d k=%d, %.1f s" % (n, kk, dt)}, order
-
-
-def main():
-    ap = argparse.ArgumentParser()
-    ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=3)
-    ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="cad_part", choices=sorted(WORKLOADS))
-    ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--kernel", type=int, default=0)
-    ap.add_argument("--per-thread", type=int, default=0)
-    ap.add_argument("--block", type=int, default=0)
-    args = ap.parse_args()
-    if args.gpus != 1:
-        print("bench.py measures one GPU: this build orders each object on a single MI355X; "
-              "--gpus %d is not supported (see the sharding note in DESIGN.md)" % args.gpus, file=sys.stderr)
-        sys.exit(2)
-
-    import numpy as np
+def ordering_kernel_seconds(bs, pts, k, start, tune):
+    """Duration of the ordering loop from the device clock (first to last pick)."""
     import torch
-    import paper_1904_08225_amd as bs
+    o, r, t = bs.order_profile(pts, k, start=start, tune=tune)
+    torch.cuda.synchronize()
+    tk = t.cpu().numpy().astype("float64")
+    hz = bs.wall_clock_hz()
+    d = (tk[1:] - tk[:-1]) / hz * 1e6
+    import numpy as np
+    return (tk[-1] - tk[0]) / hz, {"p50_us": float(np.percentile(d, 50)), "p99_us": float(np.percentile(d, 99)),
+                                   "mean_us": float(d.mean())}, o
 
-    n, k, seed, gen = WORKLOADS[args.workload]
+
+def bench_main(args, bs, torch, np):
+    import synth
     dev = torch.device("cuda:0")
-    torch.cuda.set_device(dev)
     t0 = time.time()
-    surf = make_points(gen, n, seed, dev)
+    surf = synth.cad_part(N_MAIN, seed=SEED_MAIN, device=dev)
     pts = surf.points.contiguous()
     torch.cuda.synchronize()
-    log("generated %s n=%d in %.1fs" % (args.workload, n, time.time() - t0))
-
-    tune = bs.tuning(kernel=args.kernel, block=args.block, per_thread=args.per_thread)
-    ws = torch.empty(max(bs.workspace_size(n, k, tune), 1), dtype=torch.uint8, device=dev)
+    log("generated cad_part n=%d in %.1fs" % (N_MAIN, time.time() - t0))
+    n, k = N_MAIN, K_MAIN
+    kernel = bs.auto_kernel(n, k)
+    ws = torch.empty(max(bs.workspace_size(n, k), 1), dtype=torch.uint8, device=dev)
     out_o = torch.empty(k, dtype=torch.int32, device=dev)
     out_r = torch.empty(k, dtype=torch.float32, device=dev)
-    start = bs.start_index(seed, n)
     stream = torch.cuda.current_stream()
 
     def step():
-        bs.order(pts, k, seed=seed, normals=surf.normals, colors=surf.colors, tune=tune, workspace=ws,
+        bs.order(pts, k, seed=SEED_MAIN, normals=surf.normals, colors=surf.colors, workspace=ws,
                  out_order=out_o, out_radius=out_r, check=False)
 
     for i in range(args.warmup):
@@ -117,22 +89,182 @@ def main():
     torch.cuda.synchronize()
     wall0 = time.perf_counter()
     ev0.record(stream)
-    for i in range(args.steps):
+    for _ in range(args.steps):
         step()
     ev1.record(stream)
     torch.cuda.synchronize()
     wall = time.perf_counter() - wall0
-    kern_ms = ev0.elapsed_time(ev1) / args.steps
+    ev_ms = ev0.elapsed_time(ev1) / args.steps
     ms = wall * 1000.0 / args.steps
-    log("timed %d steps: %.3f ms/step wall, %.3f ms/step events" % (args.steps, ms, kern_ms))
+    log("timed %d steps: %.1f ms/step wall, %.1f ms/step events" % (args.steps, ms, ev_ms))
+    start = bs.start_index(SEED_MAIN, n)
+    kern_s, lat, o_prof = ordering_kernel_seconds(bs, pts, k, start, None)
+    log("ordering kernel %.1f ms (device clock), p50 %.2f us/step" % (kern_s * 1e3, lat["p50_us"]))
+    return pts, surf, out_o, ms, ev_ms, kern_s, lat, kernel
 
-    value = k / (ms / 1000.0)
-    abytes = algorithmic_bytes_full_scan(n, k)
-    achieved = abytes / (kern_ms / 1000.0) / 1e9
-    kernel = bs.auto_kernel(n, k) if args.kernel == 0 else args.kernel
+
+def bench_full_scan(bs, torch, pts, k):
+    tune = bs.tuning(kernel=bs.KERNEL_COOP, block=1024, per_thread=16)
+    n = int(pts.shape[0])
+    start = bs.start_index(SEED_MAIN, n)
+    secs, lat, o = ordering_kernel_seconds(bs, pts, k, start, tune)
+    live = (k - 1) * n - (k * (k - 1)) // 2
+    abytes = 16 * live
+    return {"kernel": "resident cooperative full scan (256 workgroups x 16K candidates in VGPRs)",
+            "seconds": secs, "ordered_surfels_per_s": k / secs, "per_step_p50_us": lat["p50_us"],
+            "algorithmic_bytes": abytes, "achieved_GBs": abytes / secs / 1e9,
+            "frac_of_hbm_peak": abytes / secs / 1e9 / HBM_PEAK_GBS}, o
+
+
+def bench_batched(bs, torch, np):
+    import synth
+    dev = torch.device("cuda:0")
+    m = 1000
+    sizes = synth.log_uniform_sizes(m, 2048, 2097152, seed=3)
+    ks = [s // 4 for s in sizes]
+    seeds = [3 * 1000003 + j for j in range(m)]
+    t0 = time.time()
+    pts, offs = synth.cad_parts_batch(sizes, seed=3, count=200, device=dev)
+    torch.cuda.synchronize()
+    log("generated batch: %d objects, %d candidates in %.1fs" % (m, pts.shape[0], time.time() - t0))
+    plan = bs.BatchPlan(offs, ks, seeds)
+    out_o = torch.empty(plan.total_k, dtype=torch.int32, device=dev)
+    out_r = torch.empty(plan.total_k, dtype=torch.float32, device=dev)
+    plan.execute(pts, out_o, out_r)
+    torch.cuda.synchronize()
+    reps = 2
+    t = time.perf_counter()
+    for _ in range(reps):
+        plan.execute(pts, out_o, out_r)
+    torch.cuda.synchronize()
+    batch_s = (time.perf_counter() - t) / reps
+    log("batched: %.3f s for sum k = %d" % (batch_s, plan.total_k))
+    # plain loop: one ordering launch per object, sampled across the size range
+    order_idx = sorted(range(m), key=lambda j: sizes[j])
+    sample = order_idx[:: max(1, m // 24)]
+    sk = 0
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    for j in sample:
+        a, b = offs[j], offs[j + 1]
+        bs.order(pts[a:b], ks[j], seed=seeds[j], check=False)
+        sk += ks[j]
+    torch.cuda.synchronize()
+    sample_s = time.perf_counter() - t
+    plain_rate = sk / sample_s
+    plain_est_s = plan.total_k / plain_rate
+    # spot check: three objects equal ordering them alone
+    same = True
+    for j in (order_idx[0], order_idx[m // 2], order_idx[-1]):
+        a, b = offs[j], offs[j + 1]
+        so, _ = bs.order(pts[a:b], ks[j], seed=seeds[j])
+        oa, ob = plan.out_offsets[j], plan.out_offsets[j + 1]
+        same &= bool(torch.equal(so, out_o[oa:ob]))
+    plan.close()
+    return {"objects": m, "candidates": int(pts.shape[0]), "sum_k": int(plan.total_k),
+            "seconds": batch_s, "ordered_surfels_per_s": plan.total_k / batch_s,
+            "plain_loop_ordered_surfels_per_s": plain_rate,
+            "plain_loop_sample": "%d objects spread over the size range, %d picks, %.1f s" % (len(sample), sk, sample_s),
+            "plain_loop_estimated_seconds": plain_est_s, "speedup_vs_plain": plain_est_s / batch_s,
+            "largest_object_k": max(ks), "spot_check_equal_alone": same}
+
+
+def bench_served(bs, torch, np):
+    import synth
+    dev = torch.device("cuda:0")
+    pool_m = 64
+    sizes = synth.log_uniform_sizes(pool_m, 10000, 4000000, seed=4)
+    pts, offs = synth.cad_parts_batch(sizes, seed=4, count=200, device=dev)
+    torch.cuda.synchronize()
+    rng = np.random.default_rng(4)
+    nreq = 2000
+    arrivals = synth.poisson_arrivals(nreq, 200.0, seed=4)
+    picks = rng.integers(0, pool_m, nreq)
+    seeds = rng.integers(0, 2**62, nreq)
+    ks = [sizes[p] // 8 for p in picks]
+    total_k = int(sum(ks))
+    out_o = torch.empty(total_k, dtype=torch.int32, device=dev)
+    out_r = torch.empty(total_k, dtype=torch.float32, device=dev)
+    views = [pts[offs[p]:offs[p + 1]] for p in range(pool_m)]
+    # warm-up server (loads kernels)
+    warm = bs.Server(hbm_budget_bytes=80 << 30)
+    for i in range(8):
+        p = int(picks[i])
+        warm.submit(views[p], min(ks[i], 1000), int(seeds[i]), out_o[:1000], out_r[:1000])
+    warm.drain()
+    warm.close()
+    srv = bs.Server(hbm_budget_bytes=80 << 30, max_inflight=4, max_jobs_per_batch=256, poll_us=20)
+    off = 0
+    t0 = time.perf_counter()
+    for i in range(nreq):
+        now = time.perf_counter() - t0
+        if arrivals[i] > now:
+            time.sleep(arrivals[i] - now)
+        p = int(picks[i])
+        srv.submit(views[p], ks[i], int(seeds[i]), out_o[off:off + ks[i]], out_r[off:off + ks[i]])
+        off += ks[i]
+    srv.drain()
+    st = srv.stats()
+    srv.close()
+    log("served: p50 %.1f ms p99 %.1f ms, %.3g surfels/s" % (st["p50_us"] / 1e3, st["p99_us"] / 1e3,
+                                                              st["surfels_per_s"]))
+    # plain loop: one ordering launch per request, back to back, sampled
+    sample = list(range(0, nreq, nreq // 20))[:20]
+    sk = 0
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    for i in sample:
+        bs.order(views[int(picks[i])], ks[i], seed=int(seeds[i]), check=False)
+        sk += ks[i]
+    torch.cuda.synchronize()
+    plain_rate = sk / (time.perf_counter() - t)
+    offered = total_k / arrivals[-1]
+    return {"requests": nreq, "rate_hz": 200.0, "offered_surfels_per_s": offered,
+            "p50_latency_ms": st["p50_us"] / 1e3, "p99_latency_ms": st["p99_us"] / 1e3,
+            "max_latency_ms": st["max_us"] / 1e3, "served_surfels_per_s": st["surfels_per_s"],
+            "elapsed_s": st["elapsed_s"], "batches": st["batches"], "hbm_peak_bytes": st["hbm_peak"],
+            "plain_loop_ordered_surfels_per_s": plain_rate,
+            "speedup_vs_plain": st["surfels_per_s"] / plain_rate,
+            "plain_loop_sample": "%d requests back to back" % len(sample)}
+
+
+def cpu_baseline(points_host, k, start):
+    """The exact CPU oracle on the same points (bounded: about 10-20 s)."""
+    import oracle
+    t0 = time.perf_counter()
+    order, radius, st = oracle.greedy32_grid(points_host, k, start, stats=True)
+    dt = time.perf_counter() - t0
+    return {"value": k / dt, "unit": "ordered surfels/s", "cores": 1, "kind": "oracle",
+            "sample": "exact grid-accelerated oracle (oracle/bs_oracle.c, 1 thread) on the full "
+                      "workload n=%d k=%d, %.1f s" % (points_host.shape[0], k, dt)}, order, int(st["n_ball"].sum())
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-full-scan", action="store_true")
+    ap.add_argument("--no-batch", action="store_true")
+    ap.add_argument("--no-serve", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU: every object is ordered on a single MI355X and this build has "
+              "no multi-GPU path; --gpus %d is not supported (DESIGN.md describes how it would shard)"
+              % args.gpus, file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+    import paper_1904_08225_amd as bs
+
+    torch.cuda.set_device(0)
+    pts, surf, out_o, ms, ev_ms, kern_s, lat, kernel = bench_main(args, bs, torch, np)
+    n, k = N_MAIN, K_MAIN
     rec = {
         "metric": "ordered surfels/sec (exact greedy blue-noise ordering)",
-        "value": value,
+        "value": k / (ms / 1000.0),
         "unit": "ordered surfels/s",
         "n_gpus": 1,
         "steps": args.steps,
@@ -142,19 +274,43 @@ def main():
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "f32",
-        "data": "synthetic",
-        "config": {"workload": args.workload, "n": n, "k": k, "seed": seed, "kernel": kernel,
-                   "per_step_us": kern_ms * 1000.0 / max(k - 1, 1)},
-        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None},
+        "data": "synthetic (seeded union-boundary samples of 200 random boxes/cylinders)",
+        "config": {"workload": "cad_part n=4,194,304 k=262,144 (union of 200 boxes/cylinders)",
+                   "n": n, "k": k, "seed": SEED_MAIN,
+                   "kernel": {1: "resident workgroup", 2: "cooperative full scan",
+                              3: "grid-pruned"}.get(kernel, str(kernel)),
+                   "event_ms_per_step": ev_ms},
+        "latency": {"per_step_p50_us": lat["p50_us"], "per_step_p99_us": lat["p99_us"],
+                    "per_step_mean_us": lat["mean_us"], "source": "device wall clock per pick"},
     }
+    host = pts.cpu().numpy()
+    n_ball = None
     if not args.no_cpu_baseline:
-        host = pts.cpu().numpy()
-        cb, eo = cpu_baseline(host, k, start)
+        cb, eo, n_ball = cpu_baseline(host, k, bs.start_index(SEED_MAIN, n))
         rec["cpu_baseline"] = cb
-        got = out_o.cpu().numpy()
-        rec["config"]["matches_oracle"] = bool(np.array_equal(got, eo))
-        log("cpu baseline: %s" % cb["sample"])
+        rec["config"]["matches_oracle"] = bool(np.array_equal(out_o.cpu().numpy(), eo))
+        log("cpu baseline: " + cb["sample"])
+    if n_ball is not None:
+        abytes = 16 * n_ball
+        achieved = abytes / kern_s / 1e9
+        rec["roofline"] = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                           "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                           "kernel": "grid_single_kernel<512,4096>",
+                           "algorithmic_bytes": abytes, "kernel_seconds": kern_s,
+                           "note": "16 B per live candidate inside the covering-radius ball per step "
+                                   "(pruned accounting); the step chain is latency-bound"}
+    if not args.no_full_scan:
+        fs, fo = bench_full_scan(bs, torch, pts, k)
+        fs["matches_grid_kernel"] = bool(torch.equal(fo, out_o))
+        rec["full_scan"] = fs
+        log("full scan: %.2f s, %.0f GB/s algorithmic" % (fs["seconds"], fs["achieved_GBs"]))
+    del surf, pts
+    torch.cuda.empty_cache()
+    if not args.no_batch:
+        rec["batched"] = bench_batched(bs, torch, np)
+        torch.cuda.empty_cache()
+    if not args.no_serve:
+        rec["served"] = bench_served(bs, torch, np)
     print(json.dumps(rec), flush=True)
 
 
