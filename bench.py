@@ -44,12 +44,33 @@ HBM_PEAK_GBS = 8000.0
 N_MAIN, K_MAIN, SEED_MAIN = 4194304, 262144, 2
 
 
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "grid_cad_part_4M_hbm_counters.txt")
+
+
+def measured_traffic():
+    """HBM bytes per launch of the grid ordering kernel from the committed
+    FETCH_SIZE / WRITE_SIZE counter summary, or None when the kernel's
+    sources have changed since the counters were taken."""
+    import hashlib
+    try:
+        fields = dict(l.split(": ", 1) for l in open(TRAFFIC_FILE).read().splitlines() if ": " in l)
+        h = hashlib.sha256()
+        for src in fields["kernel_sources"].split():
+            h.update(open(os.path.join(ROOT, src), "rb").read())
+        if h.hexdigest() != fields["kernel_source_sha256"].strip():
+            return None
+        return float(fields["traffic_bytes_per_launch"])
+    except (OSError, KeyError, ValueError):
+        return None
+
+
 def log(msg):
     print("[bench] " + msg, file=sys.stderr, flush=True)
 
 
 def ordering_kernel_seconds(bs, pts, k, start, tune):
-    """Duration of the ordering loop from the device clock (first to last pick)."""
+    """Duration of the ordering loop from the device clock (first to last pick)
+    and per-step latencies."""
     import torch
     o, r, t = bs.order_profile(pts, k, start=start, tune=tune)
     torch.cuda.synchronize()
@@ -75,39 +96,54 @@ def bench_main(args, bs, torch, np):
     out_o = torch.empty(k, dtype=torch.int32, device=dev)
     out_r = torch.empty(k, dtype=torch.float32, device=dev)
     stream = torch.cuda.current_stream()
+    start = bs.start_index(SEED_MAIN, n)
 
-    def step():
-        bs.order(pts, k, seed=SEED_MAIN, normals=surf.normals, colors=surf.colors, workspace=ws,
-                 out_order=out_o, out_radius=out_r, check=False)
+    def new_event():
+        ev = torch.cuda.Event(enable_timing=True)
+        ev.record(stream)  # creates the handle the library records into
+        return ev
+
+    def step(events=None):
+        # the same kernels as bs_order; the events bracket the ordering kernel
+        bs.order_profile(pts, k, start=start, stream=stream, ticks=False, events=events, workspace=ws,
+                         out_order=out_o, out_radius=out_r)
 
     for i in range(args.warmup):
         step()
         torch.cuda.synchronize()
         log("warmup %d done" % i)
-    ev0 = torch.cuda.Event(enable_timing=True)
-    ev1 = torch.cuda.Event(enable_timing=True)
+    kev = [(new_event(), new_event()) for _ in range(args.steps)]
+    ev0, ev1 = new_event(), new_event()
     torch.cuda.synchronize()
     wall0 = time.perf_counter()
     ev0.record(stream)
-    for _ in range(args.steps):
-        step()
+    for i in range(args.steps):
+        step(kev[i])
     ev1.record(stream)
     torch.cuda.synchronize()
     wall = time.perf_counter() - wall0
     ev_ms = ev0.elapsed_time(ev1) / args.steps
+    kern_ms = sum(b.elapsed_time(e) for b, e in kev) / args.steps
     ms = wall * 1000.0 / args.steps
-    log("timed %d steps: %.1f ms/step wall, %.1f ms/step events" % (args.steps, ms, ev_ms))
-    start = bs.start_index(SEED_MAIN, n)
-    kern_s, lat, o_prof = ordering_kernel_seconds(bs, pts, k, start, None)
-    log("ordering kernel %.1f ms (device clock), p50 %.2f us/step" % (kern_s * 1e3, lat["p50_us"]))
-    return pts, surf, out_o, ms, ev_ms, kern_s, lat, kernel
+    log("timed %d steps: %.1f ms/step wall, %.1f ms/step events, ordering kernel %.1f ms"
+        % (args.steps, ms, ev_ms, kern_ms))
+    _, lat, _ = ordering_kernel_seconds(bs, pts, k, start, None)
+    log("per-step p50 %.2f us (device clock)" % lat["p50_us"])
+    return pts, surf, out_o, ms, ev_ms, kern_ms / 1e3, lat, kernel
 
 
 def bench_full_scan(bs, torch, pts, k):
     tune = bs.tuning(kernel=bs.KERNEL_COOP, block=1024, per_thread=16)
     n = int(pts.shape[0])
     start = bs.start_index(SEED_MAIN, n)
-    secs, lat, o = ordering_kernel_seconds(bs, pts, k, start, tune)
+    _, lat, _ = ordering_kernel_seconds(bs, pts, k, start, tune)
+    stream = torch.cuda.current_stream()
+    b, e = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    b.record(stream)
+    e.record(stream)
+    o, _, _ = bs.order_profile(pts, k, start=start, tune=tune, stream=stream, ticks=False, events=(b, e))
+    torch.cuda.synchronize()
+    secs = b.elapsed_time(e) / 1e3
     live = (k - 1) * n - (k * (k - 1)) // 2
     abytes = 16 * live
     return {"kernel": "resident cooperative full scan (256 workgroups x 16K candidates in VGPRs)",
@@ -248,6 +284,9 @@ def main():
     ap.add_argument("--no-full-scan", action="store_true")
     ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--no-serve", action="store_true")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
+                    help="only run two plain device-to-device copies of BYTES bytes (scales the "
+                         "FETCH_SIZE / WRITE_SIZE counters to bytes) and exit")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: every object is ordered on a single MI355X and this build has "
@@ -260,6 +299,14 @@ def main():
     import paper_1904_08225_amd as bs
 
     torch.cuda.set_device(0)
+    if args.copy_calibration > 0:
+        src = torch.empty(args.copy_calibration, dtype=torch.uint8, device="cuda:0").fill_(1)
+        dst = torch.empty_like(src)
+        for _ in range(2):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_calibration_bytes": args.copy_calibration, "copies": 2}), flush=True)
+        return
     pts, surf, out_o, ms, ev_ms, kern_s, lat, kernel = bench_main(args, bs, torch, np)
     n, k = N_MAIN, K_MAIN
     rec = {
@@ -294,9 +341,13 @@ def main():
         abytes = 16 * n_ball
         achieved = abytes / kern_s / 1e9
         rec["roofline"] = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                           "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                           "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(),
                            "kernel": "grid_single_kernel<512,4096>",
                            "algorithmic_bytes": abytes, "kernel_seconds": kern_s,
+                           "traffic_source": "rocprofv3 FETCH_SIZE and WRITE_SIZE per launch, scaled by a "
+                                             "plain copy of known size (profiles/grid_cad_part_4M_hbm_counters.txt)",
+                           "kernel_time_source": "HIP events recorded on the launch stream around the "
+                                                 "ordering kernel, mean over the timed steps",
                            "note": "16 B per live candidate inside the covering-radius ball per step "
                                    "(pruned accounting); the step chain is latency-bound"}
     if not args.no_full_scan:

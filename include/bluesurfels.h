@@ -132,15 +132,21 @@ int bs_order_ex(const float* d_points, const float* d_normals, const uint8_t* d_
                 const bs_tuning* tuning, void* stream);
 
 /*
- * Profiling form of bs_order_ex (same ordering, same workspace size): also
- * writes d_step_ticks[t] (device uint64[k]) = the device wall clock (see
- * bs_wall_clock_hz) right after pick t is emitted, so that consecutive
- * differences are per-step latencies.  start_index as in bs_order_ex, with
- * -1 meaning SplitMix64(0) mod n.  Errors: as bs_order_ex, plus
- * BS_ERR_INVALID_ARG for a null tick buffer when k > 0.
+ * Profiling form of bs_order_ex (same ordering, same workspace size, same
+ * kernels).  Two optional instruments:
+ *   d_step_ticks  NULL or device uint64[k]: the device wall clock (see
+ *                 bs_wall_clock_hz) right after pick t is emitted, so that
+ *                 consecutive differences are per-step latencies;
+ *   event_begin,  NULL or hipEvent_t handles created by the caller: recorded
+ *   event_end     on `stream` immediately before and after the launch of the
+ *                 ordering kernel itself (after validation and grid build),
+ *                 so hipEventElapsedTime gives that kernel's duration.
+ * start_index as in bs_order_ex, with -1 meaning SplitMix64(0) mod n.
+ * Errors: as bs_order_ex; BS_ERR_HIP if an event cannot be recorded.
  */
 int bs_order_profile(const float* d_points, int64_t n, int64_t k, int64_t start_index,
                      int32_t* d_out_order, float* d_out_radius, uint64_t* d_step_ticks,
+                     void* event_begin, void* event_end,
                      void* d_workspace, size_t workspace_bytes, const bs_tuning* tuning,
                      void* stream);
 

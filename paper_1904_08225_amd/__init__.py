@@ -87,7 +87,7 @@ def load():
     lib.bs_order.restype = i32
     lib.bs_order_ex.argtypes = [vp, vp, vp, i64, i64, u64, i64, vp, vp, vp, sz, tp, vp]
     lib.bs_order_ex.restype = i32
-    lib.bs_order_profile.argtypes = [vp, i64, i64, i64, vp, vp, vp, vp, sz, tp, vp]
+    lib.bs_order_profile.argtypes = [vp, i64, i64, i64, vp, vp, vp, vp, vp, vp, sz, tp, vp]
     lib.bs_order_profile.restype = i32
     lib.bs_wall_clock_hz.argtypes = []
     lib.bs_wall_clock_hz.restype = ctypes.c_double
@@ -216,25 +216,40 @@ def wall_clock_hz() -> float:
     return float(load().bs_wall_clock_hz())
 
 
-def order_profile(points, k: int, start: int = -1, tune: Optional[Tuning] = None, stream=None):
-    """Ordering plus per-step device timestamps.
+def _event_handle(ev):
+    if ev is None:
+        return None
+    h = int(ev.cuda_event)
+    if h == 0:
+        raise ValueError("event not created yet: record it once before passing it")
+    return ctypes.c_void_p(h)
 
-    Returns ``(order, radius, ticks)`` where ``ticks`` is uint64 [k] (as
-    int64 tensor) of the device wall clock after each pick."""
+
+def order_profile(points, k: int, start: int = -1, tune: Optional[Tuning] = None, stream=None,
+                  ticks: bool = True, events=None, workspace=None, out_order=None, out_radius=None):
+    """Ordering plus instruments (``bs_order_profile``).
+
+    Returns ``(order, radius, ticks)``; ``ticks`` (when requested) is uint64
+    [k] (as an int64 tensor) of the device wall clock after each pick, else
+    None.  ``events`` = (begin, end) ``torch.cuda.Event`` objects, each
+    already recorded once (so that the handle exists), are recorded on the
+    stream right before and after the ordering kernel itself."""
     import torch
     lib = load()
     points = _prep_points(points)
     n = int(points.shape[0])
     dev = points.device
     tp = ctypes.byref(tune) if tune is not None else None
-    need = int(lib.bs_workspace_size(n, k, tp))
-    ws = torch.empty(max(need, 1), dtype=torch.uint8, device=dev)
-    o = torch.empty(k, dtype=torch.int32, device=dev)
-    r = torch.empty(k, dtype=torch.float32, device=dev)
-    ticks = torch.zeros(k, dtype=torch.int64, device=dev)
-    _check(lib.bs_order_profile(_ptr(points), n, k, start, _ptr(o), _ptr(r), _ptr(ticks), _ptr(ws),
-                                int(ws.numel()), tp, _stream_handle(stream)))
-    return o, r, ticks
+    if workspace is None:
+        need = int(lib.bs_workspace_size(n, k, tp))
+        workspace = torch.empty(max(need, 1), dtype=torch.uint8, device=dev)
+    o = torch.empty(k, dtype=torch.int32, device=dev) if out_order is None else out_order
+    r = torch.empty(k, dtype=torch.float32, device=dev) if out_radius is None else out_radius
+    tk = torch.zeros(k, dtype=torch.int64, device=dev) if ticks else None
+    eb, ee = (None, None) if events is None else (_event_handle(events[0]), _event_handle(events[1]))
+    _check(lib.bs_order_profile(_ptr(points), n, k, start, _ptr(o), _ptr(r), _ptr(tk), eb, ee,
+                                _ptr(workspace), int(workspace.numel()), tp, _stream_handle(stream)))
+    return o, r, tk
 
 
 class BatchPlan:

@@ -153,8 +153,8 @@ size_t bs_workspace_size(int64_t n, int64_t k, const bs_tuning* tuning) {
 
 static int order_impl(const float* d_points, int64_t n, int64_t k, uint64_t seed,
                       int64_t start_index, int32_t* d_out_order, float* d_out_radius,
-                      uint64_t* d_ticks, void* d_workspace, size_t workspace_bytes,
-                      const bs_tuning* tuning, void* stream) {
+                      uint64_t* d_ticks, const KernelEvents* ev, void* d_workspace,
+                      size_t workspace_bytes, const bs_tuning* tuning, void* stream) {
     if (k < 0) return set_error(BS_ERR_INVALID_ARG, "k=%lld < 0", (long long)k);
     if (k == 0) return BS_OK;
     if (n < 1 || n >= (int64_t(1) << 31))
@@ -179,7 +179,7 @@ static int order_impl(const float* d_points, int64_t n, int64_t k, uint64_t seed
     hipError_t e = hipSuccess;
     if (plan.kernel == BS_KERNEL_GRID) {
         e = launch_grid(d_points, int(n), int(k), int(start), d_out_order, d_out_radius, d_workspace,
-                        plan.cell_points, plan.grid_block, d_ticks, st);
+                        plan.cell_points, plan.grid_block, d_ticks, st, ev);
     } else {
         DevHeader* hdr = reinterpret_cast<DevHeader*>(d_workspace);
         void* scratch = static_cast<char*>(d_workspace) + align_up(sizeof(DevHeader));
@@ -187,7 +187,7 @@ static int order_impl(const float* d_points, int64_t n, int64_t k, uint64_t seed
         if (e == hipSuccess) e = launch_validate(d_points, n, hdr, st);
         if (e == hipSuccess)
             e = launch_scan(plan.shape, d_points, int(n), int(k), int(start), d_out_order, d_out_radius,
-                            hdr, scratch, d_ticks, st);
+                            hdr, scratch, d_ticks, st, ev);
     }
     if (e != hipSuccess) return set_error(BS_ERR_HIP, "launch failed: %s", hipGetErrorString(e));
     return BS_OK;
@@ -199,16 +199,19 @@ int bs_order_ex(const float* d_points, const float* d_normals, const uint8_t* d_
                 size_t workspace_bytes, const bs_tuning* tuning, void* stream) {
     (void)d_normals;
     (void)d_colors;
-    return order_impl(d_points, n, k, seed, start_index, d_out_order, d_out_radius, nullptr,
+    return order_impl(d_points, n, k, seed, start_index, d_out_order, d_out_radius, nullptr, nullptr,
                       d_workspace, workspace_bytes, tuning, stream);
 }
 
 int bs_order_profile(const float* d_points, int64_t n, int64_t k, int64_t start_index,
                      int32_t* d_out_order, float* d_out_radius, uint64_t* d_step_ticks,
+                     void* event_begin, void* event_end,
                      void* d_workspace, size_t workspace_bytes, const bs_tuning* tuning,
                      void* stream) {
-    if (k > 0 && !d_step_ticks) return set_error(BS_ERR_INVALID_ARG, "null step tick buffer");
-    return order_impl(d_points, n, k, 0, start_index, d_out_order, d_out_radius, d_step_ticks,
+    KernelEvents ev;
+    ev.begin = reinterpret_cast<hipEvent_t>(event_begin);
+    ev.end = reinterpret_cast<hipEvent_t>(event_end);
+    return order_impl(d_points, n, k, 0, start_index, d_out_order, d_out_radius, d_step_ticks, &ev,
                       d_workspace, workspace_bytes, tuning, stream);
 }
 

@@ -49,7 +49,9 @@ struct GridLayout {
 GridLayout grid_layout(int64_t n, int block);
 int grid_block_size(int64_t n);
 int grid_max_blocks(int block);
+struct KernelEvents;
 hipError_t launch_grid(const float* pts, int n, int k, int start, int32_t* order, float* radius,
-                       void* ws, float target, int block, uint64_t* ticks, hipStream_t st);
+                       void* ws, float target, int block, uint64_t* ticks, hipStream_t st,
+                       const KernelEvents* ev = nullptr);
 
 }  // namespace bs

@@ -285,7 +285,8 @@ int grid_block_size(int64_t n) { return n > (int64_t(1) << 16) ? 512 : 256; }
 int grid_max_blocks(int block) { return block == 512 ? 4096 : 1024; }
 
 hipError_t launch_grid(const float* pts, int n, int k, int start, int32_t* order, float* radius,
-                       void* ws, float target, int block, uint64_t* ticks, hipStream_t st) {
+                       void* ws, float target, int block, uint64_t* ticks, hipStream_t st,
+                       const KernelEvents* ev) {
     const GridLayout g = grid_layout(n, block);
     char* base = static_cast<char*>(ws);
     DevHeader* hdr = reinterpret_cast<DevHeader*>(base + g.dev_header);
@@ -349,13 +350,16 @@ hipError_t launch_grid(const float* pts, int n, int k, int start, int32_t* order
     o.order = order;
     o.radius = radius;
     o.ticks = ticks;
+    if (ev && ev->begin && (e = hipEventRecord(ev->begin, st)) != hipSuccess) return e;
     if (block == 512)
         hipLaunchKernelGGL((grid_single_kernel<512, 4096>), dim3(1), dim3(512), 0, st, o, hdr, gh);
     else if (block == 1024)
         hipLaunchKernelGGL((grid_single_kernel<1024, 1024>), dim3(1), dim3(1024), 0, st, o, hdr, gh);
     else
         hipLaunchKernelGGL((grid_single_kernel<256, 1024>), dim3(1), dim3(256), 0, st, o, hdr, gh);
-    return hipGetLastError();
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    if (ev && ev->end) e = hipEventRecord(ev->end, st);
+    return e;
 }
 
 }  // namespace bs

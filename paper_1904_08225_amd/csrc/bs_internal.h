@@ -45,9 +45,16 @@ size_t scan_workspace_bytes(const ScanShape& s);
 // Kernel launchers (bs_scan.hip).  All return hipError_t of the launch.
 hipError_t launch_init_header(DevHeader* hdr, hipStream_t st);
 hipError_t launch_validate(const float* pts, int64_t n, DevHeader* hdr, hipStream_t st);
+// Optional events recorded on the launch stream right before and right after
+// the ordering kernel itself (not the validation / grid build before it).
+struct KernelEvents {
+    hipEvent_t begin = nullptr;
+    hipEvent_t end = nullptr;
+};
+
 hipError_t launch_scan(const ScanShape& s, const float* pts, int n, int k, int start,
                        int32_t* order, float* radius, DevHeader* hdr, void* scratch,
-                       uint64_t* ticks, hipStream_t st);
+                       uint64_t* ticks, hipStream_t st, const KernelEvents* ev = nullptr);
 
 // Batched plans (bs_batch.hip).
 struct BatchPlan;

@@ -132,18 +132,38 @@ __global__ void validate_kernel(const float* __restrict__ pts, int64_t n, DevHea
         }
     }
     (void)total;
-    if (__any(bad)) {
-        if ((threadIdx.x & 63) == 0) atomicOr(&hdr->nonfinite, 1u);
-    }
+    // wave, then workgroup reduction: one set of atomics per workgroup
+    __shared__ uint32_t s_red[4][7];
+    const int w = threadIdx.x >> 6;
+    const bool any_bad = __any(bad);
+    uint32_t v[6];
     for (int a = 0; a < 3; ++a) {
         uint32_t l = lo[a], h = hi[a];
         for (int off = 32; off > 0; off >>= 1) {
             l = min(l, uint32_t(__shfl_xor(int(l), off, 64)));
             h = max(h, uint32_t(__shfl_xor(int(h), off, 64)));
         }
-        if ((threadIdx.x & 63) == 0) {
-            atomicMin(&hdr->bbox[a], l);
-            atomicMax(&hdr->bbox[3 + a], h);
+        v[a] = l;
+        v[3 + a] = h;
+    }
+    if ((threadIdx.x & 63) == 0) {
+        for (int a = 0; a < 6; ++a) s_red[w][a] = v[a];
+        s_red[w][6] = any_bad ? 1u : 0u;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        const int nw = int(blockDim.x) >> 6;
+        for (int j = 1; j < nw; ++j) {
+            for (int a = 0; a < 3; ++a) {
+                v[a] = min(v[a], s_red[j][a]);
+                v[3 + a] = max(v[3 + a], s_red[j][3 + a]);
+            }
+            s_red[0][6] |= s_red[j][6];
+        }
+        if (s_red[0][6]) atomicOr(&hdr->nonfinite, 1u);
+        for (int a = 0; a < 3; ++a) {
+            atomicMin(&hdr->bbox[a], v[a]);
+            atomicMax(&hdr->bbox[3 + a], v[3 + a]);
         }
     }
 }
@@ -417,30 +437,35 @@ hipError_t launch_init_header(DevHeader* hdr, hipStream_t st) {
 hipError_t launch_validate(const float* pts, int64_t n, DevHeader* hdr, hipStream_t st) {
     if (n <= 0) return hipSuccess;
     int64_t blocks = (n + 255) / 256;
-    if (blocks > 2048) blocks = 2048;
+    if (blocks > 1024) blocks = 1024;
     hipLaunchKernelGGL(validate_kernel, dim3(unsigned(blocks)), dim3(256), 0, st, pts, n, hdr);
     return hipGetLastError();
 }
 
 hipError_t launch_scan(const ScanShape& s, const float* pts, int n, int k, int start,
                        int32_t* order, float* radius, DevHeader* hdr, void* scratch,
-                       uint64_t* ticks, hipStream_t st) {
+                       uint64_t* ticks, hipStream_t st, const KernelEvents* ev) {
     const ScanEntry* e = find_entry(s.block, s.per_thread);
     if (!e) return hipErrorInvalidValue;
     uint64_t* slots = reinterpret_cast<uint64_t*>(scratch);
+    hipError_t err = hipSuccess;
     if (s.groups <= 1) {
+        if (ev && ev->begin && (err = hipEventRecord(ev->begin, st)) != hipSuccess) return err;
         hipLaunchKernelGGL(e->single, dim3(1), dim3(s.block), 0, st, pts, n, k, start, order,
                            radius, hdr, slots, ticks);
-        return hipGetLastError();
+    } else {
+        // stale records from an earlier call must not carry matching tags
+        hipLaunchKernelGGL(clear_slots_kernel, dim3(1), dim3(256), 0, st, slots, 2 * s.groups * kRecWords);
+        if ((err = hipGetLastError()) != hipSuccess) return err;
+        if (ev && ev->begin && (err = hipEventRecord(ev->begin, st)) != hipSuccess) return err;
+        void* args[] = {(void*)&pts,   (void*)&n,   (void*)&k,     (void*)&start, (void*)&order,
+                        (void*)&radius, (void*)&hdr, (void*)&slots, (void*)&ticks};
+        err = hipLaunchCooperativeKernel(reinterpret_cast<const void*>(e->multi), dim3(s.groups),
+                                         dim3(s.block), args, 0, st);
     }
-    // stale records from an earlier call must not carry matching tags
-    hipLaunchKernelGGL(clear_slots_kernel, dim3(1), dim3(256), 0, st, slots, 2 * s.groups * kRecWords);
-    hipError_t err = hipGetLastError();
-    if (err != hipSuccess) return err;
-    void* args[] = {(void*)&pts,   (void*)&n,   (void*)&k,     (void*)&start, (void*)&order,
-                    (void*)&radius, (void*)&hdr, (void*)&slots, (void*)&ticks};
-    return hipLaunchCooperativeKernel(reinterpret_cast<const void*>(e->multi), dim3(s.groups),
-                                      dim3(s.block), args, 0, st);
+    if (err == hipSuccess) err = hipGetLastError();
+    if (err == hipSuccess && ev && ev->end) err = hipEventRecord(ev->end, st);
+    return err;
 }
 
 }  // namespace bs

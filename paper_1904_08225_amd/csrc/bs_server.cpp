@@ -42,6 +42,7 @@ struct Job {
 
 struct InFlight {
     int stream_index;
+    bool long_jobs = false;
     BatchPlan* plan = nullptr;
     void* staging = nullptr;
     void* ws = nullptr;
@@ -91,21 +92,43 @@ size_t job_bytes_estimate(int64_t n, int64_t k) {
     return size_t(n) * 64;
 }
 
-// Launch one micro-batch from the front of the pending queue (caller holds mu).
-bool launch_batch(Server& s, int si) {
+// Jobs of very different lengths are not mixed in one micro-batch: a batch
+// holds its stream until its longest job ends.  Long jobs (k >= kLongK) may
+// occupy at most half of the streams, so short jobs always find one.
+constexpr int64_t kLongK = 32768;
+
+bool is_long(const Job& j) { return j.req.k >= kLongK; }
+
+// Launch one micro-batch on stream si (caller holds mu).  Takes, in arrival
+// order, pending jobs of the oldest admissible job's length class.
+bool launch_batch(Server& s, int si, int long_streams_busy) {
     std::vector<uint64_t> take;
     size_t bytes = 0;
     int64_t total_n = 0;
     const size_t budget = s.cfg.hbm_budget_bytes;
-    while (!s.pending.empty() && int(take.size()) < s.cfg.max_jobs_per_batch &&
-           int(take.size()) < int(s.free_flags.size())) {
-        const Job& j = s.jobs[s.pending.front()];
+    const int max_long = std::max(1, int(s.streams.size()) / 2);
+    int cls = -1;
+    for (auto it = s.pending.begin(); it != s.pending.end();) {
+        if (int(take.size()) >= s.cfg.max_jobs_per_batch || int(take.size()) >= int(s.free_flags.size())) break;
+        const Job& j = s.jobs[*it];
+        const int c = is_long(j) ? 1 : 0;
+        if (cls < 0) {
+            if (c == 1 && long_streams_busy >= max_long) {
+                ++it;  // no stream for another long batch: look for short jobs
+                continue;
+            }
+            cls = c;
+        }
+        if (c != cls) {
+            ++it;
+            continue;
+        }
         const size_t b = job_bytes_estimate(j.req.n, j.req.k);
         if (s.bytes_in_use + bytes + b > budget) break;  // waits until memory frees up
         bytes += b;
         total_n += j.req.n;
-        take.push_back(s.pending.front());
-        s.pending.pop_front();
+        take.push_back(*it);
+        it = s.pending.erase(it);
     }
     if (take.empty()) return false;
 
@@ -150,7 +173,7 @@ bool launch_batch(Server& s, int si) {
             s.free_flags.push_back(j.flag_slot);
             j.flag_slot = -1;
             if (!s.inflight.empty()) {  // wait for memory to free up
-                s.pending.push_front(take[0]);
+                s.pending.insert(std::lower_bound(s.pending.begin(), s.pending.end(), take[0]), take[0]);
                 return false;
             }
             j.done = true;  // can never fit
@@ -163,7 +186,7 @@ bool launch_batch(Server& s, int si) {
         Job& last = s.jobs[take.back()];
         s.free_flags.push_back(last.flag_slot);
         last.flag_slot = -1;
-        s.pending.push_front(take.back());
+        s.pending.insert(std::lower_bound(s.pending.begin(), s.pending.end(), take.back()), take.back());
         take.pop_back();
         offs.resize(take.size() + 1);
         ks.resize(take.size());
@@ -212,6 +235,7 @@ bool launch_batch(Server& s, int si) {
         s.cv_done.notify_all();
         return true;
     }
+    f.long_jobs = is_long(s.jobs[take[0]]);
     s.bytes_in_use += f.bytes;
     s.bytes_peak = std::max(s.bytes_peak, s.bytes_in_use);
     s.admitted += int64_t(take.size());
@@ -275,13 +299,15 @@ void dispatcher(Server* sp) {
     std::unique_lock<std::mutex> lk(s.mu);
     while (true) {
         reap(s);
-        // admit while a stream is free and the head of the queue fits
+        // admit while a stream is free and pending jobs fit
         bool launched = true;
         while (launched && !s.pending.empty()) {
             launched = false;
+            int long_busy = 0;
+            for (const InFlight& f : s.inflight) long_busy += f.long_jobs ? 1 : 0;
             for (size_t si = 0; si < s.streams.size(); ++si) {
                 if (!s.stream_busy[si]) {
-                    launched = launch_batch(s, int(si));
+                    launched = launch_batch(s, int(si), long_busy);
                     break;
                 }
             }
