@@ -89,7 +89,10 @@ typedef struct {
     int32_t per_thread;    /* candidates per thread for resident kernels (0 = auto) */
     int32_t groups;        /* workgroups of a cooperative launch (0 = auto) */
     float cell_points;     /* grid kernel: target mean candidates per cell (0 = auto) */
-    int32_t reserved[7];   /* must be zero */
+    int32_t picks;         /* grid kernel: most picks per round, 0 = auto, 1 = one pick
+                              per round, 2..16 = several exact picks per round (same
+                              result; see bs_order_ex) */
+    int32_t reserved[6];   /* must be zero */
 } bs_tuning;
 
 /* ------------------------------------------------------- single instance */

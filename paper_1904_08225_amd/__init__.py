@@ -46,12 +46,13 @@ class BSError(RuntimeError):
 class Tuning(ctypes.Structure):
     _fields_ = [("kernel", ctypes.c_int32), ("block", ctypes.c_int32),
                 ("per_thread", ctypes.c_int32), ("groups", ctypes.c_int32),
-                ("cell_points", ctypes.c_float), ("reserved", ctypes.c_int32 * 7)]
+                ("cell_points", ctypes.c_float), ("picks", ctypes.c_int32),
+                ("reserved", ctypes.c_int32 * 6)]
 
 
 def tuning(kernel: int = 0, block: int = 0, per_thread: int = 0, groups: int = 0,
-           cell_points: float = 0.0) -> Tuning:
-    return Tuning(kernel, block, per_thread, groups, cell_points)
+           cell_points: float = 0.0, picks: int = 0) -> Tuning:
+    return Tuning(kernel, block, per_thread, groups, cell_points, picks)
 
 
 def header_functions():

@@ -33,20 +33,26 @@ int device_cus() {
     return g_dev[dev].cus;
 }
 
+constexpr int kMaxGridPicks = 16;     // picks per round of the grid kernel
+constexpr int kDefaultGridPicks = 16;
+
 bool tuning_clean(const bs_tuning* t) {
     if (!t) return true;
     for (int r : t->reserved)
         if (r != 0) return false;
+    if (t->picks < 0 || t->picks > kMaxGridPicks) return false;
     return t->kernel >= BS_KERNEL_AUTO && t->kernel <= BS_KERNEL_GRID;
 }
 
-constexpr float kDefaultCellPoints = 32.f;
+constexpr float kDefaultCellPoints = 32.f;       // one pick per round
+constexpr float kDefaultCellPointsMulti = 8.f;   // several picks per round
 constexpr int64_t kAutoResidentMax = 16384;  // one workgroup holds these in VGPRs
 
 struct Plan {
     int kernel = 0;
     ScanShape shape;     // resident kernels
     int grid_block = 0;  // grid kernel workgroup size
+    int grid_picks = kDefaultGridPicks;
     float cell_points = kDefaultCellPoints;
 };
 
@@ -56,14 +62,18 @@ int plan_single(int64_t n, int64_t k, const bs_tuning* t, Plan* p) {
     const int want = t ? t->kernel : BS_KERNEL_AUTO;
     const int wb = t ? t->block : 0, wp = t ? t->per_thread : 0, wg = t ? t->groups : 0;
     (void)k;
-    p->cell_points = (t && t->cell_points > 0.f) ? t->cell_points : kDefaultCellPoints;
-    if (p->cell_points < 1.f) p->cell_points = 1.f;
     if (want == BS_KERNEL_GRID || (want == BS_KERNEL_AUTO && n > kAutoResidentMax)) {
-        int b = wb > 0 ? wb : grid_block_size(n);
+        p->grid_picks = (t && t->picks > 0) ? t->picks : kDefaultGridPicks;
+        const bool multi = p->grid_picks > 1;
+        int b = wb > 0 ? wb : (multi ? 1024 : grid_block_size(n));
         if (b != 256 && b != 512 && b != 1024)
             return set_error(BS_ERR_UNSUPPORTED, "grid kernel block must be 256, 512 or 1024, got %d", b);
         p->kernel = BS_KERNEL_GRID;
         p->grid_block = b;
+        // several picks per round favour more (smaller) cells: more superblocks
+        p->cell_points = (t && t->cell_points > 0.f) ? t->cell_points
+                                                      : (multi ? kDefaultCellPointsMulti : kDefaultCellPoints);
+        if (p->cell_points < 1.f) p->cell_points = 1.f;
         return BS_OK;
     }
     if (want == BS_KERNEL_AUTO) {
@@ -179,7 +189,7 @@ static int order_impl(const float* d_points, int64_t n, int64_t k, uint64_t seed
     hipError_t e = hipSuccess;
     if (plan.kernel == BS_KERNEL_GRID) {
         e = launch_grid(d_points, int(n), int(k), int(start), d_out_order, d_out_radius, d_workspace,
-                        plan.cell_points, plan.grid_block, d_ticks, st, ev);
+                        plan.cell_points, plan.grid_block, plan.grid_picks, d_ticks, st, ev);
     } else {
         DevHeader* hdr = reinterpret_cast<DevHeader*>(d_workspace);
         void* scratch = static_cast<char*>(d_workspace) + align_up(sizeof(DevHeader));

@@ -321,8 +321,10 @@ __global__ void bcells_kernel(const int32_t* __restrict__ cstart, int N, const i
     cstat[2 * size_t(c) + 1] = make_float4(hx, hy, hz, __int_as_float(e - s));
     const uint64_t key = make_key(INFINITY, best_id);
     const float4 w = xyzm[best_pos];
-    cdyn[2 * size_t(c) + 0] = make_uint4(uint32_t(key), uint32_t(key >> 32), uint32_t(best_pos), 0u);
-    cdyn[2 * size_t(c) + 1] = make_uint4(__float_as_uint(w.x), __float_as_uint(w.y), __float_as_uint(w.z), 0u);
+    // second key slot: the best key bounds the other keys until the first update
+    cdyn[2 * size_t(c) + 0] = make_uint4(uint32_t(key), uint32_t(key >> 32), uint32_t(best_pos), uint32_t(key));
+    cdyn[2 * size_t(c) + 1] = make_uint4(__float_as_uint(w.x), __float_as_uint(w.y), __float_as_uint(w.z),
+                                         uint32_t(key >> 32));
 }
 
 // object owning global block / superblock b: largest j with base(j) <= b

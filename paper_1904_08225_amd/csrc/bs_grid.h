@@ -36,6 +36,7 @@ struct GridObject {
     int32_t* order;
     float* radius;
     uint64_t* ticks;           // optional: device wall clock after each step
+    int max_picks;             // several-picks-per-round kernel: picks per round (<= 16)
 };
 
 // Byte offsets of the grid workspace pieces.
@@ -48,10 +49,12 @@ struct GridLayout {
 
 GridLayout grid_layout(int64_t n, int block);
 int grid_block_size(int64_t n);
-int grid_max_blocks(int block);
+// Blocks of 64 cells one workgroup of `block` threads holds in LDS; `picks`
+// > 1 selects the several-picks-per-round kernel (at most `picks` per round).
+int grid_max_blocks(int block, int picks);
 struct KernelEvents;
 hipError_t launch_grid(const float* pts, int n, int k, int start, int32_t* order, float* radius,
-                       void* ws, float target, int block, uint64_t* ticks, hipStream_t st,
-                       const KernelEvents* ev = nullptr);
+                       void* ws, float target, int block, int picks, uint64_t* ticks,
+                       hipStream_t st, const KernelEvents* ev = nullptr);
 
 }  // namespace bs

@@ -30,6 +30,7 @@
 
 #include "bs_grid.h"
 #include "bs_grid_device.h"
+#include "bs_grid_multi.h"
 #include "bs_internal.h"
 
 namespace bs {
@@ -156,8 +157,11 @@ __global__ void cell_build_kernel(const int32_t* __restrict__ cstart, int n,
     cstat[2 * c + 1] = make_float4(hx, hy, hz, __int_as_float(e - s));
     const uint64_t key = make_key(INFINITY, best_id);
     const float4 w = xyzm[best_pos];
-    cdyn[2 * c + 0] = make_uint4(uint32_t(key), uint32_t(key >> 32), uint32_t(best_pos), 0u);
-    cdyn[2 * c + 1] = make_uint4(__float_as_uint(w.x), __float_as_uint(w.y), __float_as_uint(w.z), 0u);
+    // second key slot (w words): a bound on the cell's other keys; the best
+    // key itself is one until the cell is first updated
+    cdyn[2 * c + 0] = make_uint4(uint32_t(key), uint32_t(key >> 32), uint32_t(best_pos), uint32_t(key));
+    cdyn[2 * c + 1] = make_uint4(__float_as_uint(w.x), __float_as_uint(w.y), __float_as_uint(w.z),
+                                 uint32_t(key >> 32));
 }
 
 // One thread per block: union box and best over its cells.
@@ -239,6 +243,27 @@ __global__ void __launch_bounds__(BLOCK) grid_single_kernel(GridObject o, const 
     grid_order_object<BLOCK, MAXB>(obj, L);
 }
 
+template <int BLOCK, int MAXB>
+__global__ void __launch_bounds__(BLOCK) grid_multi_kernel(GridObject o, const DevHeader* hdr,
+                                                           const GridHeader* gh) {
+    __shared__ GridLdsMP<BLOCK / 64, MAXB> L;
+    GridObject obj = o;
+    if (o.k <= 0) return;
+    if (hdr->nonfinite) {
+        for (int t = threadIdx.x; t < o.k; t += BLOCK) {
+            o.order[t] = -1;
+            if (o.radius) o.radius[t] = __builtin_nanf("");
+        }
+        return;
+    }
+    obj.C = gh->C;
+    obj.B = gh->B;
+    obj.NB = gh->NB;
+    obj.start_pos = gh->start_pos;
+    obj.start_cell = gh->start_cell;
+    grid_order_object_mp<BLOCK, MAXB>(obj, L);
+}
+
 }  // namespace
 
 // ------------------------------------------------------------ host side
@@ -282,11 +307,14 @@ GridLayout grid_layout(int64_t n, int block) {
 
 int grid_block_size(int64_t n) { return n > (int64_t(1) << 16) ? 512 : 256; }
 
-int grid_max_blocks(int block) { return block == 512 ? 4096 : 1024; }
+int grid_max_blocks(int block, int picks) {
+    if (picks > 1 && block == 1024) return 2048;
+    return block == 512 ? 4096 : 1024;
+}
 
 hipError_t launch_grid(const float* pts, int n, int k, int start, int32_t* order, float* radius,
-                       void* ws, float target, int block, uint64_t* ticks, hipStream_t st,
-                       const KernelEvents* ev) {
+                       void* ws, float target, int block, int picks, uint64_t* ticks,
+                       hipStream_t st, const KernelEvents* ev) {
     const GridLayout g = grid_layout(n, block);
     char* base = static_cast<char*>(ws);
     DevHeader* hdr = reinterpret_cast<DevHeader*>(base + g.dev_header);
@@ -322,7 +350,7 @@ hipError_t launch_grid(const float* pts, int n, int k, int start, int32_t* order
     const int hblk = nblk < 1024 ? nblk : 1024;
     hipLaunchKernelGGL(level_hist_kernel, dim3(hblk), dim3(tb), 0, st, codes_s, n, gh);
     hipLaunchKernelGGL(choose_level_kernel, dim3(1), dim3(64), 0, st, n, gh, target,
-                       grid_max_blocks(block));
+                       grid_max_blocks(block, picks));
     hipLaunchKernelGGL(cell_flag_kernel, dim3(nblk), dim3(tb), 0, st, codes_s, n, gh, flags);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     tbytes = g.temp_bytes;
@@ -350,8 +378,16 @@ hipError_t launch_grid(const float* pts, int n, int k, int start, int32_t* order
     o.order = order;
     o.radius = radius;
     o.ticks = ticks;
+    o.max_picks = picks < kMaxPicks ? picks : kMaxPicks;
     if (ev && ev->begin && (e = hipEventRecord(ev->begin, st)) != hipSuccess) return e;
-    if (block == 512)
+    if (picks > 1) {
+        if (block == 512)
+            hipLaunchKernelGGL((grid_multi_kernel<512, 4096>), dim3(1), dim3(512), 0, st, o, hdr, gh);
+        else if (block == 1024)
+            hipLaunchKernelGGL((grid_multi_kernel<1024, 2048>), dim3(1), dim3(1024), 0, st, o, hdr, gh);
+        else
+            hipLaunchKernelGGL((grid_multi_kernel<256, 1024>), dim3(1), dim3(256), 0, st, o, hdr, gh);
+    } else if (block == 512)
         hipLaunchKernelGGL((grid_single_kernel<512, 4096>), dim3(1), dim3(512), 0, st, o, hdr, gh);
     else if (block == 1024)
         hipLaunchKernelGGL((grid_single_kernel<1024, 1024>), dim3(1), dim3(1024), 0, st, o, hdr, gh);

@@ -2,7 +2,9 @@
 
 The pruning must not change a single bit: orders and radii equal the plain
 oracle's (small cases) or the exact grid oracle's (large cases, itself
-pinned bit-exact to the plain oracle).
+pinned bit-exact to the plain oracle).  Both forms of the kernel are
+covered: one pick per round (picks=1) and several exact picks per round
+(picks=2..16, the default).
 """
 import numpy as np
 import pytest
@@ -15,15 +17,29 @@ from tests.test_gpu_scan import assert_parity, run
 pytestmark = pytest.mark.gpu
 
 
+@pytest.mark.parametrize("picks", [1, 16])
 @pytest.mark.parametrize("block", [256, 512, 1024])
 @pytest.mark.parametrize("name", sorted(cases.ADVERSARIAL))
-def test_grid_adversarial(hip, name, block):
+def test_grid_adversarial(hip, name, block, picks):
     for n in (1, 2, 3, 65, 1000, 4097):
         P = cases.ADVERSARIAL[name](n, 41 + n)
         st = (5 * n) // 7
         eo, er = oracle.greedy32(P, n, st)
-        o, r = run(hip, P, n, start=st, tune=hip.tuning(kernel=hip.KERNEL_GRID, block=block))
-        assert_parity(o, r, eo, er, "grid %s n=%d block=%d" % (name, n, block))
+        o, r = run(hip, P, n, start=st, tune=hip.tuning(kernel=hip.KERNEL_GRID, block=block, picks=picks))
+        assert_parity(o, r, eo, er, "grid %s n=%d block=%d picks=%d" % (name, n, block, picks))
+
+
+@pytest.mark.parametrize("picks", [2, 3, 7, 16])
+def test_grid_picks_per_round(hip, picks):
+    """Every read-ahead limit gives the same order (several superblock sizes)."""
+    for n, cp in ((50000, 32.0), (20000, 4.0), (3000, 1.0)):
+        P = synth.cad_part(n, seed=60 + n % 7).points.numpy()
+        k = n // 2
+        eo, er = oracle.greedy32_grid(P, k, 11)
+        for block in (256, 512, 1024):
+            o, r = run(hip, P, k, start=11,
+                       tune=hip.tuning(kernel=hip.KERNEL_GRID, block=block, cell_points=cp, picks=picks))
+            assert_parity(o, r, eo, er, "n=%d cell=%g block=%d picks=%d" % (n, cp, block, picks))
 
 
 @pytest.mark.parametrize("cell_points", [1.0, 4.0, 32.0, 200.0])
@@ -79,7 +95,8 @@ def test_grid_repeat_and_agrees_with_resident(hip):
 
 
 def test_grid_cad_part_full_size(hip):
-    """4,194,304 candidates to k = 262,144 through the automatic choice."""
+    """4,194,304 candidates to k = 262,144 through the automatic choice, and
+    with one pick per round."""
     n, k = 4194304, 262144
     P = synth.cad_part(n, seed=2).points.numpy()
     st = oracle.start_index(2, n)
@@ -87,3 +104,19 @@ def test_grid_cad_part_full_size(hip):
     o, r = run(hip, P, k, seed=2)
     eo, er = oracle.greedy32_grid(P, k, st)
     assert_parity(o, r, eo, er, "grid cad_part full")
+    o1, r1 = run(hip, P, k, seed=2, tune=hip.tuning(kernel=hip.KERNEL_GRID, picks=1))
+    assert_parity(o1, r1, eo, er, "grid cad_part full, one pick per round")
+
+
+@pytest.mark.parametrize("picks", [1, 16])
+def test_grid_overflowing_distances(hip, picks):
+    """Coordinates ~1e19: most squared distances are +inf, so a pick's ball
+    reaches no box and whole blocks are never updated; their entries must
+    still come from the grid build (regression: n = 23,004 read unset LDS)."""
+    for n, seed in ((23004, 806), (60000, 807)):
+        P = cases.huge_coords(n, seed)
+        eo, er = oracle.greedy32_grid(P, n // 3, 5)
+        for block in (256, 512, 1024):
+            o, r = run(hip, P, n // 3, start=5,
+                       tune=hip.tuning(kernel=hip.KERNEL_GRID, block=block, picks=picks))
+            assert_parity(o, r, eo, er, "huge n=%d block=%d picks=%d" % (n, block, picks))
