@@ -262,7 +262,7 @@ int bs_batch_plan_create(const int64_t* h_offsets, const int64_t* h_k, const uin
     if (!out_plan) return set_error(BS_ERR_INVALID_ARG, "null plan pointer");
     *out_plan = nullptr;
     if (!tuning_clean(tuning)) return set_error(BS_ERR_INVALID_ARG, "bad tuning struct");
-    const float target = (tuning && tuning->cell_points > 0.f) ? tuning->cell_points : kDefaultCellPoints;
+    const float target = (tuning && tuning->cell_points > 0.f) ? tuning->cell_points : kDefaultCellPointsMulti;
     bs::BatchPlan* p = nullptr;
     const int rc = batch_plan_create(h_offsets, h_k, h_seed, m, target, &p);
     if (rc != BS_OK) return rc;

@@ -22,6 +22,7 @@
 
 #include "bs_grid.h"
 #include "bs_grid_device.h"
+#include "bs_grid_multi.h"
 #include "bs_internal.h"
 
 namespace bs {
@@ -448,6 +449,7 @@ __global__ void bdesc_kernel(int m, const ObjHdr* __restrict__ hd, const int32_t
         d.done = nullptr;
     }
     o.ticks = nullptr;
+    o.max_picks = kMaxPicks;
     d.nonfinite = int(h.nonfinite);
     desc[j] = d;
 }
@@ -461,7 +463,7 @@ __global__ void queue_reset_kernel(uint32_t* q) {
 __global__ void __launch_bounds__(kBatchBlock)
     batch_order_kernel(const ObjDesc* __restrict__ desc, const int32_t* __restrict__ lpt, int mwork,
                        uint32_t* __restrict__ queue) {
-    __shared__ GridLds<kBatchBlock / 64, kBatchMaxBlocks> L;
+    __shared__ GridLdsMP<kBatchBlock / 64, kBatchMaxBlocks> L;
     __shared__ int s_item;
     for (;;) {
         if (threadIdx.x == 0) s_item = int(atomicAdd(queue, 1u));
@@ -479,7 +481,7 @@ __global__ void __launch_bounds__(kBatchBlock)
                     if (o.radius) o.radius[t] = __builtin_nanf("");
                 }
             } else {
-                grid_order_object<kBatchBlock, kBatchMaxBlocks>(o, L);
+                grid_order_object_mp<kBatchBlock, kBatchMaxBlocks>(o, L);
             }
         }
         __syncthreads();

@@ -161,7 +161,7 @@ bool launch_batch(Server& s, int si, int long_streams_busy) {
             f.plan = nullptr;
         }
         rc = batch_plan_create(offs.data(), ks.data(), seeds.data(), int32_t(take.size()),
-                               s.cfg.cell_points > 0.f ? s.cfg.cell_points : 32.f, &f.plan);
+                               s.cfg.cell_points > 0.f ? s.cfg.cell_points : 8.f, &f.plan);
         if (rc != BS_OK) break;
         total_n = offs[take.size()];
         f.bytes = batch_workspace_bytes(f.plan) + align_up(size_t(total_n) * 12);
