@@ -1,26 +1,33 @@
 """Benchmark of the greedy blue-noise ordering on one MI355X.
 
-python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-batch] [--no-serve]
-                [--no-cpu-baseline] [--no-full-scan]
+python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-batch] [--no-scene]
+                [--no-serve] [--no-cpu-baseline] [--no-full-scan]
+                [--copy-calibration BYTES]
 
 A step is one full ordering of one synthetic CAD-like part -- the union
 boundary of 200 random boxes/cylinders, 4,194,304 binary32 candidates,
-ordered to k = 262,144 -- through the library's automatic kernel choice:
-input validation, grid build, every greedy step (select + min-distance
-update) and the emitted order and radii, with the candidates already
-resident in HBM.  `value` is ordered surfels per second of that step.
+ordered to k = 262,144 -- through the library's automatic kernel choice
+(autotuned for this size before the timed steps): input validation, grid
+build, every greedy step (select + min-distance update) and the emitted
+order and radii, with the candidates already resident in HBM.  `value` is
+ordered surfels per second of that step.
 
 The same JSON line also carries
   roofline      the dominant kernel (grid-pruned ordering) against HBM,
                 with its algorithmic bytes (16 B per candidate inside the
                 covering-radius ball, counted by the CPU oracle on the same
-                points) over its duration (device clock, launch stream);
-  latency       per-step p50 / p99 from device timestamps;
+                points) over its duration (HIP events on the launch stream)
+                and the HBM traffic measured by counters (profiles/);
+  latency       per-round p50 / p99 from device timestamps (a round emits
+                several exact picks);
   full_scan     the cooperative register-resident full scan on the same
                 input (16 B per live candidate per step);
   batched       1,000 parts of the same kind, n log-uniform 2,048..2,097,152,
-                k = n/4, in one graph-captured persistent launch, against a
-                plain loop of one ordering launch per object (sampled);
+                k = n/4, in one graph-captured persistent launch (cell
+                occupancy autotuned), against a plain loop of one ordering
+                launch per object (sampled);
+  scene_batched the heterogeneous scene: 10,000 objects (thin sheets, tori,
+                small-box clusters), 1.5e9 candidates, k = 12% of n;
   served        a Poisson stream (mean 200 requests/s) of jobs with n
                 log-uniform 1e4..4e6, k = n/8, under an 80 GB budget:
                 p50 / p99 latency and throughput, against the plain loop;
@@ -96,6 +103,10 @@ def bench_main(args, bs, torch, np):
     torch.cuda.synchronize()
     log("generated cad_part n=%d in %.1fs" % (N_MAIN, time.time() - t0))
     n, k = N_MAIN, K_MAIN
+    t0 = time.time()
+    tuned = bs.autotune(pts, k, seed=SEED_MAIN)  # recorded for this size; untimed
+    log("autotune: kernel %d block %d cells %g picks %d in %.1fs"
+        % (tuned.kernel, tuned.block, tuned.cell_points, tuned.picks, time.time() - t0))
     kernel = bs.auto_kernel(n, k)
     ws = torch.empty(max(bs.workspace_size(n, k), 1), dtype=torch.uint8, device=dev)
     out_o = torch.empty(k, dtype=torch.int32, device=dev)
@@ -135,7 +146,7 @@ def bench_main(args, bs, torch, np):
     _, lat, _ = ordering_kernel_seconds(bs, pts, k, start, None)
     log("rounds %d (%.2f picks each), per-round p50 %.2f us, %.2f us per pick (device clock)"
         % (lat["rounds"], lat["picks_per_round"], lat["p50_us"], lat["mean_us_per_pick"]))
-    return pts, surf, out_o, ms, ev_ms, kern_ms / 1e3, lat, kernel
+    return pts, surf, out_o, ms, ev_ms, kern_ms / 1e3, lat, kernel, tuned
 
 
 def bench_full_scan(bs, torch, pts, k):
@@ -170,7 +181,10 @@ def bench_batched(bs, torch, np):
     pts, offs = synth.cad_parts_batch(sizes, seed=3, count=200, device=dev)
     torch.cuda.synchronize()
     log("generated batch: %d objects, %d candidates in %.1fs" % (m, pts.shape[0], time.time() - t0))
-    plan = bs.BatchPlan(offs, ks, seeds)
+    t0 = time.time()
+    tune = bs.batch_autotune(pts, offs, ks, seeds)
+    log("batch autotune: cell target %g in %.1fs" % (tune.cell_points, time.time() - t0))
+    plan = bs.BatchPlan(offs, ks, seeds, tune=tune)
     out_o = torch.empty(plan.total_k, dtype=torch.int32, device=dev)
     out_r = torch.empty(plan.total_k, dtype=torch.float32, device=dev)
     plan.execute(pts, out_o, out_r)
@@ -205,11 +219,63 @@ def bench_batched(bs, torch, np):
         same &= bool(torch.equal(so, out_o[oa:ob]))
     plan.close()
     return {"objects": m, "candidates": int(pts.shape[0]), "sum_k": int(plan.total_k),
-            "seconds": batch_s, "ordered_surfels_per_s": plan.total_k / batch_s,
+            "cell_target": float(tune.cell_points), "seconds": batch_s, "ordered_surfels_per_s": plan.total_k / batch_s,
             "plain_loop_ordered_surfels_per_s": plain_rate,
             "plain_loop_sample": "%d objects spread over the size range, %d picks, %.1f s" % (len(sample), sk, sample_s),
             "plain_loop_estimated_seconds": plain_est_s, "speedup_vs_plain": plain_est_s / batch_s,
             "largest_object_k": max(ks), "spot_check_equal_alone": same}
+
+
+def bench_scene(bs, torch, np):
+    """Heterogeneous scene: 10,000 objects (thin sheets, tori, small-box
+    clusters), 1.5e9 candidates, k_j = 12% of n_j, one batched launch."""
+    import synth
+    dev = torch.device("cuda:0")
+    m = 10000
+    sizes = synth.scene_sizes(m, 1_500_000_000, seed=5)
+    ks = [int(0.12 * s) for s in sizes]
+    seeds = [5 * 1000003 + j for j in range(m)]
+    t0 = time.time()
+    pts, offs = synth.scene_batch(sizes, seed=5, device=dev)
+    torch.cuda.synchronize()
+    log("generated scene: %d objects, %d candidates in %.1fs" % (m, pts.shape[0], time.time() - t0))
+    t0 = time.time()
+    tune = bs.batch_autotune(pts, offs, ks, seeds)
+    log("batch autotune: cell target %g in %.1fs" % (tune.cell_points, time.time() - t0))
+    plan = bs.BatchPlan(offs, ks, seeds, tune=tune)
+    out_o = torch.empty(plan.total_k, dtype=torch.int32, device=dev)
+    out_r = torch.empty(plan.total_k, dtype=torch.float32, device=dev)
+    plan.execute(pts, out_o, out_r)
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    plan.execute(pts, out_o, out_r)
+    torch.cuda.synchronize()
+    batch_s = time.perf_counter() - t
+    log("scene batched: %.3f s for sum k = %d" % (batch_s, plan.total_k))
+    order_idx = sorted(range(m), key=lambda j: sizes[j])
+    sample = order_idx[:: max(1, m // 20)]
+    sk = 0
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    for j in sample:
+        bs.order(pts[offs[j]:offs[j + 1]], ks[j], seed=seeds[j], check=False)
+        sk += ks[j]
+    torch.cuda.synchronize()
+    sample_s = time.perf_counter() - t
+    plain_rate = sk / sample_s
+    same = True
+    for j in (order_idx[0], order_idx[m // 2], order_idx[-1]):
+        so, _ = bs.order(pts[offs[j]:offs[j + 1]], ks[j], seed=seeds[j])
+        oa, ob = plan.out_offsets[j], plan.out_offsets[j + 1]
+        same &= bool(torch.equal(so, out_o[oa:ob]))
+    res = {"objects": m, "candidates": int(pts.shape[0]), "sum_k": int(plan.total_k),
+           "workspace_bytes": int(plan.workspace_bytes), "cell_target": float(tune.cell_points),
+           "seconds": batch_s, "ordered_surfels_per_s": plan.total_k / batch_s,
+           "plain_loop_ordered_surfels_per_s": plain_rate,
+           "plain_loop_sample": "%d objects spread over the size range, %d picks, %.1f s" % (len(sample), sk, sample_s),
+           "speedup_vs_plain": (plan.total_k / plain_rate) / batch_s, "spot_check_equal_alone": same}
+    plan.close()
+    return res
 
 
 def bench_served(bs, torch, np):
@@ -291,6 +357,7 @@ def main():
     ap.add_argument("--no-full-scan", action="store_true")
     ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--no-serve", action="store_true")
+    ap.add_argument("--no-scene", action="store_true")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
                     help="only run two plain device-to-device copies of BYTES bytes (scales the "
                          "FETCH_SIZE / WRITE_SIZE counters to bytes) and exit")
@@ -314,7 +381,7 @@ def main():
         torch.cuda.synchronize()
         print(json.dumps({"copy_calibration_bytes": args.copy_calibration, "copies": 2}), flush=True)
         return
-    pts, surf, out_o, ms, ev_ms, kern_s, lat, kernel = bench_main(args, bs, torch, np)
+    pts, surf, out_o, ms, ev_ms, kern_s, lat, kernel, tuned = bench_main(args, bs, torch, np)
     n, k = N_MAIN, K_MAIN
     rec = {
         "metric": "ordered surfels/sec (exact greedy blue-noise ordering)",
@@ -333,7 +400,10 @@ def main():
                    "n": n, "k": k, "seed": SEED_MAIN,
                    "kernel": {1: "resident workgroup", 2: "cooperative full scan",
                               3: "grid-pruned, several exact picks per round"}.get(kernel, str(kernel)),
-                   "event_ms_per_step": ev_ms},
+                   "event_ms_per_step": ev_ms,
+                   "tuning": {"kernel": int(tuned.kernel), "block": int(tuned.block),
+                              "cell_points": float(tuned.cell_points), "picks": int(tuned.picks),
+                              "source": "library autotuner (bs_autotune), run before the timed steps"}},
         "latency": {"per_round_p50_us": lat["p50_us"], "per_round_p99_us": lat["p99_us"],
                     "per_round_mean_us": lat["mean_us"], "rounds": lat["rounds"],
                     "picks_per_round": lat["picks_per_round"], "mean_us_per_pick": lat["mean_us_per_pick"],
@@ -352,7 +422,8 @@ def main():
         achieved = abytes / kern_s / 1e9
         rec["roofline"] = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                            "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(),
-                           "kernel": "grid_multi_kernel<1024,2048>",
+                           "kernel": {3: "grid_multi_kernel<%d,...>" % (tuned.block or 1024)}.get(
+                               kernel, "kernel %d" % kernel),
                            "algorithmic_bytes": abytes, "kernel_seconds": kern_s,
                            "traffic_source": "rocprofv3 FETCH_SIZE and WRITE_SIZE per launch, scaled by a "
                                              "plain copy of known size (profiles/grid_cad_part_4M_hbm_counters.txt)",
@@ -369,6 +440,9 @@ def main():
     torch.cuda.empty_cache()
     if not args.no_batch:
         rec["batched"] = bench_batched(bs, torch, np)
+        torch.cuda.empty_cache()
+    if not args.no_scene:
+        rec["scene_batched"] = bench_scene(bs, torch, np)
         torch.cuda.empty_cache()
     if not args.no_serve:
         rec["served"] = bench_served(bs, torch, np)

@@ -166,6 +166,45 @@ int64_t bs_start_index(uint64_t seed, int64_t n);
 /* Which kernel the automatic choice uses for (n, k) (a bs_kernel value). */
 int bs_auto_kernel(int64_t n, int64_t k);
 
+/* ------------------------------------------------------------ autotuner */
+
+/*
+ * Autotuner: times candidate configurations (resident full scan, cooperative
+ * full scan, grid kernel with 512/1024 threads, cell occupancies 4..32, one
+ * or several picks per round) on the caller's points for a prefix of the
+ * ordering (max(1024, k/8) picks), and keeps the fastest in a per-device
+ * table keyed by (floor(log2 n), floor(log2 k)).  Calls with a NULL tuning
+ * (bs_order, bs_order_ex, bs_workspace_size, bs_auto_kernel) use the table
+ * entry of their size when there is one; query bs_workspace_size after
+ * tuning.  Every configuration gives the same ordering; only speed differs.
+ *   d_points     device float[n][3]
+ *   1 <= k <= n  the ordering to tune for; seed as in bs_order
+ *   out_tuning   host: receives the chosen configuration
+ * Synchronous: allocates scratch from the stream-ordered pool, runs the
+ * candidates on `stream` and waits for them.  Errors: BS_ERR_INVALID_ARG,
+ * BS_ERR_OUT_OF_MEMORY, BS_ERR_UNSUPPORTED (no candidate fits), BS_ERR_HIP.
+ */
+int bs_autotune(const float* d_points, int64_t n, int64_t k, uint64_t seed,
+                bs_tuning* out_tuning, void* stream);
+
+/* The table entry for (n, k) on the current device: BS_OK and *out_tuning,
+ * or BS_ERR_NOT_READY when that size has not been tuned. */
+int bs_autotune_lookup(int64_t n, int64_t k, bs_tuning* out_tuning);
+
+/* Forget every tuned entry (all devices). */
+void bs_autotune_clear(void);
+
+/*
+ * Autotuner for a batch (arguments as bs_batch_plan_create, plus the
+ * device candidates d_points): orders a sample of the objects (the four with
+ * the largest k and twelve spread over the rest, each cut to at most 4096
+ * picks) as batches with cell occupancies 4, 8, 16 and 32 candidates and
+ * returns the fastest in out_tuning->cell_points (kernel = BS_KERNEL_GRID),
+ * to pass to bs_batch_plan_create.  Synchronous; errors as bs_autotune.
+ */
+int bs_batch_autotune(const int64_t* h_offsets, const int64_t* h_k, const uint64_t* h_seed,
+                      int32_t m, const float* d_points, bs_tuning* out_tuning, void* stream);
+
 /* -------------------------------------------------------------- batched */
 
 /*

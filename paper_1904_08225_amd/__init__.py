@@ -82,6 +82,14 @@ def load():
     lib.bs_start_index.restype = i64
     lib.bs_auto_kernel.argtypes = [i64, i64]
     lib.bs_auto_kernel.restype = i32
+    lib.bs_autotune.argtypes = [vp, i64, i64, u64, tp, vp]
+    lib.bs_autotune.restype = i32
+    lib.bs_autotune_lookup.argtypes = [i64, i64, tp]
+    lib.bs_autotune_lookup.restype = i32
+    lib.bs_autotune_clear.argtypes = []
+    lib.bs_autotune_clear.restype = None
+    lib.bs_batch_autotune.argtypes = [vp, vp, vp, i32, vp, tp, vp]
+    lib.bs_batch_autotune.restype = i32
     lib.bs_workspace_size.argtypes = [i64, i64, tp]
     lib.bs_workspace_size.restype = sz
     lib.bs_order.argtypes = [vp, vp, vp, i64, i64, u64, vp, vp, vp]
@@ -141,6 +149,45 @@ def start_index(seed: int, n: int) -> int:
 
 def auto_kernel(n: int, k: int) -> int:
     return int(load().bs_auto_kernel(n, k))
+
+
+def autotune(points, k: int, seed: int = 0, stream=None) -> Tuning:
+    """Time candidate configurations for ordering ``points`` to ``k`` (a
+    prefix of the ordering) and record the fastest for this size; later
+    calls without a tuning use it (``bs_autotune``)."""
+    lib = load()
+    points = _prep_points(points)
+    t = Tuning()
+    _check(lib.bs_autotune(_ptr(points), int(points.shape[0]), int(k), ctypes.c_uint64(seed & (2**64 - 1)),
+                           ctypes.byref(t), _stream_handle(stream)))
+    return t
+
+
+def autotune_lookup(n: int, k: int) -> Optional[Tuning]:
+    """The recorded configuration for (n, k), or None."""
+    t = Tuning()
+    rc = load().bs_autotune_lookup(int(n), int(k), ctypes.byref(t))
+    return t if rc == 0 else None
+
+
+def autotune_clear() -> None:
+    load().bs_autotune_clear()
+
+
+def batch_autotune(points, offsets, ks, seeds=None, stream=None) -> Tuning:
+    """Grid cell occupancy for a batch, timed on a sample of its objects
+    (``bs_batch_autotune``); pass the result to ``BatchPlan``."""
+    import numpy as np
+    lib = load()
+    points = _prep_points(points)
+    offs = np.ascontiguousarray(np.asarray(offsets, dtype=np.int64))
+    kk = np.ascontiguousarray(np.asarray(ks, dtype=np.int64))
+    sd = None if seeds is None else np.ascontiguousarray(np.asarray(seeds, dtype=np.uint64))
+    t = Tuning()
+    _check(lib.bs_batch_autotune(offs.ctypes.data_as(ctypes.c_void_p), kk.ctypes.data_as(ctypes.c_void_p),
+                                 None if sd is None else sd.ctypes.data_as(ctypes.c_void_p), int(kk.shape[0]),
+                                 _ptr(points), ctypes.byref(t), _stream_handle(stream)))
+    return t
 
 
 def workspace_size(n: int, k: int, tune: Optional[Tuning] = None) -> int:

@@ -58,6 +58,8 @@ struct Plan {
 
 // Resolve the kernel and its launch shape.
 int plan_single(int64_t n, int64_t k, const bs_tuning* t, Plan* p) {
+    bs_tuning tuned;
+    if (!t && tuned_lookup(n, k, &tuned)) t = &tuned;  // the autotuner's choice for this size
     const int cus = device_cus() > 0 ? device_cus() : 256;
     const int want = t ? t->kernel : BS_KERNEL_AUTO;
     const int wb = t ? t->block : 0, wp = t ? t->per_thread : 0, wg = t ? t->groups : 0;

@@ -73,4 +73,7 @@ int batch_plan_execute(BatchPlan* p, const float* pts, int32_t* out_order, float
 // Error reporting (bs_api.cpp).
 int set_error(int code, const char* fmt, ...);
 
+// The autotuned configuration for (n, k) on the current device, if any.
+bool tuned_lookup(int64_t n, int64_t k, bs_tuning* out);
+
 }  // namespace bs

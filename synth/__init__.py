@@ -418,3 +418,104 @@ def cad_parts_batch(sizes: List[int], seed: int = 3, count: int = 200, device="c
         offs.append(offs[-1] + n)
     assert pts.shape[0] == offs[-1], "generator did not reach the requested sizes"
     return pts, offs
+
+
+def scene_batch(sizes: List[int], seed: int = 5, device="cpu", chunk: int = 1 << 24, pad: int = 24):
+    """The heterogeneous scene's objects at once: object j is kind j % 3 of
+    :func:`scene_object` (0 thin two-sided sheet, 1 torus, 2 cluster of 24
+    small boxes), drawn with its own parameters, with sizes[j] area-uniform
+    union-boundary samples in its local frame.  Returns (points [N,3]
+    float32, offsets list of m+1), like :func:`cad_parts_batch`, but writes
+    samples straight into their object's rows so that 10^4 objects and 10^9
+    samples stay cheap."""
+    device = torch.device(device)
+    m = len(sizes)
+    g = _gen(seed * 7919 + 31, device)
+    P = pad
+    kind = torch.full((m, P), BOX, dtype=torch.int64, device=device)
+    prm = torch.zeros((m, P, 3), dtype=torch.float64, device=device)  # zero size: never drawn, never inside
+    center = torch.zeros((m, P, 3), dtype=torch.float64, device=device)
+    rot = _random_rotations(g, m * P, device).view(m, P, 3, 3)
+    ok_kind = torch.arange(m, device=device) % 3
+    # sheets: one thin box
+    dims = _log_uniform(g, (m, 3), 0.2, 1.0, device)
+    dims[:, 2] = _log_uniform(g, (m,), 1e-3, 1e-2, device)
+    sheet = ok_kind == 0
+    prm[sheet, 0] = dims[sheet] / 2
+    # tori: R in [0.2, 1], r = R * U(0.1, 0.4)
+    R = _log_uniform(g, (m,), 0.2, 1.0, device)
+    r = R * (0.1 + 0.3 * _rand(g, (m,), device))
+    tor = ok_kind == 1
+    kind[tor, 0] = TORUS
+    prm[tor, 0] = torch.stack([R, r, torch.zeros_like(R)], 1)[tor]
+    # clusters: `pad` small boxes, edges 0.01..0.05, centres in a 0.15 cube
+    cl = ok_kind == 2
+    cd = _log_uniform(g, (m, P, 3), 0.01, 0.05, device)
+    cc = 0.15 * _rand(g, (m, P, 3), device)
+    prm[cl] = cd[cl] / 2
+    center[cl] = cc[cl]
+    flat = Primitives(kind.reshape(-1), center.reshape(-1, 3), rot.reshape(-1, 3, 3), prm.reshape(-1, 3),
+                      torch.zeros((m * P, 3), dtype=torch.uint8, device=device))
+    area = _area(flat).view(m, P)
+    cdf = torch.cumsum(area, 1) / area.sum(1, keepdim=True)
+    cdf[:, -1] = 1.0
+    flat_cdf = (cdf + torch.arange(m, device=device, dtype=torch.float64)[:, None]).reshape(-1)
+    bound = _bound_radius(flat).view(m, P)
+    nprim = (area > 0).sum(1)
+    sizes_t = torch.tensor(sizes, dtype=torch.int64, device=device)
+    offs_t = torch.cumsum(sizes_t, 0) - sizes_t
+    out = torch.empty((int(sizes_t.sum()), 3), dtype=torch.float32, device=device)
+    have = torch.zeros(m, dtype=torch.int64, device=device)
+    over = 1.2
+    rounds = 0
+    need = sizes_t.clone()
+    while bool((need > 0).any()) and rounds < 16:
+        rounds += 1
+        want = torch.clamp((need.double() * over).ceil().long() + 16, min=0) * (need > 0)
+        obj_all = torch.repeat_interleave(torch.arange(m, device=device), want)
+        for s0 in range(0, int(obj_all.numel()), chunk):
+            obj = obj_all[s0:s0 + chunk]
+            u = _rand(g, (obj.numel(),), device) * 0.999999999 + obj.double()
+            pid = torch.searchsorted(flat_cdf, u, right=True).clamp(max=m * P - 1)
+            pid = torch.maximum(pid, obj * P)
+            q, nrm, okk = _sample_local(g, flat, pid, device)
+            pts = torch.einsum("mij,mj->mi", flat.rot[pid], q) + flat.center[pid]
+            keep = okk.clone()
+            own = pid - obj * P
+            multi = nprim[obj] > 1
+            for p in range(P):
+                fp = obj * P + p
+                near = keep & multi & (own != p) & \
+                    ((pts - flat.center[fp]).pow(2).sum(1) < bound.view(-1)[fp] ** 2)
+                idx = near.nonzero().squeeze(1)
+                if idx.numel():
+                    f = fp[idx]
+                    ins = _inside_batched(flat.kind[f], flat.prm[f], flat.center[f], flat.rot[f], pts[idx])
+                    keep[idx[ins]] = False
+            kept = keep.nonzero().squeeze(1)
+            ko = obj[kept]  # non-decreasing: samples are drawn object by object
+            counts = torch.bincount(ko, minlength=m)
+            starts = torch.cumsum(counts, 0) - counts
+            rank = torch.arange(ko.numel(), device=device) - starts[ko]
+            take = rank < (sizes_t - have)[ko]
+            pos = offs_t[ko[take]] + have[ko[take]] + rank[take]
+            out[pos] = pts[kept[take]].to(torch.float32)
+            have += torch.bincount(ko[take], minlength=m)
+        need = sizes_t - have
+        over *= 1.5
+    assert bool((need == 0).all()), "generator did not reach the requested sizes"
+    offs = [0]
+    for n in sizes:
+        offs.append(offs[-1] + n)
+    return out, offs
+
+
+def scene_sizes(m: int = 10000, total: int = 1_500_000_000, lo: int = 5000, hi: int = 1_000_000,
+                seed: int = 5) -> List[int]:
+    """Object sizes of the heterogeneous scene: log-uniform in [lo, hi], then
+    scaled so that they sum to `total` exactly."""
+    s = log_uniform_sizes(m, lo, hi, seed)
+    f = total / float(sum(s))
+    out = [max(1, int(round(x * f))) for x in s]
+    out[max(range(m), key=lambda j: out[j])] += total - sum(out)
+    return out

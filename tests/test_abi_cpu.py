@@ -78,3 +78,20 @@ def test_server_config_validation_without_device(lib):
     cfg = bs.ServerConfig(1 << 30, 0, 4, 16, 50, 0.0)
     cfg.reserved[2] = 5
     assert lib.bs_server_create(ctypes.byref(cfg), ctypes.byref(srv)) == bs.BS_ERR_INVALID_ARG
+
+
+def test_autotune_validation_without_device(lib):
+    fake = ctypes.c_void_p(0x1000)
+    t = bs.Tuning()
+    assert lib.bs_autotune(None, 10, 5, 0, ctypes.byref(t), None) == bs.BS_ERR_INVALID_ARG
+    assert lib.bs_autotune(fake, 10, 0, 0, ctypes.byref(t), None) == bs.BS_ERR_INVALID_ARG
+    assert lib.bs_autotune(fake, 10, 11, 0, ctypes.byref(t), None) == bs.BS_ERR_INVALID_ARG
+    assert lib.bs_autotune(fake, 10, 5, 0, None, None) == bs.BS_ERR_INVALID_ARG
+    # nothing tuned (and no device): the lookup reports not ready
+    lib.bs_autotune_clear()
+    assert lib.bs_autotune_lookup(4096, 100, ctypes.byref(t)) == bs.BS_ERR_NOT_READY
+    assert lib.bs_batch_autotune(None, None, None, 0, fake, ctypes.byref(t), None) == bs.BS_ERR_INVALID_ARG
+    # tuning fields: picks outside 0..16 is rejected like the reserved words
+    bad = bs.tuning(kernel=3, picks=17)
+    assert lib.bs_workspace_size(1000, 10, ctypes.byref(bad)) == 0
+    assert lib.bs_workspace_size(1000, 10, ctypes.byref(bs.tuning(kernel=3, picks=16))) > 0

@@ -108,3 +108,24 @@ def test_batch_many_small_objects(hip):
         eo, er = oracle.greedy32(objs[j], ks[j], oracle.start_index(seeds[j], sizes[j]))
         assert_parity(o[a:b], r[a:b], eo, er, "small object %d" % j)
     plan.close()
+
+
+def test_batch_scene_objects(hip):
+    """Objects of the heterogeneous scene (sheets, tori, box clusters) in one
+    batch equal the oracle, at the scene's k = 12% of n."""
+    import torch
+    sizes = synth.scene_sizes(24, total=60000, lo=200, hi=12000, seed=9)
+    pts, offs = synth.scene_batch(sizes, seed=9)
+    ks = [int(0.12 * s) for s in sizes]
+    seeds = [90 + j for j in range(len(sizes))]
+    plan = hip.BatchPlan(offs, ks, seeds)
+    o, r = plan.execute(pts.cuda())
+    torch.cuda.synchronize()
+    oo, rr = o.cpu().numpy(), r.cpu().numpy()
+    P = pts.numpy()
+    for j in range(len(sizes)):
+        a, b = plan.out_offsets[j], plan.out_offsets[j + 1]
+        Pj = P[offs[j]:offs[j + 1]]
+        eo, er = oracle.greedy32(Pj, ks[j], oracle.start_index(seeds[j], Pj.shape[0]))
+        assert_parity(oo[a:b], rr[a:b], eo, er, "scene object %d (kind %d)" % (j, j % 3))
+    plan.close()

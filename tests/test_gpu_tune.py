@@ -1,0 +1,52 @@
+"""Autotuner: the chosen configuration is recorded for its size, used by
+calls without a tuning, and (like every configuration) orders exactly as the
+oracle; the batch tuner's cell occupancy gives the same batch results."""
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from tests.test_gpu_batch import make_batch
+from tests.test_gpu_scan import assert_parity
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.mark.parametrize("n,k", [(16384, 16384), (60000, 6000)])
+def test_autotune_records_and_orders_exactly(hip, n, k):
+    import torch
+    hip.autotune_clear()
+    P = synth.cad_part(n, seed=71).points.numpy()
+    pts = torch.from_numpy(P).cuda()
+    t = hip.autotune(pts, k, seed=4)
+    assert t.kernel in (hip.KERNEL_WG, hip.KERNEL_COOP, hip.KERNEL_GRID)
+    got = hip.autotune_lookup(n, k)
+    assert got is not None and bytes(got) == bytes(t)
+    assert hip.auto_kernel(n, k) == t.kernel
+    # calls without a tuning now use the recorded one
+    o, r = hip.order(pts, k, seed=4)
+    torch.cuda.synchronize()
+    eo, er = oracle.greedy32_grid(P, k, oracle.start_index(4, n))
+    assert_parity(o.cpu().numpy(), r.cpu().numpy(), eo, er, "tuned n=%d" % n)
+    hip.autotune_clear()
+    assert hip.autotune_lookup(n, k) is None
+
+
+def test_batch_autotune(hip):
+    import torch
+    objs, ks, seeds, offs = make_batch(17)
+    pts = torch.from_numpy(np.concatenate(objs).astype(np.float32)).cuda()
+    t = hip.batch_autotune(pts, offs, ks, seeds)
+    assert t.kernel == hip.KERNEL_GRID and t.cell_points in (4.0, 8.0, 16.0, 32.0)
+    plan = hip.BatchPlan(offs, ks, seeds, tune=t)
+    o, r = plan.execute(pts)
+    torch.cuda.synchronize()
+    oo = o.cpu().numpy()
+    rr = r.cpu().numpy()
+    for j in range(len(objs)):
+        if ks[j] == 0:
+            continue
+        a, b = plan.out_offsets[j], plan.out_offsets[j + 1]
+        eo, er = oracle.greedy32(objs[j], ks[j], oracle.start_index(seeds[j], objs[j].shape[0]))
+        assert_parity(oo[a:b], rr[a:b], eo, er, "tuned batch object %d" % j)
+    plan.close()
