@@ -302,7 +302,7 @@ def bench_served(bs, torch, np):
         warm.submit(views[p], min(ks[i], 1000), int(seeds[i]), out_o[:1000], out_r[:1000])
     warm.drain()
     warm.close()
-    srv = bs.Server(hbm_budget_bytes=80 << 30, max_inflight=4, max_jobs_per_batch=256, poll_us=20)
+    srv = bs.Server(hbm_budget_bytes=80 << 30, max_jobs_per_batch=256, poll_us=20)
     off = 0
     t0 = time.perf_counter()
     for i in range(nreq):
@@ -312,6 +312,9 @@ def bench_served(bs, torch, np):
         p = int(picks[i])
         srv.submit(views[p], ks[i], int(seeds[i]), out_o[off:off + ks[i]], out_r[off:off + ks[i]])
         off += ks[i]
+        if (i + 1) % 500 == 0:
+            st = srv.stats()
+            log("served: %d submitted, %d completed" % (i + 1, st["completed"]))
     srv.drain()
     st = srv.stats()
     srv.close()

@@ -256,23 +256,31 @@ void bs_batch_plan_destroy(bs_batch_plan* plan);
 /* -------------------------------------------------------------- serving */
 
 /*
- * A serving loop with continuous batching under an HBM budget.  Jobs are
- * submitted from any host thread; a dispatcher thread admits pending jobs,
- * in arrival order, into micro-batches whenever one of `max_inflight`
- * streams is free and the job fits the remaining budget; micro-batches run
- * concurrently on the device, one workgroup per job (the batched ordering
- * above).  Each job is timed from submit to the moment its completion flag
- * (written by the device into pinned host memory) is observed.  Results
- * are bit-identical to bs_order on the same job.
+ * A serving loop with continuous batching under an HBM budget (the paper
+ * generates approximations per scene node ahead of rendering, Sec. 3.4 and
+ * Sec. 5.2; here orderings are requested and answered while others run).
+ * Jobs are submitted from any host thread.  A persistent kernel of
+ * `workgroups` ordering workers stays resident on the device; a dispatcher
+ * thread admits pending jobs, in arrival order, into micro-batches while the
+ * job fits the remaining budget, builds their grids on a preprocessing
+ * stream and publishes them into a device ring, from which each idle worker
+ * claims the next job (largest k first within a micro-batch).  A job never
+ * waits for another job to finish, only for a free worker.  Each job is timed
+ * from submit to the moment its completion flag (written by its worker into
+ * pinned host memory) is observed.  Results are bit-identical to bs_order on
+ * the same job.  Workers exit a few milliseconds after the last job and are
+ * relaunched on demand (so a device-wide synchronisation waits at most that
+ * long for them).
  */
 typedef struct {
     size_t hbm_budget_bytes;     /* device bytes the server may hold at once (> 0) */
     int32_t device;              /* HIP device ordinal */
-    int32_t max_inflight;        /* concurrent micro-batches (streams); 0 = 4 */
+    int32_t max_inflight;        /* micro-batches admitted and not finished; 0 = 64 */
     int32_t max_jobs_per_batch;  /* 0 = 512 */
     int32_t poll_us;             /* dispatcher polling period while busy; 0 = 50 */
-    float cell_points;           /* grid cell target, 0 = 32 */
-    int32_t reserved[7];         /* must be zero */
+    float cell_points;           /* grid cell target, 0 = 8 */
+    int32_t workgroups;          /* resident ordering workers, 0 = one per compute unit */
+    int32_t reserved[6];         /* must be zero */
 } bs_server_config;
 
 typedef struct {

@@ -366,7 +366,7 @@ class ServerConfig(ctypes.Structure):
     _fields_ = [("hbm_budget_bytes", ctypes.c_size_t), ("device", ctypes.c_int32),
                 ("max_inflight", ctypes.c_int32), ("max_jobs_per_batch", ctypes.c_int32),
                 ("poll_us", ctypes.c_int32), ("cell_points", ctypes.c_float),
-                ("reserved", ctypes.c_int32 * 7)]
+                ("workgroups", ctypes.c_int32), ("reserved", ctypes.c_int32 * 6)]
 
 
 class Job(ctypes.Structure):
@@ -392,11 +392,13 @@ class Server:
     ``submit`` takes device tensors (points float32 [n, 3], order int32 [k],
     radius float32 [k]) which must stay alive until the job is done."""
 
-    def __init__(self, hbm_budget_bytes: int, device: int = 0, max_inflight: int = 4,
-                 max_jobs_per_batch: int = 512, poll_us: int = 50, cell_points: float = 0.0):
+    def __init__(self, hbm_budget_bytes: int, device: int = 0, max_inflight: int = 0,
+                 max_jobs_per_batch: int = 512, poll_us: int = 50, cell_points: float = 0.0,
+                 workgroups: int = 0):
         lib = load()
         self._lib = lib
-        cfg = ServerConfig(int(hbm_budget_bytes), device, max_inflight, max_jobs_per_batch, poll_us, cell_points)
+        cfg = ServerConfig(int(hbm_budget_bytes), device, max_inflight, max_jobs_per_batch, poll_us, cell_points,
+                           workgroups)
         self._srv = ctypes.c_void_p()
         _check(lib.bs_server_create(ctypes.byref(cfg), ctypes.byref(self._srv)))
         self._keep = {}

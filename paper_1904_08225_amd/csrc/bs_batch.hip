@@ -493,6 +493,80 @@ __global__ void __launch_bounds__(kBatchBlock)
     }
 }
 
+// Appends count descriptors, largest k first, at ring positions base, ...
+// and then publishes them by advancing tail (release at device scope: the
+// descriptors and everything the preprocessing wrote before them become
+// visible to a worker that observes the new tail).
+__global__ void publish_kernel(const ObjDesc* __restrict__ desc, const int32_t* __restrict__ lpt, int count,
+                               ObjDesc* __restrict__ slots, uint32_t cap, uint32_t base, uint32_t* tail) {
+    for (int i = threadIdx.x; i < count; i += blockDim.x) slots[(base + uint32_t(i)) % cap] = desc[lpt[i]];
+    __threadfence();
+    __syncthreads();
+    if (threadIdx.x == 0) __hip_atomic_store(tail, base + uint32_t(count), __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Persistent serving workers: each workgroup claims the next published
+// descriptor (compare-and-swap on head below tail), copies it into LDS with
+// device-coherent loads (ring slots are rewritten while the kernel runs),
+// orders that object and sets its completion flag.  A workgroup exits when
+// stop is set and nothing is left to claim, or after idle_polls empty polls.
+__global__ void __launch_bounds__(kBatchBlock)
+    serve_kernel(const ObjDesc* __restrict__ slots, uint32_t cap, uint32_t* head, const uint32_t* tail,
+                 const uint32_t* stop, uint32_t idle_polls) {
+    __shared__ GridLdsMP<kBatchBlock / 64, kBatchMaxBlocks> L;
+    __shared__ int s_item;
+    __shared__ __align__(16) uint32_t s_desc[(sizeof(ObjDesc) + 3) / 4];
+    static_assert(sizeof(ObjDesc) % 4 == 0, "descriptor words");
+    constexpr int kWords = int(sizeof(ObjDesc) / 4);
+    static_assert(kWords <= kBatchBlock, "one word per thread");
+    for (;;) {
+        if (threadIdx.x == 0) {
+            int item = -1;
+            uint32_t idle = 0;
+            for (;;) {
+                const uint32_t t = __hip_atomic_load(tail, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+                uint32_t h = __hip_atomic_load(head, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                if (h < t) {
+                    if (__hip_atomic_compare_exchange_strong(head, &h, h + 1, __ATOMIC_ACQ_REL, __ATOMIC_RELAXED,
+                                                             __HIP_MEMORY_SCOPE_AGENT)) {
+                        item = int(h % cap);
+                        break;
+                    }
+                    continue;
+                }
+                if (__hip_atomic_load(stop, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_SYSTEM) != 0u) break;
+                if (++idle > idle_polls) break;
+                __builtin_amdgcn_s_sleep(127);
+            }
+            s_item = item;
+        }
+        __syncthreads();
+        const int item = s_item;
+        if (item < 0) return;
+        if (int(threadIdx.x) < kWords)
+            s_desc[threadIdx.x] = __hip_atomic_load(reinterpret_cast<const uint32_t*>(slots + item) + threadIdx.x,
+                                                    __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __syncthreads();
+        const ObjDesc d = *reinterpret_cast<const ObjDesc*>(s_desc);
+        const GridObject& o = d.o;
+        if (o.k > 0) {
+            if (d.nonfinite) {
+                for (int t = threadIdx.x; t < o.k; t += kBatchBlock) {
+                    o.order[t] = -1;
+                    if (o.radius) o.radius[t] = __builtin_nanf("");
+                }
+            } else {
+                grid_order_object_mp<kBatchBlock, kBatchMaxBlocks>(o, L);
+            }
+        }
+        __syncthreads();
+        if (d.done && threadIdx.x == 0) {
+            __atomic_thread_fence(__ATOMIC_RELEASE);
+            __hip_atomic_store(d.done, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
+        }
+    }
+}
+
 template <class T>
 T* carve(char* base, size_t& off, size_t count) {
     T* p = reinterpret_cast<T*>(base + off);
@@ -728,17 +802,18 @@ int64_t batch_total_k(const BatchPlan* p) { return p ? p->total_k : 0; }
 const int64_t* batch_out_offsets(const BatchPlan* p) { return p->h_out_offs.data(); }
 int batch_slots(const BatchPlan* p) { return p ? p->slots : 0; }
 
-int batch_plan_execute(BatchPlan* p, const float* pts, int32_t* out_order, float* out_radius, void* ws,
-                       size_t ws_bytes, hipStream_t st) {
-    if (!p) return set_error(BS_ERR_INVALID_ARG, "null plan");
-    if (p->mwork == 0) return BS_OK;
+namespace {
+
+// Validation, per-object grids and the objects' descriptors (w.desc), all
+// enqueued on st; shared by the batched launch and the serving ring.
+int batch_preprocess(BatchPlan* p, const float* pts, int32_t* out_order, float* out_radius, void* ws,
+                     size_t ws_bytes, hipStream_t st, BatchWs& w) {
     if (!pts || (!out_order && p->h_io.empty())) return set_error(BS_ERR_INVALID_ARG, "null points or output");
     if (!ws || ws_bytes < p->ws_bytes)
         return set_error(BS_ERR_INVALID_ARG, "workspace %zu bytes < %zu needed", ws_bytes, p->ws_bytes);
     if (reinterpret_cast<uintptr_t>(ws) % kAlign)
         return set_error(BS_ERR_INVALID_ARG, "workspace not %zu-byte aligned", kAlign);
-    std::lock_guard<std::mutex> lk(p->mu);
-    const BatchWs w = batch_layout(*p, static_cast<char*>(ws));
+    w = batch_layout(*p, static_cast<char*>(ws));
     const int N = p->N, m = p->m;
     hipError_t e = hipMemcpyAsync(w.offs, p->h_offs.data(), p->h_offs.size() * 4, hipMemcpyHostToDevice, st);
     if (e == hipSuccess && m)
@@ -785,6 +860,20 @@ int batch_plan_execute(BatchPlan* p, const float* pts, int32_t* out_order, float
                        w.outo, w.xyzm, w.ids, w.cstat, w.cdyn, w.bstat, w.bdyn, w.sbstat,
                        out_order, out_radius, use_io ? w.io : nullptr, w.desc);
     if ((e = hipGetLastError()) != hipSuccess) return set_error(BS_ERR_HIP, "%s", hipGetErrorString(e));
+    return BS_OK;
+}
+
+}  // namespace
+
+int batch_plan_execute(BatchPlan* p, const float* pts, int32_t* out_order, float* out_radius, void* ws,
+                       size_t ws_bytes, hipStream_t st) {
+    if (!p) return set_error(BS_ERR_INVALID_ARG, "null plan");
+    if (p->mwork == 0) return BS_OK;
+    std::lock_guard<std::mutex> lk(p->mu);
+    BatchWs w;
+    const int rc = batch_preprocess(p, pts, out_order, out_radius, ws, ws_bytes, st, w);
+    if (rc != BS_OK) return rc;
+    hipError_t e = hipSuccess;
     if (!p->use_graph) {
         hipLaunchKernelGGL(queue_reset_kernel, dim3(1), dim3(64), 0, st, w.queue);
         hipLaunchKernelGGL(batch_order_kernel, dim3(p->slots), dim3(kBatchBlock), 0, st, w.desc, w.lpt,
@@ -801,6 +890,33 @@ int batch_plan_execute(BatchPlan* p, const float* pts, int32_t* out_order, float
     e = hipGraphLaunch(p->exec, st);
     if (e != hipSuccess) return set_error(BS_ERR_HIP, "graph launch: %s", hipGetErrorString(e));
     return BS_OK;
+}
+
+int batch_work_count(const BatchPlan* p) { return p ? p->mwork : 0; }
+
+int batch_plan_publish(BatchPlan* p, const float* pts, void* ws, size_t ws_bytes, const ServeRing& ring,
+                       uint32_t base, hipStream_t st) {
+    if (!p) return set_error(BS_ERR_INVALID_ARG, "null plan");
+    if (p->mwork == 0) return BS_OK;
+    if (p->h_io.empty()) return set_error(BS_ERR_INVALID_ARG, "serving needs per-job outputs");
+    std::lock_guard<std::mutex> lk(p->mu);
+    BatchWs w;
+    const int rc = batch_preprocess(p, pts, nullptr, nullptr, ws, ws_bytes, st, w);
+    if (rc != BS_OK) return rc;
+    hipLaunchKernelGGL(publish_kernel, dim3(1), dim3(256), 0, st, w.desc, w.lpt, p->mwork,
+                       static_cast<ObjDesc*>(ring.slots), ring.cap, base, ring.tail);
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return set_error(BS_ERR_HIP, "publish: %s", hipGetErrorString(e));
+    return BS_OK;
+}
+
+size_t serve_slot_bytes() { return sizeof(ObjDesc); }
+
+hipError_t launch_serve(const ServeRing& ring, int workgroups, uint32_t idle_polls, hipStream_t st) {
+    hipLaunchKernelGGL(serve_kernel, dim3(workgroups), dim3(kBatchBlock), 0, st,
+                       static_cast<const ObjDesc*>(ring.slots), ring.cap, ring.head, ring.tail, ring.stop,
+                       idle_polls);
+    return hipGetLastError();
 }
 
 }  // namespace bs

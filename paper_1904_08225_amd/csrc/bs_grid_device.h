@@ -41,6 +41,17 @@ __device__ __forceinline__ float box_lower(float lx, float ly, float lz, float h
     return s + zz;
 }
 
+// A load whose address every lane shares, kept on the vector memory path
+// (the address goes through a vector register): a persistent kernel reads
+// such data for one work item after another, and memory may be rewritten
+// between items.
+template <class T>
+__device__ __forceinline__ T load_vec(const T* p) {
+    int z = 0;
+    asm volatile("" : "+v"(z));
+    return p[z];
+}
+
 __device__ __forceinline__ uint64_t make_key(float m, uint32_t id) {
     return (uint64_t(__float_as_uint(m)) << 32) | uint64_t(0x7FFFFFFFu - id);
 }

@@ -272,7 +272,7 @@ __device__ inline int process_block_mp(const GridObject& o, Lds& L, int b, const
     const bool valid = cell < o.C;
     const float4 lo = rec.lo, hi = rec.hi;
     const uint4 d0 = rec.d0, d1 = rec.d1;
-    const float4 blo = o.bstat[2 * b], bhi = o.bstat[2 * b + 1];
+    const float4 blo = load_vec(o.bstat + 2 * b), bhi = load_vec(o.bstat + 2 * b + 1);
     uint64_t ckey = valid ? ((uint64_t(d0.y) << 32) | d0.x) : 0ull;
     uint64_t csec = valid ? ((uint64_t(d1.w) << 32) | d0.w) : 0ull;
     float4 cwin = make_float4(__uint_as_float(d1.x), __uint_as_float(d1.y), __uint_as_float(d1.z),
@@ -409,7 +409,7 @@ __device__ inline void collect_block(const GridObject& o, Lds& L, int b, const B
     const bool valid = cell < o.C;
     const float4 lo = rec.lo, hi = rec.hi;
     const uint4 d0 = rec.d0, d1 = rec.d1;
-    const float4 blo = o.bstat[2 * b], bhi = o.bstat[2 * b + 1];
+    const float4 blo = load_vec(o.bstat + 2 * b), bhi = load_vec(o.bstat + 2 * b + 1);
     const bool bt = lane < K && ((pcell >> 6) == b ||
                                  box_lower(blo.x, blo.y, blo.z, bhi.x, bhi.y, bhi.z, px, py, pz) < pm);
     uint32_t cm = 0;
@@ -678,7 +678,7 @@ __device__ inline void grid_order_object_mp(const GridObject& o, GridLdsMP<BLOCK
         L.sbhi[lane] = make_float4(shx, shy, shz, 0.f);
         L.spm[lane] = lane < nsb ? 1u : 0u;  // the start reaches every superblock
         if (lane == 0) {
-            const float4 sp = o.xyzm[o.start_pos];
+            const float4 sp = load_vec(o.xyzm + o.start_pos);
             o.order[0] = int32_t(o.start_id);
             if (o.radius) o.radius[0] = INFINITY;
 #ifndef BS_PHASE_PROF

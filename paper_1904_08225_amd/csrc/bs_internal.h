@@ -67,6 +67,26 @@ const int64_t* batch_out_offsets(const BatchPlan* p);
 int batch_slots(const BatchPlan* p);
 void batch_set_job_io(BatchPlan* p, const std::vector<int32_t*>& order, const std::vector<float*>& radius,
                       const std::vector<uint32_t*>& done);
+// Serving ring: descriptors of published objects, consumed by a persistent
+// kernel.  head = next descriptor to claim, tail = published count (both
+// device memory); stop lives in pinned host memory.
+struct ServeRing {
+    void* slots = nullptr;      // cap descriptors of serve_slot_bytes() each
+    uint32_t cap = 0;
+    uint32_t* head = nullptr;
+    uint32_t* tail = nullptr;
+    const uint32_t* stop = nullptr;
+};
+int batch_work_count(const BatchPlan* p);  // objects with k > 0
+// Preprocess the plan's objects on st, then append their descriptors
+// (largest k first) at ring positions base, base + 1, ... and advance tail.
+int batch_plan_publish(BatchPlan* p, const float* pts, void* ws, size_t ws_bytes, const ServeRing& ring,
+                       uint32_t base, hipStream_t st);
+size_t serve_slot_bytes();
+// Persistent ordering workers: claim published descriptors until stop is set
+// and nothing is left, or after idle_polls polls without work.
+hipError_t launch_serve(const ServeRing& ring, int workgroups, uint32_t idle_polls, hipStream_t st);
+
 int batch_plan_execute(BatchPlan* p, const float* pts, int32_t* out_order, float* out_radius, void* ws,
                        size_t ws_bytes, hipStream_t st);
 

@@ -1,16 +1,17 @@
 // bs_server.cpp -- serving loop with continuous batching under an HBM budget.
 //
 // Requests (ordering jobs of any size) are submitted from any host thread.
-// A dispatcher thread admits pending jobs, in arrival order, into
-// micro-batches whenever an in-flight slot (a stream) is free and the HBM
-// budget allows; jobs that arrive while others run are admitted as slots
-// and memory free up, and several micro-batches run on the device at the
-// same time on different streams.  Each micro-batch copies its jobs'
-// candidates into one staging buffer, runs the batched grid ordering (one
-// workgroup per job, largest k first) straight into each job's own output
-// buffers, and every job sets its own completion flag in pinned host
-// memory, so a job's latency does not wait for the rest of its batch.
-// Results are bit-identical to ordering each job alone.
+// A persistent kernel of ordering workers (one workgroup per compute unit by
+// default) stays resident on the device and takes jobs from a device ring.
+// A dispatcher thread admits pending jobs in arrival order while they fit the
+// HBM budget, groups the admitted jobs into micro-batches, copies their
+// candidates into one staging buffer, builds all their grids with the
+// batched preprocessing on a preprocessing stream, and appends their
+// descriptors to the ring.  Idle workers claim descriptors as soon as they
+// are published, so a job only waits for a free worker, never for another
+// job.  Each job sets its own completion flag in pinned host memory; once all
+// jobs of a micro-batch are done, its memory returns to the budget.  Results
+// are bit-identical to ordering each job alone.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -30,6 +31,13 @@ namespace {
 
 using Clock = std::chrono::steady_clock;
 
+// The dispatcher raises the stop flag as soon as the server has no job
+// queued or on the device (the workers then leave within one poll, so a
+// device-wide synchronisation by the caller does not wait for them), and
+// relaunches the workers for the next job.  As a safety net the workers also
+// leave by themselves after this many empty polls (each about 5 us).
+constexpr uint32_t kIdlePolls = 4u << 20;
+
 struct Job {
     uint64_t ticket;
     bs_job req;
@@ -40,15 +48,13 @@ struct Job {
     int status = BS_OK;
 };
 
+// An admitted micro-batch whose jobs are on the device.
 struct InFlight {
-    int stream_index;
-    bool long_jobs = false;
     BatchPlan* plan = nullptr;
     void* staging = nullptr;
     void* ws = nullptr;
     size_t bytes = 0;
-    hipEvent_t finished = nullptr;
-    std::vector<uint64_t> tickets;
+    std::vector<uint64_t> tickets;  // jobs with device work
 };
 
 }  // namespace
@@ -56,12 +62,19 @@ struct InFlight {
 struct Server {
     bs_server_config cfg{};
     int device = 0;
-    std::vector<hipStream_t> streams;
-    std::vector<bool> stream_busy;
-    uint32_t* flags = nullptr;       // pinned host, one per in-flight job slot
-    uint32_t* d_flags = nullptr;     // device alias of flags
+    int workgroups = 0;
+    hipStream_t prep = nullptr;    // preprocessing and publishing, in admission order
+    hipStream_t serve = nullptr;   // the persistent workers
+    hipEvent_t serve_end = nullptr;
+    bool serve_launched = false;
+    bool serve_stopping = false;   // stop raised for the running workers
+    uint32_t* flags = nullptr;     // pinned host, one per job on the device
+    uint32_t* d_flags = nullptr;   // device alias of flags
     int flag_cap = 0;
     std::vector<int> free_flags;
+    ServeRing ring;
+    uint32_t* stop_flag = nullptr;  // pinned host (ring.stop is its device alias)
+    uint32_t published = 0;
 
     std::mutex mu;
     std::condition_variable cv_work;   // dispatcher wake-up
@@ -92,56 +105,113 @@ size_t job_bytes_estimate(int64_t n, int64_t k) {
     return size_t(n) * 64;
 }
 
-// Jobs of very different lengths are not mixed in one micro-batch: a batch
-// holds its stream until its longest job ends.  Long jobs (k >= kLongK) may
-// occupy at most half of the streams, so short jobs always find one.
-constexpr int64_t kLongK = 32768;
+void finish_job(Server& s, Job& j, int status, Clock::time_point now) {
+    j.done = true;
+    j.status = status;
+    j.done_at = now;
+    if (status == BS_OK) {
+        s.completed += 1;
+        s.k_done += j.req.k;
+        s.latencies_us.push_back(std::chrono::duration<double, std::micro>(j.done_at - j.submitted).count());
+        s.t_last_done = now;
+    }
+}
 
-bool is_long(const Job& j) { return j.req.k >= kLongK; }
+bool workers_running(Server& s) { return s.serve_launched && hipEventQuery(s.serve_end) != hipSuccess; }
 
-// Launch one micro-batch on stream si (caller holds mu).  Takes, in arrival
-// order, pending jobs of the oldest admissible job's length class.
-bool launch_batch(Server& s, int si, int long_streams_busy) {
+// Make sure all workers run.  Workers told to stop are idle and leave within
+// one poll: wait for them, then start a full set.
+int ensure_workers(Server& s) {
+    if (workers_running(s)) {
+        if (!s.serve_stopping) return BS_OK;
+        (void)hipEventSynchronize(s.serve_end);
+    }
+    __atomic_store_n(&s.stop_flag[0], 0u, __ATOMIC_RELEASE);
+    s.serve_stopping = false;
+    hipError_t e = launch_serve(s.ring, s.workgroups, kIdlePolls, s.serve);
+    if (e == hipSuccess) e = hipEventRecord(s.serve_end, s.serve);
+    if (e != hipSuccess) return set_error(BS_ERR_HIP, "serve launch: %s", hipGetErrorString(e));
+    s.serve_launched = true;
+    return BS_OK;
+}
+
+// Nothing queued or on the device: let the workers leave.
+void stop_workers(Server& s) {
+    if (s.serve_stopping || !workers_running(s)) return;
+    __atomic_store_n(&s.stop_flag[0], 1u, __ATOMIC_RELEASE);
+    s.serve_stopping = true;
+}
+
+// Admit one micro-batch from the front of the pending queue (caller holds
+// mu).  Returns false when nothing could be admitted now.
+bool admit_batch(Server& s) {
     std::vector<uint64_t> take;
     size_t bytes = 0;
-    int64_t total_n = 0;
     const size_t budget = s.cfg.hbm_budget_bytes;
-    const int max_long = std::max(1, int(s.streams.size()) / 2);
-    int cls = -1;
-    for (auto it = s.pending.begin(); it != s.pending.end();) {
+    const auto now = Clock::now();
+    bool any = false;
+    while (!s.pending.empty()) {
         if (int(take.size()) >= s.cfg.max_jobs_per_batch || int(take.size()) >= int(s.free_flags.size())) break;
-        const Job& j = s.jobs[*it];
-        const int c = is_long(j) ? 1 : 0;
-        if (cls < 0) {
-            if (c == 1 && long_streams_busy >= max_long) {
-                ++it;  // no stream for another long batch: look for short jobs
-                continue;
-            }
-            cls = c;
-        }
-        if (c != cls) {
-            ++it;
+        Job& j = s.jobs[s.pending.front()];
+        if (j.req.k == 0) {  // nothing to order
+            s.pending.pop_front();
+            s.admitted += 1;
+            finish_job(s, j, BS_OK, now);
+            any = true;
             continue;
         }
         const size_t b = job_bytes_estimate(j.req.n, j.req.k);
         if (s.bytes_in_use + bytes + b > budget) break;  // waits until memory frees up
         bytes += b;
-        total_n += j.req.n;
-        take.push_back(*it);
-        it = s.pending.erase(it);
+        take.push_back(s.pending.front());
+        s.pending.pop_front();
     }
-    if (take.empty()) return false;
+    if (any) s.cv_done.notify_all();
+    if (take.empty()) return any;
 
-    std::vector<int64_t> offs(take.size() + 1, 0), ks(take.size());
-    std::vector<uint64_t> seeds(take.size());
+    // exact bytes of the plan: give jobs back from the tail until it fits
+    InFlight f;
+    std::vector<int64_t> offs, ks;
+    std::vector<uint64_t> seeds;
+    int rc = BS_OK;
+    while (true) {
+        offs.assign(take.size() + 1, 0);
+        ks.resize(take.size());
+        seeds.resize(take.size());
+        for (size_t i = 0; i < take.size(); ++i) {
+            const Job& j = s.jobs[take[i]];
+            offs[i + 1] = offs[i] + j.req.n;
+            ks[i] = j.req.k;
+            seeds[i] = j.req.seed;
+        }
+        if (f.plan) batch_plan_free(f.plan);
+        f.plan = nullptr;
+        rc = batch_plan_create(offs.data(), ks.data(), seeds.data(), int32_t(take.size()),
+                               s.cfg.cell_points > 0.f ? s.cfg.cell_points : 8.f, &f.plan);
+        if (rc != BS_OK) break;
+        f.bytes = batch_workspace_bytes(f.plan) + align_up(size_t(offs.back()) * 12);
+        if (s.bytes_in_use + f.bytes <= budget) break;
+        if (take.size() == 1) {
+            batch_plan_free(f.plan);
+            f.plan = nullptr;
+            if (!s.inflight.empty()) {  // wait for memory to free up
+                s.pending.push_front(take[0]);
+                return false;
+            }
+            Job& j = s.jobs[take[0]];  // can never fit
+            finish_job(s, j, BS_ERR_OVER_BUDGET, now);
+            s.rejected += 1;
+            s.cv_done.notify_all();
+            return true;
+        }
+        s.pending.push_front(take.back());
+        take.pop_back();
+    }
     std::vector<int32_t*> outo(take.size());
     std::vector<float*> outr(take.size());
     std::vector<uint32_t*> done(take.size());
     for (size_t i = 0; i < take.size(); ++i) {
         Job& j = s.jobs[take[i]];
-        offs[i + 1] = offs[i] + j.req.n;
-        ks[i] = j.req.k;
-        seeds[i] = j.req.seed;
         outo[i] = j.req.d_out_order;
         outr[i] = j.req.d_out_radius;
         j.flag_slot = s.free_flags.back();
@@ -149,140 +219,72 @@ bool launch_batch(Server& s, int si, int long_streams_busy) {
         s.flags[j.flag_slot] = 0u;
         done[i] = s.d_flags + j.flag_slot;
     }
-    InFlight f;
-    f.stream_index = si;
-    hipStream_t st = s.streams[si];
-    int rc = BS_OK;
-    // admission on the exact bytes of the plan: give back jobs from the tail
-    // of this batch until it fits the remaining budget
-    while (true) {
-        if (f.plan) {
-            batch_plan_free(f.plan);
-            f.plan = nullptr;
-        }
-        rc = batch_plan_create(offs.data(), ks.data(), seeds.data(), int32_t(take.size()),
-                               s.cfg.cell_points > 0.f ? s.cfg.cell_points : 8.f, &f.plan);
-        if (rc != BS_OK) break;
-        total_n = offs[take.size()];
-        f.bytes = batch_workspace_bytes(f.plan) + align_up(size_t(total_n) * 12);
-        if (s.bytes_in_use + f.bytes <= budget) break;
-        if (take.size() == 1) {
-            batch_plan_free(f.plan);
-            f.plan = nullptr;
-            Job& j = s.jobs[take[0]];
-            s.free_flags.push_back(j.flag_slot);
-            j.flag_slot = -1;
-            if (!s.inflight.empty()) {  // wait for memory to free up
-                s.pending.insert(std::lower_bound(s.pending.begin(), s.pending.end(), take[0]), take[0]);
-                return false;
-            }
-            j.done = true;  // can never fit
-            j.status = BS_ERR_OVER_BUDGET;
-            j.done_at = Clock::now();
-            s.rejected += 1;
-            s.cv_done.notify_all();
-            return true;
-        }
-        Job& last = s.jobs[take.back()];
-        s.free_flags.push_back(last.flag_slot);
-        last.flag_slot = -1;
-        s.pending.insert(std::lower_bound(s.pending.begin(), s.pending.end(), take.back()), take.back());
-        take.pop_back();
-        offs.resize(take.size() + 1);
-        ks.resize(take.size());
-        seeds.resize(take.size());
-        outo.resize(take.size());
-        outr.resize(take.size());
-        done.resize(take.size());
-    }
-    f.tickets = take;
     hipError_t e = hipSuccess;
     if (rc == BS_OK) {
         batch_set_job_io(f.plan, outo, outr, done);
-        e = hipMallocAsync(&f.staging, std::max<size_t>(size_t(total_n) * 12, 16), st);
-        if (e == hipSuccess) e = hipMallocAsync(&f.ws, std::max<size_t>(batch_workspace_bytes(f.plan), 256), st);
+        e = hipMallocAsync(&f.staging, std::max<size_t>(size_t(offs.back()) * 12, 16), s.prep);
+        if (e == hipSuccess) e = hipMallocAsync(&f.ws, std::max<size_t>(batch_workspace_bytes(f.plan), 256), s.prep);
         for (size_t i = 0; e == hipSuccess && i < take.size(); ++i) {
             const Job& j = s.jobs[take[i]];
-            if (j.req.n > 0)
-                e = hipMemcpyAsync(static_cast<char*>(f.staging) + size_t(offs[i]) * 12, j.req.d_points,
-                                   size_t(j.req.n) * 12, hipMemcpyDeviceToDevice, st);
+            e = hipMemcpyAsync(static_cast<char*>(f.staging) + size_t(offs[i]) * 12, j.req.d_points,
+                               size_t(j.req.n) * 12, hipMemcpyDeviceToDevice, s.prep);
         }
         if (e == hipSuccess) {
-            rc = batch_plan_execute(f.plan, static_cast<const float*>(f.staging), nullptr, nullptr, f.ws,
-                                    batch_workspace_bytes(f.plan), st);
+            rc = batch_plan_publish(f.plan, static_cast<const float*>(f.staging), f.ws,
+                                    batch_workspace_bytes(f.plan), s.ring, s.published, s.prep);
+            if (rc == BS_OK) rc = ensure_workers(s);
         } else {
-            rc = BS_ERR_HIP;
+            rc = set_error(BS_ERR_HIP, "staging: %s", hipGetErrorString(e));
         }
-        if (e == hipSuccess) e = hipEventCreateWithFlags(&f.finished, hipEventDisableTiming);
-        if (e == hipSuccess) e = hipEventRecord(f.finished, st);
-        if (f.staging) (void)hipFreeAsync(f.staging, st);
-        if (f.ws) (void)hipFreeAsync(f.ws, st);
-        if (e != hipSuccess && rc == BS_OK) rc = BS_ERR_HIP;
     }
     if (rc != BS_OK) {
-        // fail the jobs of this batch; nothing of it is pending on the device
-        if (f.finished) (void)hipEventSynchronize(f.finished);
+        // nothing of this batch is pending on the device: fail its jobs
+        (void)hipStreamSynchronize(s.prep);
         for (uint64_t t : take) {
             Job& j = s.jobs[t];
-            j.done = true;
-            j.status = rc;
-            j.done_at = Clock::now();
+            finish_job(s, j, rc, now);
             s.free_flags.push_back(j.flag_slot);
+            j.flag_slot = -1;
         }
+        if (f.staging) (void)hipFreeAsync(f.staging, s.prep);
+        if (f.ws) (void)hipFreeAsync(f.ws, s.prep);
         if (f.plan) batch_plan_free(f.plan);
-        if (f.finished) (void)hipEventDestroy(f.finished);
         s.last_error = rc;
         s.cv_done.notify_all();
         return true;
     }
-    f.long_jobs = is_long(s.jobs[take[0]]);
+    s.published += uint32_t(batch_work_count(f.plan));
+    f.tickets = take;
     s.bytes_in_use += f.bytes;
     s.bytes_peak = std::max(s.bytes_peak, s.bytes_in_use);
     s.admitted += int64_t(take.size());
     s.batches += 1;
-    s.stream_busy[si] = true;
     s.inflight.push_back(std::move(f));
     return true;
 }
 
-// Record finished jobs and retire finished batches (caller holds mu).
+// Record finished jobs and release finished micro-batches (caller holds mu).
 bool reap(Server& s) {
     bool any = false;
     const auto now = Clock::now();
     for (size_t b = 0; b < s.inflight.size();) {
         InFlight& f = s.inflight[b];
+        bool all = true;
         for (uint64_t t : f.tickets) {
             Job& j = s.jobs[t];
             if (!j.done && __atomic_load_n(&s.flags[j.flag_slot], __ATOMIC_ACQUIRE) != 0u) {
-                j.done = true;
-                j.done_at = now;
-                s.completed += 1;
-                s.k_done += j.req.k;
-                s.latencies_us.push_back(
-                    std::chrono::duration<double, std::micro>(j.done_at - j.submitted).count());
-                s.t_last_done = now;
-                any = true;
-            }
-        }
-        if (hipEventQuery(f.finished) == hipSuccess) {
-            for (uint64_t t : f.tickets) {
-                Job& j = s.jobs[t];
-                if (!j.done) {  // flag not seen (k = 0 jobs also set it): count it now
-                    j.done = true;
-                    j.done_at = now;
-                    s.completed += 1;
-                    s.k_done += j.req.k;
-                    s.latencies_us.push_back(
-                        std::chrono::duration<double, std::micro>(j.done_at - j.submitted).count());
-                    s.t_last_done = now;
-                }
+                finish_job(s, j, BS_OK, now);
                 s.free_flags.push_back(j.flag_slot);
                 j.flag_slot = -1;
+                any = true;
             }
-            s.bytes_in_use -= f.bytes;
-            s.stream_busy[f.stream_index] = false;
+            all = all && j.done;
+        }
+        if (all) {  // no worker touches this batch any more
+            (void)hipFreeAsync(f.staging, s.prep);
+            (void)hipFreeAsync(f.ws, s.prep);
             batch_plan_free(f.plan);
-            (void)hipEventDestroy(f.finished);
+            s.bytes_in_use -= f.bytes;
             s.inflight.erase(s.inflight.begin() + long(b));
             any = true;
             continue;
@@ -299,18 +301,12 @@ void dispatcher(Server* sp) {
     std::unique_lock<std::mutex> lk(s.mu);
     while (true) {
         reap(s);
-        // admit while a stream is free and pending jobs fit
-        bool launched = true;
-        while (launched && !s.pending.empty()) {
-            launched = false;
-            int long_busy = 0;
-            for (const InFlight& f : s.inflight) long_busy += f.long_jobs ? 1 : 0;
-            for (size_t si = 0; si < s.streams.size(); ++si) {
-                if (!s.stream_busy[si]) {
-                    launched = launch_batch(s, int(si), long_busy);
-                    break;
-                }
-            }
+        while (!s.pending.empty() && int(s.inflight.size()) < s.cfg.max_inflight && admit_batch(s)) {
+        }
+        if (!s.inflight.empty()) {
+            if (ensure_workers(s) != BS_OK) s.last_error = BS_ERR_HIP;
+        } else if (s.pending.empty()) {
+            stop_workers(s);
         }
         if (s.stop && s.pending.empty() && s.inflight.empty()) break;
         if (s.inflight.empty() && s.pending.empty())
@@ -327,6 +323,19 @@ double percentile(std::vector<double> v, double q) {
     const size_t i = size_t(pos);
     const double f = pos - double(i);
     return i + 1 < v.size() ? v[i] * (1 - f) + v[i + 1] * f : v[i];
+}
+
+void release(Server* s) {
+    if (s->serve) (void)hipStreamSynchronize(s->serve);
+    if (s->prep) (void)hipStreamSynchronize(s->prep);
+    if (s->serve_end) (void)hipEventDestroy(s->serve_end);
+    if (s->ring.slots) (void)hipFree(s->ring.slots);
+    if (s->ring.head) (void)hipFree(s->ring.head);
+    if (s->serve) (void)hipStreamDestroy(s->serve);
+    if (s->prep) (void)hipStreamDestroy(s->prep);
+    if (s->flags) (void)hipHostFree(s->flags);
+    if (s->stop_flag) (void)hipHostFree(s->stop_flag);
+    delete s;
 }
 
 }  // namespace
@@ -346,30 +355,45 @@ int bs_server_create(const bs_server_config* cfg, bs_server** out) {
     if (cfg->hbm_budget_bytes == 0) return set_error(BS_ERR_INVALID_ARG, "zero HBM budget");
     for (int r : cfg->reserved)
         if (r) return set_error(BS_ERR_INVALID_ARG, "reserved fields must be zero");
+    if (cfg->workgroups < 0 || cfg->max_inflight < 0 || cfg->max_jobs_per_batch < 0)
+        return set_error(BS_ERR_INVALID_ARG, "negative server sizes");
     Server* s = new Server();
     s->cfg = *cfg;
-    if (s->cfg.max_inflight <= 0) s->cfg.max_inflight = 4;
+    if (s->cfg.max_inflight <= 0) s->cfg.max_inflight = 64;
     if (s->cfg.max_jobs_per_batch <= 0) s->cfg.max_jobs_per_batch = 512;
     s->device = cfg->device;
     hipError_t e = hipSetDevice(s->device);
-    for (int i = 0; e == hipSuccess && i < s->cfg.max_inflight; ++i) {
-        hipStream_t st = nullptr;
-        e = hipStreamCreateWithFlags(&st, hipStreamNonBlocking);
-        if (e == hipSuccess) {
-            s->streams.push_back(st);
-            s->stream_busy.push_back(false);
-        }
-    }
+    int cus = 0;
+    if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, s->device);
+    s->workgroups = cfg->workgroups > 0 ? cfg->workgroups : std::max(cus, 1);
+    if (e == hipSuccess) e = hipStreamCreateWithFlags(&s->prep, hipStreamNonBlocking);
+    if (e == hipSuccess) e = hipStreamCreateWithFlags(&s->serve, hipStreamNonBlocking);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&s->serve_end, hipEventDisableTiming);
     s->flag_cap = s->cfg.max_inflight * s->cfg.max_jobs_per_batch;
     if (e == hipSuccess)
         e = hipHostMalloc(reinterpret_cast<void**>(&s->flags), size_t(s->flag_cap) * 4,
                           hipHostMallocMapped | hipHostMallocCoherent);
     if (e == hipSuccess) e = hipHostGetDevicePointer(reinterpret_cast<void**>(&s->d_flags), s->flags, 0);
+    if (e == hipSuccess)
+        e = hipHostMalloc(reinterpret_cast<void**>(&s->stop_flag), 64, hipHostMallocMapped | hipHostMallocCoherent);
+    uint32_t* d_stop = nullptr;
+    if (e == hipSuccess) {
+        s->stop_flag[0] = 0u;
+        e = hipHostGetDevicePointer(reinterpret_cast<void**>(&d_stop), s->stop_flag, 0);
+    }
+    // ring: one slot per completion flag (a published job holds a flag until
+    // it is done, so an unclaimed descriptor is never overwritten)
+    s->ring.cap = uint32_t(s->flag_cap);
+    s->ring.stop = d_stop;
+    if (e == hipSuccess) e = hipMalloc(&s->ring.slots, size_t(s->flag_cap) * serve_slot_bytes());
+    if (e == hipSuccess) e = hipMalloc(reinterpret_cast<void**>(&s->ring.head), 256);
+    if (e == hipSuccess) e = hipMemset(s->ring.head, 0, 256);
+    if (e == hipSuccess) e = hipDeviceSynchronize();
+    s->ring.tail = s->ring.head ? s->ring.head + 32 : nullptr;  // its own 128-byte line
     if (e != hipSuccess) {
-        for (hipStream_t st : s->streams) (void)hipStreamDestroy(st);
-        if (s->flags) (void)hipHostFree(s->flags);
-        delete s;
-        return set_error(BS_ERR_HIP, "server setup: %s", hipGetErrorString(e));
+        const int rc = set_error(BS_ERR_HIP, "server setup: %s", hipGetErrorString(e));
+        release(s);
+        return rc;
     }
     for (int i = s->flag_cap - 1; i >= 0; --i) {
         s->flags[i] = 0u;
@@ -486,10 +510,9 @@ void bs_server_destroy(bs_server* srv) {
         s->stop = true;
     }
     s->cv_work.notify_all();
-    if (s->thread.joinable()) s->thread.join();
-    for (hipStream_t st : s->streams) (void)hipStreamDestroy(st);
-    if (s->flags) (void)hipHostFree(s->flags);
-    delete s;
+    if (s->thread.joinable()) s->thread.join();  // every job is done
+    __atomic_store_n(&s->stop_flag[0], 1u, __ATOMIC_RELEASE);  // workers leave once nothing is left
+    release(s);
     delete srv;
 }
 
