@@ -104,7 +104,10 @@ def bench_main(args, bs, torch, np):
     log("generated cad_part n=%d in %.1fs" % (N_MAIN, time.time() - t0))
     n, k = N_MAIN, K_MAIN
     t0 = time.time()
-    tuned = bs.autotune(pts, k, seed=SEED_MAIN)  # recorded for this size; untimed
+    if args.no_autotune:
+        tuned = bs.Tuning()
+    else:
+        tuned = bs.autotune(pts, k, seed=SEED_MAIN)  # recorded for this size; untimed
     log("autotune: kernel %d block %d cells %g picks %d in %.1fs"
         % (tuned.kernel, tuned.block, tuned.cell_points, tuned.picks, time.time() - t0))
     kernel = bs.auto_kernel(n, k)
@@ -361,6 +364,8 @@ def main():
     ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--no-serve", action="store_true")
     ap.add_argument("--no-scene", action="store_true")
+    ap.add_argument("--no-autotune", action="store_true",
+                    help="use the automatic kernel choice without timing candidates first")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
                     help="only run two plain device-to-device copies of BYTES bytes (scales the "
                          "FETCH_SIZE / WRITE_SIZE counters to bytes) and exit")
@@ -406,7 +411,8 @@ def main():
                    "event_ms_per_step": ev_ms,
                    "tuning": {"kernel": int(tuned.kernel), "block": int(tuned.block),
                               "cell_points": float(tuned.cell_points), "picks": int(tuned.picks),
-                              "source": "library autotuner (bs_autotune), run before the timed steps"}},
+                              "source": "library defaults (no autotuning)" if args.no_autotune else
+                              "library autotuner (bs_autotune), run before the timed steps"}},
         "latency": {"per_round_p50_us": lat["p50_us"], "per_round_p99_us": lat["p99_us"],
                     "per_round_mean_us": lat["mean_us"], "rounds": lat["rounds"],
                     "picks_per_round": lat["picks_per_round"], "mean_us_per_pick": lat["mean_us_per_pick"],
