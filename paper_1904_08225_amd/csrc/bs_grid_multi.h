@@ -50,9 +50,14 @@ struct WaveScratchMP {
     float4 gwin[64];     // x, y, z, sorted position of that best
 };
 
-// Workgroup-wide lists of the cell-parallel path (rounds touching few blocks).
-constexpr int kHitCells = 256;   // hit cells per round
-constexpr int kHitBlocks = 64;   // touched blocks per round
+// Workgroup-wide lists of the cell-parallel path (rounds touching few
+// blocks); they share LDS with the per-wavefront scratch, so wider
+// workgroups have room for longer lists.
+template <int NW>
+struct HitCaps {
+    static constexpr int cells = NW >= 16 ? 768 : 256;   // hit cells per round
+    static constexpr int blocks = NW >= 16 ? 128 : 64;   // touched blocks per round
+};
 
 struct CellResult {
     uint64_t g1, g2;  // new best and second key of the cell
@@ -73,9 +78,9 @@ template <int NW>
 union ScratchMP {
     WaveScratchMP ws[NW];
     struct {
-        int4 hc[kHitCells];          // cell, first member, member count, pick mask
-        CellResult cr[kHitCells];
-        HitBlock hb[kHitBlocks];
+        int4 hc[HitCaps<NW>::cells];     // cell, first member, member count, pick mask
+        CellResult cr[HitCaps<NW>::cells];
+        HitBlock hb[HitCaps<NW>::blocks];
     } lists;
 };
 
@@ -99,7 +104,9 @@ struct GridLdsMP {
     int sorted[64];        // superblocks by descending best key (selection)
     float4 cand[kMaxPicks];     // selection: candidates x, y, z, m
     uint32_t candsec[kMaxPicks];
-    int tlist[kHitBlocks]; // touched blocks by rank (rounds touching few blocks)
+    int tlist[HitCaps<NW>::blocks];  // touched blocks by rank (rounds touching few blocks)
+    static constexpr int kHitCells = HitCaps<NW>::cells;
+    static constexpr int kHitBlocks = HitCaps<NW>::blocks;
     int hcount, hbcount, overflow;
     ScratchMP<NW> u;
 };
@@ -432,7 +439,7 @@ __device__ inline void collect_block(const GridObject& o, Lds& L, int b, const B
     }
     base = __builtin_amdgcn_readfirstlane(base);
     hbi = __builtin_amdgcn_readfirstlane(hbi);
-    if (base + nh > kHitCells || hbi >= kHitBlocks) {
+    if (base + nh > Lds::kHitCells || hbi >= Lds::kHitBlocks) {
         if (lane == 0) L.overflow = 1;
         return;
     }
@@ -774,7 +781,7 @@ __device__ inline void grid_order_object_mp(const GridObject& o, GridLdsMP<BLOCK
         int nblk = 0, nhit = 0, ncells = 0;
         (void)nblk; (void)nhit; (void)ncells;
         uint64_t pacc[3] = {0, 0, 0};
-        bool per_block = touched > kHitBlocks;
+        bool per_block = touched > L.kHitBlocks;
         int mycount = 0;  // touched blocks of this wavefront (few-block rounds)
         if (!per_block) {
             // this wavefront's touched blocks (ranks wave, wave + NW, ...) into tlist
