@@ -173,7 +173,7 @@ def bench_full_scan(bs, torch, pts, k):
             "frac_of_hbm_peak": abytes / secs / 1e9 / HBM_PEAK_GBS}, o
 
 
-def bench_batched(bs, torch, np):
+def bench_batched(bs, torch, np, cpu=True):
     import synth
     dev = torch.device("cuda:0")
     m = 1000
@@ -221,15 +221,16 @@ def bench_batched(bs, torch, np):
         oa, ob = plan.out_offsets[j], plan.out_offsets[j + 1]
         same &= bool(torch.equal(so, out_o[oa:ob]))
     plan.close()
+    cpu_rec = cpu_oracle_objects(pts, offs, ks, seeds, order_idx, plan.total_k, batch_s) if cpu else None
     return {"objects": m, "candidates": int(pts.shape[0]), "sum_k": int(plan.total_k),
             "cell_target": float(tune.cell_points), "seconds": batch_s, "ordered_surfels_per_s": plan.total_k / batch_s,
             "plain_loop_ordered_surfels_per_s": plain_rate,
             "plain_loop_sample": "%d objects spread over the size range, %d picks, %.1f s" % (len(sample), sk, sample_s),
             "plain_loop_estimated_seconds": plain_est_s, "speedup_vs_plain": plain_est_s / batch_s,
-            "largest_object_k": max(ks), "spot_check_equal_alone": same}
+            "largest_object_k": max(ks), "spot_check_equal_alone": same, "cpu_oracle": cpu_rec}
 
 
-def bench_scene(bs, torch, np):
+def bench_scene(bs, torch, np, cpu=True):
     """Heterogeneous scene: 10,000 objects (thin sheets, tori, small-box
     clusters), 1.5e9 candidates, k_j = 12% of n_j, one batched launch."""
     import synth
@@ -278,6 +279,7 @@ def bench_scene(bs, torch, np):
            "plain_loop_sample": "%d objects spread over the size range, %d picks, %.1f s" % (len(sample), sk, sample_s),
            "speedup_vs_plain": (plan.total_k / plain_rate) / batch_s, "spot_check_equal_alone": same}
     plan.close()
+    res["cpu_oracle"] = cpu_oracle_objects(pts, offs, ks, seeds, order_idx, res["sum_k"], batch_s) if cpu else None
     return res
 
 
@@ -352,6 +354,48 @@ def cpu_baseline(points_host, k, start):
     return {"value": k / dt, "unit": "ordered surfels/s", "cores": 1, "kind": "oracle",
             "sample": "exact grid-accelerated oracle (oracle/bs_oracle.c, 1 thread) on the full "
                       "workload n=%d k=%d, %.1f s" % (points_host.shape[0], k, dt)}, order, int(st["n_ball"].sum())
+
+
+def cpu_oracle_objects(pts, offs, ks, seeds, order_idx, sum_k_total, gpu_seconds,
+                       max_k=300_000, budget_k=3_000_000, count=24):
+    """The exact CPU oracle on a bounded sample of a batch's objects (those
+    with k <= max_k, spread over their size range, at most budget_k picks),
+    object-parallel on a thread pool over the host's cores (the oracle's C
+    calls release the GIL).  The single-thread rate comes from the objects'
+    own durations inside the pool, so it includes the contention of the
+    other threads."""
+    import os
+    from concurrent.futures import ThreadPoolExecutor
+    import oracle
+    eligible = [j for j in order_idx if 0 < ks[j] <= max_k]
+    sample, sk = [], 0
+    for j in eligible[:: max(1, len(eligible) // count)]:
+        if sk + ks[j] > budget_k:
+            break
+        sample.append(j)
+        sk += ks[j]
+    host = [pts[offs[j]:offs[j + 1]].cpu().numpy() for j in sample]
+    cores = min(len(os.sched_getaffinity(0)), 16)
+
+    def one(i):
+        j = sample[i]
+        t0 = time.perf_counter()
+        oracle.greedy32_grid(host[i], ks[j], oracle.start_index(seeds[j], host[i].shape[0]))
+        return time.perf_counter() - t0
+
+    t0 = time.perf_counter()
+    with ThreadPoolExecutor(cores) as ex:
+        per = list(ex.map(one, range(len(sample))))
+    wall = time.perf_counter() - t0
+    par_rate = sk / wall
+    one_rate = sk / sum(per)
+    log("cpu oracle: %d objects, %d picks, %.1f s on %d threads" % (len(sample), sk, wall, cores))
+    return {"kind": "oracle", "cores": cores, "object_parallel_ordered_surfels_per_s": par_rate,
+            "single_thread_ordered_surfels_per_s": one_rate,
+            "estimated_seconds_object_parallel": sum_k_total / par_rate,
+            "gpu_speedup_vs_object_parallel": (sum_k_total / par_rate) / gpu_seconds,
+            "sample": "%d objects with n = %d..%d (k <= %d), %d picks, %.1f s wall on %d threads"
+                      % (len(sample), host[0].shape[0], host[-1].shape[0], max_k, sk, wall, cores)}
 
 
 def main():
@@ -448,10 +492,10 @@ def main():
     del surf, pts
     torch.cuda.empty_cache()
     if not args.no_batch:
-        rec["batched"] = bench_batched(bs, torch, np)
+        rec["batched"] = bench_batched(bs, torch, np, cpu=not args.no_cpu_baseline)
         torch.cuda.empty_cache()
     if not args.no_scene:
-        rec["scene_batched"] = bench_scene(bs, torch, np)
+        rec["scene_batched"] = bench_scene(bs, torch, np, cpu=not args.no_cpu_baseline)
         torch.cuda.empty_cache()
     if not args.no_serve:
         rec["served"] = bench_served(bs, torch, np)
