@@ -8,18 +8,24 @@ A step is one full ordering of one synthetic CAD-like part -- the union
 boundary of 200 random boxes/cylinders, 4,194,304 binary32 candidates,
 ordered to k = 262,144 -- through the library's automatic kernel choice
 (autotuned for this size before the timed steps): input validation, grid
-build, every greedy step (select + min-distance update) and the emitted
-order and radii, with the candidates already resident in HBM.  `value` is
-ordered surfels per second of that step.
+build, every greedy step (select + min-distance update: the first n/1024
+picks by the cooperative full scan over all CUs, the rest by the grid-pruned
+kernel) and the emitted order and radii, with the candidates already
+resident in HBM.  `value` is ordered surfels per second of that step.
 
 The same JSON line also carries
   roofline      the dominant kernel (grid-pruned ordering) against HBM,
                 with its algorithmic bytes (16 B per candidate inside the
-                covering-radius ball, counted by the CPU oracle on the same
-                points) over its duration (HIP events on the launch stream)
-                and the HBM traffic measured by counters (profiles/);
-  latency       per-round p50 / p99 from device timestamps (a round emits
-                several exact picks);
+                covering-radius ball over its steps, counted by the CPU
+                oracle on the same points) over its duration (HIP events on
+                the launch stream) and the HBM traffic measured by counters
+                (profiles/);
+  lead_scan     the leading cooperative full scan of the same step: its
+                picks, duration and algorithmic bytes (16 B per live
+                candidate per step);
+  latency       per-round p50 / p99 of the grid kernel from device
+                timestamps (a round emits several exact picks), and the
+                leading scan's per-step p50 / p99;
   full_scan     the cooperative register-resident full scan on the same
                 input (16 B per live candidate per step);
   batched       1,000 parts of the same kind, n log-uniform 2,048..2,097,152,
@@ -75,23 +81,34 @@ def log(msg):
     print("[bench] " + msg, file=sys.stderr, flush=True)
 
 
-def ordering_kernel_seconds(bs, pts, k, start, tune):
+def ordering_kernel_seconds(bs, pts, k, start, tune, lead=0):
     """Duration of the ordering loop from the device clock (first to last pick)
-    and per-step latencies."""
+    and per-step latencies.  With a leading full scan of `lead` picks, the
+    round statistics cover the grid kernel's picks (lead onward) and the
+    scan's steps are reported apart."""
     import torch
     o, r, t = bs.order_profile(pts, k, start=start, tune=tune)
     torch.cuda.synchronize()
     import numpy as np
     tk = t.cpu().numpy().astype("float64")
     hz = bs.wall_clock_hz()
+    lead = lead if lead >= 2 else 0
+    g = tk[lead:] if lead else tk
     # picks of one round share a timestamp: latencies are per round
-    rt = np.unique(tk)
+    rt = np.unique(g)
     d = (rt[1:] - rt[:-1]) / hz * 1e6 if rt.shape[0] > 1 else np.zeros(1)
-    span = (tk[-1] - tk[0]) / hz
-    return span, {"p50_us": float(np.percentile(d, 50)), "p99_us": float(np.percentile(d, 99)),
-                  "mean_us": float(d.mean()), "rounds": int(rt.shape[0]),
-                  "picks_per_round": float(tk.shape[0] / rt.shape[0]),
-                  "mean_us_per_pick": float(span * 1e6 / max(1, tk.shape[0] - 1))}, o
+    span = (g[-1] - g[0]) / hz
+    lat = {"p50_us": float(np.percentile(d, 50)), "p99_us": float(np.percentile(d, 99)),
+           "mean_us": float(d.mean()), "rounds": int(rt.shape[0]),
+           "picks_per_round": float(g.shape[0] / rt.shape[0]),
+           "mean_us_per_pick": float(span * 1e6 / max(1, g.shape[0] - 1))}
+    if lead:
+        ds = (tk[1:lead] - tk[:lead - 1]) / hz * 1e6
+        lat["lead_picks"] = lead
+        lat["lead_seconds"] = float((tk[lead - 1] - tk[0]) / hz)
+        lat["lead_step_p50_us"] = float(np.percentile(ds, 50))
+        lat["lead_step_p99_us"] = float(np.percentile(ds, 99))
+    return span, lat, o
 
 
 def bench_main(args, bs, torch, np):
@@ -108,8 +125,10 @@ def bench_main(args, bs, torch, np):
         tuned = bs.Tuning()
     else:
         tuned = bs.autotune(pts, k, seed=SEED_MAIN)  # recorded for this size; untimed
-    log("autotune: kernel %d block %d cells %g picks %d in %.1fs"
-        % (tuned.kernel, tuned.block, tuned.cell_points, tuned.picks, time.time() - t0))
+    plan = bs.plan_describe(n, k)  # the plan the timed calls follow (automatic choices resolved)
+    lead = int(plan.lead_picks) if plan.kernel == bs.KERNEL_GRID and plan.lead_picks > 0 else 0
+    log("autotune: kernel %d block %d cells %g picks %d lead %d in %.1fs"
+        % (plan.kernel, plan.block, plan.cell_points, plan.picks, lead, time.time() - t0))
     kernel = bs.auto_kernel(n, k)
     ws = torch.empty(max(bs.workspace_size(n, k), 1), dtype=torch.uint8, device=dev)
     out_o = torch.empty(k, dtype=torch.int32, device=dev)
@@ -146,10 +165,13 @@ def bench_main(args, bs, torch, np):
     ms = wall * 1000.0 / args.steps
     log("timed %d steps: %.1f ms/step wall, %.1f ms/step events, ordering kernel %.1f ms"
         % (args.steps, ms, ev_ms, kern_ms))
-    _, lat, _ = ordering_kernel_seconds(bs, pts, k, start, None)
+    _, lat, _ = ordering_kernel_seconds(bs, pts, k, start, None, lead)
     log("rounds %d (%.2f picks each), per-round p50 %.2f us, %.2f us per pick (device clock)"
         % (lat["rounds"], lat["picks_per_round"], lat["p50_us"], lat["mean_us_per_pick"]))
-    return pts, surf, out_o, ms, ev_ms, kern_ms / 1e3, lat, kernel, tuned
+    if lead:
+        log("leading full scan: %d picks in %.1f ms, p50 %.2f us per step"
+            % (lead, lat["lead_seconds"] * 1e3, lat["lead_step_p50_us"]))
+    return pts, surf, out_o, ms, ev_ms, kern_ms / 1e3, lat, kernel, plan, lead
 
 
 def bench_full_scan(bs, torch, pts, k):
@@ -353,7 +375,7 @@ def cpu_baseline(points_host, k, start):
     dt = time.perf_counter() - t0
     return {"value": k / dt, "unit": "ordered surfels/s", "cores": 1, "kind": "oracle",
             "sample": "exact grid-accelerated oracle (oracle/bs_oracle.c, 1 thread) on the full "
-                      "workload n=%d k=%d, %.1f s" % (points_host.shape[0], k, dt)}, order, int(st["n_ball"].sum())
+                      "workload n=%d k=%d, %.1f s" % (points_host.shape[0], k, dt)}, order, st["n_ball"]
 
 
 def cpu_oracle_objects(pts, offs, ks, seeds, order_idx, sum_k_total, gpu_seconds,
@@ -433,7 +455,7 @@ def main():
         torch.cuda.synchronize()
         print(json.dumps({"copy_calibration_bytes": args.copy_calibration, "copies": 2}), flush=True)
         return
-    pts, surf, out_o, ms, ev_ms, kern_s, lat, kernel, tuned = bench_main(args, bs, torch, np)
+    pts, surf, out_o, ms, ev_ms, kern_s, lat, kernel, tuned, lead = bench_main(args, bs, torch, np)
     n, k = N_MAIN, K_MAIN
     rec = {
         "metric": "ordered surfels/sec (exact greedy blue-noise ordering)",
@@ -455,13 +477,16 @@ def main():
                    "event_ms_per_step": ev_ms,
                    "tuning": {"kernel": int(tuned.kernel), "block": int(tuned.block),
                               "cell_points": float(tuned.cell_points), "picks": int(tuned.picks),
+                              "lead_picks": lead,
                               "source": "library defaults (no autotuning)" if args.no_autotune else
                               "library autotuner (bs_autotune), run before the timed steps"}},
         "latency": {"per_round_p50_us": lat["p50_us"], "per_round_p99_us": lat["p99_us"],
                     "per_round_mean_us": lat["mean_us"], "rounds": lat["rounds"],
                     "picks_per_round": lat["picks_per_round"], "mean_us_per_pick": lat["mean_us_per_pick"],
-                    "source": "device wall clock at each round's emission (a round emits several "
-                              "exact picks)"},
+                    "lead_step_p50_us": lat.get("lead_step_p50_us"),
+                    "lead_step_p99_us": lat.get("lead_step_p99_us"),
+                    "source": "device wall clock at each pick's emission: grid-kernel rounds (a round "
+                              "emits several exact picks) and, apart, the steps of the leading full scan"},
     }
     host = pts.cpu().numpy()
     n_ball = None
@@ -471,7 +496,9 @@ def main():
         rec["config"]["matches_oracle"] = bool(np.array_equal(out_o.cpu().numpy(), eo))
         log("cpu baseline: " + cb["sample"])
     if n_ball is not None:
-        abytes = 16 * n_ball
+        # the grid kernel makes the updates of picks lead-1 .. k-2, the leading
+        # scan those of picks 0 .. lead-2 over every live candidate
+        abytes = 16 * int(n_ball[max(lead - 1, 0):].sum())
         achieved = abytes / kern_s / 1e9
         rec["roofline"] = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                            "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(),
@@ -481,9 +508,19 @@ def main():
                            "traffic_source": "rocprofv3 FETCH_SIZE and WRITE_SIZE per launch, scaled by a "
                                              "plain copy of known size (profiles/grid_cad_part_4M_hbm_counters.txt)",
                            "kernel_time_source": "HIP events recorded on the launch stream around the "
-                                                 "ordering kernel, mean over the timed steps",
+                                                 "grid ordering kernel, mean over the timed steps",
                            "note": "16 B per live candidate inside the covering-radius ball per step "
-                                   "(pruned accounting); the step chain is latency-bound"}
+                                   "(pruned accounting) over the grid kernel's steps; the step chain is "
+                                   "latency-bound"}
+        if lead:
+            live = sum(n - j - 1 for j in range(lead - 1))
+            ls = lat["lead_seconds"]
+            rec["lead_scan"] = {"kernel": "scan_kernel<1024,%d,true> x %d workgroups" % (tuned.per_thread,
+                                                                                       tuned.groups),
+                                "picks": lead, "seconds": ls, "algorithmic_bytes": 16 * live,
+                                "achieved_GBs": 16 * live / ls / 1e9,
+                                "frac_of_hbm_peak": 16 * live / ls / 1e9 / HBM_PEAK_GBS,
+                                "time_source": "device wall clock from pick 0 to the scan's last pick"}
     if not args.no_full_scan:
         fs, fo = bench_full_scan(bs, torch, pts, k)
         fs["matches_grid_kernel"] = bool(torch.equal(fo, out_o))

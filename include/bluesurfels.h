@@ -92,7 +92,14 @@ typedef struct {
     int32_t picks;         /* grid kernel: most picks per round, 0 = auto, 1 = one pick
                               per round, 2..16 = several exact picks per round (same
                               result; see bs_order_ex) */
-    int32_t reserved[6];   /* must be zero */
+    int32_t lead_picks;    /* grid kernel with several picks per round: the first picks
+                              come from the cooperative full scan over all CUs, which
+                              then hands every candidate's distance to the grid kernel
+                              (same result).  0 = auto (n / 1024 picks from n >= 2^18
+                              candidates when a cooperative scan holds n), -1 = none,
+                              >= 2 = that many (capped at k; BS_ERR_UNSUPPORTED if no
+                              cooperative scan holds n) */
+    int32_t reserved[5];   /* must be zero */
 } bs_tuning;
 
 /* ------------------------------------------------------- single instance */
@@ -165,6 +172,18 @@ int64_t bs_start_index(uint64_t seed, int64_t n);
 
 /* Which kernel the automatic choice uses for (n, k) (a bs_kernel value). */
 int bs_auto_kernel(int64_t n, int64_t k);
+
+/*
+ * The plan bs_order_ex follows for (n, k, tuning), every automatic choice
+ * resolved into *out: kernel; for the resident kernels block, per_thread and
+ * groups; for the grid kernel block, cell_points, picks and lead_picks (-1
+ * when no leading scan runs), and with a leading scan per_thread and groups
+ * of that cooperative scan (1024-thread workgroups).  A NULL tuning takes the
+ * autotuner's table entry as bs_order does.  Reads no device memory.
+ * Errors: BS_ERR_INVALID_ARG (null out, bad sizes or tuning),
+ * BS_ERR_UNSUPPORTED (no kernel for this size and tuning).
+ */
+int bs_plan_describe(int64_t n, int64_t k, const bs_tuning* tuning, bs_tuning* out);
 
 /* ------------------------------------------------------------ autotuner */
 

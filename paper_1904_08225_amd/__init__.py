@@ -47,12 +47,12 @@ class Tuning(ctypes.Structure):
     _fields_ = [("kernel", ctypes.c_int32), ("block", ctypes.c_int32),
                 ("per_thread", ctypes.c_int32), ("groups", ctypes.c_int32),
                 ("cell_points", ctypes.c_float), ("picks", ctypes.c_int32),
-                ("reserved", ctypes.c_int32 * 6)]
+                ("lead_picks", ctypes.c_int32), ("reserved", ctypes.c_int32 * 5)]
 
 
 def tuning(kernel: int = 0, block: int = 0, per_thread: int = 0, groups: int = 0,
-           cell_points: float = 0.0, picks: int = 0) -> Tuning:
-    return Tuning(kernel, block, per_thread, groups, cell_points, picks)
+           cell_points: float = 0.0, picks: int = 0, lead_picks: int = 0) -> Tuning:
+    return Tuning(kernel, block, per_thread, groups, cell_points, picks, lead_picks)
 
 
 def header_functions():
@@ -82,6 +82,8 @@ def load():
     lib.bs_start_index.restype = i64
     lib.bs_auto_kernel.argtypes = [i64, i64]
     lib.bs_auto_kernel.restype = i32
+    lib.bs_plan_describe.argtypes = [i64, i64, vp, vp]
+    lib.bs_plan_describe.restype = i32
     lib.bs_autotune.argtypes = [vp, i64, i64, u64, tp, vp]
     lib.bs_autotune.restype = i32
     lib.bs_autotune_lookup.argtypes = [i64, i64, tp]
@@ -149,6 +151,14 @@ def start_index(seed: int, n: int) -> int:
 
 def auto_kernel(n: int, k: int) -> int:
     return int(load().bs_auto_kernel(n, k))
+
+
+def plan_describe(n: int, k: int, tune: Optional[Tuning] = None) -> Tuning:
+    """The plan ``order`` follows for (n, k, tune), automatic choices resolved
+    (``bs_plan_describe``)."""
+    out = Tuning()
+    _check(load().bs_plan_describe(n, k, ctypes.byref(tune) if tune is not None else None, ctypes.byref(out)))
+    return out
 
 
 def autotune(points, k: int, seed: int = 0, stream=None) -> Tuning:

@@ -41,12 +41,18 @@ bool tuning_clean(const bs_tuning* t) {
     for (int r : t->reserved)
         if (r != 0) return false;
     if (t->picks < 0 || t->picks > kMaxGridPicks) return false;
+    if (t->lead_picks < -1) return false;
     return t->kernel >= BS_KERNEL_AUTO && t->kernel <= BS_KERNEL_GRID;
 }
 
 constexpr float kDefaultCellPoints = 32.f;       // one pick per round
 constexpr float kDefaultCellPointsMulti = 8.f;   // several picks per round
 constexpr int64_t kAutoResidentMax = 16384;  // one workgroup holds these in VGPRs
+// Automatic leading full scan of the grid kernel: from this many candidates,
+// for the first n / kAutoLeadDiv picks (while a pick's covering ball still
+// holds many candidates, a step over all CUs beats one workgroup's pruned step).
+constexpr int64_t kAutoLeadMinN = int64_t(1) << 18;
+constexpr int64_t kAutoLeadDiv = 1024;
 
 struct Plan {
     int kernel = 0;
@@ -54,6 +60,8 @@ struct Plan {
     int grid_block = 0;  // grid kernel workgroup size
     int grid_picks = kDefaultGridPicks;
     float cell_points = kDefaultCellPoints;
+    int lead = 0;          // picks made by a leading cooperative full scan (0: none)
+    ScanShape lead_shape;  // its launch shape
 };
 
 // Resolve the kernel and its launch shape.
@@ -63,7 +71,6 @@ int plan_single(int64_t n, int64_t k, const bs_tuning* t, Plan* p) {
     const int cus = device_cus() > 0 ? device_cus() : 256;
     const int want = t ? t->kernel : BS_KERNEL_AUTO;
     const int wb = t ? t->block : 0, wp = t ? t->per_thread : 0, wg = t ? t->groups : 0;
-    (void)k;
     if (want == BS_KERNEL_GRID || (want == BS_KERNEL_AUTO && n > kAutoResidentMax)) {
         p->grid_picks = (t && t->picks > 0) ? t->picks : kDefaultGridPicks;
         const bool multi = p->grid_picks > 1;
@@ -76,6 +83,18 @@ int plan_single(int64_t n, int64_t k, const bs_tuning* t, Plan* p) {
         p->cell_points = (t && t->cell_points > 0.f) ? t->cell_points
                                                       : (multi ? kDefaultCellPointsMulti : kDefaultCellPoints);
         if (p->cell_points < 1.f) p->cell_points = 1.f;
+        // leading full scan (several-picks kernel only; needs a cooperative shape)
+        const int lp = t ? t->lead_picks : 0;
+        int64_t lead = 0;
+        if (lp > 0) lead = lp;
+        else if (lp == 0 && n >= kAutoLeadMinN) lead = n / kAutoLeadDiv;
+        if (lead > k) lead = k;
+        if (multi && lead >= 2 && choose_scan_shape(n, cus, 0, 0, 0, &p->lead_shape) &&
+            p->lead_shape.groups > 1) {
+            p->lead = int(lead);
+        } else if (lp > 1 && multi) {
+            return set_error(BS_ERR_UNSUPPORTED, "no cooperative scan holds n=%lld for lead_picks", (long long)n);
+        }
         return BS_OK;
     }
     if (want == BS_KERNEL_AUTO) {
@@ -156,6 +175,36 @@ int bs_auto_kernel(int64_t n, int64_t k) {
     return p.kernel;
 }
 
+int bs_plan_describe(int64_t n, int64_t k, const bs_tuning* tuning, bs_tuning* out) {
+    if (!out) return set_error(BS_ERR_INVALID_ARG, "null output");
+    if (n < 1 || n >= (int64_t(1) << 31) || k < 0 || k > n)
+        return set_error(BS_ERR_INVALID_ARG, "n=%lld k=%lld outside 1 <= n < 2^31, 0 <= k <= n", (long long)n,
+                         (long long)k);
+    if (!tuning_clean(tuning)) return set_error(BS_ERR_INVALID_ARG, "bad tuning struct");
+    Plan p;
+    const int rc = plan_single(n, k, tuning, &p);
+    if (rc != BS_OK) return rc;
+    bs_tuning d;
+    memset(&d, 0, sizeof(d));
+    d.kernel = p.kernel;
+    if (p.kernel == BS_KERNEL_GRID) {
+        d.block = p.grid_block;
+        d.cell_points = p.cell_points;
+        d.picks = p.grid_picks;
+        d.lead_picks = p.lead > 0 ? p.lead : -1;
+        if (p.lead > 0) {
+            d.per_thread = p.lead_shape.per_thread;
+            d.groups = p.lead_shape.groups;
+        }
+    } else {
+        d.block = p.shape.block;
+        d.per_thread = p.shape.per_thread;
+        d.groups = p.shape.groups;
+    }
+    *out = d;
+    return BS_OK;
+}
+
 size_t bs_workspace_size(int64_t n, int64_t k, const bs_tuning* tuning) {
     if (n < 1 || n >= (int64_t(1) << 31) || k < 0 || k > n || !tuning_clean(tuning)) return 0;
     Plan p;
@@ -191,7 +240,8 @@ static int order_impl(const float* d_points, int64_t n, int64_t k, uint64_t seed
     hipError_t e = hipSuccess;
     if (plan.kernel == BS_KERNEL_GRID) {
         e = launch_grid(d_points, int(n), int(k), int(start), d_out_order, d_out_radius, d_workspace,
-                        plan.cell_points, plan.grid_block, plan.grid_picks, d_ticks, st, ev);
+                        plan.cell_points, plan.grid_block, plan.grid_picks, d_ticks, st, ev, plan.lead,
+                        plan.lead > 0 ? &plan.lead_shape : nullptr);
     } else {
         DevHeader* hdr = reinterpret_cast<DevHeader*>(d_workspace);
         void* scratch = static_cast<char*>(d_workspace) + align_up(sizeof(DevHeader));

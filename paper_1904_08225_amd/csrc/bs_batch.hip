@@ -353,6 +353,7 @@ __global__ void bblocks_kernel(int m, const ObjHdr* __restrict__ hd, const int32
     const int cb = hd[j].cell_base, C = hd[j].C;
     float lx = INFINITY, ly = INFINITY, lz = INFINITY, hx = -INFINITY, hy = -INFINITY, hz = -INFINITY;
     uint64_t best = 0;
+    uint32_t other = 0;  // value bits of the best key of the cells other than the best one
     int bc = lb * 64;
     for (int c = lb * 64; c < C && c < (lb + 1) * 64; ++c) {
         const size_t g = size_t(cb) + c;
@@ -366,16 +367,20 @@ __global__ void bblocks_kernel(int m, const ObjHdr* __restrict__ hd, const int32
         const uint4 d = cdyn[2 * g];
         const uint64_t key = (uint64_t(d.y) << 32) | d.x;
         if (key > best) {
+            if (best) other = max(other, uint32_t(best >> 32));
             best = key;
             bc = c;
+        } else {
+            other = max(other, d.y);
         }
     }
     bstat[2 * size_t(b) + 0] = make_float4(lx, ly, lz, 0.f);
     bstat[2 * size_t(b) + 1] = make_float4(hx, hy, hz, 0.f);
     const size_t g = size_t(cb) + bc;
     const uint4 d0 = cdyn[2 * g], d1 = cdyn[2 * g + 1];
+    // last word: value bits of a bound on the block's other keys
     bdyn[2 * size_t(b) + 0] = make_uint4(d0.x, d0.y, d0.z, uint32_t(bc));
-    bdyn[2 * size_t(b) + 1] = d1;
+    bdyn[2 * size_t(b) + 1] = make_uint4(d1.x, d1.y, d1.z, max(other, d1.w));
 }
 
 __global__ void bsuper_kernel(int m, const ObjHdr* __restrict__ hd, const int32_t* __restrict__ totals,
@@ -450,6 +455,8 @@ __global__ void bdesc_kernel(int m, const ObjHdr* __restrict__ hd, const int32_t
     }
     o.ticks = nullptr;
     o.max_picks = kMaxPicks;
+    o.t0 = 0;
+    o.start_m = INFINITY;
     d.nonfinite = int(h.nonfinite);
     desc[j] = d;
 }

@@ -16,7 +16,9 @@ struct GridHeader {
     int32_t NB;          // blocks (<= workgroup size)
     int32_t start_pos;   // sorted position of the start candidate
     int32_t start_cell;  // its cell
-    int32_t pad[46];
+    uint32_t lead_id;    // after a leading full scan: its last pick (original index)
+    uint32_t lead_m;     // and the bits of that pick's m
+    int32_t pad[44];
 };
 static_assert(sizeof(GridHeader) == 256, "grid header size");
 
@@ -37,12 +39,15 @@ struct GridObject {
     float* radius;
     uint64_t* ticks;           // optional: device wall clock after each step
     int max_picks;             // several-picks-per-round kernel: picks per round (<= 16)
+    int t0;                    // index of the start pick in the order (0, or the picks a
+                               // leading full scan made minus one)
+    float start_m;             // m of the start pick (+inf, or its value after a leading scan)
 };
 
 // Byte offsets of the grid workspace pieces.
 struct GridLayout {
     size_t dev_header, grid_header, codes, vals, codes_sorted, ids, flags, cellidx, cstart, xyzm,
-        cstat, cdyn, bstat, bdyn, sbstat, temp;
+        cstat, cdyn, bstat, bdyn, sbstat, lead_slots, temp;
     size_t temp_bytes;
     size_t total;
 };
@@ -53,8 +58,13 @@ int grid_block_size(int64_t n);
 // > 1 selects the several-picks-per-round kernel (at most `picks` per round).
 int grid_max_blocks(int block, int picks);
 struct KernelEvents;
+// lead >= 2 (several-picks kernel only): picks 0 .. lead-1 come from the
+// cooperative full scan of shape *lead_shape, which hands its state to the
+// grid kernel; otherwise the grid kernel makes every pick.
+struct ScanShape;
 hipError_t launch_grid(const float* pts, int n, int k, int start, int32_t* order, float* radius,
                        void* ws, float target, int block, int picks, uint64_t* ticks,
-                       hipStream_t st, const KernelEvents* ev = nullptr);
+                       hipStream_t st, const KernelEvents* ev = nullptr, int lead = 0,
+                       const ScanShape* lead_shape = nullptr);
 
 }  // namespace bs

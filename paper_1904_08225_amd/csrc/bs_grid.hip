@@ -108,15 +108,18 @@ __global__ void cell_flag_kernel(const uint32_t* __restrict__ codes, int n, cons
     flags[i] = (i == 0 || (codes[i] >> s) != (codes[i - 1] >> s)) ? 1u : 0u;
 }
 
+// m_in: NULL (every m = +inf) or each candidate's m left by a leading scan,
+// whose last pick (gh->lead_id) is then the start.
 __global__ void gather_kernel(const float* __restrict__ pts, const uint32_t* __restrict__ ids,
                               const uint32_t* __restrict__ flags,
                               const uint32_t* __restrict__ cellidx, int n, int start,
                               GridHeader* gh, float4* __restrict__ xyzm,
-                              int32_t* __restrict__ cstart) {
+                              int32_t* __restrict__ cstart, const float* __restrict__ m_in) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
     const uint32_t id = ids[i];
-    xyzm[i] = make_float4(pts[3 * id + 0], pts[3 * id + 1], pts[3 * id + 2], INFINITY);
+    if (m_in) start = int(gh->lead_id);
+    xyzm[i] = make_float4(pts[3 * id + 0], pts[3 * id + 1], pts[3 * id + 2], m_in ? m_in[id] : INFINITY);
     const int cell = int(cellidx[i]) - 1;
     if (flags[i]) cstart[cell] = i;
     if (int(id) == start) {
@@ -125,8 +128,8 @@ __global__ void gather_kernel(const float* __restrict__ pts, const uint32_t* __r
     }
 }
 
-// One thread per cell: exact member box, start/count, initial best (all m = +inf:
-// the lowest original index wins).
+// One thread per cell: exact member box, start/count, best and second key
+// of the members' m (chosen candidates, m = -1, have none).
 __global__ void cell_build_kernel(const int32_t* __restrict__ cstart, int n,
                                   const GridHeader* gh, const float4* __restrict__ xyzm,
                                   const uint32_t* __restrict__ ids, float4* __restrict__ cstat,
@@ -138,7 +141,7 @@ __global__ void cell_build_kernel(const int32_t* __restrict__ cstart, int n,
     const int e = (c + 1 < C) ? cstart[c + 1] : n;
     float lx = INFINITY, ly = INFINITY, lz = INFINITY, hx = -INFINITY, hy = -INFINITY,
           hz = -INFINITY;
-    uint32_t best_id = 0xFFFFFFFFu;
+    uint64_t key = 0, sec = 0;
     int best_pos = s;
     for (int i = s; i < e; ++i) {
         const float4 p = xyzm[i];
@@ -148,23 +151,27 @@ __global__ void cell_build_kernel(const int32_t* __restrict__ cstart, int n,
         hx = fmaxf(hx, p.x);
         hy = fmaxf(hy, p.y);
         hz = fmaxf(hz, p.z);
-        if (ids[i] < best_id) {
-            best_id = ids[i];
+        const uint64_t kk = p.w >= 0.f ? make_key(p.w, ids[i]) : 0ull;
+        if (kk > key) {
+            sec = key;
+            key = kk;
             best_pos = i;
+        } else if (kk > sec) {
+            sec = kk;
         }
     }
     cstat[2 * c + 0] = make_float4(lx, ly, lz, __int_as_float(s));
     cstat[2 * c + 1] = make_float4(hx, hy, hz, __int_as_float(e - s));
-    const uint64_t key = make_key(INFINITY, best_id);
     const float4 w = xyzm[best_pos];
-    // second key slot (w words): a bound on the cell's other keys; the best
-    // key itself is one until the cell is first updated
-    cdyn[2 * c + 0] = make_uint4(uint32_t(key), uint32_t(key >> 32), uint32_t(best_pos), uint32_t(key));
+    // second key slot (w words): the cell's second key
+    cdyn[2 * c + 0] = make_uint4(uint32_t(key), uint32_t(key >> 32), uint32_t(best_pos), uint32_t(sec));
     cdyn[2 * c + 1] = make_uint4(__float_as_uint(w.x), __float_as_uint(w.y), __float_as_uint(w.z),
-                                 uint32_t(key >> 32));
+                                 uint32_t(sec >> 32));
 }
 
-// One thread per block: union box and best over its cells.
+// One thread per block: union box, best over its cells, and in the last word
+// the value bits of a bound on the block's other keys (the best cell's second
+// key and the other cells' best keys).
 __global__ void block_build_kernel(const GridHeader* gh, const float4* __restrict__ cstat,
                                    const uint4* __restrict__ cdyn, float4* __restrict__ bstat,
                                    uint4* __restrict__ bdyn) {
@@ -174,6 +181,7 @@ __global__ void block_build_kernel(const GridHeader* gh, const float4* __restric
     float lx = INFINITY, ly = INFINITY, lz = INFINITY, hx = -INFINITY, hy = -INFINITY,
           hz = -INFINITY;
     uint64_t best = 0;
+    uint32_t other = 0;  // value bits of the best key among the cells that are not the best cell
     int bc = b * B;
     for (int c = b * B; c < C && c < (b + 1) * B; ++c) {
         const float4 lo = cstat[2 * c], hi = cstat[2 * c + 1];
@@ -186,15 +194,18 @@ __global__ void block_build_kernel(const GridHeader* gh, const float4* __restric
         const uint4 d = cdyn[2 * c];
         const uint64_t key = (uint64_t(d.y) << 32) | d.x;
         if (key > best) {
+            if (best) other = max(other, uint32_t(best >> 32));
             best = key;
             bc = c;
+        } else {
+            other = max(other, d.y);
         }
     }
     bstat[2 * b + 0] = make_float4(lx, ly, lz, 0.f);
     bstat[2 * b + 1] = make_float4(hx, hy, hz, 0.f);
     const uint4 d0 = cdyn[2 * bc], d1 = cdyn[2 * bc + 1];
     bdyn[2 * b + 0] = make_uint4(d0.x, d0.y, d0.z, uint32_t(bc));
-    bdyn[2 * b + 1] = d1;
+    bdyn[2 * b + 1] = make_uint4(d1.x, d1.y, d1.z, max(other, d1.w));
 }
 
 // One thread per superblock (64 consecutive blocks): union box.
@@ -256,11 +267,16 @@ __global__ void __launch_bounds__(BLOCK) grid_multi_kernel(GridObject o, const D
         }
         return;
     }
+    if (hdr->error) return;  // a leading scan gave up: its state is incomplete
     obj.C = gh->C;
     obj.B = gh->B;
     obj.NB = gh->NB;
     obj.start_pos = gh->start_pos;
     obj.start_cell = gh->start_cell;
+    if (o.t0 > 0) {
+        obj.start_id = gh->lead_id;
+        obj.start_m = __uint_as_float(gh->lead_m);
+    }
     grid_order_object_mp<BLOCK, MAXB>(obj, L);
 }
 
@@ -293,6 +309,7 @@ GridLayout grid_layout(int64_t n, int block) {
     g.bstat = take(size_t(kMaxBlocksAny) * 32);
     g.bdyn = take(size_t(kMaxBlocksAny) * 32);
     g.sbstat = take(size_t(kMaxBlocksAny / 64) * 32);
+    g.lead_slots = take(scan_slot_bytes(kMaxCoopGroups));
     size_t sort_bytes = 0, scan_bytes = 0;
     hipcub::DeviceRadixSort::SortPairs(nullptr, sort_bytes, (const uint32_t*)nullptr, (uint32_t*)nullptr,
                                        (const uint32_t*)nullptr, (uint32_t*)nullptr, int(n), 0,
@@ -314,7 +331,9 @@ int grid_max_blocks(int block, int picks) {
 
 hipError_t launch_grid(const float* pts, int n, int k, int start, int32_t* order, float* radius,
                        void* ws, float target, int block, int picks, uint64_t* ticks,
-                       hipStream_t st, const KernelEvents* ev) {
+                       hipStream_t st, const KernelEvents* ev, int lead, const ScanShape* lead_shape) {
+    if (picks <= 1 || !lead_shape || lead < 2) lead = 0;
+    if (lead > k) lead = k;
     const GridLayout g = grid_layout(n, block);
     char* base = static_cast<char*>(ws);
     DevHeader* hdr = reinterpret_cast<DevHeader*>(base + g.dev_header);
@@ -356,8 +375,17 @@ hipError_t launch_grid(const float* pts, int n, int k, int start, int32_t* order
     tbytes = g.temp_bytes;
     e = hipcub::DeviceScan::InclusiveSum(temp, tbytes, flags, cellidx, n, st);
     if (e != hipSuccess) return e;
+    float* m_lead = nullptr;
+    if (lead >= 2) {
+        // picks 0 .. lead-1 by the cooperative full scan; its m values land in
+        // the (now unused) unsorted Morton codes, its last pick in the header
+        m_lead = reinterpret_cast<float*>(codes);
+        e = launch_scan(*lead_shape, pts, n, k, start, order, radius, hdr, base + g.lead_slots, ticks, st,
+                        nullptr, lead, m_lead, &gh->lead_id);
+        if (e != hipSuccess) return e;
+    }
     hipLaunchKernelGGL(gather_kernel, dim3(nblk), dim3(tb), 0, st, pts, ids, flags, cellidx, n, start,
-                       gh, xyzm, cstart);
+                       gh, xyzm, cstart, m_lead);
     hipLaunchKernelGGL(cell_build_kernel, dim3(nblk), dim3(tb), 0, st, cstart, n, gh, xyzm, ids, cstat,
                        cdyn);
     hipLaunchKernelGGL(block_build_kernel, dim3((kMaxBlocksAny + tb - 1) / tb), dim3(tb), 0, st, gh,
@@ -379,6 +407,8 @@ hipError_t launch_grid(const float* pts, int n, int k, int start, int32_t* order
     o.radius = radius;
     o.ticks = ticks;
     o.max_picks = picks < kMaxPicks ? picks : kMaxPicks;
+    o.t0 = lead >= 2 ? lead - 1 : 0;
+    o.start_m = INFINITY;
     if (ev && ev->begin && (e = hipEventRecord(ev->begin, st)) != hipSuccess) return e;
     if (picks > 1) {
         if (block == 512)

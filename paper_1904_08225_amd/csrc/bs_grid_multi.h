@@ -646,8 +646,8 @@ __device__ inline void grid_order_object_mp(const GridObject& o, GridLdsMP<BLOCK
 
     float blx[BPT], bly[BPT], blz[BPT], bhx[BPT], bhy[BPT], bhz[BPT];
     // block entries start from the grid build (best key, its coordinates and
-    // cell; the key's own value bounds the block's other keys): a block that
-    // no pick ever reaches keeps them
+    // cell, and a bound on the block's other keys): a block that no pick ever
+    // reaches keeps them
 #pragma unroll
     for (int j = 0; j < BPT; ++j) {
         const int b = j * BLOCK + tid;
@@ -658,7 +658,7 @@ __device__ inline void grid_order_object_mp(const GridObject& o, GridLdsMP<BLOCK
             const uint4 d0 = o.bdyn[2 * b], d1 = o.bdyn[2 * b + 1];
             const uint64_t key = (uint64_t(d0.y) << 32) | d0.x;
             L.bkey[b] = key;
-            L.bsec[b] = uint32_t(key >> 32);
+            L.bsec[b] = d1.w;
             L.bwin[b] = make_float4(__uint_as_float(d1.x), __uint_as_float(d1.y), __uint_as_float(d1.z),
                                     __int_as_float(int(d0.z)));
             L.bcell[b] = int(d0.w);
@@ -685,13 +685,17 @@ __device__ inline void grid_order_object_mp(const GridObject& o, GridLdsMP<BLOCK
         L.sbhi[lane] = make_float4(shx, shy, shz, 0.f);
         L.spm[lane] = lane < nsb ? 1u : 0u;  // the start reaches every superblock
         if (lane == 0) {
+            // the start pick: pick 0, or the last pick of a leading scan
+            // (already emitted; its update is this kernel's first round)
             const float4 sp = load_vec(o.xyzm + o.start_pos);
-            o.order[0] = int32_t(o.start_id);
-            if (o.radius) o.radius[0] = INFINITY;
+            if (o.t0 == 0) {
+                o.order[0] = int32_t(o.start_id);
+                if (o.radius) o.radius[0] = INFINITY;
 #ifndef BS_PHASE_PROF
-            if (o.ticks) o.ticks[0] = wall_clock64();
+                if (o.ticks) o.ticks[0] = wall_clock64();
 #endif
-            L.pk[0] = make_float4(sp.x, sp.y, sp.z, INFINITY);
+            }
+            L.pk[0] = make_float4(sp.x, sp.y, sp.z, o.start_m);
             L.pkpos[0] = o.start_pos;
             L.pkcell[0] = o.start_cell;
             L.npicks = 1;
@@ -704,7 +708,7 @@ __device__ inline void grid_order_object_mp(const GridObject& o, GridLdsMP<BLOCK
     for (int sb = wave; sb < nsb; sb += NW) superblock_refresh(L, sb, sbshift, NB);
     __syncthreads();
 
-    int t = 1;
+    int t = o.t0 + 1;
     int round_no = 0;
     (void)round_no;
     while (true) {
@@ -920,20 +924,43 @@ __device__ inline void grid_order_object_mp(const GridObject& o, GridLdsMP<BLOCK
             // candidate j follows i < j unless i lowers it or i's superblock
             // may hold a larger key: all pairs (j, i) at once, 16 per j
             uint32_t failj = 0;  // bit j: some i < j stops candidate j
+#ifdef BS_PHASE_PROF
+            uint32_t faild = 0, fails = 0;
+#endif
             for (int q = 0; q < (nv + 3) / 4; ++q) {
                 const int jj = q * 4 + (lane >> 4), ii = lane & 15;
                 bool f = false;
+#ifdef BS_PHASE_PROF
+                bool fd = false, fs = false;
+#endif
                 if (ii < jj && jj < nv) {
                     const float4 cj = L.cand[jj], ci = L.cand[ii];
                     f = dist2(cj.x, cj.y, cj.z, ci.x, ci.y, ci.z) < cj.w ||
                         __float_as_uint(cj.w) <= L.candsec[ii];
+#ifdef BS_PHASE_PROF
+                    fd = dist2(cj.x, cj.y, cj.z, ci.x, ci.y, ci.z) < cj.w;
+                    fs = __float_as_uint(cj.w) <= L.candsec[ii];
+#endif
                 }
                 const uint64_t fb = __ballot(f);
                 for (int g = 0; g < 4; ++g)
                     failj |= ((fb >> (16 * g)) & 0xFFFFull) ? (1u << (q * 4 + g)) : 0u;
+#ifdef BS_PHASE_PROF
+                const uint64_t fdb = __ballot(fd), fsb = __ballot(fs);
+                for (int g = 0; g < 4; ++g) {
+                    faild |= ((fdb >> (16 * g)) & 0xFFFFull) ? (1u << (q * 4 + g)) : 0u;
+                    fails |= ((fsb >> (16 * g)) & 0xFFFFull) ? (1u << (q * 4 + g)) : 0u;
+                }
+#endif
             }
             BS_MPROF(12, wall_clock64());
             const int Kn = nv > 0 ? min(nv, int(__builtin_ctz(failj | 0x80000000u))) : 0;
+#ifdef BS_PHASE_PROF
+            // candidates, filter count, and the first rejection's causes
+            BS_MPROF(21, uint64_t(nv) | (uint64_t(__popcll(candm)) << 8) |
+                             (uint64_t((faild >> Kn) & 1u) << 16) | (uint64_t((fails >> Kn) & 1u) << 17) |
+                             (uint64_t(nsb) << 24));
+#endif
             if (WAVE0_SBTEST) L.spm[lane] = superblock_picks(L, nsb, sbshift, Kn, cw.x, cw.y, cw.z, cm, cc);
             if (lane < Kn) {
                 o.order[t + lane] = int32_t(key_id(ck));

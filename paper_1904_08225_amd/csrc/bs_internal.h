@@ -41,6 +41,8 @@ bool scan_shape_supported(int block, int per_thread);
 bool choose_scan_shape(int64_t n, int cus, int want_block, int want_pt, int want_groups,
                        ScanShape* out);
 size_t scan_workspace_bytes(const ScanShape& s);
+// Exchange records of a cooperative scan of `groups` workgroups.
+size_t scan_slot_bytes(int groups);
 
 // Kernel launchers (bs_scan.hip).  All return hipError_t of the launch.
 hipError_t launch_init_header(DevHeader* hdr, hipStream_t st);
@@ -52,9 +54,12 @@ struct KernelEvents {
     hipEvent_t end = nullptr;
 };
 
+// Picks 0 .. k_stop-1 (k_stop < 0: all k); with m_out / handoff the scan
+// leaves its state for a following kernel (see scan_kernel).
 hipError_t launch_scan(const ScanShape& s, const float* pts, int n, int k, int start,
                        int32_t* order, float* radius, DevHeader* hdr, void* scratch,
-                       uint64_t* ticks, hipStream_t st, const KernelEvents* ev = nullptr);
+                       uint64_t* ticks, hipStream_t st, const KernelEvents* ev = nullptr,
+                       int k_stop = -1, float* m_out = nullptr, uint32_t* handoff = nullptr);
 
 // Batched plans (bs_batch.hip).
 struct BatchPlan;

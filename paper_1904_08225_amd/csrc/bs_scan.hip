@@ -170,12 +170,18 @@ __global__ void validate_kernel(const float* __restrict__ pts, int64_t n, DevHea
 
 // Persistent resident scan.  Workgroup g owns candidates
 // [g*BLOCK*P, (g+1)*BLOCK*P); thread `tid` owns g*BLOCK*P + j*BLOCK + tid.
+// It makes picks 0 .. k_stop-1 of a k-pick ordering.  With k_stop < k it
+// hands the ordering over: m_out[i] receives every candidate's m after the
+// updates of picks 0 .. k_stop-2 (-1 for chosen ones, pick k_stop-1
+// included), and handoff[0], handoff[1] the last pick's index and the bits
+// of its m (its update is left to the next kernel).
 template <int BLOCK, int P, bool MULTI>
 __global__ void __launch_bounds__(BLOCK)
     scan_kernel(const float* __restrict__ pts, int n, int k, int start,
                 int32_t* __restrict__ order, float* __restrict__ radius,
                 DevHeader* __restrict__ hdr, uint64_t* __restrict__ slots,
-                uint64_t* __restrict__ ticks) {
+                uint64_t* __restrict__ ticks, int k_stop, float* __restrict__ m_out,
+                uint32_t* __restrict__ handoff) {
     constexpr int NW = BLOCK / 64;
     __shared__ uint64_t s_key[2][NW];
     __shared__ float s_pos[2][NW][4];
@@ -229,7 +235,8 @@ __global__ void __launch_bounds__(BLOCK)
     if (tid == 0) s_abort = 0;
     __syncthreads();
 
-    for (int t = 1; t < k; ++t) {
+    float cm = INFINITY;  // m of the latest pick
+    for (int t = 1; t < k_stop; ++t) {
         const int buf = t & 1;
         // fused update + thread-local argmax
         float bv = -1.f, bx = 0.f, by = 0.f, bz = 0.f;
@@ -337,6 +344,7 @@ __global__ void __launch_bounds__(BLOCK)
         }
 
         c = int(key_index(best));
+        cm = key_value(best);
         cx = ncx;
         cy = ncy;
         cz = ncz;
@@ -355,10 +363,21 @@ __global__ void __launch_bounds__(BLOCK)
             if (ticks) ticks[t] = wall_clock64();
         }
     }
+    if (m_out) {
+#pragma unroll
+        for (int j = 0; j < P; ++j) {
+            const int i = base + j * BLOCK + tid;
+            if (i < n) m_out[i] = m[j];
+        }
+    }
+    if (handoff && g == 0 && tid == 0) {
+        handoff[0] = uint32_t(c);
+        handoff[1] = __float_as_uint(cm);
+    }
 }
 
 using ScanFn = void (*)(const float*, int, int, int, int32_t*, float*, DevHeader*, uint64_t*,
-                       uint64_t*);
+                       uint64_t*, int, float*, uint32_t*);
 
 struct ScanEntry {
     int block, per_thread;
@@ -424,10 +443,9 @@ bool choose_scan_shape(int64_t n, int cus, int want_block, int want_pt, int want
     return false;
 }
 
-size_t scan_workspace_bytes(const ScanShape& s) {
-    return align_up(sizeof(DevHeader)) +
-           align_up(size_t(2) * size_t(s.groups > 0 ? s.groups : 1) * kRecWords * 8);
-}
+size_t scan_slot_bytes(int groups) { return align_up(size_t(2) * size_t(groups > 0 ? groups : 1) * kRecWords * 8); }
+
+size_t scan_workspace_bytes(const ScanShape& s) { return align_up(sizeof(DevHeader)) + scan_slot_bytes(s.groups); }
 
 hipError_t launch_init_header(DevHeader* hdr, hipStream_t st) {
     hipLaunchKernelGGL(init_header_kernel, dim3(1), dim3(64), 0, st, hdr);
@@ -444,22 +462,25 @@ hipError_t launch_validate(const float* pts, int64_t n, DevHeader* hdr, hipStrea
 
 hipError_t launch_scan(const ScanShape& s, const float* pts, int n, int k, int start,
                        int32_t* order, float* radius, DevHeader* hdr, void* scratch,
-                       uint64_t* ticks, hipStream_t st, const KernelEvents* ev) {
+                       uint64_t* ticks, hipStream_t st, const KernelEvents* ev, int k_stop,
+                       float* m_out, uint32_t* handoff) {
     const ScanEntry* e = find_entry(s.block, s.per_thread);
     if (!e) return hipErrorInvalidValue;
+    if (k_stop < 0 || k_stop > k) k_stop = k;
     uint64_t* slots = reinterpret_cast<uint64_t*>(scratch);
     hipError_t err = hipSuccess;
     if (s.groups <= 1) {
         if (ev && ev->begin && (err = hipEventRecord(ev->begin, st)) != hipSuccess) return err;
         hipLaunchKernelGGL(e->single, dim3(1), dim3(s.block), 0, st, pts, n, k, start, order,
-                           radius, hdr, slots, ticks);
+                           radius, hdr, slots, ticks, k_stop, m_out, handoff);
     } else {
         // stale records from an earlier call must not carry matching tags
         hipLaunchKernelGGL(clear_slots_kernel, dim3(1), dim3(256), 0, st, slots, 2 * s.groups * kRecWords);
         if ((err = hipGetLastError()) != hipSuccess) return err;
         if (ev && ev->begin && (err = hipEventRecord(ev->begin, st)) != hipSuccess) return err;
-        void* args[] = {(void*)&pts,   (void*)&n,   (void*)&k,     (void*)&start, (void*)&order,
-                        (void*)&radius, (void*)&hdr, (void*)&slots, (void*)&ticks};
+        void* args[] = {(void*)&pts,   (void*)&n,     (void*)&k,      (void*)&start,
+                        (void*)&order, (void*)&radius, (void*)&hdr,   (void*)&slots,
+                        (void*)&ticks, (void*)&k_stop, (void*)&m_out, (void*)&handoff};
         err = hipLaunchCooperativeKernel(reinterpret_cast<const void*>(e->multi), dim3(s.groups),
                                          dim3(s.block), args, 0, st);
     }

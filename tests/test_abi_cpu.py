@@ -95,3 +95,38 @@ def test_autotune_validation_without_device(lib):
     bad = bs.tuning(kernel=3, picks=17)
     assert lib.bs_workspace_size(1000, 10, ctypes.byref(bad)) == 0
     assert lib.bs_workspace_size(1000, 10, ctypes.byref(bs.tuning(kernel=3, picks=16))) > 0
+
+
+def test_lead_picks_validation(lib):
+    """lead_picks: -1 (none) and 0 (auto) are accepted, below -1 rejected; an
+    explicit lead needs a cooperative scan that holds n (n = 10,000 fits one
+    workgroup, so no cooperative shape exists)."""
+    ws = lambda n, k, t: lib.bs_workspace_size(n, k, ctypes.byref(t))
+    assert ws(1000, 10, bs.tuning(kernel=3, picks=16, lead_picks=-2)) == 0
+    assert ws(1000, 10, bs.tuning(kernel=3, picks=16, lead_picks=-1)) > 0
+    assert ws(1000, 10, bs.tuning(kernel=3, picks=16, lead_picks=0)) > 0
+    assert ws(10000, 1000, bs.tuning(kernel=3, picks=16, lead_picks=100)) == 0
+    assert ws(100000, 1000, bs.tuning(kernel=3, picks=16, lead_picks=100)) > 0
+    # one pick per round ignores the lead
+    assert ws(10000, 1000, bs.tuning(kernel=3, picks=1, lead_picks=100)) > 0
+    # the struct keeps its size: 12 words
+    assert ctypes.sizeof(bs.Tuning) == 48
+
+
+def test_plan_describe(lib):
+    """Automatic choices resolved: the headline size takes the grid kernel
+    with 16 picks per round and a leading scan of n / 1024 picks (256
+    workgroups x 16 per thread); small sizes take the resident workgroup."""
+    lib.bs_autotune_clear()
+    p = bs.plan_describe(4194304, 262144)
+    assert (p.kernel, p.block, p.picks, p.lead_picks) == (bs.KERNEL_GRID, 1024, 16, 4096)
+    assert (p.per_thread, p.groups) == (16, 256)
+    p = bs.plan_describe(4194304, 262144, bs.tuning(kernel=3, picks=16, lead_picks=-1))
+    assert p.lead_picks == -1 and p.groups == 0
+    p = bs.plan_describe(4194304, 2000, bs.tuning(kernel=3, picks=16))
+    assert p.lead_picks == 2000  # capped at k
+    p = bs.plan_describe(10000, 100)
+    assert p.kernel == bs.KERNEL_WG and p.groups == 1
+    out = bs.Tuning()
+    assert lib.bs_plan_describe(10, 11, None, ctypes.byref(out)) == bs.BS_ERR_INVALID_ARG
+    assert lib.bs_plan_describe(10, 5, None, None) == bs.BS_ERR_INVALID_ARG

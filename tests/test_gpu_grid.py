@@ -120,3 +120,32 @@ def test_grid_overflowing_distances(hip, picks):
             o, r = run(hip, P, n // 3, start=5,
                        tune=hip.tuning(kernel=hip.KERNEL_GRID, block=block, picks=picks))
             assert_parity(o, r, eo, er, "huge n=%d block=%d picks=%d" % (n, block, picks))
+
+
+@pytest.mark.parametrize("name", ["random", "duplicates", "huge", "mixed_scale", "lattice"])
+def test_grid_lead_scan_handoff(hip, name):
+    """A leading cooperative full scan hands its distances to the grid kernel
+    after 2, 3, 100, k-1 or k picks: the same order and radii."""
+    n = 40000
+    P = cases.ADVERSARIAL[name](n, 900)
+    k = n // 2
+    eo, er = oracle.greedy32_grid(P, k, 13)
+    for lead in (2, 3, 100, k - 1, k):
+        for block in (512, 1024):
+            o, r = run(hip, P, k, start=13,
+                       tune=hip.tuning(kernel=hip.KERNEL_GRID, block=block, picks=16, lead_picks=lead))
+            assert_parity(o, r, eo, er, "%s lead=%d block=%d" % (name, lead, block))
+
+
+def test_grid_lead_scan_cad_part(hip):
+    """n = 300,000 (automatic lead of n / 1024 picks) and explicit leads, with
+    several read-ahead limits and cell sizes."""
+    n, k = 300000, 30000
+    P = synth.cad_part(n, seed=33).points.numpy()
+    eo, er = oracle.greedy32_grid(P, k, 101)
+    for lead, picks, block, cp in ((0, 16, 1024, 0.0), (5000, 16, 1024, 0.0), (700, 2, 512, 4.0),
+                                   (29999, 7, 256, 16.0), (-1, 16, 1024, 0.0), (3000, 1, 512, 0.0)):
+        o, r = run(hip, P, k, start=101,
+                   tune=hip.tuning(kernel=hip.KERNEL_GRID, block=block, picks=picks, cell_points=cp,
+                                   lead_picks=lead))
+        assert_parity(o, r, eo, er, "lead=%d picks=%d block=%d cells=%g" % (lead, picks, block, cp))
