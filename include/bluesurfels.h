@@ -90,7 +90,7 @@ typedef struct {
     int32_t groups;        /* workgroups of a cooperative launch (0 = auto) */
     float cell_points;     /* grid kernel: target mean candidates per cell (0 = auto) */
     int32_t picks;         /* grid kernel: most picks per round, 0 = auto, 1 = one pick
-                              per round, 2..16 = several exact picks per round (same
+                              per round, 2..32 = several exact picks per round (same
                               result; see bs_order_ex) */
     int32_t lead_picks;    /* grid kernel with several picks per round: the first picks
                               come from the cooperative full scan over all CUs, which

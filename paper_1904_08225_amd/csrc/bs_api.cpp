@@ -33,7 +33,7 @@ int device_cus() {
     return g_dev[dev].cus;
 }
 
-constexpr int kMaxGridPicks = 16;     // picks per round of the grid kernel
+constexpr int kMaxGridPicks = 32;     // picks per round of the grid kernel
 constexpr int kDefaultGridPicks = 16;
 
 bool tuning_clean(const bs_tuning* t) {

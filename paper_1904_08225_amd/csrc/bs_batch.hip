@@ -454,7 +454,7 @@ __global__ void bdesc_kernel(int m, const ObjHdr* __restrict__ hd, const int32_t
         d.done = nullptr;
     }
     o.ticks = nullptr;
-    o.max_picks = kMaxPicks;
+    o.max_picks = 16;
     o.t0 = 0;
     o.start_m = INFINITY;
     d.nonfinite = int(h.nonfinite);

@@ -38,7 +38,7 @@ struct GridObject {
     int32_t* order;
     float* radius;
     uint64_t* ticks;           // optional: device wall clock after each step
-    int max_picks;             // several-picks-per-round kernel: picks per round (<= 16)
+    int max_picks;             // several-picks-per-round kernel: picks per round (<= 32)
     int t0;                    // index of the start pick in the order (0, or the picks a
                                // leading full scan made minus one)
     float start_m;             // m of the start pick (+inf, or its value after a leading scan)

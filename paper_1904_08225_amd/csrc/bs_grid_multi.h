@@ -10,12 +10,15 @@
 //        i < j (then min(m, d2) = m, its key is unchanged), and
 //   (ii) every remaining candidate other than q_j has a key below q_j's
 //        before the round (then after the round too, since keys only drop).
-// (ii) is checked with second-best bounds: the hierarchy keeps, for every
-// superblock, its best key and a bound on all its other keys (the value bits
-// of its second largest key).  Walking the superblocks by descending best
-// key, q_j = best of the j-th superblock is accepted while (i) holds and its
-// value exceeds the bounds of the superblocks already used; the walk stops
-// at the first failure.  The round then applies all accepted picks at once:
+// (ii) is checked with bounds: every superblock offers two entries, the best
+// keys of its two best blocks, and keeps a bound R on all its other keys.
+// The candidates are the entries by descending key; q_j is accepted while
+// (i) holds and its value exceeds R of every superblock with an entry among
+// q_1 .. q_{j-1} (an entry of a superblock none of q_1 .. q_{j-1} came from
+// lies below q_j by the order itself); the walk stops at the first failure.
+// Every wavefront ranks a share of the candidates (two ballots per
+// candidate) and tests it against the higher-ranked ones; the accepted count
+// is the lowest failing rank.  The round then applies all accepted picks at once:
 // m_i <- min(m_i, d2(p_i, q_1), ..., d2(p_i, q_K)), which equals the
 // sequential updates because min is exact and order-free; a candidate or box
 // is skipped for pick q_j when its binary32 box lower bound is >= m(q_j),
@@ -24,7 +27,8 @@
 // Levels: cells keep their best key, its position/coordinates and their
 // exact second key (cdyn); blocks of 64 cells keep best key, coordinates,
 // cell and second-value bound in LDS; superblocks of SBS = 2^s blocks (at
-// most 64 superblocks, one per lane) keep best key, block and bound in LDS.
+// most 64 superblocks, one per lane) keep their two entries, their blocks
+// and the bound R in LDS.
 #pragma once
 #pragma clang fp contract(off)
 
@@ -39,7 +43,7 @@ namespace bs {
 #define BS_MPROF(slot, val) do { } while (0)
 #endif
 
-constexpr int kMaxPicks = 16;  // picks per round (<= 32: pick masks are 32-bit)
+constexpr int kMaxPicks = 32;  // picks per round (<= 32: pick masks are 32-bit)
 
 // Per-wavefront scratch of the wavefront-per-block path.
 struct WaveScratchMP {
@@ -92,18 +96,17 @@ struct GridLdsMP {
     uint32_t bsec[MAXB];   // value bits bounding every other key of the block
     float4 bwin[MAXB];
     int bcell[MAXB];
-    uint64_t sbkey[64];
-    uint32_t sbsec[64];
-    int sbblk[64];
+    uint64_t sbkey[64];    // superblock entries: best key of its best block
+    uint64_t sbkey2[64];   //   and of its second best block (0: none)
+    uint32_t sbsec[64];    // value bits bounding every key of the superblock but the two entries
+    int sbblk[64], sbblk2[64];  // the blocks of the two entries
     float4 sblo[64], sbhi[64];  // superblock boxes
-    uint32_t spm[64];      // picks of the round reaching each superblock
-    float4 pk[kMaxPicks];  // picks of the round: x, y, z, m
+    uint32_t spm[64];      // picks (by rank) reaching each superblock
+    float4 pk[kMaxPicks];  // picks of the round by rank: x, y, z, m
     int pkpos[kMaxPicks];
     int pkcell[kMaxPicks];
-    int npicks;
-    int sorted[64];        // superblocks by descending best key (selection)
-    float4 cand[kMaxPicks];     // selection: candidates x, y, z, m
-    uint32_t candsec[kMaxPicks];
+    uint32_t pkid[kMaxPicks];  // their original indices
+    int kfail;             // selection: lowest rank that cannot follow the ranks before it
     int tlist[HitCaps<NW>::blocks];  // touched blocks by rank (rounds touching few blocks)
     static constexpr int kHitCells = HitCaps<NW>::cells;
     static constexpr int kHitBlocks = HitCaps<NW>::blocks;
@@ -579,9 +582,10 @@ __device__ inline void finish_blocks(Lds& L) {
     }
 }
 
-// Best block of superblock sb (blocks sb*SBS .. sb*SBS + SBS - 1, SBS <= 64)
-// and the value bound of all its other keys, from LDS, into the superblock
-// entry.  One wavefront.
+// The two best blocks of superblock sb (blocks sb*SBS .. sb*SBS + SBS - 1,
+// SBS <= 64) and the value bound R of every other key (the two blocks'
+// second bounds, the other blocks' best values), from LDS, into the
+// superblock entry.  One wavefront.
 template <class Lds>
 __device__ __forceinline__ void superblock_refresh(Lds& L, int sb, int sbshift, int NB) {
     const int lane = threadIdx.x & 63;
@@ -590,49 +594,33 @@ __device__ __forceinline__ void superblock_refresh(Lds& L, int sb, int sbshift, 
     const uint64_t v = in ? L.bkey[b] : 0ull;
     const uint32_t sec = in ? L.bsec[b] : 0u;
     const uint64_t w1 = wave_max_key(v);
-    const int wl = __builtin_ctzll(__ballot(v == w1) | (1ull << 63));
-    const uint32_t s2 = wave_max_u32(lane == wl ? sec : uint32_t(v >> 32));
+    const int l1 = w1 != 0 ? __builtin_ctzll(__ballot(v == w1)) : -1;
+    const uint64_t v2 = lane == l1 ? 0ull : v;
+    const uint64_t w2 = wave_max_key(v2);
+    const int l2 = w2 != 0 ? __builtin_ctzll(__ballot(v2 == w2)) : -1;
+    const uint32_t rest = wave_max_u32((lane == l1 || lane == l2) ? sec : uint32_t(v >> 32));
     if (lane == 0) {
         L.sbkey[sb] = w1;
-        L.sbsec[sb] = s2;
-        L.sbblk[sb] = (sb << sbshift) + wl;
+        L.sbkey2[sb] = w2;
+        L.sbsec[sb] = rest;
+        L.sbblk[sb] = (sb << sbshift) + (l1 > 0 ? l1 : 0);
+        L.sbblk2[sb] = (sb << sbshift) + (l2 > 0 ? l2 : 0);
     }
-}
-
-// Superblock pick masks for the new picks (lanes = superblocks, picks held
-// by lanes 0..K-1 of the calling wavefront).
-template <class Lds>
-__device__ __forceinline__ uint32_t superblock_picks(const Lds& L, int nsb, int sbshift, int K, float px,
-                                                     float py, float pz, float pm, int pcell) {
-    const int lane = threadIdx.x & 63;
-    uint32_t spm = 0;
-    const float4 lo = L.sblo[lane], hi = L.sbhi[lane];
-    for (int j = 0; j < K; ++j) {
-        const float qx = rl(px, j), qy = rl(py, j), qz = rl(pz, j), qm = rl(pm, j);
-        const int qs = (__builtin_amdgcn_readlane(pcell, j) >> 6) >> sbshift;
-        const bool h = lane < nsb &&
-                       (lane == qs || box_lower(lo.x, lo.y, lo.z, hi.x, hi.y, hi.z, qx, qy, qz) < qm);
-        spm |= h ? (1u << j) : 0u;
-    }
-    return spm;
 }
 
 // Whole ordering of one object by one workgroup, several picks per round.
 //
-// A round: (1) every wavefront tests its block boxes against the picks of
-// the superblocks they lie in -> touched-block masks; (2) few touched blocks:
-// collect hit cells, update them with all lanes, rebuild the blocks' LDS
-// entries; many: one wavefront per touched block; (3) refresh the touched
-// superblocks; (4) wavefront 0 alone selects the next picks, tests them
-// against the superblock boxes and publishes them through LDS.
+// A round: (1) every wavefront tests its block boxes against the picks that
+// reach the superblocks they lie in -> touched-block masks; (2) few touched
+// blocks: collect hit cells, update them with all lanes, rebuild the blocks'
+// LDS entries; many: one wavefront per touched block; (3) refresh the
+// touched superblocks; (4) every wavefront ranks and tests its share of the
+// candidates for the next round and publishes them by rank through LDS.
 template <int BLOCK, int MAXB>
 __device__ inline void grid_order_object_mp(const GridObject& o, GridLdsMP<BLOCK / 64, MAXB>& L) {
     constexpr int NW = BLOCK / 64;
     constexpr int UMAX = BLOCK >= 1024 ? 2 : 4;  // member loads in flight per lane
     constexpr bool PREFETCH = BLOCK < 1024;      // next block's records during this one
-    // superblock tests of the new picks: by wavefront 0 during the selection
-    // (wide workgroups), or by each wavefront for its own superblocks
-    constexpr bool WAVE0_SBTEST = BLOCK >= 1024;
     constexpr int BPT = MAXB / BLOCK;            // block boxes held per thread
     const int tid = threadIdx.x;
     const int lane = tid & 63;
@@ -683,7 +671,7 @@ __device__ inline void grid_order_object_mp(const GridObject& o, GridLdsMP<BLOCK
         }
         L.sblo[lane] = make_float4(slx, sly, slz, 0.f);
         L.sbhi[lane] = make_float4(shx, shy, shz, 0.f);
-        L.spm[lane] = lane < nsb ? 1u : 0u;  // the start reaches every superblock
+        L.spm[lane] = lane < nsb ? 1u : 0u;  // the start may reach every superblock
         if (lane == 0) {
             // the start pick: pick 0, or the last pick of a leading scan
             // (already emitted; its update is this kernel's first round)
@@ -698,7 +686,7 @@ __device__ inline void grid_order_object_mp(const GridObject& o, GridLdsMP<BLOCK
             L.pk[0] = make_float4(sp.x, sp.y, sp.z, o.start_m);
             L.pkpos[0] = o.start_pos;
             L.pkcell[0] = o.start_cell;
-            L.npicks = 1;
+            L.pkid[0] = o.start_id;
             L.hcount = 0;
             L.hbcount = 0;
             L.overflow = 0;
@@ -708,13 +696,13 @@ __device__ inline void grid_order_object_mp(const GridObject& o, GridLdsMP<BLOCK
     for (int sb = wave; sb < nsb; sb += NW) superblock_refresh(L, sb, sbshift, NB);
     __syncthreads();
 
-    int t = o.t0 + 1;
+    int t = o.t0 + 1;  // picks emitted once this round's picks are
+    int K = 1;         // picks of this round (ranks 0 .. K-1 of the LDS pick arrays)
     int round_no = 0;
-    (void)round_no;
     while (true) {
         BS_MPROF(0, wall_clock64());
+        BS_MPROF(8, uint64_t(K));
         // ---- the round's picks: lane j of every wavefront holds pick j
-        const int K = L.npicks;
         float px = 0.f, py = 0.f, pz = 0.f, pm = 0.f;
         int ppos = 0, pcell = 0;
         if (lane < K) {
@@ -723,44 +711,22 @@ __device__ inline void grid_order_object_mp(const GridObject& o, GridLdsMP<BLOCK
             ppos = L.pkpos[lane];
             pcell = L.pkcell[lane];
         }
-
-        // ---- superblocks this wavefront's blocks lie in, against the picks:
-        // lanes take (own superblock, pick) pairs; a superblock (at most 64
-        // blocks, aligned) lies in exactly one wavefront's 64-block chunk
-        if (!WAVE0_SBTEST) {
-            // own superblocks: those whose first block lies in one of this
-            // wavefront's 64-block chunks (chunk index = block / 64)
-            const bool own = lane < nsb && (((lane << sbshift) >> 6) % NW) == wave;
-            const uint64_t ownm = __ballot(own);
-            const int nown = __popcll(ownm);
-            int* const olist = &L.u.ws[wave].tab[0].x;  // free until the round's cell lists
-            if (own) {
-                olist[__popcll(ownm & ((1ull << lane) - 1))] = lane;
-                L.spm[lane] = 0u;
-            }
-            wave_lds_sync();
-            const int npairs = nown * K;
-            for (int p0 = 0; p0 < npairs; p0 += 64) {
-                const int p = p0 + lane;
-                if (p < npairs) {
-                    const int c = p % nown, j = p / nown;
-                    const int sb = olist[c];
-                    const float4 lo = L.sblo[sb], hi = L.sbhi[sb];
-                    const float4 q = L.pk[j];
-                    const int qs = (L.pkcell[j] >> 6) >> sbshift;
-                    if (sb == qs || box_lower(lo.x, lo.y, lo.z, hi.x, hi.y, hi.z, q.x, q.y, q.z) < q.w)
-                        atomicOr(&L.spm[sb], 1u << j);
-                }
-            }
-            wave_lds_sync();
+        if (round_no > 0 && wave == 0 && lane < K) {  // emit them (the start pick was emitted before)
+            o.order[t - K + lane] = int32_t(L.pkid[lane]);
+            if (o.radius) o.radius[t - K + lane] = sqrtf(pm);
+#ifndef BS_PHASE_PROF
+            if (o.ticks) o.ticks[t - K + lane] = wall_clock64();
+#endif
         }
+        const uint32_t kmask = K >= 32 ? 0xFFFFFFFFu : ((1u << K) - 1u);
+
         // ---- touched blocks: this wavefront's block boxes against the picks
-        // of the superblocks they lie in
+        // that reach the superblocks they lie in
 #pragma unroll
         for (int jb = 0; jb < BPT; ++jb) {
             const int b = jb * BLOCK + tid;
             const int sb = min(b >> sbshift, 63);
-            const uint32_t mine = b < NB ? L.spm[sb] : 0u;
+            const uint32_t mine = b < NB ? (L.spm[sb] & kmask) : 0u;
             uint32_t wm = 0;
             for (int j = 0; j < K; ++j) wm |= __ballot((mine >> j) & 1u) ? (1u << j) : 0u;
             bool touch = false;
@@ -855,7 +821,8 @@ __device__ inline void grid_order_object_mp(const GridObject& o, GridLdsMP<BLOCK
         __syncthreads();
         BS_MPROF(4, wall_clock64());
 
-        // ---- refresh the touched superblocks, spread over the wavefronts
+        // ---- refresh the touched superblocks, spread over the wavefronts;
+        // clear the selection's LDS state (nothing reads it before the barrier)
         {
             bool st = false;
             if (lane < nsb) {
@@ -874,118 +841,97 @@ __device__ inline void grid_order_object_mp(const GridObject& o, GridLdsMP<BLOCK
                 if (r2 % NW == wave) superblock_refresh(L, sb, sbshift, NB);
                 ++r2;
             }
+            if (wave == NW - 1) {
+                L.spm[lane] = 0u;
+                if (lane == 0) {
+                    L.kfail = kMaxPicks;
+                    L.hcount = 0;
+                    L.hbcount = 0;
+                    L.overflow = 0;
+                }
+            }
         }
         BS_MPROF(5, wall_clock64());
         __syncthreads();
         BS_MPROF(6, wall_clock64());
         if (t >= k) break;
 
-        // ---- next picks: wavefront 0 alone
-        if (wave == 0) {
-            const uint64_t sk = lane < nsb ? L.sbkey[lane] : 0ull;
-            const uint32_t ssv = lane < nsb ? L.sbsec[lane] : 0u;
-            // only superblocks whose best beats the top superblock's bound can
-            // follow the top pick; rank those among themselves
-            const uint64_t top = wave_max_key(sk);
-            const int tl = __builtin_ctzll(__ballot(sk == top) | (1ull << 63));
-            const uint32_t tsec = uint32_t(__builtin_amdgcn_readlane(int(ssv), tl));
-            const uint64_t candm = __ballot(sk != 0 && (lane == tl || uint32_t(sk >> 32) > tsec));
-            int srank = 0;
-            for (uint64_t cs = candm; cs; cs &= cs - 1) {
-                const int i = __builtin_ctzll(cs);
-                const uint32_t olo = uint32_t(__builtin_amdgcn_readlane(int(uint32_t(sk)), i));
-                const uint32_t ohi = uint32_t(__builtin_amdgcn_readlane(int(uint32_t(sk >> 32)), i));
-                srank += ((uint64_t(ohi) << 32) | olo) > sk ? 1 : 0;
-            }
-            BS_MPROF(11, wall_clock64());
-            if (((candm >> lane) & 1ull) && srank < kMaxPicks) L.sorted[srank] = lane;
-            wave_lds_sync();
-            int nv = __popcll(candm);
-            nv = min(nv, o.max_picks);
-            nv = min(nv, k - t);
-            uint64_t ck = 0;
-            uint32_t csv = 0;
-            float4 cw = make_float4(0.f, 0.f, 0.f, 0.f);
-            int cc = 0;
-            if (lane < nv) {
-                const int sb = L.sorted[lane];
-                ck = L.sbkey[sb];
-                csv = L.sbsec[sb];
-                const int blk = L.sbblk[sb];
-                cw = L.bwin[blk];
-                cc = L.bcell[blk];
-            }
-            const float cm = key_value(ck);
-            if (lane < nv) {
-                L.cand[lane] = make_float4(cw.x, cw.y, cw.z, cm);
-                L.candsec[lane] = csv;
-            }
-            wave_lds_sync();
-            // candidate j follows i < j unless i lowers it or i's superblock
-            // may hold a larger key: all pairs (j, i) at once, 16 per j
-            uint32_t failj = 0;  // bit j: some i < j stops candidate j
-#ifdef BS_PHASE_PROF
-            uint32_t faild = 0, fails = 0;
-#endif
-            for (int q = 0; q < (nv + 3) / 4; ++q) {
-                const int jj = q * 4 + (lane >> 4), ii = lane & 15;
-                bool f = false;
-#ifdef BS_PHASE_PROF
-                bool fd = false, fs = false;
-#endif
-                if (ii < jj && jj < nv) {
-                    const float4 cj = L.cand[jj], ci = L.cand[ii];
-                    f = dist2(cj.x, cj.y, cj.z, ci.x, ci.y, ci.z) < cj.w ||
-                        __float_as_uint(cj.w) <= L.candsec[ii];
-#ifdef BS_PHASE_PROF
-                    fd = dist2(cj.x, cj.y, cj.z, ci.x, ci.y, ci.z) < cj.w;
-                    fs = __float_as_uint(cj.w) <= L.candsec[ii];
-#endif
-                }
-                const uint64_t fb = __ballot(f);
-                for (int g = 0; g < 4; ++g)
-                    failj |= ((fb >> (16 * g)) & 0xFFFFull) ? (1u << (q * 4 + g)) : 0u;
-#ifdef BS_PHASE_PROF
-                const uint64_t fdb = __ballot(fd), fsb = __ballot(fs);
-                for (int g = 0; g < 4; ++g) {
-                    faild |= ((fdb >> (16 * g)) & 0xFFFFull) ? (1u << (q * 4 + g)) : 0u;
-                    fails |= ((fsb >> (16 * g)) & 0xFFFFull) ? (1u << (q * 4 + g)) : 0u;
-                }
-#endif
-            }
-            BS_MPROF(12, wall_clock64());
-            const int Kn = nv > 0 ? min(nv, int(__builtin_ctz(failj | 0x80000000u))) : 0;
-#ifdef BS_PHASE_PROF
-            // candidates, filter count, and the first rejection's causes
-            BS_MPROF(21, uint64_t(nv) | (uint64_t(__popcll(candm)) << 8) |
-                             (uint64_t((faild >> Kn) & 1u) << 16) | (uint64_t((fails >> Kn) & 1u) << 17) |
-                             (uint64_t(nsb) << 24));
-#endif
-            if (WAVE0_SBTEST) L.spm[lane] = superblock_picks(L, nsb, sbshift, Kn, cw.x, cw.y, cw.z, cm, cc);
-            if (lane < Kn) {
-                o.order[t + lane] = int32_t(key_id(ck));
-                if (o.radius) o.radius[t + lane] = sqrtf(cm);
-#ifndef BS_PHASE_PROF
-                if (o.ticks) o.ticks[t + lane] = wall_clock64();
-#endif
-                L.pk[lane] = make_float4(cw.x, cw.y, cw.z, cm);
-                L.pkpos[lane] = __float_as_int(cw.w);
-                L.pkcell[lane] = cc;
-            }
-            if (lane == 0) {
-                L.npicks = Kn;
-                L.hcount = 0;
-                L.hbcount = 0;
-                L.overflow = 0;
-            }
-            BS_MPROF(7, wall_clock64());
-            BS_MPROF(8, uint64_t(Kn));
+        // ---- next picks.  Candidates: the entries (lane = superblock, slot 1
+        // or 2) above the top superblock's bound, and the top entry itself.
+        // Every wavefront ranks every NW-th candidate; a candidate of rank r
+        // fails when some higher-ranked candidate lowers it or comes from a
+        // superblock whose bound R reaches its value.
+        const int cap = min(min(o.max_picks, kMaxPicks), k - t);
+        const bool inl = lane < nsb;
+        const uint64_t e1 = inl ? L.sbkey[lane] : 0ull;
+        const uint64_t e2 = inl ? L.sbkey2[lane] : 0ull;
+        const uint32_t rb = inl ? L.sbsec[lane] : 0u;
+        const uint64_t top = wave_max_key(e1);
+        const int tl = __builtin_ctzll(__ballot(e1 == top) | (1ull << 63));
+        const uint32_t trb = uint32_t(__builtin_amdgcn_readlane(int(rb), tl));
+        const bool c1 = e1 != 0 && (lane == tl || uint32_t(e1 >> 32) > trb);
+        const bool c2 = e2 != 0 && uint32_t(e2 >> 32) > trb;
+        const uint64_t m1 = __ballot(c1), m2 = __ballot(c2);
+        const int nc = __popcll(m1) + __popcll(m2);
+        float4 w1 = make_float4(0.f, 0.f, 0.f, 0.f), w2 = w1;
+        int cl1 = 0, cl2 = 0;
+        if (c1) {
+            const int bb = L.sbblk[lane];
+            w1 = L.bwin[bb];
+            cl1 = L.bcell[bb];
         }
+        if (c2) {
+            const int bb = L.sbblk2[lane];
+            w2 = L.bwin[bb];
+            cl2 = L.bcell[bb];
+        }
+        const float4 slo = L.sblo[lane], shi = L.sbhi[lane];
+        const uint64_t lt = (1ull << lane) - 1ull;
+        const int i1 = __popcll(m1 & lt) + __popcll(m2 & lt);  // position of slot 1 in lane order
+        const int i2 = i1 + (c1 ? 1 : 0);
+        const uint64_t my1 = __ballot(c1 && (i1 % NW) == wave);
+        const uint64_t my2 = __ballot(c2 && (i2 % NW) == wave);
+        BS_MPROF(11, wall_clock64());
+#pragma unroll
+        for (int slot = 0; slot < 2; ++slot) {
+            const uint64_t ek = slot == 0 ? e1 : e2;
+            const float4 wk = slot == 0 ? w1 : w2;
+            const int ck = slot == 0 ? cl1 : cl2;
+            for (uint64_t mm = slot == 0 ? my1 : my2; mm; mm &= mm - 1) {
+                const int lc = __builtin_ctzll(mm);
+                const uint32_t klo = uint32_t(__builtin_amdgcn_readlane(int(uint32_t(ek)), lc));
+                const uint32_t khi = uint32_t(__builtin_amdgcn_readlane(int(uint32_t(ek >> 32)), lc));
+                const uint64_t kc = (uint64_t(khi) << 32) | klo;
+                const bool g1 = c1 && e1 > kc, g2 = c2 && e2 > kc;
+                const int rank = __popcll(__ballot(g1)) + __popcll(__ballot(g2));
+                if (rank >= cap) continue;
+                const float cx = rl(wk.x, lc), cy = rl(wk.y, lc), cz = rl(wk.z, lc);
+                const int cpos = __builtin_amdgcn_readlane(__float_as_int(wk.w), lc);
+                const int ccell = __builtin_amdgcn_readlane(ck, lc);
+                const float cm = key_value(kc);
+                const bool f = (g1 && (dist2(w1.x, w1.y, w1.z, cx, cy, cz) < cm || khi <= rb)) ||
+                               (g2 && (dist2(w2.x, w2.y, w2.z, cx, cy, cz) < cm || khi <= rb));
+                const bool fail = __ballot(f) != 0;
+                const int csb = (ccell >> 6) >> sbshift;
+                const bool reach = inl && (lane == csb ||
+                                           box_lower(slo.x, slo.y, slo.z, shi.x, shi.y, shi.z, cx, cy, cz) < cm);
+                if (reach) atomicOr(&L.spm[lane], 1u << rank);
+                if (lane == 0) {
+                    if (fail) atomicMin(&L.kfail, rank);
+                    L.pk[rank] = make_float4(cx, cy, cz, cm);
+                    L.pkpos[rank] = cpos;
+                    L.pkcell[rank] = ccell;
+                    L.pkid[rank] = key_id(kc);
+                }
+            }
+        }
+        BS_MPROF(7, wall_clock64());
+        BS_MPROF(21, uint64_t(nc) | (uint64_t(nsb) << 24));
         ++round_no;
         __syncthreads();
-        const int Kn = L.npicks;
-        if (Kn <= 0) break;  // cannot happen while t < k <= n; keeps the loop finite
-        t += Kn;
+        K = min(min(L.kfail, nc), cap);
+        if (K <= 0) break;  // cannot happen while t < k <= n; keeps the loop finite
+        t += K;
     }
 }
 

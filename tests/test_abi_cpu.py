@@ -91,8 +91,8 @@ def test_autotune_validation_without_device(lib):
     lib.bs_autotune_clear()
     assert lib.bs_autotune_lookup(4096, 100, ctypes.byref(t)) == bs.BS_ERR_NOT_READY
     assert lib.bs_batch_autotune(None, None, None, 0, fake, ctypes.byref(t), None) == bs.BS_ERR_INVALID_ARG
-    # tuning fields: picks outside 0..16 is rejected like the reserved words
-    bad = bs.tuning(kernel=3, picks=17)
+    # tuning fields: picks outside 0..32 is rejected like the reserved words
+    bad = bs.tuning(kernel=3, picks=33)
     assert lib.bs_workspace_size(1000, 10, ctypes.byref(bad)) == 0
     assert lib.bs_workspace_size(1000, 10, ctypes.byref(bs.tuning(kernel=3, picks=16))) > 0
 

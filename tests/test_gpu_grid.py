@@ -29,7 +29,7 @@ def test_grid_adversarial(hip, name, block, picks):
         assert_parity(o, r, eo, er, "grid %s n=%d block=%d picks=%d" % (name, n, block, picks))
 
 
-@pytest.mark.parametrize("picks", [2, 3, 7, 16])
+@pytest.mark.parametrize("picks", [2, 3, 7, 16, 24, 32])
 def test_grid_picks_per_round(hip, picks):
     """Every read-ahead limit gives the same order (several superblock sizes)."""
     for n, cp in ((50000, 32.0), (20000, 4.0), (3000, 1.0)):
