@@ -9,8 +9,8 @@ namespace bs {
 
 // Device-written description of one object's grid (chosen on the device).
 struct GridHeader {
-    uint32_t hist[12];   // adjacent sorted pairs first separated at each Morton level
-    int32_t level;       // grid level: cells of side extent / 2^level
+    uint32_t hist[31];   // adjacent sorted pairs first separated by each code prefix length
+    int32_t level;       // cells: runs of sorted Morton codes sharing their top `level` bits
     int32_t C;           // occupied cells
     int32_t B;           // cells per block (power of two >= 64)
     int32_t NB;          // blocks (<= workgroup size)
@@ -18,7 +18,7 @@ struct GridHeader {
     int32_t start_cell;  // its cell
     uint32_t lead_id;    // after a leading full scan: its last pick (original index)
     uint32_t lead_m;     // and the bits of that pick's m
-    int32_t pad[44];
+    int32_t pad[25];
 };
 static_assert(sizeof(GridHeader) == 256, "grid header size");
 

@@ -64,22 +64,25 @@ __global__ void morton_kernel(const float* __restrict__ pts, int n, const DevHea
     vals[i] = uint32_t(i);
 }
 
-// hist[l] = number of adjacent sorted pairs whose cells first differ at level l
+// Cells are the runs of sorted codes sharing their top `level` bits (one
+// bit at a time: each step halves a cell along one axis, so the cell count
+// can follow the target closely).  hist[p] = number of adjacent sorted pairs
+// whose codes first differ within the top p bits (p = 1 .. 3 * kMortonBits).
 __global__ void level_hist_kernel(const uint32_t* __restrict__ codes, int n, GridHeader* gh) {
-    __shared__ uint32_t h[kMortonBits + 1];
-    if (threadIdx.x <= kMortonBits) h[threadIdx.x] = 0;
+    constexpr int kBits = 3 * kMortonBits;
+    __shared__ uint32_t h[kBits + 1];
+    if (threadIdx.x <= kBits) h[threadIdx.x] = 0;
     __syncthreads();
     const int stride = gridDim.x * blockDim.x;
     for (int i = blockIdx.x * blockDim.x + threadIdx.x + 1; i < n; i += stride) {
         const uint32_t d = codes[i] ^ codes[i - 1];
         if (d) {
-            const int b = 31 - __clz(d);            // highest differing bit
-            const int l = kMortonBits - b / 3;       // first level that separates them
-            atomicAdd(&h[l], 1u);
+            const int b = 31 - __clz(d);  // highest differing bit (< kBits)
+            atomicAdd(&h[kBits - b], 1u); // first prefix length that separates them
         }
     }
     __syncthreads();
-    if (threadIdx.x <= kMortonBits && h[threadIdx.x]) atomicAdd(&gh->hist[threadIdx.x], h[threadIdx.x]);
+    if (threadIdx.x <= kBits && h[threadIdx.x]) atomicAdd(&gh->hist[threadIdx.x], h[threadIdx.x]);
 }
 
 __global__ void choose_level_kernel(int n, GridHeader* gh, float target, int max_blocks) {
@@ -87,7 +90,7 @@ __global__ void choose_level_kernel(int n, GridHeader* gh, float target, int max
     const double cap = fmin(fmax(1.0, double(n) / double(target)), double(64 * max_blocks));
     int level = 0;
     uint32_t cells = 1, acc = 1;
-    for (int l = 1; l <= kMortonBits; ++l) {
+    for (int l = 1; l <= 3 * kMortonBits; ++l) {
         acc += gh->hist[l];
         if (double(acc) <= cap) {
             level = l;
@@ -104,7 +107,7 @@ __global__ void cell_flag_kernel(const uint32_t* __restrict__ codes, int n, cons
                                  uint32_t* __restrict__ flags) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
-    const int s = 3 * (kMortonBits - gh->level);
+    const int s = 3 * kMortonBits - gh->level;
     flags[i] = (i == 0 || (codes[i] >> s) != (codes[i - 1] >> s)) ? 1u : 0u;
 }
 
