@@ -33,15 +33,16 @@ constexpr int kBatchBlock = 256;         // threads per ordering workgroup
 constexpr int kBatchMaxBlocks = 1024;    // blocks of 64 cells per object
 constexpr int kObjBits = 30;             // Morton bits below the object id
 
-// Per-object device state of the batched preprocessing (128 bytes).
+// Per-object device state of the batched preprocessing (256 bytes).
 struct ObjHdr {
     uint32_t bbox[6];  // order-preserving encodings: min x,y,z, max x,y,z
     uint32_t nonfinite;
-    uint32_t hist[11];
-    int32_t level, cell_base, C, NB, block_base, nsb, sb_base, start_pos, start_cell;
-    int32_t pad[5];
+    uint32_t hist[31];  // adjacent sorted pairs first separated by each code prefix length
+    int32_t level;      // cells: runs of codes sharing their top `level` bits
+    int32_t cell_base, C, NB, block_base, nsb, sb_base, start_pos, start_cell;
+    int32_t pad[17];
 };
-static_assert(sizeof(ObjHdr) == 128, "object header size");
+static_assert(sizeof(ObjHdr) == 256, "object header size");
 
 __device__ __forceinline__ uint32_t ord_encode_f(float f) {
     const uint32_t u = __float_as_uint(f);
@@ -147,13 +148,15 @@ __global__ void bmorton_kernel(const float* __restrict__ pts, int N, const int32
     vals[i] = uint32_t(i);
 }
 
-// per object: adjacent sorted pairs first separated at each Morton level
+// per object: adjacent sorted pairs first separated by each code prefix
+// length (cells are chosen one Morton bit at a time, as for one object)
 __global__ void bhist_kernel(const uint64_t* __restrict__ keys, int N, ObjHdr* __restrict__ hd) {
-    __shared__ uint32_t h[kMortonBits + 1];
+    constexpr int kBits = 3 * kMortonBits;
+    __shared__ uint32_t h[kBits + 1];
     const int first = blockIdx.x * blockDim.x;
     if (first >= N) return;
     const int obj0 = int(keys[first] >> kObjBits);
-    if (threadIdx.x <= kMortonBits) h[threadIdx.x] = 0;
+    if (threadIdx.x <= kBits) h[threadIdx.x] = 0;
     __syncthreads();
     const int i = first + threadIdx.x;
     if (i >= 1 && i < N) {
@@ -161,7 +164,7 @@ __global__ void bhist_kernel(const uint64_t* __restrict__ keys, int N, ObjHdr* _
         if ((a >> kObjBits) == (b >> kObjBits)) {
             const uint32_t d = uint32_t(a ^ b) & ((1u << kObjBits) - 1u);
             if (d) {
-                const int l = kMortonBits - (31 - __clz(d)) / 3;
+                const int l = kBits - (31 - __clz(d));
                 const int obj = int(a >> kObjBits);
                 if (obj == obj0) atomicAdd(&h[l], 1u);
                 else atomicAdd(&hd[obj].hist[l], 1u);
@@ -169,7 +172,7 @@ __global__ void bhist_kernel(const uint64_t* __restrict__ keys, int N, ObjHdr* _
         }
     }
     __syncthreads();
-    if (threadIdx.x <= kMortonBits && h[threadIdx.x]) atomicAdd(&hd[obj0].hist[threadIdx.x], h[threadIdx.x]);
+    if (threadIdx.x <= kBits && h[threadIdx.x]) atomicAdd(&hd[obj0].hist[threadIdx.x], h[threadIdx.x]);
 }
 
 __global__ void blevel_kernel(int m, const int32_t* __restrict__ offs, ObjHdr* __restrict__ hd,
@@ -180,7 +183,7 @@ __global__ void blevel_kernel(int m, const int32_t* __restrict__ offs, ObjHdr* _
     const double cap = fmin(fmax(1.0, double(n) / double(target)), double(64 * max_blocks));
     int level = 0;
     uint32_t acc = 1;
-    for (int l = 1; l <= kMortonBits; ++l) {
+    for (int l = 1; l <= 3 * kMortonBits; ++l) {
         acc += hd[j].hist[l];
         if (double(acc) <= cap) level = l;
     }
@@ -198,7 +201,7 @@ __global__ void bflag_kernel(const uint64_t* __restrict__ keys, int N, const Obj
     }
     const uint64_t b = keys[i - 1];
     const int obj = int(a >> kObjBits);
-    const int s = 3 * (kMortonBits - hd[obj].level);
+    const int s = 3 * kMortonBits - hd[obj].level;
     const uint32_t ca = uint32_t(a) & ((1u << kObjBits) - 1u), cb = uint32_t(b) & ((1u << kObjBits) - 1u);
     flags[i] = ((a >> kObjBits) != (b >> kObjBits) || (ca >> s) != (cb >> s)) ? 1u : 0u;
 }
