@@ -593,11 +593,15 @@ __device__ __forceinline__ void superblock_refresh(Lds& L, int sb, int sbshift, 
     const bool in = lane < (1 << sbshift) && b < NB;
     const uint64_t v = in ? L.bkey[b] : 0ull;
     const uint32_t sec = in ? L.bsec[b] : 0u;
-    const uint64_t w1 = wave_max_key(v);
+    // top two keys of the superblock in one merge (keys are unique)
+    uint64_t a1 = v, a2 = 0;
+    group_top2(a1, a2, 6);
+    const uint64_t w1 = (uint64_t(uint32_t(__builtin_amdgcn_readlane(int(uint32_t(a1 >> 32)), 63))) << 32) |
+                        uint32_t(__builtin_amdgcn_readlane(int(uint32_t(a1)), 63));
+    const uint64_t w2 = (uint64_t(uint32_t(__builtin_amdgcn_readlane(int(uint32_t(a2 >> 32)), 63))) << 32) |
+                        uint32_t(__builtin_amdgcn_readlane(int(uint32_t(a2)), 63));
     const int l1 = w1 != 0 ? __builtin_ctzll(__ballot(v == w1)) : -1;
-    const uint64_t v2 = lane == l1 ? 0ull : v;
-    const uint64_t w2 = wave_max_key(v2);
-    const int l2 = w2 != 0 ? __builtin_ctzll(__ballot(v2 == w2)) : -1;
+    const int l2 = w2 != 0 ? __builtin_ctzll(__ballot(v == w2)) : -1;
     const uint32_t rest = wave_max_u32((lane == l1 || lane == l2) ? sec : uint32_t(v >> 32));
     if (lane == 0) {
         L.sbkey[sb] = w1;
