@@ -99,7 +99,13 @@ typedef struct {
                               candidates when a cooperative scan holds n), -1 = none,
                               >= 2 = that many (capped at k; BS_ERR_UNSUPPORTED if no
                               cooperative scan holds n) */
-    int32_t reserved[5];   /* must be zero */
+    int32_t batch_wide;    /* batch plans: how many of the objects with the largest k are
+                              ordered by 1024-thread workgroups (a second persistent
+                              kernel beside the 256-thread one, on at most half the CUs;
+                              same result).  0 = auto (objects with k >= 65536 and more
+                              than half the mean k per 256-thread workgroup slot), -1 =
+                              none */
+    int32_t reserved[4];   /* must be zero */
 } bs_tuning;
 
 /* ------------------------------------------------------- single instance */

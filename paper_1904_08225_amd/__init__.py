@@ -47,12 +47,13 @@ class Tuning(ctypes.Structure):
     _fields_ = [("kernel", ctypes.c_int32), ("block", ctypes.c_int32),
                 ("per_thread", ctypes.c_int32), ("groups", ctypes.c_int32),
                 ("cell_points", ctypes.c_float), ("picks", ctypes.c_int32),
-                ("lead_picks", ctypes.c_int32), ("reserved", ctypes.c_int32 * 5)]
+                ("lead_picks", ctypes.c_int32), ("batch_wide", ctypes.c_int32),
+                ("reserved", ctypes.c_int32 * 4)]
 
 
 def tuning(kernel: int = 0, block: int = 0, per_thread: int = 0, groups: int = 0,
-           cell_points: float = 0.0, picks: int = 0, lead_picks: int = 0) -> Tuning:
-    return Tuning(kernel, block, per_thread, groups, cell_points, picks, lead_picks)
+           cell_points: float = 0.0, picks: int = 0, lead_picks: int = 0, batch_wide: int = 0) -> Tuning:
+    return Tuning(kernel, block, per_thread, groups, cell_points, picks, lead_picks, batch_wide)
 
 
 def header_functions():

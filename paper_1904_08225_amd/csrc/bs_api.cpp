@@ -41,7 +41,7 @@ bool tuning_clean(const bs_tuning* t) {
     for (int r : t->reserved)
         if (r != 0) return false;
     if (t->picks < 0 || t->picks > kMaxGridPicks) return false;
-    if (t->lead_picks < -1) return false;
+    if (t->lead_picks < -1 || t->batch_wide < -1) return false;
     return t->kernel >= BS_KERNEL_AUTO && t->kernel <= BS_KERNEL_GRID;
 }
 
@@ -316,7 +316,7 @@ int bs_batch_plan_create(const int64_t* h_offsets, const int64_t* h_k, const uin
     if (!tuning_clean(tuning)) return set_error(BS_ERR_INVALID_ARG, "bad tuning struct");
     const float target = (tuning && tuning->cell_points > 0.f) ? tuning->cell_points : kDefaultCellPointsMulti;
     bs::BatchPlan* p = nullptr;
-    const int rc = batch_plan_create(h_offsets, h_k, h_seed, m, target, &p);
+    const int rc = batch_plan_create(h_offsets, h_k, h_seed, m, target, tuning ? tuning->batch_wide : 0, &p);
     if (rc != BS_OK) return rc;
     *out_plan = new bs_batch_plan{p, m};
     return BS_OK;

@@ -30,6 +30,8 @@ namespace bs {
 namespace {
 
 constexpr int kBatchBlock = 256;         // threads per ordering workgroup
+constexpr int kWideBlock = 1024;         // threads per workgroup for the largest objects
+constexpr int64_t kWideMinK = 65536;     // automatic choice: smallest k given a wide workgroup
 constexpr int kBatchMaxBlocks = 1024;    // blocks of 64 cells per object
 constexpr int kObjBits = 30;             // Morton bits below the object id
 
@@ -465,15 +467,18 @@ __global__ void bdesc_kernel(int m, const ObjHdr* __restrict__ hd, const int32_t
 }
 
 __global__ void queue_reset_kernel(uint32_t* q) {
-    if (threadIdx.x == 0) q[0] = 0u;
+    if (threadIdx.x < 2) q[threadIdx.x] = 0u;
 }
 
 // Persistent work queue: each workgroup pops objects (largest k first) until
 // the queue is drained; every pop ends the loop for all its waves alike.
-__global__ void __launch_bounds__(kBatchBlock)
+// BLOCK = 256 for most objects; the largest ones may get 1024-thread
+// workgroups (a second launch of the same loop with its own queue).
+template <int BLOCK>
+__global__ void __launch_bounds__(BLOCK)
     batch_order_kernel(const ObjDesc* __restrict__ desc, const int32_t* __restrict__ lpt, int mwork,
                        uint32_t* __restrict__ queue) {
-    __shared__ GridLdsMP<kBatchBlock / 64, kBatchMaxBlocks> L;
+    __shared__ GridLdsMP<BLOCK / 64, kBatchMaxBlocks> L;
     __shared__ int s_item;
     for (;;) {
         if (threadIdx.x == 0) s_item = int(atomicAdd(queue, 1u));
@@ -486,12 +491,12 @@ __global__ void __launch_bounds__(kBatchBlock)
         uint32_t* done = desc[j].done;
         if (o.k > 0) {
             if (desc[j].nonfinite) {
-                for (int t = threadIdx.x; t < o.k; t += kBatchBlock) {
+                for (int t = threadIdx.x; t < o.k; t += BLOCK) {
                     o.order[t] = -1;
                     if (o.radius) o.radius[t] = __builtin_nanf("");
                 }
             } else {
-                grid_order_object_mp<kBatchBlock, kBatchMaxBlocks>(o, L);
+                grid_order_object_mp<BLOCK, kBatchMaxBlocks>(o, L);
             }
         }
         __syncthreads();
@@ -603,6 +608,10 @@ struct BatchPlan {
     size_t sort_bytes = 0, scan_bytes = 0;
     size_t ws_bytes = 0;
     int slots = 0;                  // persistent workgroups
+    int nwide = 0;                  // the first nwide objects of h_lpt go to 1024-thread workgroups
+    int wide_slots = 0;             // their persistent workgroups
+    hipStream_t side = nullptr;     // stream of the wide launch (forked from the caller's)
+    hipEvent_t fork = nullptr, join = nullptr;
     bool use_graph = true;
     // the captured ordering graph, valid for one workspace address
     hipGraphExec_t exec = nullptr;
@@ -696,9 +705,8 @@ hipError_t capture_order_graph(BatchPlan& p, const BatchWs& w) {
     if (e != hipSuccess) return e;
     e = hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal);
     if (e == hipSuccess) {
-        hipLaunchKernelGGL(queue_reset_kernel, dim3(1), dim3(64), 0, cap, w.queue);
-        hipLaunchKernelGGL(batch_order_kernel, dim3(p.slots), dim3(kBatchBlock), 0, cap, w.desc,
-                           w.lpt, p.mwork, w.queue);
+        hipLaunchKernelGGL(batch_order_kernel<kBatchBlock>, dim3(p.slots), dim3(kBatchBlock), 0, cap, w.desc,
+                           w.lpt + p.nwide, p.mwork - p.nwide, w.queue);
         hipError_t e2 = hipStreamEndCapture(cap, &p.graph);
         e = (e2 != hipSuccess) ? e2 : hipGetLastError();
     }
@@ -713,11 +721,14 @@ void batch_plan_free(BatchPlan* p) {
     if (!p) return;
     if (p->exec) (void)hipGraphExecDestroy(p->exec);
     if (p->graph) (void)hipGraphDestroy(p->graph);
+    if (p->side) (void)hipStreamDestroy(p->side);
+    if (p->fork) (void)hipEventDestroy(p->fork);
+    if (p->join) (void)hipEventDestroy(p->join);
     delete p;
 }
 
 int batch_plan_create(const int64_t* h_offsets, const int64_t* h_k, const uint64_t* h_seed, int32_t m,
-                      float target, BatchPlan** out) {
+                      float target, int wide, BatchPlan** out) {
     if (!out || m < 0 || (m > 0 && (!h_offsets || !h_k)))
         return set_error(BS_ERR_INVALID_ARG, "null plan arguments");
     if (h_offsets && h_offsets[0] != 0) return set_error(BS_ERR_INVALID_ARG, "offsets[0] must be 0");
@@ -786,11 +797,36 @@ int batch_plan_create(const int64_t* h_offsets, const int64_t* h_k, const uint64
     int dev = 0, cus = 0, per = 0;
     (void)hipGetDevice(&dev);
     (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
-    (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, reinterpret_cast<const void*>(batch_order_kernel),
-                                                       kBatchBlock, 0);
+    (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(
+        &per, reinterpret_cast<const void*>(batch_order_kernel<kBatchBlock>), kBatchBlock, 0);
     if (cus <= 0) cus = 256;
     if (per <= 0) per = 1;
-    p->slots = std::max(1, std::min(cus * per, std::max(p->mwork, 1)));
+    // the largest objects (the head of the LPT order) on 1024-thread
+    // workgroups, one CU each, on at most half the CUs: those whose chain is
+    // long against the mean work of a 256-thread slot (a 1024-thread
+    // workgroup finishes a long chain ~2.5x sooner but takes a whole CU, which
+    // costs throughput on short chains), or as many as asked
+    int nw = 0;
+    if (wide > 0) {
+        nw = std::min(wide, p->mwork);
+    } else if (wide == 0 && p->mwork > 1) {
+        const double mean = double(p->total_k) / double(cus * per);
+        while (nw < p->mwork && p->h_k[p->h_lpt[nw]] >= kWideMinK && double(p->h_k[p->h_lpt[nw]]) > 0.5 * mean)
+            ++nw;
+    }
+    p->nwide = nw;
+    p->wide_slots = std::min(nw, std::max(1, cus / 2));
+    const int rest = p->mwork - nw;
+    p->slots = std::max(1, std::min((cus - p->wide_slots) * per, std::max(rest, 1)));
+    if (nw > 0) {
+        hipError_t e = hipStreamCreateWithFlags(&p->side, hipStreamNonBlocking);
+        if (e == hipSuccess) e = hipEventCreateWithFlags(&p->fork, hipEventDisableTiming);
+        if (e == hipSuccess) e = hipEventCreateWithFlags(&p->join, hipEventDisableTiming);
+        if (e != hipSuccess) {
+            batch_plan_free(p);
+            return set_error(BS_ERR_HIP, "batch plan stream: %s", hipGetErrorString(e));
+        }
+    }
     *out = p;
     return BS_OK;
 }
@@ -883,22 +919,40 @@ int batch_plan_execute(BatchPlan* p, const float* pts, int32_t* out_order, float
     BatchWs w;
     const int rc = batch_preprocess(p, pts, out_order, out_radius, ws, ws_bytes, st, w);
     if (rc != BS_OK) return rc;
-    hipError_t e = hipSuccess;
-    if (!p->use_graph) {
-        hipLaunchKernelGGL(queue_reset_kernel, dim3(1), dim3(64), 0, st, w.queue);
-        hipLaunchKernelGGL(batch_order_kernel, dim3(p->slots), dim3(kBatchBlock), 0, st, w.desc, w.lpt,
-                           p->mwork, w.queue);
-        e = hipGetLastError();
-        if (e != hipSuccess) return set_error(BS_ERR_HIP, "order launch: %s", hipGetErrorString(e));
-        return BS_OK;
+    // both queues restart before either launch can pop
+    hipLaunchKernelGGL(queue_reset_kernel, dim3(1), dim3(64), 0, st, w.queue);
+    hipError_t e = hipGetLastError();
+    if (e == hipSuccess && p->nwide > 0) {
+        // the largest objects: 1024-thread workgroups on the side stream,
+        // enqueued first so that they find whole CUs free
+        e = hipEventRecord(p->fork, st);
+        if (e == hipSuccess) e = hipStreamWaitEvent(p->side, p->fork, 0);
+        if (e == hipSuccess) {
+            hipLaunchKernelGGL(batch_order_kernel<kWideBlock>, dim3(p->wide_slots), dim3(kWideBlock), 0, p->side,
+                               w.desc, w.lpt, p->nwide, w.queue + 1);
+            e = hipGetLastError();
+        }
+        if (e == hipSuccess) e = hipEventRecord(p->join, p->side);
     }
-    if (!p->exec || p->graph_ws != ws) {
-        e = capture_order_graph(*p, w);
-        if (e != hipSuccess) return set_error(BS_ERR_HIP, "graph capture: %s", hipGetErrorString(e));
-        p->graph_ws = ws;
+    if (e != hipSuccess) return set_error(BS_ERR_HIP, "order launch: %s", hipGetErrorString(e));
+    if (p->mwork > p->nwide) {
+        if (!p->use_graph) {
+            hipLaunchKernelGGL(batch_order_kernel<kBatchBlock>, dim3(p->slots), dim3(kBatchBlock), 0, st, w.desc,
+                               w.lpt + p->nwide, p->mwork - p->nwide, w.queue);
+            e = hipGetLastError();
+            if (e != hipSuccess) return set_error(BS_ERR_HIP, "order launch: %s", hipGetErrorString(e));
+        } else {
+            if (!p->exec || p->graph_ws != ws) {
+                e = capture_order_graph(*p, w);
+                if (e != hipSuccess) return set_error(BS_ERR_HIP, "graph capture: %s", hipGetErrorString(e));
+                p->graph_ws = ws;
+            }
+            e = hipGraphLaunch(p->exec, st);
+            if (e != hipSuccess) return set_error(BS_ERR_HIP, "graph launch: %s", hipGetErrorString(e));
+        }
     }
-    e = hipGraphLaunch(p->exec, st);
-    if (e != hipSuccess) return set_error(BS_ERR_HIP, "graph launch: %s", hipGetErrorString(e));
+    if (p->nwide > 0 && (e = hipStreamWaitEvent(st, p->join, 0)) != hipSuccess)
+        return set_error(BS_ERR_HIP, "join: %s", hipGetErrorString(e));
     return BS_OK;
 }
 

@@ -63,8 +63,10 @@ hipError_t launch_scan(const ScanShape& s, const float* pts, int n, int k, int s
 
 // Batched plans (bs_batch.hip).
 struct BatchPlan;
+// wide: objects (largest k first) for 1024-thread workgroups in
+// batch_plan_execute; 0 = automatic, -1 = none (see bs_tuning.batch_wide)
 int batch_plan_create(const int64_t* h_offsets, const int64_t* h_k, const uint64_t* h_seed, int32_t m,
-                      float target, BatchPlan** out);
+                      float target, int wide, BatchPlan** out);
 void batch_plan_free(BatchPlan* p);
 size_t batch_workspace_bytes(const BatchPlan* p);
 int64_t batch_total_k(const BatchPlan* p);

@@ -187,7 +187,7 @@ bool admit_batch(Server& s) {
         if (f.plan) batch_plan_free(f.plan);
         f.plan = nullptr;
         rc = batch_plan_create(offs.data(), ks.data(), seeds.data(), int32_t(take.size()),
-                               s.cfg.cell_points > 0.f ? s.cfg.cell_points : 8.f, &f.plan);
+                               s.cfg.cell_points > 0.f ? s.cfg.cell_points : 8.f, -1, &f.plan);
         if (rc != BS_OK) break;
         f.bytes = batch_workspace_bytes(f.plan) + align_up(size_t(offs.back()) * 12);
         if (s.bytes_in_use + f.bytes <= budget) break;

@@ -129,3 +129,40 @@ def test_batch_scene_objects(hip):
         eo, er = oracle.greedy32(Pj, ks[j], oracle.start_index(seeds[j], Pj.shape[0]))
         assert_parity(oo[a:b], rr[a:b], eo, er, "scene object %d (kind %d)" % (j, j % 3))
     plan.close()
+
+
+@pytest.mark.parametrize("wide", [2, 5])
+def test_batch_wide_workgroups(hip, wide):
+    """The objects with the largest k on 1024-thread workgroups beside the
+    256-thread ones (a non-finite object and a k = 0 object among the large
+    ones): every object equals the oracle, or -1 / NaN when non-finite."""
+    import torch
+    rng = np.random.default_rng(70 + wide)
+    objs, ks, seeds = [], [], []
+    for j in range(12):
+        n = int(rng.integers(40000, 160000)) if j < 6 else int(rng.integers(200, 5000))
+        P = np.ascontiguousarray(synth.cad_part(n, seed=900 + j, count=30).points.numpy())
+        if j == 2:
+            P[17, 1] = np.nan
+        objs.append(P)
+        ks.append(0 if j == 4 else n // 4)
+        seeds.append(int(rng.integers(0, 2**63)))
+    offs = np.concatenate([[0], np.cumsum([o.shape[0] for o in objs])]).astype(np.int64)
+    plan = hip.BatchPlan(offs, ks, seeds, tune=hip.tuning(batch_wide=wide))
+    allp = torch.from_numpy(np.concatenate(objs)).cuda()
+    for rep in range(2):
+        o, r = plan.execute(allp)
+        torch.cuda.synchronize()
+        o = o.cpu().numpy()
+        r = r.cpu().numpy()
+        for j, P in enumerate(objs):
+            a, b = plan.out_offsets[j], plan.out_offsets[j + 1]
+            if ks[j] == 0:
+                continue
+            if j == 2:
+                assert (o[a:b] == -1).all() and np.isnan(r[a:b]).all()
+                continue
+            eo, er = oracle.greedy32_grid(P, ks[j], oracle.start_index(seeds[j], P.shape[0]))
+            assert_parity(o[a:b], r[a:b], eo, er, "wide=%d object %d (n=%d k=%d) rep %d"
+                          % (wide, j, P.shape[0], ks[j], rep))
+    plan.close()
