@@ -246,10 +246,13 @@ int bs_batch_autotune(const int64_t* h_offsets, const int64_t* h_k, const uint64
  * (0 .. n_j-1).
  *
  * The plan copies its host arrays; it owns a few small device arrays and,
- * after the first execute, a captured hipGraph of the ordering launch (a
- * queue reset and one persistent work-queue kernel whose workgroups order
- * objects largest-k first).  Preprocessing (per-object grids) is enqueued
- * as ordinary launches before the graph.
+ * after the first execute, a captured hipGraph of the ordering launch (one
+ * persistent work-queue kernel whose 256-thread workgroups order objects
+ * largest-k first).  Preprocessing (per-object grids) and the queue reset
+ * are enqueued as ordinary launches before the graph.  The objects with the
+ * longest chains (bs_tuning.batch_wide) are ordered meanwhile by a second
+ * persistent kernel of 1024-thread workgroups on a stream of the plan,
+ * forked from and joined back into `stream`.
  *
  *   h_offsets  host int64[m+1], non-decreasing, h_offsets[0] = 0, total < 2^31
  *   h_k        host int64[m], 0 <= k_j <= n_j
