@@ -55,6 +55,14 @@ def _bind(path: str):
     lib.oracle_along_order64.restype = ctypes.c_int
     lib.oracle_greedy32_grid.argtypes = [vp, i64, i64, i64, vp, vp, ctypes.c_double, vp]
     lib.oracle_greedy32_grid.restype = ctypes.c_int
+    lib.oracle_oct_encode_n.argtypes = [vp, i64, vp]
+    lib.oracle_oct_encode_n.restype = ctypes.c_int
+    lib.oracle_emit_surfels.argtypes = [vp, vp, vp, i64, vp, i64, vp]
+    lib.oracle_emit_surfels.restype = ctypes.c_int
+    lib.oracle_median_nn.argtypes = [vp, i64, vp, i64, vp]
+    lib.oracle_median_nn.restype = ctypes.c_int
+    lib.oracle_prefix_length.argtypes = [ctypes.c_double, ctypes.c_double, i64, i64]
+    lib.oracle_prefix_length.restype = i64
     return lib
 
 
@@ -150,6 +158,41 @@ def along_order64(points, order, lib=None) -> np.ndarray:
     r = np.empty(o.shape[0], dtype=np.float64)
     _check((lib or _load()).oracle_along_order64(_ptr(p), p.shape[0], _ptr(o), o.shape[0], _ptr(r)), False)
     return r
+
+
+def oct_encode(normals, lib=None) -> np.ndarray:
+    """Octahedral codes (int16 [n, 2]) of float32 normals [n, 3]."""
+    nrm = np.ascontiguousarray(np.asarray(normals, dtype=np.float32).reshape(-1, 3))
+    out = np.empty((nrm.shape[0], 2), dtype=np.int16)
+    _check((lib or _load()).oracle_oct_encode_n(_ptr(nrm), nrm.shape[0], _ptr(out)), False)
+    return out
+
+
+def emit_surfels(points, order, normals=None, colors=None, lib=None) -> np.ndarray:
+    """The ordered 20-byte surfel records (uint8 [k, 20]) of ``order``."""
+    p = _points32(points)
+    o = np.ascontiguousarray(np.asarray(order, dtype=np.int32))
+    nrm = None if normals is None else np.ascontiguousarray(np.asarray(normals, dtype=np.float32).reshape(-1, 3))
+    col = None if colors is None else np.ascontiguousarray(np.asarray(colors, dtype=np.uint8).reshape(-1, 3))
+    out = np.empty((o.shape[0], 20), dtype=np.uint8)
+    _check((lib or _load()).oracle_emit_surfels(_ptr(p), _ptr(nrm), _ptr(col), p.shape[0], _ptr(o), o.shape[0],
+                                                _ptr(out)), False)
+    return out
+
+
+def median_nn(points, order, pm: int, lib=None) -> float:
+    """r_m: median over the first ``pm`` ordered surfels of each one's
+    distance to its nearest other surfel of that prefix (Sec. 4.1)."""
+    p = _points32(points)
+    o = np.ascontiguousarray(np.asarray(order, dtype=np.int32))
+    out = np.empty(1, dtype=np.float32)
+    _check((lib or _load()).oracle_median_nn(_ptr(p), p.shape[0], _ptr(o), int(pm), _ptr(out)), False)
+    return out[0]
+
+
+def prefix_length(r: float, r_m: float, pm: int, k: int, lib=None) -> int:
+    """p(r) = pm (r_m / r)^2, rounded up, clamped to [1, k] (Sec. 4.1)."""
+    return int((lib or _load()).oracle_prefix_length(float(r), float(r_m), int(pm), int(k)))
 
 
 def compile_variant(src_text: str, out_path: str):

@@ -43,6 +43,11 @@
  *                            bit-exact to oracle_greedy32 by the test suite
  *                            and exists only so that large inputs can be
  *                            checked in seconds.
+ *   oracle_oct_encode        octahedral code of a normal (2 x snorm16).
+ *   oracle_emit_surfels      the ordered 20-byte surfel records of a prefix.
+ *   oracle_median_nn         r_m: median nearest-neighbour distance within
+ *                            the first p_m ordered surfels (Sec. 4.1).
+ *   oracle_prefix_length     p(r) = p_m (r_m / r)^2, rounded up, in [1, k].
  */
 #include <math.h>
 #include <stdint.h>
@@ -466,5 +471,141 @@ int oracle_greedy32_grid(const float* P, int64_t n, int64_t k, int64_t start,
 
     free(cells); free(cell_of); free(members); free(htab); free(hkey);
     free(tree); free(m); free(sel); free(visit);
+    return ORACLE_OK;
+}
+
+/* -------------------------------------------- ordered surfel buffer (a6) */
+/*
+ * The paper stores an approximation as one contiguous vertex buffer of
+ * surfels (position, normal, material), ordered so that any prefix is a
+ * level of detail (Sec. 3, and the per-surfel size that Table 1 implies:
+ * 20 bytes).  It does not say how the normal and colour are packed.
+ * Readings (listed in the design notes):
+ *   record = x, y, z as binary32 (12 bytes), the normal as an octahedral
+ *   code of two signed 16-bit normalised integers (4 bytes), and the colour
+ *   as r, g, b, a bytes with a = 255 (4 bytes), little-endian;
+ *   octahedral map (Meyer et al. 2010, "On floating-point normal vectors";
+ *   survey by Cigolle et al. 2014): p = (n.x, n.y) / (|n.x| + |n.y| + |n.z|),
+ *   folded for n.z < 0 to ((1 - |p.y|) sgn(p.x), (1 - |p.x|) sgn(p.y)) with
+ *   sgn(0) = +1; each component to round-to-nearest-even(clamp(p, -1, 1) *
+ *   32767) in binary32 without contraction;
+ *   a normal whose |n.x| + |n.y| + |n.z| is zero or not finite, or no normal
+ *   array, codes as (0, 0); no colour array gives 255, 255, 255, 255;
+ *   an order entry outside [0, n) (a non-finite input's -1) gives a NaN
+ *   position, normal code (0, 0) and colour 0, 0, 0, 0.
+ */
+static float sgn_nz(float v) { return v >= 0.0f ? 1.0f : -1.0f; }
+
+static int16_t snorm16(float v)
+{
+    float c = v < -1.0f ? -1.0f : (v > 1.0f ? 1.0f : v);
+    return (int16_t)lrintf(c * 32767.0f);
+}
+
+void oracle_oct_encode(const float* nrm, int16_t* out)
+{
+    float ax = fabsf(nrm[0]), ay = fabsf(nrm[1]), az = fabsf(nrm[2]);
+    float s = ax + ay;
+    float l1 = s + az;
+    if (!(l1 > 0.0f) || !isfinite(l1)) {
+        out[0] = 0;
+        out[1] = 0;
+        return;
+    }
+    float px = nrm[0] / l1;
+    float py = nrm[1] / l1;
+    if (nrm[2] < 0.0f) {
+        float qx = (1.0f - fabsf(py)) * sgn_nz(px);
+        float qy = (1.0f - fabsf(px)) * sgn_nz(py);
+        px = qx;
+        py = qy;
+    }
+    out[0] = snorm16(px);
+    out[1] = snorm16(py);
+}
+
+int oracle_emit_surfels(const float* P, const float* N, const uint8_t* C, int64_t n, const int32_t* order,
+                        int64_t k, uint8_t* out)
+{
+    if (k < 0 || (k > 0 && (!P || !order || !out))) return ORACLE_BAD_ARG;
+    for (int64_t t = 0; t < k; ++t) {
+        uint8_t* r = out + 20 * t;
+        int64_t i = order[t];
+        float pos[3];
+        int16_t code[2] = {0, 0};
+        uint8_t col[4] = {0, 0, 0, 0};
+        if (i < 0 || i >= n) {
+            pos[0] = pos[1] = pos[2] = NAN;
+        } else {
+            memcpy(pos, P + 3 * i, 12);
+            if (N) oracle_oct_encode(N + 3 * i, code);
+            if (C) {
+                col[0] = C[3 * i];
+                col[1] = C[3 * i + 1];
+                col[2] = C[3 * i + 2];
+                col[3] = 255;
+            } else {
+                col[0] = col[1] = col[2] = col[3] = 255;
+            }
+        }
+        memcpy(r, pos, 12);
+        memcpy(r + 12, code, 4);
+        memcpy(r + 16, col, 4);
+    }
+    return ORACLE_OK;
+}
+
+/* ---------------------------------------------- prefix length estimate */
+/*
+ * Sec. 4.1: every prefix of a greedy permutation is an r-net; the prefix
+ * length for a surfel radius r is estimated as p(r) = p_m (r_m / r)^2, with
+ * r_m the median, over the first p_m ordered surfels, of each one's minimum
+ * distance to the other surfels of that prefix.  Readings: distances in
+ * binary32 with the fixed d2 above and a correctly rounded sqrtf; the median
+ * of an even count is the binary32 mean 0.5f * (a + b) of the two middle
+ * values; p(r) is rounded up (the minimal length) and clamped to [1, k].
+ */
+static int cmp_f32(const void* a, const void* b)
+{
+    float x = *(const float*)a, y = *(const float*)b;
+    return (x > y) - (x < y);
+}
+
+int oracle_median_nn(const float* P, int64_t n, const int32_t* order, int64_t pm, float* out_rm)
+{
+    if (pm < 2 || !P || !order || !out_rm) return ORACLE_BAD_ARG;
+    for (int64_t a = 0; a < pm; ++a)
+        if (order[a] < 0 || order[a] >= n) return ORACLE_BAD_ARG;
+    float* nn = (float*)malloc(sizeof(float) * (size_t)pm);
+    if (!nn) return ORACLE_NO_MEM;
+    for (int64_t a = 0; a < pm; ++a) {
+        float m = INFINITY;
+        for (int64_t b = 0; b < pm; ++b) {
+            if (b == a) continue;
+            float d = d2_f32(P + 3 * (int64_t)order[a], P + 3 * (int64_t)order[b]);
+            if (d < m) m = d;
+        }
+        nn[a] = sqrtf(m);
+    }
+    qsort(nn, (size_t)pm, sizeof(float), cmp_f32);
+    if (pm % 2) *out_rm = nn[pm / 2];
+    else *out_rm = 0.5f * (nn[pm / 2 - 1] + nn[pm / 2]);
+    free(nn);
+    return ORACLE_OK;
+}
+
+int64_t oracle_prefix_length(double r, double r_m, int64_t pm, int64_t k)
+{
+    if (k < 1) return 0;
+    if (!(r > 0.0)) return k;
+    double p = ceil((double)pm * (r_m / r) * (r_m / r));
+    if (!(p >= 1.0)) return 1;
+    return p > (double)k ? k : (int64_t)p;
+}
+
+int oracle_oct_encode_n(const float* N, int64_t n, int16_t* out)
+{
+    if (n < 0 || (n > 0 && (!N || !out))) return ORACLE_BAD_ARG;
+    for (int64_t i = 0; i < n; ++i) oracle_oct_encode(N + 3 * i, out + 2 * i);
     return ORACLE_OK;
 }

@@ -202,9 +202,87 @@ def check_grid_equals_plain(P, k, start, lib=None, target=12.0):
     assert same_f32(r1, r2)
 
 
+def oct_decode64(code):
+    """Inverse octahedral map in binary64 (written from the map's
+    definition, independently of the encoder): unit normals [n, 3]."""
+    p = np.asarray(code, dtype=np.float64).reshape(-1, 2) / 32767.0
+    x, y = p[:, 0], p[:, 1]
+    z = 1.0 - np.abs(x) - np.abs(y)
+    neg = z < 0
+    xn = np.where(neg, (1 - np.abs(y)) * np.where(x >= 0, 1.0, -1.0), x)
+    yn = np.where(neg, (1 - np.abs(x)) * np.where(y >= 0, 1.0, -1.0), y)
+    d = np.stack([xn, yn, z], 1)
+    return d / np.linalg.norm(d, axis=1, keepdims=True)
+
+
+def check_surfel_records(lib=None):
+    """Octahedral codes: hand-derived values at the axes, at an exact half
+    (round to nearest even) and on the folded lower hemisphere; the inverse
+    map recovers random unit normals within 4e-4 rad.  Records: byte layout,
+    absent normals / colours, out-of-range order entries."""
+    hand = {(0, 0, 1): (0, 0), (0, 0, -1): (32767, 32767), (1, 0, 0): (32767, 0), (-1, 0, 0): (-32767, 0),
+            (0, 1, 0): (0, 32767), (0, -1, 0): (0, -32767), (0.5, -0.25, -0.25): (24575, -16384),
+            (0.70710677, 0.70710677, 0.0): (16384, 16384), (0, 0, 0): (0, 0)}
+    for n, c in hand.items():
+        got = tuple(int(v) for v in oracle.oct_encode(np.array([n], dtype=np.float32), lib=lib)[0])
+        assert got == c, "octahedral code of %s: %s, expected %s" % (n, got, c)
+    rng = np.random.default_rng(11)
+    v = rng.normal(size=(20000, 3))
+    v /= np.linalg.norm(v, axis=1, keepdims=True)
+    v32 = v.astype(np.float32)
+    d = oct_decode64(oracle.oct_encode(v32, lib=lib))
+    ang = np.arccos(np.clip((d * v32.astype(np.float64)).sum(1), -1.0, 1.0))
+    assert ang.max() < 4e-4, "octahedral round trip error %g rad" % ang.max()
+    # records
+    P = np.array([[1.5, -2.0, 3.25], [0.0, 0.0, 0.0], [7.0, 8.0, 9.0]], dtype=np.float32)
+    N = np.array([[0, 0, -1], [1, 0, 0], [0, 0, 0]], dtype=np.float32)
+    C = np.array([[10, 20, 30], [40, 50, 60], [70, 80, 90]], dtype=np.uint8)
+    order = np.array([2, 0, -1, 1], dtype=np.int32)
+    rec = oracle.emit_surfels(P, order, N, C, lib=lib)
+    assert rec.shape == (4, 20)
+    pos = rec[:, :12].copy().view(np.float32).reshape(4, 3)
+    code = rec[:, 12:16].copy().view(np.int16).reshape(4, 2)
+    col = rec[:, 16:20]
+    assert np.array_equal(pos[[0, 1, 3]], P[[2, 0, 1]]) and np.isnan(pos[2]).all()
+    assert code.tolist() == [[0, 0], [32767, 32767], [0, 0], [32767, 0]]
+    assert col.tolist() == [[70, 80, 90, 255], [10, 20, 30, 255], [0, 0, 0, 0], [40, 50, 60, 255]]
+    bare = oracle.emit_surfels(P, order[[0, 1]], None, None, lib=lib)
+    assert (bare[:, 12:16] == 0).all() and (bare[:, 16:20] == 255).all()
+
+
+def check_prefix_estimate(lib=None):
+    """r_m on point sets whose nearest-neighbour distances are known: a unit
+    lattice (every NN distance 1), points on a line with gaps 1, 2, 3, 4
+    (median 2) and 1 .. 5 (even count: mean of the middle two, 2.5), only the
+    first p_m ordered points counting; on a greedy order, r_m is at least the
+    covering radius of the prefix (an r-net: no two prefix points closer).
+    p(r) = p_m (r_m / r)^2 at r = r_m, r_m / 2, 2 r_m, and clamped to [1, k]."""
+    L = np.stack(np.meshgrid(np.arange(10), np.arange(10), np.arange(10), indexing="ij"), -1)
+    L = L.reshape(-1, 3).astype(np.float32)
+    ident = np.arange(L.shape[0], dtype=np.int32)
+    assert oracle.median_nn(L, ident, 1000, lib=lib) == 1.0
+    assert oracle.median_nn(L, ident, 500, lib=lib) == 1.0
+    line = np.array([[0, 0, 0], [1, 0, 0], [3, 0, 0], [6, 0, 0], [10, 0, 0], [15, 0, 0], [100, 0, 0]],
+                    dtype=np.float32)
+    o7 = np.array([4, 0, 3, 1, 2, 5, 6], dtype=np.int32)
+    assert oracle.median_nn(line, o7, 5, lib=lib) == 2.0   # {10, 0, 6, 1, 3}: NN 4, 1, 3, 1, 2
+    assert oracle.median_nn(line, o7, 6, lib=lib) == 2.5   # + 15: NN 4, 1, 3, 1, 2, 5
+    P = cases.random_cloud(2000, 21)
+    o, r = oracle.greedy32(P, 600, 3, lib=lib)
+    for pm in (50, 200, 600):
+        assert oracle.median_nn(P, o, pm, lib=lib) >= r[pm - 1]
+    assert oracle.prefix_length(0.1, 0.1, 1000, 10**6, lib=lib) == 1000
+    assert oracle.prefix_length(0.05, 0.1, 1000, 10**6, lib=lib) == 4000
+    assert oracle.prefix_length(0.2, 0.1, 1000, 10**6, lib=lib) == 250
+    assert oracle.prefix_length(0.001, 0.1, 1000, 5000, lib=lib) == 5000
+    assert oracle.prefix_length(50.0, 0.1, 1000, 5000, lib=lib) == 1
+
+
 def pin_battery(lib=None):
     """The quick subset used against planted mistakes."""
     check_closed_forms(lib)
+    check_surfel_records(lib)
+    check_prefix_estimate(lib)
     check_bruteforce(lib, sizes=(2, 5, 17, 40))
     check_two_approx(lib, trials=4)
     P = cases.random_cloud(300, 9)

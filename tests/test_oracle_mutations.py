@@ -30,6 +30,18 @@ MUTANTS = {
     "splitmix_constant": ("z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;",
                           "z = (z ^ (z >> 27)) * 0x94D049BB133111EAull;"),
     "fp64_dropped_dz": ("    double dz = a[2] - b[2];", "    double dz = 0.0 * (a[2] - b[2]);"),
+    "oct_no_fold": ("    if (nrm[2] < 0.0f) {\n        float qx", "    if (0) {\n        float qx"),
+    "oct_fold_swapped": ("        float qx = (1.0f - fabsf(py)) * sgn_nz(px);",
+                         "        float qx = (1.0f - fabsf(px)) * sgn_nz(px);"),
+    "oct_truncates": ("    return (int16_t)lrintf(c * 32767.0f);", "    return (int16_t)(c * 32767.0f);"),
+    "oct_l2_norm": ("    float l1 = s + az;", "    float l1 = sqrtf(nrm[0] * nrm[0] + nrm[1] * nrm[1] + nrm[2] * nrm[2]);"),
+    "emit_alpha_zero": ("                col[3] = 255;\n            } else {", "                col[3] = 0;\n            } else {"),
+    "median_lower_middle": ("    else *out_rm = 0.5f * (nn[pm / 2 - 1] + nn[pm / 2]);",
+                            "    else *out_rm = nn[pm / 2 - 1];"),
+    "nn_includes_self": ("            if (b == a) continue;\n            float d = d2_f32",
+                         "            float d = d2_f32"),
+    "prefix_linear": ("    double p = ceil((double)pm * (r_m / r) * (r_m / r));",
+                      "    double p = ceil((double)pm * (r_m / r));"),
     "along_order_max": ("            if (d < best) best = d;\n        }\n        r64[t] = sqrt(best);",
                         "            if (d > best || isinf(best)) best = d;\n        }\n        r64[t] = sqrt(best);"),
 }
