@@ -174,6 +174,36 @@ def bench_main(args, bs, torch, np):
     return pts, surf, out_o, ms, ev_ms, kern_ms / 1e3, lat, kernel, plan, lead
 
 
+def bench_emit(bs, torch, surf, pts, order):
+    """The ordered 20-byte surfel records of the headline ordering (gather of
+    position, normal, colour; 51 algorithmic bytes per record: 4 B index,
+    12 + 12 + 3 B read, 20 B written) and r_m over the first 1000 picks."""
+    nrm = surf.normals.contiguous()
+    col = surf.colors.contiguous()
+    k = int(order.shape[0])
+    out = torch.empty((k, 20), dtype=torch.uint8, device=pts.device)
+    stream = torch.cuda.current_stream()
+    bs.emit_surfels(pts, order, nrm, col, out=out)
+    reps = 50
+    b, e = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    b.record(stream)
+    for _ in range(reps):
+        bs.emit_surfels(pts, order, nrm, col, out=out)
+    e.record(stream)
+    torch.cuda.synchronize()
+    secs = b.elapsed_time(e) / 1e3 / reps
+    rm_b, rm_e = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    rm_b.record(stream)
+    r_m = bs.prefix_median_nn(pts, order, 1000)
+    rm_e.record(stream)
+    torch.cuda.synchronize()
+    abytes = 51 * k
+    return {"records": k, "record_bytes": 20, "seconds": secs, "algorithmic_bytes": abytes,
+            "achieved_GBs": abytes / secs / 1e9, "frac_of_hbm_peak": abytes / secs / 1e9 / HBM_PEAK_GBS,
+            "median_nn_p_m": 1000, "r_m": r_m, "median_nn_seconds": rm_b.elapsed_time(rm_e) / 1e3,
+            "note": "one launch of 1,024 workgroups: at this size launch latency, not HBM, bounds it"}
+
+
 def bench_full_scan(bs, torch, pts, k):
     tune = bs.tuning(kernel=bs.KERNEL_COOP, block=1024, per_thread=16)
     n = int(pts.shape[0])
@@ -521,6 +551,9 @@ def main():
                                 "achieved_GBs": 16 * live / ls / 1e9,
                                 "frac_of_hbm_peak": 16 * live / ls / 1e9 / HBM_PEAK_GBS,
                                 "time_source": "device wall clock from pick 0 to the scan's last pick"}
+    rec["emit"] = bench_emit(bs, torch, surf, pts, out_o)
+    log("emit: %.1f us for %d records (%.0f GB/s algorithmic); r_m in %.1f us"
+        % (rec["emit"]["seconds"] * 1e6, k, rec["emit"]["achieved_GBs"], rec["emit"]["median_nn_seconds"] * 1e6))
     if not args.no_full_scan:
         fs, fo = bench_full_scan(bs, torch, pts, k)
         fs["matches_grid_kernel"] = bool(torch.equal(fo, out_o))

@@ -191,6 +191,64 @@ int bs_auto_kernel(int64_t n, int64_t k);
  */
 int bs_plan_describe(int64_t n, int64_t k, const bs_tuning* tuning, bs_tuning* out);
 
+/* ------------------------------------------------- ordered surfel buffer */
+
+/*
+ * One surfel of an ordered vertex buffer: the paper stores an approximation
+ * as one contiguous buffer of surfels (position, normal, material) whose
+ * every prefix is a level of detail (Sec. 3); Table 1 implies 20 bytes per
+ * surfel.  The packing is this library's reading (the paper does not give
+ * it): position as binary32; the normal as an octahedral code (Meyer et al.
+ * 2010): p = (n.x, n.y) / (|n.x| + |n.y| + |n.z|), folded to
+ * ((1 - |p.y|) sgn p.x, (1 - |p.x|) sgn p.y) for n.z < 0 (sgn 0 = +1), each
+ * component round-to-nearest-even(clamp(p, -1, 1) * 32767); colour r, g, b
+ * and a = 255.
+ */
+typedef struct {
+    float x, y, z;
+    int16_t normal[2];  /* octahedral code; (0, 0) for a zero / non-finite normal or no normals */
+    uint8_t rgba[4];    /* (255, 255, 255, 255) without colours */
+} bs_surfel;
+
+/*
+ * Gather the ordered surfels: d_out[t] = record of candidate d_order[t],
+ * t < k.  d_normals (float[n][3]) and d_colors (uint8[n][3]) may be NULL.
+ * An order entry outside [0, n) (a non-finite input's -1) gives a record
+ * with NaN position, normal (0, 0) and colour (0, 0, 0, 0).  All pointers
+ * are device memory; the call enqueues one kernel on `stream`.
+ * Errors: BS_ERR_INVALID_ARG (null pointers with k > 0, k < 0, n < 0),
+ * BS_ERR_HIP.
+ */
+int bs_emit_surfels(const float* d_points, const float* d_normals, const uint8_t* d_colors, int64_t n,
+                    const int32_t* d_order, int64_t k, bs_surfel* d_out, void* stream);
+
+/*
+ * r_m of the prefix-length estimate (Sec. 4.1): the median, over the first
+ * p_m ordered surfels, of each one's distance to its nearest other surfel in
+ * that prefix (binary32, d2 = (dx*dx + dy*dy) + dz*dz, correctly rounded
+ * sqrt; an even count takes 0.5f * (a + b) of the middle two).  Writes one
+ * float to d_out_rm (device memory) on `stream`; NaN if an order entry lies
+ * outside [0, n).  2 <= p_m <= 4096.
+ * Errors: BS_ERR_INVALID_ARG, BS_ERR_HIP.
+ */
+int bs_prefix_median_nn(const float* d_points, int64_t n, const int32_t* d_order, int64_t p_m, float* d_out_rm,
+                        void* stream);
+
+/*
+ * Estimated prefix length for surfel radius r (Sec. 4.1):
+ * p(r) = p_m (r_m / r)^2, rounded up and clamped to [1, k]; k when r <= 0.
+ * Host only.
+ */
+int64_t bs_prefix_length(double r, double r_m, int64_t p_m, int64_t k);
+
+/*
+ * Exact prefix length for radius r from an ordering's radii (host memory,
+ * h_radius[t] = covering radius of the t-prefix, non-increasing): the least
+ * t >= 1 with h_radius[t] <= r, so that every candidate lies within r of the
+ * first t surfels; k if there is none.  Host only.
+ */
+int64_t bs_prefix_for_radius(const float* h_radius, int64_t k, float r);
+
 /* ------------------------------------------------------------ autotuner */
 
 /*

@@ -85,6 +85,14 @@ def load():
     lib.bs_auto_kernel.restype = i32
     lib.bs_plan_describe.argtypes = [i64, i64, vp, vp]
     lib.bs_plan_describe.restype = i32
+    lib.bs_emit_surfels.argtypes = [vp, vp, vp, i64, vp, i64, vp, vp]
+    lib.bs_emit_surfels.restype = i32
+    lib.bs_prefix_median_nn.argtypes = [vp, i64, vp, i64, vp, vp]
+    lib.bs_prefix_median_nn.restype = i32
+    lib.bs_prefix_length.argtypes = [ctypes.c_double, ctypes.c_double, i64, i64]
+    lib.bs_prefix_length.restype = i64
+    lib.bs_prefix_for_radius.argtypes = [vp, i64, ctypes.c_float]
+    lib.bs_prefix_for_radius.restype = i64
     lib.bs_autotune.argtypes = [vp, i64, i64, u64, tp, vp]
     lib.bs_autotune.restype = i32
     lib.bs_autotune_lookup.argtypes = [i64, i64, tp]
@@ -269,6 +277,52 @@ def order(points, k: Optional[int] = None, seed: int = 0, *, normals=None, color
         if int(out_order[0]) == -1:
             raise ValueError("non-finite candidate coordinates")
     return out_order, out_radius
+
+
+def emit_surfels(points, order, normals=None, colors=None, stream=None, out=None):
+    """The ordered 20-byte surfel records (``bs_emit_surfels``) of ``order``:
+    a uint8 tensor [k, 20] on the points' device (position f32 x 3,
+    octahedral normal code int16 x 2, RGBA8)."""
+    import torch
+    lib = load()
+    pts = _prep_points(points)
+    o = order if order.dtype == torch.int32 else order.to(torch.int32)
+    o = o.contiguous()
+    k = int(o.shape[0])
+    if out is None:
+        out = torch.empty((k, 20), dtype=torch.uint8, device=pts.device)
+    nrm = None if normals is None else normals.to(torch.float32).contiguous()
+    col = None if colors is None else colors.to(torch.uint8).contiguous()
+    _check(lib.bs_emit_surfels(_ptr(pts), _ptr(nrm) if nrm is not None else None,
+                               _ptr(col) if col is not None else None, int(pts.shape[0]), _ptr(o), k, _ptr(out),
+                               _stream_handle(stream)))
+    return out
+
+
+def prefix_median_nn(points, order, pm: int = 1000, stream=None) -> float:
+    """r_m (``bs_prefix_median_nn``): median nearest-neighbour distance within
+    the first ``pm`` ordered surfels (paper Sec. 4.1)."""
+    import torch
+    lib = load()
+    pts = _prep_points(points)
+    o = (order if order.dtype == torch.int32 else order.to(torch.int32)).contiguous()
+    out = torch.empty(1, dtype=torch.float32, device=pts.device)
+    _check(lib.bs_prefix_median_nn(_ptr(pts), int(pts.shape[0]), _ptr(o), int(pm), _ptr(out), _stream_handle(stream)))
+    return float(out.cpu()[0])
+
+
+def prefix_length(r: float, r_m: float, pm: int, k: int) -> int:
+    """p(r) = pm (r_m / r)^2 rounded up, in [1, k] (``bs_prefix_length``)."""
+    return int(load().bs_prefix_length(float(r), float(r_m), int(pm), int(k)))
+
+
+def prefix_for_radius(radius, r: float) -> int:
+    """Least prefix whose covering radius is <= r (``bs_prefix_for_radius``);
+    ``radius`` is an ordering's radius array (host copy taken if needed)."""
+    import numpy as np
+    h = radius.detach().cpu().numpy() if hasattr(radius, "detach") else np.asarray(radius)
+    h = np.ascontiguousarray(h, dtype=np.float32)
+    return int(load().bs_prefix_for_radius(h.ctypes.data_as(ctypes.c_void_p), int(h.shape[0]), float(r)))
 
 
 def wall_clock_hz() -> float:

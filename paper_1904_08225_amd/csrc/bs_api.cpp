@@ -2,6 +2,7 @@
 // sizing, kernel choice and enqueueing.  See include/bluesurfels.h.
 #include <hip/hip_runtime.h>
 
+#include <cmath>
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
@@ -203,6 +204,50 @@ int bs_plan_describe(int64_t n, int64_t k, const bs_tuning* tuning, bs_tuning* o
     }
     *out = d;
     return BS_OK;
+}
+
+int bs_emit_surfels(const float* d_points, const float* d_normals, const uint8_t* d_colors, int64_t n,
+                    const int32_t* d_order, int64_t k, bs_surfel* d_out, void* stream) {
+    static_assert(sizeof(bs_surfel) == 20, "surfel record size");
+    if (k < 0 || n < 0) return set_error(BS_ERR_INVALID_ARG, "n=%lld k=%lld", (long long)n, (long long)k);
+    if (k == 0) return BS_OK;
+    if (!d_points || !d_order || !d_out) return set_error(BS_ERR_INVALID_ARG, "null points, order or output");
+    const hipError_t e = launch_emit(d_points, d_normals, d_colors, n, d_order, k, d_out,
+                                     reinterpret_cast<hipStream_t>(stream));
+    if (e != hipSuccess) return set_error(BS_ERR_HIP, "emit launch: %s", hipGetErrorString(e));
+    return BS_OK;
+}
+
+int bs_prefix_median_nn(const float* d_points, int64_t n, const int32_t* d_order, int64_t p_m, float* d_out_rm,
+                        void* stream) {
+    if (!d_points || !d_order || !d_out_rm) return set_error(BS_ERR_INVALID_ARG, "null pointer");
+    if (p_m < 2 || p_m > kMaxPrefixPm || n < p_m)
+        return set_error(BS_ERR_INVALID_ARG, "p_m=%lld outside [2, min(n, %d)]", (long long)p_m, kMaxPrefixPm);
+    const hipError_t e = launch_median_nn(d_points, n, d_order, int(p_m), d_out_rm,
+                                          reinterpret_cast<hipStream_t>(stream));
+    if (e != hipSuccess) return set_error(BS_ERR_HIP, "median launch: %s", hipGetErrorString(e));
+    return BS_OK;
+}
+
+int64_t bs_prefix_length(double r, double r_m, int64_t p_m, int64_t k) {
+    if (k < 1) return 0;
+    if (!(r > 0.0)) return k;
+    const double q = r_m / r;
+    const double p = std::ceil(double(p_m) * q * q);
+    if (!(p >= 1.0)) return 1;
+    return p > double(k) ? k : int64_t(p);
+}
+
+int64_t bs_prefix_for_radius(const float* h_radius, int64_t k, float r) {
+    if (!h_radius || k < 1) return k < 1 ? 0 : k;
+    // radii are non-increasing from index 1: binary search for the first <= r
+    int64_t lo = 1, hi = k;  // answer in [lo, hi]; hi = k means none
+    while (lo < hi) {
+        const int64_t mid = lo + (hi - lo) / 2;
+        if (h_radius[mid] <= r) hi = mid;
+        else lo = mid + 1;
+    }
+    return lo;
 }
 
 size_t bs_workspace_size(int64_t n, int64_t k, const bs_tuning* tuning) {

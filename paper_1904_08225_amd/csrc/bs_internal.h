@@ -97,6 +97,13 @@ hipError_t launch_serve(const ServeRing& ring, int workgroups, uint32_t idle_pol
 int batch_plan_execute(BatchPlan* p, const float* pts, int32_t* out_order, float* out_radius, void* ws,
                        size_t ws_bytes, hipStream_t st);
 
+// Ordered surfel records and the prefix-length estimate (bs_emit.hip).
+constexpr int kMaxPrefixPm = 4096;  // largest p_m of the median estimate
+hipError_t launch_emit(const float* pts, const float* nrm, const uint8_t* col, int64_t n, const int32_t* order,
+                       int64_t k, void* out, hipStream_t st);
+hipError_t launch_median_nn(const float* pts, int64_t n, const int32_t* order, int pm, float* out_rm,
+                            hipStream_t st);
+
 // Error reporting (bs_api.cpp).
 int set_error(int code, const char* fmt, ...);
 

@@ -130,3 +130,27 @@ def test_plan_describe(lib):
     out = bs.Tuning()
     assert lib.bs_plan_describe(10, 11, None, ctypes.byref(out)) == bs.BS_ERR_INVALID_ARG
     assert lib.bs_plan_describe(10, 5, None, None) == bs.BS_ERR_INVALID_ARG
+
+
+def test_prefix_host_functions(lib):
+    """bs_prefix_length equals the oracle's formula; bs_prefix_for_radius
+    equals a linear scan over the oracle's radii (least t >= 1 with
+    radius[t] <= r, else k); argument errors of bs_emit_surfels."""
+    import numpy as np
+    import oracle
+    from tests import cases
+    for r, rm, pm, k in ((0.1, 0.1, 1000, 10**6), (0.05, 0.1, 1000, 10**6), (0.3, 0.1, 1000, 10**6),
+                         (1e-4, 0.1, 1000, 5000), (7.0, 0.1, 1000, 5000), (0.0, 0.1, 1000, 77), (0.02, 0.013, 250, 900)):
+        assert bs.prefix_length(r, rm, pm, k) == oracle.prefix_length(r, rm, pm, k)
+    P = cases.random_cloud(3000, 5)
+    o, rad = oracle.greedy32(P, 800, 2)
+    for r in (1e9, float(rad[1]), float(rad[57]), float(rad[57]) * 1.0001, float(rad[799]), float(rad[799]) * 0.5, 0.0):
+        ok = [t for t in range(1, 800) if rad[t] <= r]
+        assert bs.prefix_for_radius(rad, r) == (ok[0] if ok else 800)
+    assert bs.prefix_for_radius(rad[:1], 0.0) == 1
+    fake = ctypes.c_void_p(0x1000)
+    assert lib.bs_emit_surfels(fake, None, None, 10, fake, -1, fake, None) == bs.BS_ERR_INVALID_ARG
+    assert lib.bs_emit_surfels(None, None, None, 10, fake, 5, fake, None) == bs.BS_ERR_INVALID_ARG
+    assert lib.bs_emit_surfels(None, None, None, 0, None, 0, None, None) == bs.BS_OK
+    assert lib.bs_prefix_median_nn(fake, 10, fake, 1, fake, None) == bs.BS_ERR_INVALID_ARG
+    assert lib.bs_prefix_median_nn(fake, 5000, fake, 4097, fake, None) == bs.BS_ERR_INVALID_ARG
