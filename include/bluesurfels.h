@@ -346,7 +346,8 @@ void bs_batch_plan_destroy(bs_batch_plan* plan);
  * generates approximations per scene node ahead of rendering, Sec. 3.4 and
  * Sec. 5.2; here orderings are requested and answered while others run).
  * Jobs are submitted from any host thread.  A persistent kernel of
- * `workgroups` ordering workers stays resident on the device; a dispatcher
+ * `workgroups` ordering workers (1024 threads each) stays resident on the
+ * device, leaving the other compute units to the preprocessing; a dispatcher
  * thread admits pending jobs, in arrival order, into micro-batches while the
  * job fits the remaining budget, builds their grids on a preprocessing
  * stream and publishes them into a device ring, from which each idle worker
@@ -365,7 +366,8 @@ typedef struct {
     int32_t max_jobs_per_batch;  /* 0 = 512 */
     int32_t poll_us;             /* dispatcher polling period while busy; 0 = 50 */
     float cell_points;           /* grid cell target, 0 = 8 */
-    int32_t workgroups;          /* resident ordering workers, 0 = one per compute unit */
+    int32_t workgroups;          /* resident 1024-thread ordering workers (each holds a whole
+                                    compute unit), 0 = half the compute units */
     int32_t reserved[6];         /* must be zero */
 } bs_server_config;
 

@@ -525,15 +525,18 @@ __global__ void publish_kernel(const ObjDesc* __restrict__ desc, const int32_t* 
 // device-coherent loads (ring slots are rewritten while the kernel runs),
 // orders that object and sets its completion flag.  A workgroup exits when
 // stop is set and nothing is left to claim, or after idle_polls empty polls.
-__global__ void __launch_bounds__(kBatchBlock)
+// Workers have 1024 threads: a worker then holds a whole CU (its waves take
+// most of each SIMD's registers), so as many workers as half the CUs leave
+// the other CUs free for the preprocessing kernels of later micro-batches.
+__global__ void __launch_bounds__(kWideBlock)
     serve_kernel(const ObjDesc* __restrict__ slots, uint32_t cap, uint32_t* head, const uint32_t* tail,
                  const uint32_t* stop, uint32_t idle_polls) {
-    __shared__ GridLdsMP<kBatchBlock / 64, kBatchMaxBlocks> L;
+    __shared__ GridLdsMP<kWideBlock / 64, kBatchMaxBlocks> L;
     __shared__ int s_item;
     __shared__ __align__(16) uint32_t s_desc[(sizeof(ObjDesc) + 3) / 4];
     static_assert(sizeof(ObjDesc) % 4 == 0, "descriptor words");
     constexpr int kWords = int(sizeof(ObjDesc) / 4);
-    static_assert(kWords <= kBatchBlock, "one word per thread");
+    static_assert(kWords <= kWideBlock, "one word per thread");
     for (;;) {
         if (threadIdx.x == 0) {
             int item = -1;
@@ -566,12 +569,12 @@ __global__ void __launch_bounds__(kBatchBlock)
         const GridObject& o = d.o;
         if (o.k > 0) {
             if (d.nonfinite) {
-                for (int t = threadIdx.x; t < o.k; t += kBatchBlock) {
+                for (int t = threadIdx.x; t < o.k; t += kWideBlock) {
                     o.order[t] = -1;
                     if (o.radius) o.radius[t] = __builtin_nanf("");
                 }
             } else {
-                grid_order_object_mp<kBatchBlock, kBatchMaxBlocks>(o, L);
+                grid_order_object_mp<kWideBlock, kBatchMaxBlocks>(o, L);
             }
         }
         __syncthreads();
@@ -977,7 +980,7 @@ int batch_plan_publish(BatchPlan* p, const float* pts, void* ws, size_t ws_bytes
 size_t serve_slot_bytes() { return sizeof(ObjDesc); }
 
 hipError_t launch_serve(const ServeRing& ring, int workgroups, uint32_t idle_polls, hipStream_t st) {
-    hipLaunchKernelGGL(serve_kernel, dim3(workgroups), dim3(kBatchBlock), 0, st,
+    hipLaunchKernelGGL(serve_kernel, dim3(workgroups), dim3(kWideBlock), 0, st,
                        static_cast<const ObjDesc*>(ring.slots), ring.cap, ring.head, ring.tail, ring.stop,
                        idle_polls);
     return hipGetLastError();

@@ -1,8 +1,10 @@
 // bs_server.cpp -- serving loop with continuous batching under an HBM budget.
 //
 // Requests (ordering jobs of any size) are submitted from any host thread.
-// A persistent kernel of ordering workers (one workgroup per compute unit by
-// default) stays resident on the device and takes jobs from a device ring.
+// A persistent kernel of ordering workers (1024-thread workgroups, each
+// holding a whole compute unit, on half the compute units by default, so that
+// the preprocessing kernels of later micro-batches find free CUs) stays
+// resident on the device and takes jobs from a device ring.
 // A dispatcher thread admits pending jobs in arrival order while they fit the
 // HBM budget, groups the admitted jobs into micro-batches, copies their
 // candidates into one staging buffer, builds all their grids with the
@@ -365,7 +367,7 @@ int bs_server_create(const bs_server_config* cfg, bs_server** out) {
     hipError_t e = hipSetDevice(s->device);
     int cus = 0;
     if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, s->device);
-    s->workgroups = cfg->workgroups > 0 ? cfg->workgroups : std::max(cus, 1);
+    s->workgroups = cfg->workgroups > 0 ? cfg->workgroups : std::max(cus / 2, 1);
     if (e == hipSuccess) e = hipStreamCreateWithFlags(&s->prep, hipStreamNonBlocking);
     if (e == hipSuccess) e = hipStreamCreateWithFlags(&s->serve, hipStreamNonBlocking);
     if (e == hipSuccess) e = hipEventCreateWithFlags(&s->serve_end, hipEventDisableTiming);
