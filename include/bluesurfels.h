@@ -91,7 +91,9 @@ typedef struct {
     float cell_points;     /* grid kernel: target mean candidates per cell (0 = auto) */
     int32_t picks;         /* grid kernel: most picks per round, 0 = auto, 1 = one pick
                               per round, 2..32 = several exact picks per round (same
-                              result; see bs_order_ex) */
+                              result; see bs_order_ex).  Cooperative full scan
+                              (BS_KERNEL_COOP): 2..32 = several exact picks per step,
+                              every workgroup a bucket offering its two best keys */
     int32_t lead_picks;    /* grid kernel with several picks per round: the first picks
                               come from the cooperative full scan over all CUs, which
                               then hands every candidate's distance to the grid kernel

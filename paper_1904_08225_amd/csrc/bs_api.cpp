@@ -63,6 +63,7 @@ struct Plan {
     float cell_points = kDefaultCellPoints;
     int lead = 0;          // picks made by a leading cooperative full scan (0: none)
     ScanShape lead_shape;  // its launch shape
+    int scan_picks = 1;    // cooperative full scan: most exact picks per step
 };
 
 // Resolve the kernel and its launch shape.
@@ -113,6 +114,11 @@ int plan_single(int64_t n, int64_t k, const bs_tuning* t, Plan* p) {
             return set_error(BS_ERR_UNSUPPORTED, "n=%lld does not fit one workgroup", (long long)n);
         if (want == BS_KERNEL_COOP && p->shape.groups > cus * 2)
             return set_error(BS_ERR_UNSUPPORTED, "cooperative grid of %d groups too large", p->shape.groups);
+        if (want == BS_KERNEL_COOP && t && t->picks > 1) {
+            if (!scan_several_supported(p->shape))
+                return set_error(BS_ERR_UNSUPPORTED, "no several-picks cooperative scan for this shape");
+            p->scan_picks = t->picks;
+        }
         p->kernel = want;
         return BS_OK;
     }
@@ -121,6 +127,7 @@ int plan_single(int64_t n, int64_t k, const bs_tuning* t, Plan* p) {
 
 size_t workspace_for(int64_t n, const Plan& p) {
     if (p.kernel == BS_KERNEL_GRID) return grid_layout(n, p.grid_block).total;
+    if (p.scan_picks > 1) return grid_layout(n, 1024).total;
     return scan_workspace_bytes(p.shape);
 }
 
@@ -201,6 +208,7 @@ int bs_plan_describe(int64_t n, int64_t k, const bs_tuning* tuning, bs_tuning* o
         d.block = p.shape.block;
         d.per_thread = p.shape.per_thread;
         d.groups = p.shape.groups;
+        d.picks = p.scan_picks;
     }
     *out = d;
     return BS_OK;
@@ -287,6 +295,9 @@ static int order_impl(const float* d_points, int64_t n, int64_t k, uint64_t seed
         e = launch_grid(d_points, int(n), int(k), int(start), d_out_order, d_out_radius, d_workspace,
                         plan.cell_points, plan.grid_block, plan.grid_picks, d_ticks, st, ev, plan.lead,
                         plan.lead > 0 ? &plan.lead_shape : nullptr);
+    } else if (plan.scan_picks > 1) {
+        e = launch_scan_several(plan.shape, d_points, int(n), int(k), int(start), d_out_order, d_out_radius,
+                                d_workspace, d_ticks, plan.scan_picks, st, ev);
     } else {
         DevHeader* hdr = reinterpret_cast<DevHeader*>(d_workspace);
         void* scratch = static_cast<char*>(d_workspace) + align_up(sizeof(DevHeader));

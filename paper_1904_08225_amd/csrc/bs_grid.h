@@ -58,6 +58,18 @@ int grid_block_size(int64_t n);
 // > 1 selects the several-picks-per-round kernel (at most `picks` per round).
 int grid_max_blocks(int block, int picks);
 struct KernelEvents;
+// Candidates in Morton order (validation, codes, radix sort, gather) in the
+// grid workspace, for the sorted cooperative scan.
+struct DevHeader;
+struct SortedPoints {
+    DevHeader* hdr;
+    const float4* xyzm;        // [n] x, y, z, +inf in Morton order
+    const uint32_t* ids;       // [n] original index of each
+    const int32_t* start_pos;  // device: sorted position of the start
+    void* slots;               // exchange records of the cooperative scan
+};
+hipError_t launch_sorted_points(const float* pts, int n, int start, void* ws, hipStream_t st, SortedPoints* out);
+
 // lead >= 2 (several-picks kernel only): picks 0 .. lead-1 come from the
 // cooperative full scan of shape *lead_shape, which hands its state to the
 // grid kernel; otherwise the grid kernel makes every pick.

@@ -131,6 +131,16 @@ __global__ void gather_kernel(const float* __restrict__ pts, const uint32_t* __r
     }
 }
 
+// Candidates in Morton order for the sorted full scan: x, y, z, m = +inf.
+__global__ void sorted_gather_kernel(const float* __restrict__ pts, const uint32_t* __restrict__ ids, int n,
+                                     int start, GridHeader* gh, float4* __restrict__ xyzm) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const uint32_t id = ids[i];
+    xyzm[i] = make_float4(pts[3 * id + 0], pts[3 * id + 1], pts[3 * id + 2], INFINITY);
+    if (int(id) == start) gh->start_pos = i;
+}
+
 // One thread per cell: exact member box, start/count, best and second key
 // of the members' m (chosen candidates, m = -1, have none).
 __global__ void cell_build_kernel(const int32_t* __restrict__ cstart, int n,
@@ -323,6 +333,39 @@ GridLayout grid_layout(int64_t n, int block) {
     g.temp_bytes = sort_bytes > scan_bytes ? sort_bytes : scan_bytes;
     g.total = off;
     return g;
+}
+
+hipError_t launch_sorted_points(const float* pts, int n, int start, void* ws, hipStream_t st, SortedPoints* out) {
+    const GridLayout g = grid_layout(n, 1024);
+    char* base = static_cast<char*>(ws);
+    DevHeader* hdr = reinterpret_cast<DevHeader*>(base + g.dev_header);
+    GridHeader* gh = reinterpret_cast<GridHeader*>(base + g.grid_header);
+    uint32_t* codes = reinterpret_cast<uint32_t*>(base + g.codes);
+    uint32_t* vals = reinterpret_cast<uint32_t*>(base + g.vals);
+    uint32_t* codes_s = reinterpret_cast<uint32_t*>(base + g.codes_sorted);
+    uint32_t* ids = reinterpret_cast<uint32_t*>(base + g.ids);
+    float4* xyzm = reinterpret_cast<float4*>(base + g.xyzm);
+    void* temp = base + g.temp;
+    hipError_t e = launch_init_header(hdr, st);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(init_grid_header_kernel, dim3(1), dim3(64), 0, st, gh);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    if ((e = launch_validate(pts, n, hdr, st)) != hipSuccess) return e;
+    const int tb = 256;
+    const int nblk = (n + tb - 1) / tb;
+    hipLaunchKernelGGL(morton_kernel, dim3(nblk), dim3(tb), 0, st, pts, n, hdr, codes, vals);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    size_t tbytes = g.temp_bytes;
+    e = hipcub::DeviceRadixSort::SortPairs(temp, tbytes, codes, codes_s, vals, ids, n, 0, 3 * kMortonBits, st);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(sorted_gather_kernel, dim3(nblk), dim3(tb), 0, st, pts, ids, n, start, gh, xyzm);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    out->hdr = hdr;
+    out->xyzm = xyzm;
+    out->ids = ids;
+    out->start_pos = &gh->start_pos;
+    out->slots = base + g.lead_slots;
+    return hipSuccess;
 }
 
 int grid_block_size(int64_t n) { return n > (int64_t(1) << 16) ? 512 : 256; }

@@ -61,6 +61,14 @@ hipError_t launch_scan(const ScanShape& s, const float* pts, int n, int k, int s
                        uint64_t* ticks, hipStream_t st, const KernelEvents* ev = nullptr,
                        int k_stop = -1, float* m_out = nullptr, uint32_t* handoff = nullptr);
 
+// Several exact picks per step (bs_scan_mp.hip): the candidates in Morton
+// order in the grid workspace `ws` (grid_layout(n, 1024).total bytes), at
+// most `picks` per step.  Shapes: 1024-thread workgroups, 2..256 of them.
+bool scan_several_supported(const ScanShape& s);
+hipError_t launch_scan_several(const ScanShape& s, const float* pts, int n, int k, int start, int32_t* order,
+                               float* radius, void* ws, uint64_t* ticks, int picks, hipStream_t st,
+                               const KernelEvents* ev = nullptr);
+
 // Batched plans (bs_batch.hip).
 struct BatchPlan;
 // wide: objects (largest k first) for 1024-thread workgroups in

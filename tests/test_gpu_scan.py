@@ -152,3 +152,33 @@ def test_cooperative_cad_part_full_size(hip):
     o, r = run(hip, P, k, start=st, tune=hip.tuning(kernel=hip.KERNEL_COOP, block=1024, per_thread=16))
     eo, er = oracle.greedy32_grid(P, k, st)
     assert_parity(o, r, eo, er, "cad_part full")
+
+
+@pytest.mark.parametrize("picks", [2, 8, 32])
+def test_cooperative_several_picks(hip, picks):
+    """Several exact picks per step of the cooperative full scan (every
+    workgroup a bucket with two entries and a third-best bound): the same
+    order and radii, across shapes and point sets with ties and duplicates."""
+    n = 100000
+    P = synth.cad_part(n, seed=71).points.numpy()
+    eo, er = oracle.greedy32_grid(P, 20000, 23)
+    for pt in (4, 8, 16):
+        o, r = run(hip, P, 20000, start=23,
+                   tune=hip.tuning(kernel=hip.KERNEL_COOP, block=1024, per_thread=pt, picks=picks))
+        assert_parity(o, r, eo, er, "cad n=%d per_thread=%d picks=%d" % (n, pt, picks))
+    for name in ("duplicates", "lattice", "huge", "mixed_scale", "collinear"):
+        Q = cases.ADVERSARIAL[name](40000, 77)
+        eo, er = oracle.greedy32_grid(Q, 40000 // 3, 5)
+        o, r = run(hip, Q, 40000 // 3, start=5,
+                   tune=hip.tuning(kernel=hip.KERNEL_COOP, block=1024, per_thread=4, picks=picks))
+        assert_parity(o, r, eo, er, "%s picks=%d" % (name, picks))
+
+
+def test_cooperative_several_picks_full_size(hip):
+    """4,194,304 candidates to k = 262,144, 32 picks per step at most."""
+    n, k = 4194304, 262144
+    P = synth.cad_part(n, seed=2).points.numpy()
+    st = oracle.start_index(2, n)
+    eo, er = oracle.greedy32_grid(P, k, st)
+    o, r = run(hip, P, k, seed=2, tune=hip.tuning(kernel=hip.KERNEL_COOP, block=1024, per_thread=16, picks=32))
+    assert_parity(o, r, eo, er, "cooperative several picks, full size")
