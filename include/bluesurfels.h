@@ -92,8 +92,10 @@ typedef struct {
     int32_t picks;         /* grid kernel: most picks per round, 0 = auto, 1 = one pick
                               per round, 2..32 = several exact picks per round (same
                               result; see bs_order_ex).  Cooperative full scan
-                              (BS_KERNEL_COOP): 2..32 = several exact picks per step,
-                              every workgroup a bucket offering its two best keys */
+                              (BS_KERNEL_COOP, 1024-thread workgroups, 4, 8, 12 or 16
+                              per thread): 2..64 = several exact picks per step over
+                              the candidates in Morton order, every workgroup a bucket
+                              offering its two best keys */
     int32_t lead_picks;    /* grid kernel with several picks per round: the first picks
                               come from the cooperative full scan over all CUs, which
                               then hands every candidate's distance to the grid kernel

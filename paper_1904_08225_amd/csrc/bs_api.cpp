@@ -35,13 +35,14 @@ int device_cus() {
 }
 
 constexpr int kMaxGridPicks = 32;     // picks per round of the grid kernel
+constexpr int kMaxScanPicks = 64;     // picks per step of the cooperative full scan
 constexpr int kDefaultGridPicks = 16;
 
 bool tuning_clean(const bs_tuning* t) {
     if (!t) return true;
     for (int r : t->reserved)
         if (r != 0) return false;
-    if (t->picks < 0 || t->picks > kMaxGridPicks) return false;
+    if (t->picks < 0 || t->picks > kMaxScanPicks) return false;
     if (t->lead_picks < -1 || t->batch_wide < -1) return false;
     return t->kernel >= BS_KERNEL_AUTO && t->kernel <= BS_KERNEL_GRID;
 }
@@ -75,6 +76,8 @@ int plan_single(int64_t n, int64_t k, const bs_tuning* t, Plan* p) {
     const int wb = t ? t->block : 0, wp = t ? t->per_thread : 0, wg = t ? t->groups : 0;
     if (want == BS_KERNEL_GRID || (want == BS_KERNEL_AUTO && n > kAutoResidentMax)) {
         p->grid_picks = (t && t->picks > 0) ? t->picks : kDefaultGridPicks;
+        if (p->grid_picks > kMaxGridPicks)
+            return set_error(BS_ERR_UNSUPPORTED, "grid kernel: at most %d picks per round", kMaxGridPicks);
         const bool multi = p->grid_picks > 1;
         int b = wb > 0 ? wb : (multi ? 1024 : grid_block_size(n));
         if (b != 256 && b != 512 && b != 1024)

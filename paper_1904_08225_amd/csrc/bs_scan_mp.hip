@@ -41,8 +41,69 @@ namespace {
 constexpr uint32_t kMpSpinLimit = 1u << 21;  // bounded wait (about a second), then give up
 constexpr int kMpRecStride = 16;              // words per exchange record
 constexpr int kMpWords = 13;  // e1 hi, lo, x, y, z, pos; e2 hi, lo, x, y, z, pos; R
-constexpr int kMpMaxPicks = 32;
+constexpr int kMpMaxPicks = 64;  // one lane per pick in the reach test
 constexpr int kMpMaxGroups = 256;
+
+// A workgroup barrier ordering LDS only: within a step the workgroup's
+// threads share nothing through global memory, so a barrier need not wait
+// for the record and output stores still in flight.
+__device__ __forceinline__ void lds_barrier() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+    __builtin_amdgcn_s_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
+
+// Wavefront maxima through DPP row operations (no LDS round trips): after
+// the row steps every row holds its maximum, the two row broadcasts carry
+// them to lane 63.  Lanes a step leaves unwritten read 0, the identity.
+template <int CTRL, int ROWS>
+__device__ __forceinline__ uint32_t dpp_u32(uint32_t v) {
+    return uint32_t(__builtin_amdgcn_update_dpp(0, int(v), CTRL, ROWS, 0xF, false));
+}
+__device__ __forceinline__ uint32_t wave_max_u32(uint32_t v) {
+    v = max(v, dpp_u32<0xB1, 0xF>(v));
+    v = max(v, dpp_u32<0x4E, 0xF>(v));
+    v = max(v, dpp_u32<0x141, 0xF>(v));
+    v = max(v, dpp_u32<0x140, 0xF>(v));
+    v = max(v, dpp_u32<0x142, 0xA>(v));
+    v = max(v, dpp_u32<0x143, 0xC>(v));
+    return uint32_t(__builtin_amdgcn_readlane(int(v), 63));
+}
+template <int CTRL, int ROWS>
+__device__ __forceinline__ uint64_t dpp_max_u64(uint64_t v) {
+    const uint32_t lo = dpp_u32<CTRL, ROWS>(uint32_t(v)), hi = dpp_u32<CTRL, ROWS>(uint32_t(v >> 32));
+    const uint64_t o = (uint64_t(hi) << 32) | lo;
+    return o > v ? o : v;
+}
+__device__ __forceinline__ uint64_t wave_max_u64(uint64_t v) {
+    v = dpp_max_u64<0xB1, 0xF>(v);
+    v = dpp_max_u64<0x4E, 0xF>(v);
+    v = dpp_max_u64<0x141, 0xF>(v);
+    v = dpp_max_u64<0x140, 0xF>(v);
+    v = dpp_max_u64<0x142, 0xA>(v);
+    v = dpp_max_u64<0x143, 0xC>(v);
+    return (uint64_t(uint32_t(__builtin_amdgcn_readlane(int(uint32_t(v >> 32)), 63))) << 32) |
+           uint32_t(__builtin_amdgcn_readlane(int(uint32_t(v)), 63));
+}
+
+// Key of entry e (two per record: words 0-1 and 6-7).
+__device__ __forceinline__ uint64_t rec_key(const uint32_t* rw, int e) {
+    const uint32_t* p = rw + (e >> 1) * kMpWords + 6 * (e & 1);
+    return (uint64_t(p[0]) << 32) | p[1];
+}
+
+// Phase timestamps of workgroup 0 per step (profiling builds only; ticks then
+// holds 32 words per step instead of one per pick).
+#ifdef BS_PHASE_PROF
+#define BS_SPROF(slot, v)                                                                      \
+    do {                                                                                       \
+        if (ticks && g == 0 && tid == 0) ticks[size_t(step) * 32 + (slot)] = uint64_t(v);     \
+    } while (0)
+#else
+#define BS_SPROF(slot, v) \
+    do {                  \
+    } while (0)
+#endif
 
 __device__ __forceinline__ void st_rec(uint64_t* p, uint64_t v) {
     __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -95,18 +156,19 @@ __global__ void __launch_bounds__(BLOCK)
                    float* __restrict__ radius, const DevHeader* __restrict__ hdr, uint32_t* __restrict__ err,
                    uint64_t* __restrict__ slots, uint64_t* __restrict__ ticks, int max_picks) {
     constexpr int NW = BLOCK / 64;
-    static_assert(kMpMaxPicks * kMpMaxPicks <= BLOCK, "one pair per thread");
+    static_assert(kMpMaxPicks <= 64, "one lane per pick");
     __shared__ uint64_t s_w[NW][3];                // per wavefront: its three best keys (cached)
     __shared__ float4 s_wc[NW][2];                 // and x, y, z, sorted position of the best two
-    __shared__ uint64_t s_ek[2 * kMpMaxGroups];    // entries: keys (2 per workgroup)
-    __shared__ float4 s_ec[2 * kMpMaxGroups];      // entries: x, y, z, sorted position
-    __shared__ uint32_t s_er[kMpMaxGroups];        // per workgroup: R
+    __shared__ uint32_t s_rw[kMpMaxGroups * kMpWords];  // every workgroup's record (low words)
+    __shared__ int s_pend[3];                      // record words still missing, by round
+    __shared__ uint64_t s_mk[2 * kMpMaxGroups];    // members: keys
+    __shared__ int s_mi[2 * kMpMaxGroups];         // members: entry index
     __shared__ float4 s_pk[kMpMaxPicks];           // picks by rank: x, y, z, m
     __shared__ uint32_t s_pid[kMpMaxPicks];        // original index
     __shared__ int s_ppos[kMpMaxPicks];            // sorted position
     __shared__ uint32_t s_id[P * BLOCK];           // original index of each held candidate
     __shared__ float s_z[P * BLOCK];               // and its z
-    __shared__ int s_kfail, s_abort;
+    __shared__ int s_kfail, s_na;
 
     const int tid = threadIdx.x;
     const int lane = tid & 63;
@@ -162,7 +224,7 @@ __global__ void __launch_bounds__(BLOCK)
         s_pk[0] = make_float4(c.x, c.y, c.z, INFINITY);
         s_pid[0] = uint32_t(start);
         s_ppos[0] = sp;
-        s_abort = 0;
+        s_pend[0] = s_pend[1] = s_pend[2] = 0;
         if (g == 0) {
             order[0] = start;
             if (radius) radius[0] = INFINITY;
@@ -175,6 +237,7 @@ __global__ void __launch_bounds__(BLOCK)
     int K = 1;  // picks of the previous step, in s_pk by rank
     for (uint32_t step = 1;; ++step) {
         const int buf = step & 1;
+        BS_SPROF(0, wall_clock64());
         // 1. the previous step's picks: the ones whose ball reaches this
         // wavefront's box lower m; the ones it owns become chosen
         bool reach = false, own = false;
@@ -184,15 +247,15 @@ __global__ void __launch_bounds__(BLOCK)
             const int off = s_ppos[lane] - wbase;
             own = off >= 0 && off < 64 * P;
         }
-        const uint32_t rm = uint32_t(__ballot(reach)), om = uint32_t(__ballot(own));
-        if ((rm | om) != 0u || step == 1) {  // step 1 fills every wavefront's cache
-            for (uint32_t mm = rm; mm; mm &= mm - 1) {
-                const float4 q = s_pk[__builtin_ctz(mm)];
+        const uint64_t rm = __ballot(reach), om = __ballot(own);
+        if ((rm | om) != 0ull || step == 1) {  // step 1 fills every wavefront's cache
+            for (uint64_t mm = rm; mm; mm &= mm - 1) {
+                const float4 q = s_pk[__builtin_ctzll(mm)];
 #pragma unroll
                 for (int j = 0; j < P; ++j) m[j] = fminf(m[j], dist2(px[j], py[j], s_z[j * BLOCK + tid], q.x, q.y, q.z));
             }
-            for (uint32_t mm = om; mm; mm &= mm - 1) {
-                const int off = s_ppos[__builtin_ctz(mm)] - wbase;
+            for (uint64_t mm = om; mm; mm &= mm - 1) {
+                const int off = s_ppos[__builtin_ctzll(mm)] - wbase;
 #pragma unroll
                 for (int j = 0; j < P; ++j)
                     if (off == j * 64 + lane) m[j] = -1.f;
@@ -226,167 +289,197 @@ __global__ void __launch_bounds__(BLOCK)
                 s_w[wave][2] = w3;
             }
         }
-        __syncthreads();
-        // 2. the workgroup's three best and the entries of its record
-        uint64_t v1 = lane < NW ? s_w[lane][0] : 0ull, v2 = lane < NW ? s_w[lane][1] : 0ull,
-                 v3 = lane < NW ? s_w[lane][2] : 0ull;
-        dpp_top3_step<0xB1, 0xF>(v1, v2, v3);
-        dpp_top3_step<0x4E, 0xF>(v1, v2, v3);
-        dpp_top3_step<0x141, 0xF>(v1, v2, v3);
-        dpp_top3_step<0x140, 0xF>(v1, v2, v3);  // every lane of row 0 holds the result
-        const uint64_t e1 = rl64(v1, 0), e2 = rl64(v2, 0);
-        const uint32_t rg = uint32_t(__builtin_amdgcn_readlane(int(uint32_t(v3 >> 32)), 0));
-        // 3. publish this workgroup's record, read every record
+        BS_SPROF(1, wall_clock64());
+        lds_barrier();
+        BS_SPROF(2, wall_clock64());
+        // 2. wavefront 0: the workgroup's three best, its two entries' data
+        // (from the wavefronts that hold them) and its record, one word a lane
         const uint64_t tag = uint64_t(step) << 32;
-        if (tid == 0) {
+        if (wave == 0) {
+            const uint64_t c1 = lane < NW ? s_w[lane][0] : 0ull, c2 = lane < NW ? s_w[lane][1] : 0ull;
+            uint64_t v1 = c1, v2 = c2, v3 = lane < NW ? s_w[lane][2] : 0ull;
+            dpp_top3_step<0xB1, 0xF>(v1, v2, v3);
+            dpp_top3_step<0x4E, 0xF>(v1, v2, v3);
+            dpp_top3_step<0x141, 0xF>(v1, v2, v3);
+            dpp_top3_step<0x140, 0xF>(v1, v2, v3);  // every lane of row 0 holds the result
+            const uint64_t e1 = rl64(v1, 0), e2 = rl64(v2, 0);
+            const uint32_t rg = uint32_t(__builtin_amdgcn_readlane(int(uint32_t(v3 >> 32)), 0));
+            const uint64_t h1 = __ballot(e1 != 0 && (c1 == e1 || c2 == e1));
+            const uint64_t h2 = __ballot(e2 != 0 && (c1 == e2 || c2 == e2));
             float4 x1 = make_float4(0.f, 0.f, 0.f, 0.f), x2 = x1;
-            for (int w = 0; w < NW; ++w) {
-                if (e1 != 0 && s_w[w][0] == e1) x1 = s_wc[w][0];
-                if (e1 != 0 && s_w[w][1] == e1) x1 = s_wc[w][1];
-                if (e2 != 0 && s_w[w][0] == e2) x2 = s_wc[w][0];
-                if (e2 != 0 && s_w[w][1] == e2) x2 = s_wc[w][1];
+            if (h1) {
+                const int l = __builtin_ctzll(h1);
+                x1 = s_wc[l][rl64(c1, l) == e1 ? 0 : 1];
             }
-            uint64_t* rec = slots + (size_t(buf) * G + g) * kMpRecStride;
-            st_rec(rec + 0, tag | uint32_t(e1 >> 32));
-            st_rec(rec + 1, tag | uint32_t(e1));
-            st_rec(rec + 2, tag | __float_as_uint(x1.x));
-            st_rec(rec + 3, tag | __float_as_uint(x1.y));
-            st_rec(rec + 4, tag | __float_as_uint(x1.z));
-            st_rec(rec + 5, tag | __float_as_uint(x1.w));
-            st_rec(rec + 6, tag | uint32_t(e2 >> 32));
-            st_rec(rec + 7, tag | uint32_t(e2));
-            st_rec(rec + 8, tag | __float_as_uint(x2.x));
-            st_rec(rec + 9, tag | __float_as_uint(x2.y));
-            st_rec(rec + 10, tag | __float_as_uint(x2.z));
-            st_rec(rec + 11, tag | __float_as_uint(x2.w));
-            st_rec(rec + 12, tag | rg);
+            if (h2) {
+                const int l = __builtin_ctzll(h2);
+                x2 = s_wc[l][rl64(c1, l) == e2 ? 0 : 1];
+            }
+            uint32_t wv = rg;
+            wv = lane == 11 ? __float_as_uint(x2.w) : wv;
+            wv = lane == 10 ? __float_as_uint(x2.z) : wv;
+            wv = lane == 9 ? __float_as_uint(x2.y) : wv;
+            wv = lane == 8 ? __float_as_uint(x2.x) : wv;
+            wv = lane == 7 ? uint32_t(e2) : wv;
+            wv = lane == 6 ? uint32_t(e2 >> 32) : wv;
+            wv = lane == 5 ? __float_as_uint(x1.w) : wv;
+            wv = lane == 4 ? __float_as_uint(x1.z) : wv;
+            wv = lane == 3 ? __float_as_uint(x1.y) : wv;
+            wv = lane == 2 ? __float_as_uint(x1.x) : wv;
+            wv = lane == 1 ? uint32_t(e1) : wv;
+            wv = lane == 0 ? uint32_t(e1 >> 32) : wv;
+            if (lane < kMpWords) st_rec(slots + (size_t(buf) * G + g) * kMpRecStride + lane, tag | wv);
         }
-        if (wave * 64 < G) {
-            const int r = tid;
-            bool ok = r >= G;
-            bool aborted = false;
-            uint32_t w[kMpWords];  // low words; the high word of each is the step
-#pragma unroll
-            for (int q = 0; q < kMpWords; ++q) w[q] = 0;
-            const uint64_t* rec = slots + (size_t(buf) * G + (r < G ? r : 0)) * kMpRecStride;
+        BS_SPROF(3, wall_clock64());
+        // 3. every record, a few words a thread, into s_rw (13 words per
+        // workgroup); a word is current once its high half is this step
+        {
+            constexpr int RW = (kMpMaxGroups * kMpWords + BLOCK - 1) / BLOCK;  // words a thread reads
+            const int nw = G * kMpWords;
+            const uint64_t* recs = slots + size_t(buf) * G * kMpRecStride;
             uint32_t spins = 0;
-            while (true) {
-                if (!ok) {
-                    uint32_t all_and = ~0u, all_or = 0;
+            for (int round = 0;; ++round) {
+                uint64_t v[RW];
 #pragma unroll
-                    for (int q = 0; q < kMpWords; ++q) {
-                        const uint64_t v = ld_rec(rec + q);
-                        w[q] = uint32_t(v);
-                        all_and &= uint32_t(v >> 32);
-                        all_or |= uint32_t(v >> 32);
-                    }
-                    ok = all_and == step && all_or == step;
+                for (int c = 0; c < RW; ++c) {
+                    const int i = min(tid + c * BLOCK, nw - 1);
+                    const int r = i / kMpWords;
+                    int off = r * kMpRecStride + (i - r * kMpWords);
+                    // the 32-bit offset stays live across steps, the 64-bit
+                    // address is formed here (two per offset would not fit)
+                    asm volatile("" : "+v"(off));
+                    v[c] = ld_rec(recs + off);
                 }
-                if (__ballot(!ok) == 0) break;
-                if (++spins > kMpSpinLimit) {
-                    aborted = true;
-                    break;
+                bool pending = false;
+#pragma unroll
+                for (int c = 0; c < RW; ++c) {
+                    const int i = tid + c * BLOCK;
+                    if (i < nw) {
+                        if (uint32_t(v[c] >> 32) == step) s_rw[i] = uint32_t(v[c]);
+                        else pending = true;
+                    }
+                }
+                // any thread still waiting: flags in three rotating slots,
+                // each cleared two rounds before its next use
+                const int slot = round % 3;
+                if (pending) s_pend[slot] = 1;
+                lds_barrier();
+                const bool again = s_pend[slot] != 0;
+                if (tid == 0) s_pend[(round + 2) % 3] = 0;
+                if (!again) break;
+                if (++spins > kMpSpinLimit) {  // uniform: every thread counts the same rounds
+                    if (tid == 0) atomicOr(err, 1u);
+                    return;
                 }
                 __builtin_amdgcn_s_sleep(1);
             }
-            if (r < G) {
-                s_ek[2 * r] = (uint64_t(w[0]) << 32) | w[1];
-                s_ec[2 * r] = make_float4(__uint_as_float((w[2])), __uint_as_float((w[3])),
-                                          __uint_as_float((w[4])), __uint_as_float((w[5])));
-                s_ek[2 * r + 1] = (uint64_t(w[6]) << 32) | w[7];
-                s_ec[2 * r + 1] = make_float4(__uint_as_float((w[8])), __uint_as_float((w[9])),
-                                              __uint_as_float((w[10])), __uint_as_float((w[11])));
-                s_er[r] = w[12];
-            }
-            if (aborted && lane == 0) {
-                s_abort = 1;
-                atomicOr(err, 1u);
-            }
+            BS_SPROF(11, spins);
         }
         if (tid == 0) s_kfail = kMpMaxPicks;
-        __syncthreads();
-        if (s_abort) return;
+        lds_barrier();
+        BS_SPROF(4, wall_clock64());
 
-        // 4. the accepted set: tau from the top workgroup's R up to its fixed
-        // point; members ranked among themselves, the first `cap` published
+        // 4. the accepted set (wavefront 0): the top entry, tau from the top
+        // workgroup's R up to its fixed point (a workgroup holds an entry
+        // above tau iff its first does), the members listed in s_mk / s_mi
         const int cap = min(cap_picks, k - t);
-        const int ne = 2 * G;
-        uint64_t top = 0;
-        int topw = 0;
-        for (int e = lane; e < ne; e += 64) {
-            const uint64_t kk = s_ek[e];
-            if (kk > top) {
-                top = kk;
-                topw = e >> 1;
-            }
-        }
-        {
-            uint64_t tk = top;
+        if (wave == 0) {
+            uint64_t k1[kMpMaxGroups / 64], k2[kMpMaxGroups / 64];
+            uint32_t rr[kMpMaxGroups / 64];
 #pragma unroll
-            for (int d = 32; d > 0; d >>= 1) {
-                const uint32_t lo = uint32_t(__shfl_xor(int(uint32_t(tk)), d, 64));
-                const uint32_t hi = uint32_t(__shfl_xor(int(uint32_t(tk >> 32)), d, 64));
-                const uint64_t o = (uint64_t(hi) << 32) | lo;
-                tk = o > tk ? o : tk;
+            for (int c = 0; c < kMpMaxGroups / 64; ++c) {
+                const int w = c * 64 + lane;
+                k1[c] = w < G ? rec_key(s_rw, 2 * w) : 0ull;
+                k2[c] = w < G ? rec_key(s_rw, 2 * w + 1) : 0ull;
+                rr[c] = w < G ? s_rw[w * kMpWords + 12] : 0u;
             }
-            const int tl = __builtin_ctzll(__ballot(top == tk) | (1ull << 63));
-            topw = __builtin_amdgcn_readlane(topw, tl);
-            top = tk;
-        }
-        uint32_t tau = s_er[topw];
-        for (int it = 0; it <= kMpMaxGroups; ++it) {  // tau strictly rises through R values: ends in time
-            uint32_t mr = 0;
-            for (int e = lane; e < ne; e += 64) {
-                const uint64_t kk = s_ek[e];
-                if (kk != 0 && uint32_t(kk >> 32) > tau) mr = max(mr, s_er[e >> 1]);
-            }
+            uint64_t top = 0;
+            uint32_t topr = 0;
 #pragma unroll
-            for (int d = 32; d > 0; d >>= 1) mr = max(mr, uint32_t(__shfl_xor(int(mr), d, 64)));
-            if (mr <= tau) break;
-            tau = mr;
+            for (int c = 0; c < kMpMaxGroups / 64; ++c) {
+                topr = k1[c] > top ? rr[c] : topr;
+                top = k1[c] > top ? k1[c] : top;
+            }
+            const uint64_t tk = wave_max_u64(top);
+            // R of the top workgroup, then tau up to its fixed point
+            uint32_t tau = uint32_t(__builtin_amdgcn_readlane(int(topr), __builtin_ctzll(__ballot(top == tk))));
+            for (int it = 0; it <= kMpMaxGroups; ++it) {  // at most two passes in exact arithmetic
+                uint32_t mr = 0;
+#pragma unroll
+                for (int c = 0; c < kMpMaxGroups / 64; ++c) mr = uint32_t(k1[c] >> 32) > tau ? max(mr, rr[c]) : mr;
+                mr = wave_max_u32(mr);
+                BS_SPROF(10, it + 1);
+                if (mr <= tau) break;
+                tau = mr;
+            }
+            BS_SPROF(5, wall_clock64());
+            int na = 0;
+#pragma unroll
+            for (int c = 0; c < kMpMaxGroups / 64; ++c) {
+                const int w = c * 64 + lane;
+                const bool m1 = k1[c] != 0 && (k1[c] == tk || uint32_t(k1[c] >> 32) > tau);
+                const bool m2 = k2[c] != 0 && uint32_t(k2[c] >> 32) > tau;  // e2 < e1 <= top
+                const uint64_t b1 = __ballot(m1), b2 = __ballot(m2);
+                const uint64_t below = (1ull << lane) - 1;
+                const int p1 = na + __popcll(b1 & below);
+                const int p2 = na + __popcll(b1) + __popcll(b2 & below);
+                if (m1) {
+                    s_mk[p1] = k1[c];
+                    s_mi[p1] = 2 * w;
+                }
+                if (m2) {
+                    s_mk[p2] = k2[c];
+                    s_mi[p2] = 2 * w + 1;
+                }
+                na += __popcll(b1) + __popcll(b2);
+            }
+            if (lane == 0) s_na = na;
         }
-        int na = 0;
-        for (int e0 = 0; e0 < ne; e0 += 64) {
-            const int e = e0 + lane;
-            const uint64_t kk = e < ne ? s_ek[e] : 0ull;
-            const bool mem = kk != 0 && (kk == top || uint32_t(kk >> 32) > tau);
-            const uint64_t mm0 = __ballot(mem);
-            const int pos = na + __popcll(mm0 & ((1ull << lane) - 1));
-            na += __popcll(mm0);
-            for (uint64_t mm = __ballot(mem && (pos % NW) == wave); mm; mm &= mm - 1) {
-                const int lc = __builtin_ctzll(mm);
-                const uint64_t kc = rl64(kk, lc);
-                int rank = 0;
-                for (int f0 = 0; f0 < ne; f0 += 64) {
-                    const int f = f0 + lane;
-                    const uint64_t kf = f < ne ? s_ek[f] : 0ull;
-                    const bool mf = kf != 0 && (kf == top || uint32_t(kf >> 32) > tau);
-                    rank += __popcll(__ballot(mf && kf > kc));
-                }
-                if (rank < cap && lane == 0) {
-                    const float4 c = s_ec[e0 + lc];
-                    s_pk[rank] = make_float4(c.x, c.y, c.z, key_value(kc));
-                    s_pid[rank] = key_id(kc);
-                    s_ppos[rank] = __float_as_int(c.w);
-                }
+        lds_barrier();
+        const int na = s_na;
+        // members ranked among themselves, the first `cap` published
+        if (tid < na) {
+            const uint64_t kc = s_mk[tid];
+            int rank = 0, j = 0;
+            for (; j + 8 <= na; j += 8) {
+                uint64_t kb[8];
+#pragma unroll
+                for (int u = 0; u < 8; ++u) kb[u] = s_mk[j + u];
+#pragma unroll
+                for (int u = 0; u < 8; ++u) rank += kb[u] > kc ? 1 : 0;
+            }
+            for (; j < na; ++j) rank += s_mk[j] > kc ? 1 : 0;
+            if (rank < cap) {
+                const uint32_t* x = s_rw + (s_mi[tid] >> 1) * kMpWords + 6 * (s_mi[tid] & 1) + 2;
+                const float4 c = make_float4(__uint_as_float(x[0]), __uint_as_float(x[1]), __uint_as_float(x[2]),
+                                             __uint_as_float(x[3]));
+                s_pk[rank] = make_float4(c.x, c.y, c.z, key_value(kc));
+                s_pid[rank] = key_id(kc);
+                s_ppos[rank] = __float_as_int(c.w);
             }
         }
         const int nr = min(na, cap);
-        __syncthreads();
-        // 5. distance conflicts: thread (j, i) tests member j against i < j
-        {
-            const int j = tid / kMpMaxPicks, i = tid % kMpMaxPicks;
-            if (j < nr && i < j) {
+        BS_SPROF(8, na);
+        lds_barrier();
+        BS_SPROF(6, wall_clock64());
+        // 5. distance conflicts: pair (j, i) tests member j against i < j
+        for (int pr = tid; pr < nr * nr; pr += BLOCK) {
+            const int j = pr / nr, i = pr - j * nr;
+            if (i < j) {
                 const float4 cj = s_pk[j], ci = s_pk[i];
                 if (dist2(cj.x, cj.y, cj.z, ci.x, ci.y, ci.z) < cj.w) atomicMin(&s_kfail, j);
             }
         }
-        __syncthreads();
+        lds_barrier();
         K = min(s_kfail, nr);
+        BS_SPROF(7, wall_clock64());
+        BS_SPROF(9, K);
         if (g == 0 && tid < K) {
             order[t + tid] = int32_t(s_pid[tid]);
             if (radius) radius[t + tid] = sqrtf(s_pk[tid].w);
+#ifndef BS_PHASE_PROF
             if (ticks) ticks[t + tid] = wall_clock64();
+#endif
         }
         t += K;
         if (t >= k || K <= 0) break;
@@ -397,15 +490,15 @@ using ScanMpFn = void (*)(const float4*, const uint32_t*, const int32_t*, int, i
                           const DevHeader*, uint32_t*, uint64_t*, uint64_t*, int);
 
 struct MpEntry {
+    int block;
     int per_thread;
     ScanMpFn fn;
 };
 
 const MpEntry kMpTable[] = {
-    {4, scan_mp_kernel<1024, 4>},
-    {8, scan_mp_kernel<1024, 8>},
-    {12, scan_mp_kernel<1024, 12>},
-    {16, scan_mp_kernel<1024, 16>},
+    {1024, 4, scan_mp_kernel<1024, 4>},   {1024, 8, scan_mp_kernel<1024, 8>},
+    {1024, 12, scan_mp_kernel<1024, 12>}, {1024, 16, scan_mp_kernel<1024, 16>},
+    {512, 24, scan_mp_kernel<512, 24>},   {512, 32, scan_mp_kernel<512, 32>},
 };
 
 __global__ void clear_mp_slots_kernel(uint64_t* slots, int nwords) {
@@ -415,9 +508,9 @@ __global__ void clear_mp_slots_kernel(uint64_t* slots, int nwords) {
 }  // namespace
 
 bool scan_several_supported(const ScanShape& s) {
-    if (s.block != 1024 || s.groups <= 1 || s.groups > kMpMaxGroups) return false;
+    if (s.groups <= 1 || s.groups > kMpMaxGroups) return false;
     for (const MpEntry& e : kMpTable)
-        if (e.per_thread == s.per_thread) return true;
+        if (e.block == s.block && e.per_thread == s.per_thread) return true;
     return false;
 }
 
@@ -426,7 +519,7 @@ hipError_t launch_scan_several(const ScanShape& s, const float* pts, int n, int 
                                const KernelEvents* ev) {
     ScanMpFn fn = nullptr;
     for (const MpEntry& e : kMpTable)
-        if (e.per_thread == s.per_thread) fn = e.fn;
+        if (e.block == s.block && e.per_thread == s.per_thread) fn = e.fn;
     if (!fn || !scan_several_supported(s)) return hipErrorInvalidValue;
     SortedPoints sp{};
     hipError_t e = launch_sorted_points(pts, n, start, ws, st, &sp);

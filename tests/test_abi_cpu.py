@@ -91,9 +91,10 @@ def test_autotune_validation_without_device(lib):
     lib.bs_autotune_clear()
     assert lib.bs_autotune_lookup(4096, 100, ctypes.byref(t)) == bs.BS_ERR_NOT_READY
     assert lib.bs_batch_autotune(None, None, None, 0, fake, ctypes.byref(t), None) == bs.BS_ERR_INVALID_ARG
-    # tuning fields: picks outside 0..32 is rejected like the reserved words
-    bad = bs.tuning(kernel=3, picks=33)
-    assert lib.bs_workspace_size(1000, 10, ctypes.byref(bad)) == 0
+    # tuning fields: picks outside 0..64 is rejected like the reserved words;
+    # the grid kernel takes at most 32 per round
+    assert lib.bs_workspace_size(1000, 10, ctypes.byref(bs.tuning(kernel=3, picks=65))) == 0
+    assert lib.bs_workspace_size(1000, 10, ctypes.byref(bs.tuning(kernel=3, picks=33))) == 0
     assert lib.bs_workspace_size(1000, 10, ctypes.byref(bs.tuning(kernel=3, picks=16))) > 0
 
 

@@ -154,7 +154,7 @@ def test_cooperative_cad_part_full_size(hip):
     assert_parity(o, r, eo, er, "cad_part full")
 
 
-@pytest.mark.parametrize("picks", [2, 8, 32])
+@pytest.mark.parametrize("picks", [2, 8, 32, 64])
 def test_cooperative_several_picks(hip, picks):
     """Several exact picks per step of the cooperative full scan (every
     workgroup a bucket with two entries and a third-best bound): the same
@@ -162,10 +162,10 @@ def test_cooperative_several_picks(hip, picks):
     n = 100000
     P = synth.cad_part(n, seed=71).points.numpy()
     eo, er = oracle.greedy32_grid(P, 20000, 23)
-    for pt in (4, 8, 16):
+    for blk, pt in ((1024, 4), (1024, 8), (1024, 16), (512, 24), (512, 32)):
         o, r = run(hip, P, 20000, start=23,
-                   tune=hip.tuning(kernel=hip.KERNEL_COOP, block=1024, per_thread=pt, picks=picks))
-        assert_parity(o, r, eo, er, "cad n=%d per_thread=%d picks=%d" % (n, pt, picks))
+                   tune=hip.tuning(kernel=hip.KERNEL_COOP, block=blk, per_thread=pt, picks=picks))
+        assert_parity(o, r, eo, er, "cad n=%d block=%d per_thread=%d picks=%d" % (n, blk, pt, picks))
     for name in ("duplicates", "lattice", "huge", "mixed_scale", "collinear"):
         Q = cases.ADVERSARIAL[name](40000, 77)
         eo, er = oracle.greedy32_grid(Q, 40000 // 3, 5)
