@@ -7,25 +7,24 @@ python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-batch] [--no-scene]
 A step is one full ordering of one synthetic CAD-like part -- the union
 boundary of 200 random boxes/cylinders, 4,194,304 binary32 candidates,
 ordered to k = 262,144 -- through the library's automatic kernel choice
-(autotuned for this size before the timed steps): input validation, grid
-build, every greedy step (select + min-distance update: the first n/1024
-picks by the cooperative full scan over all CUs, the rest by the grid-pruned
-kernel) and the emitted order and radii, with the candidates already
-resident in HBM.  `value` is ordered surfels per second of that step.
+(autotuned for this size before the timed steps): input validation, Morton
+sort, every greedy step (select + min-distance update; at this size the
+cooperative scan over all CUs with the candidates in VGPRs, several exact
+picks per step) and the emitted order and radii, with the candidates
+already resident in HBM.  `value` is ordered surfels per second of that step.
 
 The same JSON line also carries
-  roofline      the dominant kernel (grid-pruned ordering) against HBM,
-                with its algorithmic bytes (16 B per candidate inside the
+  roofline      the dominant kernel (the ordering kernel) against HBM, with
+                its algorithmic bytes (16 B per candidate inside the
                 covering-radius ball over its steps, counted by the CPU
                 oracle on the same points) over its duration (HIP events on
                 the launch stream) and the HBM traffic measured by counters
-                (profiles/);
-  lead_scan     the leading cooperative full scan of the same step: its
-                picks, duration and algorithmic bytes (16 B per live
-                candidate per step);
-  latency       per-round p50 / p99 of the grid kernel from device
-                timestamps (a round emits several exact picks), and the
-                leading scan's per-step p50 / p99;
+                (profiles/); the plain-definition rate (16 B per live
+                candidate per step) beside it;
+  lead_scan     when the grid kernel is chosen: the leading cooperative full
+                scan of the same step (picks, duration, algorithmic bytes);
+  latency       per-step p50 / p99 of the ordering kernel from device
+                timestamps (a step emits several exact picks);
   full_scan     the cooperative register-resident full scan on the same
                 input (16 B per live candidate per step);
   batched       1,000 parts of the same kind, n log-uniform 2,048..2,097,152,
@@ -57,16 +56,17 @@ HBM_PEAK_GBS = 8000.0
 N_MAIN, K_MAIN, SEED_MAIN = 4194304, 262144, 2
 
 
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "grid_cad_part_4M_hbm_counters.txt")
+TRAFFIC_FILES = {"grid": os.path.join(ROOT, "profiles", "grid_cad_part_4M_hbm_counters.txt"),
+                 "scan_mp": os.path.join(ROOT, "profiles", "scan_mp_cad_part_4M_hbm_counters.txt")}
 
 
-def measured_traffic():
-    """HBM bytes per launch of the grid ordering kernel from the committed
-    FETCH_SIZE / WRITE_SIZE counter summary, or None when the kernel's
-    sources have changed since the counters were taken."""
+def measured_traffic(which):
+    """HBM bytes per launch of the ordering kernel (`which`: "grid" or
+    "scan_mp") from the committed FETCH_SIZE / WRITE_SIZE counter summary, or
+    None when the kernel's sources have changed since the counters were taken."""
     import hashlib
     try:
-        fields = dict(l.split(": ", 1) for l in open(TRAFFIC_FILE).read().splitlines() if ": " in l)
+        fields = dict(l.split(": ", 1) for l in open(TRAFFIC_FILES[which]).read().splitlines() if ": " in l)
         h = hashlib.sha256()
         for src in fields["kernel_sources"].split():
             h.update(open(os.path.join(ROOT, src), "rb").read())
@@ -502,10 +502,13 @@ def main():
         "data": "synthetic (seeded union-boundary samples of 200 random boxes/cylinders)",
         "config": {"workload": "cad_part n=4,194,304 k=262,144 (union of 200 boxes/cylinders)",
                    "n": n, "k": k, "seed": SEED_MAIN,
-                   "kernel": {1: "resident workgroup", 2: "cooperative full scan",
-                              3: "grid-pruned, several exact picks per round"}.get(kernel, str(kernel)),
+                   "kernel": ("cooperative scan over all CUs, candidates in VGPRs in Morton order, "
+                              "several exact picks per step" if kernel == 2 and tuned.picks > 1 else
+                              {1: "resident workgroup", 2: "cooperative full scan",
+                               3: "grid-pruned, several exact picks per round"}.get(kernel, str(kernel))),
                    "event_ms_per_step": ev_ms,
                    "tuning": {"kernel": int(tuned.kernel), "block": int(tuned.block),
+                              "per_thread": int(tuned.per_thread), "groups": int(tuned.groups),
                               "cell_points": float(tuned.cell_points), "picks": int(tuned.picks),
                               "lead_picks": lead,
                               "source": "library defaults (no autotuning)" if args.no_autotune else
@@ -515,8 +518,9 @@ def main():
                     "picks_per_round": lat["picks_per_round"], "mean_us_per_pick": lat["mean_us_per_pick"],
                     "lead_step_p50_us": lat.get("lead_step_p50_us"),
                     "lead_step_p99_us": lat.get("lead_step_p99_us"),
-                    "source": "device wall clock at each pick's emission: grid-kernel rounds (a round "
-                              "emits several exact picks) and, apart, the steps of the leading full scan"},
+                    "source": "device wall clock at each pick's emission: steps of the ordering kernel "
+                              "(a step emits several exact picks) and, for the grid plan, apart, the "
+                              "steps of its leading full scan"},
     }
     host = pts.cpu().numpy()
     n_ball = None
@@ -526,22 +530,33 @@ def main():
         rec["config"]["matches_oracle"] = bool(np.array_equal(out_o.cpu().numpy(), eo))
         log("cpu baseline: " + cb["sample"])
     if n_ball is not None:
-        # the grid kernel makes the updates of picks lead-1 .. k-2, the leading
-        # scan those of picks 0 .. lead-2 over every live candidate
+        several = kernel == bs.KERNEL_COOP and tuned.picks > 1
+        if several:
+            kname = "scan_mp_kernel<%d,%d> x %d workgroups" % (tuned.block, tuned.per_thread, tuned.groups)
+            which = "scan_mp"
+        else:
+            kname = {3: "grid_multi_kernel<%d,...>" % (tuned.block or 1024)}.get(kernel, "kernel %d" % kernel)
+            which = "grid"
+        # the ordering kernel makes the updates of picks lead-1 .. k-2 (a
+        # leading scan of the grid plan those of picks 0 .. lead-2)
         abytes = 16 * int(n_ball[max(lead - 1, 0):].sum())
         achieved = abytes / kern_s / 1e9
+        plain = 16 * sum(n - j - 1 for j in range(max(lead - 1, 0), k - 1))
         rec["roofline"] = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                           "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(),
-                           "kernel": {3: "grid_multi_kernel<%d,...>" % (tuned.block or 1024)}.get(
-                               kernel, "kernel %d" % kernel),
-                           "algorithmic_bytes": abytes, "kernel_seconds": kern_s,
+                           "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(which),
+                           "kernel": kname, "algorithmic_bytes": abytes, "kernel_seconds": kern_s,
+                           "plain_definition_bytes": plain,
+                           "plain_definition_GBs": plain / kern_s / 1e9,
                            "traffic_source": "rocprofv3 FETCH_SIZE and WRITE_SIZE per launch, scaled by a "
-                                             "plain copy of known size (profiles/grid_cad_part_4M_hbm_counters.txt)",
+                                             "plain copy of known size (%s)"
+                                             % os.path.relpath(TRAFFIC_FILES[which], ROOT),
                            "kernel_time_source": "HIP events recorded on the launch stream around the "
-                                                 "grid ordering kernel, mean over the timed steps",
+                                                 "ordering kernel, mean over the timed steps",
                            "note": "16 B per live candidate inside the covering-radius ball per step "
-                                   "(pruned accounting) over the grid kernel's steps; the step chain is "
-                                   "latency-bound"}
+                                   "(pruned accounting); the step chain is latency-bound (one exchange "
+                                   "across all CUs per step).  plain_definition: 16 B per live candidate "
+                                   "per step, the work of the method as defined, which register residency "
+                                   "and ball pruning let the kernel exceed the HBM peak on"}
         if lead:
             live = sum(n - j - 1 for j in range(lead - 1))
             ls = lat["lead_seconds"]
@@ -556,7 +571,7 @@ def main():
         % (rec["emit"]["seconds"] * 1e6, k, rec["emit"]["achieved_GBs"], rec["emit"]["median_nn_seconds"] * 1e6))
     if not args.no_full_scan:
         fs, fo = bench_full_scan(bs, torch, pts, k)
-        fs["matches_grid_kernel"] = bool(torch.equal(fo, out_o))
+        fs["matches_ordering_kernel"] = bool(torch.equal(fo, out_o))
         rec["full_scan"] = fs
         log("full scan: %.2f s, %.0f GB/s algorithmic" % (fs["seconds"], fs["achieved_GBs"]))
     del surf, pts

@@ -55,6 +55,8 @@ constexpr int64_t kAutoResidentMax = 16384;  // one workgroup holds these in VGP
 // holds many candidates, a step over all CUs beats one workgroup's pruned step).
 constexpr int64_t kAutoLeadMinN = int64_t(1) << 18;
 constexpr int64_t kAutoLeadDiv = 1024;
+// Automatic several-picks cooperative scan: at most this many picks per step.
+constexpr int kAutoScanPicks = 64;
 
 struct Plan {
     int kernel = 0;
@@ -67,6 +69,28 @@ struct Plan {
     int scan_picks = 1;    // cooperative full scan: most exact picks per step
 };
 
+// Shape of the several-picks cooperative scan for n candidates: the most
+// workgroups (fewest candidates per thread) that fit one per CU, two at
+// least -- every workgroup offers two entries per step, so more workgroups
+// accept more picks per step.
+bool choose_several_shape(int64_t n, int cus, int want_block, int want_pt, int want_groups, ScanShape* out) {
+    static const int kBlocks[] = {1024, 512};
+    static const int kPer[] = {4, 8, 12, 16, 24, 32};
+    for (int b : kBlocks) {
+        if (want_block > 0 && b != want_block) continue;
+        for (int pt : kPer) {
+            if (want_pt > 0 && pt != want_pt) continue;
+            ScanShape s;
+            if (!choose_scan_shape(n, cus, b, pt, want_groups, &s)) continue;
+            if (s.groups >= 2 && s.groups <= cus && scan_several_supported(s)) {
+                *out = s;
+                return true;
+            }
+        }
+    }
+    return false;
+}
+
 // Resolve the kernel and its launch shape.
 int plan_single(int64_t n, int64_t k, const bs_tuning* t, Plan* p) {
     bs_tuning tuned;
@@ -74,6 +98,11 @@ int plan_single(int64_t n, int64_t k, const bs_tuning* t, Plan* p) {
     const int cus = device_cus() > 0 ? device_cus() : 256;
     const int want = t ? t->kernel : BS_KERNEL_AUTO;
     const int wb = t ? t->block : 0, wp = t ? t->per_thread : 0, wg = t ? t->groups : 0;
+    if (want == BS_KERNEL_AUTO && n > kAutoResidentMax && choose_several_shape(n, cus, wb, wp, wg, &p->shape)) {
+        p->kernel = BS_KERNEL_COOP;
+        p->scan_picks = (t && t->picks > 1) ? t->picks : kAutoScanPicks;
+        return BS_OK;
+    }
     if (want == BS_KERNEL_GRID || (want == BS_KERNEL_AUTO && n > kAutoResidentMax)) {
         p->grid_picks = (t && t->picks > 0) ? t->picks : kDefaultGridPicks;
         if (p->grid_picks > kMaxGridPicks)
@@ -109,6 +138,14 @@ int plan_single(int64_t n, int64_t k, const bs_tuning* t, Plan* p) {
         }
         return set_error(BS_ERR_UNSUPPORTED, "no kernel holds n=%lld candidates", (long long)n);
     }
+    if (want == BS_KERNEL_COOP && t && t->picks > 1) {
+        if (!choose_several_shape(n, cus, wb, wp, wg, &p->shape))
+            return set_error(BS_ERR_UNSUPPORTED, "no several-picks cooperative scan holds n=%lld with this tuning",
+                             (long long)n);
+        p->kernel = BS_KERNEL_COOP;
+        p->scan_picks = t->picks;
+        return BS_OK;
+    }
     if (want == BS_KERNEL_WG || want == BS_KERNEL_COOP) {
         if (!choose_scan_shape(n, cus, wb, wp, want == BS_KERNEL_WG ? 1 : wg, &p->shape))
             return set_error(BS_ERR_UNSUPPORTED, "resident kernel cannot hold n=%lld with this tuning",
@@ -117,11 +154,6 @@ int plan_single(int64_t n, int64_t k, const bs_tuning* t, Plan* p) {
             return set_error(BS_ERR_UNSUPPORTED, "n=%lld does not fit one workgroup", (long long)n);
         if (want == BS_KERNEL_COOP && p->shape.groups > cus * 2)
             return set_error(BS_ERR_UNSUPPORTED, "cooperative grid of %d groups too large", p->shape.groups);
-        if (want == BS_KERNEL_COOP && t && t->picks > 1) {
-            if (!scan_several_supported(p->shape))
-                return set_error(BS_ERR_UNSUPPORTED, "no several-picks cooperative scan for this shape");
-            p->scan_picks = t->picks;
-        }
         p->kernel = want;
         return BS_OK;
     }

@@ -52,10 +52,14 @@ std::vector<bs_tuning> single_candidates(int64_t n) {
         c.push_back(make_tuning(BS_KERNEL_GRID, 256, 0, 8.f, 16));
         return c;
     }
-    if (n <= 256 * 16384) c.push_back(make_tuning(BS_KERNEL_COOP, 1024, 0, 0.f, 0));
+    if (n <= 256 * 16384) {
+        // several-picks cooperative scan: candidates per thread (more
+        // workgroups offer more entries per step) and picks per step
+        for (int pt : {4, 8, 12, 16}) c.push_back(make_tuning(BS_KERNEL_COOP, 1024, pt, 0.f, 64));
+        c.push_back(make_tuning(BS_KERNEL_COOP, 0, 0, 0.f, 32));
+    }
     for (int block : {512, 1024})
-        for (float cp : {8.f, 16.f, 32.f}) c.push_back(make_tuning(BS_KERNEL_GRID, block, 0, cp, 16));
-    c.push_back(make_tuning(BS_KERNEL_GRID, 512, 0, 32.f, 1));
+        for (float cp : {8.f, 16.f}) c.push_back(make_tuning(BS_KERNEL_GRID, block, 0, cp, 16));
     return c;
 }
 

@@ -115,11 +115,23 @@ def test_lead_picks_validation(lib):
 
 
 def test_plan_describe(lib):
-    """Automatic choices resolved: the headline size takes the grid kernel
-    with 16 picks per round and a leading scan of n / 1024 picks (256
-    workgroups x 16 per thread); small sizes take the resident workgroup."""
+    """Automatic choices resolved: up to 256 workgroups of 1024 threads, the
+    several-picks cooperative scan with 64 picks per step on the most
+    workgroups that fit (fewest candidates per thread); above 4,194,304 the
+    grid kernel with 16 picks per round (asked for at 4,194,304: with a
+    leading scan of n / 1024 picks); small sizes the resident workgroup."""
     lib.bs_autotune_clear()
     p = bs.plan_describe(4194304, 262144)
+    assert (p.kernel, p.block, p.per_thread, p.groups, p.picks) == (bs.KERNEL_COOP, 1024, 16, 256, 64)
+    p = bs.plan_describe(2097152, 1000)
+    assert (p.kernel, p.per_thread, p.groups, p.picks) == (bs.KERNEL_COOP, 8, 256, 64)
+    p = bs.plan_describe(100000, 1000)
+    assert (p.kernel, p.per_thread, p.groups) == (bs.KERNEL_COOP, 4, 25)
+    p = bs.plan_describe(100000, 1000, bs.tuning(kernel=2, per_thread=16, picks=8))
+    assert (p.kernel, p.per_thread, p.groups, p.picks) == (bs.KERNEL_COOP, 16, 7, 8)
+    p = bs.plan_describe(8000000, 262144)
+    assert (p.kernel, p.block, p.picks, p.lead_picks) == (bs.KERNEL_GRID, 1024, 16, -1)  # no cooperative shape holds 8M
+    p = bs.plan_describe(4194304, 262144, bs.tuning(kernel=3, picks=16))
     assert (p.kernel, p.block, p.picks, p.lead_picks) == (bs.KERNEL_GRID, 1024, 16, 4096)
     assert (p.per_thread, p.groups) == (16, 256)
     p = bs.plan_describe(4194304, 262144, bs.tuning(kernel=3, picks=16, lead_picks=-1))
@@ -128,6 +140,9 @@ def test_plan_describe(lib):
     assert p.lead_picks == 2000  # capped at k
     p = bs.plan_describe(10000, 100)
     assert p.kernel == bs.KERNEL_WG and p.groups == 1
+    # several picks per step need two workgroups at least
+    with pytest.raises(Exception):
+        bs.plan_describe(2000, 100, bs.tuning(kernel=2, picks=8))
     out = bs.Tuning()
     assert lib.bs_plan_describe(10, 11, None, ctypes.byref(out)) == bs.BS_ERR_INVALID_ARG
     assert lib.bs_plan_describe(10, 5, None, None) == bs.BS_ERR_INVALID_ARG

@@ -95,15 +95,18 @@ def test_grid_repeat_and_agrees_with_resident(hip):
 
 
 def test_grid_cad_part_full_size(hip):
-    """4,194,304 candidates to k = 262,144 through the automatic choice, and
-    with one pick per round."""
+    """4,194,304 candidates to k = 262,144 through the grid kernel (16 picks
+    per round after a leading scan of n / 1024 picks), through the automatic
+    choice (the several-picks cooperative scan), and with one pick per round."""
     n, k = 4194304, 262144
     P = synth.cad_part(n, seed=2).points.numpy()
     st = oracle.start_index(2, n)
-    assert hip.auto_kernel(n, k) == hip.KERNEL_GRID
-    o, r = run(hip, P, k, seed=2)
+    o, r = run(hip, P, k, seed=2, tune=hip.tuning(kernel=hip.KERNEL_GRID))
     eo, er = oracle.greedy32_grid(P, k, st)
     assert_parity(o, r, eo, er, "grid cad_part full")
+    assert hip.auto_kernel(n, k) == hip.KERNEL_COOP
+    o, r = run(hip, P, k, seed=2)
+    assert_parity(o, r, eo, er, "automatic cad_part full")
     o1, r1 = run(hip, P, k, seed=2, tune=hip.tuning(kernel=hip.KERNEL_GRID, picks=1))
     assert_parity(o1, r1, eo, er, "grid cad_part full, one pick per round")
 

@@ -182,3 +182,34 @@ def test_cooperative_several_picks_full_size(hip):
     eo, er = oracle.greedy32_grid(P, k, st)
     o, r = run(hip, P, k, seed=2, tune=hip.tuning(kernel=hip.KERNEL_COOP, block=1024, per_thread=16, picks=32))
     assert_parity(o, r, eo, er, "cooperative several picks, full size")
+
+
+@pytest.mark.parametrize("n,k", [(20000, 1), (20000, 2), (20000, 3), (20000, 20000), (262144, 32768),
+                                 (1000003, 40000)])
+def test_several_picks_automatic_plan(hip, n, k):
+    """The automatic plan (several-picks cooperative scan on the most
+    workgroups that fit) against the oracle: the first picks, a full order
+    (every candidate chosen, the last steps with fewer live candidates than
+    picks), and ragged sizes spanning many workgroups."""
+    plan = hip.plan_describe(n, k)
+    assert plan.kernel == hip.KERNEL_COOP and plan.picks == 64 and plan.groups >= 2
+    P = synth.cad_part(n, seed=13).points.numpy()
+    st = oracle.start_index(4, n)
+    eo, er = oracle.greedy32_grid(P, k, st)
+    o, r = run(hip, P, k, seed=4)
+    assert_parity(o, r, eo, er, "automatic n=%d k=%d (%d x %d)" % (n, k, plan.groups, plan.per_thread))
+
+
+def test_several_picks_nonfinite_input(hip):
+    """A non-finite coordinate: every output entry is -1 with a NaN radius,
+    as for the other kernels."""
+    import torch
+    P = synth.cad_part(50000, seed=3).points.numpy().copy()
+    P[31337, 1] = np.inf
+    Pt = torch.from_numpy(P).cuda()
+    o, r = hip.order(Pt, 5000, start=0, tune=hip.tuning(kernel=hip.KERNEL_COOP, per_thread=4, picks=64),
+                     check=False)
+    torch.cuda.synchronize()
+    assert (o.cpu().numpy() == -1).all() and np.isnan(r.cpu().numpy()).all()
+    with pytest.raises(ValueError):
+        hip.order(Pt, 5000, start=0, tune=hip.tuning(kernel=hip.KERNEL_COOP, per_thread=4, picks=64))
