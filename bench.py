@@ -36,6 +36,7 @@ The same JSON line also carries
   served        a Poisson stream (mean 200 requests/s) of jobs with n
                 log-uniform 1e4..4e6, k = n/8, under an 80 GB budget:
                 p50 / p99 latency and throughput, against the plain loop;
+                and the same requests queued at once (capacity);
   cpu_baseline  the exact CPU oracle (grid-accelerated, one thread) on the
                 same points.
 """
@@ -121,16 +122,17 @@ def bench_main(args, bs, torch, np):
     log("generated cad_part n=%d in %.1fs" % (N_MAIN, time.time() - t0))
     n, k = N_MAIN, K_MAIN
     t0 = time.time()
-    if args.no_autotune:
+    force = bs.tuning(kernel=bs.KERNEL_GRID) if args.plan == "grid" else None
+    if args.no_autotune or force is not None:
         tuned = bs.Tuning()
     else:
         tuned = bs.autotune(pts, k, seed=SEED_MAIN)  # recorded for this size; untimed
-    plan = bs.plan_describe(n, k)  # the plan the timed calls follow (automatic choices resolved)
+    plan = bs.plan_describe(n, k, force)  # the plan the timed calls follow (automatic choices resolved)
     lead = int(plan.lead_picks) if plan.kernel == bs.KERNEL_GRID and plan.lead_picks > 0 else 0
     log("autotune: kernel %d block %d cells %g picks %d lead %d in %.1fs"
         % (plan.kernel, plan.block, plan.cell_points, plan.picks, lead, time.time() - t0))
-    kernel = bs.auto_kernel(n, k)
-    ws = torch.empty(max(bs.workspace_size(n, k), 1), dtype=torch.uint8, device=dev)
+    kernel = int(plan.kernel)
+    ws = torch.empty(max(bs.workspace_size(n, k, force), 1), dtype=torch.uint8, device=dev)
     out_o = torch.empty(k, dtype=torch.int32, device=dev)
     out_r = torch.empty(k, dtype=torch.float32, device=dev)
     stream = torch.cuda.current_stream()
@@ -143,8 +145,8 @@ def bench_main(args, bs, torch, np):
 
     def step(events=None):
         # the same kernels as bs_order; the events bracket the ordering kernel
-        bs.order_profile(pts, k, start=start, stream=stream, ticks=False, events=events, workspace=ws,
-                         out_order=out_o, out_radius=out_r)
+        bs.order_profile(pts, k, start=start, tune=force, stream=stream, ticks=False, events=events,
+                         workspace=ws, out_order=out_o, out_radius=out_r)
 
     for i in range(args.warmup):
         step()
@@ -165,7 +167,7 @@ def bench_main(args, bs, torch, np):
     ms = wall * 1000.0 / args.steps
     log("timed %d steps: %.1f ms/step wall, %.1f ms/step events, ordering kernel %.1f ms"
         % (args.steps, ms, ev_ms, kern_ms))
-    _, lat, _ = ordering_kernel_seconds(bs, pts, k, start, None, lead)
+    _, lat, _ = ordering_kernel_seconds(bs, pts, k, start, force, lead)
     log("rounds %d (%.2f picks each), per-round p50 %.2f us, %.2f us per pick (device clock)"
         % (lat["rounds"], lat["picks_per_round"], lat["p50_us"], lat["mean_us_per_pick"]))
     if lead:
@@ -377,6 +379,18 @@ def bench_served(bs, torch, np):
     srv.close()
     log("served: p50 %.1f ms p99 %.1f ms, %.3g surfels/s" % (st["p50_us"] / 1e3, st["p99_us"] / 1e3,
                                                               st["surfels_per_s"]))
+    # capacity: the same requests all queued at once (the offered rate above
+    # caps the served rate, so this is what compares with the plain loop)
+    sat = bs.Server(hbm_budget_bytes=80 << 30, max_jobs_per_batch=256, poll_us=20)
+    off = 0
+    for i in range(nreq):
+        p = int(picks[i])
+        sat.submit(views[p], ks[i], int(seeds[i]), out_o[off:off + ks[i]], out_r[off:off + ks[i]])
+        off += ks[i]
+    sat.drain()
+    st2 = sat.stats()
+    sat.close()
+    log("served, saturated: %.3g surfels/s in %.2f s" % (st2["surfels_per_s"], st2["elapsed_s"]))
     # plain loop: one ordering launch per request, back to back, sampled
     sample = list(range(0, nreq, nreq // 20))[:20]
     sk = 0
@@ -394,6 +408,11 @@ def bench_served(bs, torch, np):
             "elapsed_s": st["elapsed_s"], "batches": st["batches"], "hbm_peak_bytes": st["hbm_peak"],
             "plain_loop_ordered_surfels_per_s": plain_rate,
             "speedup_vs_plain": st["surfels_per_s"] / plain_rate,
+            "speedup_bound_by_offered_load": offered / plain_rate,
+            "saturated": {"surfels_per_s": st2["surfels_per_s"], "elapsed_s": st2["elapsed_s"],
+                          "batches": st2["batches"], "hbm_peak_bytes": st2["hbm_peak"],
+                          "speedup_vs_plain": st2["surfels_per_s"] / plain_rate,
+                          "note": "the same 2,000 requests queued at once: the serving path's capacity"},
             "plain_loop_sample": "%d requests back to back" % len(sample)}
 
 
@@ -453,13 +472,15 @@ def cpu_oracle_objects(pts, offs, ks, seeds, order_idx, sum_k_total, gpu_seconds
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=3)
-    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-full-scan", action="store_true")
     ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--no-serve", action="store_true")
     ap.add_argument("--no-scene", action="store_true")
+    ap.add_argument("--plan", choices=("auto", "grid"), default="auto",
+                    help="main leg: the automatic plan, or the grid kernel (16 picks per round, leading scan)")
     ap.add_argument("--no-autotune", action="store_true",
                     help="use the automatic kernel choice without timing candidates first")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
@@ -511,7 +532,8 @@ def main():
                               "per_thread": int(tuned.per_thread), "groups": int(tuned.groups),
                               "cell_points": float(tuned.cell_points), "picks": int(tuned.picks),
                               "lead_picks": lead,
-                              "source": "library defaults (no autotuning)" if args.no_autotune else
+                              "source": "grid kernel asked for (--plan grid)" if args.plan == "grid" else
+                              "library defaults (no autotuning)" if args.no_autotune else
                               "library autotuner (bs_autotune), run before the timed steps"}},
         "latency": {"per_round_p50_us": lat["p50_us"], "per_round_p99_us": lat["p99_us"],
                     "per_round_mean_us": lat["mean_us"], "rounds": lat["rounds"],
