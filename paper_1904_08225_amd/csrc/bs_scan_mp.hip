@@ -86,6 +86,11 @@ __device__ __forceinline__ uint64_t wave_max_u64(uint64_t v) {
            uint32_t(__builtin_amdgcn_readlane(int(uint32_t(v)), 63));
 }
 
+// Set bits of a wavefront mask below this lane.
+__device__ __forceinline__ int lanes_below(uint64_t m) {
+    return int(__builtin_amdgcn_mbcnt_hi(uint32_t(m >> 32), __builtin_amdgcn_mbcnt_lo(uint32_t(m), 0u)));
+}
+
 // Key of entry e (two per record: words 0-1 and 6-7).
 __device__ __forceinline__ uint64_t rec_key(const uint32_t* rw, int e) {
     const uint32_t* p = rw + (e >> 1) * kMpWords + 6 * (e & 1);
@@ -160,15 +165,14 @@ __global__ void __launch_bounds__(BLOCK)
     __shared__ uint64_t s_w[NW][3];                // per wavefront: its three best keys (cached)
     __shared__ float4 s_wc[NW][2];                 // and x, y, z, sorted position of the best two
     __shared__ uint32_t s_rw[kMpMaxGroups * kMpWords];  // every workgroup's record (low words)
-    __shared__ int s_pend[3];                      // record words still missing, by round
-    __shared__ uint64_t s_mk[2 * kMpMaxGroups];    // members: keys
+    __shared__ __align__(16) uint64_t s_mk[2 * kMpMaxGroups];  // members: keys
     __shared__ int s_mi[2 * kMpMaxGroups];         // members: entry index
     __shared__ float4 s_pk[kMpMaxPicks];           // picks by rank: x, y, z, m
     __shared__ uint32_t s_pid[kMpMaxPicks];        // original index
     __shared__ int s_ppos[kMpMaxPicks];            // sorted position
     __shared__ uint32_t s_id[P * BLOCK];           // original index of each held candidate
     __shared__ float s_z[P * BLOCK];               // and its z
-    __shared__ int s_kfail, s_na;
+    __shared__ int s_kfail, s_na, s_abort;
 
     const int tid = threadIdx.x;
     const int lane = tid & 63;
@@ -224,7 +228,7 @@ __global__ void __launch_bounds__(BLOCK)
         s_pk[0] = make_float4(c.x, c.y, c.z, INFINITY);
         s_pid[0] = uint32_t(start);
         s_ppos[0] = sp;
-        s_pend[0] = s_pend[1] = s_pend[2] = 0;
+        s_abort = 0;
         if (g == 0) {
             order[0] = start;
             if (radius) radius[0] = INFINITY;
@@ -236,6 +240,13 @@ __global__ void __launch_bounds__(BLOCK)
     int t = 1;  // picks made
     int K = 1;  // picks of the previous step, in s_pk by rank
     for (uint32_t step = 1;; ++step) {
+        // thread-derived values are recomputed every step from an opaque copy
+        // of the thread index (a few VALU operations) instead of being kept
+        // live across the loop next to the 48 registers of candidates, where
+        // the compiler would spill them
+        int tid_v = int(threadIdx.x);
+        asm volatile("" : "+v"(tid_v));
+        const int tid = tid_v, lane = tid_v & 63;
         const int buf = step & 1;
         BS_SPROF(0, wall_clock64());
         // 1. the previous step's picks: the ones whose ball reaches this
@@ -338,7 +349,8 @@ __global__ void __launch_bounds__(BLOCK)
             const int nw = G * kMpWords;
             const uint64_t* recs = slots + size_t(buf) * G * kMpRecStride;
             uint32_t spins = 0;
-            for (int round = 0;; ++round) {
+            bool aborted = false;
+            while (true) {  // each wavefront polls its own words; one barrier after
                 uint64_t v[RW];
 #pragma unroll
                 for (int c = 0; c < RW; ++c) {
@@ -359,25 +371,23 @@ __global__ void __launch_bounds__(BLOCK)
                         else pending = true;
                     }
                 }
-                // any thread still waiting: flags in three rotating slots,
-                // each cleared two rounds before its next use
-                const int slot = round % 3;
-                if (pending) s_pend[slot] = 1;
-                lds_barrier();
-                const bool again = s_pend[slot] != 0;
-                if (tid == 0) s_pend[(round + 2) % 3] = 0;
-                if (!again) break;
-                if (++spins > kMpSpinLimit) {  // uniform: every thread counts the same rounds
-                    if (tid == 0) atomicOr(err, 1u);
-                    return;
+                if (__ballot(pending) == 0) break;
+                if (++spins > kMpSpinLimit) {
+                    aborted = true;
+                    break;
                 }
                 __builtin_amdgcn_s_sleep(1);
             }
+            if (aborted && lane == 0) s_abort = 1;
             BS_SPROF(11, spins);
         }
         if (tid == 0) s_kfail = kMpMaxPicks;
         lds_barrier();
         BS_SPROF(4, wall_clock64());
+        if (s_abort) {  // a wait gave up: every workgroup's waits end the same way
+            if (tid == 0) atomicOr(err, 1u);
+            return;
+        }
 
         // 4. the accepted set (wavefront 0): the top entry, tau from the top
         // workgroup's R up to its fixed point (a workgroup holds an entry
@@ -420,9 +430,8 @@ __global__ void __launch_bounds__(BLOCK)
                 const bool m1 = k1[c] != 0 && (k1[c] == tk || uint32_t(k1[c] >> 32) > tau);
                 const bool m2 = k2[c] != 0 && uint32_t(k2[c] >> 32) > tau;  // e2 < e1 <= top
                 const uint64_t b1 = __ballot(m1), b2 = __ballot(m2);
-                const uint64_t below = (1ull << lane) - 1;
-                const int p1 = na + __popcll(b1 & below);
-                const int p2 = na + __popcll(b1) + __popcll(b2 & below);
+                const int p1 = na + lanes_below(b1);
+                const int p2 = na + __popcll(b1) + lanes_below(b2);
                 if (m1) {
                     s_mk[p1] = k1[c];
                     s_mi[p1] = 2 * w;
@@ -434,21 +443,26 @@ __global__ void __launch_bounds__(BLOCK)
                 na += __popcll(b1) + __popcll(b2);
             }
             if (lane == 0) s_na = na;
+            BS_SPROF(12, wall_clock64());
         }
         lds_barrier();
+        BS_SPROF(13, wall_clock64());
         const int na = s_na;
         // members ranked among themselves, the first `cap` published
         if (tid < na) {
             const uint64_t kc = s_mk[tid];
+            // two keys per 16-byte LDS read, four reads in flight
+            const ulonglong2* mk2 = reinterpret_cast<const ulonglong2*>(s_mk);
             int rank = 0, j = 0;
             for (; j + 8 <= na; j += 8) {
-                uint64_t kb[8];
+                ulonglong2 kb[4];
 #pragma unroll
-                for (int u = 0; u < 8; ++u) kb[u] = s_mk[j + u];
+                for (int u = 0; u < 4; ++u) kb[u] = mk2[j / 2 + u];
 #pragma unroll
-                for (int u = 0; u < 8; ++u) rank += kb[u] > kc ? 1 : 0;
+                for (int u = 0; u < 4; ++u) rank += (kb[u].x > kc ? 1 : 0) + (kb[u].y > kc ? 1 : 0);
             }
             for (; j < na; ++j) rank += s_mk[j] > kc ? 1 : 0;
+            BS_SPROF(14, wall_clock64());
             if (rank < cap) {
                 const uint32_t* x = s_rw + (s_mi[tid] >> 1) * kMpWords + 6 * (s_mi[tid] & 1) + 2;
                 const float4 c = make_float4(__uint_as_float(x[0]), __uint_as_float(x[1]), __uint_as_float(x[2]),
@@ -462,13 +476,20 @@ __global__ void __launch_bounds__(BLOCK)
         BS_SPROF(8, na);
         lds_barrier();
         BS_SPROF(6, wall_clock64());
-        // 5. distance conflicts: pair (j, i) tests member j against i < j
-        for (int pr = tid; pr < nr * nr; pr += BLOCK) {
-            const int j = pr / nr, i = pr - j * nr;
-            if (i < j) {
-                const float4 cj = s_pk[j], ci = s_pk[i];
-                if (dist2(cj.x, cj.y, cj.z, ci.x, ci.y, ci.z) < cj.w) atomicMin(&s_kfail, j);
+        // 5. distance conflicts: lane i of a wavefront tests member i against
+        // the wavefront's members j = wave, wave + NW, ... (pairs i < j); the
+        // lowest failing j of a wavefront goes to LDS in one atomic
+        {
+            uint32_t fail = kMpMaxPicks;
+            if (lane < nr) {
+                const float4 ci = s_pk[lane];
+                for (int j = wave; j < nr; j += NW) {
+                    const float4 cj = s_pk[j];
+                    if (lane < j && dist2(cj.x, cj.y, cj.z, ci.x, ci.y, ci.z) < cj.w) fail = min(fail, uint32_t(j));
+                }
             }
+            fail = ~wave_max_u32(~fail);  // wavefront minimum
+            if (lane == 0 && fail < uint32_t(kMpMaxPicks)) atomicMin(&s_kfail, int(fail));
         }
         lds_barrier();
         K = min(s_kfail, nr);
