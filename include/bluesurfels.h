@@ -93,7 +93,7 @@ typedef struct {
                               per round, 2..32 = several exact picks per round (same
                               result; see bs_order_ex).  Cooperative full scan
                               (BS_KERNEL_COOP, 1024-thread workgroups, 4, 8, 12 or 16
-                              per thread): 2..64 = several exact picks per step over
+                              per thread): 2..128 = several exact picks per step over
                               the candidates in Morton order, every workgroup a bucket
                               offering its two best keys */
     int32_t lead_picks;    /* grid kernel with several picks per round: the first picks

@@ -35,7 +35,7 @@ int device_cus() {
 }
 
 constexpr int kMaxGridPicks = 32;     // picks per round of the grid kernel
-constexpr int kMaxScanPicks = 64;     // picks per step of the cooperative full scan
+constexpr int kMaxScanPicks = 128;    // picks per step of the cooperative full scan
 constexpr int kDefaultGridPicks = 16;
 
 bool tuning_clean(const bs_tuning* t) {
@@ -56,7 +56,7 @@ constexpr int64_t kAutoResidentMax = 16384;  // one workgroup holds these in VGP
 constexpr int64_t kAutoLeadMinN = int64_t(1) << 18;
 constexpr int64_t kAutoLeadDiv = 1024;
 // Automatic several-picks cooperative scan: at most this many picks per step.
-constexpr int kAutoScanPicks = 64;
+constexpr int kAutoScanPicks = 128;
 
 struct Plan {
     int kernel = 0;

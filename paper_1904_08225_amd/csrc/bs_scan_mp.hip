@@ -41,7 +41,7 @@ namespace {
 constexpr uint32_t kMpSpinLimit = 1u << 21;  // bounded wait (about a second), then give up
 constexpr int kMpRecStride = 16;              // words per exchange record
 constexpr int kMpWords = 13;  // e1 hi, lo, x, y, z, pos; e2 hi, lo, x, y, z, pos; R
-constexpr int kMpMaxPicks = 64;  // one lane per pick in the reach test
+constexpr int kMpMaxPicks = 128;  // two passes of one lane per pick in the reach test
 constexpr int kMpMaxGroups = 256;
 
 // A workgroup barrier ordering LDS only: within a step the workgroup's
@@ -161,7 +161,7 @@ __global__ void __launch_bounds__(BLOCK)
                    float* __restrict__ radius, const DevHeader* __restrict__ hdr, uint32_t* __restrict__ err,
                    uint64_t* __restrict__ slots, uint64_t* __restrict__ ticks, int max_picks) {
     constexpr int NW = BLOCK / 64;
-    static_assert(kMpMaxPicks <= 64, "one lane per pick");
+    static_assert(kMpMaxPicks <= 128, "two passes of one lane per pick");
     __shared__ uint64_t s_w[NW][3];                // per wavefront: its three best keys (cached)
     __shared__ float4 s_wc[NW][2];                 // and x, y, z, sorted position of the best two
     __shared__ uint32_t s_rw[kMpMaxGroups * kMpWords];  // every workgroup's record (low words)
@@ -251,26 +251,37 @@ __global__ void __launch_bounds__(BLOCK)
         BS_SPROF(0, wall_clock64());
         // 1. the previous step's picks: the ones whose ball reaches this
         // wavefront's box lower m; the ones it owns become chosen
-        bool reach = false, own = false;
-        if (lane < K) {
-            const float4 q = s_pk[lane];
-            reach = box_lower(lx, ly, lz, hx, hy, hz, q.x, q.y, q.z) < q.w;
-            const int off = s_ppos[lane] - wbase;
-            own = off >= 0 && off < 64 * P;
+        uint64_t rm[2], om[2];  // picks 0-63 and 64-127
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            const int qi = h * 64 + lane;
+            bool reach = false, own = false;
+            if (qi < K) {
+                const float4 q = s_pk[qi];
+                reach = box_lower(lx, ly, lz, hx, hy, hz, q.x, q.y, q.z) < q.w;
+                const int off = s_ppos[qi] - wbase;
+                own = off >= 0 && off < 64 * P;
+            }
+            rm[h] = __ballot(reach);
+            om[h] = __ballot(own);
         }
-        const uint64_t rm = __ballot(reach), om = __ballot(own);
-        if ((rm | om) != 0ull || step == 1) {  // step 1 fills every wavefront's cache
-            for (uint64_t mm = rm; mm; mm &= mm - 1) {
-                const float4 q = s_pk[__builtin_ctzll(mm)];
+        if ((rm[0] | rm[1] | om[0] | om[1]) != 0ull || step == 1) {  // step 1 fills every wavefront's cache
 #pragma unroll
-                for (int j = 0; j < P; ++j) m[j] = fminf(m[j], dist2(px[j], py[j], s_z[j * BLOCK + tid], q.x, q.y, q.z));
-            }
-            for (uint64_t mm = om; mm; mm &= mm - 1) {
-                const int off = s_ppos[__builtin_ctzll(mm)] - wbase;
+            for (int h = 0; h < 2; ++h)
+                for (uint64_t mm = rm[h]; mm; mm &= mm - 1) {
+                    const float4 q = s_pk[h * 64 + __builtin_ctzll(mm)];
 #pragma unroll
-                for (int j = 0; j < P; ++j)
-                    if (off == j * 64 + lane) m[j] = -1.f;
-            }
+                    for (int j = 0; j < P; ++j)
+                        m[j] = fminf(m[j], dist2(px[j], py[j], s_z[j * BLOCK + tid], q.x, q.y, q.z));
+                }
+#pragma unroll
+            for (int h = 0; h < 2; ++h)
+                for (uint64_t mm = om[h]; mm; mm &= mm - 1) {
+                    const int off = s_ppos[h * 64 + __builtin_ctzll(mm)] - wbase;
+#pragma unroll
+                    for (int j = 0; j < P; ++j)
+                        if (off == j * 64 + lane) m[j] = -1.f;
+                }
             uint64_t a1 = 0, a2 = 0, a3 = 0;
 #pragma unroll
             for (int j = 0; j < P; ++j) insert3(m[j] >= 0.f ? make_key(m[j], s_id[j * BLOCK + tid]) : 0ull, a1, a2, a3);
@@ -476,16 +487,16 @@ __global__ void __launch_bounds__(BLOCK)
         BS_SPROF(8, na);
         lds_barrier();
         BS_SPROF(6, wall_clock64());
-        // 5. distance conflicts: lane i of a wavefront tests member i against
+        // 5. distance conflicts: lane i of a wavefront tests members i, i + 64 against
         // the wavefront's members j = wave, wave + NW, ... (pairs i < j); the
         // lowest failing j of a wavefront goes to LDS in one atomic
         {
             uint32_t fail = kMpMaxPicks;
-            if (lane < nr) {
-                const float4 ci = s_pk[lane];
+            for (int i = lane; i < nr; i += 64) {
+                const float4 ci = s_pk[i];
                 for (int j = wave; j < nr; j += NW) {
                     const float4 cj = s_pk[j];
-                    if (lane < j && dist2(cj.x, cj.y, cj.z, ci.x, ci.y, ci.z) < cj.w) fail = min(fail, uint32_t(j));
+                    if (i < j && dist2(cj.x, cj.y, cj.z, ci.x, ci.y, ci.z) < cj.w) fail = min(fail, uint32_t(j));
                 }
             }
             fail = ~wave_max_u32(~fail);  // wavefront minimum

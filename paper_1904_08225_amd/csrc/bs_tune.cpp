@@ -55,8 +55,8 @@ std::vector<bs_tuning> single_candidates(int64_t n) {
     if (n <= 256 * 16384) {
         // several-picks cooperative scan: candidates per thread (more
         // workgroups offer more entries per step) and picks per step
-        for (int pt : {4, 8, 12, 16}) c.push_back(make_tuning(BS_KERNEL_COOP, 1024, pt, 0.f, 64));
-        c.push_back(make_tuning(BS_KERNEL_COOP, 0, 0, 0.f, 32));
+        for (int pt : {4, 8, 12, 16}) c.push_back(make_tuning(BS_KERNEL_COOP, 1024, pt, 0.f, 128));
+        c.push_back(make_tuning(BS_KERNEL_COOP, 0, 0, 0.f, 64));
     }
     for (int block : {512, 1024})
         for (float cp : {8.f, 16.f}) c.push_back(make_tuning(BS_KERNEL_GRID, block, 0, cp, 16));

@@ -91,9 +91,9 @@ def test_autotune_validation_without_device(lib):
     lib.bs_autotune_clear()
     assert lib.bs_autotune_lookup(4096, 100, ctypes.byref(t)) == bs.BS_ERR_NOT_READY
     assert lib.bs_batch_autotune(None, None, None, 0, fake, ctypes.byref(t), None) == bs.BS_ERR_INVALID_ARG
-    # tuning fields: picks outside 0..64 is rejected like the reserved words;
+    # tuning fields: picks outside 0..128 is rejected like the reserved words;
     # the grid kernel takes at most 32 per round
-    assert lib.bs_workspace_size(1000, 10, ctypes.byref(bs.tuning(kernel=3, picks=65))) == 0
+    assert lib.bs_workspace_size(1000, 10, ctypes.byref(bs.tuning(kernel=3, picks=129))) == 0
     assert lib.bs_workspace_size(1000, 10, ctypes.byref(bs.tuning(kernel=3, picks=33))) == 0
     assert lib.bs_workspace_size(1000, 10, ctypes.byref(bs.tuning(kernel=3, picks=16))) > 0
 
@@ -116,15 +116,15 @@ def test_lead_picks_validation(lib):
 
 def test_plan_describe(lib):
     """Automatic choices resolved: up to 256 workgroups of 1024 threads, the
-    several-picks cooperative scan with 64 picks per step on the most
+    several-picks cooperative scan with 128 picks per step on the most
     workgroups that fit (fewest candidates per thread); above 4,194,304 the
     grid kernel with 16 picks per round (asked for at 4,194,304: with a
     leading scan of n / 1024 picks); small sizes the resident workgroup."""
     lib.bs_autotune_clear()
     p = bs.plan_describe(4194304, 262144)
-    assert (p.kernel, p.block, p.per_thread, p.groups, p.picks) == (bs.KERNEL_COOP, 1024, 16, 256, 64)
+    assert (p.kernel, p.block, p.per_thread, p.groups, p.picks) == (bs.KERNEL_COOP, 1024, 16, 256, 128)
     p = bs.plan_describe(2097152, 1000)
-    assert (p.kernel, p.per_thread, p.groups, p.picks) == (bs.KERNEL_COOP, 8, 256, 64)
+    assert (p.kernel, p.per_thread, p.groups, p.picks) == (bs.KERNEL_COOP, 8, 256, 128)
     p = bs.plan_describe(100000, 1000)
     assert (p.kernel, p.per_thread, p.groups) == (bs.KERNEL_COOP, 4, 25)
     p = bs.plan_describe(100000, 1000, bs.tuning(kernel=2, per_thread=16, picks=8))

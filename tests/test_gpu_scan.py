@@ -154,7 +154,7 @@ def test_cooperative_cad_part_full_size(hip):
     assert_parity(o, r, eo, er, "cad_part full")
 
 
-@pytest.mark.parametrize("picks", [2, 8, 32, 64])
+@pytest.mark.parametrize("picks", [2, 8, 32, 64, 128])
 def test_cooperative_several_picks(hip, picks):
     """Several exact picks per step of the cooperative full scan (every
     workgroup a bucket with two entries and a third-best bound): the same
@@ -175,13 +175,15 @@ def test_cooperative_several_picks(hip, picks):
 
 
 def test_cooperative_several_picks_full_size(hip):
-    """4,194,304 candidates to k = 262,144, 32 picks per step at most."""
+    """4,194,304 candidates to k = 262,144, at most 32 and 128 picks per step."""
     n, k = 4194304, 262144
     P = synth.cad_part(n, seed=2).points.numpy()
     st = oracle.start_index(2, n)
     eo, er = oracle.greedy32_grid(P, k, st)
-    o, r = run(hip, P, k, seed=2, tune=hip.tuning(kernel=hip.KERNEL_COOP, block=1024, per_thread=16, picks=32))
-    assert_parity(o, r, eo, er, "cooperative several picks, full size")
+    for picks in (32, 128):
+        o, r = run(hip, P, k, seed=2,
+                   tune=hip.tuning(kernel=hip.KERNEL_COOP, block=1024, per_thread=16, picks=picks))
+        assert_parity(o, r, eo, er, "cooperative several picks, full size, picks=%d" % picks)
 
 
 @pytest.mark.parametrize("n,k", [(20000, 1), (20000, 2), (20000, 3), (20000, 20000), (262144, 32768),
@@ -192,7 +194,7 @@ def test_several_picks_automatic_plan(hip, n, k):
     (every candidate chosen, the last steps with fewer live candidates than
     picks), and ragged sizes spanning many workgroups."""
     plan = hip.plan_describe(n, k)
-    assert plan.kernel == hip.KERNEL_COOP and plan.picks == 64 and plan.groups >= 2
+    assert plan.kernel == hip.KERNEL_COOP and plan.picks == 128 and plan.groups >= 2
     P = synth.cad_part(n, seed=13).points.numpy()
     st = oracle.start_index(4, n)
     eo, er = oracle.greedy32_grid(P, k, st)
