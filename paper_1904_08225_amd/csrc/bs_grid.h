@@ -65,6 +65,7 @@ struct SortedPoints {
     DevHeader* hdr;
     const float4* xyzm;        // [n] x, y, z, +inf in Morton order
     const uint32_t* ids;       // [n] original index of each
+    const uint32_t* codes;     // [n] their Morton codes, ascending
     const int32_t* start_pos;  // device: sorted position of the start
     void* slots;               // exchange records of the cooperative scan
 };

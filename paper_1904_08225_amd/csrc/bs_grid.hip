@@ -363,6 +363,7 @@ hipError_t launch_sorted_points(const float* pts, int n, int start, void* ws, hi
     out->hdr = hdr;
     out->xyzm = xyzm;
     out->ids = ids;
+    out->codes = codes_s;
     out->start_pos = &gh->start_pos;
     out->slots = base + g.lead_slots;
     return hipSuccess;

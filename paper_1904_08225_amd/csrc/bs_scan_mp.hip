@@ -86,6 +86,28 @@ __device__ __forceinline__ uint64_t wave_max_u64(uint64_t v) {
            uint32_t(__builtin_amdgcn_readlane(int(uint32_t(v)), 63));
 }
 
+// A box the whole wavefront shares (held in scalar registers).
+struct WaveBox {
+    float lo[3], hi[3];
+};
+__device__ __forceinline__ float uniform_f32(float v) {
+    return __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(v)));
+}
+__device__ __forceinline__ float wave_min_f32(float v) {
+#pragma unroll
+    for (int d = 32; d > 0; d >>= 1) v = fminf(v, __shfl_xor(v, d, 64));
+    return uniform_f32(v);
+}
+__device__ __forceinline__ float wave_max_f32(float v) {
+#pragma unroll
+    for (int d = 32; d > 0; d >>= 1) v = fmaxf(v, __shfl_xor(v, d, 64));
+    return uniform_f32(v);
+}
+// Binary32 lower bound of d2 from c to the box (+inf for an empty box).
+__device__ __forceinline__ float wave_box_lower(const WaveBox& b, float cx, float cy, float cz) {
+    return box_lower(b.lo[0], b.lo[1], b.lo[2], b.hi[0], b.hi[1], b.hi[2], cx, cy, cz);
+}
+
 // Set bits of a wavefront mask below this lane.
 __device__ __forceinline__ int lanes_below(uint64_t m) {
     return int(__builtin_amdgcn_mbcnt_hi(uint32_t(m >> 32), __builtin_amdgcn_mbcnt_lo(uint32_t(m), 0u)));
@@ -104,7 +126,35 @@ __device__ __forceinline__ uint64_t rec_key(const uint32_t* rw, int e) {
     do {                                                                                       \
         if (ticks && g == 0 && tid == 0) ticks[size_t(step) * 32 + (slot)] = uint64_t(v);     \
     } while (0)
+// per workgroup and step (profiling builds): publish and exchange-done times
+#define BS_WPROF(half, v)                                                                          \
+    do {                                                                                           \
+        if (ticks && tid == 0 && (size_t(step) + 1) * G <= size_t(k) * 8)                          \
+            ticks[size_t(k) * 16 + size_t(half) * size_t(k) * 8 + size_t(step) * G + g] = uint64_t(v); \
+    } while (0)
+// per workgroup and step (profiling builds): (pick, wavefront) reach pairs
+#define BS_RPROF(v)                                                                     \
+    do {                                                                                \
+        if (ticks && tid == 0 && (size_t(step) + 1) * G <= size_t(k) * 4)               \
+            ticks[size_t(k) * 4 + size_t(step) * G + g] = uint64_t(v);                   \
+    } while (0)
+// per workgroup and step (profiling builds): step start and after the
+// update barrier
+#define BS_TPROF(q, v)                                                                      \
+    do {                                                                                    \
+        if (ticks && tid == 0 && (size_t(step) + 1) * G <= size_t(k) * 4)                   \
+            ticks[size_t(k) * 8 + size_t(q) * size_t(k) * 4 + size_t(step) * G + g] = uint64_t(v); \
+    } while (0)
 #else
+#define BS_TPROF(q, v) \
+    do {               \
+    } while (0)
+#define BS_RPROF(v) \
+    do {            \
+    } while (0)
+#define BS_WPROF(half, v) \
+    do {                  \
+    } while (0)
 #define BS_SPROF(slot, v) \
     do {                  \
     } while (0)
@@ -157,7 +207,7 @@ __device__ __forceinline__ uint64_t rl64(uint64_t v, int l) {
 template <int BLOCK, int P>
 __global__ void __launch_bounds__(BLOCK)
     scan_mp_kernel(const float4* __restrict__ xyzm, const uint32_t* __restrict__ ids,
-                   const int32_t* __restrict__ start_pos, int n, int k, int start, int32_t* __restrict__ order,
+                   const uint32_t* __restrict__ codes, const int32_t* __restrict__ start_pos, int n, int k, int start, int32_t* __restrict__ order,
                    float* __restrict__ radius, const DevHeader* __restrict__ hdr, uint32_t* __restrict__ err,
                    uint64_t* __restrict__ slots, uint64_t* __restrict__ ticks, int max_picks) {
     constexpr int NW = BLOCK / 64;
@@ -171,12 +221,15 @@ __global__ void __launch_bounds__(BLOCK)
     __shared__ uint32_t s_pid[kMpMaxPicks];        // original index
     __shared__ int s_ppos[kMpMaxPicks];            // sorted position
     __shared__ uint32_t s_id[P * BLOCK];           // original index of each held candidate
-    __shared__ float s_z[P * BLOCK];               // and its z
+    __shared__ float4 s_slo[NW][P], s_shi[NW][P];  // box of each slab of 64 (x, y, z; w unused)
     __shared__ int s_kfail, s_na, s_abort;
+#ifdef BS_PHASE_PROF
+    __shared__ int s_reach;
+#endif
 
     const int tid = threadIdx.x;
     const int lane = tid & 63;
-    const int wave = tid >> 6;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);  // uniform: addresses stay scalar
     const int G = int(gridDim.x);
     const int g = int(blockIdx.x);
     if (k <= 0) return;
@@ -190,8 +243,7 @@ __global__ void __launch_bounds__(BLOCK)
     const int cap_picks = max_picks < kMpMaxPicks ? max_picks : kMpMaxPicks;
     const int wbase = g * BLOCK * P + wave * 64 * P;
 
-    float px[P], py[P], m[P];  // z in LDS: 16 candidates a thread fit 128 registers
-    float lx = INFINITY, ly = INFINITY, lz = INFINITY, hx = -INFINITY, hy = -INFINITY, hz = -INFINITY;
+    float px[P], py[P], pz[P], m[P];
 #pragma unroll
     for (int j = 0; j < P; ++j) {
         const int i = wbase + j * 64 + lane;
@@ -199,24 +251,91 @@ __global__ void __launch_bounds__(BLOCK)
             const float4 q = xyzm[i];
             px[j] = q.x;
             py[j] = q.y;
-            s_z[j * BLOCK + tid] = q.z;
+            pz[j] = q.z;
             m[j] = INFINITY;
             s_id[j * BLOCK + tid] = ids[i];
-            lx = fminf(lx, q.x); ly = fminf(ly, q.y); lz = fminf(lz, q.z);
-            hx = fmaxf(hx, q.x); hy = fmaxf(hy, q.y); hz = fmaxf(hz, q.z);
         } else {
-            px[j] = py[j] = 0.f;
-            s_z[j * BLOCK + tid] = 0.f;
+            px[j] = py[j] = pz[j] = 0.f;
             m[j] = -1.f;  // padding: never selectable, min() keeps it at -1
             s_id[j * BLOCK + tid] = 0;
         }
     }
-    // this wavefront's box (uniform)
+    // The wavefront's candidates (positions p = j*64 + lane, Morton order)
+    // form two groups, p < split and p >= split, split where the first and
+    // last codes first differ: each group lies in one cell of the Morton tree,
+    // so a wavefront across a large jump of the curve does not get one box
+    // spanning both sides (which nearly every pick would reach).
+    int split = 64 * P;
+    {
+        const int wn = min(64 * P, n - wbase);
+        if (wn > 1) {
+            const uint32_t c0 = codes[wbase], c1 = codes[wbase + wn - 1];
+            if (c0 != c1) {
+                const uint32_t bit = 1u << (31 - __builtin_clz(c0 ^ c1));
+                int cnt = 0;
 #pragma unroll
-    for (int d = 32; d > 0; d >>= 1) {
-        lx = fminf(lx, __shfl_xor(lx, d, 64)); ly = fminf(ly, __shfl_xor(ly, d, 64));
-        lz = fminf(lz, __shfl_xor(lz, d, 64)); hx = fmaxf(hx, __shfl_xor(hx, d, 64));
-        hy = fmaxf(hy, __shfl_xor(hy, d, 64)); hz = fmaxf(hz, __shfl_xor(hz, d, 64));
+                for (int j = 0; j < P; ++j) {
+                    const int i = wbase + j * 64 + lane;
+                    cnt += __popcll(__ballot(i < n && (codes[i] & bit) == 0u));
+                }
+                split = __builtin_amdgcn_readfirstlane(cnt);  // sorted: the first cnt positions have the bit clear
+            }
+        }
+    }
+    // slabs of 64 positions holding group a / group b members (uniform)
+    uint32_t slabs_a = 0u, slabs_b = 0u;
+#pragma unroll
+    for (int j = 0; j < P; ++j) {
+        if (j * 64 < split) slabs_a |= 1u << j;
+        if ((j + 1) * 64 > split) slabs_b |= 1u << j;
+    }
+    slabs_a = __builtin_amdgcn_readfirstlane(slabs_a);
+    slabs_b = __builtin_amdgcn_readfirstlane(slabs_b);
+    // each slab's box (lane j of the reach test below tests slab j), from
+    // the sorted points again so that the loop need not unroll
+#pragma unroll 1
+    for (int j = 0; j < P; ++j) {
+        const int i = wbase + j * 64 + lane;
+        const bool live = i < n;
+        const float4 c = live ? xyzm[i] : make_float4(0.f, 0.f, 0.f, 0.f);
+        const float lx = wave_min_f32(live ? c.x : INFINITY), hx = wave_max_f32(live ? c.x : -INFINITY);
+        const float ly = wave_min_f32(live ? c.y : INFINITY), hy = wave_max_f32(live ? c.y : -INFINITY);
+        const float lz = wave_min_f32(live ? c.z : INFINITY), hz = wave_max_f32(live ? c.z : -INFINITY);
+        if (lane == 0) {
+            s_slo[wave][j] = make_float4(lx, ly, lz, 0.f);
+            s_shi[wave][j] = make_float4(hx, hy, hz, 0.f);
+        }
+    }
+    WaveBox ba, bb;  // groups p < split, p >= split (uniform)
+    {
+        float lo[2][3], hi[2][3];
+#pragma unroll
+        for (int gi = 0; gi < 2; ++gi)
+#pragma unroll
+            for (int d = 0; d < 3; ++d) {
+                lo[gi][d] = INFINITY;
+                hi[gi][d] = -INFINITY;
+            }
+#pragma unroll
+        for (int j = 0; j < P; ++j) {
+            if (m[j] < 0.f) continue;  // padding
+            const int gi = j * 64 + lane < split ? 0 : 1;
+            const float c[3] = {px[j], py[j], pz[j]};
+#pragma unroll
+            for (int d = 0; d < 3; ++d) {
+                lo[gi][d] = fminf(lo[gi][d], c[d]);
+                hi[gi][d] = fmaxf(hi[gi][d], c[d]);
+            }
+        }
+#pragma unroll
+        for (int gi = 0; gi < 2; ++gi) {
+            WaveBox& b = gi == 0 ? ba : bb;
+#pragma unroll
+            for (int d = 0; d < 3; ++d) {
+                b.lo[d] = wave_min_f32(lo[gi][d]);
+                b.hi[d] = wave_max_f32(hi[gi][d]);
+            }
+        }
     }
     if (lane == 0) {
         s_w[wave][0] = s_w[wave][1] = s_w[wave][2] = 0ull;
@@ -229,6 +348,9 @@ __global__ void __launch_bounds__(BLOCK)
         s_pid[0] = uint32_t(start);
         s_ppos[0] = sp;
         s_abort = 0;
+#ifdef BS_PHASE_PROF
+        s_reach = 0;
+#endif
         if (g == 0) {
             order[0] = start;
             if (radius) radius[0] = INFINITY;
@@ -249,30 +371,50 @@ __global__ void __launch_bounds__(BLOCK)
         const int tid = tid_v, lane = tid_v & 63;
         const int buf = step & 1;
         BS_SPROF(0, wall_clock64());
-        // 1. the previous step's picks: the ones whose ball reaches this
-        // wavefront's box lower m; the ones it owns become chosen
-        uint64_t rm[2], om[2];  // picks 0-63 and 64-127
+        BS_TPROF(0, wall_clock64());
+        // 1. the previous step's picks: the ones whose ball reaches a group's
+        // box lower m in that group's slabs of 64; the ones it owns become chosen
+        uint64_t ra[2], rb[2], om[2];  // picks 0-63 and 64-127
 #pragma unroll
         for (int h = 0; h < 2; ++h) {
             const int qi = h * 64 + lane;
-            bool reach = false, own = false;
+            bool reach_a = false, reach_b = false, own = false;
             if (qi < K) {
                 const float4 q = s_pk[qi];
-                reach = box_lower(lx, ly, lz, hx, hy, hz, q.x, q.y, q.z) < q.w;
+                reach_a = wave_box_lower(ba, q.x, q.y, q.z) < q.w;
+                reach_b = wave_box_lower(bb, q.x, q.y, q.z) < q.w;
                 const int off = s_ppos[qi] - wbase;
                 own = off >= 0 && off < 64 * P;
             }
-            rm[h] = __ballot(reach);
+            ra[h] = __ballot(reach_a);
+            rb[h] = __ballot(reach_b);
             om[h] = __ballot(own);
         }
-        if ((rm[0] | rm[1] | om[0] | om[1]) != 0ull || step == 1) {  // step 1 fills every wavefront's cache
+#ifdef BS_PHASE_PROF
+        if (lane == 0) atomicAdd(&s_reach, __popcll(ra[0] | rb[0]) + __popcll(ra[1] | rb[1]));
+#endif
+        if ((ra[0] | ra[1] | rb[0] | rb[1] | om[0] | om[1]) != 0ull || step == 1) {  // step 1 fills every cache
 #pragma unroll
             for (int h = 0; h < 2; ++h)
-                for (uint64_t mm = rm[h]; mm; mm &= mm - 1) {
-                    const float4 q = s_pk[h * 64 + __builtin_ctzll(mm)];
+                for (uint64_t mm = ra[h] | rb[h]; mm; mm &= mm - 1) {
+                    const int bq = __builtin_ctzll(mm);
+                    const float4 q = s_pk[h * 64 + bq];
+                    // the slabs holding a group the pick reaches, then of those
+                    // the ones whose own box it reaches (lane j tests slab j)
+                    const uint32_t sg = (((ra[h] >> bq) & 1ull) ? slabs_a : 0u) | (((rb[h] >> bq) & 1ull) ? slabs_b : 0u);
+                    bool hit = false;
+                    if (lane < P && ((sg >> lane) & 1u)) {
+                        const float4 lo = s_slo[wave][lane], hi = s_shi[wave][lane];
+                        hit = box_lower(lo.x, lo.y, lo.z, hi.x, hi.y, hi.z, q.x, q.y, q.z) < q.w;
+                    }
+                    const uint32_t sm = uint32_t(__ballot(hit));
 #pragma unroll
-                    for (int j = 0; j < P; ++j)
-                        m[j] = fminf(m[j], dist2(px[j], py[j], s_z[j * BLOCK + tid], q.x, q.y, q.z));
+                    for (int j = 0; j < P; ++j) {
+                        if (sm & (1u << j)) {
+                            const float d = dist2(px[j], py[j], pz[j], q.x, q.y, q.z);
+                            m[j] = d < m[j] ? d : m[j];  // no NaN here: min without canonicalising
+                        }
+                    }
                 }
 #pragma unroll
             for (int h = 0; h < 2; ++h)
@@ -302,7 +444,7 @@ __global__ void __launch_bounds__(BLOCK)
                     const uint64_t kk = make_key(m[j], s_id[j * BLOCK + tid]);
                     if (kk == w1 || kk == w2)
                         s_wc[wave][kk == w1 ? 0 : 1] =
-                            make_float4(px[j], py[j], s_z[j * BLOCK + tid], __int_as_float(wbase + j * 64 + lane));
+                            make_float4(px[j], py[j], pz[j], __int_as_float(wbase + j * 64 + lane));
                 }
             }
             if (lane == 0) {
@@ -314,6 +456,12 @@ __global__ void __launch_bounds__(BLOCK)
         BS_SPROF(1, wall_clock64());
         lds_barrier();
         BS_SPROF(2, wall_clock64());
+        BS_TPROF(1, wall_clock64());
+#ifdef BS_PHASE_PROF
+        BS_RPROF(s_reach);
+        lds_barrier();
+        if (tid == 0) s_reach = 0;
+#endif
         // 2. wavefront 0: the workgroup's three best, its two entries' data
         // (from the wavefronts that hold them) and its record, one word a lane
         const uint64_t tag = uint64_t(step) << 32;
@@ -353,6 +501,7 @@ __global__ void __launch_bounds__(BLOCK)
             if (lane < kMpWords) st_rec(slots + (size_t(buf) * G + g) * kMpRecStride + lane, tag | wv);
         }
         BS_SPROF(3, wall_clock64());
+        BS_WPROF(0, wall_clock64());
         // 3. every record, a few words a thread, into s_rw (13 words per
         // workgroup); a word is current once its high half is this step
         {
@@ -395,6 +544,7 @@ __global__ void __launch_bounds__(BLOCK)
         if (tid == 0) s_kfail = kMpMaxPicks;
         lds_barrier();
         BS_SPROF(4, wall_clock64());
+        BS_WPROF(1, wall_clock64());
         if (s_abort) {  // a wait gave up: every workgroup's waits end the same way
             if (tid == 0) atomicOr(err, 1u);
             return;
@@ -518,7 +668,7 @@ __global__ void __launch_bounds__(BLOCK)
     }
 }
 
-using ScanMpFn = void (*)(const float4*, const uint32_t*, const int32_t*, int, int, int, int32_t*, float*,
+using ScanMpFn = void (*)(const float4*, const uint32_t*, const uint32_t*, const int32_t*, int, int, int, int32_t*, float*,
                           const DevHeader*, uint32_t*, uint64_t*, uint64_t*, int);
 
 struct MpEntry {
@@ -562,10 +712,11 @@ hipError_t launch_scan_several(const ScanShape& s, const float* pts, int n, int 
     if (ev && ev->begin && (e = hipEventRecord(ev->begin, st)) != hipSuccess) return e;
     const float4* xyzm = sp.xyzm;
     const uint32_t* ids = sp.ids;
+    const uint32_t* codes = sp.codes;
     const int32_t* start_pos = sp.start_pos;
     const DevHeader* hdr = sp.hdr;
     uint32_t* err = &sp.hdr->error;
-    void* args[] = {(void*)&xyzm,  (void*)&ids,   (void*)&start_pos, (void*)&n,     (void*)&k,
+    void* args[] = {(void*)&xyzm,  (void*)&ids,   (void*)&codes, (void*)&start_pos, (void*)&n,     (void*)&k,
                     (void*)&start, (void*)&order, (void*)&radius,    (void*)&hdr,   (void*)&err,
                     (void*)&slots, (void*)&ticks, (void*)&picks};
     e = hipLaunchCooperativeKernel(reinterpret_cast<const void*>(fn), dim3(s.groups), dim3(s.block), args, 0, st);
