@@ -145,31 +145,7 @@ __device__ __forceinline__ uint64_t rec_key(const uint32_t* rw, int e) {
         if (ticks && tid == 0 && (size_t(step) + 1) * G <= size_t(k) * 4)                   \
             ticks[size_t(k) * 8 + size_t(q) * size_t(k) * 4 + size_t(step) * G + g] = uint64_t(v); \
     } while (0)
-// steps 3000 .. 4023 (profiling builds): per workgroup the longest phase 1 of
-// one wavefront (clock ticks) and (most picks reaching one wavefront) << 16 |
-// (wavefronts reached)
-#define BS_VPROF(q, v)                                                                          \
-    do {                                                                                        \
-        if (ticks && tid == 0 && step >= 3000u && step < 4024u)                                \
-            ticks[size_t(k) * 2 + size_t(q) * size_t(k) + size_t(step - 3000u) * G + g] = uint64_t(v); \
-    } while (0)
-// whole run (profiling builds): per workgroup, cycles of the reached-wavefront
-// path by part, and counts
-#define BS_CPROF_MARK(name) const uint64_t name = __builtin_amdgcn_s_memtime()
-#define BS_CPROF_ADD(i, v) \
-    do {                   \
-        if (lane == 0) atomicAdd(&s_acc[i], uint32_t(v)); \
-    } while (0)
 #else
-#define BS_CPROF_MARK(name) \
-    do {                    \
-    } while (0)
-#define BS_CPROF_ADD(i, v) \
-    do {                   \
-    } while (0)
-#define BS_VPROF(q, v) \
-    do {               \
-    } while (0)
 #define BS_TPROF(q, v) \
     do {               \
     } while (0)
@@ -248,9 +224,7 @@ __global__ void __launch_bounds__(BLOCK)
     __shared__ float4 s_slo[NW][P], s_shi[NW][P];  // box of each slab of 64 (x, y, z; w unused)
     __shared__ int s_kfail, s_na, s_abort;
 #ifdef BS_PHASE_PROF
-    __shared__ uint32_t s_acc[8];
-    __shared__ int s_reach, s_vreach, s_vmax;
-    __shared__ uint32_t s_vdur;
+    __shared__ int s_reach;
 #endif
 
     const int tid = threadIdx.x;
@@ -375,9 +349,7 @@ __global__ void __launch_bounds__(BLOCK)
         s_ppos[0] = sp;
         s_abort = 0;
 #ifdef BS_PHASE_PROF
-        for (int i = 0; i < 8; ++i) s_acc[i] = 0u;
-        s_reach = s_vreach = s_vmax = 0;
-        s_vdur = 0u;
+        s_reach = 0;
 #endif
         if (g == 0) {
             order[0] = start;
@@ -419,17 +391,10 @@ __global__ void __launch_bounds__(BLOCK)
             om[h] = __ballot(own);
         }
 #ifdef BS_PHASE_PROF
-        const uint64_t prof_t0 = wall_clock64();
-        if (lane == 0) {
-            const int np = __popcll(ra[0] | rb[0]) + __popcll(ra[1] | rb[1]);
-            atomicAdd(&s_reach, np);
-            if (np > 0) atomicAdd(&s_vreach, 1);
-            atomicMax(&s_vmax, np);
-        }
+        if (lane == 0) atomicAdd(&s_reach, __popcll(ra[0] | rb[0]) + __popcll(ra[1] | rb[1]));
 #endif
         if ((ra[0] | ra[1] | rb[0] | rb[1] | om[0] | om[1]) != 0ull || step == 1) {  // step 1 fills every cache
             bool lowered = false;  // some m of this lane dropped
-            BS_CPROF_MARK(c0);
 #pragma unroll
             for (int h = 0; h < 2; ++h)
                 for (uint64_t mm = ra[h] | rb[h]; mm; mm &= mm - 1) {
@@ -454,8 +419,6 @@ __global__ void __launch_bounds__(BLOCK)
                         }
                     }
                 }
-            BS_CPROF_MARK(c1);
-            BS_CPROF_ADD(0, c1 - c0);
 #pragma unroll
             for (int h = 0; h < 2; ++h)
                 for (uint64_t mm = om[h]; mm; mm &= mm - 1) {
@@ -465,18 +428,10 @@ __global__ void __launch_bounds__(BLOCK)
                         if (off == j * 64 + lane) m[j] = -1.f;
                 }
             // the cached best keys stay exact unless some m changed
-            BS_CPROF_MARK(c2);
-            BS_CPROF_ADD(1, c2 - c1);
-            BS_CPROF_ADD(6, 1);
             if (__ballot(lowered) != 0ull || (om[0] | om[1]) != 0ull || step == 1) {
-                BS_CPROF_MARK(c3);
-                BS_CPROF_ADD(2, c3 - c2);
-                BS_CPROF_ADD(7, 1);
                 uint64_t a1 = 0, a2 = 0, a3 = 0;  // this lane's three best
 #pragma unroll
                 for (int j = 0; j < P; ++j) insert3(m[j] >= 0.f ? make_key(m[j], s_id[j * BLOCK + tid]) : 0ull, a1, a2, a3);
-                BS_CPROF_MARK(c4);
-                BS_CPROF_ADD(3, c4 - c3);
                 // the wavefront's three best: three plain maxima, the lane
                 // holding each one shifting it out (keys are unique)
                 const uint64_t w1 = wave_max_u64(a1);
@@ -487,8 +442,6 @@ __global__ void __launch_bounds__(BLOCK)
                 const uint64_t w2 = wave_max_u64(a1);
                 if (a1 == w2) a1 = a2;
                 const uint64_t w3 = wave_max_u64(a1);
-                BS_CPROF_MARK(c5);
-                BS_CPROF_ADD(4, c5 - c4);
                 // coordinates of the two best: the slots whose value matches
                 // one of them (keys are unique: the index decides after)
                 uint32_t vm = 0u;
@@ -515,8 +468,6 @@ __global__ void __launch_bounds__(BLOCK)
                     if (kk == w1 || kk == w2)
                         s_wc[wave][kk == w1 ? 0 : 1] = make_float4(x, y, z, __int_as_float(wbase + js * 64 + lane));
                 }
-                BS_CPROF_MARK(c6);
-                BS_CPROF_ADD(5, c6 - c5);
                 if (lane == 0) {
                     s_w[wave][0] = w1;
                     s_w[wave][1] = w2;
@@ -524,19 +475,14 @@ __global__ void __launch_bounds__(BLOCK)
                 }
             }
         }
-#ifdef BS_PHASE_PROF
-        if (lane == 0) atomicMax(&s_vdur, uint32_t(wall_clock64() - prof_t0));
-#endif
         BS_SPROF(1, wall_clock64());
         lds_barrier();
         BS_SPROF(2, wall_clock64());
         BS_TPROF(1, wall_clock64());
 #ifdef BS_PHASE_PROF
         BS_RPROF(s_reach);
-        BS_VPROF(0, s_vdur);
-        BS_VPROF(1, (uint32_t(s_vmax) << 16) | uint32_t(s_vreach));
         lds_barrier();
-        if (tid == 0) s_reach = s_vreach = s_vmax = 0, s_vdur = 0u;
+        if (tid == 0) s_reach = 0;
 #endif
         // 2. wavefront 0: the workgroup's three best, its two entries' data
         // (from the wavefronts that hold them) and its record, one word a lane
@@ -742,10 +688,6 @@ __global__ void __launch_bounds__(BLOCK)
         t += K;
         if (t >= k || K <= 0) break;
     }
-#ifdef BS_PHASE_PROF
-    __syncthreads();
-    if (ticks && tid < 8) ticks[size_t(k) * 2 + size_t(g) * 8 + tid] = s_acc[tid];
-#endif
 }
 
 using ScanMpFn = void (*)(const float4*, const uint32_t*, const uint32_t*, const int32_t*, int, int, int, int32_t*, float*,

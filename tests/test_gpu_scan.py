@@ -215,3 +215,17 @@ def test_several_picks_nonfinite_input(hip):
     assert (o.cpu().numpy() == -1).all() and np.isnan(r.cpu().numpy()).all()
     with pytest.raises(ValueError):
         hip.order(Pt, 5000, start=0, tune=hip.tuning(kernel=hip.KERNEL_COOP, per_thread=4, picks=64))
+
+
+@pytest.mark.parametrize("name", sorted(cases.ADVERSARIAL))
+def test_several_picks_adversarial_many_groups(hip, name):
+    """The automatic plan on the adversarial point sets (duplicates, lattice
+    ties, overflowing distances, mixed scales, collinear points) at a size
+    spanning dozens of workgroups, and with 16 candidates per thread."""
+    n, k = 120000, 15000
+    Q = cases.ADVERSARIAL[name](n, 901)
+    eo, er = oracle.greedy32_grid(Q, k, 11)
+    o, r = run(hip, Q, k, start=11)
+    assert_parity(o, r, eo, er, "%s automatic" % name)
+    o, r = run(hip, Q, k, start=11, tune=hip.tuning(kernel=hip.KERNEL_COOP, block=1024, per_thread=16, picks=128))
+    assert_parity(o, r, eo, er, "%s per_thread=16" % name)
