@@ -625,29 +625,35 @@ __global__ void __launch_bounds__(BLOCK)
                 }
                 na += __popcll(b1) + __popcll(b2);
             }
-            if (lane == 0) s_na = na;
+            if (lane == 0) {
+                s_na = na;
+                if (na & 1) s_mk[na] = 0ull;  // pad the last pair (na < 2 * kMpMaxGroups when odd)
+            }
             BS_SPROF(12, wall_clock64());
         }
         lds_barrier();
         BS_SPROF(13, wall_clock64());
         const int na = s_na;
-        // members ranked among themselves, the first `cap` published
-        if (tid < na) {
-            const uint64_t kc = s_mk[tid];
-            // two keys per 16-byte LDS read, four reads in flight
+        // members ranked among themselves, the first `cap` published: T
+        // consecutive lanes per member (T | 64) count over every T-th pair of
+        // member keys, the counts summed with xor shuffles inside the group
+        int T = 16;
+        while (T > 1 && na * T > BLOCK) T >>= 1;
+        const int lt = __builtin_ctz(T);
+        const int mi = tid >> lt, part = tid & (T - 1);
+        if (mi < na) {
+            const uint64_t kc = s_mk[mi];
             const ulonglong2* mk2 = reinterpret_cast<const ulonglong2*>(s_mk);
-            int rank = 0, j = 0;
-            for (; j + 8 <= na; j += 8) {
-                ulonglong2 kb[4];
-#pragma unroll
-                for (int u = 0; u < 4; ++u) kb[u] = mk2[j / 2 + u];
-#pragma unroll
-                for (int u = 0; u < 4; ++u) rank += (kb[u].x > kc ? 1 : 0) + (kb[u].y > kc ? 1 : 0);
+            const int npairs = (na + 1) >> 1;  // an odd count is padded with a zero key
+            int rank = 0;
+            for (int q = part; q < npairs; q += T) {
+                const ulonglong2 kb = mk2[q];
+                rank += (kb.x > kc ? 1 : 0) + (kb.y > kc ? 1 : 0);
             }
-            for (; j < na; ++j) rank += s_mk[j] > kc ? 1 : 0;
+            for (int d = 1; d < T; d <<= 1) rank += __shfl_xor(rank, d, 64);
             BS_SPROF(14, wall_clock64());
-            if (rank < cap) {
-                const uint32_t* x = s_rw + (s_mi[tid] >> 1) * kMpWords + 6 * (s_mi[tid] & 1) + 2;
+            if (part == 0 && rank < cap) {
+                const uint32_t* x = s_rw + (s_mi[mi] >> 1) * kMpWords + 6 * (s_mi[mi] & 1) + 2;
                 const float4 c = make_float4(__uint_as_float(x[0]), __uint_as_float(x[1]), __uint_as_float(x[2]),
                                              __uint_as_float(x[3]));
                 s_pk[rank] = make_float4(c.x, c.y, c.z, key_value(kc));
