@@ -7,9 +7,10 @@
 // index, unique), q_j is the pick after q_1 .. q_{j-1} iff none of them
 // lowers it and every other remaining key lies below it before the step.
 //
-// Design (MI355X): the candidates, in Morton order, stay in VGPRs of 256
-// cooperative workgroups for the whole ordering; each wavefront holds 1,024
-// consecutive ones, a compact region with a bounding box.  Every workgroup
+// Design (MI355X): the candidates, in Morton order, stay in VGPRs of up to
+// 256 cooperative workgroups for the whole ordering; each wavefront holds
+// 64*P consecutive ones in P slabs of 64, split into two groups where the
+// Morton codes first differ, each group and each slab with a box.  Every workgroup
 // is a bucket: it publishes its two best keys (with coordinates and sorted
 // positions) and the value bits R of its third best, which bound all its
 // other keys.  Every workgroup reads all records and makes the same
@@ -21,10 +22,10 @@
 // Members are ranked among themselves, the first `picks` kept, and the
 // first one that an earlier member lowers ends the step.  The next step
 // applies all accepted picks at once, m <- min(m, d2(., q_1), ...), equal to
-// the sequential updates because min is exact and order-free; a wavefront
-// whose box no pick's ball reaches (binary32 box lower bound >= m of the
-// pick, which bounds every remaining m at its step) skips the update and
-// keeps its cached three best keys.
+// the sequential updates because min is exact and order-free; a group or
+// slab whose box no pick's ball reaches (binary32 box lower bound >= m of the
+// pick, which bounds every remaining m at its step) skips the update, and a
+// wavefront none of whose m changed keeps its cached three best keys.
 #pragma clang fp contract(off)
 
 #include <hip/hip_runtime.h>
@@ -119,8 +120,9 @@ __device__ __forceinline__ uint64_t rec_key(const uint32_t* rw, int e) {
     return (uint64_t(p[0]) << 32) | p[1];
 }
 
-// Phase timestamps of workgroup 0 per step (profiling builds only; ticks then
-// holds 32 words per step instead of one per pick).
+// Profiling builds only (ticks then holds 32 words per pick, laid out below):
+// phase timestamps of workgroup 0 per step (first 32 words per step; the
+// regions after them hold per-workgroup records).
 #ifdef BS_PHASE_PROF
 #define BS_SPROF(slot, v)                                                                      \
     do {                                                                                       \
@@ -364,7 +366,7 @@ __global__ void __launch_bounds__(BLOCK)
     for (uint32_t step = 1;; ++step) {
         // thread-derived values are recomputed every step from an opaque copy
         // of the thread index (a few VALU operations) instead of being kept
-        // live across the loop next to the 48 registers of candidates, where
+        // live across the loop next to the 64 registers of candidates, where
         // the compiler would spill them
         int tid_v = int(threadIdx.x);
         asm volatile("" : "+v"(tid_v));
