@@ -77,9 +77,12 @@ const char* bs_version(void);
 
 /* ---------------------------------------------------------------- tuning */
 typedef enum {
-    BS_KERNEL_AUTO = 0,  /* library picks (autotuned table) */
+    BS_KERNEL_AUTO = 0,  /* library picks (autotuned table; without one: up to 16,384
+                            candidates BS_KERNEL_WG, up to 4,194,304 BS_KERNEL_COOP with
+                            128 picks per step, above that BS_KERNEL_GRID) */
     BS_KERNEL_WG = 1,    /* one workgroup, candidates resident in registers */
-    BS_KERNEL_COOP = 2,  /* cooperative workgroups, resident, full scan */
+    BS_KERNEL_COOP = 2,  /* cooperative workgroups, resident, full scan (several picks
+                            per step with tuning picks > 1) */
     BS_KERNEL_GRID = 3   /* uniform-grid radius-pruned kernel */
 } bs_kernel;
 
@@ -92,8 +95,9 @@ typedef struct {
     int32_t picks;         /* grid kernel: most picks per round, 0 = auto, 1 = one pick
                               per round, 2..32 = several exact picks per round (same
                               result; see bs_order_ex).  Cooperative full scan
-                              (BS_KERNEL_COOP, 1024-thread workgroups, 4, 8, 12 or 16
-                              per thread): 2..128 = several exact picks per step over
+                              (BS_KERNEL_COOP; 1024-thread workgroups with 4, 8, 12 or
+                              16 per thread, or 512-thread with 24 or 32; 2..256
+                              workgroups): 2..128 = several exact picks per step over
                               the candidates in Morton order, every workgroup a bucket
                               offering its two best keys */
     int32_t lead_picks;    /* grid kernel with several picks per round: the first picks
