@@ -43,7 +43,8 @@ def brute_greedy_f32(P, k, start):
         dx = P[:, None, 0] - Q[None, :, 0]
         dy = P[:, None, 1] - Q[None, :, 1]
         dz = P[:, None, 2] - Q[None, :, 2]
-        d2 = (dx * dx + dy * dy) + dz * dz
+        with np.errstate(over="ignore"):  # overflowing coordinates: +inf is the binary32 result
+            d2 = (dx * dx + dy * dy) + dz * dz
         m = d2.min(axis=1)
         live = np.ones(n, dtype=bool)
         live[order] = False
@@ -105,7 +106,8 @@ def nearest_prefix_d2_f32(P, prefix_idx, query_idx):
     dx = X[:, None, 0] - Q[None, :, 0]
     dy = X[:, None, 1] - Q[None, :, 1]
     dz = X[:, None, 2] - Q[None, :, 2]
-    return ((dx * dx + dy * dy) + dz * dz).min(axis=1)
+    with np.errstate(over="ignore"):  # overflowing coordinates: +inf is the binary32 result
+        return ((dx * dx + dy * dy) + dz * dz).min(axis=1)
 
 
 def check_invariants(P, order, radius, steps=None):
@@ -144,7 +146,8 @@ def check_invariants(P, order, radius, steps=None):
         dx = Q[:, None, 0] - Q[None, :, 0]
         dy = Q[:, None, 1] - Q[None, :, 1]
         dz = Q[:, None, 2] - Q[None, :, 2]
-        d2 = (dx * dx + dy * dy) + dz * dz
+        with np.errstate(over="ignore"):  # overflowing coordinates: +inf is the binary32 result
+            d2 = (dx * dx + dy * dy) + dz * dz
         np.fill_diagonal(d2, np.inf)
         assert np.sqrt(d2.min()) >= radius[t], ("packing", t)
 
