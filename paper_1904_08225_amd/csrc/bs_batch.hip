@@ -789,11 +789,12 @@ int batch_plan_create(const int64_t* h_offsets, const int64_t* h_k, const uint64
                      [&](int a, int b) { return p->h_k[a] > p->h_k[b]; });
     p->mwork = int(p->h_lpt.size());
     if (p->N > 0) {
-        hipcub::DeviceRadixSort::SortPairs(nullptr, p->sort_bytes, (const uint64_t*)nullptr,
-                                           (uint64_t*)nullptr, (const uint32_t*)nullptr,
-                                           (uint32_t*)nullptr, p->N, 0, end_bit_for(p->m));
-        hipcub::DeviceScan::InclusiveSum(nullptr, p->scan_bytes, (const uint32_t*)nullptr,
-                                         (uint32_t*)nullptr, p->N);
+        // size queries only (no device work): their status carries nothing
+        (void)hipcub::DeviceRadixSort::SortPairs(nullptr, p->sort_bytes, (const uint64_t*)nullptr,
+                                                 (uint64_t*)nullptr, (const uint32_t*)nullptr,
+                                                 (uint32_t*)nullptr, p->N, 0, end_bit_for(p->m));
+        (void)hipcub::DeviceScan::InclusiveSum(nullptr, p->scan_bytes, (const uint32_t*)nullptr,
+                                               (uint32_t*)nullptr, p->N);
     }
     p->h_outo = outo;
     p->ws_bytes = batch_layout(*p, nullptr).total;

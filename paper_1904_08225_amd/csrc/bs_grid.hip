@@ -324,11 +324,12 @@ GridLayout grid_layout(int64_t n, int block) {
     g.sbstat = take(size_t(kMaxBlocksAny / 64) * 32);
     g.lead_slots = take(scan_slot_bytes(kMaxCoopGroups));
     size_t sort_bytes = 0, scan_bytes = 0;
-    hipcub::DeviceRadixSort::SortPairs(nullptr, sort_bytes, (const uint32_t*)nullptr, (uint32_t*)nullptr,
-                                       (const uint32_t*)nullptr, (uint32_t*)nullptr, int(n), 0,
-                                       3 * kMortonBits);
-    hipcub::DeviceScan::InclusiveSum(nullptr, scan_bytes, (const uint32_t*)nullptr, (uint32_t*)nullptr,
-                                     int(n));
+    // size queries only (no device work): their status carries nothing
+    (void)hipcub::DeviceRadixSort::SortPairs(nullptr, sort_bytes, (const uint32_t*)nullptr, (uint32_t*)nullptr,
+                                             (const uint32_t*)nullptr, (uint32_t*)nullptr, int(n), 0,
+                                             3 * kMortonBits);
+    (void)hipcub::DeviceScan::InclusiveSum(nullptr, scan_bytes, (const uint32_t*)nullptr, (uint32_t*)nullptr,
+                                           int(n));
     g.temp = take(sort_bytes > scan_bytes ? sort_bytes : scan_bytes);
     g.temp_bytes = sort_bytes > scan_bytes ? sort_bytes : scan_bytes;
     g.total = off;
