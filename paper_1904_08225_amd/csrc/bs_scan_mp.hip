@@ -11,9 +11,10 @@
 // 256 cooperative workgroups for the whole ordering; each wavefront holds
 // 64*P consecutive ones in P slabs of 64, split into two groups where the
 // Morton codes first differ, each group and each slab with a box.  Every workgroup
-// is a bucket: it publishes its two best keys (with coordinates and sorted
-// positions) and the value bits R of its third best, which bound all its
-// other keys.  Every workgroup reads all records and makes the same
+// is a bucket: it publishes its three best keys (with coordinates and sorted
+// positions) and value bits R that bound all its other keys (the best key a
+// wavefront keeps back, or a wavefront's third best when all three of its
+// listed keys are published).  Every workgroup reads all records and makes the same
 // selection: with tau the fixed point of "tau <- max R over the workgroups
 // holding an entry above tau" (from the top workgroup's R), the entries
 // above tau (and the top) are exactly the prefix that the sequential rule
@@ -40,8 +41,9 @@ namespace bs {
 namespace {
 
 constexpr uint32_t kMpSpinLimit = 1u << 21;  // bounded wait (about a second), then give up
-constexpr int kMpRecStride = 16;              // words per exchange record
-constexpr int kMpWords = 13;  // e1 hi, lo, x, y, z, pos; e2 hi, lo, x, y, z, pos; R
+constexpr int kMpEntries = 3;                 // entries a workgroup offers per step
+constexpr int kMpWords = 6 * kMpEntries + 1;  // per entry: key hi, lo, x, y, z, pos; then R
+constexpr int kMpRecStride = 32;              // words per exchange record
 constexpr int kMpMaxPicks = 128;  // two passes of one lane per pick in the reach test
 constexpr int kMpMaxGroups = 256;
 
@@ -75,6 +77,16 @@ __device__ __forceinline__ uint64_t dpp_max_u64(uint64_t v) {
     const uint32_t lo = dpp_u32<CTRL, ROWS>(uint32_t(v)), hi = dpp_u32<CTRL, ROWS>(uint32_t(v >> 32));
     const uint64_t o = (uint64_t(hi) << 32) | lo;
     return o > v ? o : v;
+}
+// Sum over a row of 16 lanes, held by every lane of the row (swaps within
+// pairs and quads, then the half-row and row mirrors: all permutations
+// inside the row, so rows never mix and every source lane is active).
+__device__ __forceinline__ int row_sum16(int v) {
+    v += int(dpp_u32<0xB1, 0xF>(uint32_t(v)));
+    v += int(dpp_u32<0x4E, 0xF>(uint32_t(v)));
+    v += int(dpp_u32<0x141, 0xF>(uint32_t(v)));
+    v += int(dpp_u32<0x140, 0xF>(uint32_t(v)));
+    return v;
 }
 __device__ __forceinline__ uint64_t wave_max_u64(uint64_t v) {
     v = dpp_max_u64<0xB1, 0xF>(v);
@@ -114,9 +126,13 @@ __device__ __forceinline__ int lanes_below(uint64_t m) {
     return int(__builtin_amdgcn_mbcnt_hi(uint32_t(m >> 32), __builtin_amdgcn_mbcnt_lo(uint32_t(m), 0u)));
 }
 
-// Key of entry e (two per record: words 0-1 and 6-7).
+// Entry e of the records (workgroup e / kMpEntries, slot e % kMpEntries):
+// its key, and its x, y, z, sorted position.
+__device__ __forceinline__ const uint32_t* rec_entry(const uint32_t* rw, int e) {
+    return rw + (e / kMpEntries) * kMpWords + 6 * (e % kMpEntries);
+}
 __device__ __forceinline__ uint64_t rec_key(const uint32_t* rw, int e) {
-    const uint32_t* p = rw + (e >> 1) * kMpWords + 6 * (e & 1);
+    const uint32_t* p = rec_entry(rw, e);
     return (uint64_t(p[0]) << 32) | p[1];
 }
 
@@ -215,10 +231,10 @@ __global__ void __launch_bounds__(BLOCK)
     constexpr int NW = BLOCK / 64;
     static_assert(kMpMaxPicks <= 128, "two passes of one lane per pick");
     __shared__ uint64_t s_w[NW][3];                // per wavefront: its three best keys (cached)
-    __shared__ float4 s_wc[NW][2];                 // and x, y, z, sorted position of the best two
+    __shared__ float4 s_wc[NW][3];                 // and x, y, z, sorted position of each
     __shared__ uint32_t s_rw[kMpMaxGroups * kMpWords];  // every workgroup's record (low words)
-    __shared__ __align__(16) uint64_t s_mk[2 * kMpMaxGroups];  // members: keys
-    __shared__ int s_mi[2 * kMpMaxGroups];         // members: entry index
+    __shared__ __align__(16) uint64_t s_mk[kMpEntries * kMpMaxGroups + 2];  // members: keys
+    __shared__ int s_mi[kMpEntries * kMpMaxGroups];  // members: entry index
     __shared__ float4 s_pk[kMpMaxPicks];           // picks by rank: x, y, z, m
     __shared__ uint32_t s_pid[kMpMaxPicks];        // original index
     __shared__ int s_ppos[kMpMaxPicks];            // sorted position
@@ -341,7 +357,7 @@ __global__ void __launch_bounds__(BLOCK)
     }
     if (lane == 0) {
         s_w[wave][0] = s_w[wave][1] = s_w[wave][2] = 0ull;
-        s_wc[wave][0] = s_wc[wave][1] = make_float4(0.f, 0.f, 0.f, 0.f);
+        s_wc[wave][0] = s_wc[wave][1] = s_wc[wave][2] = make_float4(0.f, 0.f, 0.f, 0.f);
     }
     if (tid == 0) {
         const int sp = *start_pos;
@@ -444,14 +460,15 @@ __global__ void __launch_bounds__(BLOCK)
                 const uint64_t w2 = wave_max_u64(a1);
                 if (a1 == w2) a1 = a2;
                 const uint64_t w3 = wave_max_u64(a1);
-                // coordinates of the two best: the slots whose value matches
+                // coordinates of the three best: the slots whose value matches
                 // one of them (keys are unique: the index decides after)
                 uint32_t vm = 0u;
-                const uint32_t w1v = uint32_t(w1 >> 32), w2v = uint32_t(w2 >> 32);
+                const uint32_t w1v = uint32_t(w1 >> 32), w2v = uint32_t(w2 >> 32), w3v = uint32_t(w3 >> 32);
 #pragma unroll
                 for (int j = 0; j < P; ++j) {
                     const uint32_t vb = __float_as_uint(m[j]);
-                    const bool cand = m[j] >= 0.f && ((w1 != 0ull && vb == w1v) || (w2 != 0ull && vb == w2v));
+                    const bool cand = m[j] >= 0.f && ((w1 != 0ull && vb == w1v) || (w2 != 0ull && vb == w2v) ||
+                                                      (w3 != 0ull && vb == w3v));
                     vm |= uint32_t(cand) << j;
                 }
                 while (vm != 0u) {  // a few lanes, a few slots each
@@ -467,8 +484,9 @@ __global__ void __launch_bounds__(BLOCK)
                         mj = hit ? m[j] : mj;
                     }
                     const uint64_t kk = make_key(mj, s_id[js * BLOCK + tid]);
-                    if (kk == w1 || kk == w2)
-                        s_wc[wave][kk == w1 ? 0 : 1] = make_float4(x, y, z, __int_as_float(wbase + js * 64 + lane));
+                    if (kk == w1 || kk == w2 || kk == w3)
+                        s_wc[wave][kk == w1 ? 0 : (kk == w2 ? 1 : 2)] =
+                            make_float4(x, y, z, __int_as_float(wbase + js * 64 + lane));
                 }
                 if (lane == 0) {
                     s_w[wave][0] = w1;
@@ -486,47 +504,57 @@ __global__ void __launch_bounds__(BLOCK)
         lds_barrier();
         if (tid == 0) s_reach = 0;
 #endif
-        // 2. wavefront 0: the workgroup's three best, its two entries' data
-        // (from the wavefronts that hold them) and its record, one word a lane
+        // 2. wavefront 0: the workgroup's three best keys become its entries,
+        // with their data from the wavefronts that hold them, and R bounds
+        // every key it does not offer; its record is one word a lane
         const uint64_t tag = uint64_t(step) << 32;
         if (wave == 0) {
-            const uint64_t c1 = lane < NW ? s_w[lane][0] : 0ull, c2 = lane < NW ? s_w[lane][1] : 0ull;
-            uint64_t v1 = c1, v2 = c2, v3 = lane < NW ? s_w[lane][2] : 0ull;
+            const uint64_t c1 = lane < NW ? s_w[lane][0] : 0ull, c2 = lane < NW ? s_w[lane][1] : 0ull,
+                           c3 = lane < NW ? s_w[lane][2] : 0ull;
+            uint64_t v1 = c1, v2 = c2, v3 = c3;
             dpp_top3_step<0xB1, 0xF>(v1, v2, v3);
             dpp_top3_step<0x4E, 0xF>(v1, v2, v3);
             dpp_top3_step<0x141, 0xF>(v1, v2, v3);
             dpp_top3_step<0x140, 0xF>(v1, v2, v3);  // every lane of row 0 holds the result
-            const uint64_t e1 = rl64(v1, 0), e2 = rl64(v2, 0);
-            const uint32_t rg = uint32_t(__builtin_amdgcn_readlane(int(uint32_t(v3 >> 32)), 0));
-            const uint64_t h1 = __ballot(e1 != 0 && (c1 == e1 || c2 == e1));
-            const uint64_t h2 = __ballot(e2 != 0 && (c1 == e2 || c2 == e2));
-            float4 x1 = make_float4(0.f, 0.f, 0.f, 0.f), x2 = x1;
+            const uint64_t e1 = rl64(v1, 0), e2 = rl64(v2, 0), e3 = rl64(v3, 0);
+            // a wavefront's entries are a prefix of its sorted list: the
+            // first key it keeps back is known exactly, unless all three
+            // listed keys are entries, when its third bounds the rest
+            const int ne = int(c1 != 0 && c1 >= e3) + int(c2 != 0 && c2 >= e3) + int(c3 != 0 && c3 >= e3);
+            const uint64_t kb = ne == 0 ? c1 : (ne == 1 ? c2 : c3);
+            const uint32_t rg = wave_max_u32(uint32_t(kb >> 32));
+            float4 x1 = make_float4(0.f, 0.f, 0.f, 0.f), x2 = x1, x3 = x1;
+            const uint64_t h1 = __ballot(e1 != 0 && (c1 == e1 || c2 == e1 || c3 == e1));
+            const uint64_t h2 = __ballot(e2 != 0 && (c1 == e2 || c2 == e2 || c3 == e2));
+            const uint64_t h3 = __ballot(e3 != 0 && (c1 == e3 || c2 == e3 || c3 == e3));
             if (h1) {
                 const int l = __builtin_ctzll(h1);
-                x1 = s_wc[l][rl64(c1, l) == e1 ? 0 : 1];
+                x1 = s_wc[l][rl64(c1, l) == e1 ? 0 : (rl64(c2, l) == e1 ? 1 : 2)];
             }
             if (h2) {
                 const int l = __builtin_ctzll(h2);
-                x2 = s_wc[l][rl64(c1, l) == e2 ? 0 : 1];
+                x2 = s_wc[l][rl64(c1, l) == e2 ? 0 : (rl64(c2, l) == e2 ? 1 : 2)];
             }
-            uint32_t wv = rg;
-            wv = lane == 11 ? __float_as_uint(x2.w) : wv;
-            wv = lane == 10 ? __float_as_uint(x2.z) : wv;
-            wv = lane == 9 ? __float_as_uint(x2.y) : wv;
-            wv = lane == 8 ? __float_as_uint(x2.x) : wv;
-            wv = lane == 7 ? uint32_t(e2) : wv;
-            wv = lane == 6 ? uint32_t(e2 >> 32) : wv;
-            wv = lane == 5 ? __float_as_uint(x1.w) : wv;
-            wv = lane == 4 ? __float_as_uint(x1.z) : wv;
-            wv = lane == 3 ? __float_as_uint(x1.y) : wv;
-            wv = lane == 2 ? __float_as_uint(x1.x) : wv;
-            wv = lane == 1 ? uint32_t(e1) : wv;
-            wv = lane == 0 ? uint32_t(e1 >> 32) : wv;
+            if (h3) {
+                const int l = __builtin_ctzll(h3);
+                x3 = s_wc[l][rl64(c1, l) == e3 ? 0 : (rl64(c2, l) == e3 ? 1 : 2)];
+            }
+            // lane 6 e + f carries word f of entry e; lane 18 carries R
+            const uint64_t ek = lane < 6 ? e1 : (lane < 12 ? e2 : e3);
+            const float4 ex = lane < 6 ? x1 : (lane < 12 ? x2 : x3);
+            const int f = lane < 6 ? lane : (lane < 12 ? lane - 6 : lane - 12);
+            uint32_t wv = __float_as_uint(ex.w);
+            wv = f == 4 ? __float_as_uint(ex.z) : wv;
+            wv = f == 3 ? __float_as_uint(ex.y) : wv;
+            wv = f == 2 ? __float_as_uint(ex.x) : wv;
+            wv = f == 1 ? uint32_t(ek) : wv;
+            wv = f == 0 ? uint32_t(ek >> 32) : wv;
+            wv = lane == 6 * kMpEntries ? rg : wv;
             if (lane < kMpWords) st_rec(slots + (size_t(buf) * G + g) * kMpRecStride + lane, tag | wv);
         }
         BS_SPROF(3, wall_clock64());
         BS_WPROF(0, wall_clock64());
-        // 3. every record, a few words a thread, into s_rw (13 words per
+        // 3. every record, a few words a thread, into s_rw (kMpWords per
         // workgroup); a word is current once its high half is this step
         {
             constexpr int RW = (kMpMaxGroups * kMpWords + BLOCK - 1) / BLOCK;  // words a thread reads
@@ -579,14 +607,13 @@ __global__ void __launch_bounds__(BLOCK)
         // above tau iff its first does), the members listed in s_mk / s_mi
         const int cap = min(cap_picks, k - t);
         if (wave == 0) {
-            uint64_t k1[kMpMaxGroups / 64], k2[kMpMaxGroups / 64];
+            uint64_t k1[kMpMaxGroups / 64];
             uint32_t rr[kMpMaxGroups / 64];
 #pragma unroll
             for (int c = 0; c < kMpMaxGroups / 64; ++c) {
                 const int w = c * 64 + lane;
-                k1[c] = w < G ? rec_key(s_rw, 2 * w) : 0ull;
-                k2[c] = w < G ? rec_key(s_rw, 2 * w + 1) : 0ull;
-                rr[c] = w < G ? s_rw[w * kMpWords + 12] : 0u;
+                k1[c] = w < G ? rec_key(s_rw, kMpEntries * w) : 0ull;
+                rr[c] = w < G ? s_rw[w * kMpWords + 6 * kMpEntries] : 0u;
             }
             uint64_t top = 0;
             uint32_t topr = 0;
@@ -613,74 +640,100 @@ __global__ void __launch_bounds__(BLOCK)
             for (int c = 0; c < kMpMaxGroups / 64; ++c) {
                 const int w = c * 64 + lane;
                 const bool m1 = k1[c] != 0 && (k1[c] == tk || uint32_t(k1[c] >> 32) > tau);
-                const bool m2 = k2[c] != 0 && uint32_t(k2[c] >> 32) > tau;  // e2 < e1 <= top
-                const uint64_t b1 = __ballot(m1), b2 = __ballot(m2);
+                const uint64_t k2 = w < G ? rec_key(s_rw, kMpEntries * w + 1) : 0ull;
+                const uint64_t k3 = w < G ? rec_key(s_rw, kMpEntries * w + 2) : 0ull;
+                const bool m2 = k2 != 0 && uint32_t(k2 >> 32) > tau;  // e3 < e2 < e1 <= top
+                const bool m3 = k3 != 0 && uint32_t(k3 >> 32) > tau;
+                const uint64_t b1 = __ballot(m1), b2 = __ballot(m2), b3 = __ballot(m3);
                 const int p1 = na + lanes_below(b1);
                 const int p2 = na + __popcll(b1) + lanes_below(b2);
+                const int p3 = na + __popcll(b1) + __popcll(b2) + lanes_below(b3);
                 if (m1) {
                     s_mk[p1] = k1[c];
-                    s_mi[p1] = 2 * w;
+                    s_mi[p1] = kMpEntries * w;
                 }
                 if (m2) {
-                    s_mk[p2] = k2[c];
-                    s_mi[p2] = 2 * w + 1;
+                    s_mk[p2] = k2;
+                    s_mi[p2] = kMpEntries * w + 1;
                 }
-                na += __popcll(b1) + __popcll(b2);
+                if (m3) {
+                    s_mk[p3] = k3;
+                    s_mi[p3] = kMpEntries * w + 2;
+                }
+                na += __popcll(b1) + __popcll(b2) + __popcll(b3);
             }
-            if (lane == 0) {
-                s_na = na;
-                if (na & 1) s_mk[na] = 0ull;  // pad the last pair (na < 2 * kMpMaxGroups when odd)
-            }
+            if (lane == 0) s_na = na;
             BS_SPROF(12, wall_clock64());
         }
         lds_barrier();
         BS_SPROF(13, wall_clock64());
         const int na = s_na;
-        // members ranked among themselves, the first `cap` published: T
-        // consecutive lanes per member (T | 64) count over every T-th pair of
-        // member keys, the counts summed with xor shuffles inside the group
-        int T = 16;
-        while (T > 1 && na * T > BLOCK) T >>= 1;
-        const int lt = __builtin_ctz(T);
-        const int mi = tid >> lt, part = tid & (T - 1);
-        if (mi < na) {
-            const uint64_t kc = s_mk[mi];
+        // members ranked among themselves, the first `cap` published: a row
+        // of 16 lanes ranks MR members, each lane counting over every 16th
+        // pair of member keys (one load serves MR compares), the counts
+        // summed across the row with DPP
+        {
+            constexpr int MR = 4;
+            const int row = tid >> 4, part = tid & 15;
             const ulonglong2* mk2 = reinterpret_cast<const ulonglong2*>(s_mk);
-            const int npairs = (na + 1) >> 1;  // an odd count is padded with a zero key
-            int rank = 0;
-            for (int q = part; q < npairs; q += T) {
-                const ulonglong2 kb = mk2[q];
-                rank += (kb.x > kc ? 1 : 0) + (kb.y > kc ? 1 : 0);
-            }
-            for (int d = 1; d < T; d <<= 1) rank += __shfl_xor(rank, d, 64);
-            BS_SPROF(14, wall_clock64());
-            if (part == 0 && rank < cap) {
-                const uint32_t* x = s_rw + (s_mi[mi] >> 1) * kMpWords + 6 * (s_mi[mi] & 1) + 2;
-                const float4 c = make_float4(__uint_as_float(x[0]), __uint_as_float(x[1]), __uint_as_float(x[2]),
-                                             __uint_as_float(x[3]));
-                s_pk[rank] = make_float4(c.x, c.y, c.z, key_value(kc));
-                s_pid[rank] = key_id(kc);
-                s_ppos[rank] = __float_as_int(c.w);
+            const int npairs = (na + 1) >> 1;  // the last pair's second key is ignored when na is odd
+            for (int base = 0; base < na; base += (BLOCK / 16) * MR) {
+                const int m0 = base + row * MR;
+                if (m0 >= na) continue;  // whole rows drop out
+                uint64_t kc[MR];
+                int rk[MR];
+#pragma unroll
+                for (int r = 0; r < MR; ++r) {
+                    kc[r] = m0 + r < na ? s_mk[m0 + r] : ~0ull;
+                    rk[r] = 0;
+                }
+#pragma unroll 2
+                for (int q = part; q < npairs; q += 16) {
+                    const ulonglong2 kb = mk2[q];
+                    const bool yok = 2 * q + 1 < na;
+#pragma unroll
+                    for (int r = 0; r < MR; ++r) rk[r] += int(kb.x > kc[r]) + int(yok && kb.y > kc[r]);
+                }
+#pragma unroll
+                for (int r = 0; r < MR; ++r) rk[r] = row_sum16(rk[r]);
+                BS_SPROF(14, wall_clock64());
+                int rank = rk[0];
+#pragma unroll
+                for (int r = 1; r < MR; ++r) rank = part == r ? rk[r] : rank;
+                const int mi = m0 + part;
+                if (part < MR && mi < na && rank < cap) {
+                    const uint32_t* x = rec_entry(s_rw, s_mi[mi]) + 2;
+                    const float4 c = make_float4(__uint_as_float(x[0]), __uint_as_float(x[1]),
+                                                 __uint_as_float(x[2]), __uint_as_float(x[3]));
+                    s_pk[rank] = make_float4(c.x, c.y, c.z, key_value(s_mk[mi]));
+                    s_pid[rank] = key_id(s_mk[mi]);
+                    s_ppos[rank] = __float_as_int(c.w);
+                }
             }
         }
         const int nr = min(na, cap);
         BS_SPROF(8, na);
         lds_barrier();
         BS_SPROF(6, wall_clock64());
-        // 5. distance conflicts: lane i of a wavefront tests members i, i + 64 against
-        // the wavefront's members j = wave, wave + NW, ... (pairs i < j); the
-        // lowest failing j of a wavefront goes to LDS in one atomic
+        // 5. distance conflicts: TPC threads per member j test it against the
+        // earlier members i < j (every TPC-th one each); a wavefront's eight
+        // or more consecutive columns give their lowest lowered j by ballot,
+        // and that goes to LDS in one atomic
         {
-            uint32_t fail = kMpMaxPicks;
-            for (int i = lane; i < nr; i += 64) {
-                const float4 ci = s_pk[i];
-                for (int j = wave; j < nr; j += NW) {
-                    const float4 cj = s_pk[j];
-                    if (i < j && dist2(cj.x, cj.y, cj.z, ci.x, ci.y, ci.z) < cj.w) fail = min(fail, uint32_t(j));
+            constexpr int TPC = BLOCK / kMpMaxPicks;  // threads per column
+            static_assert(TPC >= 1 && (TPC & (TPC - 1)) == 0 && 64 % TPC == 0, "conflict tiling");
+            const int j = tid / TPC, part = tid % TPC;  // j < kMpMaxPicks
+            bool low = false;
+            if (j < nr) {
+                const float4 cj = s_pk[j];
+#pragma unroll 2
+                for (int i = part; i < j; i += TPC) {
+                    const float4 ci = s_pk[i];
+                    if (dist2(cj.x, cj.y, cj.z, ci.x, ci.y, ci.z) < cj.w) low = true;
                 }
             }
-            fail = ~wave_max_u32(~fail);  // wavefront minimum
-            if (lane == 0 && fail < uint32_t(kMpMaxPicks)) atomicMin(&s_kfail, int(fail));
+            const uint64_t b = __ballot(low);
+            if (b != 0 && lane == 0) atomicMin(&s_kfail, (wave * 64 + __builtin_ctzll(b)) / TPC);
         }
         lds_barrier();
         K = min(s_kfail, nr);
@@ -733,6 +786,9 @@ hipError_t launch_scan_several(const ScanShape& s, const float* pts, int n, int 
     for (const MpEntry& e : kMpTable)
         if (e.block == s.block && e.per_thread == s.per_thread) fn = e.fn;
     if (!fn || !scan_several_supported(s)) return hipErrorInvalidValue;
+    // both record buffers must fit the exchange area the workspace reserves
+    if (size_t(2) * size_t(s.groups) * kMpRecStride * sizeof(uint64_t) > scan_slot_bytes(kMaxCoopGroups))
+        return hipErrorInvalidValue;
     SortedPoints sp{};
     hipError_t e = launch_sorted_points(pts, n, start, ws, st, &sp);
     if (e != hipSuccess) return e;
