@@ -593,7 +593,10 @@ __global__ void __launch_bounds__(BLOCK)
             if (aborted && lane == 0) s_abort = 1;
             BS_SPROF(11, spins);
         }
-        if (tid == 0) s_kfail = kMpMaxPicks;
+        if (tid == 0) {
+            s_kfail = kMpMaxPicks;
+            s_na = 0;
+        }
         lds_barrier();
         BS_SPROF(4, wall_clock64());
         BS_WPROF(1, wall_clock64());
@@ -602,11 +605,14 @@ __global__ void __launch_bounds__(BLOCK)
             return;
         }
 
-        // 4. the accepted set (wavefront 0): the top entry, tau from the top
-        // workgroup's R up to its fixed point (a workgroup holds an entry
-        // above tau iff its first does), the members listed in s_mk / s_mi
+        // 4. the accepted set: the top entry, tau from the top workgroup's R
+        // up to its fixed point (a workgroup holds an entry above tau iff its
+        // first does), each found by every wavefront that lists members; the
+        // members of workgroups 64 c .. 64 c + 63 listed in s_mk / s_mi by
+        // wavefront c, at a base taken with one LDS atomic (their order there
+        // is free: ranks come from the keys)
         const int cap = min(cap_picks, k - t);
-        if (wave == 0) {
+        if (wave < ((G + 63) >> 6)) {
             uint64_t k1[kMpMaxGroups / 64];
             uint32_t rr[kMpMaxGroups / 64];
 #pragma unroll
@@ -635,34 +641,38 @@ __global__ void __launch_bounds__(BLOCK)
                 tau = mr;
             }
             BS_SPROF(5, wall_clock64());
-            int na = 0;
+            const int w = wave * 64 + lane;
+            uint64_t k1w = k1[0];
 #pragma unroll
-            for (int c = 0; c < kMpMaxGroups / 64; ++c) {
-                const int w = c * 64 + lane;
-                const bool m1 = k1[c] != 0 && (k1[c] == tk || uint32_t(k1[c] >> 32) > tau);
-                const uint64_t k2 = w < G ? rec_key(s_rw, kMpEntries * w + 1) : 0ull;
-                const uint64_t k3 = w < G ? rec_key(s_rw, kMpEntries * w + 2) : 0ull;
-                const bool m2 = k2 != 0 && uint32_t(k2 >> 32) > tau;  // e3 < e2 < e1 <= top
-                const bool m3 = k3 != 0 && uint32_t(k3 >> 32) > tau;
-                const uint64_t b1 = __ballot(m1), b2 = __ballot(m2), b3 = __ballot(m3);
-                const int p1 = na + lanes_below(b1);
-                const int p2 = na + __popcll(b1) + lanes_below(b2);
-                const int p3 = na + __popcll(b1) + __popcll(b2) + lanes_below(b3);
-                if (m1) {
-                    s_mk[p1] = k1[c];
-                    s_mi[p1] = kMpEntries * w;
-                }
-                if (m2) {
-                    s_mk[p2] = k2;
-                    s_mi[p2] = kMpEntries * w + 1;
-                }
-                if (m3) {
-                    s_mk[p3] = k3;
-                    s_mi[p3] = kMpEntries * w + 2;
-                }
-                na += __popcll(b1) + __popcll(b2) + __popcll(b3);
+            for (int c = 1; c < kMpMaxGroups / 64; ++c) k1w = wave == c ? k1[c] : k1w;
+            const bool m1 = k1w != 0 && (k1w == tk || uint32_t(k1w >> 32) > tau);
+            const uint64_t k2 = w < G ? rec_key(s_rw, kMpEntries * w + 1) : 0ull;
+            const uint64_t k3 = w < G ? rec_key(s_rw, kMpEntries * w + 2) : 0ull;
+            const bool m2 = k2 != 0 && uint32_t(k2 >> 32) > tau;  // e3 < e2 < e1 <= top
+            const bool m3 = k3 != 0 && uint32_t(k3 >> 32) > tau;
+            const uint64_t b1 = __ballot(m1), b2 = __ballot(m2), b3 = __ballot(m3);
+            const int cnt = __popcll(b1) + __popcll(b2) + __popcll(b3);
+            int base = 0;
+            if (cnt != 0) {
+                int old = 0;
+                if (lane == 0) old = atomicAdd(&s_na, cnt);
+                base = __builtin_amdgcn_readfirstlane(old);  // the whole wavefront is active: lane 0
             }
-            if (lane == 0) s_na = na;
+            const int p1 = base + lanes_below(b1);
+            const int p2 = base + __popcll(b1) + lanes_below(b2);
+            const int p3 = base + __popcll(b1) + __popcll(b2) + lanes_below(b3);
+            if (m1) {
+                s_mk[p1] = k1w;
+                s_mi[p1] = kMpEntries * w;
+            }
+            if (m2) {
+                s_mk[p2] = k2;
+                s_mi[p2] = kMpEntries * w + 1;
+            }
+            if (m3) {
+                s_mk[p3] = k3;
+                s_mi[p3] = kMpEntries * w + 2;
+            }
             BS_SPROF(12, wall_clock64());
         }
         lds_barrier();
