@@ -412,7 +412,17 @@ __global__ void __launch_bounds__(BLOCK)
         if (lane == 0) atomicAdd(&s_reach, __popcll(ra[0] | rb[0]) + __popcll(ra[1] | rb[1]));
 #endif
         if ((ra[0] | ra[1] | rb[0] | rb[1] | om[0] | om[1]) != 0ull || step == 1) {  // step 1 fills every cache
-            bool lowered = false;  // some m of this lane dropped
+            // slots of this lane holding one of the wavefront's cached best
+            // keys (their sorted positions are cached with them): only a
+            // lowered m there can change the three best, since every other m
+            // lies below the third and only drops
+            uint32_t topm = 0u;
+#pragma unroll
+            for (int e = 0; e < 3; ++e) {
+                const int cp = __float_as_int(s_wc[wave][e].w) - wbase;
+                topm |= (cp >= 0 && cp < 64 * P && (cp & 63) == lane) ? 1u << (cp >> 6) : 0u;
+            }
+            uint32_t lowm = 0u;  // slots of this lane whose m dropped
 #pragma unroll
             for (int h = 0; h < 2; ++h)
                 for (uint64_t mm = ra[h] | rb[h]; mm; mm &= mm - 1) {
@@ -433,7 +443,7 @@ __global__ void __launch_bounds__(BLOCK)
                             const float d = dist2(px[j], py[j], pz[j], q.x, q.y, q.z);
                             const bool lower = d < m[j];  // no NaN here: min without canonicalising
                             m[j] = lower ? d : m[j];
-                            lowered = lowered || lower;
+                            lowm |= lower ? 1u << j : 0u;
                         }
                     }
                 }
@@ -445,8 +455,9 @@ __global__ void __launch_bounds__(BLOCK)
                     for (int j = 0; j < P; ++j)
                         if (off == j * 64 + lane) m[j] = -1.f;
                 }
-            // the cached best keys stay exact unless some m changed
-            if (__ballot(lowered) != 0ull || (om[0] | om[1]) != 0ull || step == 1) {
+            // the cached best keys stay exact unless one of their m dropped
+            // or a pick (always one of them) was taken here
+            if (__ballot((lowm & topm) != 0u) != 0ull || (om[0] | om[1]) != 0ull || step == 1) {
                 uint64_t a1 = 0, a2 = 0, a3 = 0;  // this lane's three best
 #pragma unroll
                 for (int j = 0; j < P; ++j) insert3(m[j] >= 0.f ? make_key(m[j], s_id[j * BLOCK + tid]) : 0ull, a1, a2, a3);
