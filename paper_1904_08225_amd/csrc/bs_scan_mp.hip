@@ -185,39 +185,11 @@ __device__ __forceinline__ uint64_t ld_rec(const uint64_t* p) {
     return __hip_atomic_load(const_cast<uint64_t*>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-template <int CTRL, int ROWS>
-__device__ __forceinline__ void dpp_top3_step(uint64_t& a1, uint64_t& a2, uint64_t& a3) {
-    uint64_t b[3];
-    const uint64_t a[3] = {a1, a2, a3};
-#pragma unroll
-    for (int q = 0; q < 3; ++q) {
-        const uint32_t lo = uint32_t(__builtin_amdgcn_update_dpp(0, int(uint32_t(a[q])), CTRL, ROWS, 0xF, false));
-        const uint32_t hi = uint32_t(__builtin_amdgcn_update_dpp(0, int(uint32_t(a[q] >> 32)), CTRL, ROWS, 0xF, false));
-        b[q] = (uint64_t(hi) << 32) | lo;
-    }
-    // the three largest of two descending triples (keys are unique; 0 = none)
-    const bool x = a1 > b[0];
-    const uint64_t c1 = x ? a1 : b[0];
-    const uint64_t p = x ? a2 : a1, q = x ? b[0] : b[1];
-    const bool y = p > q;
-    const uint64_t c2 = y ? p : q;
-    const uint64_t r1 = x ? (y ? a3 : a2) : (y ? a2 : a1);
-    const uint64_t r2 = x ? (y ? b[0] : b[1]) : (y ? b[1] : b[2]);
-    a1 = c1;
-    a2 = c2;
-    a3 = r1 > r2 ? r1 : r2;
-}
-
 __device__ __forceinline__ void insert3(uint64_t kk, uint64_t& a1, uint64_t& a2, uint64_t& a3) {
     const bool g1 = kk > a1, g2 = kk > a2, g3 = kk > a3;
     a3 = g2 ? a2 : (g3 ? kk : a3);
     a2 = g1 ? a1 : (g2 ? kk : a2);
     a1 = g1 ? kk : a1;
-}
-
-__device__ __forceinline__ uint64_t rl64(uint64_t v, int l) {
-    return (uint64_t(uint32_t(__builtin_amdgcn_readlane(int(uint32_t(v >> 32)), l))) << 32) |
-           uint32_t(__builtin_amdgcn_readlane(int(uint32_t(v)), l));
 }
 
 // Points: lane l of wavefront w in workgroup g holds sorted positions
@@ -230,7 +202,8 @@ __global__ void __launch_bounds__(BLOCK)
                    uint64_t* __restrict__ slots, uint64_t* __restrict__ ticks, int max_picks) {
     constexpr int NW = BLOCK / 64;
     static_assert(kMpMaxPicks <= 128, "two passes of one lane per pick");
-    __shared__ uint64_t s_w[NW][3];                // per wavefront: its three best keys (cached)
+    __shared__ __align__(16) uint64_t s_w[NW][3];  // per wavefront: its three best keys (cached)
+    __shared__ uint32_t s_ent[6 * kMpEntries];     // the record's entry words, staged by rank
     __shared__ float4 s_wc[NW][3];                 // and x, y, z, sorted position of each
     __shared__ uint32_t s_rw[kMpMaxGroups * kMpWords];  // every workgroup's record (low words)
     __shared__ __align__(16) uint64_t s_mk[kMpEntries * kMpMaxGroups + 2];  // members: keys
@@ -520,47 +493,41 @@ __global__ void __launch_bounds__(BLOCK)
         // every key it does not offer; its record is one word a lane
         const uint64_t tag = uint64_t(step) << 32;
         if (wave == 0) {
-            const uint64_t c1 = lane < NW ? s_w[lane][0] : 0ull, c2 = lane < NW ? s_w[lane][1] : 0ull,
-                           c3 = lane < NW ? s_w[lane][2] : 0ull;
-            uint64_t v1 = c1, v2 = c2, v3 = c3;
-            dpp_top3_step<0xB1, 0xF>(v1, v2, v3);
-            dpp_top3_step<0x4E, 0xF>(v1, v2, v3);
-            dpp_top3_step<0x141, 0xF>(v1, v2, v3);
-            dpp_top3_step<0x140, 0xF>(v1, v2, v3);  // every lane of row 0 holds the result
-            const uint64_t e1 = rl64(v1, 0), e2 = rl64(v2, 0), e3 = rl64(v3, 0);
-            // a wavefront's entries are a prefix of its sorted list: the
-            // first key it keeps back is known exactly, unless all three
-            // listed keys are entries, when its third bounds the rest
-            const int ne = int(c1 != 0 && c1 >= e3) + int(c2 != 0 && c2 >= e3) + int(c3 != 0 && c3 >= e3);
-            const uint64_t kb = ne == 0 ? c1 : (ne == 1 ? c2 : c3);
-            const uint32_t rg = wave_max_u32(uint32_t(kb >> 32));
-            float4 x1 = make_float4(0.f, 0.f, 0.f, 0.f), x2 = x1, x3 = x1;
-            const uint64_t h1 = __ballot(e1 != 0 && (c1 == e1 || c2 == e1 || c3 == e1));
-            const uint64_t h2 = __ballot(e2 != 0 && (c1 == e2 || c2 == e2 || c3 == e2));
-            const uint64_t h3 = __ballot(e3 != 0 && (c1 == e3 || c2 == e3 || c3 == e3));
-            if (h1) {
-                const int l = __builtin_ctzll(h1);
-                x1 = s_wc[l][rl64(c1, l) == e1 ? 0 : (rl64(c2, l) == e1 ? 1 : 2)];
+            // listed key i of wavefront w on lane 3 w + i, ranked among all
+            // listed keys by counting the larger ones (keys are unique, 0 =
+            // none); ranks 0, 1, 2 are the entries
+            constexpr int NK = 3 * NW;
+            static_assert(NK % 2 == 0 && NK <= 64 && 6 * kMpEntries <= 64, "one key a lane");
+            const int kw = lane / 3, ki = lane - 3 * (lane / 3);
+            const uint64_t kv = lane < NK ? s_w[kw][ki] : 0ull;
+            const ulonglong2* sw2 = reinterpret_cast<const ulonglong2*>(&s_w[0][0]);
+            int rank = 0;
+#pragma unroll
+            for (int c = 0; c < NK / 2; ++c) {
+                const ulonglong2 b = sw2[c];
+                rank += int(b.x > kv) + int(b.y > kv);
             }
-            if (h2) {
-                const int l = __builtin_ctzll(h2);
-                x2 = s_wc[l][rl64(c1, l) == e2 ? 0 : (rl64(c2, l) == e2 ? 1 : 2)];
+            // R: the largest listed key kept back, and each wavefront's third
+            // (which bounds the keys it did not list; a wavefront's entries
+            // are a prefix of its list)
+            const bool kept = kv != 0 && (rank >= kMpEntries || ki == 2);
+            const uint32_t rg = wave_max_u32(kept ? uint32_t(kv >> 32) : 0u);
+            const int nz = __popcll(__ballot(kv != 0));
+            if (kv != 0 && rank < kMpEntries) {
+                const float4 c = s_wc[kw][ki];
+                uint32_t* e = s_ent + 6 * rank;
+                e[0] = uint32_t(kv >> 32);
+                e[1] = uint32_t(kv);
+                e[2] = __float_as_uint(c.x);
+                e[3] = __float_as_uint(c.y);
+                e[4] = __float_as_uint(c.z);
+                e[5] = __float_as_uint(c.w);
             }
-            if (h3) {
-                const int l = __builtin_ctzll(h3);
-                x3 = s_wc[l][rl64(c1, l) == e3 ? 0 : (rl64(c2, l) == e3 ? 1 : 2)];
-            }
-            // lane 6 e + f carries word f of entry e; lane 18 carries R
-            const uint64_t ek = lane < 6 ? e1 : (lane < 12 ? e2 : e3);
-            const float4 ex = lane < 6 ? x1 : (lane < 12 ? x2 : x3);
-            const int f = lane < 6 ? lane : (lane < 12 ? lane - 6 : lane - 12);
-            uint32_t wv = __float_as_uint(ex.w);
-            wv = f == 4 ? __float_as_uint(ex.z) : wv;
-            wv = f == 3 ? __float_as_uint(ex.y) : wv;
-            wv = f == 2 ? __float_as_uint(ex.x) : wv;
-            wv = f == 1 ? uint32_t(ek) : wv;
-            wv = f == 0 ? uint32_t(ek >> 32) : wv;
-            wv = lane == 6 * kMpEntries ? rg : wv;
+            __builtin_amdgcn_wave_barrier();  // LDS in program order within the wavefront
+            // lane 6 e + f carries word f of entry e (zero past the listed
+            // keys); lane 18 carries R
+            uint32_t wv = rg;
+            if (lane < 6 * kMpEntries) wv = lane / 6 < nz ? s_ent[lane] : 0u;
             if (lane < kMpWords) st_rec(slots + (size_t(buf) * G + g) * kMpRecStride + lane, tag | wv);
         }
         BS_SPROF(3, wall_clock64());
