@@ -50,6 +50,18 @@ def mixed_scale(n, seed):
     return np.concatenate([a, b, c]).astype(np.float32)
 
 
+def clumped_outliers(n, seed, clumps=8, per=4):
+    """A unit cube of points plus `clumps` tight clumps of `per` points far
+    away: each clump sits consecutively in Morton order, so one wavefront
+    of the several-picks scan holds all of its workgroup's best keys."""
+    rng = np.random.default_rng(seed)
+    m = clumps * per
+    body = rng.random((n - m, 3))
+    centres = 40.0 + 15.0 * rng.random((clumps, 3)) * np.array([1.0, -1.0, 1.0])
+    clump = np.repeat(centres, per, 0) + 1e-3 * rng.random((m, 3))
+    return np.concatenate([body, clump]).astype(np.float32)
+
+
 ADVERSARIAL = {
     "random": lambda n, s: random_cloud(n, s),
     "lattice": lambda n, s: integer_lattice(*_lattice_dims(n))[:n],

@@ -229,3 +229,17 @@ def test_several_picks_adversarial_many_groups(hip, name):
     assert_parity(o, r, eo, er, "%s automatic" % name)
     o, r = run(hip, Q, k, start=11, tune=hip.tuning(kernel=hip.KERNEL_COOP, block=1024, per_thread=16, picks=128))
     assert_parity(o, r, eo, er, "%s per_thread=16" % name)
+
+
+def test_several_picks_one_wavefront_holds_every_entry(hip):
+    """Far clumps of four points: each clump's workgroup offers three keys
+    from one wavefront, so its bound R comes from that wavefront's third
+    key (an entry itself) rather than from a key kept back."""
+    n, k = 120000, 15000
+    Q = cases.clumped_outliers(n, 23, clumps=24)
+    eo, er = oracle.greedy32_grid(Q, k, 5)
+    o, r = run(hip, Q, k, start=5)
+    assert_parity(o, r, eo, er, "clumped automatic")
+    for pt in (4, 16):
+        o, r = run(hip, Q, k, start=5, tune=hip.tuning(kernel=hip.KERNEL_COOP, block=1024, per_thread=pt, picks=128))
+        assert_parity(o, r, eo, er, "clumped per_thread=%d" % pt)

@@ -73,6 +73,16 @@ def test_grid_equals_plain_adversarial():
                 pins.check_grid_equals_plain(P, n, n // 3, target=target)
 
 
+def test_grid_equals_plain_clumped_outliers():
+    # Far clumps of nearly coincident points: the grid's cells span both
+    # the cube and the clumps, and the clumps are chosen first.
+    for n in (40, 700):
+        P = cases.clumped_outliers(n, 17)
+        pins.check_grid_equals_plain(P, n, n // 2)
+        o, r = oracle.greedy32(P, n, n // 2)
+        pins.check_invariants(P, o, r)
+
+
 @pytest.mark.parametrize("which", ["sphere_and_box", "cad_part"])
 def test_grid_equals_plain_surfaces(which):
     if which == "sphere_and_box":
