@@ -77,9 +77,10 @@ const char* bs_version(void);
 
 /* ---------------------------------------------------------------- tuning */
 typedef enum {
-    BS_KERNEL_AUTO = 0,  /* library picks (autotuned table; without one: up to 16,384
-                            candidates BS_KERNEL_WG, up to 4,194,304 BS_KERNEL_COOP with
-                            128 picks per step, above that BS_KERNEL_GRID) */
+    BS_KERNEL_AUTO = 0,  /* library picks (autotuned table; without one: up to 4,096
+                            candidates BS_KERNEL_WG, from 4,097 (two workgroups) to
+                            4,194,304 BS_KERNEL_COOP with 128 picks per step, above
+                            that BS_KERNEL_GRID) */
     BS_KERNEL_WG = 1,    /* one workgroup, candidates resident in registers */
     BS_KERNEL_COOP = 2,  /* cooperative workgroups, resident, full scan (several picks
                             per step with tuning picks > 1) */

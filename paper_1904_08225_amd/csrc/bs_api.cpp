@@ -71,8 +71,10 @@ struct Plan {
 
 // Shape of the several-picks cooperative scan for n candidates: the most
 // workgroups (fewest candidates per thread) that fit one per CU, two at
-// least -- every workgroup offers two entries per step, so more workgroups
-// accept more picks per step.
+// least -- every workgroup offers three entries per step, so more workgroups
+// accept more picks per step.  The automatic plan takes it whenever such a
+// shape exists (from 4,097 candidates): even a few workgroups beat the one
+// resident workgroup, whose step is one pick.
 bool choose_several_shape(int64_t n, int cus, int want_block, int want_pt, int want_groups, ScanShape* out) {
     static const int kBlocks[] = {1024, 512};
     static const int kPer[] = {4, 8, 12, 16, 24, 32};
@@ -98,7 +100,7 @@ int plan_single(int64_t n, int64_t k, const bs_tuning* t, Plan* p) {
     const int cus = device_cus() > 0 ? device_cus() : 256;
     const int want = t ? t->kernel : BS_KERNEL_AUTO;
     const int wb = t ? t->block : 0, wp = t ? t->per_thread : 0, wg = t ? t->groups : 0;
-    if (want == BS_KERNEL_AUTO && n > kAutoResidentMax && choose_several_shape(n, cus, wb, wp, wg, &p->shape)) {
+    if (want == BS_KERNEL_AUTO && choose_several_shape(n, cus, wb, wp, wg, &p->shape)) {
         p->kernel = BS_KERNEL_COOP;
         p->scan_picks = (t && t->picks > 1) ? t->picks : kAutoScanPicks;
         return BS_OK;

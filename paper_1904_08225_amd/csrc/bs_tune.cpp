@@ -48,6 +48,7 @@ std::vector<bs_tuning> single_candidates(int64_t n) {
     std::vector<bs_tuning> c;
     if (n <= 16384) {
         c.push_back(make_tuning(BS_KERNEL_WG, 0, 0, 0.f, 0));
+        if (n > 4 * 1024) c.push_back(make_tuning(BS_KERNEL_COOP, 1024, 4, 0.f, 128));  // two workgroups or more
         for (float cp : {4.f, 8.f}) c.push_back(make_tuning(BS_KERNEL_GRID, 1024, 0, cp, 16));
         c.push_back(make_tuning(BS_KERNEL_GRID, 256, 0, 8.f, 16));
         return c;

@@ -119,7 +119,7 @@ def test_plan_describe(lib):
     several-picks cooperative scan with 128 picks per step on the most
     workgroups that fit (fewest candidates per thread); above 4,194,304 the
     grid kernel with 16 picks per round (asked for at 4,194,304: with a
-    leading scan of n / 1024 picks); small sizes the resident workgroup."""
+    leading scan of n / 1024 picks); up to 4,096 the resident workgroup."""
     lib.bs_autotune_clear()
     p = bs.plan_describe(4194304, 262144)
     assert (p.kernel, p.block, p.per_thread, p.groups, p.picks) == (bs.KERNEL_COOP, 1024, 16, 256, 128)
@@ -138,7 +138,9 @@ def test_plan_describe(lib):
     assert p.lead_picks == -1 and p.groups == 0
     p = bs.plan_describe(4194304, 2000, bs.tuning(kernel=3, picks=16))
     assert p.lead_picks == 2000  # capped at k
-    p = bs.plan_describe(10000, 100)
+    p = bs.plan_describe(10000, 100)  # from two workgroups on, the several-picks scan
+    assert (p.kernel, p.per_thread, p.groups, p.picks) == (bs.KERNEL_COOP, 4, 3, 128)
+    p = bs.plan_describe(4096, 100)
     assert p.kernel == bs.KERNEL_WG and p.groups == 1
     # several picks per step need two workgroups at least
     with pytest.raises(Exception):

@@ -35,6 +35,8 @@ def test_sphere_box_full_order(hip):
     eo, er = oracle.greedy32(P, 16384, st)
     o, r = run(hip, P, 16384, start=st)
     assert_parity(o, r, eo, er, "sphere_and_box")
+    o, r = run(hip, P, 16384, start=st, tune=hip.tuning(kernel=hip.KERNEL_WG))
+    assert_parity(o, r, eo, er, "sphere_and_box one workgroup")
     # radius within 1e-6 relative of the binary64 recomputation along the order
     r64 = oracle.along_order64(P, o)
     assert np.all(np.abs(r[1:].astype(np.float64) - r64[1:]) <= 1e-6 * r64[1:])
