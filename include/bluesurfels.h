@@ -96,7 +96,7 @@ typedef struct {
     int32_t picks;         /* grid kernel: most picks per round, 0 = auto, 1 = one pick
                               per round, 2..32 = several exact picks per round (same
                               result; see bs_order_ex).  Cooperative full scan
-                              (BS_KERNEL_COOP; 1024-thread workgroups with 4, 8, 12 or
+                              (BS_KERNEL_COOP; 1024-thread workgroups with 1, 2, 4, 8, 12 or
                               16 per thread, or 512-thread with 24 or 32; 2..256
                               workgroups): 2..128 = several exact picks per step over
                               the candidates in Morton order, every workgroup a bucket

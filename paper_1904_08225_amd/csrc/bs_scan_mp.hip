@@ -749,6 +749,7 @@ struct MpEntry {
 };
 
 const MpEntry kMpTable[] = {
+    {1024, 1, scan_mp_kernel<1024, 1>},   {1024, 2, scan_mp_kernel<1024, 2>},
     {1024, 4, scan_mp_kernel<1024, 4>},   {1024, 8, scan_mp_kernel<1024, 8>},
     {1024, 12, scan_mp_kernel<1024, 12>}, {1024, 16, scan_mp_kernel<1024, 16>},
     {512, 24, scan_mp_kernel<512, 24>},   {512, 32, scan_mp_kernel<512, 32>},

@@ -48,7 +48,8 @@ std::vector<bs_tuning> single_candidates(int64_t n) {
     std::vector<bs_tuning> c;
     if (n <= 16384) {
         c.push_back(make_tuning(BS_KERNEL_WG, 0, 0, 0.f, 0));
-        if (n > 4 * 1024) c.push_back(make_tuning(BS_KERNEL_COOP, 1024, 4, 0.f, 128));  // two workgroups or more
+        if (n > 4096)
+            for (int pt : {1, 2, 4}) c.push_back(make_tuning(BS_KERNEL_COOP, 1024, pt, 0.f, 128));
         for (float cp : {4.f, 8.f}) c.push_back(make_tuning(BS_KERNEL_GRID, 1024, 0, cp, 16));
         c.push_back(make_tuning(BS_KERNEL_GRID, 256, 0, 8.f, 16));
         return c;
@@ -58,7 +59,7 @@ std::vector<bs_tuning> single_candidates(int64_t n) {
         // workgroups offer more entries per step), the most picks per step
         // (a lower cap only binds late in the ordering, beyond the prefixes
         // timed here, and is never faster there)
-        for (int pt : {4, 8, 12, 16}) c.push_back(make_tuning(BS_KERNEL_COOP, 1024, pt, 0.f, 128));
+        for (int pt : {1, 2, 4, 8, 12, 16}) c.push_back(make_tuning(BS_KERNEL_COOP, 1024, pt, 0.f, 128));
     }
     for (int block : {512, 1024})
         for (float cp : {8.f, 16.f}) c.push_back(make_tuning(BS_KERNEL_GRID, block, 0, cp, 16));

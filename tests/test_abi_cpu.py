@@ -126,7 +126,9 @@ def test_plan_describe(lib):
     p = bs.plan_describe(2097152, 1000)
     assert (p.kernel, p.per_thread, p.groups, p.picks) == (bs.KERNEL_COOP, 8, 256, 128)
     p = bs.plan_describe(100000, 1000)
-    assert (p.kernel, p.per_thread, p.groups) == (bs.KERNEL_COOP, 4, 25)
+    assert (p.kernel, p.per_thread, p.groups) == (bs.KERNEL_COOP, 1, 98)
+    p = bs.plan_describe(500000, 1000)
+    assert (p.kernel, p.per_thread, p.groups) == (bs.KERNEL_COOP, 2, 245)
     p = bs.plan_describe(100000, 1000, bs.tuning(kernel=2, per_thread=16, picks=8))
     assert (p.kernel, p.per_thread, p.groups, p.picks) == (bs.KERNEL_COOP, 16, 7, 8)
     p = bs.plan_describe(8000000, 262144)
@@ -139,12 +141,12 @@ def test_plan_describe(lib):
     p = bs.plan_describe(4194304, 2000, bs.tuning(kernel=3, picks=16))
     assert p.lead_picks == 2000  # capped at k
     p = bs.plan_describe(10000, 100)  # from two workgroups on, the several-picks scan
-    assert (p.kernel, p.per_thread, p.groups, p.picks) == (bs.KERNEL_COOP, 4, 3, 128)
+    assert (p.kernel, p.per_thread, p.groups, p.picks) == (bs.KERNEL_COOP, 1, 10, 128)
     p = bs.plan_describe(4096, 100)
     assert p.kernel == bs.KERNEL_WG and p.groups == 1
     # several picks per step need two workgroups at least
     with pytest.raises(Exception):
-        bs.plan_describe(2000, 100, bs.tuning(kernel=2, picks=8))
+        bs.plan_describe(1000, 100, bs.tuning(kernel=2, picks=8))  # one workgroup even at 1 per thread
     out = bs.Tuning()
     assert lib.bs_plan_describe(10, 11, None, ctypes.byref(out)) == bs.BS_ERR_INVALID_ARG
     assert lib.bs_plan_describe(10, 5, None, None) == bs.BS_ERR_INVALID_ARG

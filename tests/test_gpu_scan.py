@@ -159,21 +159,23 @@ def test_cooperative_cad_part_full_size(hip):
 @pytest.mark.parametrize("picks", [2, 8, 32, 64, 128])
 def test_cooperative_several_picks(hip, picks):
     """Several exact picks per step of the cooperative full scan (every
-    workgroup a bucket with two entries and a third-best bound): the same
-    order and radii, across shapes and point sets with ties and duplicates."""
+    workgroup a bucket with three entries and a bound on the rest): the
+    same order and radii, across shapes and point sets with ties and
+    duplicates."""
     n = 100000
     P = synth.cad_part(n, seed=71).points.numpy()
     eo, er = oracle.greedy32_grid(P, 20000, 23)
-    for blk, pt in ((1024, 4), (1024, 8), (1024, 16), (512, 24), (512, 32)):
+    for blk, pt in ((1024, 1), (1024, 2), (1024, 4), (1024, 8), (1024, 16), (512, 24), (512, 32)):
         o, r = run(hip, P, 20000, start=23,
                    tune=hip.tuning(kernel=hip.KERNEL_COOP, block=blk, per_thread=pt, picks=picks))
         assert_parity(o, r, eo, er, "cad n=%d block=%d per_thread=%d picks=%d" % (n, blk, pt, picks))
     for name in ("duplicates", "lattice", "huge", "mixed_scale", "collinear"):
         Q = cases.ADVERSARIAL[name](40000, 77)
         eo, er = oracle.greedy32_grid(Q, 40000 // 3, 5)
-        o, r = run(hip, Q, 40000 // 3, start=5,
-                   tune=hip.tuning(kernel=hip.KERNEL_COOP, block=1024, per_thread=4, picks=picks))
-        assert_parity(o, r, eo, er, "%s picks=%d" % (name, picks))
+        for pt in (1, 4):
+            o, r = run(hip, Q, 40000 // 3, start=5,
+                       tune=hip.tuning(kernel=hip.KERNEL_COOP, block=1024, per_thread=pt, picks=picks))
+            assert_parity(o, r, eo, er, "%s per_thread=%d picks=%d" % (name, pt, picks))
 
 
 def test_cooperative_several_picks_full_size(hip):
