@@ -606,9 +606,19 @@ __global__ void __launch_bounds__(BLOCK)
                 topr = k1[c] > top ? rr[c] : topr;
                 top = k1[c] > top ? k1[c] : top;
             }
-            const uint64_t tk = wave_max_u64(top);
+            // the top key: its value bits by a 32-bit maximum, its index
+            // bits only when values tie (keys are unique)
+            const uint32_t tv = wave_max_u32(uint32_t(top >> 32));
+            const bool atv = uint32_t(top >> 32) == tv;
+            const uint64_t tied = __ballot(atv);
+            int tl = __builtin_ctzll(tied);
+            if (__popcll(tied) > 1) {
+                const uint32_t tlo = wave_max_u32(atv ? uint32_t(top) : 0u);
+                tl = __builtin_ctzll(__ballot(atv && uint32_t(top) == tlo));
+            }
+            const uint64_t tk = (uint64_t(tv) << 32) | uint32_t(__builtin_amdgcn_readlane(int(uint32_t(top)), tl));
             // R of the top workgroup, then tau up to its fixed point
-            uint32_t tau = uint32_t(__builtin_amdgcn_readlane(int(topr), __builtin_ctzll(__ballot(top == tk))));
+            uint32_t tau = uint32_t(__builtin_amdgcn_readlane(int(topr), tl));
             for (int it = 0; it <= kMpMaxGroups; ++it) {  // at most two passes in exact arithmetic
                 uint32_t mr = 0;
 #pragma unroll
