@@ -55,6 +55,8 @@ def _bind(path: str):
     lib.oracle_along_order64.restype = ctypes.c_int
     lib.oracle_greedy32_grid.argtypes = [vp, i64, i64, i64, vp, vp, ctypes.c_double, vp]
     lib.oracle_greedy32_grid.restype = ctypes.c_int
+    lib.oracle_greedy32_grid_h.argtypes = [vp, i64, i64, i64, vp, vp, ctypes.c_double, ctypes.c_double, vp]
+    lib.oracle_greedy32_grid_h.restype = ctypes.c_int
     lib.oracle_oct_encode_n.argtypes = [vp, i64, vp]
     lib.oracle_oct_encode_n.restype = ctypes.c_int
     lib.oracle_emit_surfels.argtypes = [vp, vp, vp, i64, vp, i64, vp]
@@ -128,15 +130,18 @@ def greedy32(points, k: int, start: int, stats: bool = False, lib=None):
     return (order, radius, st) if stats else (order, radius)
 
 
-def greedy32_grid(points, k: int, start: int, target: float = 12.0, stats: bool = False, lib=None):
-    """Exact grid-accelerated binary32 greedy; equal to :func:`greedy32`."""
+def greedy32_grid(points, k: int, start: int, target: float = 12.0, stats: bool = False, lib=None,
+                  cell_side: float = 0.0):
+    """Exact grid-accelerated binary32 greedy; equal to :func:`greedy32`.
+    ``cell_side`` > 0 fixes the grid's cell side (else it follows ``target``
+    candidates per cell)."""
     p = _points32(points)
     n = p.shape[0]
     order = np.empty(max(k, 0), dtype=np.int32)
     radius = np.empty(max(k, 0), dtype=np.float32)
     ball = np.zeros(max(k - 1, 0), dtype=np.int64) if stats else None
-    rc = (lib or _load()).oracle_greedy32_grid(_ptr(p), n, k, start, _ptr(order), _ptr(radius),
-                                      float(target), _ptr(ball))
+    rc = (lib or _load()).oracle_greedy32_grid_h(_ptr(p), n, k, start, _ptr(order), _ptr(radius),
+                                        float(target), float(cell_side), _ptr(ball))
     _check(rc)
     return (order, radius, {"n_ball": ball}) if stats else (order, radius)
 

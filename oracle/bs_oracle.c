@@ -43,6 +43,8 @@
  *                            bit-exact to oracle_greedy32 by the test suite
  *                            and exists only so that large inputs can be
  *                            checked in seconds.
+ *   oracle_greedy32_grid_h   the same with the cell side given (for pins that
+ *                            place points on cell boundaries).
  *   oracle_oct_encode        octahedral code of a normal (2 x snorm16).
  *   oracle_emit_surfels      the ordered 20-byte surfel records of a prefix.
  *   oracle_median_nn         r_m: median nearest-neighbour distance within
@@ -294,11 +296,22 @@ static uint64_t sel_key(float d2, int64_t i)
  * cell is skipped when the binary64 distance from the pick to the cell's
  * exact member box, shrunk by a relative margin of 1e-5 (binary32 rounding
  * of d2 is within 5 * 2^-24 relative, plus underflow of order 1e-38), is at
- * least m(c).  `target` is the desired mean number of points per cell.
+ * least m(c).  `target` is the desired mean number of points per cell;
+ * `cell_side` > 0 fixes the cell side instead (at most 1e6 cells per axis)
+ * and always walks the cells within `span` (without it, a span box holding
+ * more cells than are occupied makes every cell a box-test candidate).
+ *
+ * Which cells are looked at: those within `span` cells of the pick's cell
+ * along every axis.  A cell further away lies, along one axis, more than
+ * (span - 1e-9) * h from the pick (cell indices are floors of binary64
+ * quotients below 1e6, off by far less than 1e-9 of a cell).  span is
+ * chosen so that distance exceeds rr = sqrt((m(c) + 1e-37) / (1 - 1e-5)),
+ * the same margin as the box test: such a point's binary32 d2 cannot fall
+ * below m(c), so skipping its cell changes no min-distance and no count.
  */
-int oracle_greedy32_grid(const float* P, int64_t n, int64_t k, int64_t start,
-                         int32_t* order, float* radius, double target,
-                         int64_t* n_ball)
+int oracle_greedy32_grid_h(const float* P, int64_t n, int64_t k, int64_t start,
+                           int32_t* order, float* radius, double target,
+                           double cell_side, int64_t* n_ball)
 {
     if (k == 0) return ORACLE_OK;
     if (!P || !order || n < 1 || k < 0 || k > n || start < 0 || start >= n)
@@ -325,7 +338,8 @@ int oracle_greedy32_grid(const float* P, int64_t n, int64_t k, int64_t start,
 
     /* pick the cell side h: start from a volume-filling guess and refine by
      * the observed occupancy (surfaces occupy far fewer cells) */
-    double h = ext / cbrt((double)n / target);
+    double h = cell_side > 0.0 ? cell_side : ext / cbrt((double)n / target);
+    if (cell_side > 0.0 && ext / h > 1.0e6) { free(rec); return ORACLE_BAD_ARG; }
     int64_t ncell = 0;
     for (int iter = 0; iter < 3; ++iter) {
         if (ext / h > 1.0e6) h = ext / 1.0e6;
@@ -340,7 +354,7 @@ int oracle_greedy32_grid(const float* P, int64_t n, int64_t k, int64_t start,
         for (int64_t i = 0; i < n; ++i)
             if (i == 0 || rec[i].key != rec[i - 1].key) ++ncell;
         double per = (double)n / (double)ncell;
-        if (iter == 2 || (per > 0.5 * target && per < 2.0 * target)) break;
+        if (cell_side > 0.0 || iter == 2 || (per > 0.5 * target && per < 2.0 * target)) break;
         h *= sqrt(target / per);
     }
 
@@ -406,11 +420,11 @@ int oracle_greedy32_grid(const float* P, int64_t n, int64_t k, int64_t start,
         double pcd[3] = {pc[0], pc[1], pc[2]};
         /* gather the cells that may contain an affected candidate */
         int64_t nvisit = 0;
-        double rr = sqrt((double)mc);
-        int64_t span = isinf(rr) ? INT64_MAX : (int64_t)floor(rr / h) + 1;
+        double rr = sqrt(((double)mc + 1e-37) / (1.0 - 1e-5));
+        int64_t span = isinf(rr) ? INT64_MAX : (int64_t)floor(rr / h) + 2;
         double boxes = (double)(2 * (double)span + 1);
         boxes = boxes * boxes * boxes;
-        if (isinf(rr) || boxes >= (double)ncell) {
+        if (isinf(rr) || (cell_side <= 0.0 && boxes >= (double)ncell)) {
             for (int64_t q = 0; q < ncell; ++q) visit[nvisit++] = q;
         } else {
             int64_t g0 = (int64_t)floor((pcd[0] - lo[0]) / h);
@@ -472,6 +486,13 @@ int oracle_greedy32_grid(const float* P, int64_t n, int64_t k, int64_t start,
     free(cells); free(cell_of); free(members); free(htab); free(hkey);
     free(tree); free(m); free(sel); free(visit);
     return ORACLE_OK;
+}
+
+int oracle_greedy32_grid(const float* P, int64_t n, int64_t k, int64_t start,
+                         int32_t* order, float* radius, double target,
+                         int64_t* n_ball)
+{
+    return oracle_greedy32_grid_h(P, n, k, start, order, radius, target, 0.0, n_ball);
 }
 
 /* -------------------------------------------- ordered surfel buffer (a6) */

@@ -198,6 +198,133 @@ def check_fp64_bound(P, order, radius, lib=None, rel=1e-6):
         assert r64[t] >= (1 - rel) * best, (t, r64[t], best)
 
 
+def brute_statistics_f32(P, order):
+    """Per-update counts of a greedy order, recomputed from scratch (numpy).
+
+    For the update with pick u (u = 0 .. k-2), c = order[u], the prefix
+    order[:u] and the live set (everything outside order[:u + 1]):
+      n_live  size of the live set;
+      n_ball  live candidates with d2(p, c) < m(c), where m(c) is c's binary32
+              squared distance to its nearest earlier pick (+inf for u = 0);
+      n_dec   live candidates with d2(p, c) < their own nearest-prefix d2
+              (+inf for u = 0): the min-distances this pick lowers.
+    Each distance comes from the full matrix with the association
+    ((dx*dx + dy*dy) + dz*dz), independently of the oracle's loop."""
+    P = np.asarray(P, dtype=np.float32)
+    n = P.shape[0]
+    k = len(order)
+    dx = P[:, None, 0] - P[None, :, 0]
+    dy = P[:, None, 1] - P[None, :, 1]
+    dz = P[:, None, 2] - P[None, :, 2]
+    with np.errstate(over="ignore"):  # overflowing coordinates: +inf is the binary32 result
+        D = (dx * dx + dy * dy) + dz * dz
+    out = {key: np.zeros(max(k - 1, 0), dtype=np.int64) for key in ("n_live", "n_ball", "n_dec")}
+    inf = np.float32(np.inf)
+    for u in range(k - 1):
+        c = int(order[u])
+        prefix = np.asarray(order[:u], dtype=np.int64)
+        live = np.ones(n, dtype=bool)
+        live[np.asarray(order[:u + 1], dtype=np.int64)] = False
+        m_before = D[:, prefix].min(axis=1) if u > 0 else np.full(n, inf, dtype=np.float32)
+        mc = m_before[c]
+        d = D[:, c]
+        out["n_live"][u] = int(live.sum())
+        out["n_ball"][u] = int((live & (d < mc)).sum())
+        out["n_dec"][u] = int((live & (d < m_before)).sum())
+    return out
+
+
+def check_statistics(lib=None, sizes=(2, 9, 27, 64)):
+    """The oracle's n_live / n_ball / n_dec (the ball populations that set
+    the pruned method's algorithmic bytes) equal a from-scratch count, on
+    adversarial sets including lattices where d2 == m(c) exactly; the grid
+    oracle's n_ball equals it too."""
+    for name, gen in cases.ADVERSARIAL.items():
+        for n in sizes:
+            P = gen(n, 300 + n)
+            for s in sorted({0, n // 2, n - 1}):
+                o, r, st = oracle.greedy32(P, n, s, stats=True, lib=lib)
+                bf = brute_statistics_f32(P, o)
+                for key in ("n_live", "n_ball", "n_dec"):
+                    assert np.array_equal(st[key], bf[key]), (name, n, s, key, st[key], bf[key])
+                _, _, sg = oracle.greedy32_grid(P, n, s, target=2.0, stats=True, lib=lib)
+                assert np.array_equal(sg["n_ball"], bf["n_ball"]), (name, n, s, "grid n_ball")
+
+
+def span_boundary_case(seed=0, S=16):
+    """Four points and a cell side h that put a candidate q one cell beyond
+    span = floor(sqrt(m(c)) / h) + 1 of the pick c (along x) while its binary32
+    d2 to c is below m(c): the subtraction x_q - x_c rounds down to the float
+    just under sqrt(m(c)) although the exact distance is just above.  A grid
+    walk whose span carries no rounding margin misses q in the ball count.
+
+    Points: A (the start), c (the farthest from A, so the first pick), q, and
+    D0, which fixes the grid's lower x bound so that c sits just under the
+    top of its cell.  Returns (P, h) or raises if the float conditions were
+    not met within the trials."""
+    rng = np.random.default_rng(seed)
+    f32 = np.float32
+    for _ in range(20000):
+        a = f32(0.78 + 0.04 * rng.random())
+        yA = f32(0.58 + 0.04 * rng.random())
+        # c = (-eps, 0, 0) with eps set below; m(c) = d2(A, c) is nearly that of (a, yA)
+        dxa = np.float32(a)
+        mc = np.float32(np.float32(dxa * dxa) + np.float32(yA * yA))
+        rr = float(np.sqrt(np.float64(mc)))
+        f0 = np.float32(rr)
+        if float(f0) > rr:
+            f0 = np.nextafter(f0, f32(0))
+        ulp = float(np.nextafter(f0, f32(np.inf))) - float(f0)
+        gap = rr - float(f0)
+        if not (0.2 * ulp < gap < 0.4 * ulp):
+            continue
+        if not (np.float32(f0 * f0) < mc):
+            continue
+        lo = np.float32(-(rr / S + gap))
+        while -float(lo) <= rr / S + gap:
+            lo = np.nextafter(lo, f32(-np.inf))
+        eta = -float(lo) - rr / S - gap
+        eps = np.float32(gap + eta * S / (S + 1) + 0.25 * (0.5 * ulp - gap))
+        if not (gap + eta * S / (S + 1) < float(eps) < 0.5 * ulp):
+            continue
+        xc, xq = np.float32(-eps), f0
+        if np.float32(xq - xc) != f0:
+            continue
+        A = np.array([a - eps, yA, 0], dtype=f32)  # so that A.x - c.x rounds like a
+        c = np.array([xc, 0, 0], dtype=f32)
+        q = np.array([xq, 0, 0], dtype=f32)
+        D0 = np.array([lo, yA, 0], dtype=f32)
+        P = np.stack([A, c, q, D0]).astype(f32)
+        D = float(xc) - float(lo)
+        hi_h = (float(xq) - float(lo)) / (S + 1)
+        lo_h = max(D, rr / S)
+        if not lo_h < hi_h:
+            continue
+        h = 0.5 * (lo_h + hi_h)
+        # the construction's claims, checked here in binary64 / binary32
+        m_c = np.float32(np.float32(np.float32(P[0, 0] - P[1, 0]) ** 2) + np.float32(P[0, 1] ** 2))
+        rr = float(np.sqrt(np.float64(m_c)))
+        if int(np.floor(rr / h)) + 1 != S:
+            continue
+        if not (np.float32(np.float32(xq - xc) ** 2) < m_c and float(xq) - float(xc) > rr):
+            continue
+        if int(np.floor((float(xq) - float(lo)) / h)) - int(np.floor((float(xc) - float(lo)) / h)) != S + 1:
+            continue
+        return P, h
+    raise AssertionError("no span boundary case found")
+
+
+def check_span_boundary(lib=None):
+    """Grid oracle with the cell side of span_boundary_case: its ball counts
+    (and order) equal the plain oracle's."""
+    P, h = span_boundary_case()
+    o1, r1, st = oracle.greedy32(P, 4, 0, stats=True, lib=lib)
+    assert o1[1] == 1 and st["n_ball"][1] == 2, (o1, st)
+    o2, r2, sg = oracle.greedy32_grid(P, 4, 0, stats=True, cell_side=h, lib=lib)
+    assert np.array_equal(o1, o2) and same_f32(r1, r2)
+    assert np.array_equal(sg["n_ball"], st["n_ball"]), ("span boundary", sg["n_ball"], st["n_ball"])
+
+
 def check_grid_equals_plain(P, k, start, lib=None, target=12.0):
     o1, r1 = oracle.greedy32(P, k, start, lib=lib)
     o2, r2 = oracle.greedy32_grid(P, k, start, target=target, lib=lib)
@@ -288,6 +415,8 @@ def pin_battery(lib=None):
     check_prefix_estimate(lib)
     check_bruteforce(lib, sizes=(2, 5, 17, 40))
     check_two_approx(lib, trials=4)
+    check_statistics(lib, sizes=(9, 27))
+    check_span_boundary(lib)
     P = cases.random_cloud(300, 9)
     o, r = oracle.greedy32(P, 300, 4, lib=lib)
     check_invariants(P, o, r, steps=(1, 2, 7, 50, 299))

@@ -25,6 +25,18 @@ MUTANTS = {
                      "        if (radius) radius[t] = mc;\n    }\n    free(m);"),
     "reselect_picked": ("        for (int64_t i = 0; i < n; ++i) {\n            if (sel[i]) continue;\n            if (best < 0 || m[i] > m[best]) best = i;\n        }\n        c = best;\n        mc",
                         "        for (int64_t i = 0; i < n; ++i) {\n            if (best < 0 || m[i] > m[best]) best = i;\n        }\n        c = best;\n        mc"),
+    "ball_counts_ties": ("                if (d < mc) ++ball;\n                if (d < m[i]) { m[i] = d; ++dec; }",
+                         "                if (d <= mc) ++ball;\n                if (d < m[i]) { m[i] = d; ++dec; }"),
+    "ball_against_own_m": ("                if (d < mc) ++ball;\n                if (d < m[i]) { m[i] = d; ++dec; }",
+                           "                if (d < m[i]) ++ball;\n                if (d < m[i]) { m[i] = d; ++dec; }"),
+    "dec_counts_ties": ("                if (d < m[i]) { m[i] = d; ++dec; }",
+                        "                if (d <= m[i]) { m[i] = d; ++dec; }"),
+    "grid_ball_ties": ("                if (d < mc) ++ball;\n                if (d < m[i]) m[i] = d;",
+                       "                if (d <= mc) ++ball;\n                if (d < m[i]) m[i] = d;"),
+    "grid_span_no_margin": ("        double rr = sqrt(((double)mc + 1e-37) / (1.0 - 1e-5));\n"
+                            "        int64_t span = isinf(rr) ? INT64_MAX : (int64_t)floor(rr / h) + 2;",
+                            "        double rr = sqrt((double)mc);\n"
+                            "        int64_t span = isinf(rr) ? INT64_MAX : (int64_t)floor(rr / h) + 1;"),
     "grid_prunes_too_much": ("if (bd * (1.0 - 1e-5) - 1e-37 >= (double)mc) continue;",
                              "if (bd * 4.0 >= (double)mc) continue;"),
     "splitmix_constant": ("z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;",

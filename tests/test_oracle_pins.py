@@ -113,6 +113,14 @@ def test_edge_cases():
     assert (o == -1).all() and np.isnan(r).all()
 
 
+def test_statistics_brute_force():
+    pins.check_statistics()
+
+
+def test_grid_span_boundary():
+    pins.check_span_boundary()
+
+
 def test_statistics_consistent():
     P = cases.random_cloud(600, 3)
     o, r, st = oracle.greedy32(P, 600, 2, stats=True)
