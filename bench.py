@@ -206,6 +206,61 @@ def bench_emit(bs, torch, surf, pts, order):
             "note": "one launch of 1,024 workgroups: at this size launch latency, not HBM, bounds it"}
 
 
+def bench_config1(bs, torch, np, cpu=True):
+    """The small single-object workload: unit sphere + 1 x 0.5 x 0.25 box,
+    16,384 candidates (seed 1), ordered completely (k = n) by the automatic
+    plan; ms per ordering (HIP events around the whole call, inputs
+    resident), per-step p50 / p99 from device timestamps, and the plain CPU
+    oracle's time on the same points."""
+    import synth
+    n = 16384
+    s = synth.sphere_and_box(n=n, seed=1)
+    dev = torch.device("cuda:0")
+    pts = s.points.to(dev).contiguous()
+    start = bs.start_index(1, n)
+    plan = bs.plan_describe(n, n)
+    ws = torch.empty(max(bs.workspace_size(n, n), 1), dtype=torch.uint8, device=dev)
+    oo = torch.empty(n, dtype=torch.int32, device=dev)
+    rr = torch.empty(n, dtype=torch.float32, device=dev)
+    stream = torch.cuda.current_stream()
+
+    def one():
+        bs.order_profile(pts, n, start=start, stream=stream, ticks=False, workspace=ws, out_order=oo, out_radius=rr)
+
+    for _ in range(3):
+        one()
+    torch.cuda.synchronize()
+    reps = 20
+    b, e = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    b.record(stream)
+    for _ in range(reps):
+        one()
+    e.record(stream)
+    torch.cuda.synchronize()
+    wall_ms = (time.perf_counter() - t0) * 1e3 / reps
+    ev_ms = b.elapsed_time(e) / reps
+    _, lat, o = ordering_kernel_seconds(bs, pts, n, start, None)
+    rec = {"workload": "sphere_and_box n=16,384 k=n=16,384 (seed 1)", "n": n, "k": n,
+           "plan": {"kernel": int(plan.kernel), "block": int(plan.block), "per_thread": int(plan.per_thread),
+                    "groups": int(plan.groups), "picks": int(plan.picks)},
+           "ms_per_ordering": ev_ms, "wall_ms_per_ordering": wall_ms,
+           "ordered_surfels_per_s": n / (ev_ms / 1e3),
+           "per_step_p50_us": lat["p50_us"], "per_step_p99_us": lat["p99_us"], "steps": lat["rounds"],
+           "picks_per_step": lat["picks_per_round"],
+           "time_source": "HIP events around %d back-to-back orderings (validation, Morton sort, ordering) on "
+                          "resident inputs; steps from the device wall clock at each pick's emission" % reps}
+    if cpu:
+        import oracle
+        t0 = time.perf_counter()
+        eo, er = oracle.greedy32(s.points.numpy(), n, start)
+        cs = time.perf_counter() - t0
+        rec["matches_oracle"] = bool(np.array_equal(o.cpu().numpy(), eo))
+        rec["cpu_oracle"] = {"kind": "oracle", "cores": 1, "seconds": cs, "ordered_surfels_per_s": n / cs,
+                             "sample": "plain binary32 oracle (oracle/bs_oracle.c, 1 thread), the whole workload"}
+    return rec
+
+
 def bench_full_scan(bs, torch, pts, k):
     tune = bs.tuning(kernel=bs.KERNEL_COOP, block=1024, per_thread=16)
     n = int(pts.shape[0])
@@ -355,13 +410,13 @@ def bench_served(bs, torch, np):
     out_r = torch.empty(total_k, dtype=torch.float32, device=dev)
     views = [pts[offs[p]:offs[p + 1]] for p in range(pool_m)]
     # warm-up server (loads kernels)
-    warm = bs.Server(hbm_budget_bytes=80 << 30)
+    warm = bs.Server(hbm_budget_bytes=80_000_000_000)
     for i in range(8):
         p = int(picks[i])
         warm.submit(views[p], min(ks[i], 1000), int(seeds[i]), out_o[:1000], out_r[:1000])
     warm.drain()
     warm.close()
-    srv = bs.Server(hbm_budget_bytes=80 << 30, max_jobs_per_batch=256, poll_us=20)
+    srv = bs.Server(hbm_budget_bytes=80_000_000_000, max_jobs_per_batch=256, poll_us=20)
     off = 0
     t0 = time.perf_counter()
     for i in range(nreq):
@@ -381,7 +436,7 @@ def bench_served(bs, torch, np):
                                                               st["surfels_per_s"]))
     # capacity: the same requests all queued at once (the offered rate above
     # caps the served rate, so this is what compares with the plain loop)
-    sat = bs.Server(hbm_budget_bytes=80 << 30, max_jobs_per_batch=256, poll_us=20)
+    sat = bs.Server(hbm_budget_bytes=80_000_000_000, max_jobs_per_batch=256, poll_us=20)
     off = 0
     for i in range(nreq):
         p = int(picks[i])
@@ -446,7 +501,9 @@ def cpu_oracle_objects(pts, offs, ks, seeds, order_idx, sum_k_total, gpu_seconds
         sample.append(j)
         sk += ks[j]
     host = [pts[offs[j]:offs[j + 1]].cpu().numpy() for j in sample]
-    cores = min(len(os.sched_getaffinity(0)), 16)
+    # one GPU's share of the host: 16 threads at most, whatever the machine shows
+    visible = len(os.sched_getaffinity(0))
+    cores = min(visible, 16)
 
     def one(i):
         j = sample[i]
@@ -461,7 +518,8 @@ def cpu_oracle_objects(pts, offs, ks, seeds, order_idx, sum_k_total, gpu_seconds
     par_rate = sk / wall
     one_rate = sk / sum(per)
     log("cpu oracle: %d objects, %d picks, %.1f s on %d threads" % (len(sample), sk, wall, cores))
-    return {"kind": "oracle", "cores": cores, "object_parallel_ordered_surfels_per_s": par_rate,
+    return {"kind": "oracle", "cores": cores, "host_cpus_visible": visible,
+            "object_parallel_ordered_surfels_per_s": par_rate,
             "single_thread_ordered_surfels_per_s": one_rate,
             "estimated_seconds_object_parallel": sum_k_total / par_rate,
             "gpu_speedup_vs_object_parallel": (sum_k_total / par_rate) / gpu_seconds,
@@ -476,6 +534,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-full-scan", action="store_true")
+    ap.add_argument("--no-config1", action="store_true")
     ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--no-serve", action="store_true")
     ap.add_argument("--no-scene", action="store_true")
@@ -588,6 +647,11 @@ def main():
                                 "achieved_GBs": 16 * live / ls / 1e9,
                                 "frac_of_hbm_peak": 16 * live / ls / 1e9 / HBM_PEAK_GBS,
                                 "time_source": "device wall clock from pick 0 to the scan's last pick"}
+    if not args.no_config1:
+        rec["config1"] = bench_config1(bs, torch, np, cpu=not args.no_cpu_baseline)
+        log("config1: %.2f ms per ordering of sphere_and_box 16,384 (k = n), step p50 %.2f us p99 %.2f us"
+            % (rec["config1"]["ms_per_ordering"], rec["config1"]["per_step_p50_us"],
+               rec["config1"]["per_step_p99_us"]))
     rec["emit"] = bench_emit(bs, torch, surf, pts, out_o)
     log("emit: %.1f us for %d records (%.0f GB/s algorithmic); r_m in %.1f us"
         % (rec["emit"]["seconds"] * 1e6, k, rec["emit"]["achieved_GBs"], rec["emit"]["median_nn_seconds"] * 1e6))

@@ -36,7 +36,11 @@
  *     (null pointers, bad sizes, too small workspace) are returned
  *     synchronously and nothing is enqueued;
  *   - candidates with a non-finite coordinate are detected on the device;
- *     the outputs are then out_order[:] = -1 and out_radius[:] = NaN.
+ *     the outputs are then out_order[:] = -1 and out_radius[:] = NaN;
+ *   - the cooperative kernels wait for one another at every step with a
+ *     bounded wait (about a second); if one gives up, every workgroup
+ *     leaves and the outputs become out_order[:] = -2, out_radius[:] = NaN
+ *     (bs_order_status reports it as BS_ERR_TIMEOUT).
  *   - normals and colours are accepted for interface completeness (a surfel
  *     is position + normal + material, Sec. 3.1) but the selection ignores
  *     them, as the paper's sampling does (Sec. 5 limitations); they may be
@@ -114,7 +118,11 @@ typedef struct {
                               same result).  0 = auto (objects with k >= 65536 and more
                               than half the mean k per 256-thread workgroup slot), -1 =
                               none */
-    int32_t reserved[4];   /* must be zero */
+    int32_t spin_limit;    /* cooperative kernels: polls of a bounded wait for the other
+                              workgroups before giving up (0 = default, about a second).
+                              A small value forces the give-up path from the host (tests
+                              of the error contract); results are unchanged otherwise */
+    int32_t reserved[3];   /* must be zero */
 } bs_tuning;
 
 /* ------------------------------------------------------- single instance */
@@ -174,6 +182,16 @@ int bs_order_profile(const float* d_points, int64_t n, int64_t k, int64_t start_
                      void* event_begin, void* event_end,
                      void* d_workspace, size_t workspace_bytes, const bs_tuning* tuning,
                      void* stream);
+
+/*
+ * Status of the last ordering enqueued on `d_workspace` (bs_order_ex,
+ * bs_order_profile): waits for `stream` (a hipStream_t), then reads the
+ * workspace's device header.  Returns BS_OK; BS_ERR_INVALID_ARG if a
+ * coordinate was not finite (outputs -1 / NaN); BS_ERR_TIMEOUT if a
+ * cooperative kernel's bounded wait gave up (outputs -2 / NaN);
+ * BS_ERR_HIP if the stream reports an error.  Synchronous.
+ */
+int bs_order_status(const void* d_workspace, void* stream);
 
 /* Frequency of the device wall clock used by bs_order_profile (Hz); 0 on error. */
 double bs_wall_clock_hz(void);
@@ -387,6 +405,10 @@ typedef struct {
     uint64_t seed;           /* start = SplitMix64(seed) mod n */
     int32_t* d_out_order;    /* device int32[k] */
     float* d_out_radius;     /* device float[k] or NULL */
+    void* ready_event;       /* hipEvent_t recorded after the work that writes d_points, or
+                                NULL when the points are complete at submit: the server reads
+                                them on its own stream, after waiting for this event (which
+                                must stay valid until the job is done) */
 } bs_job;
 
 typedef struct {

@@ -48,12 +48,13 @@ class Tuning(ctypes.Structure):
                 ("per_thread", ctypes.c_int32), ("groups", ctypes.c_int32),
                 ("cell_points", ctypes.c_float), ("picks", ctypes.c_int32),
                 ("lead_picks", ctypes.c_int32), ("batch_wide", ctypes.c_int32),
-                ("reserved", ctypes.c_int32 * 4)]
+                ("spin_limit", ctypes.c_int32), ("reserved", ctypes.c_int32 * 3)]
 
 
 def tuning(kernel: int = 0, block: int = 0, per_thread: int = 0, groups: int = 0,
-           cell_points: float = 0.0, picks: int = 0, lead_picks: int = 0, batch_wide: int = 0) -> Tuning:
-    return Tuning(kernel, block, per_thread, groups, cell_points, picks, lead_picks, batch_wide)
+           cell_points: float = 0.0, picks: int = 0, lead_picks: int = 0, batch_wide: int = 0,
+           spin_limit: int = 0) -> Tuning:
+    return Tuning(kernel, block, per_thread, groups, cell_points, picks, lead_picks, batch_wide, spin_limit)
 
 
 def header_functions():
@@ -109,6 +110,8 @@ def load():
     lib.bs_order_ex.restype = i32
     lib.bs_order_profile.argtypes = [vp, i64, i64, i64, vp, vp, vp, vp, vp, vp, sz, tp, vp]
     lib.bs_order_profile.restype = i32
+    lib.bs_order_status.argtypes = [vp, vp]
+    lib.bs_order_status.restype = i32
     lib.bs_wall_clock_hz.argtypes = []
     lib.bs_wall_clock_hz.restype = ctypes.c_double
     lib.bs_batch_plan_create.argtypes = [vp, vp, vp, ctypes.c_int32, tp, ctypes.POINTER(vp)]
@@ -274,9 +277,24 @@ def order(points, k: Optional[int] = None, seed: int = 0, *, normals=None, color
     _check(rc)
     if check and k > 0:
         torch.cuda.current_stream().synchronize() if stream is None else stream.synchronize()
-        if int(out_order[0]) == -1:
-            raise ValueError("non-finite candidate coordinates")
+        _check_outputs(int(out_order[0]))
     return out_order, out_radius
+
+
+def _check_outputs(first: int):
+    # the device's error contract: -1 everywhere for non-finite input, -2 when
+    # a cooperative kernel's bounded wait gave up
+    if first == -1:
+        raise ValueError("non-finite candidate coordinates")
+    if first == -2:
+        raise BSError(BS_ERR_TIMEOUT, "a cooperative kernel's bounded wait gave up; the outputs are invalid")
+
+
+def order_status(workspace, stream=None) -> int:
+    """Status of the last ordering enqueued on ``workspace`` (``bs_order_status``):
+    BS_OK, BS_ERR_INVALID_ARG (non-finite input) or BS_ERR_TIMEOUT (a bounded
+    wait gave up).  Synchronises the stream."""
+    return int(load().bs_order_status(_ptr(workspace), _stream_handle(stream)))
 
 
 def emit_surfels(points, order, normals=None, colors=None, stream=None, out=None):
@@ -436,7 +454,8 @@ class ServerConfig(ctypes.Structure):
 
 class Job(ctypes.Structure):
     _fields_ = [("d_points", ctypes.c_void_p), ("n", ctypes.c_int64), ("k", ctypes.c_int64),
-                ("seed", ctypes.c_uint64), ("d_out_order", ctypes.c_void_p), ("d_out_radius", ctypes.c_void_p)]
+                ("seed", ctypes.c_uint64), ("d_out_order", ctypes.c_void_p), ("d_out_radius", ctypes.c_void_p),
+                ("ready_event", ctypes.c_void_p)]
 
 
 class ServingStats(ctypes.Structure):
@@ -468,13 +487,22 @@ class Server:
         _check(lib.bs_server_create(ctypes.byref(cfg), ctypes.byref(self._srv)))
         self._keep = {}
 
-    def submit(self, points, k: int, seed: int, out_order, out_radius=None) -> int:
+    def submit(self, points, k: int, seed: int, out_order, out_radius=None, ready=True) -> int:
+        """Queue a job.  With ``ready`` (default) an event recorded on the
+        current stream orders the server's read of ``points`` after the work
+        already queued there (e.g. the kernel that generated them)."""
+        import torch
         n = int(points.shape[0])
+        ev = None
+        if ready and n:
+            ev = torch.cuda.Event()
+            ev.record(torch.cuda.current_stream(points.device))
         job = Job(ctypes.c_void_p(points.data_ptr()) if n else None, n, int(k), seed & (2**64 - 1),
-                  _ptr(out_order) if k else None, _ptr(out_radius) if (out_radius is not None and k) else None)
+                  _ptr(out_order) if k else None, _ptr(out_radius) if (out_radius is not None and k) else None,
+                  ctypes.c_void_p(int(ev.cuda_event)) if ev is not None else None)
         t = ctypes.c_uint64()
         _check(self._lib.bs_server_submit(self._srv, ctypes.byref(job), ctypes.byref(t)))
-        self._keep[t.value] = (points, out_order, out_radius)
+        self._keep[t.value] = (points, out_order, out_radius, ev)
         return t.value
 
     def wait(self, ticket: int, timeout_us: int = -1):

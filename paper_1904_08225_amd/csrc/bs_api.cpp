@@ -43,7 +43,7 @@ bool tuning_clean(const bs_tuning* t) {
     for (int r : t->reserved)
         if (r != 0) return false;
     if (t->picks < 0 || t->picks > kMaxScanPicks) return false;
-    if (t->lead_picks < -1 || t->batch_wide < -1) return false;
+    if (t->lead_picks < -1 || t->batch_wide < -1 || t->spin_limit < 0) return false;
     return t->kernel >= BS_KERNEL_AUTO && t->kernel <= BS_KERNEL_GRID;
 }
 
@@ -308,7 +308,7 @@ size_t bs_workspace_size(int64_t n, int64_t k, const bs_tuning* tuning) {
 
 static int order_impl(const float* d_points, int64_t n, int64_t k, uint64_t seed,
                       int64_t start_index, int32_t* d_out_order, float* d_out_radius,
-                      uint64_t* d_ticks, const KernelEvents* ev, void* d_workspace,
+                      uint64_t* d_ticks, const LaunchOpts* ev, void* d_workspace,
                       size_t workspace_bytes, const bs_tuning* tuning, void* stream) {
     if (k < 0) return set_error(BS_ERR_INVALID_ARG, "k=%lld < 0", (long long)k);
     if (k == 0) return BS_OK;
@@ -331,6 +331,9 @@ static int order_impl(const float* d_points, int64_t n, int64_t k, uint64_t seed
         return set_error(BS_ERR_INVALID_ARG, "workspace not %zu-byte aligned", kAlign);
 
     hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+    LaunchOpts opts = ev ? *ev : LaunchOpts{};
+    opts.spin_limit = tuning ? uint32_t(tuning->spin_limit) : 0u;
+    ev = &opts;
     hipError_t e = hipSuccess;
     if (plan.kernel == BS_KERNEL_GRID) {
         e = launch_grid(d_points, int(n), int(k), int(start), d_out_order, d_out_radius, d_workspace,
@@ -367,11 +370,24 @@ int bs_order_profile(const float* d_points, int64_t n, int64_t k, int64_t start_
                      void* event_begin, void* event_end,
                      void* d_workspace, size_t workspace_bytes, const bs_tuning* tuning,
                      void* stream) {
-    KernelEvents ev;
+    LaunchOpts ev;
     ev.begin = reinterpret_cast<hipEvent_t>(event_begin);
     ev.end = reinterpret_cast<hipEvent_t>(event_end);
     return order_impl(d_points, n, k, 0, start_index, d_out_order, d_out_radius, d_step_ticks, &ev,
                       d_workspace, workspace_bytes, tuning, stream);
+}
+
+int bs_order_status(const void* d_workspace, void* stream) {
+    if (!d_workspace) return set_error(BS_ERR_INVALID_ARG, "null workspace");
+    hipError_t e = hipStreamSynchronize(reinterpret_cast<hipStream_t>(stream));
+    if (e != hipSuccess) return set_error(BS_ERR_HIP, "stream: %s", hipGetErrorString(e));
+    uint32_t w[2] = {0, 0};  // DevHeader: nonfinite, error (every plan's workspace starts with it)
+    e = hipMemcpy(w, d_workspace, sizeof(w), hipMemcpyDeviceToHost);
+    if (e != hipSuccess) return set_error(BS_ERR_HIP, "reading the workspace header: %s", hipGetErrorString(e));
+    if (w[0]) return set_error(BS_ERR_INVALID_ARG, "a candidate coordinate is not finite (outputs -1 / NaN)");
+    if (w[1])
+        return set_error(BS_ERR_TIMEOUT, "a cooperative kernel's bounded wait gave up (outputs -2 / NaN)");
+    return BS_OK;
 }
 
 double bs_wall_clock_hz(void) {

@@ -57,7 +57,7 @@ int grid_block_size(int64_t n);
 // Blocks of 64 cells one workgroup of `block` threads holds in LDS; `picks`
 // > 1 selects the several-picks-per-round kernel (at most `picks` per round).
 int grid_max_blocks(int block, int picks);
-struct KernelEvents;
+struct LaunchOpts;
 // Candidates in Morton order (validation, codes, radix sort, gather) in the
 // grid workspace, for the sorted cooperative scan.
 struct DevHeader;
@@ -77,7 +77,7 @@ hipError_t launch_sorted_points(const float* pts, int n, int start, void* ws, hi
 struct ScanShape;
 hipError_t launch_grid(const float* pts, int n, int k, int start, int32_t* order, float* radius,
                        void* ws, float target, int block, int picks, uint64_t* ticks,
-                       hipStream_t st, const KernelEvents* ev = nullptr, int lead = 0,
+                       hipStream_t st, const LaunchOpts* ev = nullptr, int lead = 0,
                        const ScanShape* lead_shape = nullptr);
 
 }  // namespace bs

@@ -379,7 +379,7 @@ int grid_max_blocks(int block, int picks) {
 
 hipError_t launch_grid(const float* pts, int n, int k, int start, int32_t* order, float* radius,
                        void* ws, float target, int block, int picks, uint64_t* ticks,
-                       hipStream_t st, const KernelEvents* ev, int lead, const ScanShape* lead_shape) {
+                       hipStream_t st, const LaunchOpts* ev, int lead, const ScanShape* lead_shape) {
     if (picks <= 1 || !lead_shape || lead < 2) lead = 0;
     if (lead > k) lead = k;
     const GridLayout g = grid_layout(n, block);
@@ -428,8 +428,10 @@ hipError_t launch_grid(const float* pts, int n, int k, int start, int32_t* order
         // picks 0 .. lead-1 by the cooperative full scan; its m values land in
         // the (now unused) unsorted Morton codes, its last pick in the header
         m_lead = reinterpret_cast<float*>(codes);
+        LaunchOpts lo;  // the events bracket the grid kernel; the wait limit applies here
+        lo.spin_limit = ev ? ev->spin_limit : 0;
         e = launch_scan(*lead_shape, pts, n, k, start, order, radius, hdr, base + g.lead_slots, ticks, st,
-                        nullptr, lead, m_lead, &gh->lead_id);
+                        &lo, lead, m_lead, &gh->lead_id);
         if (e != hipSuccess) return e;
     }
     hipLaunchKernelGGL(gather_kernel, dim3(nblk), dim3(tb), 0, st, pts, ids, flags, cellidx, n, start,
@@ -472,7 +474,8 @@ hipError_t launch_grid(const float* pts, int n, int k, int start, int32_t* order
     else
         hipLaunchKernelGGL((grid_single_kernel<256, 1024>), dim3(1), dim3(256), 0, st, o, hdr, gh);
     if ((e = hipGetLastError()) != hipSuccess) return e;
-    if (ev && ev->end) e = hipEventRecord(ev->end, st);
+    if (ev && ev->end && (e = hipEventRecord(ev->end, st)) != hipSuccess) return e;
+    if (lead >= 2) e = launch_finish(hdr, order, radius, k, st);
     return e;
 }
 

@@ -47,18 +47,30 @@ size_t scan_slot_bytes(int groups);
 // Kernel launchers (bs_scan.hip).  All return hipError_t of the launch.
 hipError_t launch_init_header(DevHeader* hdr, hipStream_t st);
 hipError_t launch_validate(const float* pts, int64_t n, DevHeader* hdr, hipStream_t st);
-// Optional events recorded on the launch stream right before and right after
-// the ordering kernel itself (not the validation / grid build before it).
-struct KernelEvents {
+// Per-call launch options of the ordering kernels: optional events recorded
+// on the launch stream right before and right after the ordering kernel
+// itself (not the validation / grid build before it), and the poll limit of
+// the cooperative kernels' bounded waits (0 = the default, about a second).
+struct LaunchOpts {
     hipEvent_t begin = nullptr;
     hipEvent_t end = nullptr;
+    uint32_t spin_limit = 0;
 };
+// Default poll limit of a bounded wait (each poll sleeps a few cycles).
+constexpr uint32_t kDefaultSpinLimit = 1u << 21;
+inline uint32_t spin_limit_of(const LaunchOpts* o) {
+    return (o && o->spin_limit) ? o->spin_limit : kDefaultSpinLimit;
+}
+// After an ordering kernel whose bounded wait may give up: if the header's
+// error word is set, every output becomes order = -2, radius = NaN (the
+// outputs were left partly written).
+hipError_t launch_finish(const DevHeader* hdr, int32_t* order, float* radius, int k, hipStream_t st);
 
 // Picks 0 .. k_stop-1 (k_stop < 0: all k); with m_out / handoff the scan
 // leaves its state for a following kernel (see scan_kernel).
 hipError_t launch_scan(const ScanShape& s, const float* pts, int n, int k, int start,
                        int32_t* order, float* radius, DevHeader* hdr, void* scratch,
-                       uint64_t* ticks, hipStream_t st, const KernelEvents* ev = nullptr,
+                       uint64_t* ticks, hipStream_t st, const LaunchOpts* ev = nullptr,
                        int k_stop = -1, float* m_out = nullptr, uint32_t* handoff = nullptr);
 
 // Several exact picks per step (bs_scan_mp.hip): the candidates in Morton
@@ -67,7 +79,7 @@ hipError_t launch_scan(const ScanShape& s, const float* pts, int n, int k, int s
 bool scan_several_supported(const ScanShape& s);
 hipError_t launch_scan_several(const ScanShape& s, const float* pts, int n, int k, int start, int32_t* order,
                                float* radius, void* ws, uint64_t* ticks, int picks, hipStream_t st,
-                               const KernelEvents* ev = nullptr);
+                               const LaunchOpts* ev = nullptr);
 
 // Batched plans (bs_batch.hip).
 struct BatchPlan;

@@ -28,7 +28,6 @@
 namespace bs {
 namespace {
 
-constexpr uint32_t kSpinLimit = 1u << 21;  // bounded wait (about a second), then give up
 // Exchange record: five 64-bit words, each (step tag << 32) | 32-bit payload:
 // key high, key low, x, y, z.  A reader accepts a record only when all five
 // carry the current step's tag, so words of different steps (relaxed stores
@@ -112,6 +111,17 @@ __global__ void init_header_kernel(DevHeader* hdr) {
     }
 }
 
+// A bounded wait gave up: the outputs are partly written, so all of them
+// become order = -2, radius = NaN.  Nothing to do otherwise.
+__global__ void finish_kernel(const DevHeader* __restrict__ hdr, int32_t* __restrict__ order,
+                              float* __restrict__ radius, int k) {
+    if (__hip_atomic_load(&hdr->error, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0) return;
+    for (int t = blockIdx.x * blockDim.x + threadIdx.x; t < k; t += gridDim.x * blockDim.x) {
+        order[t] = -2;
+        if (radius) radius[t] = __builtin_nanf("");
+    }
+}
+
 __global__ void clear_slots_kernel(uint64_t* slots, int nslots) {
     for (int i = threadIdx.x; i < nslots; i += blockDim.x) st_dev(slots + i, 0);
 }
@@ -181,7 +191,7 @@ __global__ void __launch_bounds__(BLOCK)
                 int32_t* __restrict__ order, float* __restrict__ radius,
                 DevHeader* __restrict__ hdr, uint64_t* __restrict__ slots,
                 uint64_t* __restrict__ ticks, int k_stop, float* __restrict__ m_out,
-                uint32_t* __restrict__ handoff) {
+                uint32_t* __restrict__ handoff, uint32_t spin_limit) {
     constexpr int NW = BLOCK / 64;
     __shared__ uint64_t s_key[2][NW];
     __shared__ float s_pos[2][NW][4];
@@ -305,7 +315,7 @@ __global__ void __launch_bounds__(BLOCK)
                              ((w0 | w1 | w2 | w3 | w4) >> 32) == uint64_t(uint32_t(t));
                     }
                     if (__ballot(!ok) == 0) break;
-                    if (++spins > kSpinLimit) {
+                    if (++spins > spin_limit) {
                         aborted = true;
                         break;
                     }
@@ -377,7 +387,7 @@ __global__ void __launch_bounds__(BLOCK)
 }
 
 using ScanFn = void (*)(const float*, int, int, int, int32_t*, float*, DevHeader*, uint64_t*,
-                       uint64_t*, int, float*, uint32_t*);
+                       uint64_t*, int, float*, uint32_t*, uint32_t);
 
 struct ScanEntry {
     int block, per_thread;
@@ -452,6 +462,14 @@ hipError_t launch_init_header(DevHeader* hdr, hipStream_t st) {
     return hipGetLastError();
 }
 
+hipError_t launch_finish(const DevHeader* hdr, int32_t* order, float* radius, int k, hipStream_t st) {
+    if (k <= 0) return hipSuccess;
+    int blocks = (k + 255) / 256;
+    if (blocks > 256) blocks = 256;
+    hipLaunchKernelGGL(finish_kernel, dim3(blocks), dim3(256), 0, st, hdr, order, radius, k);
+    return hipGetLastError();
+}
+
 hipError_t launch_validate(const float* pts, int64_t n, DevHeader* hdr, hipStream_t st) {
     if (n <= 0) return hipSuccess;
     int64_t blocks = (n + 255) / 256;
@@ -462,17 +480,18 @@ hipError_t launch_validate(const float* pts, int64_t n, DevHeader* hdr, hipStrea
 
 hipError_t launch_scan(const ScanShape& s, const float* pts, int n, int k, int start,
                        int32_t* order, float* radius, DevHeader* hdr, void* scratch,
-                       uint64_t* ticks, hipStream_t st, const KernelEvents* ev, int k_stop,
+                       uint64_t* ticks, hipStream_t st, const LaunchOpts* ev, int k_stop,
                        float* m_out, uint32_t* handoff) {
     const ScanEntry* e = find_entry(s.block, s.per_thread);
     if (!e) return hipErrorInvalidValue;
     if (k_stop < 0 || k_stop > k) k_stop = k;
     uint64_t* slots = reinterpret_cast<uint64_t*>(scratch);
+    uint32_t spin = spin_limit_of(ev);
     hipError_t err = hipSuccess;
     if (s.groups <= 1) {
         if (ev && ev->begin && (err = hipEventRecord(ev->begin, st)) != hipSuccess) return err;
         hipLaunchKernelGGL(e->single, dim3(1), dim3(s.block), 0, st, pts, n, k, start, order,
-                           radius, hdr, slots, ticks, k_stop, m_out, handoff);
+                           radius, hdr, slots, ticks, k_stop, m_out, handoff, spin);
     } else {
         // stale records from an earlier call must not carry matching tags
         hipLaunchKernelGGL(clear_slots_kernel, dim3(1), dim3(256), 0, st, slots, 2 * s.groups * kRecWords);
@@ -480,12 +499,16 @@ hipError_t launch_scan(const ScanShape& s, const float* pts, int n, int k, int s
         if (ev && ev->begin && (err = hipEventRecord(ev->begin, st)) != hipSuccess) return err;
         void* args[] = {(void*)&pts,   (void*)&n,     (void*)&k,      (void*)&start,
                         (void*)&order, (void*)&radius, (void*)&hdr,   (void*)&slots,
-                        (void*)&ticks, (void*)&k_stop, (void*)&m_out, (void*)&handoff};
+                        (void*)&ticks, (void*)&k_stop, (void*)&m_out, (void*)&handoff,
+                        (void*)&spin};
         err = hipLaunchCooperativeKernel(reinterpret_cast<const void*>(e->multi), dim3(s.groups),
                                          dim3(s.block), args, 0, st);
     }
     if (err == hipSuccess) err = hipGetLastError();
     if (err == hipSuccess && ev && ev->end) err = hipEventRecord(ev->end, st);
+    // a cooperative wait may give up (a following kernel of a handoff checks
+    // the error word itself and finishes the outputs)
+    if (err == hipSuccess && s.groups > 1 && !handoff) err = launch_finish(hdr, order, radius, k, st);
     return err;
 }
 

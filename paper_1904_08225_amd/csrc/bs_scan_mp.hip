@@ -40,7 +40,6 @@
 namespace bs {
 namespace {
 
-constexpr uint32_t kMpSpinLimit = 1u << 21;  // bounded wait (about a second), then give up
 constexpr int kMpEntries = 3;                 // entries a workgroup offers per step
 constexpr int kMpWords = 6 * kMpEntries + 1;  // per entry: key hi, lo, x, y, z, pos; then R
 constexpr int kMpRecStride = 32;              // words per exchange record
@@ -199,7 +198,8 @@ __global__ void __launch_bounds__(BLOCK)
     scan_mp_kernel(const float4* __restrict__ xyzm, const uint32_t* __restrict__ ids,
                    const uint32_t* __restrict__ codes, const int32_t* __restrict__ start_pos, int n, int k, int start, int32_t* __restrict__ order,
                    float* __restrict__ radius, const DevHeader* __restrict__ hdr, uint32_t* __restrict__ err,
-                   uint64_t* __restrict__ slots, uint64_t* __restrict__ ticks, int max_picks) {
+                   uint64_t* __restrict__ slots, uint64_t* __restrict__ ticks, int max_picks,
+                   uint32_t spin_limit) {
     constexpr int NW = BLOCK / 64;
     static_assert(kMpMaxPicks <= 128, "two passes of one lane per pick");
     __shared__ __align__(16) uint64_t s_w[NW][3];  // per wavefront: its three best keys (cached)
@@ -562,7 +562,7 @@ __global__ void __launch_bounds__(BLOCK)
                     }
                 }
                 if (__ballot(pending) == 0) break;
-                if (++spins > kMpSpinLimit) {
+                if (++spins > spin_limit) {
                     aborted = true;
                     break;
                 }
@@ -750,7 +750,7 @@ __global__ void __launch_bounds__(BLOCK)
 }
 
 using ScanMpFn = void (*)(const float4*, const uint32_t*, const uint32_t*, const int32_t*, int, int, int, int32_t*, float*,
-                          const DevHeader*, uint32_t*, uint64_t*, uint64_t*, int);
+                          const DevHeader*, uint32_t*, uint64_t*, uint64_t*, int, uint32_t);
 
 struct MpEntry {
     int block;
@@ -780,7 +780,7 @@ bool scan_several_supported(const ScanShape& s) {
 
 hipError_t launch_scan_several(const ScanShape& s, const float* pts, int n, int k, int start, int32_t* order,
                                float* radius, void* ws, uint64_t* ticks, int picks, hipStream_t st,
-                               const KernelEvents* ev) {
+                               const LaunchOpts* ev) {
     ScanMpFn fn = nullptr;
     for (const MpEntry& e : kMpTable)
         if (e.block == s.block && e.per_thread == s.per_thread) fn = e.fn;
@@ -801,12 +801,14 @@ hipError_t launch_scan_several(const ScanShape& s, const float* pts, int n, int 
     const int32_t* start_pos = sp.start_pos;
     const DevHeader* hdr = sp.hdr;
     uint32_t* err = &sp.hdr->error;
+    uint32_t spin = spin_limit_of(ev);
     void* args[] = {(void*)&xyzm,  (void*)&ids,   (void*)&codes, (void*)&start_pos, (void*)&n,     (void*)&k,
                     (void*)&start, (void*)&order, (void*)&radius,    (void*)&hdr,   (void*)&err,
-                    (void*)&slots, (void*)&ticks, (void*)&picks};
+                    (void*)&slots, (void*)&ticks, (void*)&picks, (void*)&spin};
     e = hipLaunchCooperativeKernel(reinterpret_cast<const void*>(fn), dim3(s.groups), dim3(s.block), args, 0, st);
     if (e == hipSuccess) e = hipGetLastError();
     if (e == hipSuccess && ev && ev->end) e = hipEventRecord(ev->end, st);
+    if (e == hipSuccess) e = launch_finish(sp.hdr, order, radius, k, st);
     return e;
 }
 

@@ -228,7 +228,10 @@ bool admit_batch(Server& s) {
         if (e == hipSuccess) e = hipMallocAsync(&f.ws, std::max<size_t>(batch_workspace_bytes(f.plan), 256), s.prep);
         for (size_t i = 0; e == hipSuccess && i < take.size(); ++i) {
             const Job& j = s.jobs[take[i]];
-            e = hipMemcpyAsync(static_cast<char*>(f.staging) + size_t(offs[i]) * 12, j.req.d_points,
+            if (j.req.ready_event)  // the producer of the points
+                e = hipStreamWaitEvent(s.prep, reinterpret_cast<hipEvent_t>(j.req.ready_event), 0);
+            if (e == hipSuccess)
+                e = hipMemcpyAsync(static_cast<char*>(f.staging) + size_t(offs[i]) * 12, j.req.d_points,
                                size_t(j.req.n) * 12, hipMemcpyDeviceToDevice, s.prep);
         }
         if (e == hipSuccess) {

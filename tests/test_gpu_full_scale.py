@@ -90,7 +90,7 @@ def test_served_poisson_stream(hip):
     arrivals = synth.poisson_arrivals(nreq, 200.0, seed=4)
     picks = rng.integers(0, pool_m, nreq)
     seeds = rng.integers(0, 2**62, nreq)
-    srv = hip.Server(hbm_budget_bytes=80 << 30, max_jobs_per_batch=256, poll_us=20)
+    srv = hip.Server(hbm_budget_bytes=80_000_000_000, max_jobs_per_batch=256, poll_us=20)
     jobs = []
     t0 = time.perf_counter()
     for i in range(nreq):

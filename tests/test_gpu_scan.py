@@ -247,3 +247,45 @@ def test_several_picks_one_wavefront_holds_every_entry(hip):
     for pt in (4, 16):
         o, r = run(hip, Q, k, start=5, tune=hip.tuning(kernel=hip.KERNEL_COOP, block=1024, per_thread=pt, picks=128))
         assert_parity(o, r, eo, er, "clumped per_thread=%d" % pt)
+
+
+def test_bounded_wait_give_up_is_reported(hip):
+    """A poll limit of one makes the cooperative kernels' bounded wait give
+    up (forced from the host; every workgroup still leaves normally): the
+    outputs become -2 / NaN, bs_order_status reports BS_ERR_TIMEOUT and the
+    checked binding raises.  Without the limit the same call orders
+    normally and the status is BS_OK."""
+    import torch
+    n, k = 262144, 6000
+    P = synth.cad_part(n, seed=9).points.numpy()
+    pts = torch.from_numpy(P).cuda()
+    tunes = {"several picks": dict(kernel=hip.KERNEL_COOP, picks=128),
+             "full scan": dict(kernel=hip.KERNEL_COOP, block=1024, per_thread=16),
+             "grid with a leading scan": dict(kernel=hip.KERNEL_GRID, picks=16, lead_picks=1000)}
+    eo, er = oracle.greedy32_grid(P, k, 11)
+    for label, kw in tunes.items():
+        print("give-up case:", label, flush=True)
+        forced = hip.tuning(spin_limit=1, **kw)
+        ws = torch.empty(hip.workspace_size(n, k, forced), dtype=torch.uint8, device="cuda")
+        o, r = hip.order(pts, k, start=11, tune=forced, workspace=ws, check=False)
+        assert hip.order_status(ws) == hip.BS_ERR_TIMEOUT, label
+        o, r = o.cpu().numpy(), r.cpu().numpy()
+        assert (o == -2).all() and np.isnan(r).all(), label
+        with pytest.raises(hip.BSError) as err:
+            hip.order(pts, k, start=11, tune=forced, workspace=ws)
+        assert err.value.code == hip.BS_ERR_TIMEOUT
+        # the workspace header is reset by the next call: a normal ordering
+        o, r = hip.order(pts, k, start=11, tune=hip.tuning(**kw), workspace=ws)
+        assert hip.order_status(ws) == hip.BS_OK
+        assert_parity(o.cpu().numpy(), r.cpu().numpy(), eo, er, label + " after a give-up")
+
+
+def test_order_status_nonfinite(hip):
+    import torch
+    P = synth.cad_part(30000, seed=4).points.numpy().copy()
+    P[123, 2] = np.inf
+    pts = torch.from_numpy(P).cuda()
+    ws = torch.empty(hip.workspace_size(30000, 500), dtype=torch.uint8, device="cuda")
+    o, r = hip.order(pts, 500, start=0, workspace=ws, check=False)
+    assert hip.order_status(ws) == hip.BS_ERR_INVALID_ARG
+    assert (o.cpu().numpy() == -1).all()
