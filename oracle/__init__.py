@@ -65,6 +65,13 @@ def _bind(path: str):
     lib.oracle_median_nn.restype = ctypes.c_int
     lib.oracle_prefix_length.argtypes = [ctypes.c_double, ctypes.c_double, i64, i64]
     lib.oracle_prefix_length.restype = i64
+    lib.oracle_philox4x32_10.argtypes = [vp, vp, vp]
+    lib.oracle_philox4x32_10.restype = None
+    lib.oracle_sample32.argtypes = [vp, i64, i64, u64, i64, ctypes.c_int32, ctypes.c_int32, ctypes.c_float,
+                                    vp, vp, vp]
+    lib.oracle_sample32.restype = ctypes.c_int
+    lib.oracle_prefix_nn.argtypes = [vp, i64, vp, i64, vp]
+    lib.oracle_prefix_nn.restype = ctypes.c_int
     return lib
 
 
@@ -198,6 +205,44 @@ def median_nn(points, order, pm: int, lib=None) -> float:
 def prefix_length(r: float, r_m: float, pm: int, k: int, lib=None) -> int:
     """p(r) = pm (r_m / r)^2, rounded up, clamped to [1, k] (Sec. 4.1)."""
     return int((lib or _load()).oracle_prefix_length(float(r), float(r_m), int(pm), int(k)))
+
+
+def philox4x32_10(ctr, key, lib=None):
+    """Philox4x32-10 (Salmon et al., SC'11) of a 4-word counter and 2-word key."""
+    c = np.ascontiguousarray(np.asarray(ctr, dtype=np.uint32).reshape(4))
+    kk = np.ascontiguousarray(np.asarray(key, dtype=np.uint32).reshape(2))
+    out = np.empty(4, dtype=np.uint32)
+    (lib or _load()).oracle_philox4x32_10(_ptr(c), _ptr(kk), _ptr(out))
+    return out
+
+
+def sample32(points, k: int, seed: int, start: int, sample_size: int = 200, growth_rounds: int = 500,
+             vicinity: float = 0.0, lib=None):
+    """The paper's randomized progressive sampler (Sec. 3.2).
+
+    Returns ``(order int32[k], radius float32[k], count)``; entries past
+    ``count`` (the input ran out, only with ``vicinity`` > 0) are -3 / NaN.
+    ``sample_size`` 0 samples the whole remaining set (exact greedy)."""
+    p = _points32(points)
+    n = p.shape[0]
+    order = np.empty(max(k, 0), dtype=np.int32)
+    radius = np.empty(max(k, 0), dtype=np.float32)
+    cnt = np.zeros(1, dtype=np.int64)
+    rc = (lib or _load()).oracle_sample32(_ptr(p), n, k, ctypes.c_uint64(seed & (2**64 - 1)), start,
+                                          int(sample_size), int(growth_rounds), float(vicinity),
+                                          _ptr(order), _ptr(radius), _ptr(cnt))
+    _check(rc)
+    return order, radius, int(cnt[0])
+
+
+def prefix_nn(points, order, p: int, lib=None) -> np.ndarray:
+    """Each of the first ``p`` ordered surfels' distance to its nearest other
+    surfel of that prefix (Sec. 3.3 quality measure)."""
+    pts = _points32(points)
+    o = np.ascontiguousarray(np.asarray(order, dtype=np.int32))
+    out = np.empty(int(p), dtype=np.float32)
+    _check((lib or _load()).oracle_prefix_nn(_ptr(pts), pts.shape[0], _ptr(o), int(p), _ptr(out)), False)
+    return out
 
 
 def compile_variant(src_text: str, out_path: str):

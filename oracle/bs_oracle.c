@@ -50,6 +50,13 @@
  *   oracle_median_nn         r_m: median nearest-neighbour distance within
  *                            the first p_m ordered surfels (Sec. 4.1).
  *   oracle_prefix_length     p(r) = p_m (r_m / r)^2, rounded up, in [1, k].
+ *   oracle_philox4x32_10     the counter-based generator the sampler draws
+ *                            from (Salmon et al., SC'11), from its definition.
+ *   oracle_sample32          the paper's randomized progressive sampler
+ *                            (Sec. 3.2), rounds of ~200 random candidates.
+ *   oracle_prefix_nn         each prefix surfel's distance to its nearest
+ *                            other prefix surfel (the Sec. 3.3 quality
+ *                            measure of a prefix).
  */
 #include <math.h>
 #include <stdint.h>
@@ -628,5 +635,195 @@ int oracle_oct_encode_n(const float* N, int64_t n, int16_t* out)
 {
     if (n < 0 || (n > 0 && (!N || !out))) return ORACLE_BAD_ARG;
     for (int64_t i = 0; i < n; ++i) oracle_oct_encode(N + 3 * i, out + 2 * i);
+    return ORACLE_OK;
+}
+
+/* ------------------------------------------- randomized sampler (Sec. 3.2) */
+/*
+ * Philox4x32-10 (Salmon, Moraes, Dror and Shaw, "Parallel random numbers: as
+ * easy as 1, 2, 3", SC 2011): a 4 x 32-bit counter and a 2 x 32-bit key; each
+ * of the 10 rounds multiplies counter words 0 and 2 by the round constants
+ * 0xD2511F53 and 0xCD9E8D57 into 64-bit products and mixes the halves with
+ * words 1 and 3 and the key; the key grows by the Weyl increments
+ * 0x9E3779B9 and 0xBB67AE85 between rounds.
+ */
+void oracle_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4])
+{
+    uint32_t x0 = ctr[0], x1 = ctr[1], x2 = ctr[2], x3 = ctr[3];
+    uint32_t k0 = key[0], k1 = key[1];
+    for (int r = 0; r < 10; ++r) {
+        if (r > 0) {
+            k0 += 0x9E3779B9u;
+            k1 += 0xBB67AE85u;
+        }
+        uint64_t p0 = (uint64_t)0xD2511F53u * x0;
+        uint64_t p1 = (uint64_t)0xCD9E8D57u * x2;
+        uint32_t hi0 = (uint32_t)(p0 >> 32), lo0 = (uint32_t)p0;
+        uint32_t hi1 = (uint32_t)(p1 >> 32), lo1 = (uint32_t)p1;
+        uint32_t y0 = hi1 ^ x1 ^ k0;
+        uint32_t y2 = hi0 ^ x3 ^ k1;
+        x0 = y0;
+        x1 = lo1;
+        x2 = y2;
+        x3 = lo0;
+    }
+    out[0] = x0; out[1] = x1; out[2] = x2; out[3] = x3;
+}
+
+/*
+ * The paper's randomized approximation of the greedy permutation (Sec. 3.2):
+ * remove a random start surfel and output it; then, round after round, draw
+ * a random sample of the remaining input set, append the sample member whose
+ * distance to all surfels chosen before is largest and remove it from the
+ * input; optionally remove sample members in close vicinity of the chosen
+ * surfels; stop after k surfels or when the input set is empty.  Heuristic:
+ * after every K rounds one more surfel is taken from each sample.
+ *
+ * Readings (the paper does not fix them; listed in the design notes):
+ *   - start = SplitMix64(seed) mod n (as the exact ordering);
+ *   - the sample of round i (i = 0 for the first round after the start):
+ *     slot j = 0 .. S-1 tries up to 16 draws a = 0, 1, ...: the first output
+ *     word u of Philox4x32-10 with counter (i, j, a, 0) and key (seed low,
+ *     seed high 32 bits) names candidate floor(u * n / 2^32); the slot takes
+ *     the first draw that names a remaining candidate (else stays empty).
+ *     The sample is the set of the slots' candidates (a candidate named twice
+ *     counts once);
+ *   - S = 0 means the whole remaining set (the exact greedy permutation);
+ *   - a round whose slots all stayed empty takes the remaining candidate with
+ *     the largest distance (the whole input as its sample);
+ *   - "distance to all surfels chosen before" is the binary32 squared
+ *     distance to the nearest chosen surfel (the fixed d2 above, so ties and
+ *     radii follow the exact ordering's rules); largest wins, lowest index on
+ *     ties; radius[t] = sqrtf of that squared distance;
+ *   - round i takes q_i = 1 + floor(i / K) picks (K < 0: always one), one
+ *     after another from the same sample, each the member farthest from all
+ *     surfels chosen so far, including the round's earlier picks;
+ *   - vicinity v > 0: after the round's picks, every remaining sample member
+ *     whose squared distance to the nearest chosen surfel is below
+ *     (v * v) * d1, d1 the squared distance of the round's first pick, is
+ *     removed from the input (binary32); v = 0 removes nothing;
+ *   - the output may end early (input set empty, only with v > 0): count
+ *     picks are made, entries count .. k-1 get order -3 and radius NaN.
+ * The distance of every remaining candidate to the chosen set is kept for
+ * all candidates (a plain O(n) update per pick), which is the definition.
+ */
+int oracle_sample32(const float* P, int64_t n, int64_t k, uint64_t seed, int64_t start,
+                    int32_t S, int32_t K, float vicinity,
+                    int32_t* order, float* radius, int64_t* out_count)
+{
+    if (out_count) *out_count = 0;
+    if (k == 0) return ORACLE_OK;
+    if (!P || !order || n < 1 || k < 0 || k > n || start < 0 || start >= n || S < 0 ||
+        !(vicinity >= 0.0f) || (S == 0 && vicinity > 0.0f) || n >= ((int64_t)1 << 31))
+        return ORACLE_BAD_ARG;
+    if (!all_finite(P, n)) {
+        fill_nonfinite(order, radius, k);
+        return ORACLE_NONFINITE;
+    }
+    float* m = (float*)malloc(sizeof(float) * (size_t)n);
+    unsigned char* alive = (unsigned char*)malloc((size_t)n);
+    int64_t* sample = (int64_t*)malloc(sizeof(int64_t) * (size_t)(S > 0 ? S : 1));
+    if (!m || !alive || !sample) { free(m); free(alive); free(sample); return ORACLE_NO_MEM; }
+    for (int64_t i = 0; i < n; ++i) { m[i] = INFINITY; alive[i] = 1; }
+    const uint32_t key[2] = {(uint32_t)seed, (uint32_t)(seed >> 32)};
+
+    /* the start: output it, remove it, distances of the rest to it */
+    int64_t t = 1, remaining = n - 1;
+    int64_t c = start;
+    order[0] = (int32_t)c;
+    if (radius) radius[0] = INFINITY;
+    alive[c] = 0;
+    for (int64_t i = 0; i < n; ++i) {
+        if (!alive[i]) continue;
+        float d = d2_f32(P + 3 * i, P + 3 * c);
+        if (d < m[i]) m[i] = d;
+    }
+    for (int64_t round = 0; t < k && remaining > 0; ++round) {
+        int64_t ns = 0;
+        int whole = S == 0;
+        if (!whole) {
+            for (int32_t j = 0; j < S; ++j) {
+                for (uint32_t a = 0; a < 16; ++a) {
+                    const uint32_t ctr[4] = {(uint32_t)round, (uint32_t)j, a, 0u};
+                    uint32_t u[4];
+                    oracle_philox4x32_10(ctr, key, u);
+                    int64_t idx = (int64_t)(((uint64_t)u[0] * (uint64_t)n) >> 32);
+                    if (!alive[idx]) continue;
+                    int dup = 0;
+                    for (int64_t q = 0; q < ns; ++q) if (sample[q] == idx) dup = 1;
+                    if (!dup) sample[ns++] = idx;
+                    break;
+                }
+            }
+            if (ns == 0) whole = 1;  /* no draw hit: the whole input this round */
+        }
+        int64_t q = K < 0 ? 1 : 1 + round / (K > 0 ? K : 1);
+        if (whole && S > 0) q = 1;
+        float d_first = 0.0f;
+        for (int64_t p = 0; p < q && t < k; ++p) {
+            int64_t best = -1;
+            if (whole) {
+                for (int64_t i = 0; i < n; ++i)
+                    if (alive[i] && (best < 0 || m[i] > m[best])) best = i;
+            } else {
+                for (int64_t s2 = 0; s2 < ns; ++s2) {
+                    int64_t i = sample[s2];
+                    if (!alive[i]) continue;
+                    if (best < 0 || m[i] > m[best] || (m[i] == m[best] && i < best)) best = i;
+                }
+            }
+            if (best < 0) break;
+            if (p == 0) d_first = m[best];
+            c = best;
+            order[t] = (int32_t)c;
+            if (radius) radius[t] = sqrtf(m[c]);
+            alive[c] = 0;
+            --remaining;
+            ++t;
+            for (int64_t i = 0; i < n; ++i) {
+                if (!alive[i]) continue;
+                float d = d2_f32(P + 3 * i, P + 3 * c);
+                if (d < m[i]) m[i] = d;
+            }
+        }
+        if (vicinity > 0.0f && !whole) {
+            const float thr = (vicinity * vicinity) * d_first;
+            for (int64_t s2 = 0; s2 < ns; ++s2) {
+                int64_t i = sample[s2];
+                if (alive[i] && m[i] < thr) { alive[i] = 0; --remaining; }
+            }
+        }
+    }
+    if (out_count) *out_count = t;
+    for (int64_t u = t; u < k; ++u) {
+        order[u] = -3;
+        if (radius) radius[u] = NAN;
+    }
+    free(m); free(alive); free(sample);
+    return ORACLE_OK;
+}
+
+/*
+ * Sec. 3.3 measures how evenly a prefix of an ordering covers the surface by
+ * each prefix surfel's distance to its nearest other surfel of the prefix.
+ * out[a] = sqrtf(min over b != a of d2(P[order[a]], P[order[b]])), a < p,
+ * binary32 with the fixed d2; +inf when p = 1.
+ */
+int oracle_prefix_nn(const float* P, int64_t n, const int32_t* order, int64_t p, float* out)
+{
+    if (p < 1 || !P || !order || !out) return ORACLE_BAD_ARG;
+    for (int64_t a = 0; a < p; ++a)
+        if (order[a] < 0 || order[a] >= n) return ORACLE_BAD_ARG;
+    for (int64_t a = 0; a < p; ++a) {
+        const float* pa = P + 3 * (int64_t)order[a];
+        float best = INFINITY;
+        for (int64_t b = 0; b < p; ++b) {
+            if (b != a) {
+                float d = d2_f32(pa, P + 3 * (int64_t)order[b]);
+                if (d < best) best = d;
+            }
+        }
+        out[a] = sqrtf(best);
+    }
     return ORACLE_OK;
 }

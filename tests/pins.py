@@ -424,3 +424,163 @@ def pin_battery(lib=None):
     for name in ("random", "duplicates", "mixed_scale"):
         Q = cases.ADVERSARIAL[name](700, 3)
         check_grid_equals_plain(Q, 700, 1, lib=lib)
+    sampler_battery(lib)
+
+
+# ------------------------------------------------ randomized sampler (Sec. 3.2)
+
+PHILOX_KAT = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "philox4x32_10_kat.json")
+_M32 = 0xFFFFFFFF
+
+
+def philox_py(ctr, key):
+    """Philox4x32-10 in plain Python integers, written from the SC'11
+    definition independently of the oracle's C (used by the brute force)."""
+    x0, x1, x2, x3 = (int(v) & _M32 for v in ctr)
+    k0, k1 = (int(v) & _M32 for v in key)
+    for r in range(10):
+        if r:
+            k0 = (k0 + 0x9E3779B9) & _M32
+            k1 = (k1 + 0xBB67AE85) & _M32
+        p0 = 0xD2511F53 * x0
+        p1 = 0xCD9E8D57 * x2
+        x0, x1, x2, x3 = ((p1 >> 32) ^ x1 ^ k0) & _M32, p1 & _M32, ((p0 >> 32) ^ x3 ^ k1) & _M32, p0 & _M32
+    return (x0, x1, x2, x3)
+
+
+def check_philox_kat(lib=None):
+    with open(PHILOX_KAT) as f:
+        kat = json.load(f)
+    for v in kat["vectors"]:
+        ctr = [int(h, 16) for h in v["ctr"]]
+        key = [int(h, 16) for h in v["key"]]
+        exp = [int(h, 16) for h in v["out"]]
+        got = [int(w) for w in oracle.philox4x32_10(ctr, key, lib=lib)]
+        assert got == exp, ("philox", v, ["%08x" % g for g in got])
+        assert list(philox_py(ctr, key)) == exp
+
+
+def brute_sample_f32(P, k, seed, start, S, K, vicinity):
+    """From-scratch numpy sampler: every pick recomputes each candidate's
+    binary32 squared distance to the nearest chosen surfel from the full
+    candidate-by-chosen matrix.  Rules as the sampler's readings: slot j of
+    round i tries draws a = 0..15 (Philox counter (i, j, a, 0), key = seed
+    halves, candidate floor(u0 * n / 2^32)) and keeps the first remaining one;
+    S = 0 or an empty sample means the whole remaining set (one pick when
+    the sample came up empty); round i makes 1 + i // K picks (K < 0: one)."""
+    P = np.asarray(P, dtype=np.float32)
+    n = P.shape[0]
+    key = (seed & _M32, (seed >> 32) & _M32)
+    alive = np.ones(n, dtype=bool)
+    chosen = [start]
+    rad = [np.float32(np.inf)]
+    alive[start] = False
+
+    def mind():
+        Q = P[np.array(chosen)]
+        dx = P[:, None, 0] - Q[None, :, 0]
+        dy = P[:, None, 1] - Q[None, :, 1]
+        dz = P[:, None, 2] - Q[None, :, 2]
+        with np.errstate(over="ignore"):
+            return ((dx * dx + dy * dy) + dz * dz).min(axis=1)
+
+    rnd = 0
+    while len(chosen) < k and alive.any():
+        sample = []
+        if S > 0:
+            for j in range(S):
+                for a in range(16):
+                    u = philox_py((rnd, j, a, 0), key)[0]
+                    idx = (u * n) >> 32
+                    if alive[idx]:
+                        if idx not in sample:
+                            sample.append(idx)
+                        break
+        whole = S == 0 or not sample
+        q = 1 if (K < 0 or (whole and S > 0)) else 1 + rnd // max(K, 1)
+        d_first = None
+        for _ in range(q):
+            if len(chosen) >= k:
+                break
+            m = mind()
+            pool = np.nonzero(alive)[0] if whole else np.array([i for i in sample if alive[i]], dtype=np.int64)
+            if pool.size == 0:
+                break
+            vals = m[pool]
+            best = pool[vals == vals.max()].min()
+            if d_first is None:
+                d_first = m[best]
+            chosen.append(int(best))
+            rad.append(np.sqrt(m[best]))
+            alive[best] = False
+        if vicinity > 0 and not whole and d_first is not None:
+            m = mind()
+            thr = np.float32(np.float32(vicinity) * np.float32(vicinity)) * d_first
+            for i in sample:
+                if alive[i] and m[i] < thr:
+                    alive[i] = False
+        rnd += 1
+    cnt = len(chosen)
+    order = np.full(k, -3, dtype=np.int32)
+    radius = np.full(k, np.nan, dtype=np.float32)
+    order[:cnt] = chosen
+    radius[:cnt] = rad
+    return order, radius, cnt
+
+
+def check_sampler_bruteforce(lib=None, sizes=(2, 9, 40, 64)):
+    """The oracle's sampler equals the from-scratch reformulation on small
+    adversarial sets, over sample sizes (including ones the remaining set
+    cannot fill), growth periods and vicinity removal."""
+    configs = [(200, 500, 0.0), (3, 2, 0.0), (5, 1, 0.0), (8, -1, 0.0), (4, 3, 0.5), (6, 2, 1.0), (1, 1, 0.0)]
+    for name, gen in cases.ADVERSARIAL.items():
+        for n in sizes:
+            P = gen(n, 700 + n)
+            for ci, (S, K, v) in enumerate(configs):
+                seed = (0x9E3779B97F4A7C15 * (n + 31 * ci)) & (2**64 - 1)
+                start = (seed >> 7) % n
+                k = n if ci % 2 == 0 else max(1, (2 * n) // 3)
+                o, r, c = oracle.sample32(P, k, seed, start, S, K, v, lib=lib)
+                bo, br, bc = brute_sample_f32(P, k, seed, start, S, K, v)
+                assert c == bc, (name, n, ci, c, bc)
+                assert np.array_equal(o, bo), (name, n, ci, o, bo)
+                assert same_f32(r, br), (name, n, ci, r, br)
+
+
+def check_sampler_whole_is_greedy(lib=None):
+    """With the whole remaining set as the sample, every pick is the exact
+    greedy one, however many picks a round takes."""
+    for name in ("random", "lattice", "duplicates", "mixed_scale"):
+        P = cases.ADVERSARIAL[name](300, 5)
+        eo, er = oracle.greedy32(P, 300, 7, lib=lib)
+        for K in (1, 2, 7, 500, -1):
+            o, r, c = oracle.sample32(P, 300, 123, 7, 0, K, 0.0, lib=lib)
+            assert c == 300 and np.array_equal(o, eo) and same_f32(r, er), (name, K)
+
+
+def check_prefix_nn(lib=None):
+    """Nearest-neighbour distances inside a prefix on sets where they are
+    known: a unit lattice (all 1), a line with gaps 1, 2, 3, 4, 5, 85, a single
+    point (+inf); on a greedy order every value is at least the prefix's
+    covering radius (an r-net)."""
+    L = np.stack(np.meshgrid(np.arange(6), np.arange(6), np.arange(6), indexing="ij"), -1)
+    L = L.reshape(-1, 3).astype(np.float32)
+    ident = np.arange(L.shape[0], dtype=np.int32)
+    assert np.all(oracle.prefix_nn(L, ident, L.shape[0], lib=lib) == 1.0)
+    line = np.array([[0, 0, 0], [1, 0, 0], [3, 0, 0], [6, 0, 0], [10, 0, 0], [15, 0, 0], [100, 0, 0]],
+                    dtype=np.float32)
+    o7 = np.array([4, 0, 3, 1, 2, 5, 6], dtype=np.int32)
+    assert oracle.prefix_nn(line, o7, 5, lib=lib).tolist() == [4.0, 1.0, 3.0, 1.0, 2.0]
+    assert oracle.prefix_nn(line, o7, 7, lib=lib).tolist() == [4.0, 1.0, 3.0, 1.0, 2.0, 5.0, 85.0]
+    assert np.isinf(oracle.prefix_nn(line, o7, 1, lib=lib)[0])
+    P = cases.random_cloud(1500, 8)
+    o, r = oracle.greedy32(P, 500, 2, lib=lib)
+    for p in (10, 100, 500):
+        assert oracle.prefix_nn(P, o, p, lib=lib).min() >= r[p - 1]
+
+
+def sampler_battery(lib=None):
+    check_philox_kat(lib)
+    check_sampler_bruteforce(lib, sizes=(9, 40))
+    check_sampler_whole_is_greedy(lib)
+    check_prefix_nn(lib)

@@ -37,6 +37,23 @@ MUTANTS = {
                             "        int64_t span = isinf(rr) ? INT64_MAX : (int64_t)floor(rr / h) + 2;",
                             "        double rr = sqrt((double)mc);\n"
                             "        int64_t span = isinf(rr) ? INT64_MAX : (int64_t)floor(rr / h) + 1;"),
+    "philox_multiplier": ("        uint64_t p0 = (uint64_t)0xD2511F53u * x0;", "        uint64_t p0 = (uint64_t)0xD2511F55u * x0;"),
+    "philox_key_bump": ("            k1 += 0xBB67AE85u;", "            k1 += 0x9E3779B9u;"),
+    "philox_no_first_key": ("        if (r > 0) {\n            k0 += 0x9E3779B9u;", "        {\n            k0 += 0x9E3779B9u;"),
+    "sampler_growth_late": ("        int64_t q = K < 0 ? 1 : 1 + round / (K > 0 ? K : 1);",
+                            "        int64_t q = K < 0 ? 1 : 1 + (round + 1) / (K > 0 ? K : 1);"),
+    "sampler_highest_index_tie": ("(m[i] == m[best] && i < best)", "(m[i] == m[best] && i > best)"),
+    "sampler_draw_modulo": ("                    int64_t idx = (int64_t)(((uint64_t)u[0] * (uint64_t)n) >> 32);",
+                            "                    int64_t idx = (int64_t)((uint64_t)u[0] % (uint64_t)n);"),
+    "sampler_draws_removed": ("                    if (!alive[idx]) continue;\n                    int dup = 0;",
+                              "                    int dup = 0;"),
+    "sampler_counter_swapped": ("                    const uint32_t ctr[4] = {(uint32_t)round, (uint32_t)j, a, 0u};",
+                                "                    const uint32_t ctr[4] = {(uint32_t)j, (uint32_t)round, a, 0u};"),
+    "sampler_vicinity_ties": ("                if (alive[i] && m[i] < thr) { alive[i] = 0; --remaining; }",
+                              "                if (alive[i] && m[i] <= thr) { alive[i] = 0; --remaining; }"),
+    "sampler_radius_after_removal": ("            if (radius) radius[t] = sqrtf(m[c]);\n            alive[c] = 0;\n            --remaining;",
+                                     "            if (radius) radius[t] = sqrtf(m[c] * 0.5f);\n            alive[c] = 0;\n            --remaining;"),
+    "prefix_nn_self": ("            if (b != a) {\n                float d = d2_f32(pa,", "            {\n                float d = d2_f32(pa,"),
     "grid_prunes_too_much": ("if (bd * (1.0 - 1e-5) - 1e-37 >= (double)mc) continue;",
                              "if (bd * 4.0 >= (double)mc) continue;"),
     "splitmix_constant": ("z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;",

@@ -121,6 +121,59 @@ def test_grid_span_boundary():
     pins.check_span_boundary()
 
 
+def test_philox_known_answers():
+    pins.check_philox_kat()
+
+
+def test_sampler_bruteforce():
+    pins.check_sampler_bruteforce()
+
+
+def test_sampler_whole_set_is_exact_greedy():
+    pins.check_sampler_whole_is_greedy()
+
+
+def test_prefix_nn():
+    pins.check_prefix_nn()
+
+
+def test_sampler_edges():
+    P = cases.random_cloud(50, 2)
+    o, r, c = oracle.sample32(P, 0, 1, 0)
+    assert c == 0 and o.size == 0
+    o, r, c = oracle.sample32(P[:1], 1, 1, 0)
+    assert c == 1 and o.tolist() == [0] and np.isinf(r[0])
+    with pytest.raises(oracle.OracleError):
+        oracle.sample32(P, 51, 1, 0)                      # k > n
+    with pytest.raises(oracle.OracleError):
+        oracle.sample32(P, 5, 1, 0, sample_size=0, vicinity=0.5)  # removal needs a sample
+    Q = P.copy()
+    Q[3, 0] = np.nan
+    o, r, c = oracle.sample32(Q, 10, 1, 0)
+    assert (o == -1).all() and np.isnan(r).all()
+    # prefix stability holds for the sampler too (the rounds do not depend on k)
+    full, rf, _ = oracle.sample32(P, 50, 99, 4, sample_size=7, growth_rounds=3)
+    for k in (1, 2, 13, 49):
+        o, r, c = oracle.sample32(P, k, 99, 4, sample_size=7, growth_rounds=3)
+        assert c == k and np.array_equal(o, full[:k]) and pins.same_f32(r, rf[:k])
+    # vicinity removal can exhaust the input: the tail is -3 / NaN
+    o, r, c = oracle.sample32(P, 50, 5, 0, sample_size=50, growth_rounds=-1, vicinity=3.0)
+    assert c < 50 and (o[c:] == -3).all() and np.isnan(r[c:]).all() and (o[:c] >= 0).all()
+
+
+def test_sampler_quality_between_random_and_greedy():
+    # Sec. 3.3: the sampler's prefixes cover the surface almost as evenly as
+    # the greedy permutation's and far better than a random subset's
+    import synth
+    P = synth.cad_part(20000, seed=3).points.numpy()
+    eo, _ = oracle.greedy32_grid(P, 2000, 0)
+    so, _, _ = oracle.sample32(P, 2000, 7, 0)
+    ro = np.random.default_rng(1).permutation(P.shape[0])[:2000].astype(np.int32)
+    for p in (500, 2000):
+        g, s, r = (np.median(oracle.prefix_nn(P, o, p)) for o in (eo, so, ro))
+        assert g >= s > 1.5 * r, (p, g, s, r)
+
+
 def test_statistics_consistent():
     P = cases.random_cloud(600, 3)
     o, r, st = oracle.greedy32(P, 600, 2, stats=True)
