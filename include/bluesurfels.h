@@ -184,6 +184,26 @@ int bs_order_profile(const float* d_points, int64_t n, int64_t k, int64_t start_
                      void* stream);
 
 /*
+ * For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the
+ * ordering of bs_order_ex with the workspace taken from a device array the
+ * library holds, one per GPU, from module load to process exit
+ * (bs_noalloc_max_bytes() bytes: 64 MiB, the several-picks scan up to
+ * 524,288 candidates).  The call allocates nothing and frees nothing; the
+ * caller passes inputs and outputs.  Every call on one GPU shares that GPU's
+ * array, so calls that overlap on one GPU race: order them (one stream, or
+ * events).  Arguments as bs_order_ex (start_index -1 = from seed; tuning
+ * NULL = automatic).  Errors: as bs_order_ex; BS_ERR_UNSUPPORTED when
+ * bs_workspace_size(n, k, tuning) exceeds the array; BS_ERR_HIP if the
+ * array's device address cannot be found (looked up on a device's first
+ * call, with that device current).
+ */
+int bs_order_noalloc(const float* d_points, int64_t n, int64_t k, uint64_t seed, int64_t start_index,
+                     int32_t* d_out_order, float* d_out_radius, const bs_tuning* tuning, void* stream);
+/* Bytes of the per-GPU array bs_order_noalloc uses as its workspace. */
+size_t bs_noalloc_max_bytes(void);
+
+/*
  * Status of the last ordering enqueued on `d_workspace` (bs_order_ex,
  * bs_order_profile): waits for `stream` (a hipStream_t), then reads the
  * workspace's device header.  Returns BS_OK; BS_ERR_INVALID_ARG if a

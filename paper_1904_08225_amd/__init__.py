@@ -110,6 +110,10 @@ def load():
     lib.bs_order_ex.restype = i32
     lib.bs_order_profile.argtypes = [vp, i64, i64, i64, vp, vp, vp, vp, vp, vp, sz, tp, vp]
     lib.bs_order_profile.restype = i32
+    lib.bs_order_noalloc.argtypes = [vp, i64, i64, u64, i64, vp, vp, tp, vp]
+    lib.bs_order_noalloc.restype = i32
+    lib.bs_noalloc_max_bytes.argtypes = []
+    lib.bs_noalloc_max_bytes.restype = sz
     lib.bs_order_status.argtypes = [vp, vp]
     lib.bs_order_status.restype = i32
     lib.bs_wall_clock_hz.argtypes = []
@@ -295,6 +299,36 @@ def order_status(workspace, stream=None) -> int:
     BS_OK, BS_ERR_INVALID_ARG (non-finite input) or BS_ERR_TIMEOUT (a bounded
     wait gave up).  Synchronises the stream."""
     return int(load().bs_order_status(_ptr(workspace), _stream_handle(stream)))
+
+
+def order_noalloc(points, k: Optional[int] = None, seed: int = 0, *, start: Optional[int] = None,
+                  tune: Optional[Tuning] = None, out_order=None, out_radius=None, stream=None,
+                  check: bool = True) -> Tuple["torch.Tensor", "torch.Tensor"]:
+    """``bs_order_noalloc``: the ordering with the library's per-GPU scratch
+    array as workspace (no device allocation by the library; the outputs are
+    allocated here unless given).  Calls on one GPU must not overlap."""
+    import torch
+    lib = load()
+    points = _prep_points(points)
+    n = int(points.shape[0])
+    k = n if k is None else int(k)
+    dev = points.device
+    if out_order is None:
+        out_order = torch.empty(max(k, 0), dtype=torch.int32, device=dev)
+    if out_radius is None:
+        out_radius = torch.empty(max(k, 0), dtype=torch.float32, device=dev)
+    tp = ctypes.byref(tune) if tune is not None else None
+    _check(lib.bs_order_noalloc(_ptr(points), n, k, ctypes.c_uint64(seed & (2**64 - 1)),
+                                -1 if start is None else int(start), _ptr(out_order), _ptr(out_radius), tp,
+                                _stream_handle(stream)))
+    if check and k > 0:
+        torch.cuda.current_stream().synchronize() if stream is None else stream.synchronize()
+        _check_outputs(int(out_order[0]))
+    return out_order, out_radius
+
+
+def noalloc_max_bytes() -> int:
+    return int(load().bs_noalloc_max_bytes())
 
 
 def emit_surfels(points, order, normals=None, colors=None, stream=None, out=None):

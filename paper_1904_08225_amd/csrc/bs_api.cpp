@@ -306,10 +306,11 @@ size_t bs_workspace_size(int64_t n, int64_t k, const bs_tuning* tuning) {
     return workspace_for(n, p);
 }
 
-static int order_impl(const float* d_points, int64_t n, int64_t k, uint64_t seed,
-                      int64_t start_index, int32_t* d_out_order, float* d_out_radius,
-                      uint64_t* d_ticks, const LaunchOpts* ev, void* d_workspace,
-                      size_t workspace_bytes, const bs_tuning* tuning, void* stream) {
+}  // extern "C"
+
+int bs::order_impl(const float* d_points, int64_t n, int64_t k, uint64_t seed, int64_t start_index,
+                   int32_t* d_out_order, float* d_out_radius, uint64_t* d_ticks, const LaunchOpts* ev,
+                   void* d_workspace, size_t workspace_bytes, const bs_tuning* tuning, void* stream) {
     if (k < 0) return set_error(BS_ERR_INVALID_ARG, "k=%lld < 0", (long long)k);
     if (k == 0) return BS_OK;
     if (n < 1 || n >= (int64_t(1) << 31))
@@ -354,6 +355,8 @@ static int order_impl(const float* d_points, int64_t n, int64_t k, uint64_t seed
     if (e != hipSuccess) return set_error(BS_ERR_HIP, "launch failed: %s", hipGetErrorString(e));
     return BS_OK;
 }
+
+extern "C" {
 
 int bs_order_ex(const float* d_points, const float* d_normals, const uint8_t* d_colors,
                 int64_t n, int64_t k, uint64_t seed, int64_t start_index,

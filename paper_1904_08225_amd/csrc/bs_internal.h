@@ -127,6 +127,12 @@ hipError_t launch_median_nn(const float* pts, int64_t n, const int32_t* order, i
 // Error reporting (bs_api.cpp).
 int set_error(int code, const char* fmt, ...);
 
+// One ordering on a caller-provided workspace (bs_api.cpp): argument checks,
+// plan, launches.  start_index -1 derives the start from `seed`.
+int order_impl(const float* d_points, int64_t n, int64_t k, uint64_t seed, int64_t start_index,
+               int32_t* d_out_order, float* d_out_radius, uint64_t* d_ticks, const LaunchOpts* ev,
+               void* d_workspace, size_t workspace_bytes, const bs_tuning* tuning, void* stream);
+
 // The autotuned configuration for (n, k) on the current device, if any.
 bool tuned_lookup(int64_t n, int64_t k, bs_tuning* out);
 
