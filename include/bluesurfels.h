@@ -385,6 +385,84 @@ int bs_batch_plan_execute(bs_batch_plan* plan, const float* d_points, int32_t* d
                           float* d_out_radius, void* d_workspace, size_t workspace_bytes,
                           void* stream);
 void bs_batch_plan_destroy(bs_batch_plan* plan);
+/*
+ * The randomized sampler (bs_sample, paper Sec. 3.2) over the plan's objects
+ * instead of the exact ordering: one persistent launch whose 256-thread
+ * workgroups take objects largest k first.  Object j's picks are bit-identical
+ * to bs_sample on it alone with seed h_seed[j].  Outputs and workspace as
+ * bs_batch_plan_execute; d_out_count: NULL or device int32[m] (objects as
+ * given; 0 for objects with k = 0).  params NULL = bs_sampler_defaults().
+ * Defined after the sampler's parameter struct below.
+ */
+
+/* ------------------------------------ randomized sampler (paper Sec. 3.2) */
+
+/*
+ * Parameters of the paper's randomized progressive sampler (Sec. 3.2), which
+ * approximates the greedy permutation with rounds of random samples.
+ */
+typedef struct {
+    int32_t sample_size;    /* candidates drawn per round, 1..256 (the paper: about 200); 0 = the
+                               whole remaining set, which makes every pick the exact greedy one */
+    int32_t growth_rounds;  /* after every growth_rounds rounds one more pick is taken from each
+                               sample (the paper: 500); < 0 = one pick per round; 0 is invalid */
+    float vicinity;         /* v > 0: after a round, its sample members whose squared distance to
+                               the nearest chosen surfel is below v^2 times that of the round's
+                               first pick are removed from the input (the paper's optional removal
+                               of samples near the chosen ones, for which it gives no threshold);
+                               0 = no removal (needs sample_size > 0 otherwise) */
+    int32_t reserved[5];    /* must be zero */
+} bs_sampler;
+
+/* The paper's values: 200 samples per round, one more pick every 500 rounds, no removal. */
+bs_sampler bs_sampler_defaults(void);
+
+/* Device workspace bytes bs_sample needs for n candidates (0 if n is out of range). */
+size_t bs_sample_workspace_size(int64_t n);
+
+/*
+ * The paper's randomized approximation of the greedy permutation (Sec. 3.2):
+ * the start (SplitMix64(seed) mod n, or start_index >= 0), then rounds
+ * i = 0, 1, ...: draw a random sample of the remaining candidates; append the
+ * member whose distance to all chosen surfels is largest (binary32 d2 as in
+ * the exact ordering, lowest index on ties) and remove it, 1 + floor(i /
+ * growth_rounds) times from the same sample; optionally remove sample members
+ * near the chosen surfels; stop after k picks or when the input is empty.
+ * The draws: slot j of round i tries up to 16 times the candidate
+ * floor(u * n / 2^32), u the first output word of Philox4x32-10 (Salmon et
+ * al., SC 2011) with counter (i, j, attempt, 0) and key (low, high 32 bits of
+ * seed), and keeps the first one that remains; a candidate named by two slots
+ * counts once; a round whose slots all miss takes the farthest remaining
+ * candidate.  The result depends only on (points, k, seed, start, params).
+ *   params        NULL = bs_sampler_defaults()
+ *   d_out_order   device int32[k]: picks; entries from the count on (the input ran
+ *                 out, only with vicinity > 0) are -3, their radius NaN
+ *   d_out_radius  device float[k] or NULL: each pick's distance to the surfels
+ *                 chosen before it (+inf for the start)
+ *   d_out_count   device int32[1] or NULL: picks made (not written when k == 0)
+ *   d_workspace   device, at least bs_sample_workspace_size(n) bytes, 256-byte aligned
+ * Non-finite coordinates give order -1, radius NaN, count 0.  Enqueues on
+ * `stream` (one workgroup orders the object).  Errors: BS_ERR_INVALID_ARG
+ * (sizes, pointers, parameters, workspace), BS_ERR_HIP.
+ */
+int bs_sample(const float* d_points, int64_t n, int64_t k, uint64_t seed, int64_t start_index,
+              const bs_sampler* params, int32_t* d_out_order, float* d_out_radius, int32_t* d_out_count,
+              void* d_workspace, size_t workspace_bytes, void* stream);
+
+/*
+ * Sec. 3.3 compares orderings by each prefix surfel's distance to its nearest
+ * other surfel of the prefix: d_out[a] = sqrtf(min over b != a, b < p of
+ * d2(points[order[a]], points[order[b]])), a < p (binary32 with the fixed d2;
+ * +inf for p = 1); NaN everywhere if an order entry lies outside [0, n).
+ * 1 <= p <= min(n, 2^20); all pointers device memory; one kernel on `stream`.
+ */
+int bs_prefix_nn(const float* d_points, int64_t n, const int32_t* d_order, int64_t p, float* d_out,
+                 void* stream);
+
+/* The sampler over a batch plan (see bs_batch_plan_execute above). */
+int bs_batch_plan_execute_sample(bs_batch_plan* plan, const bs_sampler* params, const float* d_points,
+                                 int32_t* d_out_order, float* d_out_radius, int32_t* d_out_count,
+                                 void* d_workspace, size_t workspace_bytes, void* stream);
 
 /* -------------------------------------------------------------- serving */
 

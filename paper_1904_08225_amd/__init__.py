@@ -57,6 +57,16 @@ def tuning(kernel: int = 0, block: int = 0, per_thread: int = 0, groups: int = 0
     return Tuning(kernel, block, per_thread, groups, cell_points, picks, lead_picks, batch_wide, spin_limit)
 
 
+class Sampler(ctypes.Structure):
+    _fields_ = [("sample_size", ctypes.c_int32), ("growth_rounds", ctypes.c_int32), ("vicinity", ctypes.c_float),
+                ("reserved", ctypes.c_int32 * 5)]
+
+
+def sampler(sample_size: int = 200, growth_rounds: int = 500, vicinity: float = 0.0) -> Sampler:
+    """Sampler parameters (``bs_sampler``); the defaults are the paper's."""
+    return Sampler(int(sample_size), int(growth_rounds), float(vicinity))
+
+
 def header_functions():
     """Names of the functions declared in include/bluesurfels.h."""
     with open(HEADER) as f:
@@ -110,6 +120,16 @@ def load():
     lib.bs_order_ex.restype = i32
     lib.bs_order_profile.argtypes = [vp, i64, i64, i64, vp, vp, vp, vp, vp, vp, sz, tp, vp]
     lib.bs_order_profile.restype = i32
+    lib.bs_sampler_defaults.argtypes = []
+    lib.bs_sampler_defaults.restype = Sampler
+    lib.bs_sample_workspace_size.argtypes = [i64]
+    lib.bs_sample_workspace_size.restype = sz
+    lib.bs_sample.argtypes = [vp, i64, i64, u64, i64, ctypes.POINTER(Sampler), vp, vp, vp, vp, sz, vp]
+    lib.bs_sample.restype = i32
+    lib.bs_prefix_nn.argtypes = [vp, i64, vp, i64, vp, vp]
+    lib.bs_prefix_nn.restype = i32
+    lib.bs_batch_plan_execute_sample.argtypes = [vp, ctypes.POINTER(Sampler), vp, vp, vp, vp, vp, sz, vp]
+    lib.bs_batch_plan_execute_sample.restype = i32
     lib.bs_order_noalloc.argtypes = [vp, i64, i64, u64, i64, vp, vp, tp, vp]
     lib.bs_order_noalloc.restype = i32
     lib.bs_noalloc_max_bytes.argtypes = []
@@ -327,6 +347,53 @@ def order_noalloc(points, k: Optional[int] = None, seed: int = 0, *, start: Opti
     return out_order, out_radius
 
 
+def sample(points, k: Optional[int] = None, seed: int = 0, *, start: Optional[int] = None,
+           sample_size: int = 200, growth_rounds: int = 500, vicinity: float = 0.0, workspace=None,
+           out_order=None, out_radius=None, stream=None, check: bool = True):
+    """The paper's randomized progressive sampler (``bs_sample``, Sec. 3.2).
+
+    Returns ``(order int32[k], radius float32[k], count)``; ``count`` (picks
+    made; less than k only when ``vicinity`` removal empties the input) is read
+    back after a sync."""
+    import torch
+    lib = load()
+    points = _prep_points(points)
+    n = int(points.shape[0])
+    k = n if k is None else int(k)
+    dev = points.device
+    prm = sampler(sample_size, growth_rounds, vicinity)
+    if out_order is None:
+        out_order = torch.empty(max(k, 0), dtype=torch.int32, device=dev)
+    if out_radius is None:
+        out_radius = torch.empty(max(k, 0), dtype=torch.float32, device=dev)
+    cnt = torch.zeros(1, dtype=torch.int32, device=dev)
+    if workspace is None:
+        need = int(lib.bs_sample_workspace_size(n)) if n > 0 else 0
+        workspace = torch.empty(max(need, 1), dtype=torch.uint8, device=dev)
+    _check(lib.bs_sample(_ptr(points), n, k, ctypes.c_uint64(seed & (2**64 - 1)), -1 if start is None else int(start),
+                         ctypes.byref(prm), _ptr(out_order), _ptr(out_radius), _ptr(cnt), _ptr(workspace),
+                         int(workspace.numel()), _stream_handle(stream)))
+    count = 0
+    if k > 0:
+        torch.cuda.current_stream().synchronize() if stream is None else stream.synchronize()
+        count = int(cnt.cpu()[0])
+        if check and int(out_order[0]) == -1:
+            raise ValueError("non-finite candidate coordinates")
+    return out_order, out_radius, count
+
+
+def prefix_nn(points, order, p: int, stream=None):
+    """Each of the first ``p`` ordered surfels' distance to its nearest other
+    surfel of the prefix (``bs_prefix_nn``, the Sec. 3.3 measure): float32 [p]."""
+    import torch
+    lib = load()
+    pts = _prep_points(points)
+    o = (order if order.dtype == torch.int32 else order.to(torch.int32)).contiguous()
+    out = torch.empty(int(p), dtype=torch.float32, device=pts.device)
+    _check(lib.bs_prefix_nn(_ptr(pts), int(pts.shape[0]), _ptr(o), int(p), _ptr(out), _stream_handle(stream)))
+    return out
+
+
 def noalloc_max_bytes() -> int:
     return int(load().bs_noalloc_max_bytes())
 
@@ -466,6 +533,29 @@ class BatchPlan:
         _check(self._lib.bs_batch_plan_execute(self._plan, _ptr(points), _ptr(out_order), _ptr(out_radius),
                                                _ptr(workspace), int(workspace.numel()), _stream_handle(stream)))
         return out_order[: self.total_k], out_radius[: self.total_k]
+
+    def execute_sample(self, points, sample_size: int = 200, growth_rounds: int = 500, vicinity: float = 0.0,
+                       out_order=None, out_radius=None, out_count=None, workspace=None, stream=None):
+        """The randomized sampler (Sec. 3.2) over the plan's objects
+        (``bs_batch_plan_execute_sample``): ``(order, radius, count int32[m])``."""
+        import torch
+        points = _prep_points(points) if points.shape[0] > 0 else points
+        dev = points.device
+        if out_order is None:
+            out_order = torch.empty(max(self.total_k, 1), dtype=torch.int32, device=dev)
+        if out_radius is None:
+            out_radius = torch.empty(max(self.total_k, 1), dtype=torch.float32, device=dev)
+        if out_count is None:
+            out_count = torch.zeros(max(self.m, 1), dtype=torch.int32, device=dev)
+        if workspace is None:
+            if self._ws is None or self._ws.numel() < self.workspace_bytes:
+                self._ws = torch.empty(max(self.workspace_bytes, 1), dtype=torch.uint8, device=dev)
+            workspace = self._ws
+        prm = sampler(sample_size, growth_rounds, vicinity)
+        _check(self._lib.bs_batch_plan_execute_sample(self._plan, ctypes.byref(prm), _ptr(points), _ptr(out_order),
+                                                      _ptr(out_radius), _ptr(out_count), _ptr(workspace),
+                                                      int(workspace.numel()), _stream_handle(stream)))
+        return out_order[: self.total_k], out_radius[: self.total_k], out_count[: self.m]
 
     def close(self):
         if getattr(self, "_plan", None):

@@ -10,6 +10,7 @@
 
 #include "bs_grid.h"
 #include "bs_internal.h"
+#include "bs_sample.h"
 
 namespace bs {
 
@@ -457,6 +458,19 @@ int bs_batch_plan_execute(bs_batch_plan* plan, const float* d_points, int32_t* d
     if (!plan) return set_error(BS_ERR_INVALID_ARG, "null plan");
     return batch_plan_execute(plan->p, d_points, d_out_order, d_out_radius, d_workspace,
                               workspace_bytes, reinterpret_cast<hipStream_t>(stream));
+}
+
+int bs_batch_plan_execute_sample(bs_batch_plan* plan, const bs_sampler* params, const float* d_points,
+                                 int32_t* d_out_order, float* d_out_radius, int32_t* d_out_count,
+                                 void* d_workspace, size_t workspace_bytes, void* stream) {
+    if (!plan) return set_error(BS_ERR_INVALID_ARG, "null plan");
+    if (params)
+        for (int r : params->reserved)
+            if (r) return set_error(BS_ERR_INVALID_ARG, "sampler: reserved fields must be zero");
+    const bs_sampler p = params ? *params : bs_sampler_defaults();
+    return batch_plan_execute_sample(plan->p, p.sample_size, p.growth_rounds, p.vicinity, d_points, d_out_order,
+                                     d_out_radius, d_out_count, d_workspace, workspace_bytes,
+                                     reinterpret_cast<hipStream_t>(stream));
 }
 
 void bs_batch_plan_destroy(bs_batch_plan* plan) {

@@ -24,6 +24,7 @@
 #include "bs_grid_device.h"
 #include "bs_grid_multi.h"
 #include "bs_internal.h"
+#include "bs_sample_device.h"
 
 namespace bs {
 
@@ -470,6 +471,78 @@ __global__ void queue_reset_kernel(uint32_t* q) {
     if (threadIdx.x < 2) q[threadIdx.x] = 0u;
 }
 
+// Randomized sampler (Sec. 3.2) over the same grids: each object's sorted
+// position of every original index, and its sampler parameters.
+__global__ void bpos_kernel(const uint64_t* __restrict__ keys_s, const uint32_t* __restrict__ ids, int N,
+                            const int32_t* __restrict__ offs, int32_t* __restrict__ pos_of) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= N) return;
+    const int obj = int(keys_s[i] >> kObjBits);
+    pos_of[offs[obj] + int(ids[i])] = i;
+}
+
+struct SampleParams {
+    int S, K;
+    float vicinity;
+    int pad;
+};
+
+__global__ void bsdesc_kernel(int m, const ObjHdr* __restrict__ hd, const int32_t* __restrict__ offs,
+                              const uint64_t* __restrict__ seeds, const int32_t* __restrict__ kept,
+                              const int32_t* __restrict__ pos_of, const uint32_t* __restrict__ cellidx,
+                              SampleParams prm, int32_t* out_count, SampleSpec* __restrict__ sdesc) {
+    const int j = blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= m) return;
+    SampleSpec s{};
+    s.key0 = uint32_t(seeds[j]);
+    s.key1 = uint32_t(seeds[j] >> 32);
+    s.S = prm.S;
+    s.K = prm.K;
+    s.vicinity = prm.vicinity;
+    s.n = offs[j + 1] - offs[j];
+    s.pos_of = pos_of + offs[j];
+    s.cellidx = cellidx;
+    s.cell_base = hd[j].cell_base;
+    s.count = out_count ? out_count + kept[j] : nullptr;
+    sdesc[j] = s;
+}
+
+__global__ void fill_i32_kernel(int32_t* p, int n, int32_t v) {
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) p[i] = v;
+}
+
+// Persistent work queue of sampler runs (largest k first), one object per
+// 256-thread workgroup.
+__global__ void __launch_bounds__(kBatchBlock)
+    sample_batch_kernel(const ObjDesc* __restrict__ desc, const SampleSpec* __restrict__ sdesc,
+                        const int32_t* __restrict__ lpt, int mwork, uint32_t* __restrict__ queue) {
+    __shared__ GridLds<kBatchBlock / 64, kBatchMaxBlocks> L;
+    __shared__ SampleLds<kBatchBlock / 64> SL;
+    __shared__ int s_item;
+    for (;;) {
+        if (threadIdx.x == 0) s_item = int(atomicAdd(queue, 1u));
+        __syncthreads();
+        const int item = s_item;
+        __syncthreads();
+        if (item >= mwork) return;
+        const int j = lpt[item];
+        const GridObject o = desc[j].o;
+        const SampleSpec sp = sdesc[j];
+        if (o.k > 0) {
+            if (desc[j].nonfinite) {
+                for (int t = threadIdx.x; t < o.k; t += kBatchBlock) {
+                    o.order[t] = -1;
+                    if (o.radius) o.radius[t] = __builtin_nanf("");
+                }
+                if (threadIdx.x == 0 && sp.count) *sp.count = 0;
+            } else {
+                sample_object<kBatchBlock, kBatchMaxBlocks>(o, sp, L, SL);
+            }
+        }
+        __syncthreads();
+    }
+}
+
 // Persistent work queue: each workgroup pops objects (largest k first) until
 // the queue is drained; every pop ends the loop for all its waves alike.
 // BLOCK = 256 for most objects; the largest ones may get 1024-thread
@@ -602,6 +675,8 @@ struct BatchPlan {
     float target = 32.f;
     std::vector<int32_t> h_offs;    // m + 1
     std::vector<int32_t> h_k, h_start, h_lpt;
+    std::vector<uint64_t> h_seed;     // kept objects' seeds (the sampler's Philox keys)
+    std::vector<int32_t> h_kept;      // caller object number of each kept object (device upload)
     std::vector<int64_t> h_out_offs;  // m_all + 1 (caller's object numbering)
     std::vector<int64_t> h_outo;      // m + 1 (kept objects)
     std::vector<JobIo> h_io;          // optional per-object outputs (kept objects)
@@ -650,6 +725,10 @@ struct BatchWs {
     int32_t* lpt;
     int64_t* outo;
     JobIo* io;
+    int32_t* pos_of;
+    SampleSpec* sdesc;
+    uint64_t* seeds;
+    int32_t* kept;
     void* temp;
     size_t total;
 };
@@ -682,6 +761,10 @@ BatchWs batch_layout(const BatchPlan& p, char* base) {
     w.lpt = carve<int32_t>(base, off, m + 1);
     w.outo = carve<int64_t>(base, off, m + 1);
     w.io = carve<JobIo>(base, off, m + 1);
+    w.pos_of = carve<int32_t>(base, off, std::max<size_t>(N, 1));
+    w.sdesc = carve<SampleSpec>(base, off, m + 1);
+    w.seeds = carve<uint64_t>(base, off, m + 1);
+    w.kept = carve<int32_t>(base, off, m + 1);
     w.temp = base + off;
     off += align_up(std::max(p.sort_bytes, p.scan_bytes));
     w.total = off;
@@ -756,10 +839,12 @@ int batch_plan_create(const int64_t* h_offsets, const int64_t* h_k, const uint64
     p->total_k = p->h_out_offs[m];
     p->m = int(keep.size());
     p->kept = keep;
+    p->h_kept.assign(keep.begin(), keep.end());
     p->N = m > 0 ? int(h_offsets[m]) : 0;
     p->h_offs.resize(size_t(p->m) + 1);
     p->h_k.resize(p->m);
     p->h_start.resize(p->m);
+    p->h_seed.resize(p->m);
     std::vector<int64_t> outo(size_t(p->m) + 1);
     size_t maxC = 0, maxB = 0, maxS = 0;
     for (int i = 0; i < p->m; ++i) {
@@ -768,6 +853,7 @@ int batch_plan_create(const int64_t* h_offsets, const int64_t* h_k, const uint64
         p->h_offs[i] = int32_t(h_offsets[j]);
         p->h_k[i] = int32_t(h_k[j]);
         p->h_start[i] = int32_t(bs_start_index(h_seed ? h_seed[j] : 0, n));
+        p->h_seed[i] = h_seed ? h_seed[j] : 0;
         outo[i] = p->h_out_offs[j];
         const double cap = std::min(std::max(1.0, double(n) / double(p->target)), double(64 * kBatchMaxBlocks));
         const size_t c = size_t(cap);
@@ -957,6 +1043,46 @@ int batch_plan_execute(BatchPlan* p, const float* pts, int32_t* out_order, float
     }
     if (p->nwide > 0 && (e = hipStreamWaitEvent(st, p->join, 0)) != hipSuccess)
         return set_error(BS_ERR_HIP, "join: %s", hipGetErrorString(e));
+    return BS_OK;
+}
+
+int batch_plan_execute_sample(BatchPlan* p, int S, int K, float vicinity, const float* pts, int32_t* out_order,
+                              float* out_radius, int32_t* out_count, void* ws, size_t ws_bytes, hipStream_t st) {
+    if (!p) return set_error(BS_ERR_INVALID_ARG, "null plan");
+    if (S < 0 || S > kSampleMaxSlots || K == 0 || !(vicinity >= 0.f) || (S == 0 && vicinity > 0.f))
+        return set_error(BS_ERR_INVALID_ARG, "sampler: sample size %d (0..%d), growth %d (>= 1 or < 0), vicinity %g",
+                         S, kSampleMaxSlots, K, double(vicinity));
+    std::lock_guard<std::mutex> lk(p->mu);
+    hipError_t e = hipSuccess;
+    if (out_count && p->m_all > 0) {  // objects with no work made no picks
+        hipLaunchKernelGGL(fill_i32_kernel, dim3(std::min((p->m_all + 255) / 256, 1024)), dim3(256), 0, st,
+                           out_count, p->m_all, 0);
+        if ((e = hipGetLastError()) != hipSuccess) return set_error(BS_ERR_HIP, "%s", hipGetErrorString(e));
+    }
+    if (p->mwork == 0) return BS_OK;
+    BatchWs w;
+    const int rc = batch_preprocess(p, pts, out_order, out_radius, ws, ws_bytes, st, w);
+    if (rc != BS_OK) return rc;
+    const int m = p->m, N = p->N, tb = 256;
+    e = hipMemcpyAsync(w.seeds, p->h_seed.data(), size_t(m) * 8, hipMemcpyHostToDevice, st);
+    if (e == hipSuccess) e = hipMemcpyAsync(w.kept, p->h_kept.data(), size_t(m) * 4, hipMemcpyHostToDevice, st);
+    if (e != hipSuccess) return set_error(BS_ERR_HIP, "sampler upload: %s", hipGetErrorString(e));
+    hipLaunchKernelGGL(bpos_kernel, dim3((N + tb - 1) / tb), dim3(tb), 0, st, w.keys_s, w.ids, N, w.offs, w.pos_of);
+    SampleParams prm{S, K, vicinity, 0};
+    hipLaunchKernelGGL(bsdesc_kernel, dim3((m + tb - 1) / tb), dim3(tb), 0, st, m, w.hd, w.offs, w.seeds, w.kept,
+                       w.pos_of, w.cellidx, prm, out_count, w.sdesc);
+    hipLaunchKernelGGL(queue_reset_kernel, dim3(1), dim3(64), 0, st, w.queue);
+    int dev = 0, cus = 0, per = 0;
+    (void)hipGetDevice(&dev);
+    (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, reinterpret_cast<const void*>(sample_batch_kernel),
+                                                       kBatchBlock, 0);
+    if (cus <= 0) cus = 256;
+    if (per <= 0) per = 1;
+    const int slots = std::max(1, std::min(cus * per, p->mwork));
+    hipLaunchKernelGGL(sample_batch_kernel, dim3(slots), dim3(kBatchBlock), 0, st, w.desc, w.sdesc, w.lpt, p->mwork,
+                       w.queue);
+    if ((e = hipGetLastError()) != hipSuccess) return set_error(BS_ERR_HIP, "sampler launch: %s", hipGetErrorString(e));
     return BS_OK;
 }
 

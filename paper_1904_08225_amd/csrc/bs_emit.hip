@@ -136,7 +136,62 @@ __global__ void __launch_bounds__(kNnBlock)
         *out_rm = s_bad ? __builtin_nanf("") : ((pm & 1) ? nn[pm / 2] : 0.5f * (nn[pm / 2 - 1] + nn[pm / 2]));
 }
 
+// Each of the first p ordered surfels' distance to its nearest other surfel
+// of the prefix (Sec. 3.3): one thread per prefix surfel, the prefix staged
+// through LDS a tile at a time.  Any order entry outside [0, n) makes every
+// output NaN.
+constexpr int kPnnBlock = 256;
+
+__global__ void __launch_bounds__(kPnnBlock)
+    prefix_nn_kernel(const float* __restrict__ pts, int64_t n, const int32_t* __restrict__ order, int p,
+                     float* __restrict__ out) {
+    __shared__ float tx[kPnnBlock], ty[kPnnBlock], tz[kPnnBlock];
+    __shared__ int s_bad;
+    const int a = blockIdx.x * kPnnBlock + threadIdx.x;
+    if (threadIdx.x == 0) s_bad = 0;
+    float ax = 0.f, ay = 0.f, az = 0.f;
+    if (a < p) {
+        const int64_t i = order[a];
+        if (i >= 0 && i < n) {
+            ax = pts[3 * i + 0];
+            ay = pts[3 * i + 1];
+            az = pts[3 * i + 2];
+        }
+    }
+    float m = INFINITY;
+    for (int base = 0; base < p; base += kPnnBlock) {
+        __syncthreads();
+        const int b = base + threadIdx.x;
+        if (b < p) {
+            const int64_t i = order[b];
+            if (i < 0 || i >= n) {
+                s_bad = 1;
+                tx[threadIdx.x] = ty[threadIdx.x] = tz[threadIdx.x] = 0.f;
+            } else {
+                tx[threadIdx.x] = pts[3 * i + 0];
+                ty[threadIdx.x] = pts[3 * i + 1];
+                tz[threadIdx.x] = pts[3 * i + 2];
+            }
+        }
+        __syncthreads();
+        const int cnt = p - base < kPnnBlock ? p - base : kPnnBlock;
+        for (int j = 0; j < cnt; ++j) {
+            const float d = sq_dist(ax, ay, az, tx[j], ty[j], tz[j]);
+            m = (base + j != a && d < m) ? d : m;
+        }
+    }
+    __syncthreads();
+    if (a < p) out[a] = s_bad ? __builtin_nanf("") : sqrtf(m);
+}
+
 }  // namespace
+
+hipError_t launch_prefix_nn(const float* pts, int64_t n, const int32_t* order, int p, float* out, hipStream_t st) {
+    if (p < 1) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(prefix_nn_kernel, dim3((p + kPnnBlock - 1) / kPnnBlock), dim3(kPnnBlock), 0, st, pts, n,
+                       order, p, out);
+    return hipGetLastError();
+}
 
 hipError_t launch_emit(const float* pts, const float* nrm, const uint8_t* col, int64_t n, const int32_t* order,
                        int64_t k, void* out, hipStream_t st) {

@@ -32,6 +32,7 @@
 #include "bs_grid_device.h"
 #include "bs_grid_multi.h"
 #include "bs_internal.h"
+#include "bs_sample_device.h"
 
 namespace bs {
 namespace {
@@ -293,6 +294,36 @@ __global__ void __launch_bounds__(BLOCK) grid_multi_kernel(GridObject o, const D
     grid_order_object_mp<BLOCK, MAXB>(obj, L);
 }
 
+// pos_of[id] = sorted position of candidate id
+__global__ void position_kernel(const uint32_t* __restrict__ ids, int n, int32_t* __restrict__ pos_of) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) pos_of[ids[i]] = i;
+}
+
+// The paper's randomized sampler (Sec. 3.2) on one object's grid.
+template <int BLOCK, int MAXB>
+__global__ void __launch_bounds__(BLOCK) sample_single_kernel(GridObject o, SampleSpec sp, const DevHeader* hdr,
+                                                              const GridHeader* gh) {
+    __shared__ GridLds<BLOCK / 64, MAXB> L;
+    __shared__ SampleLds<BLOCK / 64> SL;
+    GridObject obj = o;
+    if (o.k <= 0) return;
+    if (hdr->nonfinite) {
+        for (int t = threadIdx.x; t < o.k; t += BLOCK) {
+            o.order[t] = -1;
+            if (o.radius) o.radius[t] = __builtin_nanf("");
+        }
+        if (threadIdx.x == 0 && sp.count) *sp.count = 0;
+        return;
+    }
+    obj.C = gh->C;
+    obj.B = gh->B;
+    obj.NB = gh->NB;
+    obj.start_pos = gh->start_pos;
+    obj.start_cell = gh->start_cell;
+    sample_object<BLOCK, MAXB>(obj, sp, L, SL);
+}
+
 }  // namespace
 
 // ------------------------------------------------------------ host side
@@ -377,71 +408,166 @@ int grid_max_blocks(int block, int picks) {
     return block == 512 ? 4096 : 1024;
 }
 
+namespace {
+
+// Pieces of one object's grid workspace.
+struct GridPieces {
+    DevHeader* hdr;
+    GridHeader* gh;
+    uint32_t *codes, *vals, *codes_s, *ids, *flags, *cellidx;
+    int32_t* cstart;
+    float4 *xyzm, *cstat, *bstat, *sbstat;
+    uint4 *cdyn, *bdyn;
+    void* temp;
+    char* lead_slots;
+};
+
+GridPieces grid_pieces(int n, int block, void* ws) {
+    const GridLayout g = grid_layout(n, block);
+    char* base = static_cast<char*>(ws);
+    GridPieces q;
+    q.hdr = reinterpret_cast<DevHeader*>(base + g.dev_header);
+    q.gh = reinterpret_cast<GridHeader*>(base + g.grid_header);
+    q.codes = reinterpret_cast<uint32_t*>(base + g.codes);
+    q.vals = reinterpret_cast<uint32_t*>(base + g.vals);
+    q.codes_s = reinterpret_cast<uint32_t*>(base + g.codes_sorted);
+    q.ids = reinterpret_cast<uint32_t*>(base + g.ids);
+    q.flags = reinterpret_cast<uint32_t*>(base + g.flags);
+    q.cellidx = reinterpret_cast<uint32_t*>(base + g.cellidx);
+    q.cstart = reinterpret_cast<int32_t*>(base + g.cstart);
+    q.xyzm = reinterpret_cast<float4*>(base + g.xyzm);
+    q.cstat = reinterpret_cast<float4*>(base + g.cstat);
+    q.cdyn = reinterpret_cast<uint4*>(base + g.cdyn);
+    q.bstat = reinterpret_cast<float4*>(base + g.bstat);
+    q.bdyn = reinterpret_cast<uint4*>(base + g.bdyn);
+    q.sbstat = reinterpret_cast<float4*>(base + g.sbstat);
+    q.temp = base + g.temp;
+    q.lead_slots = base + g.lead_slots;
+    return q;
+}
+
+// First half of the grid build: header, validation, Morton codes and their
+// sort, the cell level, cell flags and cell indices.
+hipError_t grid_build_sort(const float* pts, int n, const GridPieces& q, size_t temp_bytes, float target,
+                           int max_blocks, hipStream_t st) {
+    hipError_t e = launch_init_header(q.hdr, st);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(init_grid_header_kernel, dim3(1), dim3(64), 0, st, q.gh);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    if ((e = launch_validate(pts, n, q.hdr, st)) != hipSuccess) return e;
+    const int tb = 256;
+    const int nblk = (n + tb - 1) / tb;
+    hipLaunchKernelGGL(morton_kernel, dim3(nblk), dim3(tb), 0, st, pts, n, q.hdr, q.codes, q.vals);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    size_t tbytes = temp_bytes;
+    e = hipcub::DeviceRadixSort::SortPairs(q.temp, tbytes, q.codes, q.codes_s, q.vals, q.ids, n, 0,
+                                           3 * kMortonBits, st);
+    if (e != hipSuccess) return e;
+    const int hblk = nblk < 1024 ? nblk : 1024;
+    hipLaunchKernelGGL(level_hist_kernel, dim3(hblk), dim3(tb), 0, st, q.codes_s, n, q.gh);
+    hipLaunchKernelGGL(choose_level_kernel, dim3(1), dim3(64), 0, st, n, q.gh, target, max_blocks);
+    hipLaunchKernelGGL(cell_flag_kernel, dim3(nblk), dim3(tb), 0, st, q.codes_s, n, q.gh, q.flags);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    tbytes = temp_bytes;
+    return hipcub::DeviceScan::InclusiveSum(q.temp, tbytes, q.flags, q.cellidx, n, st);
+}
+
+// Second half: the sorted candidates (with m from a leading scan, or +inf),
+// cell records, blocks and superblocks.
+hipError_t grid_build_cells(const float* pts, int n, int start, const GridPieces& q, const float* m_lead,
+                            hipStream_t st) {
+    const int tb = 256;
+    const int nblk = (n + tb - 1) / tb;
+    hipLaunchKernelGGL(gather_kernel, dim3(nblk), dim3(tb), 0, st, pts, q.ids, q.flags, q.cellidx, n, start,
+                       q.gh, q.xyzm, q.cstart, m_lead);
+    hipLaunchKernelGGL(cell_build_kernel, dim3(nblk), dim3(tb), 0, st, q.cstart, n, q.gh, q.xyzm, q.ids, q.cstat,
+                       q.cdyn);
+    hipLaunchKernelGGL(block_build_kernel, dim3((kMaxBlocksAny + tb - 1) / tb), dim3(tb), 0, st, q.gh, q.cstat,
+                       q.cdyn, q.bstat, q.bdyn);
+    hipLaunchKernelGGL(superblock_build_kernel, dim3(1), dim3(64), 0, st, q.gh, q.bstat, q.sbstat);
+    return hipGetLastError();
+}
+
+}  // namespace
+
+hipError_t launch_grid_sample(const float* pts, int n, int k, int start, uint64_t seed, int S, int K,
+                              float vicinity, int32_t* order, float* radius, int32_t* count, void* ws,
+                              float target, uint64_t* ticks, hipStream_t st, const LaunchOpts* ev) {
+    constexpr int kBlock = 1024, kMaxB = 1024;
+    const GridLayout g = grid_layout(n, kBlock);
+    const GridPieces q = grid_pieces(n, kBlock, ws);
+    hipError_t e = grid_build_sort(pts, n, q, g.temp_bytes, target, kMaxB, st);
+    if (e != hipSuccess) return e;
+    if ((e = grid_build_cells(pts, n, start, q, nullptr, st)) != hipSuccess) return e;
+    // the unsorted Morton values are dead after the sort: each candidate's sorted position
+    int32_t* pos_of = reinterpret_cast<int32_t*>(q.vals);
+    hipLaunchKernelGGL(position_kernel, dim3((n + 255) / 256), dim3(256), 0, st, q.ids, n, pos_of);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    GridObject o{};
+    o.k = k;
+    o.start_id = uint32_t(start);
+    o.xyzm = q.xyzm;
+    o.ids = q.ids;
+    o.cstat = q.cstat;
+    o.cdyn = q.cdyn;
+    o.bstat = q.bstat;
+    o.bdyn = q.bdyn;
+    o.sbstat = q.sbstat;
+    o.order = order;
+    o.radius = radius;
+    o.ticks = ticks;
+    o.max_picks = 1;
+    o.t0 = 0;
+    o.start_m = INFINITY;
+    SampleSpec sp{};
+    sp.key0 = uint32_t(seed);
+    sp.key1 = uint32_t(seed >> 32);
+    sp.S = S;
+    sp.K = K;
+    sp.vicinity = vicinity;
+    sp.n = n;
+    sp.pos_of = pos_of;
+    sp.cellidx = q.cellidx;
+    sp.cell_base = 0;
+    sp.count = count;
+    if (ev && ev->begin && (e = hipEventRecord(ev->begin, st)) != hipSuccess) return e;
+    hipLaunchKernelGGL((sample_single_kernel<kBlock, kMaxB>), dim3(1), dim3(kBlock), 0, st, o, sp, q.hdr, q.gh);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    if (ev && ev->end) e = hipEventRecord(ev->end, st);
+    return e;
+}
+
 hipError_t launch_grid(const float* pts, int n, int k, int start, int32_t* order, float* radius,
                        void* ws, float target, int block, int picks, uint64_t* ticks,
                        hipStream_t st, const LaunchOpts* ev, int lead, const ScanShape* lead_shape) {
     if (picks <= 1 || !lead_shape || lead < 2) lead = 0;
     if (lead > k) lead = k;
     const GridLayout g = grid_layout(n, block);
-    char* base = static_cast<char*>(ws);
-    DevHeader* hdr = reinterpret_cast<DevHeader*>(base + g.dev_header);
-    GridHeader* gh = reinterpret_cast<GridHeader*>(base + g.grid_header);
-    uint32_t* codes = reinterpret_cast<uint32_t*>(base + g.codes);
-    uint32_t* vals = reinterpret_cast<uint32_t*>(base + g.vals);
-    uint32_t* codes_s = reinterpret_cast<uint32_t*>(base + g.codes_sorted);
-    uint32_t* ids = reinterpret_cast<uint32_t*>(base + g.ids);
-    uint32_t* flags = reinterpret_cast<uint32_t*>(base + g.flags);
-    uint32_t* cellidx = reinterpret_cast<uint32_t*>(base + g.cellidx);
-    int32_t* cstart = reinterpret_cast<int32_t*>(base + g.cstart);
-    float4* xyzm = reinterpret_cast<float4*>(base + g.xyzm);
-    float4* cstat = reinterpret_cast<float4*>(base + g.cstat);
-    uint4* cdyn = reinterpret_cast<uint4*>(base + g.cdyn);
-    float4* bstat = reinterpret_cast<float4*>(base + g.bstat);
-    uint4* bdyn = reinterpret_cast<uint4*>(base + g.bdyn);
-    float4* sbstat = reinterpret_cast<float4*>(base + g.sbstat);
-    void* temp = base + g.temp;
+    const GridPieces q = grid_pieces(n, block, ws);
+    DevHeader* hdr = q.hdr;
+    GridHeader* gh = q.gh;
+    float4* xyzm = q.xyzm;
+    uint32_t* ids = q.ids;
+    float4* cstat = q.cstat;
+    uint4* cdyn = q.cdyn;
+    float4* bstat = q.bstat;
+    uint4* bdyn = q.bdyn;
+    float4* sbstat = q.sbstat;
 
-    hipError_t e = launch_init_header(hdr, st);
-    if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(init_grid_header_kernel, dim3(1), dim3(64), 0, st, gh);
-    if ((e = hipGetLastError()) != hipSuccess) return e;
-    if ((e = launch_validate(pts, n, hdr, st)) != hipSuccess) return e;
-    const int tb = 256;
-    const int nblk = (n + tb - 1) / tb;
-    hipLaunchKernelGGL(morton_kernel, dim3(nblk), dim3(tb), 0, st, pts, n, hdr, codes, vals);
-    if ((e = hipGetLastError()) != hipSuccess) return e;
-    size_t tbytes = g.temp_bytes;
-    e = hipcub::DeviceRadixSort::SortPairs(temp, tbytes, codes, codes_s, vals, ids, n, 0,
-                                           3 * kMortonBits, st);
-    if (e != hipSuccess) return e;
-    const int hblk = nblk < 1024 ? nblk : 1024;
-    hipLaunchKernelGGL(level_hist_kernel, dim3(hblk), dim3(tb), 0, st, codes_s, n, gh);
-    hipLaunchKernelGGL(choose_level_kernel, dim3(1), dim3(64), 0, st, n, gh, target,
-                       grid_max_blocks(block, picks));
-    hipLaunchKernelGGL(cell_flag_kernel, dim3(nblk), dim3(tb), 0, st, codes_s, n, gh, flags);
-    if ((e = hipGetLastError()) != hipSuccess) return e;
-    tbytes = g.temp_bytes;
-    e = hipcub::DeviceScan::InclusiveSum(temp, tbytes, flags, cellidx, n, st);
+    hipError_t e = grid_build_sort(pts, n, q, g.temp_bytes, target, grid_max_blocks(block, picks), st);
     if (e != hipSuccess) return e;
     float* m_lead = nullptr;
     if (lead >= 2) {
         // picks 0 .. lead-1 by the cooperative full scan; its m values land in
         // the (now unused) unsorted Morton codes, its last pick in the header
-        m_lead = reinterpret_cast<float*>(codes);
+        m_lead = reinterpret_cast<float*>(q.codes);
         LaunchOpts lo;  // the events bracket the grid kernel; the wait limit applies here
         lo.spin_limit = ev ? ev->spin_limit : 0;
-        e = launch_scan(*lead_shape, pts, n, k, start, order, radius, hdr, base + g.lead_slots, ticks, st,
-                        &lo, lead, m_lead, &gh->lead_id);
+        e = launch_scan(*lead_shape, pts, n, k, start, order, radius, hdr, q.lead_slots, ticks, st, &lo, lead,
+                        m_lead, &gh->lead_id);
         if (e != hipSuccess) return e;
     }
-    hipLaunchKernelGGL(gather_kernel, dim3(nblk), dim3(tb), 0, st, pts, ids, flags, cellidx, n, start,
-                       gh, xyzm, cstart, m_lead);
-    hipLaunchKernelGGL(cell_build_kernel, dim3(nblk), dim3(tb), 0, st, cstart, n, gh, xyzm, ids, cstat,
-                       cdyn);
-    hipLaunchKernelGGL(block_build_kernel, dim3((kMaxBlocksAny + tb - 1) / tb), dim3(tb), 0, st, gh,
-                       cstat, cdyn, bstat, bdyn);
-    hipLaunchKernelGGL(superblock_build_kernel, dim3(1), dim3(64), 0, st, gh, bstat, sbstat);
-    if ((e = hipGetLastError()) != hipSuccess) return e;
+    if ((e = grid_build_cells(pts, n, start, q, m_lead, st)) != hipSuccess) return e;
 
     GridObject o{};
     o.k = k;

@@ -171,7 +171,9 @@ constexpr int kUnroll = 8;  // members per lane in flight
 
 // Update members start + s, start + s + G, ... (< start + count) of one cell
 // with the pick, U of them in flight per lane; track the lane's best key.
-template <int U>
+// UPD = false only marks the candidate at c_pos as taken (a removal that is
+// not a pick) and recomputes the best key; no distance changes.
+template <int U, bool UPD = true>
 __device__ __forceinline__ void member_batches(float4* __restrict__ xyzm,
                                                const uint32_t* __restrict__ ids, int start,
                                                int count, int s, int G, int c_pos, float cx,
@@ -196,7 +198,7 @@ __device__ __forceinline__ void member_batches(float4* __restrict__ xyzm,
             const bool pick = ok[u] && pos[u] == c_pos;
             const bool live = ok[u] && !pick && p[u].w >= 0.f;
             const float d = dist2(p[u].x, p[u].y, p[u].z, cx, cy, cz);
-            const bool dec = live && d < p[u].w;
+            const bool dec = UPD && live && d < p[u].w;
             const float m = dec ? d : p[u].w;
             if (dec || (pick && p[u].w != -1.f)) xyzm[pos[u]].w = pick ? -1.f : d;
             const uint64_t kk = live ? make_key(m, id[u]) : 0ull;
@@ -212,7 +214,7 @@ __device__ __forceinline__ void member_batches(float4* __restrict__ xyzm,
 // aligned group of 64 / 2^ceil(log2 nh) lanes.  Wave-local: no barrier.
 // Loads are issued unconditionally (clamped to a valid address) so that a
 // batch of them is in flight together.
-template <class Lds>
+template <class Lds, bool UPD = true>
 __device__ inline void process_block(const GridObject& o, Lds& L, int b, int c_pos, int c_cell,
                               float cx, float cy, float cz, float mc, int prof_t) {
     (void)prof_t;
@@ -265,9 +267,9 @@ __device__ inline void process_block(const GridObject& o, Lds& L, int b, int c_p
     const int per = count > s ? (count - s + G - 1) >> gshift : 0;
     const int maxper = __builtin_amdgcn_readfirstlane(int(wave_max_key(uint64_t(per) << 32) >> 32));
     if (maxper <= 2)
-        member_batches<2>(xyzm, ids, start, count, s, G, c_pos, cx, cy, cz, lk, lw);
+        member_batches<2, UPD>(xyzm, ids, start, count, s, G, c_pos, cx, cy, cz, lk, lw);
     else
-        member_batches<kUnroll>(xyzm, ids, start, count, s, G, c_pos, cx, cy, cz, lk, lw);
+        member_batches<kUnroll, UPD>(xyzm, ids, start, count, s, G, c_pos, cx, cy, cz, lk, lw);
     BS_PROF(9);
 
     if (nh == 1) {
