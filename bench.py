@@ -261,6 +261,74 @@ def bench_config1(bs, torch, np, cpu=True):
     return rec
 
 
+def prefix_quality(bs, torch, pts, orders, prefixes=(1000, 5000, 10000)):
+    """Sec. 3.3's measure: each prefix surfel's distance to its nearest other
+    surfel of the prefix (bs_prefix_nn), min / median / mean relative to the
+    part's bounding-box diagonal, per ordering and prefix length."""
+    lo = pts.min(0).values
+    hi = pts.max(0).values
+    diag = float(torch.linalg.vector_norm((hi - lo).double()))
+    out = {}
+    for name, o in orders.items():
+        rows = {}
+        for p in prefixes:
+            if p > o.shape[0]:
+                continue
+            nn = bs.prefix_nn(pts, o, p).double() / diag
+            rows[str(p)] = {"min": float(nn.min()), "median": float(nn.median()), "mean": float(nn.mean())}
+        out[name] = rows
+    return {"bbox_diagonal": diag, "relative_nn_distance": out,
+            "note": "nearest-neighbour distance inside each prefix / bounding-box diagonal (Sec. 3.3 compares "
+                    "orderings by the minimum relative point distances of their prefixes)"}
+
+
+def bench_sampler(bs, torch, np, pts, exact_order, cpu=True):
+    """The paper's randomized sampler (Sec. 3.2, 200 samples per round, one
+    more pick every 500 rounds) on the headline part, k = 262,144: ms per
+    run (HIP events, inputs resident), and its prefixes against the exact
+    ordering's and a random subset's (Sec. 3.3)."""
+    n = int(pts.shape[0])
+    k = int(exact_order.shape[0])
+    dev = pts.device
+    seed = SEED_MAIN
+    ws = torch.empty(max(bs.load().bs_sample_workspace_size(n), 1), dtype=torch.uint8, device=dev)
+    oo = torch.empty(k, dtype=torch.int32, device=dev)
+    rr = torch.empty(k, dtype=torch.float32, device=dev)
+    o, r, c = bs.sample(pts, k, seed=seed, workspace=ws, out_order=oo, out_radius=rr)  # warm-up
+    stream = torch.cuda.current_stream()
+    b, e = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    reps = 2
+    b.record(stream)
+    for _ in range(reps):
+        bs.sample(pts, k, seed=seed, workspace=ws, out_order=oo, out_radius=rr, check=False)
+    e.record(stream)
+    torch.cuda.synchronize()
+    secs = b.elapsed_time(e) / 1e3 / reps
+    g = torch.Generator(device=dev)
+    g.manual_seed(12345)
+    rnd = torch.randperm(n, generator=g, device=dev)[:k].to(torch.int32)
+    rec = {"workload": "cad_part n=4,194,304 k=262,144 (the headline part), seed %d" % seed,
+           "params": {"sample_size": 200, "growth_rounds": 500, "vicinity": 0.0},
+           "seconds": secs, "ordered_surfels_per_s": k / secs, "picks_made": int(c),
+           "exact_ordering_seconds": None,
+           "kernel": "sample_single_kernel<1024,1024>: one workgroup, grid-pruned exact distances, one update "
+                     "pass per pick",
+           "quality": prefix_quality(bs, torch, pts, {"greedy_permutation": exact_order, "sampler": oo,
+                                                      "random": rnd})}
+    if cpu:
+        import oracle
+        host = pts.cpu().numpy()
+        kk = 1500
+        t0 = time.perf_counter()
+        eo, _, _ = oracle.sample32(host, kk, seed, bs.start_index(seed, n))
+        cs = time.perf_counter() - t0
+        rec["matches_oracle_prefix"] = bool(np.array_equal(eo, oo[:kk].cpu().numpy()))
+        rec["cpu_oracle"] = {"kind": "oracle", "cores": 1, "value": kk / cs, "unit": "ordered surfels/s",
+                             "sample": "oracle/bs_oracle.c oracle_sample32 (plain O(n) distance update per pick, "
+                                       "1 thread): the first %d picks of the same run, %.1f s" % (kk, cs)}
+    return rec
+
+
 def bench_full_scan(bs, torch, pts, k):
     tune = bs.tuning(kernel=bs.KERNEL_COOP, block=1024, per_thread=16)
     n = int(pts.shape[0])
@@ -308,6 +376,18 @@ def bench_batched(bs, torch, np, cpu=True):
     torch.cuda.synchronize()
     batch_s = (time.perf_counter() - t) / reps
     log("batched: %.3f s for sum k = %d" % (batch_s, plan.total_k))
+    # the same objects through the paper's randomized sampler (one persistent launch)
+    so, sr, sc = plan.execute_sample(pts)
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    so, sr, sc = plan.execute_sample(pts)
+    torch.cuda.synchronize()
+    sample_s = time.perf_counter() - t
+    log("batched sampler: %.3f s for sum k = %d" % (sample_s, int(sc.sum())))
+    sampler_rec = {"seconds": sample_s, "ordered_surfels_per_s": int(sc.sum()) / sample_s,
+                   "params": {"sample_size": 200, "growth_rounds": 500, "vicinity": 0.0},
+                   "kernel": "sample_batch_kernel: 256-thread workgroups, objects largest k first"}
+    del so, sr, sc
     # plain loop: one ordering launch per object, sampled across the size range
     order_idx = sorted(range(m), key=lambda j: sizes[j])
     sample = order_idx[:: max(1, m // 24)]
@@ -336,7 +416,8 @@ def bench_batched(bs, torch, np, cpu=True):
             "plain_loop_ordered_surfels_per_s": plain_rate,
             "plain_loop_sample": "%d objects spread over the size range, %d picks, %.1f s" % (len(sample), sk, sample_s),
             "plain_loop_estimated_seconds": plain_est_s, "speedup_vs_plain": plain_est_s / batch_s,
-            "largest_object_k": max(ks), "spot_check_equal_alone": same, "cpu_oracle": cpu_rec}
+            "largest_object_k": max(ks), "spot_check_equal_alone": same, "cpu_oracle": cpu_rec,
+            "randomized_sampler": sampler_rec}
 
 
 def bench_scene(bs, torch, np, cpu=True):
@@ -535,6 +616,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-full-scan", action="store_true")
     ap.add_argument("--no-config1", action="store_true")
+    ap.add_argument("--no-sampler", action="store_true")
     ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--no-serve", action="store_true")
     ap.add_argument("--no-scene", action="store_true")
@@ -655,6 +737,10 @@ def main():
     rec["emit"] = bench_emit(bs, torch, surf, pts, out_o)
     log("emit: %.1f us for %d records (%.0f GB/s algorithmic); r_m in %.1f us"
         % (rec["emit"]["seconds"] * 1e6, k, rec["emit"]["achieved_GBs"], rec["emit"]["median_nn_seconds"] * 1e6))
+    if not args.no_sampler:
+        rec["sampler"] = bench_sampler(bs, torch, np, pts, out_o, cpu=not args.no_cpu_baseline)
+        rec["sampler"]["exact_ordering_seconds"] = ms / 1e3
+        log("sampler: %.3f s for %d picks (exact ordering %.1f ms)" % (rec["sampler"]["seconds"], k, ms))
     if not args.no_full_scan:
         fs, fo = bench_full_scan(bs, torch, pts, k)
         fs["matches_ordering_kernel"] = bool(torch.equal(fo, out_o))
