@@ -464,6 +464,55 @@ int bs_batch_plan_execute_sample(bs_batch_plan* plan, const bs_sampler* params, 
                                  int32_t* d_out_order, float* d_out_radius, int32_t* d_out_count,
                                  void* d_workspace, size_t workspace_bytes, void* stream);
 
+/* ------------------------------ hierarchical generation (paper Sec. 3.4) */
+
+/*
+ * Bottom-up generation over a scene hierarchy (Sec. 3.4): the paper makes one
+ * approximation per complex subtree and, bottom-up, takes the surfels already
+ * chosen for a node's children as that node's initial candidates.  Here node
+ * j's candidates are, for a leaf (a node no other node names as parent), its
+ * own rows h_leaf_offsets[j] .. h_leaf_offsets[j+1]-1 of d_points; for an
+ * inner node, the k picks of each child, children in increasing node order,
+ * each child's picks in order.  Every node is then ordered like a batch object
+ * (exact greedy, or the randomized sampler), so node j's picks equal
+ * bs_order (or bs_sample) with seed h_seed[j] on that candidate array.  Nodes
+ * of equal depth form one batched launch (a single node: the single-object
+ * path over all CUs); depths run leaves first.
+ *   m               nodes, numbered so that a parent comes after its children
+ *   h_parent        host int32[m]: the parent, or -1
+ *   h_leaf_offsets  host int64[m+1], non-decreasing from 0: leaves' rows (inner nodes
+ *                   have empty ranges); total < 2^31
+ *   h_k             host int64[m]: picks of node j, 0 <= k_j <= its candidate count
+ *                   (the paper's budget for a subtree of T triangles is min(200,000, T/2))
+ *   h_seed          host uint64[m] or NULL (0)
+ *   tuning          NULL or as bs_batch_plan_create (cell_points, batch_wide)
+ * Errors: BS_ERR_INVALID_ARG (a parent before its child, k outside its range,
+ * rows given for an inner node, sizes), BS_ERR_UNSUPPORTED, BS_ERR_HIP.
+ */
+typedef struct bs_hier_plan bs_hier_plan;
+int bs_hier_plan_create(int32_t m, const int32_t* h_parent, const int64_t* h_leaf_offsets, const int64_t* h_k,
+                        const uint64_t* h_seed, const bs_tuning* tuning, bs_hier_plan** out_plan);
+/* Device workspace bytes bs_hier_plan_execute needs (256-byte aligned). */
+size_t bs_hier_workspace_size(const bs_hier_plan* plan);
+/* Sum of k over the nodes (length of the outputs). */
+int64_t bs_hier_total_k(const bs_hier_plan* plan);
+/* Writes the m+1 output offsets (exclusive prefix sum of h_k) to host memory. */
+int bs_hier_out_offsets(const bs_hier_plan* plan, int64_t* h_out_offsets);
+/*
+ * Enqueue the generation on `stream`.  Node j's picks go to rows
+ * out_off[j] .. out_off[j]+k_j-1 of d_out_order (indices into the node's own
+ * candidate array), d_out_radius (NULL allowed) and d_out_source (device
+ * int32[total_k]: the row of d_points each pick came from, so that normals
+ * and colours of the original candidates follow the surfel up the tree).
+ * sampler NULL = exact greedy; else the randomized sampler with those
+ * parameters.  A node whose candidates hold a non-finite coordinate gets
+ * order -1 and source -1, and so do its ancestors.
+ */
+int bs_hier_plan_execute(bs_hier_plan* plan, const float* d_points, const bs_sampler* sampler,
+                         int32_t* d_out_order, float* d_out_radius, int32_t* d_out_source, void* d_workspace,
+                         size_t workspace_bytes, void* stream);
+void bs_hier_plan_destroy(bs_hier_plan* plan);
+
 /* -------------------------------------------------------------- serving */
 
 /*

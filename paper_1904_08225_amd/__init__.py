@@ -130,6 +130,18 @@ def load():
     lib.bs_prefix_nn.restype = i32
     lib.bs_batch_plan_execute_sample.argtypes = [vp, ctypes.POINTER(Sampler), vp, vp, vp, vp, vp, sz, vp]
     lib.bs_batch_plan_execute_sample.restype = i32
+    lib.bs_hier_plan_create.argtypes = [ctypes.c_int32, vp, vp, vp, vp, tp, ctypes.POINTER(vp)]
+    lib.bs_hier_plan_create.restype = i32
+    lib.bs_hier_workspace_size.argtypes = [vp]
+    lib.bs_hier_workspace_size.restype = sz
+    lib.bs_hier_total_k.argtypes = [vp]
+    lib.bs_hier_total_k.restype = i64
+    lib.bs_hier_out_offsets.argtypes = [vp, vp]
+    lib.bs_hier_out_offsets.restype = i32
+    lib.bs_hier_plan_execute.argtypes = [vp, vp, ctypes.POINTER(Sampler), vp, vp, vp, vp, sz, vp]
+    lib.bs_hier_plan_execute.restype = i32
+    lib.bs_hier_plan_destroy.argtypes = [vp]
+    lib.bs_hier_plan_destroy.restype = None
     lib.bs_order_noalloc.argtypes = [vp, i64, i64, u64, i64, vp, vp, tp, vp]
     lib.bs_order_noalloc.restype = i32
     lib.bs_noalloc_max_bytes.argtypes = []
@@ -560,6 +572,68 @@ class BatchPlan:
     def close(self):
         if getattr(self, "_plan", None):
             self._lib.bs_batch_plan_destroy(self._plan)
+            self._plan = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class HierPlan:
+    """Bottom-up generation over a scene hierarchy (``bs_hier_plan_*``, Sec. 3.4).
+
+    ``parents``: int [m] (-1 for roots; a parent after its children);
+    ``leaf_offsets``: int [m+1] rows of each leaf in the candidate array
+    (inner nodes empty); ``ks``: picks per node; ``seeds``: [m] or None.
+    ``execute`` returns ``(order, radius, source)`` of length ``total_k``;
+    node j's picks are at ``out_offsets[j]:out_offsets[j+1]``; ``source`` is
+    the candidate row each pick came from."""
+
+    def __init__(self, parents, leaf_offsets, ks, seeds=None, tune: Optional[Tuning] = None):
+        import numpy as np
+        lib = load()
+        self._lib = lib
+        par = np.ascontiguousarray(np.asarray(parents, dtype=np.int32))
+        offs = np.ascontiguousarray(np.asarray(leaf_offsets, dtype=np.int64))
+        kk = np.ascontiguousarray(np.asarray(ks, dtype=np.int64))
+        m = int(par.shape[0])
+        if offs.shape[0] != m + 1 or kk.shape[0] != m:
+            raise ValueError("leaf_offsets must have m + 1 entries and ks m")
+        sd = None if seeds is None else np.ascontiguousarray(
+            np.asarray([int(s) & (2**64 - 1) for s in seeds], dtype=np.uint64))
+        self.m = m
+        self._plan = ctypes.c_void_p()
+        tp = ctypes.byref(tune) if tune is not None else None
+        _check(lib.bs_hier_plan_create(m, par.ctypes.data_as(ctypes.c_void_p), offs.ctypes.data_as(ctypes.c_void_p),
+                                       kk.ctypes.data_as(ctypes.c_void_p),
+                                       None if sd is None else sd.ctypes.data_as(ctypes.c_void_p), tp,
+                                       ctypes.byref(self._plan)))
+        self.total_k = int(lib.bs_hier_total_k(self._plan))
+        self.workspace_bytes = int(lib.bs_hier_workspace_size(self._plan))
+        oo = np.zeros(m + 1, dtype=np.int64)
+        _check(lib.bs_hier_out_offsets(self._plan, oo.ctypes.data_as(ctypes.c_void_p)))
+        self.out_offsets = oo
+        self._ws = None
+
+    def execute(self, points, sampler_params: Optional[Sampler] = None, stream=None):
+        import torch
+        points = _prep_points(points)
+        dev = points.device
+        o = torch.empty(max(self.total_k, 1), dtype=torch.int32, device=dev)
+        r = torch.empty(max(self.total_k, 1), dtype=torch.float32, device=dev)
+        s = torch.empty(max(self.total_k, 1), dtype=torch.int32, device=dev)
+        if self._ws is None or self._ws.numel() < self.workspace_bytes:
+            self._ws = torch.empty(max(self.workspace_bytes, 1), dtype=torch.uint8, device=dev)
+        sp = ctypes.byref(sampler_params) if sampler_params is not None else None
+        _check(self._lib.bs_hier_plan_execute(self._plan, _ptr(points), sp, _ptr(o), _ptr(r), _ptr(s),
+                                              _ptr(self._ws), int(self._ws.numel()), _stream_handle(stream)))
+        return o[: self.total_k], r[: self.total_k], s[: self.total_k]
+
+    def close(self):
+        if getattr(self, "_plan", None):
+            self._lib.bs_hier_plan_destroy(self._plan)
             self._plan = None
 
     def __del__(self):

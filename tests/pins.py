@@ -584,3 +584,39 @@ def sampler_battery(lib=None):
     check_sampler_bruteforce(lib, sizes=(9, 40))
     check_sampler_whole_is_greedy(lib)
     check_prefix_nn(lib)
+
+
+# ------------------------------------------ hierarchical generation (Sec. 3.4)
+
+def hier_reference(P, parents, leaf_offsets, ks, seeds, sampler=None):
+    """Bottom-up generation (Sec. 3.4) composed from the oracle: a leaf's
+    candidates are its own rows, an inner node's the positions its children
+    chose (children in increasing node order, picks in order); each node is
+    ordered by oracle_greedy32 (or oracle_sample32 with `sampler` = (S, K, v))
+    with start = SplitMix64(seed) mod n.  Returns per node (order, radius,
+    source rows)."""
+    P = np.asarray(P, dtype=np.float32)
+    m = len(parents)
+    children = [[] for _ in range(m)]
+    for j, p in enumerate(parents):
+        if p >= 0:
+            children[p].append(j)
+    res = [None] * m
+    for j in range(m):
+        if children[j]:
+            src = np.concatenate([res[c][2] for c in children[j]]) if any(ks[c] for c in children[j]) \
+                else np.zeros(0, dtype=np.int64)
+        else:
+            src = np.arange(leaf_offsets[j], leaf_offsets[j + 1], dtype=np.int64)
+        k = int(ks[j])
+        if k == 0:
+            res[j] = (np.zeros(0, np.int32), np.zeros(0, np.float32), np.zeros(0, np.int64))
+            continue
+        Q = P[src]
+        st = oracle.start_index(seeds[j], Q.shape[0])
+        if sampler is None:
+            o, r = oracle.greedy32(Q, k, st)
+        else:
+            o, r, _ = oracle.sample32(Q, k, seeds[j], st, *sampler)
+        res[j] = (o, r, src[o] if (o >= 0).all() else np.full(k, -1, np.int64))
+    return res

@@ -174,3 +174,19 @@ def test_prefix_host_functions(lib):
     assert lib.bs_emit_surfels(None, None, None, 0, None, 0, None, None) == bs.BS_OK
     assert lib.bs_prefix_median_nn(fake, 10, fake, 1, fake, None) == bs.BS_ERR_INVALID_ARG
     assert lib.bs_prefix_median_nn(fake, 5000, fake, 4097, fake, None) == bs.BS_ERR_INVALID_ARG
+
+
+def test_hier_plan_validation_on_cpu():
+    """Plan creation is host-only: its checks and output offsets."""
+    import paper_1904_08225_amd as bs
+    bs.load()
+    with pytest.raises(bs.BSError):
+        bs.HierPlan([1, -1], [0, 10, 10], [3, 4])          # parent 1 has 3 candidates
+    with pytest.raises(bs.BSError):
+        bs.HierPlan([-1, 0], [0, 10, 20], [3, 1])          # a parent before its child
+    with pytest.raises(bs.BSError):
+        bs.HierPlan([2, 2, -1], [0, 10, 20, 25], [3, 3, 2])  # rows for an inner node
+    p = bs.HierPlan([2, 2, -1], [0, 10, 20, 20], [3, 4, 7], [1, 2, 3])
+    assert p.total_k == 14 and p.out_offsets.tolist() == [0, 3, 7, 14]
+    assert p.workspace_bytes > 0
+    p.close()
