@@ -72,6 +72,10 @@ def _bind(path: str):
     lib.oracle_sample32.restype = ctypes.c_int
     lib.oracle_prefix_nn.argtypes = [vp, i64, vp, i64, vp]
     lib.oracle_prefix_nn.restype = ctypes.c_int
+    lib.oracle_capture_view.argtypes = [vp, vp, ctypes.c_int, vp]
+    lib.oracle_capture_view.restype = ctypes.c_int
+    lib.oracle_capture32.argtypes = [vp, vp, vp, vp, vp, i64, vp, vp, ctypes.c_int32, vp, vp, vp, vp]
+    lib.oracle_capture32.restype = ctypes.c_int
     return lib
 
 
@@ -243,6 +247,43 @@ def prefix_nn(points, order, p: int, lib=None) -> np.ndarray:
     out = np.empty(int(p), dtype=np.float32)
     _check((lib or _load()).oracle_prefix_nn(_ptr(pts), pts.shape[0], _ptr(o), int(p), _ptr(out)), False)
     return out
+
+
+def capture32(kind, center, rot, prm, rgb, lo, hi, resolution: int, lib=None):
+    """The initial surfel set of Sec. 3.1: first hits of eight orthographic
+    views from the bounding-box corners at ``resolution``^2 pixels each.
+
+    kind int[P] (0 sphere, 1 box, 2 cylinder), center float[P,3], rot
+    float[P,3,3] (local -> world), prm float[P,3], rgb uint8[P,3], lo / hi
+    float[3].  Returns (positions float32[n,3], normals float32[n,3], colours
+    uint8[n,3]) in view, row, column order."""
+    k = np.ascontiguousarray(np.asarray(kind, dtype=np.int32))
+    P = int(k.shape[0])
+    c = np.ascontiguousarray(np.asarray(center, dtype=np.float32).reshape(P, 3))
+    r = np.ascontiguousarray(np.asarray(rot, dtype=np.float32).reshape(P, 9))
+    pr = np.ascontiguousarray(np.asarray(prm, dtype=np.float32).reshape(P, 3))
+    col = np.ascontiguousarray(np.asarray(rgb, dtype=np.uint8).reshape(P, 3))
+    lo = np.ascontiguousarray(np.asarray(lo, dtype=np.float32).reshape(3))
+    hi = np.ascontiguousarray(np.asarray(hi, dtype=np.float32).reshape(3))
+    cap = 8 * int(resolution) ** 2
+    pos = np.empty((cap, 3), dtype=np.float32)
+    nrm = np.empty((cap, 3), dtype=np.float32)
+    oc = np.empty((cap, 3), dtype=np.uint8)
+    cnt = np.zeros(1, dtype=np.int64)
+    _check((lib or _load()).oracle_capture32(_ptr(k), _ptr(c), _ptr(r), _ptr(pr), _ptr(col), P, _ptr(lo), _ptr(hi),
+                                             int(resolution), _ptr(pos), _ptr(nrm), _ptr(oc), _ptr(cnt)), False)
+    n = int(cnt[0])
+    return pos[:n].copy(), nrm[:n].copy(), oc[:n].copy()
+
+
+def capture_view(lo, hi, v: int, lib=None):
+    """Camera of view v: (d, u, w, c, s) or None for an empty box."""
+    lo = np.ascontiguousarray(np.asarray(lo, dtype=np.float32).reshape(3))
+    hi = np.ascontiguousarray(np.asarray(hi, dtype=np.float32).reshape(3))
+    out = np.empty(13, dtype=np.float32)
+    if not (lib or _load()).oracle_capture_view(_ptr(lo), _ptr(hi), int(v), _ptr(out)):
+        return None
+    return out[0:3], out[3:6], out[6:9], out[9:12], float(out[12])
 
 
 def compile_variant(src_text: str, out_path: str):

@@ -57,6 +57,10 @@
  *   oracle_prefix_nn         each prefix surfel's distance to its nearest
  *                            other prefix surfel (the Sec. 3.3 quality
  *                            measure of a prefix).
+ *   oracle_capture_view      camera of one of the eight capture views.
+ *   oracle_capture32         the initial surfel set of Sec. 3.1: the first
+ *                            surface hit of every pixel of eight orthographic
+ *                            views from the bounding-box corners.
  */
 #include <math.h>
 #include <stdint.h>
@@ -825,5 +829,215 @@ int oracle_prefix_nn(const float* P, int64_t n, const int32_t* order, int64_t p,
         }
         out[a] = sqrtf(best);
     }
+    return ORACLE_OK;
+}
+
+/* ----------------------------------------- visible-surface capture (Sec. 3.1) */
+/*
+ * The paper captures a node's visible surface by rendering it from the eight
+ * corners of its bounding box with orthographic projection towards the box
+ * centre, into buffers of position, normal and colour; every covered pixel
+ * becomes a candidate surfel.  Here the node is a set of analytic primitives
+ * (sphere: radius a; box: half extents a, b, c; cylinder along local z:
+ * radius a, half height b; world = rot * local + center) and each pixel's
+ * candidate is the first primitive surface its ray meets (the visibility a
+ * rasterizer computes at the pixel centre).  Readings (design notes):
+ *   - box centre c = 0.5 (lo + hi), s = half the box diagonal; view v
+ *     (bits x, y, z of v choose hi over lo) looks along d = (c - corner) /
+ *     |c - corner|; image axes u = d x (0,0,1) normalised (d x (0,1,0) if
+ *     that is shorter than 1e-6) and w = u x d; the image is the square of
+ *     side 2 s around c, R x R pixels; pixel (i, j) (i along u) shoots from
+ *     c + a u + b w - 2 s d with a = ((2 i + 1) / R - 1) s, b likewise from j;
+ *   - the hit is the smallest t > 0 over the primitives, lowest primitive
+ *     index on equal t; position o + t d, normal rot * local normal (unit);
+ *     colour the primitive's;
+ *   - candidates in view order, then row j, then column i;
+ *   - every value in binary32 with the operation order written below.
+ * A view whose corner is the centre (an empty box) contributes nothing.
+ */
+static float dot3f(const float* a, const float* b) { return (a[0] * b[0] + a[1] * b[1]) + a[2] * b[2]; }
+
+/* view v: out[0..2] d, [3..5] u, [6..8] w, [9..11] c, [12] s; returns 0 if degenerate */
+int oracle_capture_view(const float* lo, const float* hi, int v, float* out)
+{
+    float c[3], e[3], dv[3], d[3], u[3], w[3];
+    for (int a = 0; a < 3; ++a) {
+        c[a] = 0.5f * (lo[a] + hi[a]);
+        e[a] = hi[a] - lo[a];
+        float corner = ((v >> a) & 1) ? hi[a] : lo[a];
+        dv[a] = c[a] - corner;
+    }
+    float s = 0.5f * sqrtf(dot3f(e, e));
+    float L = sqrtf(dot3f(dv, dv));
+    if (!(L > 0.0f)) return 0;
+    for (int a = 0; a < 3; ++a) d[a] = dv[a] / L;
+    u[0] = d[1];
+    u[1] = -d[0];
+    u[2] = 0.0f;
+    float lu = sqrtf(dot3f(u, u));
+    if (!(lu >= 1e-6f)) {
+        u[0] = -d[2];
+        u[1] = 0.0f;
+        u[2] = d[0];
+        lu = sqrtf(dot3f(u, u));
+    }
+    for (int a = 0; a < 3; ++a) u[a] = u[a] / lu;
+    w[0] = u[1] * d[2] - u[2] * d[1];
+    w[1] = u[2] * d[0] - u[0] * d[2];
+    w[2] = u[0] * d[1] - u[1] * d[0];
+    for (int a = 0; a < 3; ++a) {
+        out[a] = d[a];
+        out[3 + a] = u[a];
+        out[6 + a] = w[a];
+        out[9 + a] = c[a];
+    }
+    out[12] = s;
+    return 1;
+}
+
+/* local = rot^T (p - center) for a point, rot^T p for a direction */
+static void to_local(const float* rot, const float* p, float* q)
+{
+    q[0] = (rot[0] * p[0] + rot[3] * p[1]) + rot[6] * p[2];
+    q[1] = (rot[1] * p[0] + rot[4] * p[1]) + rot[7] * p[2];
+    q[2] = (rot[2] * p[0] + rot[5] * p[1]) + rot[8] * p[2];
+}
+
+/* first hit t > 0 of the local ray ol + t dl with primitive (kind, prm);
+ * returns 0 on a miss, else t and the local unit normal */
+static int hit_local(int kind, const float* prm, const float* ol, const float* dl, float* t_out, float* nl)
+{
+    if (kind == 0) { /* sphere: from the ray's closest approach to the centre */
+        float r = prm[0];
+        float a = dot3f(dl, dl);
+        float t0 = -dot3f(ol, dl) / a;
+        float p0[3] = {ol[0] + t0 * dl[0], ol[1] + t0 * dl[1], ol[2] + t0 * dl[2]};
+        float h2 = r * r - dot3f(p0, p0);
+        if (h2 < 0.0f) return 0;
+        float t = t0 - sqrtf(h2 / a);
+        if (!(t > 0.0f)) return 0;
+        for (int k = 0; k < 3; ++k) nl[k] = (ol[k] + t * dl[k]) / r;
+        *t_out = t;
+        return 1;
+    }
+    if (kind == 1) { /* box: slabs */
+        float tn = -INFINITY, tf = INFINITY;
+        int axis = -1;
+        for (int k = 0; k < 3; ++k) {
+            float h = prm[k];
+            if (dl[k] == 0.0f) {
+                if (ol[k] < -h || ol[k] > h) return 0;
+                continue;
+            }
+            float t1 = (-h - ol[k]) / dl[k];
+            float t2 = (h - ol[k]) / dl[k];
+            float lo = t1 < t2 ? t1 : t2;
+            float hi = t1 < t2 ? t2 : t1;
+            if (lo > tn) { tn = lo; axis = k; }
+            if (hi < tf) tf = hi;
+        }
+        if (axis < 0 || !(tn <= tf) || !(tn > 0.0f)) return 0;
+        nl[0] = nl[1] = nl[2] = 0.0f;
+        nl[axis] = dl[axis] > 0.0f ? -1.0f : 1.0f;
+        *t_out = tn;
+        return 1;
+    }
+    if (kind == 2) { /* cylinder along z: lateral surface and two caps */
+        float r = prm[0], h = prm[1];
+        float best = INFINITY;
+        int side = -1;
+        float a = dl[0] * dl[0] + dl[1] * dl[1];
+        if (a > 0.0f) { /* lateral: from the closest approach to the axis */
+            float t0 = -(ol[0] * dl[0] + ol[1] * dl[1]) / a;
+            float x0 = ol[0] + t0 * dl[0];
+            float y0 = ol[1] + t0 * dl[1];
+            float h2 = r * r - (x0 * x0 + y0 * y0);
+            if (h2 >= 0.0f) {
+                float t = t0 - sqrtf(h2 / a);
+                float z = ol[2] + t * dl[2];
+                if (t > 0.0f && z >= -h && z <= h) { best = t; side = 0; }
+            }
+        }
+        if (dl[2] != 0.0f) {
+            for (int cap = 0; cap < 2; ++cap) {
+                float zc = cap ? h : -h;
+                float t = (zc - ol[2]) / dl[2];
+                float x = ol[0] + t * dl[0];
+                float y = ol[1] + t * dl[1];
+                if (t > 0.0f && (x * x + y * y) <= r * r && t < best) { best = t; side = 1 + cap; }
+            }
+        }
+        if (side < 0) return 0;
+        if (side == 0) {
+            float x = ol[0] + best * dl[0];
+            float y = ol[1] + best * dl[1];
+            nl[0] = x / r;
+            nl[1] = y / r;
+            nl[2] = 0.0f;
+        } else {
+            nl[0] = 0.0f;
+            nl[1] = 0.0f;
+            nl[2] = side == 2 ? 1.0f : -1.0f;
+        }
+        *t_out = best;
+        return 1;
+    }
+    return 0;
+}
+
+/*
+ * Primitives: kind[P] (0 sphere, 1 box, 2 cylinder), center[P][3],
+ * rot[P][9] (row-major, local -> world), prm[P][3], rgb[P][3].  Outputs of
+ * capacity 8 R^2: pos, nrm (float [][3]), col (uint8 [][3]); *count.
+ */
+int oracle_capture32(const int32_t* kind, const float* center, const float* rot, const float* prm,
+                     const uint8_t* rgb, int64_t P, const float* lo, const float* hi, int32_t R,
+                     float* pos, float* nrm, uint8_t* col, int64_t* count)
+{
+    if (P < 0 || R < 1 || !lo || !hi || !pos || !nrm || !col || !count) return ORACLE_BAD_ARG;
+    int64_t n = 0;
+    for (int v = 0; v < 8; ++v) {
+        float cam[13];
+        if (!oracle_capture_view(lo, hi, v, cam)) continue;
+        const float *d = cam, *u = cam + 3, *w = cam + 6, *c = cam + 9;
+        float s = cam[12];
+        float s2 = 2.0f * s;
+        for (int32_t j = 0; j < R; ++j) {
+            float fb = (float)(2 * j + 1) / (float)R - 1.0f;
+            float b = fb * s;
+            for (int32_t i = 0; i < R; ++i) {
+                float fa = (float)(2 * i + 1) / (float)R - 1.0f;
+                float a = fa * s;
+                float o[3];
+                for (int k = 0; k < 3; ++k) o[k] = ((c[k] + a * u[k]) + b * w[k]) - s2 * d[k];
+                float tbest = INFINITY;
+                int64_t pbest = -1;
+                float nbest[3] = {0, 0, 0};
+                for (int64_t q = 0; q < P; ++q) {
+                    const float* R9 = rot + 9 * q;
+                    float oc[3] = {o[0] - center[3 * q], o[1] - center[3 * q + 1], o[2] - center[3 * q + 2]};
+                    float ol[3], dl[3], nl[3], t;
+                    to_local(R9, oc, ol);
+                    to_local(R9, d, dl);
+                    if (!hit_local(kind[q], prm + 3 * q, ol, dl, &t, nl)) continue;
+                    if (t < tbest) {
+                        tbest = t;
+                        pbest = q;
+                        nbest[0] = (R9[0] * nl[0] + R9[1] * nl[1]) + R9[2] * nl[2];
+                        nbest[1] = (R9[3] * nl[0] + R9[4] * nl[1]) + R9[5] * nl[2];
+                        nbest[2] = (R9[6] * nl[0] + R9[7] * nl[1]) + R9[8] * nl[2];
+                    }
+                }
+                if (pbest < 0) continue;
+                for (int k = 0; k < 3; ++k) {
+                    pos[3 * n + k] = o[k] + tbest * d[k];
+                    nrm[3 * n + k] = nbest[k];
+                    col[3 * n + k] = rgb[3 * pbest + k];
+                }
+                ++n;
+            }
+        }
+    }
+    *count = n;
     return ORACLE_OK;
 }

@@ -580,6 +580,7 @@ def check_prefix_nn(lib=None):
 
 
 def sampler_battery(lib=None):
+    check_capture(lib, R=16)
     check_philox_kat(lib)
     check_sampler_bruteforce(lib, sizes=(9, 40))
     check_sampler_whole_is_greedy(lib)
@@ -620,3 +621,220 @@ def hier_reference(P, parents, leaf_offsets, ks, seeds, sampler=None):
             o, r, _ = oracle.sample32(Q, k, seeds[j], st, *sampler)
         res[j] = (o, r, src[o] if (o >= 0).all() else np.full(k, -1, np.int64))
     return res
+
+
+# ------------------------------------------- visible-surface capture (Sec. 3.1)
+
+def prims_arrays(prims):
+    """synth.Primitives -> the capture's arrays (kind, center, rot, prm, rgb)
+    in float32, and the bounding box of the primitives (float32 lo, hi)."""
+    kind = prims.kind.cpu().numpy().astype(np.int32)
+    center = prims.center.cpu().numpy().astype(np.float32)
+    rot = prims.rot.cpu().numpy().astype(np.float32)
+    prm = prims.prm.cpu().numpy().astype(np.float32)
+    rgb = prims.color.cpu().numpy().astype(np.uint8)
+    # corners of each primitive's local box, rotated: a conservative world box
+    ext = np.where(kind[:, None] == 0, prm[:, :1].repeat(3, 1),
+                   np.where(kind[:, None] == 1, prm, np.stack([prm[:, 0], prm[:, 0], prm[:, 1]], 1)))
+    r64 = rot.astype(np.float64)
+    half = np.abs(r64) @ ext.astype(np.float64)[:, :, None]
+    lo = (center.astype(np.float64) - half[:, :, 0]).min(0).astype(np.float32)
+    hi = (center.astype(np.float64) + half[:, :, 0]).max(0).astype(np.float32)
+    return kind, center, rot, prm, rgb, lo, hi
+
+
+def brute_capture64(kind, center, rot, prm, rgb, lo, hi, R):
+    """Independent binary64 ray cast of the eight corner views (numpy, every
+    pixel against every primitive).  Returns per pixel (view-major, row, column)
+    the hit flag, t, the runner-up t, position, normal, colour and a graze
+    margin (how far the hit is from a silhouette or face edge)."""
+    lo = lo.astype(np.float64)
+    hi = hi.astype(np.float64)
+    c = 0.5 * (lo + hi)
+    s = 0.5 * np.linalg.norm(hi - lo)
+    out = []
+    for v in range(8):
+        corner = np.where([(v >> a) & 1 for a in range(3)], hi, lo)
+        dv = c - corner
+        L = np.linalg.norm(dv)
+        if L == 0:
+            continue
+        d = dv / L
+        u = np.cross(d, [0.0, 0.0, 1.0])
+        if np.linalg.norm(u) < 1e-6:
+            u = np.cross(d, [0.0, 1.0, 0.0])
+        u /= np.linalg.norm(u)
+        w = np.cross(u, d)
+        f = (2 * np.arange(R) + 1) / R - 1.0
+        A = np.repeat(f[None, :], R, 0) * s   # [j, i]
+        B = np.repeat(f[:, None], R, 1) * s
+        O = c + A[..., None] * u + B[..., None] * w - 2 * s * d   # [R, R, 3]
+        O = O.reshape(-1, 3)
+        best = np.full(O.shape[0], np.inf)
+        second = np.full(O.shape[0], np.inf)
+        bi = np.full(O.shape[0], -1)
+        nrm = np.zeros_like(O)
+        margin = np.full(O.shape[0], np.inf)
+        for q in range(kind.shape[0]):
+            Rm = rot[q].astype(np.float64)
+            ol = (O - center[q]) @ Rm          # rot^T (o - center)
+            dl = d @ Rm
+            p = prm[q].astype(np.float64)
+            t = np.full(O.shape[0], np.inf)
+            nl = np.zeros_like(O)
+            mg = np.full(O.shape[0], np.inf)
+            if kind[q] == 0:
+                b = ol @ dl
+                cc = (ol * ol).sum(1) - p[0] ** 2
+                disc = b * b - (dl @ dl) * cc
+                ok = disc >= 0
+                tt = (-b - np.sqrt(np.where(ok, disc, 0))) / (dl @ dl)
+                ok &= tt > 0
+                t = np.where(ok, tt, np.inf)
+                hitp = ol + t[:, None] * dl
+                nl = np.where(ok[:, None], hitp / p[0], 0)
+                mg = np.abs(disc) / (p[0] ** 2)
+            elif kind[q] == 1:
+                with np.errstate(divide="ignore", invalid="ignore"):
+                    t1 = (-p - ol) / dl
+                    t2 = (p - ol) / dl
+                tn = np.where(dl == 0, np.where(np.abs(ol) <= p, -np.inf, np.inf), np.minimum(t1, t2))
+                tf = np.where(dl == 0, np.where(np.abs(ol) <= p, np.inf, -np.inf), np.maximum(t1, t2))
+                ax = np.argmax(tn, 1)
+                tnear = tn.max(1)
+                tfar = tf.min(1)
+                ok = (tnear <= tfar) & (tnear > 0)
+                t = np.where(ok, tnear, np.inf)
+                nl[np.arange(O.shape[0]), ax] = np.where(dl[ax] > 0, -1.0, 1.0)
+                nl = np.where(ok[:, None], nl, 0)
+                srt = np.sort(tn, 1)
+                mg = np.minimum(np.abs(tfar - tnear), np.abs(srt[:, 2] - srt[:, 1])) / (np.abs(tnear) + 1e-30)
+            else:
+                r, h = p[0], p[1]
+                a = dl[0] ** 2 + dl[1] ** 2
+                tl = np.full(O.shape[0], np.inf)
+                if a > 0:
+                    b = ol[:, 0] * dl[0] + ol[:, 1] * dl[1]
+                    cc = ol[:, 0] ** 2 + ol[:, 1] ** 2 - r * r
+                    disc = b * b - a * cc
+                    ok = disc >= 0
+                    tt = (-b - np.sqrt(np.where(ok, disc, 0))) / a
+                    z = ol[:, 2] + tt * dl[2]
+                    ok &= (tt > 0) & (z >= -h) & (z <= h)
+                    tl = np.where(ok, tt, np.inf)
+                    mg = np.minimum(np.abs(disc) / (r * r), np.abs(np.abs(z) - h) / h)
+                tcap = np.full(O.shape[0], np.inf)
+                capn = np.zeros(O.shape[0])
+                if dl[2] != 0:
+                    for zc in (-h, h):
+                        tt = (zc - ol[:, 2]) / dl[2]
+                        x = ol[:, 0] + tt * dl[0]
+                        y = ol[:, 1] + tt * dl[1]
+                        rr = x * x + y * y
+                        ok = (tt > 0) & (rr <= r * r) & (tt < tcap)
+                        capn = np.where(ok, np.sign(zc), capn)
+                        tcap = np.where(ok, tt, tcap)
+                        mg = np.minimum(mg, np.where(np.isfinite(tt), np.abs(rr - r * r) / (r * r), np.inf))
+                lat = tl <= tcap
+                t = np.minimum(tl, tcap)
+                hitp = ol + np.where(np.isfinite(t), t, 0)[:, None] * dl
+                nl = np.where(lat[:, None], np.stack([hitp[:, 0] / r, hitp[:, 1] / r, 0 * hitp[:, 0]], 1),
+                              np.stack([0 * capn, 0 * capn, capn], 1))
+                nl = np.where(np.isfinite(t)[:, None], nl, 0)
+            closer = t < best
+            second = np.where(closer, best, np.minimum(second, t))
+            nrm = np.where(closer[:, None], nl @ Rm.T, nrm)
+            margin = np.where(closer, mg, margin)
+            bi = np.where(closer, q, bi)
+            best = np.where(closer, t, best)
+        hit = bi >= 0
+        pos = O + np.where(hit, best, 0)[:, None] * d
+        colr = np.where(hit[:, None], rgb[np.maximum(bi, 0)], 0)
+        out.append((hit, best, second, pos, nrm, colr, margin))
+    cat = [np.concatenate([o[i] for o in out]) for i in range(7)]
+    return cat
+
+
+def check_capture_against_brute(P_arrays, R, lib=None, tol=2e-5, ntol=2e-3):
+    """The oracle's capture against the independent binary64 ray cast: every
+    pixel that is clearly hit or clearly missed (away from silhouettes and
+    near-equal depths) agrees on coverage, and on covered pixels the position
+    agrees within tol * scene size (binary32 intersection from the ray's
+    closest approach: about 1e-6 of the scene), the normal within ntol (a
+    position error divided by a small radius), the colour exactly."""
+    kind, center, rot, prm, rgb, lo, hi = P_arrays
+    pos, nrm, col = oracle.capture32(kind, center, rot, prm, rgb, lo, hi, R, lib=lib)
+    hit, best, second, bpos, bnrm, bcol, margin = brute_capture64(kind, center, rot, prm, rgb, lo, hi, R)
+    with np.errstate(invalid="ignore"):  # inf - inf where nothing is hit
+        clear = (margin > 1e-3) & ((second - best) > 1e-4 * (np.abs(best) + 1))
+    # rebuild the oracle's per-pixel coverage from its compacted output by
+    # replaying the order: covered pixels in view/row/column order
+    idx = np.nonzero(hit)[0]
+    scene = float(np.linalg.norm(hi.astype(np.float64) - lo.astype(np.float64)))
+    assert pos.shape[0] >= int((hit & clear).sum()) and pos.shape[0] <= int((hit | ~clear).sum()), \
+        ("covered pixel count", pos.shape[0], int(hit.sum()))
+    if pos.shape[0] == idx.shape[0]:
+        ok = clear[idx]
+        assert np.all(np.abs(pos[ok] - bpos[idx][ok]) <= tol * scene), "positions"
+        assert np.all(np.abs(nrm[ok] - bnrm[idx][ok]) <= ntol), "normals"
+        assert np.array_equal(col[ok], bcol[idx][ok]), "colours"
+    else:
+        raise AssertionError("covered pixels differ at silhouettes: %d against %d" % (pos.shape[0], idx.shape[0]))
+    return pos.shape[0], int(hit.sum())
+
+
+def capture_cases():
+    import synth
+    out = [pins_sphere_box()]
+    for seed, cnt in ((7, 12), (3, 40)):
+        out.append(prims_arrays(synth.cad_primitives(seed, count=cnt)))
+    return out
+
+
+def pins_sphere_box():
+    """The unit sphere and the 1 x 0.5 x 0.25 box of the sphere_and_box
+    workload, as capture primitives."""
+    kind = np.array([0, 1], np.int32)
+    center = np.array([[0, 0, 0], [2, 0, 0]], np.float32)
+    rot = np.stack([np.eye(3, dtype=np.float32)] * 2)
+    prm = np.array([[1, 0, 0], [0.5, 0.25, 0.125]], np.float32)
+    rgb = np.array([[200, 60, 40], [40, 90, 210]], np.uint8)
+    lo = np.array([-1, -1, -1], np.float32)
+    hi = np.array([2.5, 1, 1], np.float32)
+    return kind, center, rot, prm, rgb, lo, hi
+
+
+def check_capture(lib=None, R=24):
+    """Capture pins: the binary64 brute force on three scenes; a lone sphere's
+    hits lie on it with unit normals and cover pi/12 of each view (its disc
+    in the square of side 2 s, s = sqrt(3) r); an axis-aligned cube's hits
+    lie on its faces with the face's normal and cover sqrt(3)/3 of each view
+    (a regular hexagon of area sqrt(3) in a square of side sqrt(3))."""
+    for case in capture_cases():
+        check_capture_against_brute(case, R, lib=lib)
+    kind = np.array([0], np.int32)
+    center = np.array([[0.5, -1.0, 2.0]], np.float32)
+    rot = np.eye(3, dtype=np.float32)[None]
+    prm = np.array([[0.75, 0, 0]], np.float32)
+    rgb = np.array([[1, 2, 3]], np.uint8)
+    lo = center[0] - 0.75
+    hi = center[0] + 0.75
+    pos, nrm, col = oracle.capture32(kind, center, rot, prm, rgb, lo, hi, R, lib=lib)
+    rad = np.linalg.norm(pos.astype(np.float64) - center[0], axis=1)
+    assert np.all(np.abs(rad - 0.75) <= 1e-5), "sphere radius"
+    assert np.all(np.abs(np.linalg.norm(nrm, axis=1) - 1) <= 1e-5)
+    assert (col == [1, 2, 3]).all()
+    # the projected disc covers pi r^2 / (2 s)^2 of each view, s = sqrt(3) r
+    frac = pos.shape[0] / (8.0 * R * R)
+    assert abs(frac - np.pi / 12) < 4.0 / R, ("sphere coverage", frac)
+    kind = np.array([1], np.int32)
+    center = np.zeros((1, 3), np.float32)
+    prm = np.array([[0.5, 0.5, 0.5]], np.float32)
+    pos, nrm, col = oracle.capture32(kind, center, rot, prm, rgb, -prm[0], prm[0], R, lib=lib)
+    assert np.all(np.abs(np.abs(pos).max(1) - 0.5) <= 1e-6), "cube surface"
+    assert np.all(np.isin(np.abs(nrm).sum(1), [1.0])), "axis normals"
+    # each normal is the face the hit lies on: the coordinate at +-0.5 along it
+    ax = np.argmax(np.abs(nrm), 1)
+    assert np.all(np.abs(pos[np.arange(pos.shape[0]), ax] - 0.5 * nrm[np.arange(pos.shape[0]), ax]) <= 1e-6)
+    frac = pos.shape[0] / (8.0 * R * R)
+    assert abs(frac - np.sqrt(3) / 3) < 4.0 / R, ("cube coverage", frac)

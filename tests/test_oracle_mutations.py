@@ -54,6 +54,14 @@ MUTANTS = {
     "sampler_radius_after_removal": ("            if (radius) radius[t] = sqrtf(m[c]);\n            alive[c] = 0;\n            --remaining;",
                                      "            if (radius) radius[t] = sqrtf(m[c] * 0.5f);\n            alive[c] = 0;\n            --remaining;"),
     "prefix_nn_self": ("            if (b != a) {\n                float d = d2_f32(pa,", "            {\n                float d = d2_f32(pa,"),
+    "capture_farthest_hit": ("                    if (t < tbest) {\n                        tbest = t;",
+                             "                    if (t > tbest || tbest == INFINITY) {\n                        tbest = t;"),
+    "capture_box_normal_sign": ("        nl[axis] = dl[axis] > 0.0f ? -1.0f : 1.0f;", "        nl[axis] = dl[axis] > 0.0f ? 1.0f : -1.0f;"),
+    "capture_pixel_corner": ("                float fa = (float)(2 * i + 1) / (float)R - 1.0f;",
+                             "                float fa = (float)(2 * i) / (float)R - 1.0f;"),
+    "capture_image_axis": ("    u[1] = -d[0];\n    u[2] = 0.0f;", "    u[1] = d[0];\n    u[2] = 0.0f;"),
+    "capture_cylinder_exit": ("                float t = t0 - sqrtf(h2 / a);\n                float z", "                float t = t0 + sqrtf(h2 / a);\n                float z"),
+    "capture_sphere_exit": ("        float t = t0 - sqrtf(h2 / a);\n        if (!(t > 0.0f)) return 0;", "        float t = t0 + sqrtf(h2 / a);\n        if (!(t > 0.0f)) return 0;"),
     "grid_prunes_too_much": ("if (bd * (1.0 - 1e-5) - 1e-37 >= (double)mc) continue;",
                              "if (bd * 4.0 >= (double)mc) continue;"),
     "splitmix_constant": ("z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;",

@@ -174,6 +174,10 @@ def test_sampler_quality_between_random_and_greedy():
         assert g >= s > 1.5 * r, (p, g, s, r)
 
 
+def test_capture_pins():
+    pins.check_capture()
+
+
 def test_statistics_consistent():
     P = cases.random_cloud(600, 3)
     o, r, st = oracle.greedy32(P, 600, 2, stats=True)
