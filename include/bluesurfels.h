@@ -395,6 +395,53 @@ void bs_batch_plan_destroy(bs_batch_plan* plan);
  * Defined after the sampler's parameter struct below.
  */
 
+/* ----------------------------- visible-surface capture (paper Sec. 3.1) */
+
+/*
+ * An analytic primitive of a node (world = rot * local + center).
+ *   kind 0 sphere: prm[0] radius;  kind 1 box: prm = half extents;
+ *   kind 2 cylinder along local z: prm[0] radius, prm[1] half height (capped).
+ */
+typedef struct {
+    int32_t kind;
+    float center[3];
+    float rot[9];      /* row-major 3 x 3, local -> world */
+    float prm[3];
+    uint8_t rgb[4];    /* colour; rgb[3] unused */
+} bs_primitive;
+
+/* Device workspace bytes of bs_capture at `resolution` pixels per side
+ * (a G-buffer of 32 B per pixel of the eight views); 0 if out of 1..8192. */
+size_t bs_capture_workspace_size(int32_t resolution);
+
+/*
+ * The initial surfel set of a node (Sec. 3.1): its visible surface seen from
+ * the eight corners of its bounding box with orthographic projection towards
+ * the box centre, resolution^2 pixels per view (the paper uses 1024^2); every
+ * covered pixel gives one candidate: the first primitive surface its ray
+ * meets (position, unit normal, the primitive's colour).  The camera of view
+ * v (bits x, y, z of v pick hi over lo): c = (lo + hi) / 2, s = |hi - lo| / 2,
+ * d = (c - corner) / |c - corner|, u = d x (0,0,1) normalised (d x (0,1,0)
+ * when that is shorter than 1e-6), w = u x d; pixel (i, j) casts along d from
+ * c + a u + b w - 2 s d, a = ((2 i + 1) / resolution - 1) s, b likewise.
+ * Nearest t > 0 wins, the lower primitive index on equal t.  Binary32 with a
+ * fixed operation order; candidates in view, row, column order.  Spheres,
+ * boxes and capped cylinders (no tori).
+ *   d_prims          device bs_primitive[count]
+ *   h_lo, h_hi       host float[3]: the node's bounding box (finite, lo <= hi)
+ *   d_out_points     device float[8 resolution^2][3] (capacity)
+ *   d_out_normals    device float[8 resolution^2][3] or NULL
+ *   d_out_colors     device uint8[8 resolution^2][3] or NULL
+ *   d_out_count      device int64[1]: candidates written
+ *   d_workspace      bs_capture_workspace_size(resolution) bytes, 256-byte aligned
+ * The outputs feed bs_order / bs_sample directly (the count stays on the
+ * device; read it back to size the ordering).  Enqueues three kernels.
+ * Errors: BS_ERR_INVALID_ARG, BS_ERR_HIP.
+ */
+int bs_capture(const bs_primitive* d_prims, int32_t count, const float* h_lo, const float* h_hi, int32_t resolution,
+               float* d_out_points, float* d_out_normals, uint8_t* d_out_colors, int64_t* d_out_count,
+               void* d_workspace, size_t workspace_bytes, void* stream);
+
 /* ------------------------------------ randomized sampler (paper Sec. 3.2) */
 
 /*

@@ -142,6 +142,10 @@ def load():
     lib.bs_hier_plan_execute.restype = i32
     lib.bs_hier_plan_destroy.argtypes = [vp]
     lib.bs_hier_plan_destroy.restype = None
+    lib.bs_capture_workspace_size.argtypes = [ctypes.c_int32]
+    lib.bs_capture_workspace_size.restype = sz
+    lib.bs_capture.argtypes = [vp, ctypes.c_int32, vp, vp, ctypes.c_int32, vp, vp, vp, vp, vp, sz, vp]
+    lib.bs_capture.restype = i32
     lib.bs_order_noalloc.argtypes = [vp, i64, i64, u64, i64, vp, vp, tp, vp]
     lib.bs_order_noalloc.restype = i32
     lib.bs_noalloc_max_bytes.argtypes = []
@@ -404,6 +408,49 @@ def prefix_nn(points, order, p: int, stream=None):
     out = torch.empty(int(p), dtype=torch.float32, device=pts.device)
     _check(lib.bs_prefix_nn(_ptr(pts), int(pts.shape[0]), _ptr(o), int(p), _ptr(out), _stream_handle(stream)))
     return out
+
+
+def primitive_records(kind, center, rot, prm, rgb):
+    """Pack primitives into the 68-byte ``bs_primitive`` records (numpy
+    structured array): kind int[P] (0 sphere, 1 box, 2 cylinder), center
+    [P,3], rot [P,3,3] local -> world, prm [P,3], rgb uint8 [P,3]."""
+    import numpy as np
+    dt = np.dtype([("kind", "<i4"), ("center", "<f4", 3), ("rot", "<f4", 9), ("prm", "<f4", 3),
+                   ("rgb", "u1", 4)])
+    assert dt.itemsize == 68
+    k = np.asarray(kind)
+    rec = np.zeros(k.shape[0], dtype=dt)
+    rec["kind"] = k
+    rec["center"] = np.asarray(center, dtype=np.float32).reshape(-1, 3)
+    rec["rot"] = np.asarray(rot, dtype=np.float32).reshape(-1, 9)
+    rec["prm"] = np.asarray(prm, dtype=np.float32).reshape(-1, 3)
+    rec["rgb"][:, :3] = np.asarray(rgb, dtype=np.uint8).reshape(-1, 3)
+    return rec
+
+
+def capture(records, lo, hi, resolution: int = 1024, stream=None, device="cuda"):
+    """The visible-surface candidates of a node (``bs_capture``, Sec. 3.1):
+    ``(points float32[n,3], normals float32[n,3], colors uint8[n,3])`` on the
+    GPU, from primitive records (:func:`primitive_records`) and the node's
+    bounding box."""
+    import numpy as np
+    import torch
+    lib = load()
+    R = int(resolution)
+    raw = torch.from_numpy(np.ascontiguousarray(records).view(np.uint8).copy()).to(device)
+    cap = 8 * R * R
+    pts = torch.empty((cap, 3), dtype=torch.float32, device=device)
+    nrm = torch.empty((cap, 3), dtype=torch.float32, device=device)
+    col = torch.empty((cap, 3), dtype=torch.uint8, device=device)
+    cnt = torch.zeros(1, dtype=torch.int64, device=device)
+    ws = torch.empty(max(int(lib.bs_capture_workspace_size(R)), 1), dtype=torch.uint8, device=device)
+    lo32 = np.ascontiguousarray(np.asarray(lo, dtype=np.float32).reshape(3))
+    hi32 = np.ascontiguousarray(np.asarray(hi, dtype=np.float32).reshape(3))
+    _check(lib.bs_capture(_ptr(raw), int(records.shape[0]), lo32.ctypes.data_as(ctypes.c_void_p),
+                          hi32.ctypes.data_as(ctypes.c_void_p), R, _ptr(pts), _ptr(nrm), _ptr(col), _ptr(cnt),
+                          _ptr(ws), int(ws.numel()), _stream_handle(stream)))
+    n = int(cnt.cpu()[0])
+    return pts[:n], nrm[:n], col[:n]
 
 
 def noalloc_max_bytes() -> int:
