@@ -329,6 +329,83 @@ def bench_sampler(bs, torch, np, pts, exact_order, cpu=True):
     return rec
 
 
+def bench_capture(bs, torch, np, cpu=True):
+    """Sec. 3.1 + 3.2/3.3 as one preprocessing pipeline on the device: the
+    visible surface of a CAD-like part (200 boxes / cylinders, seed 2) from
+    the eight bounding-box corners at 1024^2 pixels per view, then the exact
+    ordering of the captured candidates to k = 262,144 (or all of them)."""
+    import synth
+    sys.path.insert(0, os.path.join(ROOT, "tests"))
+    prims = synth.cad_primitives(2, count=200)
+    kind = prims.kind.numpy().astype(np.int32)
+    center = prims.center.numpy().astype(np.float32)
+    rot = prims.rot.numpy().astype(np.float32)
+    prm = prims.prm.numpy().astype(np.float32)
+    rgb = prims.color.numpy().astype(np.uint8)
+    ext = np.where(kind[:, None] == 0, prm[:, :1].repeat(3, 1),
+                   np.where(kind[:, None] == 1, prm, np.stack([prm[:, 0], prm[:, 0], prm[:, 1]], 1)))
+    half = (np.abs(rot.astype(np.float64)) @ ext.astype(np.float64)[:, :, None])[:, :, 0]
+    lo = (center - half).min(0).astype(np.float32)
+    hi = (center + half).max(0).astype(np.float32)
+    rec = bs.primitive_records(kind, center, rot, prm, rgb)
+    R = 1024
+    pts, nrm, col = bs.capture(rec, lo, hi, R)  # warm-up
+    stream = torch.cuda.current_stream()
+    lib = bs.load()
+    raw = torch.from_numpy(rec.view(np.uint8).copy()).cuda()
+    cap = 8 * R * R
+    P = torch.empty((cap, 3), dtype=torch.float32, device="cuda")
+    N = torch.empty((cap, 3), dtype=torch.float32, device="cuda")
+    C = torch.empty((cap, 3), dtype=torch.uint8, device="cuda")
+    cnt = torch.zeros(1, dtype=torch.int64, device="cuda")
+    ws = torch.empty(int(lib.bs_capture_workspace_size(R)), dtype=torch.uint8, device="cuda")
+    import ctypes
+    reps = 10
+    b, e = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    b.record(stream)
+    for _ in range(reps):
+        rc = lib.bs_capture(ctypes.c_void_p(raw.data_ptr()), int(rec.shape[0]), lo.ctypes.data_as(ctypes.c_void_p),
+                            hi.ctypes.data_as(ctypes.c_void_p), R, ctypes.c_void_p(P.data_ptr()),
+                            ctypes.c_void_p(N.data_ptr()), ctypes.c_void_p(C.data_ptr()),
+                            ctypes.c_void_p(cnt.data_ptr()), ctypes.c_void_p(ws.data_ptr()), int(ws.numel()),
+                            ctypes.c_void_p(stream.cuda_stream))
+        assert rc == 0
+    e.record(stream)
+    torch.cuda.synchronize()
+    cap_s = b.elapsed_time(e) / 1e3 / reps
+    n = int(cnt.cpu()[0])
+    k = min(262144, n)
+    cand = P[:n]
+    o, r = bs.order(cand, k, seed=2)  # warm-up
+    b2, e2 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    b2.record(stream)
+    o, r = bs.order(cand, k, seed=2, check=False)
+    e2.record(stream)
+    torch.cuda.synchronize()
+    ord_s = b2.elapsed_time(e2) / 1e3
+    tests = 8 * R * R * int(rec.shape[0])
+    rec_out = {"workload": "cad_primitives seed 2 (200 boxes / cylinders), 8 views x 1024^2 pixels",
+               "candidates": n, "capture_seconds": cap_s, "ray_primitive_tests_per_s": tests / cap_s,
+               "gbuffer_bytes": 8 * R * R * 32, "order_k": k, "order_seconds": ord_s,
+               "pipeline_seconds": cap_s + ord_s,
+               "note": "capture kernel (ray cast, G-buffer) + scan + scatter, then bs_order on the captured "
+                       "candidates on the device: the paper's render-to-texture, initial-set and sampling stages "
+                       "without a host round trip"}
+    if cpu:
+        import oracle
+        Rs = 256
+        t0 = time.perf_counter()
+        ep, _, _ = oracle.capture32(kind, center, rot, prm, rgb, lo, hi, Rs)
+        cs = time.perf_counter() - t0
+        gp, _, _ = bs.capture(rec, lo, hi, Rs)
+        rec_out["matches_oracle_at_256"] = bool(np.array_equal(gp.cpu().numpy().view(np.uint32),
+                                                               ep.view(np.uint32)))
+        rec_out["cpu_oracle"] = {"kind": "oracle", "cores": 1, "seconds": cs,
+                                 "ray_primitive_tests_per_s": 8 * Rs * Rs * int(rec.shape[0]) / cs,
+                                 "sample": "oracle_capture32 (1 thread) at 256^2 pixels per view"}
+    return rec_out
+
+
 def bench_full_scan(bs, torch, pts, k):
     tune = bs.tuning(kernel=bs.KERNEL_COOP, block=1024, per_thread=16)
     n = int(pts.shape[0])
@@ -462,14 +539,62 @@ def bench_scene(bs, torch, np, cpu=True):
         so, _ = bs.order(pts[offs[j]:offs[j + 1]], ks[j], seed=seeds[j])
         oa, ob = plan.out_offsets[j], plan.out_offsets[j + 1]
         same &= bool(torch.equal(so, out_o[oa:ob]))
+    plan.close()
+    plan._ws = None  # the scene plan's 99 GB workspace, before the hierarchy takes its own
+    torch.cuda.empty_cache()
+    hier = bench_hierarchy(bs, torch, np, pts, offs, sizes, ks, seeds)
     res = {"objects": m, "candidates": int(pts.shape[0]), "sum_k": int(plan.total_k),
            "workspace_bytes": int(plan.workspace_bytes), "cell_target": float(tune.cell_points),
            "seconds": batch_s, "ordered_surfels_per_s": plan.total_k / batch_s,
            "plain_loop_ordered_surfels_per_s": plain_rate,
            "plain_loop_sample": "%d objects spread over the size range, %d picks, %.1f s" % (len(sample), sk, sample_s),
-           "speedup_vs_plain": (plan.total_k / plain_rate) / batch_s, "spot_check_equal_alone": same}
-    plan.close()
+           "speedup_vs_plain": (plan.total_k / plain_rate) / batch_s, "spot_check_equal_alone": same,
+           "hierarchy": hier}
     res["cpu_oracle"] = cpu_oracle_objects(pts, offs, ks, seeds, order_idx, res["sum_k"], batch_s) if cpu else None
+    return res
+
+
+def bench_hierarchy(bs, torch, np, pts, offs, sizes, ks, seeds):
+    """Sec. 3.4 bottom-up generation over the scene: its 10,000 objects are
+    leaves placed in 20 clusters of 500 (an 8^3 lattice of 2.5-unit spacing
+    per cluster, clusters on a 3^3 lattice 30 units apart); each cluster node
+    orders the surfels its objects chose, and the root the clusters' surfels.
+    Leaf k = 12% of n; an inner node keeps min(200,000, half its candidates)
+    (the paper's bound for a subtree, with its children's surfels standing in
+    for its triangles)."""
+    m = len(sizes)
+    per = 500
+    nc = (m + per - 1) // per
+    j = torch.arange(m, device=pts.device)
+    cl = j // per
+    w = j % per
+    ctr = torch.stack([(cl % 3), (cl // 3) % 3, cl // 9], 1).double() * 30.0
+    loc = torch.stack([w % 8, (w // 8) % 8, w // 64], 1).double() * 2.5
+    shift = (ctr + loc).float()
+    counts = torch.tensor([offs[i + 1] - offs[i] for i in range(m)], device=pts.device)
+    pts += torch.repeat_interleave(shift, counts, 0)
+    parents = [m + i // per for i in range(m)] + [m + nc] * nc + [-1]
+    leaf_offs = list(offs) + [offs[-1]] * (nc + 1)
+    kk = list(ks)
+    for c in range(nc):
+        kk.append(min(200000, sum(ks[c * per:(c + 1) * per]) // 2))
+    kk.append(min(200000, sum(kk[m:m + nc]) // 2))
+    sd = list(seeds) + [77 + c for c in range(nc)] + [99]
+    plan = bs.HierPlan(parents, leaf_offs, kk, sd)
+    o, r, s = plan.execute(pts)
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    o, r, s = plan.execute(pts)
+    torch.cuda.synchronize()
+    secs = time.perf_counter() - t
+    root = plan.out_offsets[-2]
+    res = {"nodes": len(parents), "levels": 3, "leaves": m, "cluster_nodes": nc,
+           "sum_k": int(plan.total_k), "cluster_k": kk[m], "root_k": kk[-1], "seconds": secs,
+           "ordered_surfels_per_s": plan.total_k / secs, "workspace_bytes": int(plan.workspace_bytes),
+           "root_sources_valid": bool((s[root:] >= 0).all())}
+    plan.close()
+    pts -= torch.repeat_interleave(shift, counts, 0)
+    log("hierarchy: %d nodes, sum k %d in %.3f s" % (len(parents), plan.total_k, secs))
     return res
 
 
@@ -617,6 +742,7 @@ def main():
     ap.add_argument("--no-full-scan", action="store_true")
     ap.add_argument("--no-config1", action="store_true")
     ap.add_argument("--no-sampler", action="store_true")
+    ap.add_argument("--no-capture", action="store_true")
     ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--no-serve", action="store_true")
     ap.add_argument("--no-scene", action="store_true")
@@ -737,6 +863,11 @@ def main():
     rec["emit"] = bench_emit(bs, torch, surf, pts, out_o)
     log("emit: %.1f us for %d records (%.0f GB/s algorithmic); r_m in %.1f us"
         % (rec["emit"]["seconds"] * 1e6, k, rec["emit"]["achieved_GBs"], rec["emit"]["median_nn_seconds"] * 1e6))
+    if not args.no_capture:
+        rec["capture"] = bench_capture(bs, torch, np, cpu=not args.no_cpu_baseline)
+        log("capture: %d candidates in %.2f ms, ordered to %d in %.1f ms" % (
+            rec["capture"]["candidates"], rec["capture"]["capture_seconds"] * 1e3, rec["capture"]["order_k"],
+            rec["capture"]["order_seconds"] * 1e3))
     if not args.no_sampler:
         rec["sampler"] = bench_sampler(bs, torch, np, pts, out_o, cpu=not args.no_cpu_baseline)
         rec["sampler"]["exact_ordering_seconds"] = ms / 1e3
