@@ -573,7 +573,9 @@ void bs_hier_plan_destroy(bs_hier_plan* plan);
  * job fits the remaining budget, builds their grids on a preprocessing
  * stream and publishes them into a device ring, from which each idle worker
  * claims the next job (largest k first within a micro-batch).  A job never
- * waits for another job to finish, only for a free worker.  Each job is timed
+ * waits for another job to finish, only for a free worker (and, if the
+ * device runs a micro-batch's preprocessing behind the resident workers, for
+ * the stop that stall_us triggers).  Each job is timed
  * from submit to the moment its completion flag (written by its worker into
  * pinned host memory) is observed.  Results are bit-identical to bs_order on
  * the same job.  Workers exit a few milliseconds after the last job and are
@@ -589,7 +591,11 @@ typedef struct {
     float cell_points;           /* grid cell target, 0 = 8 */
     int32_t workgroups;          /* resident 1024-thread ordering workers (each holds a whole
                                     compute unit), 0 = half the compute units */
-    int32_t reserved[6];         /* must be zero */
+    int32_t stall_us;            /* a micro-batch whose preprocessing has not finished this long
+                                    (plus 0.2 us per 1,000 candidates) after its admission stops
+                                    the workers, so that preprocessing queued behind them on the
+                                    device can run; they restart once it is done.  0 = 2,000 */
+    int32_t reserved[5];         /* must be zero */
 } bs_server_config;
 
 typedef struct {

@@ -694,7 +694,7 @@ class ServerConfig(ctypes.Structure):
     _fields_ = [("hbm_budget_bytes", ctypes.c_size_t), ("device", ctypes.c_int32),
                 ("max_inflight", ctypes.c_int32), ("max_jobs_per_batch", ctypes.c_int32),
                 ("poll_us", ctypes.c_int32), ("cell_points", ctypes.c_float),
-                ("workgroups", ctypes.c_int32), ("reserved", ctypes.c_int32 * 6)]
+                ("workgroups", ctypes.c_int32), ("stall_us", ctypes.c_int32), ("reserved", ctypes.c_int32 * 5)]
 
 
 class Job(ctypes.Structure):
@@ -723,11 +723,11 @@ class Server:
 
     def __init__(self, hbm_budget_bytes: int, device: int = 0, max_inflight: int = 0,
                  max_jobs_per_batch: int = 512, poll_us: int = 50, cell_points: float = 0.0,
-                 workgroups: int = 0):
+                 workgroups: int = 0, stall_us: int = 0):
         lib = load()
         self._lib = lib
         cfg = ServerConfig(int(hbm_budget_bytes), device, max_inflight, max_jobs_per_batch, poll_us, cell_points,
-                           workgroups)
+                           workgroups, stall_us)
         self._srv = ctypes.c_void_p()
         _check(lib.bs_server_create(ctypes.byref(cfg), ctypes.byref(self._srv)))
         self._keep = {}

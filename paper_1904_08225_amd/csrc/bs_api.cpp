@@ -15,8 +15,6 @@
 namespace bs {
 
 namespace {
-thread_local char g_msg[512] = "";
-
 struct DeviceInfo {
     int cus = 0;
 };
@@ -175,13 +173,7 @@ size_t workspace_for(int64_t n, const Plan& p) {
 
 }  // namespace
 
-int set_error(int code, const char* fmt, ...) {
-    va_list ap;
-    va_start(ap, fmt);
-    vsnprintf(g_msg, sizeof(g_msg), fmt, ap);
-    va_end(ap);
-    return code;
-}
+
 
 }  // namespace bs
 
@@ -189,24 +181,7 @@ using namespace bs;
 
 extern "C" {
 
-const char* bs_error_string(int code) {
-    switch (code) {
-        case BS_OK: return "BS_OK";
-        case BS_ERR_INVALID_ARG: return "BS_ERR_INVALID_ARG";
-        case BS_ERR_OUT_OF_MEMORY: return "BS_ERR_OUT_OF_MEMORY";
-        case BS_ERR_HIP: return "BS_ERR_HIP";
-        case BS_ERR_OVER_BUDGET: return "BS_ERR_OVER_BUDGET";
-        case BS_ERR_NOT_READY: return "BS_ERR_NOT_READY";
-        case BS_ERR_UNSUPPORTED: return "BS_ERR_UNSUPPORTED";
-        case BS_ERR_TIMEOUT: return "BS_ERR_TIMEOUT";
-        case BS_ERR_DEVICE: return "BS_ERR_DEVICE";
-        default: return "BS_ERR_UNKNOWN";
-    }
-}
 
-const char* bs_last_error_message(void) { return g_msg; }
-
-const char* bs_version(void) { return "0.1.0"; }
 
 int64_t bs_start_index(uint64_t seed, int64_t n) {
     if (n < 1) return -1;

@@ -81,3 +81,46 @@ def test_server_budget_admission_and_rejection(hip):
         eo, _ = oracle.greedy32_grid(P, 2000, oracle.start_index(s, 50000))
         assert np.array_equal(oo.cpu().numpy(), eo)
     srv.close()
+
+
+def test_server_later_job_overlaps_earlier(hip):
+    """A job admitted while a long one is on the device finishes first (it
+    only waits for a free worker), and both equal the oracle."""
+    import torch
+    srv = hip.Server(hbm_budget_bytes=8 << 30, max_jobs_per_batch=8)
+    big = synth.cad_part(1_000_000, seed=12, count=60, device="cuda").points.contiguous()
+    kb = 200_000
+    ob = torch.empty(kb, dtype=torch.int32, device="cuda")
+    tb = srv.submit(big, kb, 5, ob)
+    time.sleep(0.02)  # the long job is claimed
+    small = synth.cad_part(3000, seed=13, count=10).points.cuda()
+    os_ = torch.empty(500, dtype=torch.int32, device="cuda")
+    ts = srv.submit(small, 500, 6, os_)
+    srv.wait(ts, timeout_us=60_000_000)
+    assert not srv.poll(tb), "the small job waited for the long one"
+    srv.wait(tb, timeout_us=120_000_000)
+    srv.close()
+    P = small.cpu().numpy()
+    eo, _ = oracle.greedy32(P, 500, oracle.start_index(6, 3000))
+    assert np.array_equal(os_.cpu().numpy(), eo)
+    B = big.cpu().numpy()
+    eo, _ = oracle.greedy32_grid(B, kb, oracle.start_index(5, B.shape[0]))
+    assert np.array_equal(ob.cpu().numpy(), eo)
+
+
+def test_server_producer_event_orders_the_copy(hip):
+    """Points written by a kernel on the caller's stream just before submit:
+    the server reads them after that work (the job's ready event)."""
+    import torch
+    srv = hip.Server(hbm_budget_bytes=1 << 30)
+    P = synth.cad_part(40000, seed=14, count=20).points
+    src = P.cuda()
+    dst = torch.zeros_like(src)
+    torch.cuda.synchronize()
+    dst.copy_(src * 1.0)  # queued on the current stream, not waited for
+    oo = torch.empty(3000, dtype=torch.int32, device="cuda")
+    t = srv.submit(dst, 3000, 9, oo)
+    srv.wait(t, timeout_us=60_000_000)
+    srv.close()
+    eo, _ = oracle.greedy32_grid(P.numpy(), 3000, oracle.start_index(9, 40000))
+    assert np.array_equal(oo.cpu().numpy(), eo)
