@@ -311,8 +311,23 @@ int64_t bs_prefix_for_radius(const float* h_radius, int64_t k, float r);
  *   1 <= k <= n  the ordering to tune for; seed as in bs_order
  *   out_tuning   host: receives the chosen configuration
  * Synchronous: allocates scratch from the stream-ordered pool, runs the
- * candidates on `stream` and waits for them.  Errors: BS_ERR_INVALID_ARG,
- * BS_ERR_OUT_OF_MEMORY, BS_ERR_UNSUPPORTED (no candidate fits), BS_ERR_HIP.
+ * candidates on `stream` and waits for them.  Errors: BS_ERR_INVALID_ARG
+ * (also: the tuning cache file named below could not be written; the
+ * in-memory entry and *out_tuning are still set), BS_ERR_OUT_OF_MEMORY,
+ * BS_ERR_UNSUPPORTED (no candidate fits), BS_ERR_HIP.
+ *
+ * Environment:
+ *   BS_TUNE_CACHE=path   bs_autotune also records its winner in this text
+ *                        file, one line per (GPU architecture, floor(log2 n),
+ *                        floor(log2 k)); calls with a NULL tuning read it when
+ *                        the in-memory table has no entry for their size, so
+ *                        a later process reuses earlier tuning runs.
+ *   BS_FORCE_KERNEL=wg|scan|several|grid
+ *                        calls with a NULL tuning take this kernel instead of
+ *                        the automatic choice (one resident workgroup, the
+ *                        cooperative full scan with one pick per step or with
+ *                        several, the grid-pruned kernel).  Any other value
+ *                        makes them fail with BS_ERR_INVALID_ARG.
  */
 int bs_autotune(const float* d_points, int64_t n, int64_t k, uint64_t seed,
                 bs_tuning* out_tuning, void* stream);
@@ -321,7 +336,8 @@ int bs_autotune(const float* d_points, int64_t n, int64_t k, uint64_t seed,
  * or BS_ERR_NOT_READY when that size has not been tuned. */
 int bs_autotune_lookup(int64_t n, int64_t k, bs_tuning* out_tuning);
 
-/* Forget every tuned entry (all devices). */
+/* Forget every tuned entry (all devices); the next lookup reads the
+ * BS_TUNE_CACHE file again. */
 void bs_autotune_clear(void);
 
 /*

@@ -5,6 +5,7 @@
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <mutex>
 
@@ -99,7 +100,13 @@ bool choose_several_shape(int64_t n, int cus, int want_block, int want_pt, int w
 // Resolve the kernel and its launch shape.
 int plan_single(int64_t n, int64_t k, const bs_tuning* t, Plan* p) {
     bs_tuning tuned;
-    if (!t && tuned_lookup(n, k, &tuned)) t = &tuned;  // the autotuner's choice for this size
+    if (!t) {
+        const int f = forced_tuning(&tuned);  // environment override of the automatic choice
+        if (f < 0)
+            return set_error(BS_ERR_INVALID_ARG, "BS_FORCE_KERNEL=%s is not one of wg, scan, several, grid",
+                             std::getenv("BS_FORCE_KERNEL"));
+        if (f > 0 || tuned_lookup(n, k, &tuned)) t = &tuned;  // else the autotuner's choice for this size
+    }
     const int cus = device_cus() > 0 ? device_cus() : 256;
     const int want = t ? t->kernel : BS_KERNEL_AUTO;
     const int wb = t ? t->block : 0, wp = t ? t->per_thread : 0, wg = t ? t->groups : 0;

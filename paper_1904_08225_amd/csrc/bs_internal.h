@@ -135,5 +135,6 @@ int order_impl(const float* d_points, int64_t n, int64_t k, uint64_t seed, int64
 
 // The autotuned configuration for (n, k) on the current device, if any.
 bool tuned_lookup(int64_t n, int64_t k, bs_tuning* out);
+int forced_tuning(bs_tuning* out);
 
 }  // namespace bs

@@ -10,23 +10,28 @@
 // Design (MI355X): the candidates, in Morton order, stay in VGPRs of up to
 // 256 cooperative workgroups for the whole ordering; each wavefront holds
 // 64*P consecutive ones in P slabs of 64, split into two groups where the
-// Morton codes first differ, each group and each slab with a box.  Every workgroup
-// is a bucket: it publishes its three best keys (with coordinates and sorted
-// positions) and value bits R that bound all its other keys (the best key a
-// wavefront keeps back, or a wavefront's third best when all three of its
-// listed keys are published).  Every workgroup reads all records and makes the same
-// selection: with tau the fixed point of "tau <- max R over the workgroups
-// holding an entry above tau" (from the top workgroup's R), the entries
+// Morton codes first differ, each group and each slab with a box.  Each
+// wavefront keeps a chain: c1, its best key; c2, its best key once c1's ball
+// has lowered the others (the value in c2's key includes that update); and
+// the bound of all its other values once both are taken.  Every workgroup
+// is a bucket: it publishes its three best chain keys (with coordinates and
+// sorted positions) and value bits R that bound every value it does not
+// offer (the largest chain key it keeps back, and every wavefront's bound
+// after its chain: a wavefront's published keys are a prefix of its chain).
+// Every workgroup reads all records and makes the same selection: with tau
+// the fixed point of "tau <- max R over the workgroups holding an entry
+// above tau" (from the top workgroup's R), the entries
 // above tau (and the top) are exactly the prefix that the sequential rule
 // accepts up to distance conflicts -- every member exceeds R of every
 // workgroup with a member, and everything else lies below every member.
 // Members are ranked among themselves, the first `picks` kept, and the
-// first one that an earlier member lowers ends the step.  The next step
-// applies all accepted picks at once, m <- min(m, d2(., q_1), ...), equal to
+// first one that an earlier member lowers ends the step (an earlier key of
+// the same chain never does: the chain value is at most that distance).
+// The next step applies all accepted picks at once, m <- min(m, d2(., q_1), ...), equal to
 // the sequential updates because min is exact and order-free; a group or
 // slab whose box no pick's ball reaches (binary32 box lower bound >= m of the
 // pick, which bounds every remaining m at its step) skips the update, and a
-// wavefront none of whose m changed keeps its cached three best keys.
+// wavefront where neither chain key's m changed keeps its cached chain.
 #pragma clang fp contract(off)
 
 #include <hip/hip_runtime.h>
@@ -104,6 +109,9 @@ struct WaveBox {
 };
 __device__ __forceinline__ float uniform_f32(float v) {
     return __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(v)));
+}
+__device__ __forceinline__ float uniform_at(float v, int l) {
+    return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), l));
 }
 __device__ __forceinline__ float wave_min_f32(float v) {
 #pragma unroll
@@ -191,6 +199,16 @@ __device__ __forceinline__ void insert3(uint64_t kk, uint64_t& a1, uint64_t& a2,
     a1 = g1 ? kk : a1;
 }
 
+// The slot of this lane holding the live candidate with original index id
+// (ids are unique; padding and chosen slots have m < 0); 0 if none.
+template <int BLOCK, int P>
+__device__ __forceinline__ int slot_of_impl(const float (&m)[P], const uint32_t* ids, uint32_t id) {
+    int js = 0;
+#pragma unroll
+    for (int j = 0; j < P; ++j) js = (m[j] >= 0.f && ids[j * BLOCK] == id) ? j : js;
+    return js;
+}
+
 // Points: lane l of wavefront w in workgroup g holds sorted positions
 // g*BLOCK*P + w*64*P + j*64 + l, j < P.
 template <int BLOCK, int P>
@@ -202,9 +220,10 @@ __global__ void __launch_bounds__(BLOCK)
                    uint32_t spin_limit) {
     constexpr int NW = BLOCK / 64;
     static_assert(kMpMaxPicks <= 128, "two passes of one lane per pick");
-    __shared__ __align__(16) uint64_t s_w[NW][3];  // per wavefront: its three best keys (cached)
+    __shared__ __align__(16) uint64_t s_w[NW][2];  // per wavefront: its chain's two keys (cached)
+    __shared__ uint32_t s_c3[NW];                  // and the bound after them (value bits)
     __shared__ uint32_t s_ent[6 * kMpEntries];     // the record's entry words, staged by rank
-    __shared__ float4 s_wc[NW][3];                 // and x, y, z, sorted position of each
+    __shared__ float4 s_wc[NW][2];                 // x, y, z, sorted position of each chain key
     __shared__ uint32_t s_rw[kMpMaxGroups * kMpWords];  // every workgroup's record (low words)
     __shared__ __align__(16) uint64_t s_mk[kMpEntries * kMpMaxGroups + 2];  // members: keys
     __shared__ int s_mi[kMpEntries * kMpMaxGroups];  // members: entry index
@@ -213,6 +232,7 @@ __global__ void __launch_bounds__(BLOCK)
     __shared__ int s_ppos[kMpMaxPicks];            // sorted position
     __shared__ uint32_t s_id[P * BLOCK];           // original index of each held candidate
     __shared__ float4 s_slo[NW][P], s_shi[NW][P];  // box of each slab of 64 (x, y, z; w unused)
+    __shared__ float4 s_gb[NW][4];                 // boxes of the wavefront's two groups (lo, hi each)
     __shared__ int s_kfail, s_na, s_abort;
 #ifdef BS_PHASE_PROF
     __shared__ int s_reach;
@@ -297,7 +317,8 @@ __global__ void __launch_bounds__(BLOCK)
             s_shi[wave][j] = make_float4(hx, hy, hz, 0.f);
         }
     }
-    WaveBox ba, bb;  // groups p < split, p >= split (uniform)
+    // boxes of the groups p < split, p >= split, in LDS (s_gb: lo, hi of
+    // each), which keeps registers for the candidates
     {
         float lo[2][3], hi[2][3];
 #pragma unroll
@@ -320,17 +341,22 @@ __global__ void __launch_bounds__(BLOCK)
         }
 #pragma unroll
         for (int gi = 0; gi < 2; ++gi) {
-            WaveBox& b = gi == 0 ? ba : bb;
+            WaveBox b;
 #pragma unroll
             for (int d = 0; d < 3; ++d) {
                 b.lo[d] = wave_min_f32(lo[gi][d]);
                 b.hi[d] = wave_max_f32(hi[gi][d]);
             }
+            if (lane == 0) {
+                s_gb[wave][2 * gi] = make_float4(b.lo[0], b.lo[1], b.lo[2], 0.f);
+                s_gb[wave][2 * gi + 1] = make_float4(b.hi[0], b.hi[1], b.hi[2], 0.f);
+            }
         }
     }
     if (lane == 0) {
-        s_w[wave][0] = s_w[wave][1] = s_w[wave][2] = 0ull;
-        s_wc[wave][0] = s_wc[wave][1] = s_wc[wave][2] = make_float4(0.f, 0.f, 0.f, 0.f);
+        s_w[wave][0] = s_w[wave][1] = 0ull;
+        s_c3[wave] = 0u;
+        s_wc[wave][0] = s_wc[wave][1] = make_float4(0.f, 0.f, 0.f, __int_as_float(-1));
     }
     if (tid == 0) {
         const int sp = *start_pos;
@@ -372,8 +398,9 @@ __global__ void __launch_bounds__(BLOCK)
             bool reach_a = false, reach_b = false, own = false;
             if (qi < K) {
                 const float4 q = s_pk[qi];
-                reach_a = wave_box_lower(ba, q.x, q.y, q.z) < q.w;
-                reach_b = wave_box_lower(bb, q.x, q.y, q.z) < q.w;
+                const float4 alo = s_gb[wave][0], ahi = s_gb[wave][1], blo = s_gb[wave][2], bhi = s_gb[wave][3];
+                reach_a = box_lower(alo.x, alo.y, alo.z, ahi.x, ahi.y, ahi.z, q.x, q.y, q.z) < q.w;
+                reach_b = box_lower(blo.x, blo.y, blo.z, bhi.x, bhi.y, bhi.z, q.x, q.y, q.z) < q.w;
                 const int off = s_ppos[qi] - wbase;
                 own = off >= 0 && off < 64 * P;
             }
@@ -385,13 +412,14 @@ __global__ void __launch_bounds__(BLOCK)
         if (lane == 0) atomicAdd(&s_reach, __popcll(ra[0] | rb[0]) + __popcll(ra[1] | rb[1]));
 #endif
         if ((ra[0] | ra[1] | rb[0] | rb[1] | om[0] | om[1]) != 0ull || step == 1) {  // step 1 fills every cache
-            // slots of this lane holding one of the wavefront's cached best
+            // slots of this lane holding one of the wavefront's two chain
             // keys (their sorted positions are cached with them): only a
-            // lowered m there can change the three best, since every other m
-            // lies below the third and only drops
+            // lowered m there can change the chain; any other m only drops,
+            // which keeps both chain keys the largest and the bound an
+            // upper bound
             uint32_t topm = 0u;
 #pragma unroll
-            for (int e = 0; e < 3; ++e) {
+            for (int e = 0; e < 2; ++e) {
                 const int cp = __float_as_int(s_wc[wave][e].w) - wbase;
                 topm |= (cp >= 0 && cp < 64 * P && (cp & 63) == lane) ? 1u << (cp >> 6) : 0u;
             }
@@ -428,54 +456,78 @@ __global__ void __launch_bounds__(BLOCK)
                     for (int j = 0; j < P; ++j)
                         if (off == j * 64 + lane) m[j] = -1.f;
                 }
-            // the cached best keys stay exact unless one of their m dropped
-            // or a pick (always one of them) was taken here
+            // the cached chain stays exact unless the m of one of its keys
+            // dropped or a pick (always one of them) was taken here
             if (__ballot((lowm & topm) != 0u) != 0ull || (om[0] | om[1]) != 0ull || step == 1) {
-                uint64_t a1 = 0, a2 = 0, a3 = 0;  // this lane's three best
-#pragma unroll
-                for (int j = 0; j < P; ++j) insert3(m[j] >= 0.f ? make_key(m[j], s_id[j * BLOCK + tid]) : 0ull, a1, a2, a3);
-                // the wavefront's three best: three plain maxima, the lane
-                // holding each one shifting it out (keys are unique)
-                const uint64_t w1 = wave_max_u64(a1);
-                if (a1 == w1) {
-                    a1 = a2;
-                    a2 = a3;
-                }
-                const uint64_t w2 = wave_max_u64(a1);
-                if (a1 == w2) a1 = a2;
-                const uint64_t w3 = wave_max_u64(a1);
-                // coordinates of the three best: the slots whose value matches
-                // one of them (keys are unique: the index decides after)
-                uint32_t vm = 0u;
-                const uint32_t w1v = uint32_t(w1 >> 32), w2v = uint32_t(w2 >> 32), w3v = uint32_t(w3 >> 32);
+                // c1: the wavefront's best key, and the slot holding it
+                uint64_t bk = 0;
 #pragma unroll
                 for (int j = 0; j < P; ++j) {
-                    const uint32_t vb = __float_as_uint(m[j]);
-                    const bool cand = m[j] >= 0.f && ((w1 != 0ull && vb == w1v) || (w2 != 0ull && vb == w2v) ||
-                                                      (w3 != 0ull && vb == w3v));
-                    vm |= uint32_t(cand) << j;
+                    const uint64_t kk = m[j] >= 0.f ? make_key(m[j], s_id[j * BLOCK + tid]) : 0ull;
+                    bk = kk > bk ? kk : bk;
                 }
-                while (vm != 0u) {  // a few lanes, a few slots each
-                    const int js = __builtin_ctz(vm);
-                    vm &= vm - 1u;
-                    float x = px[0], y = py[0], z = pz[0], mj = m[0];
+                const uint64_t c1 = wave_max_u64(bk);
+                uint64_t c2 = 0ull;
+                uint32_t c3 = 0u;
+                float4 e1 = make_float4(0.f, 0.f, 0.f, __int_as_float(-1));
+                float4 e2 = e1;
+                if (c1 != 0ull) {
+                    const int l1 = __builtin_ctzll(__ballot(bk == c1));  // keys are unique
+                    const int j1 = __builtin_amdgcn_readlane(slot_of_impl<BLOCK, P>(m, s_id + tid, key_id(c1)), l1);
+                    float x = px[0], y = py[0], z = pz[0];
 #pragma unroll
-                    for (int j = 1; j < P; ++j) {
-                        const bool hit = js == j;
-                        x = hit ? px[j] : x;
-                        y = hit ? py[j] : y;
-                        z = hit ? pz[j] : z;
-                        mj = hit ? m[j] : mj;
+                    for (int j = 1; j < P; ++j)
+                        if (j1 == j) {  // uniform
+                            x = px[j];
+                            y = py[j];
+                            z = pz[j];
+                        }
+                    const float x1 = uniform_at(x, l1), y1 = uniform_at(y, l1), z1 = uniform_at(z, l1);
+                    e1 = make_float4(x1, y1, z1, __int_as_float(wbase + j1 * 64 + l1));
+                    // c2: the best key once c1's ball has lowered the others;
+                    // the lane's two largest of those values (bits) on the side
+                    uint64_t bk2 = 0;
+                    uint32_t t1 = 0u, t2 = 0u;
+#pragma unroll
+                    for (int j = 0; j < P; ++j) {
+                        const float d = dist2(px[j], py[j], pz[j], x1, y1, z1);
+                        const float v = d < m[j] ? d : m[j];
+                        const bool live = m[j] >= 0.f && !(lane == l1 && j == j1);
+                        const uint64_t kk = live ? make_key(v, s_id[j * BLOCK + tid]) : 0ull;
+                        bk2 = kk > bk2 ? kk : bk2;
+                        const uint32_t vb = live ? __float_as_uint(v) : 0u;
+                        t2 = max(t2, min(t1, vb));
+                        t1 = max(t1, vb);
                     }
-                    const uint64_t kk = make_key(mj, s_id[js * BLOCK + tid]);
-                    if (kk == w1 || kk == w2 || kk == w3)
-                        s_wc[wave][kk == w1 ? 0 : (kk == w2 ? 1 : 2)] =
-                            make_float4(x, y, z, __int_as_float(wbase + js * 64 + lane));
+                    c2 = wave_max_u64(bk2);
+                    if (c2 != 0ull) {
+                        const int l2 = __builtin_ctzll(__ballot(bk2 == c2));
+                        const int j2 = __builtin_amdgcn_readlane(slot_of_impl<BLOCK, P>(m, s_id + tid, key_id(c2)), l2);
+                        x = px[0];
+                        y = py[0];
+                        z = pz[0];
+#pragma unroll
+                        for (int j = 1; j < P; ++j)
+                            if (j2 == j) {
+                                x = px[j];
+                                y = py[j];
+                                z = pz[j];
+                            }
+                        const float x2 = uniform_at(x, l2), y2 = uniform_at(y, l2), z2 = uniform_at(z, l2);
+                        e2 = make_float4(x2, y2, z2, __int_as_float(wbase + j2 * 64 + l2));
+                        // c3: bound of every other value once c1 and c2 are
+                        // taken -- the largest value after c1's update other
+                        // than c2's (c2's ball can only lower them further)
+                        const uint32_t b3 = lane == l2 ? t2 : t1;
+                        c3 = wave_max_u32(b3);
+                    }
                 }
                 if (lane == 0) {
-                    s_w[wave][0] = w1;
-                    s_w[wave][1] = w2;
-                    s_w[wave][2] = w3;
+                    s_w[wave][0] = c1;
+                    s_w[wave][1] = c2;
+                    s_c3[wave] = c3;
+                    s_wc[wave][0] = e1;
+                    s_wc[wave][1] = e2;
                 }
             }
         }
@@ -488,17 +540,17 @@ __global__ void __launch_bounds__(BLOCK)
         lds_barrier();
         if (tid == 0) s_reach = 0;
 #endif
-        // 2. wavefront 0: the workgroup's three best keys become its entries,
-        // with their data from the wavefronts that hold them, and R bounds
-        // every key it does not offer; its record is one word a lane
+        // 2. wavefront 0: the workgroup's three best chain keys become its
+        // entries, with their data from the wavefronts that hold them, and R
+        // bounds every value it does not offer; its record is one word a lane
         const uint64_t tag = uint64_t(step) << 32;
         if (wave == 0) {
-            // listed key i of wavefront w on lane 3 w + i, ranked among all
+            // chain key i of wavefront w on lane 2 w + i, ranked among all
             // listed keys by counting the larger ones (keys are unique, 0 =
             // none); ranks 0, 1, 2 are the entries
-            constexpr int NK = 3 * NW;
+            constexpr int NK = 2 * NW;
             static_assert(NK % 2 == 0 && NK <= 64 && 6 * kMpEntries <= 64, "one key a lane");
-            const int kw = lane / 3, ki = lane - 3 * (lane / 3);
+            const int kw = lane >> 1, ki = lane & 1;
             const uint64_t kv = lane < NK ? s_w[kw][ki] : 0ull;
             const ulonglong2* sw2 = reinterpret_cast<const ulonglong2*>(&s_w[0][0]);
             int rank = 0;
@@ -507,11 +559,14 @@ __global__ void __launch_bounds__(BLOCK)
                 const ulonglong2 b = sw2[c];
                 rank += int(b.x > kv) + int(b.y > kv);
             }
-            // R: the largest listed key kept back, and each wavefront's third
-            // (which bounds the keys it did not list; a wavefront's entries
-            // are a prefix of its list)
-            const bool kept = kv != 0 && (rank >= kMpEntries || ki == 2);
-            const uint32_t rg = wave_max_u32(kept ? uint32_t(kv >> 32) : 0u);
+            // R: the largest listed key kept back, and every wavefront's
+            // bound after its two chain keys (a wavefront's entries are a
+            // prefix of its chain, so its next listed key or that bound
+            // caps the rest of it)
+            const bool kept = kv != 0 && rank >= kMpEntries;
+            uint32_t rv = kept ? uint32_t(kv >> 32) : 0u;
+            if (lane < NW) rv = max(rv, s_c3[lane]);
+            const uint32_t rg = wave_max_u32(rv);
             const int nz = __popcll(__ballot(kv != 0));
             if (kv != 0 && rank < kMpEntries) {
                 const float4 c = s_wc[kw][ki];

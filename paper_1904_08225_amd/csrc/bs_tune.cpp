@@ -7,9 +7,12 @@
 
 #include <algorithm>
 #include <cmath>
+#include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <map>
 #include <mutex>
+#include <string>
 #include <tuple>
 #include <vector>
 
@@ -78,6 +81,97 @@ struct Timer {
     }
 };
 
+// Persistent tuning cache (environment BS_TUNE_CACHE = path of a text file).
+// One line per size class and GPU architecture:
+//   bluesurfels-tune-v1 <arch> <log2 n> <log2 k> <kernel> <block> <per_thread>
+//                       <groups> <cell_points> <picks> <lead_picks> <batch_wide>
+// bs_autotune rewrites the file with its winner (replacing the line of the
+// same key, through a temporary file and a rename); the automatic choice
+// reads it when its in-memory table has no entry.  Malformed lines are
+// skipped.
+constexpr const char* kCacheTag = "bluesurfels-tune-v1";
+using CacheKey = std::tuple<std::string, int, int>;
+std::map<CacheKey, bs_tuning> g_cache;  // entries of the loaded file
+std::string g_cache_path;               // file g_cache was loaded from ("" = none)
+bool g_cache_loaded = false;
+
+std::string device_arch(int dev) {
+    hipDeviceProp_t p;
+    if (hipGetDeviceProperties(&p, dev) != hipSuccess) return std::string();
+    std::string a(p.gcnArchName);
+    const size_t colon = a.find(':');
+    return colon == std::string::npos ? a : a.substr(0, colon);
+}
+
+bool parse_cache_line(const char* line, CacheKey* key, bs_tuning* t) {
+    char tag[32], arch[64];
+    int l2n = 0, l2k = 0;
+    bs_tuning v;
+    std::memset(&v, 0, sizeof(v));
+    const int got = std::sscanf(line, "%31s %63s %d %d %d %d %d %d %f %d %d %d", tag, arch, &l2n, &l2k, &v.kernel,
+                                &v.block, &v.per_thread, &v.groups, &v.cell_points, &v.picks, &v.lead_picks,
+                                &v.batch_wide);
+    if (got != 12 || std::strcmp(tag, kCacheTag) != 0) return false;
+    if (l2n < 0 || l2n > 31 || l2k < 0 || l2k > 31 || v.kernel < BS_KERNEL_AUTO || v.kernel > BS_KERNEL_GRID ||
+        v.block < 0 || v.per_thread < 0 || v.groups < 0 || !(v.cell_points >= 0.f) || v.picks < 0 ||
+        v.lead_picks < -1 || v.batch_wide < -1)
+        return false;
+    *key = CacheKey(arch, l2n, l2k);
+    *t = v;
+    return true;
+}
+
+std::map<CacheKey, bs_tuning> read_cache_file(const std::string& path) {
+    std::map<CacheKey, bs_tuning> m;
+    FILE* f = std::fopen(path.c_str(), "r");
+    if (!f) return m;
+    char line[512];
+    while (std::fgets(line, sizeof(line), f)) {
+        CacheKey key;
+        bs_tuning t;
+        if (parse_cache_line(line, &key, &t)) m[key] = t;
+    }
+    std::fclose(f);
+    return m;
+}
+
+// caller holds g_tune_mu
+void load_cache_locked() {
+    const char* env = std::getenv("BS_TUNE_CACHE");
+    const std::string path = env ? env : "";
+    if (g_cache_loaded && path == g_cache_path) return;
+    g_cache = path.empty() ? std::map<CacheKey, bs_tuning>() : read_cache_file(path);
+    g_cache_path = path;
+    g_cache_loaded = true;
+}
+
+// caller holds g_tune_mu; returns false if the file could not be written
+bool store_cache_locked(const std::string& arch, int64_t n, int64_t k, const bs_tuning& t) {
+    const char* env = std::getenv("BS_TUNE_CACHE");
+    if (!env || !*env || arch.empty()) return true;
+    const std::string path = env;
+    std::map<CacheKey, bs_tuning> m = read_cache_file(path);  // other processes' entries too
+    m[CacheKey(arch, ilog2(std::max<int64_t>(n, 1)), ilog2(std::max<int64_t>(k, 1)))] = t;
+    const std::string tmp = path + ".tmp";
+    FILE* f = std::fopen(tmp.c_str(), "w");
+    if (!f) return false;
+    bool ok = true;
+    for (const auto& kv : m) {
+        const bs_tuning& v = kv.second;
+        ok = ok && std::fprintf(f, "%s %s %d %d %d %d %d %d %.9g %d %d %d\n", kCacheTag,
+                                std::get<0>(kv.first).c_str(), std::get<1>(kv.first), std::get<2>(kv.first),
+                                v.kernel, v.block, v.per_thread, v.groups, double(v.cell_points), v.picks,
+                                v.lead_picks, v.batch_wide) > 0;
+    }
+    ok = (std::fclose(f) == 0) && ok;
+    if (ok) ok = std::rename(tmp.c_str(), path.c_str()) == 0;
+    if (!ok) std::remove(tmp.c_str());
+    g_cache = m;
+    g_cache_path = path;
+    g_cache_loaded = true;
+    return ok;
+}
+
 }  // namespace
 
 bool tuned_lookup(int64_t n, int64_t k, bs_tuning* out) {
@@ -85,9 +179,33 @@ bool tuned_lookup(int64_t n, int64_t k, bs_tuning* out) {
     if (hipGetDevice(&dev) != hipSuccess) return false;
     std::lock_guard<std::mutex> lk(g_tune_mu);
     auto it = g_table.find(table_key(dev, n, k));
-    if (it == g_table.end()) return false;
-    *out = it->second;
+    if (it != g_table.end()) {
+        *out = it->second;
+        return true;
+    }
+    load_cache_locked();
+    if (g_cache.empty()) return false;
+    auto c = g_cache.find(CacheKey(device_arch(dev), ilog2(std::max<int64_t>(n, 1)), ilog2(std::max<int64_t>(k, 1))));
+    if (c == g_cache.end()) return false;
+    *out = c->second;
     return true;
+}
+
+// Environment BS_FORCE_KERNEL overrides the automatic choice (callers that
+// pass no tuning): "wg" one resident workgroup, "scan" the cooperative full
+// scan with one pick per step, "several" the cooperative scan with several
+// exact picks per step, "grid" the grid-pruned kernel.  Returns 0 when unset,
+// 1 with *out filled, -1 for an unknown value.
+int forced_tuning(bs_tuning* out) {
+    const char* env = std::getenv("BS_FORCE_KERNEL");
+    if (!env || !*env) return 0;
+    const std::string v = env;
+    if (v == "wg") *out = make_tuning(BS_KERNEL_WG, 0, 0, 0.f, 0);
+    else if (v == "scan") *out = make_tuning(BS_KERNEL_COOP, 0, 0, 0.f, 1);
+    else if (v == "several") *out = make_tuning(BS_KERNEL_COOP, 1024, 0, 0.f, 128);
+    else if (v == "grid") *out = make_tuning(BS_KERNEL_GRID, 0, 0, 0.f, 0);
+    else return -1;
+    return 1;
 }
 
 }  // namespace bs
@@ -161,11 +279,16 @@ extern "C" int bs_autotune(const float* d_points, int64_t n, int64_t k, uint64_t
     if (!std::isfinite(best_ms)) return set_error(BS_ERR_UNSUPPORTED, "autotune: no configuration ran");
     int dev = 0;
     (void)hipGetDevice(&dev);
+    const std::string arch = device_arch(dev);
+    bool stored = true;
     {
         std::lock_guard<std::mutex> lk(g_tune_mu);
         g_table[table_key(dev, n, k)] = best;
+        stored = store_cache_locked(arch, n, k, best);
     }
     *out_tuning = best;
+    if (!stored) return set_error(BS_ERR_INVALID_ARG, "autotune: could not write the tuning cache %s",
+                                  std::getenv("BS_TUNE_CACHE"));
     return BS_OK;
 }
 
@@ -178,6 +301,8 @@ extern "C" int bs_autotune_lookup(int64_t n, int64_t k, bs_tuning* out_tuning) {
 extern "C" void bs_autotune_clear(void) {
     std::lock_guard<std::mutex> lk(g_tune_mu);
     g_table.clear();
+    g_cache.clear();
+    g_cache_loaded = false;  // the next lookup reads the cache file again
 }
 
 extern "C" int bs_batch_autotune(const int64_t* h_offsets, const int64_t* h_k, const uint64_t* h_seed,

@@ -152,6 +152,30 @@ def test_plan_describe(lib):
     assert lib.bs_plan_describe(10, 5, None, None) == bs.BS_ERR_INVALID_ARG
 
 
+def test_forced_kernel_override(lib, monkeypatch):
+    """BS_FORCE_KERNEL replaces the automatic choice of calls that pass no
+    tuning; an explicit tuning still wins, and an unknown value is an error."""
+    lib.bs_autotune_clear()
+    for name, kernel, picks in (("wg", bs.KERNEL_WG, None), ("scan", bs.KERNEL_COOP, 1),
+                                ("several", bs.KERNEL_COOP, 128), ("grid", bs.KERNEL_GRID, 16)):
+        monkeypatch.setenv("BS_FORCE_KERNEL", name)
+        n = 4000 if name == "wg" else 100000
+        p = bs.plan_describe(n, 1000)
+        assert p.kernel == kernel, name
+        if picks is not None:
+            assert p.picks == picks, name
+    monkeypatch.setenv("BS_FORCE_KERNEL", "grid")
+    p = bs.plan_describe(100000, 1000, bs.tuning(kernel=2, per_thread=16, picks=8))
+    assert p.kernel == bs.KERNEL_COOP and p.picks == 8
+    monkeypatch.setenv("BS_FORCE_KERNEL", "fastest")
+    out = bs.Tuning()
+    assert lib.bs_plan_describe(100000, 1000, None, ctypes.byref(out)) == bs.BS_ERR_INVALID_ARG
+    assert b"BS_FORCE_KERNEL" in lib.bs_last_error_message()
+    monkeypatch.delenv("BS_FORCE_KERNEL")
+    p = bs.plan_describe(100000, 1000)
+    assert (p.kernel, p.per_thread, p.groups) == (bs.KERNEL_COOP, 1, 98)
+
+
 def test_prefix_host_functions(lib):
     """bs_prefix_length equals the oracle's formula; bs_prefix_for_radius
     equals a linear scan over the oracle's radii (least t >= 1 with

@@ -50,3 +50,36 @@ def test_batch_autotune(hip):
         eo, er = oracle.greedy32(objs[j], ks[j], oracle.start_index(seeds[j], objs[j].shape[0]))
         assert_parity(oo[a:b], rr[a:b], eo, er, "tuned batch object %d" % j)
     plan.close()
+
+
+def test_tune_cache_file(hip, tmp_path, monkeypatch):
+    """BS_TUNE_CACHE: the autotuner records its winner in the file, and after
+    the in-memory table is cleared the automatic choice reads it back (what a
+    later process does); the recorded configuration orders exactly."""
+    import torch
+    path = tmp_path / "tune.txt"
+    monkeypatch.setenv("BS_TUNE_CACHE", str(path))
+    hip.autotune_clear()
+    n, k = 30000, 3000
+    P = synth.cad_part(n, seed=72).points.numpy()
+    pts = torch.from_numpy(P).cuda()
+    t = hip.autotune(pts, k, seed=5)
+    lines = path.read_text().splitlines()
+    assert len(lines) == 1 and lines[0].startswith("bluesurfels-tune-v1 gfx")
+    f = lines[0].split()
+    assert (int(f[2]), int(f[3]), int(f[4])) == (14, 11, t.kernel)  # floor(log2 n), floor(log2 k)
+    hip.autotune_clear()
+    got = hip.autotune_lookup(n, k)
+    assert got is not None and bytes(got) == bytes(t)
+    # a malformed line and another size class leave the entry usable
+    path.write_text("garbage line\n" + lines[0] + "\n" + lines[0].replace(" 14 11 ", " 20 11 ", 1) + "\n")
+    hip.autotune_clear()
+    got = hip.autotune_lookup(n, k)
+    assert got is not None and bytes(got) == bytes(t)
+    o, r = hip.order(pts, k, seed=5)
+    torch.cuda.synchronize()
+    eo, er = oracle.greedy32_grid(P, k, oracle.start_index(5, n))
+    assert_parity(o.cpu().numpy(), r.cpu().numpy(), eo, er, "cached tuning")
+    monkeypatch.delenv("BS_TUNE_CACHE")
+    hip.autotune_clear()
+    assert hip.autotune_lookup(n, k) is None
