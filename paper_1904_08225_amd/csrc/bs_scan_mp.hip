@@ -199,14 +199,48 @@ __device__ __forceinline__ void insert3(uint64_t kk, uint64_t& a1, uint64_t& a2,
     a1 = g1 ? kk : a1;
 }
 
-// The slot of this lane holding the live candidate with original index id
-// (ids are unique; padding and chosen slots have m < 0); 0 if none.
-template <int BLOCK, int P>
-__device__ __forceinline__ int slot_of_impl(const float (&m)[P], const uint32_t* ids, uint32_t id) {
-    int js = 0;
+// The wavefront's largest key among per-slot values w (bits of the value
+// plus one; 0 = none), given each lane's largest value vm, its slot jm and
+// whether another slot of the lane ties it.  Usually one slot holds the
+// largest value and only its original index is read; otherwise every slot
+// with that value is compared by index (the lowest wins, as in the key).
+// `value(j, 0)` recomputes slot j's w.  Returns key 0 when no slot is live.
+struct BestKey {
+    uint64_t key;
+    int lane, slot;
+};
+template <int BLOCK, int P, class ValueFn>
+__device__ __forceinline__ BestKey wave_best(uint32_t vm, int jm, bool tie, const uint32_t* ids, int lane,
+                                             ValueFn value) {
+    BestKey r{0ull, 0, 0};
+    const uint32_t top = wave_max_u32(vm);
+    if (top == 0u) return r;
+    const uint64_t at = __ballot(vm == top);
+    if (__popcll(at) == 1 && __ballot(vm == top && tie) == 0ull) {
+        r.lane = __builtin_ctzll(at);
+        r.slot = __builtin_amdgcn_readlane(jm, r.lane);
+        r.key = (uint64_t(top - 1u) << 32) | (0x7FFFFFFFu - ids[r.slot * BLOCK + r.lane]);
+        return r;
+    }
+    uint32_t bi = 0u;  // complemented index of this lane's best slot with the top value
+    int bj = 0;
+    // an opaque zero: the values are recomputed here rather than kept live
+    // from the caller's loop (sixteen more registers)
+    int z = 0;
+    asm volatile("" : "+v"(z));
 #pragma unroll
-    for (int j = 0; j < P; ++j) js = (m[j] >= 0.f && ids[j * BLOCK] == id) ? j : js;
-    return js;
+    for (int j = 0; j < P; ++j) {
+        if (value(j, z) == top) {
+            const uint32_t ni = 0x7FFFFFFFu - ids[j * BLOCK + lane];  // >= 1: indices are below 2^31 - 1
+            bj = ni > bi ? j : bj;
+            bi = ni > bi ? ni : bi;
+        }
+    }
+    const uint32_t bl = wave_max_u32(bi);
+    r.lane = __builtin_ctzll(__ballot(bi == bl));
+    r.slot = __builtin_amdgcn_readlane(bj, r.lane);
+    r.key = (uint64_t(top - 1u) << 32) | bl;
+    return r;
 }
 
 // Points: lane l of wavefront w in workgroup g holds sorted positions
@@ -417,11 +451,11 @@ __global__ void __launch_bounds__(BLOCK)
             // lowered m there can change the chain; any other m only drops,
             // which keeps both chain keys the largest and the bound an
             // upper bound
-            uint32_t topm = 0u;
+            uint32_t topm[2];
 #pragma unroll
             for (int e = 0; e < 2; ++e) {
                 const int cp = __float_as_int(s_wc[wave][e].w) - wbase;
-                topm |= (cp >= 0 && cp < 64 * P && (cp & 63) == lane) ? 1u << (cp >> 6) : 0u;
+                topm[e] = (cp >= 0 && cp < 64 * P && (cp & 63) == lane) ? 1u << (cp >> 6) : 0u;
             }
             uint32_t lowm = 0u;  // slots of this lane whose m dropped
 #pragma unroll
@@ -457,76 +491,114 @@ __global__ void __launch_bounds__(BLOCK)
                         if (off == j * 64 + lane) m[j] = -1.f;
                 }
             // the cached chain stays exact unless the m of one of its keys
-            // dropped or a pick (always one of them) was taken here
-            if (__ballot((lowm & topm) != 0u) != 0ull || (om[0] | om[1]) != 0ull || step == 1) {
-                // c1: the wavefront's best key, and the slot holding it
-                uint64_t bk = 0;
-#pragma unroll
-                for (int j = 0; j < P; ++j) {
-                    const uint64_t kk = m[j] >= 0.f ? make_key(m[j], s_id[j * BLOCK + tid]) : 0ull;
-                    bk = kk > bk ? kk : bk;
-                }
-                const uint64_t c1 = wave_max_u64(bk);
-                uint64_t c2 = 0ull;
-                uint32_t c3 = 0u;
-                float4 e1 = make_float4(0.f, 0.f, 0.f, __int_as_float(-1));
-                float4 e2 = e1;
-                if (c1 != 0ull) {
-                    const int l1 = __builtin_ctzll(__ballot(bk == c1));  // keys are unique
-                    const int j1 = __builtin_amdgcn_readlane(slot_of_impl<BLOCK, P>(m, s_id + tid, key_id(c1)), l1);
-                    float x = px[0], y = py[0], z = pz[0];
-#pragma unroll
-                    for (int j = 1; j < P; ++j)
-                        if (j1 == j) {  // uniform
-                            x = px[j];
-                            y = py[j];
-                            z = pz[j];
-                        }
-                    const float x1 = uniform_at(x, l1), y1 = uniform_at(y, l1), z1 = uniform_at(z, l1);
-                    e1 = make_float4(x1, y1, z1, __int_as_float(wbase + j1 * 64 + l1));
-                    // c2: the best key once c1's ball has lowered the others;
-                    // the lane's two largest of those values (bits) on the side
-                    uint64_t bk2 = 0;
-                    uint32_t t1 = 0u, t2 = 0u;
+            // dropped or a pick (always one of them) was taken here: all of
+            // it is rebuilt when a pick was taken here or c1's m dropped
+            // (step 1 fills every cache), from c2 on when only c2's m did
+            const bool redo1 = (om[0] | om[1]) != 0ull || step == 1 || __ballot((lowm & topm[0]) != 0u) != 0ull;
+            if (redo1 || __ballot((lowm & topm[1]) != 0u) != 0ull) {
+                const uint32_t* ids = s_id + (tid - lane);  // this wavefront's column of s_id
+                uint64_t c1;
+                float4 e1;
+                if (redo1) {
+                    // c1: per lane the largest value (bits + 1; 0 = none) and its slot
+                    uint32_t vm = 0u;
+                    int jm = 0;
+                    bool tie = false;
 #pragma unroll
                     for (int j = 0; j < P; ++j) {
-                        const float d = dist2(px[j], py[j], pz[j], x1, y1, z1);
-                        const float v = d < m[j] ? d : m[j];
-                        const bool live = m[j] >= 0.f && !(lane == l1 && j == j1);
-                        const uint64_t kk = live ? make_key(v, s_id[j * BLOCK + tid]) : 0ull;
-                        bk2 = kk > bk2 ? kk : bk2;
-                        const uint32_t vb = live ? __float_as_uint(v) : 0u;
-                        t2 = max(t2, min(t1, vb));
-                        t1 = max(t1, vb);
+                        const uint32_t w = m[j] >= 0.f ? __float_as_uint(m[j]) + 1u : 0u;
+                        tie = w == vm ? true : (w > vm ? false : tie);
+                        jm = w > vm ? j : jm;
+                        vm = max(vm, w);
                     }
-                    c2 = wave_max_u64(bk2);
-                    if (c2 != 0ull) {
-                        const int l2 = __builtin_ctzll(__ballot(bk2 == c2));
-                        const int j2 = __builtin_amdgcn_readlane(slot_of_impl<BLOCK, P>(m, s_id + tid, key_id(c2)), l2);
-                        x = px[0];
-                        y = py[0];
-                        z = pz[0];
+                    const BestKey b = wave_best<BLOCK, P>(vm, jm, tie, ids, lane, [&](int j, int zero) {
+                        return m[j] >= 0.f ? (__float_as_uint(m[j]) | uint32_t(zero)) + 1u : 0u;
+                    });
+                    c1 = b.key;
+                    e1 = make_float4(0.f, 0.f, 0.f, __int_as_float(-1));
+                    if (c1 != 0ull) {
+                        float x = px[0], y = py[0], z = pz[0];
 #pragma unroll
                         for (int j = 1; j < P; ++j)
-                            if (j2 == j) {
+                            if (b.slot == j) {  // uniform
                                 x = px[j];
                                 y = py[j];
                                 z = pz[j];
                             }
-                        const float x2 = uniform_at(x, l2), y2 = uniform_at(y, l2), z2 = uniform_at(z, l2);
-                        e2 = make_float4(x2, y2, z2, __int_as_float(wbase + j2 * 64 + l2));
+                        e1 = make_float4(uniform_at(x, b.lane), uniform_at(y, b.lane), uniform_at(z, b.lane),
+                                         __int_as_float(wbase + b.slot * 64 + b.lane));
+                    }
+                } else {
+                    c1 = s_w[wave][0];
+                    e1 = s_wc[wave][0];
+                }
+                uint64_t c2 = 0ull;
+                uint32_t c3 = 0u;
+                float4 e2 = make_float4(0.f, 0.f, 0.f, __int_as_float(-1));
+                if (c1 != 0ull) {
+                    // c2: the best key once c1's ball has lowered the others.
+                    // A slab whose box lies beyond that ball keeps its values
+                    // (the box bound is at least c1's m, which bounds them all).
+                    const int p1 = __float_as_int(e1.w) - wbase;
+                    const int l1 = p1 & 63, j1 = p1 >> 6;
+                    const float x1 = e1.x, y1 = e1.y, z1 = e1.z, r1 = key_value(c1);
+                    bool hit = false;
+                    if (lane < P) {
+                        const float4 lo = s_slo[wave][lane], hi = s_shi[wave][lane];
+                        hit = box_lower(lo.x, lo.y, lo.z, hi.x, hi.y, hi.z, x1, y1, z1) < r1;
+                    }
+                    const uint32_t sm1 = uint32_t(__ballot(hit));
+                    auto value2 = [&](int j, int zero) {
+                        float v = m[j];
+                        if (sm1 & (1u << j)) {  // uniform
+                            const float d = dist2(px[j], py[j], pz[j], __int_as_float(__float_as_int(x1) | zero), y1, z1);
+                            v = d < v ? d : v;
+                        }
+                        const bool live = m[j] >= 0.f && !(lane == l1 && j == j1);
+                        return live ? __float_as_uint(v) + 1u : 0u;
+                    };
+                    // per lane the largest and second largest of those values
+                    uint32_t vm = 0u, t2 = 0u;
+                    int jm = 0;
+                    bool tie = false;
+#pragma unroll
+                    for (int j = 0; j < P; ++j) {
+                        const uint32_t w = value2(j, 0);
+                        t2 = max(t2, min(vm, w));
+                        tie = w == vm ? true : (w > vm ? false : tie);
+                        jm = w > vm ? j : jm;
+                        vm = max(vm, w);
+                        // one slot at a time: computing all sixteen values
+                        // first would need more registers than remain
+                        asm volatile("" : "+v"(vm), "+v"(jm), "+v"(t2));
+                    }
+                    const BestKey b = wave_best<BLOCK, P>(vm, jm, tie, ids, lane, value2);
+                    c2 = b.key;
+                    if (c2 != 0ull) {
+                        float x = px[0], y = py[0], z = pz[0];
+#pragma unroll
+                        for (int j = 1; j < P; ++j)
+                            if (b.slot == j) {
+                                x = px[j];
+                                y = py[j];
+                                z = pz[j];
+                            }
+                        e2 = make_float4(uniform_at(x, b.lane), uniform_at(y, b.lane), uniform_at(z, b.lane),
+                                         __int_as_float(wbase + b.slot * 64 + b.lane));
                         // c3: bound of every other value once c1 and c2 are
                         // taken -- the largest value after c1's update other
                         // than c2's (c2's ball can only lower them further)
-                        const uint32_t b3 = lane == l2 ? t2 : t1;
-                        c3 = wave_max_u32(b3);
+                        const uint32_t top = wave_max_u32(lane == b.lane ? t2 : vm);
+                        c3 = top ? top - 1u : 0u;
                     }
                 }
                 if (lane == 0) {
-                    s_w[wave][0] = c1;
+                    if (redo1) {
+                        s_w[wave][0] = c1;
+                        s_wc[wave][0] = e1;
+                    }
                     s_w[wave][1] = c2;
                     s_c3[wave] = c3;
-                    s_wc[wave][0] = e1;
                     s_wc[wave][1] = e2;
                 }
             }
