@@ -638,8 +638,8 @@ def bench_served(bs, torch, np):
     srv.drain()
     st = srv.stats()
     srv.close()
-    log("served: p50 %.1f ms p99 %.1f ms, %.3g surfels/s" % (st["p50_us"] / 1e3, st["p99_us"] / 1e3,
-                                                              st["surfels_per_s"]))
+    log("served: p50 %.1f ms p99 %.1f ms, %.3g surfels/s, %d worker launches, %d stall stops"
+        % (st["p50_us"] / 1e3, st["p99_us"] / 1e3, st["surfels_per_s"], st["worker_launches"], st["stall_stops"]))
     # capacity: the same requests all queued at once (the offered rate above
     # caps the served rate, so this is what compares with the plain loop)
     sat = bs.Server(hbm_budget_bytes=80_000_000_000, max_jobs_per_batch=256, poll_us=20)
@@ -667,11 +667,13 @@ def bench_served(bs, torch, np):
             "p50_latency_ms": st["p50_us"] / 1e3, "p99_latency_ms": st["p99_us"] / 1e3,
             "max_latency_ms": st["max_us"] / 1e3, "served_surfels_per_s": st["surfels_per_s"],
             "elapsed_s": st["elapsed_s"], "batches": st["batches"], "hbm_peak_bytes": st["hbm_peak"],
+            "worker_launches": st["worker_launches"], "stall_stops": st["stall_stops"],
             "plain_loop_ordered_surfels_per_s": plain_rate,
             "speedup_vs_plain": st["surfels_per_s"] / plain_rate,
             "speedup_bound_by_offered_load": offered / plain_rate,
             "saturated": {"surfels_per_s": st2["surfels_per_s"], "elapsed_s": st2["elapsed_s"],
                           "batches": st2["batches"], "hbm_peak_bytes": st2["hbm_peak"],
+                          "worker_launches": st2["worker_launches"], "stall_stops": st2["stall_stops"],
                           "speedup_vs_plain": st2["surfels_per_s"] / plain_rate,
                           "note": "the same 2,000 requests queued at once: the serving path's capacity"},
             "plain_loop_sample": "%d requests back to back" % len(sample)}

@@ -591,7 +591,9 @@ void bs_hier_plan_destroy(bs_hier_plan* plan);
  * claims the next job (largest k first within a micro-batch).  A job never
  * waits for another job to finish, only for a free worker (and, if the
  * device runs a micro-batch's preprocessing behind the resident workers, for
- * the stop that stall_us triggers).  Each job is timed
+ * the stop that stall_us triggers; while workers are being stopped no new
+ * micro-batch starts, and a full set is relaunched once they have left).
+ * Each job is timed
  * from submit to the moment its completion flag (written by its worker into
  * pinned host memory) is observed.  Results are bit-identical to bs_order on
  * the same job.  Workers exit a few milliseconds after the last job and are
@@ -607,10 +609,11 @@ typedef struct {
     float cell_points;           /* grid cell target, 0 = 8 */
     int32_t workgroups;          /* resident 1024-thread ordering workers (each holds a whole
                                     compute unit), 0 = half the compute units */
-    int32_t stall_us;            /* a micro-batch whose preprocessing has not finished this long
-                                    (plus 0.2 us per 1,000 candidates) after its admission stops
-                                    the workers, so that preprocessing queued behind them on the
-                                    device can run; they restart once it is done.  0 = 2,000 */
+    int32_t stall_us;            /* a micro-batch whose preprocessing has not begun on the device
+                                    this long after every earlier micro-batch was published stops
+                                    the workers (the device is then running it behind them on one
+                                    in-order hardware queue); they restart once it is published.
+                                    0 = 5,000 */
     int32_t reserved[5];         /* must be zero */
 } bs_server_config;
 
@@ -637,6 +640,8 @@ typedef struct {
     double elapsed_s;          /* first submit -> last completion */
     double surfels_per_s;      /* ordered_surfels / elapsed_s */
     size_t hbm_in_use, hbm_peak;
+    int64_t worker_launches;   /* sets of persistent workers launched so far */
+    int64_t stall_stops;       /* times an overdue publication stopped the workers */
 } bs_serving_stats;
 
 typedef struct bs_server bs_server;

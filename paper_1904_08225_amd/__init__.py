@@ -709,7 +709,8 @@ class ServingStats(ctypes.Structure):
                 ("batches", ctypes.c_int64), ("ordered_surfels", ctypes.c_int64),
                 ("p50_us", ctypes.c_double), ("p99_us", ctypes.c_double), ("mean_us", ctypes.c_double),
                 ("max_us", ctypes.c_double), ("elapsed_s", ctypes.c_double), ("surfels_per_s", ctypes.c_double),
-                ("hbm_in_use", ctypes.c_size_t), ("hbm_peak", ctypes.c_size_t)]
+                ("hbm_in_use", ctypes.c_size_t), ("hbm_peak", ctypes.c_size_t),
+                ("worker_launches", ctypes.c_int64), ("stall_stops", ctypes.c_int64)]
 
     def as_dict(self):
         return {f[0]: getattr(self, f[0]) for f in self._fields_}

@@ -11,12 +11,21 @@
 // Worker life cycle: a set of persistent workers runs while published jobs
 // are unfinished.  When nothing is queued, in flight or being published the
 // workers are told to stop (they leave once nothing is left to claim).  A
-// publication that is overdue -- its preprocessing has not finished within
-// stall_us plus a per-candidate allowance -- also stops them: if the device
-// ran the preprocessing behind the persistent workers (two streams on one
-// in-order hardware queue), the workers' exit lets it run, and the next
+// batch whose preprocessing is overdue -- it has not begun on the device
+// stall_us after every earlier batch was published (the preprocessing
+// stream is in order, so only those can hold it up) -- also stops them: the
+// device is then running it behind the persistent workers (two streams on
+// one in-order hardware queue), the workers' exit lets it run, and the next
 // workers start once the publication is done.  So a job never waits for the
-// workers' own idle time-out.
+// workers' own idle time-out, and slow preprocessing alone (large batches,
+// pool growth) does not count as a stall.
+//
+// While the workers are told to stop, no batch is started: a job published
+// then would be claimed by whichever workers had not yet left, and a new
+// full set can only start once the last of them is gone, so the set would
+// shrink to the workers that happened to be busy.  Admission resumes, and a
+// full set is launched, once every worker has left (at once when they were
+// idle; after the claimed jobs when a publication was overdue).
 #include "bs_dispatch.h"
 
 #include <algorithm>
@@ -47,7 +56,9 @@ struct InFlight {
     size_t bytes = 0;
     std::vector<uint64_t> tickets;
     Clock::time_point started{};
-    Clock::time_point deadline{};  // publication overdue after this
+    Clock::time_point head_since{};  // every earlier batch was published by then
+    bool at_head = false;            // head_since is set
+    bool began = false;              // its preprocessing has begun on the device
     bool published = false;
     bool all_done = false;
 };
@@ -174,11 +185,8 @@ bool admit_batch(Server& s) {
         s.cv_done.notify_all();
         return true;
     }
-    int64_t cand = 0;
-    for (const bs_job* r : reqs) cand += r->n;
     f.tickets = take;
     f.started = now;
-    f.deadline = now + std::chrono::microseconds(s.cfg.stall_us + cand / 5000);
     s.bytes_in_use += f.bytes;
     s.bytes_peak = std::max(s.bytes_peak, s.bytes_in_use);
     s.admitted += int64_t(take.size());
@@ -191,9 +199,16 @@ bool admit_batch(Server& s) {
 void reap(Server& s) {
     bool any = false;
     const auto now = Clock::now();
+    bool earlier_published = true;  // every batch before this one (admission order)
     for (size_t b = 0; b < s.inflight.size();) {
         InFlight& f = s.inflight[b];
         if (!f.published) f.published = s.dev->published(f.batch);
+        if (!f.began) f.began = f.published || s.dev->began(f.batch);
+        if (earlier_published && !f.at_head) {
+            f.at_head = true;
+            f.head_since = now;
+        }
+        earlier_published = earlier_published && f.published;
         bool all = true;
         for (uint64_t t : f.tickets) {
             Job& j = s.jobs[t];
@@ -225,7 +240,8 @@ void manage_workers(Server& s) {
         if (f.published) claimable = true;  // published with unfinished jobs (finished ones are reaped)
         else {
             publishing = true;
-            overdue = overdue || now > f.deadline;
+            overdue = overdue || (!f.began && f.at_head &&
+                                  now - f.head_since > std::chrono::microseconds(s.cfg.stall_us));
         }
     }
     const bool running = s.dev->workers_running();
@@ -237,6 +253,7 @@ void manage_workers(Server& s) {
         }
         return;
     }
+    s.workers_stopping = false;  // every worker has left
     // no workers on the device: start a set when there is work for them
     // (an overdue publication has the device to itself until it is done)
     if (claimable || (publishing && !overdue)) {
@@ -254,7 +271,9 @@ void dispatcher(Server* sp) {
     std::unique_lock<std::mutex> lk(s.mu);
     while (true) {
         reap(s);
-        while (!s.pending.empty() && int(s.inflight.size()) < s.cfg.max_inflight && admit_batch(s)) {
+        // nothing starts while the workers are leaving (file comment)
+        const bool hold = s.workers_stopping && s.dev->workers_running();
+        while (!hold && !s.pending.empty() && int(s.inflight.size()) < s.cfg.max_inflight && admit_batch(s)) {
         }
         manage_workers(s);
         if (s.stop && s.pending.empty() && s.inflight.empty()) break;
@@ -385,6 +404,8 @@ int server_stats(Server* sv, bs_serving_stats* out) {
     st.surfels_per_s = st.elapsed_s > 0 ? double(s.k_done) / st.elapsed_s : 0.0;
     st.hbm_in_use = s.bytes_in_use;
     st.hbm_peak = s.bytes_peak;
+    st.worker_launches = s.launches;
+    st.stall_stops = s.stall_stops;
     *out = st;
     return BS_OK;
 }

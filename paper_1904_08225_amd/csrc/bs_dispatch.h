@@ -28,6 +28,9 @@ public:
     // Enqueue the batch's copies, preprocessing and publication; job i sets
     // completion flag flags[i] when its outputs are complete.
     virtual int start(void* batch, const std::vector<const bs_job*>& jobs, const std::vector<int>& flags) = 0;
+    // The batch's preprocessing has begun on the device (everything queued
+    // before it on the device has run).
+    virtual bool began(void* batch) = 0;
     // The batch's jobs are in the ring (the workers can claim them).
     virtual bool published(void* batch) = 0;
     // Every job of the batch is done: release its memory.
@@ -49,7 +52,7 @@ struct DispatchConfig {
     int max_inflight = 64;         // micro-batches on the device at once
     int max_jobs_per_batch = 512;
     int poll_us = 50;              // dispatcher period while busy
-    int64_t stall_us = 2000;       // publication overdue after this (plus 2e-4 us per candidate)
+    int64_t stall_us = 5000;       // preprocessing overdue when not begun this long after it could
 };
 
 struct Server;

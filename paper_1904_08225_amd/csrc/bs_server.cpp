@@ -32,6 +32,7 @@ struct HipBatch {
     BatchPlan* plan = nullptr;
     void* staging = nullptr;
     void* ws = nullptr;
+    hipEvent_t began = nullptr;      // recorded before the batch's first operation
     hipEvent_t published = nullptr;
     int64_t candidates = 0;
 };
@@ -127,6 +128,8 @@ public:
         }
         batch_set_job_io(b->plan, outo, outr, done);
         hipError_t e = hipEventCreateWithFlags(&b->published, hipEventDisableTiming);
+        if (e == hipSuccess) e = hipEventCreateWithFlags(&b->began, hipEventDisableTiming);
+        if (e == hipSuccess) e = hipEventRecord(b->began, prep_);
         if (e == hipSuccess) e = hipMallocAsync(&b->staging, std::max<size_t>(size_t(b->candidates) * 12, 16), prep_);
         if (e == hipSuccess)
             e = hipMallocAsync(&b->ws, std::max<size_t>(batch_workspace_bytes(b->plan), 256), prep_);
@@ -154,6 +157,8 @@ public:
         published_ += uint32_t(batch_work_count(b->plan));
         return BS_OK;
     }
+
+    bool began(void* batch) override { return hipEventQuery(static_cast<HipBatch*>(batch)->began) == hipSuccess; }
 
     bool published(void* batch) override {
         return hipEventQuery(static_cast<HipBatch*>(batch)->published) == hipSuccess;
@@ -193,8 +198,9 @@ private:
         if (b->staging) (void)hipFreeAsync(b->staging, prep_);
         if (b->ws) (void)hipFreeAsync(b->ws, prep_);
         if (b->published) (void)hipEventDestroy(b->published);
+        if (b->began) (void)hipEventDestroy(b->began);
         b->staging = b->ws = nullptr;
-        b->published = nullptr;
+        b->published = b->began = nullptr;
     }
 
     bs_server_config cfg_{};
@@ -242,7 +248,7 @@ int bs_server_create(const bs_server_config* cfg, bs_server** out) {
     dc.max_inflight = c.max_inflight;
     dc.max_jobs_per_batch = c.max_jobs_per_batch;
     dc.poll_us = c.poll_us > 0 ? c.poll_us : 50;
-    dc.stall_us = c.stall_us > 0 ? c.stall_us : 2000;
+    dc.stall_us = c.stall_us > 0 ? c.stall_us : 5000;
     Server* s = nullptr;
     rc = server_create(dc, dev, &s);
     if (rc != BS_OK) return rc;

@@ -35,6 +35,7 @@ using Clock = std::chrono::steady_clock;
 struct FakeBatch {
     std::vector<bs_job> jobs;
     std::vector<int> flags;
+    std::atomic<bool> began{false};
     std::atomic<bool> published{false};
 };
 
@@ -49,9 +50,10 @@ struct Claim {
 
 class FakeDevice final : public bs::ServeDevice {
 public:
-    FakeDevice(int workers, bool shared_queue, int publish_delay_us, int bytes_per_candidate, int idle_ms)
+    FakeDevice(int workers, bool shared_queue, int publish_delay_us, int bytes_per_candidate, int idle_ms,
+               int exit_us)
         : workers_(workers), shared_(shared_queue), delay_us_(publish_delay_us), bpc_(bytes_per_candidate),
-          idle_ms_(idle_ms), flags_(4096) {
+          idle_ms_(idle_ms), exit_us_(exit_us), flags_(4096) {
         for (auto& f : flags_) f.store(0u);
         prep_ = std::thread([this] { prep_loop(); });
     }
@@ -77,6 +79,7 @@ public:
         cv_.notify_all();
         return BS_OK;
     }
+    bool began(void* batch) override { return static_cast<FakeBatch*>(batch)->began.load(); }
     bool published(void* batch) override { return static_cast<FakeBatch*>(batch)->published.load(); }
     void release(void* batch) override { delete static_cast<FakeBatch*>(batch); }
     bool flag(int slot) override { return flags_[size_t(slot)].load(std::memory_order_acquire) != 0u; }
@@ -119,6 +122,8 @@ public:
         if (prep_.joinable()) prep_.join();
     }
     int64_t launches() const { return launches_; }
+    // Most jobs ordered at once since the last call (and reset).
+    int take_peak() { return peak_.exchange(0); }
 
 private:
     void reap_threads() {  // caller holds mu_; joins workers that have left
@@ -131,7 +136,7 @@ private:
     void start_workers() {  // caller holds mu_
         for (int w = 0; w < workers_; ++w) {
             running_.fetch_add(1);
-            threads_.emplace_back([this] { worker_loop(); });
+            threads_.emplace_back([this, w] { worker_loop(w); });
         }
     }
 
@@ -154,6 +159,7 @@ private:
                 cv_.notify_all();
                 continue;
             }
+            it.batch->began.store(true);
             lk.unlock();
             std::this_thread::sleep_for(std::chrono::microseconds(delay_us_));
             lk.lock();
@@ -165,8 +171,13 @@ private:
         }
     }
 
-    void worker_loop() {
+    // Worker w notices the stop flag w * exit_us / workers after it was
+    // raised (a device worker sees it at its next poll, and the kernel's end
+    // is seen later still): until then it keeps claiming what is published.
+    void worker_loop(int w) {
         auto idle_since = Clock::now();
+        bool stop_seen = false;
+        Clock::time_point leave_at{};
         while (true) {
             Claim c{};
             bool got = false;
@@ -176,7 +187,12 @@ private:
                     c = ring_.front();
                     ring_.pop_front();
                     got = true;
-                } else if (stop_.load() || Clock::now() - idle_since > std::chrono::milliseconds(idle_ms_)) {
+                } else if (stop_.load() && !stop_seen) {
+                    stop_seen = true;
+                    leave_at = Clock::now() + std::chrono::microseconds(int64_t(exit_us_) * w / workers_);
+                    continue;
+                } else if ((stop_seen && Clock::now() >= leave_at) ||
+                           Clock::now() - idle_since > std::chrono::milliseconds(idle_ms_)) {
                     if (running_.fetch_sub(1) == 1 && !shared_) launched_.store(false);
                     cv_.notify_all();
                     return;
@@ -185,10 +201,15 @@ private:
                 }
             }
             if (!got) continue;
+            stop_seen = false;  // the flag is read again after the job
+            const int now_active = active_.fetch_add(1) + 1;
+            for (int p = peak_.load(); now_active > p && !peak_.compare_exchange_weak(p, now_active);) {
+            }
             const bs_job& j = c.job;
             if (j.k > 0)
                 oracle_greedy32(j.d_points, j.n, j.k, oracle_start_index(j.seed, j.n), j.d_out_order,
                                 j.d_out_radius, nullptr, nullptr, nullptr);
+            active_.fetch_sub(1);
             flags_[size_t(c.flag)].store(1u, std::memory_order_release);
             idle_since = Clock::now();
         }
@@ -196,7 +217,8 @@ private:
 
     int workers_;
     bool shared_;
-    int delay_us_, bpc_, idle_ms_;
+    int delay_us_, bpc_, idle_ms_, exit_us_;
+    std::atomic<int> active_{0}, peak_{0};
     std::vector<std::atomic<uint32_t>> flags_;
     std::mutex mu_;
     std::condition_variable cv_;
@@ -215,19 +237,26 @@ private:
 
 extern "C" {
 
+struct FakeServer {
+    bs::Server* s;
+    FakeDevice* dev;  // owned by s
+};
+
 void* fake_server_create(size_t budget, int max_jobs_per_batch, int workers, int shared_queue, int publish_delay_us,
-                         int stall_us, int bytes_per_candidate, int idle_ms) {
+                         int stall_us, int bytes_per_candidate, int idle_ms, int exit_us) {
     bs::DispatchConfig cfg;
     cfg.budget = budget;
     cfg.max_inflight = 8;
     cfg.max_jobs_per_batch = max_jobs_per_batch;
     cfg.poll_us = 50;
     cfg.stall_us = stall_us;
-    auto* dev = new FakeDevice(workers, shared_queue != 0, publish_delay_us, bytes_per_candidate, idle_ms);
+    auto* dev = new FakeDevice(workers, shared_queue != 0, publish_delay_us, bytes_per_candidate, idle_ms, exit_us);
     bs::Server* s = nullptr;
     if (bs::server_create(cfg, dev, &s) != BS_OK) return nullptr;
-    return s;
+    return new FakeServer{s, dev};
 }
+
+static bs::Server* srv_of(void* h) { return static_cast<FakeServer*>(h)->s; }
 
 int fake_server_submit(void* s, const float* pts, int64_t n, int64_t k, uint64_t seed, int32_t* out_order,
                        float* out_radius, uint64_t* ticket) {
@@ -238,23 +267,28 @@ int fake_server_submit(void* s, const float* pts, int64_t n, int64_t k, uint64_t
     j.seed = seed;
     j.d_out_order = out_order;
     j.d_out_radius = out_radius;
-    return bs::server_submit(static_cast<bs::Server*>(s), &j, ticket);
+    return bs::server_submit(srv_of(s), &j, ticket);
 }
 
 int fake_server_wait(void* s, uint64_t t, int64_t timeout_us) {
-    return bs::server_wait(static_cast<bs::Server*>(s), t, timeout_us);
+    return bs::server_wait(srv_of(s), t, timeout_us);
 }
 
-int fake_server_poll(void* s, uint64_t t, int* done) { return bs::server_poll(static_cast<bs::Server*>(s), t, done); }
+int fake_server_poll(void* s, uint64_t t, int* done) { return bs::server_poll(srv_of(s), t, done); }
 
-int fake_server_drain(void* s, int64_t timeout_us) { return bs::server_drain(static_cast<bs::Server*>(s), timeout_us); }
+int fake_server_drain(void* s, int64_t timeout_us) { return bs::server_drain(srv_of(s), timeout_us); }
 
-int fake_server_stats(void* s, bs_serving_stats* out) { return bs::server_stats(static_cast<bs::Server*>(s), out); }
+int fake_server_stats(void* s, bs_serving_stats* out) { return bs::server_stats(srv_of(s), out); }
 
-int64_t fake_server_stall_stops(void* s) { return bs::server_stall_stops(static_cast<bs::Server*>(s)); }
+int64_t fake_server_stall_stops(void* s) { return bs::server_stall_stops(srv_of(s)); }
 
-int64_t fake_server_launches(void* s) { return bs::server_worker_launches(static_cast<bs::Server*>(s)); }
+int64_t fake_server_launches(void* s) { return bs::server_worker_launches(srv_of(s)); }
 
-void fake_server_destroy(void* s) { bs::server_destroy(static_cast<bs::Server*>(s)); }
+int fake_server_take_peak(void* s) { return static_cast<FakeServer*>(s)->dev->take_peak(); }
+
+void fake_server_destroy(void* s) {
+    bs::server_destroy(srv_of(s));
+    delete static_cast<FakeServer*>(s);
+}
 
 }  // extern "C"

@@ -32,7 +32,7 @@ def _build(tmpdir, extra=()):
 def _bind(path):
     L = ctypes.CDLL(path)
     vp, i32, i64, u64, sz = ctypes.c_void_p, ctypes.c_int, ctypes.c_int64, ctypes.c_uint64, ctypes.c_size_t
-    L.fake_server_create.argtypes = [sz, i32, i32, i32, i32, i32, i32, i32]
+    L.fake_server_create.argtypes = [sz, i32, i32, i32, i32, i32, i32, i32, i32]
     L.fake_server_create.restype = vp
     L.fake_server_submit.argtypes = [vp, vp, i64, i64, u64, vp, vp, ctypes.POINTER(u64)]
     L.fake_server_submit.restype = i32
@@ -48,6 +48,8 @@ def _bind(path):
     L.fake_server_stall_stops.restype = i64
     L.fake_server_launches.argtypes = [vp]
     L.fake_server_launches.restype = i64
+    L.fake_server_take_peak.argtypes = [vp]
+    L.fake_server_take_peak.restype = i32
     L.fake_server_destroy.argtypes = [vp]
     L.fake_server_destroy.restype = None
     return L
@@ -60,9 +62,10 @@ def fake(tmp_path_factory):
 
 class _Srv:
     def __init__(self, L, budget, per_batch=64, workers=2, shared=False, delay_us=0, stall_us=2000, bpc=100,
-                 idle_ms=2000):
+                 idle_ms=2000, exit_us=0):
         self.L = L
-        self.h = L.fake_server_create(budget, per_batch, workers, int(shared), delay_us, stall_us, bpc, idle_ms)
+        self.h = L.fake_server_create(budget, per_batch, workers, int(shared), delay_us, stall_us, bpc, idle_ms,
+                                      exit_us)
         assert self.h
         self.keep = {}
 
@@ -182,6 +185,50 @@ def test_publication_behind_workers_is_bounded(fake, stall_us):
     else:
         assert stops == 0
         assert tb_done > ta_done + 0.8 * idle_ms / 1e3, (ta_done, tb_done)
+
+
+def test_slow_preprocessing_is_not_a_stall(fake):
+    """Preprocessing that takes long once it has begun (large batches, pool
+    growth) is not a stall: with its own queue a 300 ms publication delay,
+    far above stall_us, stops no workers."""
+    srv = _Srv(fake, budget=10**9, workers=2, shared=False, delay_us=300_000, stall_us=2000)
+    A = cases.random_cloud(30000, 3)
+    rc, ta = srv.submit(A, 2000, 1)
+    time.sleep(0.4)                          # A is published and running
+    B = cases.random_cloud(300, 4)
+    rc, tb = srv.submit(B, 50, 2)
+    assert srv.wait(tb) == 0 and srv.wait(ta) == 0
+    stops = fake.fake_server_stall_stops(srv.h)
+    srv.close()
+    assert stops == 0
+
+
+def test_full_worker_set_after_each_stop(fake):
+    """Rounds of four equal jobs, each round submitted as the last one ends:
+    the dispatcher then stops the idle workers, and they notice it at
+    staggered times.  No round may start while some of them are still
+    leaving (the survivors would claim the whole round and no full set could
+    start until the last of them left): every round must run four jobs at
+    once.  (A dispatcher that admitted while the workers were leaving ran
+    the rounds on 4, 3, 1, 1 and 1 workers here.)"""
+    workers = 4
+    srv = _Srv(fake, budget=10**9, per_batch=64, workers=workers, exit_us=30_000, idle_ms=5000)
+    P = [cases.random_cloud(20000, 40 + i) for i in range(workers)]
+    peaks = []
+    for r in range(5):
+        fake.fake_server_take_peak(srv.h)
+        ts = [srv.submit(P[i], 1500, 10 * r + i)[1] for i in range(workers)]
+        for t in ts:
+            assert srv.wait(t) == 0
+        peaks.append(fake.fake_server_take_peak(srv.h))
+    for i in range(workers):  # outputs of the last round
+        eo, er = oracle.greedy32(P[i], 1500, oracle.start_index(40 + i, P[i].shape[0]))
+        _, o, r = srv.keep[ts[i]]
+        assert np.array_equal(o[:1500], eo)
+    launches = fake.fake_server_launches(srv.h)
+    srv.close()
+    assert peaks == [workers] * 5, peaks
+    assert launches == 5
 
 
 def test_dispatcher_under_sanitizers(tmp_path):
