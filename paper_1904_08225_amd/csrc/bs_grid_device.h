@@ -162,13 +162,6 @@ __device__ __forceinline__ uint64_t group_max_u64(uint64_t v, int steps) {
 
 constexpr int kUnroll = 8;  // members per lane in flight
 
-#ifdef BS_PHASE_PROF
-#define BS_PROF(slot) \
-    do { if (o.ticks && threadIdx.x == 0) o.ticks[size_t(prof_t) * 16 + (slot)] = wall_clock64(); } while (0)
-#else
-#define BS_PROF(slot) do { } while (0)
-#endif
-
 // Update members start + s, start + s + G, ... (< start + count) of one cell
 // with the pick, U of them in flight per lane; track the lane's best key.
 // UPD = false only marks the candidate at c_pos as taken (a removal that is
@@ -234,7 +227,6 @@ __device__ inline void process_block(const GridObject& o, Lds& L, int b, int c_p
                                box_lower(lo.x, lo.y, lo.z, hi.x, hi.y, hi.z, cx, cy, cz) < mc);
     const uint64_t hm = __ballot(hit);
     const int nh = __popcll(hm);
-    BS_PROF(8);
     if (nh == 0) return;  // nothing in reach: the block's best is unchanged
 
     // lanes -> (hit cell r, sub-lane s)
@@ -270,7 +262,6 @@ __device__ inline void process_block(const GridObject& o, Lds& L, int b, int c_p
         member_batches<2, UPD>(xyzm, ids, start, count, s, G, c_pos, cx, cy, cz, lk, lw);
     else
         member_batches<kUnroll, UPD>(xyzm, ids, start, count, s, G, c_pos, cx, cy, cz, lk, lw);
-    BS_PROF(9);
 
     if (nh == 1) {
         // block best = max(new best of the hit cell, best of the other cells)
@@ -322,7 +313,6 @@ __device__ inline void process_block(const GridObject& o, Lds& L, int b, int c_p
         if (lane == 0) L.bkey[b] = bk;
     }
     wave_lds_sync();
-    BS_PROF(10);
 }
 
 // Best block of superblock sb (64 consecutive blocks), computed by one
@@ -383,9 +373,7 @@ __device__ inline void grid_order_object(const GridObject& o, GridLds<BLOCK / 64
     if (tid == 0) {
         o.order[0] = int32_t(o.start_id);
         if (o.radius) o.radius[0] = INFINITY;
-#ifndef BS_PHASE_PROF
         if (o.ticks) o.ticks[0] = wall_clock64();
-#endif
     }
     __syncthreads();
 
@@ -405,7 +393,6 @@ __device__ inline void grid_order_object(const GridObject& o, GridLds<BLOCK / 64
     for (int t = 1; t < k; ++t) {
         const int prof_t = t;
         (void)prof_t;
-        BS_PROF(0);
         // blocks that may hold a candidate whose m can drop, or the pick:
         // superblock boxes first (one per lane), then the blocks of touched ones
         const int cb = c_cell >> 6;
@@ -424,9 +411,7 @@ __device__ inline void grid_order_object(const GridObject& o, GridLds<BLOCK / 64
             }
             if (lane == 0) L.mask[sb] = m;
         }
-        BS_PROF(1);
         __syncthreads();
-        BS_PROF(2);
 
         // wavefront w takes the touched blocks of rank w, w + NW, ...
         const uint64_t mword = lane < nsb ? L.mask[lane] : 0ull;
@@ -444,9 +429,7 @@ __device__ inline void grid_order_object(const GridObject& o, GridLds<BLOCK / 64
                 ++rank;
             }
         }
-        BS_PROF(3);
         __syncthreads();
-        BS_PROF(4);
 
         // refresh the touched superblocks, then the argmax over superblocks
         for (uint64_t zs = nz; zs;) {
@@ -460,7 +443,6 @@ __device__ inline void grid_order_object(const GridObject& o, GridLds<BLOCK / 64
                 sbb = bb;
             }
         }
-        BS_PROF(5);
         const uint64_t best = wave_max_key(sbk);
         const int wl = __builtin_ctzll(__ballot(sbk == best) | (1ull << 63));
         const int bb = __builtin_amdgcn_readlane(sbb, wl);
@@ -471,13 +453,10 @@ __device__ inline void grid_order_object(const GridObject& o, GridLds<BLOCK / 64
         cy = win.y;
         cz = win.z;
         mc = key_value(best);
-        BS_PROF(6);
         if (tid == 0) {
             o.order[t] = int32_t(key_id(best));
             if (o.radius) o.radius[t] = sqrtf(mc);
-#ifndef BS_PHASE_PROF
             if (o.ticks) o.ticks[t] = wall_clock64();
-#endif
         }
     }
 }

@@ -36,13 +36,6 @@
 
 namespace bs {
 
-#ifdef BS_PHASE_PROF
-#define BS_MPROF(slot, val) \
-    do { if (o.ticks && threadIdx.x == 0) o.ticks[size_t(round_no) * 32 + (slot)] = (val); } while (0)
-#else
-#define BS_MPROF(slot, val) do { } while (0)
-#endif
-
 constexpr int kMaxPicks = 32;  // picks per round (<= 32: pick masks are 32-bit)
 
 // Per-wavefront scratch of the wavefront-per-block path.
@@ -272,9 +265,6 @@ template <int UMAX, class Lds>
 __device__ inline int process_block_mp(const GridObject& o, Lds& L, int b, const BlockRec& rec,
                                         int K, float px, float py, float pz, float pm, int ppos,
                                         int pcell, uint64_t* acc) {
-#ifdef BS_PHASE_PROF
-    const uint64_t tp0 = wall_clock64();
-#endif
     (void)acc;
     const int lane = threadIdx.x & 63;
     WaveScratchMP& W = L.u.ws[threadIdx.x >> 6];
@@ -305,10 +295,6 @@ __device__ inline int process_block_mp(const GridObject& o, Lds& L, int b, const
     const bool hit = cm != 0;
     const uint64_t hm = __ballot(hit);
     const int nh = __popcll(hm);
-#ifdef BS_PHASE_PROF
-    const uint64_t tp1 = wall_clock64();
-    acc[0] += tp1 - tp0;
-#endif
     if (nh == 0) return 0;  // nothing in reach: the block's entry is unchanged
 
     int start, count, G, gshift, r;
@@ -354,10 +340,6 @@ __device__ inline int process_block_mp(const GridObject& o, Lds& L, int b, const
     else
         member_batches_mp<UMAX>(o, L, start, count, s, G, gm, single, qx, qy, qz, qpos, a1, a2, lw);
 
-#ifdef BS_PHASE_PROF
-    const uint64_t tp2 = wall_clock64();
-    acc[1] += tp2 - tp1;
-#endif
     // per hit cell: best key, second key, and the coordinates of the best
     // (published by the one lane whose own best is it: keys are unique)
     const uint64_t own = a1;
@@ -392,9 +374,6 @@ __device__ inline int process_block_mp(const GridObject& o, Lds& L, int b, const
         L.bsec[b] = sv;
     }
     wave_lds_sync();
-#ifdef BS_PHASE_PROF
-    acc[2] += wall_clock64() - tp2;
-#endif
     return nh;
 }
 
@@ -683,9 +662,7 @@ __device__ inline void grid_order_object_mp(const GridObject& o, GridLdsMP<BLOCK
             if (o.t0 == 0) {
                 o.order[0] = int32_t(o.start_id);
                 if (o.radius) o.radius[0] = INFINITY;
-#ifndef BS_PHASE_PROF
                 if (o.ticks) o.ticks[0] = wall_clock64();
-#endif
             }
             L.pk[0] = make_float4(sp.x, sp.y, sp.z, o.start_m);
             L.pkpos[0] = o.start_pos;
@@ -704,8 +681,6 @@ __device__ inline void grid_order_object_mp(const GridObject& o, GridLdsMP<BLOCK
     int K = 1;         // picks of this round (ranks 0 .. K-1 of the LDS pick arrays)
     int round_no = 0;
     while (true) {
-        BS_MPROF(0, wall_clock64());
-        BS_MPROF(8, uint64_t(K));
         // ---- the round's picks: lane j of every wavefront holds pick j
         float px = 0.f, py = 0.f, pz = 0.f, pm = 0.f;
         int ppos = 0, pcell = 0;
@@ -718,9 +693,7 @@ __device__ inline void grid_order_object_mp(const GridObject& o, GridLdsMP<BLOCK
         if (round_no > 0 && wave == 0 && lane < K) {  // emit them (the start pick was emitted before)
             o.order[t - K + lane] = int32_t(L.pkid[lane]);
             if (o.radius) o.radius[t - K + lane] = sqrtf(pm);
-#ifndef BS_PHASE_PROF
             if (o.ticks) o.ticks[t - K + lane] = wall_clock64();
-#endif
         }
         const uint32_t kmask = K >= 32 ? 0xFFFFFFFFu : ((1u << K) - 1u);
 
@@ -745,9 +718,7 @@ __device__ inline void grid_order_object_mp(const GridObject& o, GridLdsMP<BLOCK
             const uint64_t m = __ballot(touch);
             if (lane == 0) L.mask[jb * NW + wave] = m;
         }
-        BS_MPROF(1, wall_clock64());
         __syncthreads();
-        BS_MPROF(2, wall_clock64());
 
         const uint64_t mword = lane < nwords ? L.mask[lane] : 0ull;
         const uint32_t pc = uint32_t(__popcll(mword));
@@ -784,17 +755,12 @@ __device__ inline void grid_order_object_mp(const GridObject& o, GridLdsMP<BLOCK
                 collect_block(o, L, b, cur, K, px, py, pz, pm, pcell);
                 if (PREFETCH) cur = nxt;
             }
-            BS_MPROF(16, wall_clock64());
             __syncthreads();
-            BS_MPROF(17, wall_clock64());
             per_block = L.overflow != 0;  // too many hit cells: redo the round per block
             if (!per_block) {
                 update_cells<NW, UMAX>(o, L);
-                BS_MPROF(18, wall_clock64());
                 __syncthreads();
-                BS_MPROF(19, wall_clock64());
                 finish_blocks<NW>(L);
-                BS_MPROF(20, uint64_t(L.hcount));
             }
         }
         if (per_block) {
@@ -817,13 +783,7 @@ __device__ inline void grid_order_object_mp(const GridObject& o, GridLdsMP<BLOCK
                 if (PREFETCH) cur = nxt;
             }
         }
-        BS_MPROF(3, wall_clock64());
-        BS_MPROF(9, uint64_t(touched));
-        BS_MPROF(13, uint64_t(nblk) | (uint64_t(nhit) << 16) | (uint64_t(ncells) << 32));
-        BS_MPROF(14, pacc[0]);
-        BS_MPROF(15, pacc[1] | (pacc[2] << 32));
         __syncthreads();
-        BS_MPROF(4, wall_clock64());
 
         // ---- refresh the touched superblocks, spread over the wavefronts;
         // clear the selection's LDS state (nothing reads it before the barrier)
@@ -855,9 +815,7 @@ __device__ inline void grid_order_object_mp(const GridObject& o, GridLdsMP<BLOCK
                 }
             }
         }
-        BS_MPROF(5, wall_clock64());
         __syncthreads();
-        BS_MPROF(6, wall_clock64());
         if (t >= k) break;
 
         // ---- next picks.  Candidates: the entries (lane = superblock, slot 1
@@ -895,7 +853,6 @@ __device__ inline void grid_order_object_mp(const GridObject& o, GridLdsMP<BLOCK
         const int i2 = i1 + (c1 ? 1 : 0);
         const uint64_t my1 = __ballot(c1 && (i1 % NW) == wave);
         const uint64_t my2 = __ballot(c2 && (i2 % NW) == wave);
-        BS_MPROF(11, wall_clock64());
 #pragma unroll
         for (int slot = 0; slot < 2; ++slot) {
             const uint64_t ek = slot == 0 ? e1 : e2;
@@ -929,8 +886,6 @@ __device__ inline void grid_order_object_mp(const GridObject& o, GridLdsMP<BLOCK
                 }
             }
         }
-        BS_MPROF(7, wall_clock64());
-        BS_MPROF(21, uint64_t(nc) | (uint64_t(nsb) << 24));
         ++round_no;
         __syncthreads();
         K = min(min(L.kfail, nc), cap);

@@ -143,48 +143,6 @@ __device__ __forceinline__ uint64_t rec_key(const uint32_t* rw, int e) {
     return (uint64_t(p[0]) << 32) | p[1];
 }
 
-// Profiling builds only (ticks then holds 32 words per pick, laid out below):
-// phase timestamps of workgroup 0 per step (first 32 words per step; the
-// regions after them hold per-workgroup records).
-#ifdef BS_PHASE_PROF
-#define BS_SPROF(slot, v)                                                                      \
-    do {                                                                                       \
-        if (ticks && g == 0 && tid == 0) ticks[size_t(step) * 32 + (slot)] = uint64_t(v);     \
-    } while (0)
-// per workgroup and step (profiling builds): publish and exchange-done times
-#define BS_WPROF(half, v)                                                                          \
-    do {                                                                                           \
-        if (ticks && tid == 0 && (size_t(step) + 1) * G <= size_t(k) * 8)                          \
-            ticks[size_t(k) * 16 + size_t(half) * size_t(k) * 8 + size_t(step) * G + g] = uint64_t(v); \
-    } while (0)
-// per workgroup and step (profiling builds): (pick, wavefront) reach pairs
-#define BS_RPROF(v)                                                                     \
-    do {                                                                                \
-        if (ticks && tid == 0 && (size_t(step) + 1) * G <= size_t(k) * 4)               \
-            ticks[size_t(k) * 4 + size_t(step) * G + g] = uint64_t(v);                   \
-    } while (0)
-// per workgroup and step (profiling builds): step start and after the
-// update barrier
-#define BS_TPROF(q, v)                                                                      \
-    do {                                                                                    \
-        if (ticks && tid == 0 && (size_t(step) + 1) * G <= size_t(k) * 4)                   \
-            ticks[size_t(k) * 8 + size_t(q) * size_t(k) * 4 + size_t(step) * G + g] = uint64_t(v); \
-    } while (0)
-#else
-#define BS_TPROF(q, v) \
-    do {               \
-    } while (0)
-#define BS_RPROF(v) \
-    do {            \
-    } while (0)
-#define BS_WPROF(half, v) \
-    do {                  \
-    } while (0)
-#define BS_SPROF(slot, v) \
-    do {                  \
-    } while (0)
-#endif
-
 __device__ __forceinline__ void st_rec(uint64_t* p, uint64_t v) {
     __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
@@ -268,9 +226,6 @@ __global__ void __launch_bounds__(BLOCK)
     __shared__ float4 s_slo[NW][P], s_shi[NW][P];  // box of each slab of 64 (x, y, z; w unused)
     __shared__ float4 s_gb[NW][4];                 // boxes of the wavefront's two groups (lo, hi each)
     __shared__ int s_kfail, s_na, s_abort;
-#ifdef BS_PHASE_PROF
-    __shared__ int s_reach;
-#endif
 
     const int tid = threadIdx.x;
     const int lane = tid & 63;
@@ -399,9 +354,6 @@ __global__ void __launch_bounds__(BLOCK)
         s_pid[0] = uint32_t(start);
         s_ppos[0] = sp;
         s_abort = 0;
-#ifdef BS_PHASE_PROF
-        s_reach = 0;
-#endif
         if (g == 0) {
             order[0] = start;
             if (radius) radius[0] = INFINITY;
@@ -421,8 +373,6 @@ __global__ void __launch_bounds__(BLOCK)
         asm volatile("" : "+v"(tid_v));
         const int tid = tid_v, lane = tid_v & 63;
         const int buf = step & 1;
-        BS_SPROF(0, wall_clock64());
-        BS_TPROF(0, wall_clock64());
         // 1. the previous step's picks: the ones whose ball reaches a group's
         // box lower m in that group's slabs of 64; the ones it owns become chosen
         uint64_t ra[2], rb[2], om[2];  // picks 0-63 and 64-127
@@ -442,9 +392,6 @@ __global__ void __launch_bounds__(BLOCK)
             rb[h] = __ballot(reach_b);
             om[h] = __ballot(own);
         }
-#ifdef BS_PHASE_PROF
-        if (lane == 0) atomicAdd(&s_reach, __popcll(ra[0] | rb[0]) + __popcll(ra[1] | rb[1]));
-#endif
         if ((ra[0] | ra[1] | rb[0] | rb[1] | om[0] | om[1]) != 0ull || step == 1) {  // step 1 fills every cache
             // slots of this lane holding one of the wavefront's two chain
             // keys (their sorted positions are cached with them): only a
@@ -603,15 +550,7 @@ __global__ void __launch_bounds__(BLOCK)
                 }
             }
         }
-        BS_SPROF(1, wall_clock64());
         lds_barrier();
-        BS_SPROF(2, wall_clock64());
-        BS_TPROF(1, wall_clock64());
-#ifdef BS_PHASE_PROF
-        BS_RPROF(s_reach);
-        lds_barrier();
-        if (tid == 0) s_reach = 0;
-#endif
         // 2. wavefront 0: the workgroup's three best chain keys become its
         // entries, with their data from the wavefronts that hold them, and R
         // bounds every value it does not offer; its record is one word a lane
@@ -657,8 +596,6 @@ __global__ void __launch_bounds__(BLOCK)
             if (lane < 6 * kMpEntries) wv = lane / 6 < nz ? s_ent[lane] : 0u;
             if (lane < kMpWords) st_rec(slots + (size_t(buf) * G + g) * kMpRecStride + lane, tag | wv);
         }
-        BS_SPROF(3, wall_clock64());
-        BS_WPROF(0, wall_clock64());
         // 3. every record, a few words a thread, into s_rw (kMpWords per
         // workgroup); a word is current once its high half is this step
         {
@@ -696,15 +633,12 @@ __global__ void __launch_bounds__(BLOCK)
                 __builtin_amdgcn_s_sleep(1);
             }
             if (aborted && lane == 0) s_abort = 1;
-            BS_SPROF(11, spins);
         }
         if (tid == 0) {
             s_kfail = kMpMaxPicks;
             s_na = 0;
         }
         lds_barrier();
-        BS_SPROF(4, wall_clock64());
-        BS_WPROF(1, wall_clock64());
         if (s_abort) {  // a wait gave up: every workgroup's waits end the same way
             if (tid == 0) atomicOr(err, 1u);
             return;
@@ -751,11 +685,9 @@ __global__ void __launch_bounds__(BLOCK)
 #pragma unroll
                 for (int c = 0; c < kMpMaxGroups / 64; ++c) mr = uint32_t(k1[c] >> 32) > tau ? max(mr, rr[c]) : mr;
                 mr = wave_max_u32(mr);
-                BS_SPROF(10, it + 1);
                 if (mr <= tau) break;
                 tau = mr;
             }
-            BS_SPROF(5, wall_clock64());
             const int w = wave * 64 + lane;
             uint64_t k1w = k1[0];
 #pragma unroll
@@ -788,10 +720,8 @@ __global__ void __launch_bounds__(BLOCK)
                 s_mk[p3] = k3;
                 s_mi[p3] = kMpEntries * w + 2;
             }
-            BS_SPROF(12, wall_clock64());
         }
         lds_barrier();
-        BS_SPROF(13, wall_clock64());
         const int na = s_na;
         // members ranked among themselves, the first `cap` published: a row
         // of 16 lanes ranks MR members, each lane counting over every 16th
@@ -821,7 +751,6 @@ __global__ void __launch_bounds__(BLOCK)
                 }
 #pragma unroll
                 for (int r = 0; r < MR; ++r) rk[r] = row_sum16(rk[r]);
-                BS_SPROF(14, wall_clock64());
                 int rank = rk[0];
 #pragma unroll
                 for (int r = 1; r < MR; ++r) rank = part == r ? rk[r] : rank;
@@ -837,9 +766,7 @@ __global__ void __launch_bounds__(BLOCK)
             }
         }
         const int nr = min(na, cap);
-        BS_SPROF(8, na);
         lds_barrier();
-        BS_SPROF(6, wall_clock64());
         // 5. distance conflicts: TPC threads per member j test it against the
         // earlier members i < j (every TPC-th one each); a wavefront's eight
         // or more consecutive columns give their lowest lowered j by ballot,
@@ -862,14 +789,10 @@ __global__ void __launch_bounds__(BLOCK)
         }
         lds_barrier();
         K = min(s_kfail, nr);
-        BS_SPROF(7, wall_clock64());
-        BS_SPROF(9, K);
         if (g == 0 && tid < K) {
             order[t + tid] = int32_t(s_pid[tid]);
             if (radius) radius[t + tid] = sqrtf(s_pk[tid].w);
-#ifndef BS_PHASE_PROF
             if (ticks) ticks[t + tid] = wall_clock64();
-#endif
         }
         t += K;
         if (t >= k || K <= 0) break;
