@@ -2,7 +2,7 @@
 
 python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-batch] [--no-scene]
                 [--no-serve] [--no-cpu-baseline] [--no-full-scan]
-                [--copy-calibration BYTES]
+                [--copy-calibration BYTES] [--profile-leg batch|serve]
 
 A step is one full ordering of one synthetic CAD-like part -- the union
 boundary of 200 random boxes/cylinders, 4,194,304 binary32 candidates,
@@ -735,6 +735,56 @@ def cpu_oracle_objects(pts, offs, ks, seeds, order_idx, sum_k_total, gpu_seconds
                       % (len(sample), host[0].shape[0], host[-1].shape[0], max_k, sk, wall, cores)}
 
 
+def profile_leg(which, bs, torch, np):
+    """The workload of the batch and serving profiles, alone on the device:
+    one execute of the 1,000-part batch (default tuning), or the serving
+    stream's 2,000 requests queued at once.  Prints one JSON line."""
+    import synth
+    dev = torch.device("cuda:0")
+    if which == "batch":
+        m = 1000
+        sizes = synth.log_uniform_sizes(m, 2048, 2097152, seed=3)
+        ks = [s // 4 for s in sizes]
+        seeds = [3 * 1000003 + j for j in range(m)]
+        pts, offs = synth.cad_parts_batch(sizes, seed=3, count=200, device=dev)
+        plan = bs.BatchPlan(offs, ks, seeds)
+        out_o = torch.empty(plan.total_k, dtype=torch.int32, device=dev)
+        out_r = torch.empty(plan.total_k, dtype=torch.float32, device=dev)
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        plan.execute(pts, out_o, out_r)
+        torch.cuda.synchronize()
+        rec = {"profile_leg": "batch", "objects": m, "candidates": int(pts.shape[0]), "sum_k": int(plan.total_k),
+               "seconds": time.perf_counter() - t}
+        plan.close()
+    else:
+        pool_m = 64
+        sizes = synth.log_uniform_sizes(pool_m, 10000, 4000000, seed=4)
+        pts, offs = synth.cad_parts_batch(sizes, seed=4, count=200, device=dev)
+        rng = np.random.default_rng(4)
+        nreq = 2000
+        picks = rng.integers(0, pool_m, nreq)
+        seeds = rng.integers(0, 2**62, nreq)
+        ks = [sizes[p] // 8 for p in picks]
+        out_o = torch.empty(int(sum(ks)), dtype=torch.int32, device=dev)
+        out_r = torch.empty(int(sum(ks)), dtype=torch.float32, device=dev)
+        views = [pts[offs[p]:offs[p + 1]] for p in range(pool_m)]
+        torch.cuda.synchronize()
+        srv = bs.Server(hbm_budget_bytes=80_000_000_000, max_jobs_per_batch=256, poll_us=20)
+        off = 0
+        for i in range(nreq):
+            p = int(picks[i])
+            srv.submit(views[p], ks[i], int(seeds[i]), out_o[off:off + ks[i]], out_r[off:off + ks[i]])
+            off += ks[i]
+        srv.drain()
+        st = srv.stats()
+        srv.close()
+        rec = {"profile_leg": "serve", "requests": nreq, "sum_k": int(sum(ks)), "seconds": st["elapsed_s"],
+               "batches": st["batches"], "worker_launches": st["worker_launches"],
+               "stall_stops": st["stall_stops"]}
+    print(json.dumps(rec), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -755,6 +805,9 @@ def main():
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
                     help="only run two plain device-to-device copies of BYTES bytes (scales the "
                          "FETCH_SIZE / WRITE_SIZE counters to bytes) and exit")
+    ap.add_argument("--profile-leg", choices=("batch", "serve"), default=None,
+                    help="only run the batched (one execute) or the saturated serving workload once, for "
+                         "a profiler, and exit")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: every object is ordered on a single MI355X and this build has "
@@ -774,6 +827,9 @@ def main():
             dst.copy_(src)
         torch.cuda.synchronize()
         print(json.dumps({"copy_calibration_bytes": args.copy_calibration, "copies": 2}), flush=True)
+        return
+    if args.profile_leg:
+        profile_leg(args.profile_leg, bs, torch, np)
         return
     pts, surf, out_o, ms, ev_ms, kern_s, lat, kernel, tuned, lead = bench_main(args, bs, torch, np)
     n, k = N_MAIN, K_MAIN
