@@ -440,7 +440,8 @@ def bench_batched(bs, torch, np, cpu=True):
     log("generated batch: %d objects, %d candidates in %.1fs" % (m, pts.shape[0], time.time() - t0))
     t0 = time.time()
     tune = bs.batch_autotune(pts, offs, ks, seeds)
-    log("batch autotune: cell target %g in %.1fs" % (tune.cell_points, time.time() - t0))
+    log("batch autotune: cell target %g, %d wide workgroups in %.1fs" % (tune.cell_points, tune.groups,
+                                                                         time.time() - t0))
     plan = bs.BatchPlan(offs, ks, seeds, tune=tune)
     out_o = torch.empty(plan.total_k, dtype=torch.int32, device=dev)
     out_r = torch.empty(plan.total_k, dtype=torch.float32, device=dev)
@@ -489,7 +490,8 @@ def bench_batched(bs, torch, np, cpu=True):
     plan.close()
     cpu_rec = cpu_oracle_objects(pts, offs, ks, seeds, order_idx, plan.total_k, batch_s) if cpu else None
     return {"objects": m, "candidates": int(pts.shape[0]), "sum_k": int(plan.total_k),
-            "cell_target": float(tune.cell_points), "seconds": batch_s, "ordered_surfels_per_s": plan.total_k / batch_s,
+            "cell_target": float(tune.cell_points), "wide_workgroups": int(tune.groups),
+            "seconds": batch_s, "ordered_surfels_per_s": plan.total_k / batch_s,
             "plain_loop_ordered_surfels_per_s": plain_rate,
             "plain_loop_sample": "%d objects spread over the size range, %d picks, %.1f s" % (len(sample), sk, sample_s),
             "plain_loop_estimated_seconds": plain_est_s, "speedup_vs_plain": plain_est_s / batch_s,

@@ -114,10 +114,11 @@ typedef struct {
                               cooperative scan holds n) */
     int32_t batch_wide;    /* batch plans: how many of the objects with the largest k are
                               ordered by 1024-thread workgroups (a second persistent
-                              kernel beside the 256-thread one, on at most half the CUs;
-                              same result).  0 = auto (objects with k >= 65536 and more
-                              than half the mean k per 256-thread workgroup slot), -1 =
-                              none */
+                              kernel beside the 256-thread one, on `groups` CUs; same
+                              result).  0 = auto (objects with k >= 65536 and more than
+                              half the mean k per 256-thread workgroup slot), -1 = none.
+                              For batch plans `groups` is the number of those 1024-thread
+                              workgroups (one CU each; 0 = three quarters of the CUs) */
     int32_t spin_limit;    /* cooperative kernels: polls of a bounded wait for the other
                               workgroups before giving up (0 = default, about a second).
                               A small value forces the give-up path from the host (tests
@@ -346,7 +347,13 @@ void bs_autotune_clear(void);
  * the largest k and twelve spread over the rest, each cut to at most 4096
  * picks) as batches with cell occupancies 4, 8, 16 and 32 candidates and
  * returns the fastest in out_tuning->cell_points (kernel = BS_KERNEL_GRID),
- * to pass to bs_batch_plan_create.  Synchronous; errors as bs_autotune.
+ * to pass to bs_batch_plan_create.  When the batch has objects for the
+ * 1024-thread workgroups (bs_tuning.batch_wide) and at most 2^27 picks in
+ * all, it then orders the whole batch once for each share of the CUs given
+ * to those workgroups (4/8 .. 7/8) and returns the fastest in
+ * out_tuning->groups (this needs the batch's workspace and outputs a second
+ * time, allocated from the stream-ordered pool).  Synchronous; errors as
+ * bs_autotune.
  */
 int bs_batch_autotune(const int64_t* h_offsets, const int64_t* h_k, const uint64_t* h_seed,
                       int32_t m, const float* d_points, bs_tuning* out_tuning, void* stream);

@@ -403,19 +403,15 @@ int bs_order(const float* d_points, const float* d_normals, const uint8_t* d_col
     return rc;
 }
 
-struct bs_batch_plan {
-    bs::BatchPlan* p;
-    int32_t m_all;
-};
-
 int bs_batch_plan_create(const int64_t* h_offsets, const int64_t* h_k, const uint64_t* h_seed,
                          int32_t m, const bs_tuning* tuning, bs_batch_plan** out_plan) {
     if (!out_plan) return set_error(BS_ERR_INVALID_ARG, "null plan pointer");
     *out_plan = nullptr;
-    if (!tuning_clean(tuning)) return set_error(BS_ERR_INVALID_ARG, "bad tuning struct");
+    if (!tuning_clean(tuning) || (tuning && tuning->groups < 0)) return set_error(BS_ERR_INVALID_ARG, "bad tuning struct");
     const float target = (tuning && tuning->cell_points > 0.f) ? tuning->cell_points : kDefaultCellPointsMulti;
     bs::BatchPlan* p = nullptr;
-    const int rc = batch_plan_create(h_offsets, h_k, h_seed, m, target, tuning ? tuning->batch_wide : 0, &p);
+    const int rc = batch_plan_create(h_offsets, h_k, h_seed, m, target, tuning ? tuning->batch_wide : 0,
+                                     tuning ? tuning->groups : 0, &p);
     if (rc != BS_OK) return rc;
     *out_plan = new bs_batch_plan{p, m};
     return BS_OK;

@@ -273,7 +273,8 @@ int bs_hier_plan_create(int32_t m, const int32_t* h_parent, const int64_t* h_lea
             need = std::max(need, sneed);
         } else {
             const int rc = batch_plan_create(offs.data(), ks.data(), seeds.data(), int32_t(L.nodes.size()), target,
-                                             tuning ? tuning->batch_wide : 0, &L.plan);
+                                             tuning ? tuning->batch_wide : 0, tuning ? tuning->groups : 0,
+                                             &L.plan);
             if (rc != BS_OK) {
                 free_plan(p);
                 return rc;

@@ -84,12 +84,15 @@ hipError_t launch_scan_several(const ScanShape& s, const float* pts, int n, int 
 // Batched plans (bs_batch.hip).
 struct BatchPlan;
 // wide: objects (largest k first) for 1024-thread workgroups in
-// batch_plan_execute; 0 = automatic, -1 = none (see bs_tuning.batch_wide)
+// batch_plan_execute; 0 = automatic, -1 = none (see bs_tuning.batch_wide);
+// wide_groups: those workgroups (0 = automatic, see bs_tuning.groups)
 int batch_plan_create(const int64_t* h_offsets, const int64_t* h_k, const uint64_t* h_seed, int32_t m,
-                      float target, int wide, BatchPlan** out);
+                      float target, int wide, int wide_groups, BatchPlan** out);
 void batch_plan_free(BatchPlan* p);
 size_t batch_workspace_bytes(const BatchPlan* p);
 int64_t batch_total_k(const BatchPlan* p);
+// Objects ordered by the 1024-thread workgroups.
+int batch_wide_count(const BatchPlan* p);
 const int64_t* batch_out_offsets(const BatchPlan* p);
 int batch_slots(const BatchPlan* p);
 void batch_set_job_io(BatchPlan* p, const std::vector<int32_t*>& order, const std::vector<float*>& radius,
@@ -138,3 +141,9 @@ bool tuned_lookup(int64_t n, int64_t k, bs_tuning* out);
 int forced_tuning(bs_tuning* out);
 
 }  // namespace bs
+
+// The C ABI's batch plan handle (opaque in the public header).
+struct bs_batch_plan {
+    bs::BatchPlan* p;
+    int32_t m_all;
+};

@@ -98,7 +98,7 @@ public:
         }
         HipBatch* b = new HipBatch();
         const int rc = batch_plan_create(offs.data(), ks.data(), seeds.data(), int32_t(jobs.size()),
-                                         cfg_.cell_points > 0.f ? cfg_.cell_points : 8.f, -1, &b->plan);
+                                         cfg_.cell_points > 0.f ? cfg_.cell_points : 8.f, -1, 0, &b->plan);
         if (rc != BS_OK) {
             delete b;
             return rc;

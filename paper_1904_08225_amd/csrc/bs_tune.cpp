@@ -305,6 +305,10 @@ extern "C" void bs_autotune_clear(void) {
     g_cache_loaded = false;  // the next lookup reads the cache file again
 }
 
+// Batches up to this many picks in all are timed whole when choosing the
+// share of the wide workgroups (about a second each at 7.4e7 picks).
+constexpr int64_t kFullBatchTuneK = int64_t(1) << 27;
+
 extern "C" int bs_batch_autotune(const int64_t* h_offsets, const int64_t* h_k, const uint64_t* h_seed,
                                  int32_t m, const float* d_points, bs_tuning* out_tuning, void* stream) {
     if (!out_tuning || !d_points || m < 1 || !h_offsets || !h_k)
@@ -389,6 +393,61 @@ extern "C" int bs_batch_autotune(const int64_t* h_offsets, const int64_t* h_k, c
     (void)hipStreamSynchronize(st);
     if (rc != BS_OK) return rc;
     if (!std::isfinite(best_ms)) return set_error(BS_ERR_UNSUPPORTED, "batch autotune: no configuration ran");
-    *out_tuning = make_tuning(BS_KERNEL_GRID, 0, 0, best_cp, 0);
+    bs_tuning best = make_tuning(BS_KERNEL_GRID, 0, 0, best_cp, 0);
+    // The compute units given to the 1024-thread workgroups of the longest
+    // chains against the 256-thread ones: that balance is a property of the
+    // whole batch (a sample keeps the longest chain but not the total work),
+    // so the whole batch is ordered once per candidate share, when it has
+    // such chains and is small enough to time.
+    int64_t full_k = 0;
+    for (int j = 0; j < m; ++j) full_k += std::max<int64_t>(h_k[j], 0);
+    int dev = 0, cus = 0;
+    (void)hipGetDevice(&dev);
+    (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    bs_batch_plan* probe = nullptr;
+    if (cus >= 8 && full_k <= kFullBatchTuneK &&
+        bs_batch_plan_create(h_offsets, h_k, h_seed, m, &best, &probe) == BS_OK) {
+        const bool has_wide = batch_wide_count(probe->p) > 0;
+        const size_t wsb = bs_batch_workspace_size(probe);
+        bs_batch_plan_destroy(probe);
+        void* ws = nullptr;
+        outo = outr = nullptr;
+        hipError_t ea = hipSuccess;
+        if (has_wide) {
+            ea = hipMallocAsync(&ws, std::max<size_t>(wsb, 256), st);
+            if (ea == hipSuccess) ea = hipMallocAsync(&outo, size_t(std::max<int64_t>(full_k, 1)) * 4, st);
+            if (ea == hipSuccess) ea = hipMallocAsync(&outr, size_t(std::max<int64_t>(full_k, 1)) * 4, st);
+        }
+        float best_full = INFINITY;
+        for (int eighths = 4; has_wide && ea == hipSuccess && eighths <= 7; ++eighths) {
+            bs_tuning t = best;
+            t.groups = cus * eighths / 8;
+            bs_batch_plan* plan = nullptr;
+            if (bs_batch_plan_create(h_offsets, h_k, h_seed, m, &t, &plan) != BS_OK) continue;
+            int r = bs_batch_plan_execute(plan, d_points, static_cast<int32_t*>(outo), static_cast<float*>(outr),
+                                          ws, wsb, stream);  // warm (captures the graph)
+            float ms = INFINITY;
+            if (r == BS_OK) {
+                (void)hipEventRecord(tm.a, st);
+                r = bs_batch_plan_execute(plan, d_points, static_cast<int32_t*>(outo), static_cast<float*>(outr),
+                                          ws, wsb, stream);
+                (void)hipEventRecord(tm.b, st);
+                if (hipEventSynchronize(tm.b) != hipSuccess) rc = set_error(BS_ERR_HIP, "autotune: device error");
+                if (r == BS_OK && rc == BS_OK && hipEventElapsedTime(&ms, tm.a, tm.b) != hipSuccess) ms = INFINITY;
+            }
+            bs_batch_plan_destroy(plan);
+            if (rc != BS_OK) break;
+            if (ms < best_full) {
+                best_full = ms;
+                best.groups = t.groups;
+            }
+        }
+        if (ws) (void)hipFreeAsync(ws, st);
+        if (outo) (void)hipFreeAsync(outo, st);
+        if (outr) (void)hipFreeAsync(outr, st);
+        (void)hipStreamSynchronize(st);
+        if (rc != BS_OK) return rc;
+    }
+    *out_tuning = best;
     return BS_OK;
 }

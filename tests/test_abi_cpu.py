@@ -69,6 +69,11 @@ def test_batch_plan_validation_without_device(lib):
     ks = np.array([1], dtype=np.int64)
     rc = lib.bs_batch_plan_create(offs.ctypes.data_as(vp), ks.ctypes.data_as(vp), None, 1, None, ctypes.byref(plan))
     assert rc == bs.BS_ERR_INVALID_ARG
+    offs = np.array([0, 5], dtype=np.int64)       # negative count of wide workgroups
+    t = bs.tuning(groups=-1)
+    rc = lib.bs_batch_plan_create(offs.ctypes.data_as(vp), ks.ctypes.data_as(vp), None, 1, ctypes.byref(t),
+                                  ctypes.byref(plan))
+    assert rc == bs.BS_ERR_INVALID_ARG
 
 
 def test_server_config_validation_without_device(lib):

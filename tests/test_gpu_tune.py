@@ -52,6 +52,37 @@ def test_batch_autotune(hip):
     plan.close()
 
 
+def test_batch_autotune_wide_share(hip):
+    """A batch with objects for the 1024-thread workgroups: the tuner also
+    times the whole batch per share of the CUs given to them and returns one
+    of its candidates in `groups`; every object of the tuned plan orders as
+    the oracle (the two long chains by the grid oracle)."""
+    import torch
+    cus = torch.cuda.get_device_properties(0).multi_processor_count
+    sizes = [270000, 262000] + [3000 + 1700 * i for i in range(10)]
+    ks = [66000, 65600] + [s // 4 for s in sizes[2:]]
+    objs = [synth.cad_part(s, seed=90 + i, count=30).points.numpy() for i, s in enumerate(sizes)]
+    seeds = [7 * i + 3 for i in range(len(sizes))]
+    offs = np.concatenate([[0], np.cumsum(sizes)]).astype(np.int64)
+    pts = torch.from_numpy(np.concatenate(objs).astype(np.float32)).cuda()
+    t = hip.batch_autotune(pts, offs, ks, seeds)
+    assert t.kernel == hip.KERNEL_GRID and t.cell_points in (4.0, 8.0, 16.0, 32.0)
+    assert t.groups in [cus * e // 8 for e in range(4, 8)], t.groups
+    plan = hip.BatchPlan(offs, ks, seeds, tune=t)
+    o, r = plan.execute(pts)
+    torch.cuda.synchronize()
+    oo, rr = o.cpu().numpy(), r.cpu().numpy()
+    for j in range(len(objs)):
+        a, b = plan.out_offsets[j], plan.out_offsets[j + 1]
+        st = oracle.start_index(seeds[j], objs[j].shape[0])
+        if ks[j] > 20000:
+            eo, er = oracle.greedy32_grid(objs[j], ks[j], st)
+        else:
+            eo, er = oracle.greedy32(objs[j], ks[j], st)
+        assert_parity(oo[a:b], rr[a:b], eo, er, "tuned wide batch object %d" % j)
+    plan.close()
+
+
 def test_tune_cache_file(hip, tmp_path, monkeypatch):
     """BS_TUNE_CACHE: the autotuner records its winner in the file, and after
     the in-memory table is cleared the automatic choice reads it back (what a
