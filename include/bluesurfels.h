@@ -297,6 +297,27 @@ int64_t bs_prefix_length(double r, double r_m, int64_t p_m, int64_t k);
  */
 int64_t bs_prefix_for_radius(const float* h_radius, int64_t k, float r);
 
+/*
+ * The Morton (Z-order) layout the ordering kernels keep candidates in.  This
+ * is not an operation of the paper (it is how this library lays out the
+ * candidates for the pruned update): 30-bit codes from a 2^10-per-axis
+ * quantization of the bounding box, scaled by its longest side
+ * (binary32: q = (int)((p - lo) * (1024.0f / extent)), clamped to
+ * [0, 1023]; x in the lowest bit of each triple), sorted stably, so equal
+ * codes stay in index order.  Exposed for spatially coherent surfel layouts
+ * and to check the sort.
+ *   bs_morton_order: d_out_perm[i] = index of the i-th candidate in that
+ *     order (device int32[n]); workspace of bs_morton_workspace_size(n)
+ *     bytes, 256-byte aligned, owned by the caller.  n = 0 is a no-op.
+ *   (bs_batch_morton_order, with the batch functions below, does the same
+ *     for every object of a batch plan.)
+ * Enqueued on `stream`.  Errors: BS_ERR_INVALID_ARG (null pointers, n < 0,
+ * n >= 2^31, small or misaligned workspace), BS_ERR_HIP.
+ */
+size_t bs_morton_workspace_size(int64_t n);
+int bs_morton_order(const float* d_points, int64_t n, int32_t* d_out_perm, void* d_workspace, size_t workspace_bytes,
+                    void* stream);
+
 /* ------------------------------------------------------------ autotuner */
 
 /*
@@ -407,6 +428,16 @@ int bs_batch_out_offsets(const bs_batch_plan* plan, int64_t* h_out_offsets);
 int bs_batch_plan_execute(bs_batch_plan* plan, const float* d_points, int32_t* d_out_order,
                           float* d_out_radius, void* d_workspace, size_t workspace_bytes,
                           void* stream);
+
+/*
+ * Each object's candidates in the Morton layout of bs_morton_order, every
+ * object sorted within its own rows: row i of object j (rows h_offsets[j] ..
+ * h_offsets[j+1]-1 of d_out_perm, device int32[N]) receives an index local
+ * to the object.  Workspace as for bs_batch_plan_execute.  Enqueued on
+ * `stream`.  Errors: BS_ERR_INVALID_ARG, BS_ERR_HIP.
+ */
+int bs_batch_morton_order(bs_batch_plan* plan, const float* d_points, int32_t* d_out_perm, void* d_workspace,
+                          size_t workspace_bytes, void* stream);
 void bs_batch_plan_destroy(bs_batch_plan* plan);
 /*
  * The randomized sampler (bs_sample, paper Sec. 3.2) over the plan's objects

@@ -164,6 +164,12 @@ def load():
     lib.bs_batch_out_offsets.restype = i32
     lib.bs_batch_plan_execute.argtypes = [vp, vp, vp, vp, vp, sz, vp]
     lib.bs_batch_plan_execute.restype = i32
+    lib.bs_batch_morton_order.argtypes = [vp, vp, vp, vp, sz, vp]
+    lib.bs_batch_morton_order.restype = i32
+    lib.bs_morton_workspace_size.argtypes = [i64]
+    lib.bs_morton_workspace_size.restype = sz
+    lib.bs_morton_order.argtypes = [vp, i64, vp, vp, sz, vp]
+    lib.bs_morton_order.restype = i32
     lib.bs_batch_plan_destroy.argtypes = [vp]
     lib.bs_batch_plan_destroy.restype = None
     lib.bs_server_create.argtypes = [vp, ctypes.POINTER(vp)]
@@ -410,6 +416,19 @@ def prefix_nn(points, order, p: int, stream=None):
     return out
 
 
+def morton_order(points, stream=None):
+    """The candidates' indices in the Morton layout of the ordering kernels
+    (``bs_morton_order``): int32 [n] on the points' device."""
+    import torch
+    lib = load()
+    pts = _prep_points(points)
+    n = int(pts.shape[0])
+    out = torch.empty(max(n, 1), dtype=torch.int32, device=pts.device)
+    ws = torch.empty(max(int(lib.bs_morton_workspace_size(n)), 1), dtype=torch.uint8, device=pts.device)
+    _check(lib.bs_morton_order(_ptr(pts), n, _ptr(out), _ptr(ws), int(ws.numel()), _stream_handle(stream)))
+    return out[:n]
+
+
 def primitive_records(kind, center, rot, prm, rgb):
     """Pack primitives into the 68-byte ``bs_primitive`` records (numpy
     structured array): kind int[P] (0 sphere, 1 box, 2 cylinder), center
@@ -592,6 +611,20 @@ class BatchPlan:
         _check(self._lib.bs_batch_plan_execute(self._plan, _ptr(points), _ptr(out_order), _ptr(out_radius),
                                                _ptr(workspace), int(workspace.numel()), _stream_handle(stream)))
         return out_order[: self.total_k], out_radius[: self.total_k]
+
+    def morton_order(self, points, stream=None):
+        """Each object's candidates in the Morton layout, indices local to
+        the object, at the object's rows (``bs_batch_morton_order``)."""
+        import torch
+        points = _prep_points(points)
+        dev = points.device
+        n = int(points.shape[0])
+        out = torch.empty(max(n, 1), dtype=torch.int32, device=dev)
+        if self._ws is None or self._ws.numel() < self.workspace_bytes:
+            self._ws = torch.empty(max(self.workspace_bytes, 1), dtype=torch.uint8, device=dev)
+        _check(self._lib.bs_batch_morton_order(self._plan, _ptr(points), _ptr(out), _ptr(self._ws),
+                                               int(self._ws.numel()), _stream_handle(stream)))
+        return out[:n]
 
     def execute_sample(self, points, sample_size: int = 200, growth_rounds: int = 500, vicinity: float = 0.0,
                        out_order=None, out_radius=None, out_count=None, workspace=None, stream=None):

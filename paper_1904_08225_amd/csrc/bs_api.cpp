@@ -282,6 +282,27 @@ int64_t bs_prefix_for_radius(const float* h_radius, int64_t k, float r) {
     return lo;
 }
 
+size_t bs_morton_workspace_size(int64_t n) {
+    if (n < 1 || n >= (int64_t(1) << 31)) return 0;
+    return grid_layout(n, 1024).total;
+}
+
+int bs_morton_order(const float* d_points, int64_t n, int32_t* d_out_perm, void* d_workspace, size_t workspace_bytes,
+                    void* stream) {
+    if (n < 0 || n >= (int64_t(1) << 31)) return set_error(BS_ERR_INVALID_ARG, "n=%lld outside [0, 2^31)", (long long)n);
+    if (n == 0) return BS_OK;
+    if (!d_points || !d_out_perm || !d_workspace) return set_error(BS_ERR_INVALID_ARG, "null pointer");
+    if (workspace_bytes < bs_morton_workspace_size(n))
+        return set_error(BS_ERR_INVALID_ARG, "workspace %zu bytes < %zu needed", workspace_bytes,
+                         bs_morton_workspace_size(n));
+    if (reinterpret_cast<uintptr_t>(d_workspace) % kAlign)
+        return set_error(BS_ERR_INVALID_ARG, "workspace not %zu-byte aligned", kAlign);
+    const hipError_t e = launch_morton_order(d_points, int(n), d_out_perm, d_workspace,
+                                             reinterpret_cast<hipStream_t>(stream));
+    if (e != hipSuccess) return set_error(BS_ERR_HIP, "morton order: %s", hipGetErrorString(e));
+    return BS_OK;
+}
+
 size_t bs_workspace_size(int64_t n, int64_t k, const bs_tuning* tuning) {
     if (n < 1 || n >= (int64_t(1) << 31) || k < 0 || k > n || !tuning_clean(tuning)) return 0;
     Plan p;
@@ -436,6 +457,13 @@ int bs_batch_plan_execute(bs_batch_plan* plan, const float* d_points, int32_t* d
     if (!plan) return set_error(BS_ERR_INVALID_ARG, "null plan");
     return batch_plan_execute(plan->p, d_points, d_out_order, d_out_radius, d_workspace,
                               workspace_bytes, reinterpret_cast<hipStream_t>(stream));
+}
+
+int bs_batch_morton_order(bs_batch_plan* plan, const float* d_points, int32_t* d_out_perm, void* d_workspace,
+                          size_t workspace_bytes, void* stream) {
+    if (!plan) return set_error(BS_ERR_INVALID_ARG, "null plan");
+    return batch_morton_order(plan->p, d_points, d_out_perm, d_workspace, workspace_bytes,
+                              reinterpret_cast<hipStream_t>(stream));
 }
 
 int bs_batch_plan_execute_sample(bs_batch_plan* plan, const bs_sampler* params, const float* d_points,

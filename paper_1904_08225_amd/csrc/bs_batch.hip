@@ -12,7 +12,6 @@
 #pragma clang fp contract(off)
 
 #include <hip/hip_runtime.h>
-#include <hipcub/hipcub.hpp>
 
 #include <algorithm>
 #include <cstring>
@@ -467,6 +466,14 @@ __global__ void bdesc_kernel(int m, const ObjHdr* __restrict__ hd, const int32_t
     desc[j] = d;
 }
 
+// Sorted position -> index within its object (the Morton order of each object).
+__global__ void blocal_kernel(const uint64_t* __restrict__ keys_s, const uint32_t* __restrict__ vals_s, int N,
+                              const int32_t* __restrict__ offs, int32_t* __restrict__ out) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= N) return;
+    out[i] = int32_t(vals_s[i]) - offs[int(keys_s[i] >> kObjBits)];
+}
+
 __global__ void queue_reset_kernel(uint32_t* q) {
     if (threadIdx.x < 2) q[threadIdx.x] = 0u;
 }
@@ -675,6 +682,7 @@ struct BatchPlan {
     float target = 32.f;
     std::vector<int32_t> h_offs;    // m + 1
     std::vector<int32_t> h_k, h_start, h_lpt;
+    std::vector<SortTile> h_tiles;  // tiles of the per-object Morton sort
     std::vector<uint64_t> h_seed;     // kept objects' seeds (the sampler's Philox keys)
     std::vector<int32_t> h_kept;      // caller object number of each kept object (device upload)
     std::vector<int64_t> h_out_offs;  // m_all + 1 (caller's object numbering)
@@ -729,6 +737,7 @@ struct BatchWs {
     SampleSpec* sdesc;
     uint64_t* seeds;
     int32_t* kept;
+    SortTile* tiles;
     void* temp;
     size_t total;
 };
@@ -765,16 +774,11 @@ BatchWs batch_layout(const BatchPlan& p, char* base) {
     w.sdesc = carve<SampleSpec>(base, off, m + 1);
     w.seeds = carve<uint64_t>(base, off, m + 1);
     w.kept = carve<int32_t>(base, off, m + 1);
+    w.tiles = carve<SortTile>(base, off, std::max<size_t>(p.h_tiles.size(), 1));
     w.temp = base + off;
     off += align_up(std::max(p.sort_bytes, p.scan_bytes));
     w.total = off;
     return w;
-}
-
-int end_bit_for(int m) {
-    int b = 1;
-    while ((1 << b) < m + 1) ++b;
-    return kObjBits + b;
 }
 
 hipError_t capture_order_graph(BatchPlan& p, const BatchWs& w) {
@@ -874,14 +878,10 @@ int batch_plan_create(const int64_t* h_offsets, const int64_t* h_k, const uint64
     std::stable_sort(p->h_lpt.begin(), p->h_lpt.end(),
                      [&](int a, int b) { return p->h_k[a] > p->h_k[b]; });
     p->mwork = int(p->h_lpt.size());
-    if (p->N > 0) {
-        // size queries only (no device work): their status carries nothing
-        (void)hipcub::DeviceRadixSort::SortPairs(nullptr, p->sort_bytes, (const uint64_t*)nullptr,
-                                                 (uint64_t*)nullptr, (const uint32_t*)nullptr,
-                                                 (uint32_t*)nullptr, p->N, 0, end_bit_for(p->m));
-        (void)hipcub::DeviceScan::InclusiveSum(nullptr, p->scan_bytes, (const uint32_t*)nullptr,
-                                               (uint32_t*)nullptr, p->N);
-    }
+    // tiles of the per-object sort (each object sorted where it lies)
+    p->h_tiles = sort_tiles(p->h_offs.data(), p->m);
+    p->sort_bytes = sort_temp_bytes(int64_t(p->h_tiles.size()));
+    p->scan_bytes = scan_temp_bytes(p->N);
     p->h_outo = outo;
     p->ws_bytes = batch_layout(*p, nullptr).total;
     int dev = 0, cus = 0, per = 0;
@@ -945,10 +945,12 @@ int batch_slots(const BatchPlan* p) { return p ? p->slots : 0; }
 namespace {
 
 // Validation, per-object grids and the objects' descriptors (w.desc), all
-// enqueued on st; shared by the batched launch and the serving ring.
+// enqueued on st; shared by the batched launch and the serving ring.  With
+// sort_only, up to the per-object Morton sort (keys_s, vals_s).
 int batch_preprocess(BatchPlan* p, const float* pts, int32_t* out_order, float* out_radius, void* ws,
-                     size_t ws_bytes, hipStream_t st, BatchWs& w) {
-    if (!pts || (!out_order && p->h_io.empty())) return set_error(BS_ERR_INVALID_ARG, "null points or output");
+                     size_t ws_bytes, hipStream_t st, BatchWs& w, bool sort_only = false) {
+    if (!pts || (!sort_only && !out_order && p->h_io.empty()))
+        return set_error(BS_ERR_INVALID_ARG, "null points or output");
     if (!ws || ws_bytes < p->ws_bytes)
         return set_error(BS_ERR_INVALID_ARG, "workspace %zu bytes < %zu needed", ws_bytes, p->ws_bytes);
     if (reinterpret_cast<uintptr_t>(ws) % kAlign)
@@ -962,6 +964,9 @@ int batch_preprocess(BatchPlan* p, const float* pts, int32_t* out_order, float* 
         e = hipMemcpyAsync(w.starts, p->h_start.data(), p->h_start.size() * 4, hipMemcpyHostToDevice, st);
     if (e == hipSuccess && p->mwork)
         e = hipMemcpyAsync(w.lpt, p->h_lpt.data(), p->h_lpt.size() * 4, hipMemcpyHostToDevice, st);
+    if (e == hipSuccess && !p->h_tiles.empty())
+        e = hipMemcpyAsync(w.tiles, p->h_tiles.data(), p->h_tiles.size() * sizeof(SortTile), hipMemcpyHostToDevice,
+                           st);
     if (e == hipSuccess)
         e = hipMemcpyAsync(w.outo, p->h_outo.data(), p->h_outo.size() * 8, hipMemcpyHostToDevice, st);
     const bool use_io = !p->h_io.empty();
@@ -975,16 +980,14 @@ int batch_preprocess(BatchPlan* p, const float* pts, int32_t* out_order, float* 
     hipLaunchKernelGGL(bvalidate_kernel, dim3(std::min(nblk, 8192)), dim3(tb), 0, st, pts, N, w.offs, m, w.hd);
     hipLaunchKernelGGL(bmorton_kernel, dim3(nblk), dim3(tb), 0, st, pts, N, w.offs, m, w.hd, w.keys, w.vals);
     if ((e = hipGetLastError()) != hipSuccess) return set_error(BS_ERR_HIP, "%s", hipGetErrorString(e));
-    size_t tbytes = std::max(p->sort_bytes, p->scan_bytes);
-    e = hipcub::DeviceRadixSort::SortPairs(w.temp, tbytes, w.keys, w.keys_s, w.vals, w.vals_s, N, 0,
-                                           end_bit_for(m), st);
+    e = sort_codes_segmented(w.keys, w.keys_s, w.vals, w.vals_s, w.tiles, int(p->h_tiles.size()), N, w.temp, st);
     if (e != hipSuccess) return set_error(BS_ERR_HIP, "sort: %s", hipGetErrorString(e));
+    if (sort_only) return BS_OK;
     hipLaunchKernelGGL(bhist_kernel, dim3(nblk), dim3(tb), 0, st, w.keys_s, N, w.hd);
     hipLaunchKernelGGL(blevel_kernel, dim3(mblk), dim3(tb), 0, st, m, w.offs, w.hd, p->target,
                        kBatchMaxBlocks);
     hipLaunchKernelGGL(bflag_kernel, dim3(nblk), dim3(tb), 0, st, w.keys_s, N, w.hd, w.flags);
-    tbytes = std::max(p->sort_bytes, p->scan_bytes);
-    e = hipcub::DeviceScan::InclusiveSum(w.temp, tbytes, w.flags, w.cellidx, N, st);
+    e = inclusive_scan_u32(w.flags, w.cellidx, N, w.temp, st);
     if (e != hipSuccess) return set_error(BS_ERR_HIP, "scan: %s", hipGetErrorString(e));
     hipLaunchKernelGGL(bgather_kernel, dim3(nblk), dim3(tb), 0, st, pts, w.keys_s, w.vals_s, w.flags,
                        w.cellidx, N, w.offs, w.starts, w.hd, w.xyzm, w.ids, w.cstart);
@@ -1091,6 +1094,20 @@ int batch_plan_execute_sample(BatchPlan* p, int S, int K, float vicinity, const 
 }
 
 int batch_work_count(const BatchPlan* p) { return p ? p->mwork : 0; }
+
+int batch_morton_order(BatchPlan* p, const float* pts, int32_t* out_perm, void* ws, size_t ws_bytes,
+                       hipStream_t st) {
+    if (!p || !out_perm) return set_error(BS_ERR_INVALID_ARG, "null plan or output");
+    if (p->N == 0) return BS_OK;
+    std::lock_guard<std::mutex> lk(p->mu);
+    BatchWs w;
+    const int rc = batch_preprocess(p, pts, nullptr, nullptr, ws, ws_bytes, st, w, true);
+    if (rc != BS_OK) return rc;
+    hipLaunchKernelGGL(blocal_kernel, dim3((p->N + 255) / 256), dim3(256), 0, st, w.keys_s, w.vals_s, p->N, w.offs,
+                       out_perm);
+    const hipError_t e = hipGetLastError();
+    return e == hipSuccess ? BS_OK : set_error(BS_ERR_HIP, "%s", hipGetErrorString(e));
+}
 
 int batch_plan_publish(BatchPlan* p, const float* pts, void* ws, size_t ws_bytes, const ServeRing& ring,
                        uint32_t base, hipStream_t st) {

@@ -70,6 +70,8 @@ struct SortedPoints {
     void* slots;               // exchange records of the cooperative scan
 };
 hipError_t launch_sorted_points(const float* pts, int n, int start, void* ws, hipStream_t st, SortedPoints* out);
+// The candidates' indices in Morton order (launch_sorted_points, then a copy).
+hipError_t launch_morton_order(const float* pts, int n, int32_t* out_perm, void* ws, hipStream_t st);
 
 // lead >= 2 (several-picks kernel only): picks 0 .. lead-1 come from the
 // cooperative full scan of shape *lead_shape, which hands its state to the

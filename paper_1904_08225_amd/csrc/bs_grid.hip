@@ -24,7 +24,6 @@
 #pragma clang fp contract(off)
 
 #include <hip/hip_runtime.h>
-#include <hipcub/hipcub.hpp>
 #include <math.h>
 #include <stdint.h>
 
@@ -354,13 +353,7 @@ GridLayout grid_layout(int64_t n, int block) {
     g.bdyn = take(size_t(kMaxBlocksAny) * 32);
     g.sbstat = take(size_t(kMaxBlocksAny / 64) * 32);
     g.lead_slots = take(scan_slot_bytes(kMaxCoopGroups));
-    size_t sort_bytes = 0, scan_bytes = 0;
-    // size queries only (no device work): their status carries nothing
-    (void)hipcub::DeviceRadixSort::SortPairs(nullptr, sort_bytes, (const uint32_t*)nullptr, (uint32_t*)nullptr,
-                                             (const uint32_t*)nullptr, (uint32_t*)nullptr, int(n), 0,
-                                             3 * kMortonBits);
-    (void)hipcub::DeviceScan::InclusiveSum(nullptr, scan_bytes, (const uint32_t*)nullptr, (uint32_t*)nullptr,
-                                           int(n));
+    const size_t sort_bytes = sort_temp_bytes(sort_tile_count(n)), scan_bytes = scan_temp_bytes(n);
     g.temp = take(sort_bytes > scan_bytes ? sort_bytes : scan_bytes);
     g.temp_bytes = sort_bytes > scan_bytes ? sort_bytes : scan_bytes;
     g.total = off;
@@ -387,8 +380,8 @@ hipError_t launch_sorted_points(const float* pts, int n, int start, void* ws, hi
     const int nblk = (n + tb - 1) / tb;
     hipLaunchKernelGGL(morton_kernel, dim3(nblk), dim3(tb), 0, st, pts, n, hdr, codes, vals);
     if ((e = hipGetLastError()) != hipSuccess) return e;
-    size_t tbytes = g.temp_bytes;
-    e = hipcub::DeviceRadixSort::SortPairs(temp, tbytes, codes, codes_s, vals, ids, n, 0, 3 * kMortonBits, st);
+    static_assert(3 * kMortonBits == 30, "the sort orders 30-bit codes");
+    e = sort_codes_u32(codes, codes_s, vals, ids, n, temp, st);
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(sorted_gather_kernel, dim3(nblk), dim3(tb), 0, st, pts, ids, n, start, gh, xyzm);
     if ((e = hipGetLastError()) != hipSuccess) return e;
@@ -399,6 +392,14 @@ hipError_t launch_sorted_points(const float* pts, int n, int start, void* ws, hi
     out->start_pos = &gh->start_pos;
     out->slots = base + g.lead_slots;
     return hipSuccess;
+}
+
+hipError_t launch_morton_order(const float* pts, int n, int32_t* out_perm, void* ws, hipStream_t st) {
+    SortedPoints sp{};
+    hipError_t e = launch_sorted_points(pts, n, 0, ws, st, &sp);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(out_perm, sp.ids, size_t(n) * sizeof(int32_t), hipMemcpyDeviceToDevice, st);
+    return e;
 }
 
 int grid_block_size(int64_t n) { return n > (int64_t(1) << 16) ? 512 : 256; }
@@ -448,7 +449,7 @@ GridPieces grid_pieces(int n, int block, void* ws) {
 
 // First half of the grid build: header, validation, Morton codes and their
 // sort, the cell level, cell flags and cell indices.
-hipError_t grid_build_sort(const float* pts, int n, const GridPieces& q, size_t temp_bytes, float target,
+hipError_t grid_build_sort(const float* pts, int n, const GridPieces& q, float target,
                            int max_blocks, hipStream_t st) {
     hipError_t e = launch_init_header(q.hdr, st);
     if (e != hipSuccess) return e;
@@ -459,17 +460,14 @@ hipError_t grid_build_sort(const float* pts, int n, const GridPieces& q, size_t 
     const int nblk = (n + tb - 1) / tb;
     hipLaunchKernelGGL(morton_kernel, dim3(nblk), dim3(tb), 0, st, pts, n, q.hdr, q.codes, q.vals);
     if ((e = hipGetLastError()) != hipSuccess) return e;
-    size_t tbytes = temp_bytes;
-    e = hipcub::DeviceRadixSort::SortPairs(q.temp, tbytes, q.codes, q.codes_s, q.vals, q.ids, n, 0,
-                                           3 * kMortonBits, st);
+    e = sort_codes_u32(q.codes, q.codes_s, q.vals, q.ids, n, q.temp, st);
     if (e != hipSuccess) return e;
     const int hblk = nblk < 1024 ? nblk : 1024;
     hipLaunchKernelGGL(level_hist_kernel, dim3(hblk), dim3(tb), 0, st, q.codes_s, n, q.gh);
     hipLaunchKernelGGL(choose_level_kernel, dim3(1), dim3(64), 0, st, n, q.gh, target, max_blocks);
     hipLaunchKernelGGL(cell_flag_kernel, dim3(nblk), dim3(tb), 0, st, q.codes_s, n, q.gh, q.flags);
     if ((e = hipGetLastError()) != hipSuccess) return e;
-    tbytes = temp_bytes;
-    return hipcub::DeviceScan::InclusiveSum(q.temp, tbytes, q.flags, q.cellidx, n, st);
+    return inclusive_scan_u32(q.flags, q.cellidx, n, q.temp, st);
 }
 
 // Second half: the sorted candidates (with m from a leading scan, or +inf),
@@ -496,7 +494,7 @@ hipError_t launch_grid_sample(const float* pts, int n, int k, int start, uint64_
     constexpr int kBlock = 1024, kMaxB = 1024;
     const GridLayout g = grid_layout(n, kBlock);
     const GridPieces q = grid_pieces(n, kBlock, ws);
-    hipError_t e = grid_build_sort(pts, n, q, g.temp_bytes, target, kMaxB, st);
+    hipError_t e = grid_build_sort(pts, n, q, target, kMaxB, st);
     if (e != hipSuccess) return e;
     if ((e = grid_build_cells(pts, n, start, q, nullptr, st)) != hipSuccess) return e;
     // the unsorted Morton values are dead after the sort: each candidate's sorted position
@@ -554,7 +552,7 @@ hipError_t launch_grid(const float* pts, int n, int k, int start, int32_t* order
     uint4* bdyn = q.bdyn;
     float4* sbstat = q.sbstat;
 
-    hipError_t e = grid_build_sort(pts, n, q, g.temp_bytes, target, grid_max_blocks(block, picks), st);
+    hipError_t e = grid_build_sort(pts, n, q, target, grid_max_blocks(block, picks), st);
     if (e != hipSuccess) return e;
     float* m_lead = nullptr;
     if (lead >= 2) {

@@ -91,6 +91,10 @@ int batch_plan_create(const int64_t* h_offsets, const int64_t* h_k, const uint64
 void batch_plan_free(BatchPlan* p);
 size_t batch_workspace_bytes(const BatchPlan* p);
 int64_t batch_total_k(const BatchPlan* p);
+// Each object's candidates in Morton order (indices within the object), at
+// the object's rows of out_perm.
+int batch_morton_order(BatchPlan* p, const float* pts, int32_t* out_perm, void* ws, size_t ws_bytes,
+                       hipStream_t st);
 // Objects ordered by the 1024-thread workgroups.
 int batch_wide_count(const BatchPlan* p);
 const int64_t* batch_out_offsets(const BatchPlan* p);
@@ -135,6 +139,28 @@ int set_error(int code, const char* fmt, ...);
 int order_impl(const float* d_points, int64_t n, int64_t k, uint64_t seed, int64_t start_index,
                int32_t* d_out_order, float* d_out_radius, uint64_t* d_ticks, const LaunchOpts* ev,
                void* d_workspace, size_t workspace_bytes, const bs_tuning* tuning, void* stream);
+
+// Sort and scans of the grid builds (bs_sort.hip): a stable radix sort of
+// 30-bit Morton codes (within segments for a batch) and an inclusive scan.
+constexpr int kSortTileKeys = 4096;
+struct SortTile {
+    int32_t start, count;  // the tile's keys
+    int32_t hbase;         // count index of (its segment, digit 0, this tile)
+    int32_t ntiles;        // tiles of its segment
+};
+int64_t sort_tile_count(int64_t n);
+// Tiles of the segments offs[j] .. offs[j+1]-1 (host).
+std::vector<SortTile> sort_tiles(const int32_t* offs, int m);
+size_t sort_temp_bytes(int64_t ntiles);
+size_t scan_temp_bytes(int64_t n);
+// One segment: (codes, vals) sorted by bits 0..29 into (codes_s, vals_s);
+// codes and vals are overwritten.
+hipError_t sort_codes_u32(uint32_t* codes, uint32_t* codes_s, uint32_t* vals, uint32_t* vals_s, int n, void* temp,
+                          hipStream_t st);
+// Segments given by device tiles (sort_tiles): each sorted where it lies.
+hipError_t sort_codes_segmented(uint64_t* keys, uint64_t* keys_s, uint32_t* vals, uint32_t* vals_s,
+                                const SortTile* d_tiles, int ntiles, int n, void* temp, hipStream_t st);
+hipError_t inclusive_scan_u32(const uint32_t* in, uint32_t* out, int64_t n, void* temp, hipStream_t st);
 
 // The autotuned configuration for (n, k) on the current device, if any.
 bool tuned_lookup(int64_t n, int64_t k, bs_tuning* out);

@@ -48,7 +48,7 @@ def test_noalloc_equals_workspace_entry(hip):
 
 def test_noalloc_rejects_beyond_the_array(hip):
     import torch
-    n = 600000
+    n = 700000  # beyond the documented 524,288 and beyond the array's bytes
     assert hip.workspace_size(n, 1000) > hip.noalloc_max_bytes()
     pts = torch.zeros((n, 3), dtype=torch.float32, device="cuda")
     with pytest.raises(hip.BSError) as e:
