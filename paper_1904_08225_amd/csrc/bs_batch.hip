@@ -699,10 +699,18 @@ struct BatchPlan {
     hipStream_t side = nullptr;     // stream of the wide launch (forked from the caller's)
     hipEvent_t fork = nullptr, join = nullptr;
     bool use_graph = true;
-    // the captured ordering graph, valid for one workspace address
+    // Device copies of the plan's arrays (batch and hierarchy plans, made by
+    // batch_plan_upload; serving plans upload theirs into the workspace).
+    void* dev = nullptr;
+    int32_t *d_offs = nullptr, *d_ks = nullptr, *d_starts = nullptr, *d_lpt = nullptr, *d_kept = nullptr;
+    int64_t* d_outo = nullptr;
+    uint64_t* d_seeds = nullptr;
+    SortTile* d_tiles = nullptr;
+    // The captured execute (preprocessing, queue reset, both ordering
+    // kernels), valid for the pointers it was captured with.
     hipGraphExec_t exec = nullptr;
     hipGraph_t graph = nullptr;
-    void* graph_ws = nullptr;
+    const void* graph_key[4] = {nullptr, nullptr, nullptr, nullptr};  // workspace, points, order, radius
     std::mutex mu;
 };
 
@@ -781,34 +789,11 @@ BatchWs batch_layout(const BatchPlan& p, char* base) {
     return w;
 }
 
-hipError_t capture_order_graph(BatchPlan& p, const BatchWs& w) {
-    if (p.exec) {
-        (void)hipGraphExecDestroy(p.exec);
-        p.exec = nullptr;
-    }
-    if (p.graph) {
-        (void)hipGraphDestroy(p.graph);
-        p.graph = nullptr;
-    }
-    hipStream_t cap = nullptr;
-    hipError_t e = hipStreamCreateWithFlags(&cap, hipStreamNonBlocking);
-    if (e != hipSuccess) return e;
-    e = hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal);
-    if (e == hipSuccess) {
-        hipLaunchKernelGGL(batch_order_kernel<kBatchBlock>, dim3(p.slots), dim3(kBatchBlock), 0, cap, w.desc,
-                           w.lpt + p.nwide, p.mwork - p.nwide, w.queue);
-        hipError_t e2 = hipStreamEndCapture(cap, &p.graph);
-        e = (e2 != hipSuccess) ? e2 : hipGetLastError();
-    }
-    if (e == hipSuccess) e = hipGraphInstantiate(&p.exec, p.graph, nullptr, nullptr, 0);
-    (void)hipStreamDestroy(cap);
-    return e;
-}
-
 }  // namespace
 
 void batch_plan_free(BatchPlan* p) {
     if (!p) return;
+    if (p->dev) (void)hipFree(p->dev);
     if (p->exec) (void)hipGraphExecDestroy(p->exec);
     if (p->graph) (void)hipGraphDestroy(p->graph);
     if (p->side) (void)hipStreamDestroy(p->side);
@@ -957,18 +942,30 @@ int batch_preprocess(BatchPlan* p, const float* pts, int32_t* out_order, float* 
         return set_error(BS_ERR_INVALID_ARG, "workspace not %zu-byte aligned", kAlign);
     w = batch_layout(*p, static_cast<char*>(ws));
     const int N = p->N, m = p->m;
-    hipError_t e = hipMemcpyAsync(w.offs, p->h_offs.data(), p->h_offs.size() * 4, hipMemcpyHostToDevice, st);
-    if (e == hipSuccess && m)
-        e = hipMemcpyAsync(w.ks, p->h_k.data(), p->h_k.size() * 4, hipMemcpyHostToDevice, st);
-    if (e == hipSuccess && m)
-        e = hipMemcpyAsync(w.starts, p->h_start.data(), p->h_start.size() * 4, hipMemcpyHostToDevice, st);
-    if (e == hipSuccess && p->mwork)
-        e = hipMemcpyAsync(w.lpt, p->h_lpt.data(), p->h_lpt.size() * 4, hipMemcpyHostToDevice, st);
-    if (e == hipSuccess && !p->h_tiles.empty())
-        e = hipMemcpyAsync(w.tiles, p->h_tiles.data(), p->h_tiles.size() * sizeof(SortTile), hipMemcpyHostToDevice,
-                           st);
-    if (e == hipSuccess)
-        e = hipMemcpyAsync(w.outo, p->h_outo.data(), p->h_outo.size() * 8, hipMemcpyHostToDevice, st);
+    hipError_t e = hipSuccess;
+    if (p->dev) {  // the plan's own device copies: nothing to upload
+        w.offs = p->d_offs;
+        w.ks = p->d_ks;
+        w.starts = p->d_starts;
+        w.lpt = p->d_lpt;
+        w.outo = p->d_outo;
+        w.tiles = p->d_tiles;
+        w.seeds = p->d_seeds;
+        w.kept = p->d_kept;
+    } else {
+        e = hipMemcpyAsync(w.offs, p->h_offs.data(), p->h_offs.size() * 4, hipMemcpyHostToDevice, st);
+        if (e == hipSuccess && m)
+            e = hipMemcpyAsync(w.ks, p->h_k.data(), p->h_k.size() * 4, hipMemcpyHostToDevice, st);
+        if (e == hipSuccess && m)
+            e = hipMemcpyAsync(w.starts, p->h_start.data(), p->h_start.size() * 4, hipMemcpyHostToDevice, st);
+        if (e == hipSuccess && p->mwork)
+            e = hipMemcpyAsync(w.lpt, p->h_lpt.data(), p->h_lpt.size() * 4, hipMemcpyHostToDevice, st);
+        if (e == hipSuccess && !p->h_tiles.empty())
+            e = hipMemcpyAsync(w.tiles, p->h_tiles.data(), p->h_tiles.size() * sizeof(SortTile),
+                               hipMemcpyHostToDevice, st);
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(w.outo, p->h_outo.data(), p->h_outo.size() * 8, hipMemcpyHostToDevice, st);
+    }
     const bool use_io = !p->h_io.empty();
     if (e == hipSuccess && use_io)
         e = hipMemcpyAsync(w.io, p->h_io.data(), p->h_io.size() * sizeof(JobIo), hipMemcpyHostToDevice, st);
@@ -1008,11 +1005,14 @@ int batch_preprocess(BatchPlan* p, const float* pts, int32_t* out_order, float* 
 
 }  // namespace
 
-int batch_plan_execute(BatchPlan* p, const float* pts, int32_t* out_order, float* out_radius, void* ws,
-                       size_t ws_bytes, hipStream_t st) {
-    if (!p) return set_error(BS_ERR_INVALID_ARG, "null plan");
-    if (p->mwork == 0) return BS_OK;
-    std::lock_guard<std::mutex> lk(p->mu);
+namespace {
+
+// Everything of one execute, enqueued on st (eagerly, or into a capture):
+// preprocessing, the queue reset, the 1024-thread kernel of the longest
+// chains on the plan's side stream (forked from st and joined back) and the
+// 256-thread kernel of the others.
+int enqueue_execute(BatchPlan* p, const float* pts, int32_t* out_order, float* out_radius, void* ws,
+                    size_t ws_bytes, hipStream_t st) {
     BatchWs w;
     const int rc = batch_preprocess(p, pts, out_order, out_radius, ws, ws_bytes, st, w);
     if (rc != BS_OK) return rc;
@@ -1020,8 +1020,8 @@ int batch_plan_execute(BatchPlan* p, const float* pts, int32_t* out_order, float
     hipLaunchKernelGGL(queue_reset_kernel, dim3(1), dim3(64), 0, st, w.queue);
     hipError_t e = hipGetLastError();
     if (e == hipSuccess && p->nwide > 0) {
-        // the largest objects: 1024-thread workgroups on the side stream,
-        // enqueued first so that they find whole CUs free
+        // the largest objects: 1024-thread workgroups, enqueued first so that
+        // they find whole CUs free
         e = hipEventRecord(p->fork, st);
         if (e == hipSuccess) e = hipStreamWaitEvent(p->side, p->fork, 0);
         if (e == hipSuccess) {
@@ -1031,25 +1031,108 @@ int batch_plan_execute(BatchPlan* p, const float* pts, int32_t* out_order, float
         }
         if (e == hipSuccess) e = hipEventRecord(p->join, p->side);
     }
-    if (e != hipSuccess) return set_error(BS_ERR_HIP, "order launch: %s", hipGetErrorString(e));
-    if (p->mwork > p->nwide) {
-        if (!p->use_graph) {
-            hipLaunchKernelGGL(batch_order_kernel<kBatchBlock>, dim3(p->slots), dim3(kBatchBlock), 0, st, w.desc,
-                               w.lpt + p->nwide, p->mwork - p->nwide, w.queue);
-            e = hipGetLastError();
-            if (e != hipSuccess) return set_error(BS_ERR_HIP, "order launch: %s", hipGetErrorString(e));
-        } else {
-            if (!p->exec || p->graph_ws != ws) {
-                e = capture_order_graph(*p, w);
-                if (e != hipSuccess) return set_error(BS_ERR_HIP, "graph capture: %s", hipGetErrorString(e));
-                p->graph_ws = ws;
-            }
-            e = hipGraphLaunch(p->exec, st);
-            if (e != hipSuccess) return set_error(BS_ERR_HIP, "graph launch: %s", hipGetErrorString(e));
-        }
+    if (e == hipSuccess && p->mwork > p->nwide) {
+        hipLaunchKernelGGL(batch_order_kernel<kBatchBlock>, dim3(p->slots), dim3(kBatchBlock), 0, st, w.desc,
+                           w.lpt + p->nwide, p->mwork - p->nwide, w.queue);
+        e = hipGetLastError();
     }
-    if (p->nwide > 0 && (e = hipStreamWaitEvent(st, p->join, 0)) != hipSuccess)
-        return set_error(BS_ERR_HIP, "join: %s", hipGetErrorString(e));
+    if (e == hipSuccess && p->nwide > 0) e = hipStreamWaitEvent(st, p->join, 0);
+    if (e != hipSuccess) return set_error(BS_ERR_HIP, "order launch: %s", hipGetErrorString(e));
+    return BS_OK;
+}
+
+void drop_graph(BatchPlan* p) {
+    if (p->exec) (void)hipGraphExecDestroy(p->exec);
+    if (p->graph) (void)hipGraphDestroy(p->graph);
+    p->exec = nullptr;
+    p->graph = nullptr;
+    for (const void*& k : p->graph_key) k = nullptr;
+}
+
+}  // namespace
+
+int batch_plan_upload(BatchPlan* p) {
+    if (!p || p->dev) return BS_OK;
+    const size_t m1 = size_t(p->m) + 1;
+    size_t off = 0;
+    auto place = [&](size_t bytes) {
+        const size_t at = off;
+        off += align_up(std::max<size_t>(bytes, 8));
+        return at;
+    };
+    const size_t o_offs = place(m1 * 4), o_ks = place(m1 * 4), o_starts = place(m1 * 4), o_lpt = place(m1 * 4),
+                 o_kept = place(m1 * 4), o_outo = place(m1 * 8), o_seeds = place(m1 * 8),
+                 o_tiles = place(std::max<size_t>(p->h_tiles.size(), 1) * sizeof(SortTile));
+    hipError_t e = hipMalloc(&p->dev, off);
+    if (e != hipSuccess) {
+        p->dev = nullptr;
+        return set_error(BS_ERR_OUT_OF_MEMORY, "plan arrays: %s", hipGetErrorString(e));
+    }
+    char* b = static_cast<char*>(p->dev);
+    p->d_offs = reinterpret_cast<int32_t*>(b + o_offs);
+    p->d_ks = reinterpret_cast<int32_t*>(b + o_ks);
+    p->d_starts = reinterpret_cast<int32_t*>(b + o_starts);
+    p->d_lpt = reinterpret_cast<int32_t*>(b + o_lpt);
+    p->d_kept = reinterpret_cast<int32_t*>(b + o_kept);
+    p->d_outo = reinterpret_cast<int64_t*>(b + o_outo);
+    p->d_seeds = reinterpret_cast<uint64_t*>(b + o_seeds);
+    p->d_tiles = reinterpret_cast<SortTile*>(b + o_tiles);
+    auto put = [&](void* dst, const void* src, size_t bytes) {
+        if (e == hipSuccess && bytes) e = hipMemcpy(dst, src, bytes, hipMemcpyHostToDevice);
+    };
+    put(p->d_offs, p->h_offs.data(), p->h_offs.size() * 4);
+    put(p->d_ks, p->h_k.data(), p->h_k.size() * 4);
+    put(p->d_starts, p->h_start.data(), p->h_start.size() * 4);
+    put(p->d_lpt, p->h_lpt.data(), p->h_lpt.size() * 4);
+    put(p->d_kept, p->h_kept.data(), p->h_kept.size() * 4);
+    put(p->d_outo, p->h_outo.data(), p->h_outo.size() * 8);
+    put(p->d_seeds, p->h_seed.data(), p->h_seed.size() * 8);
+    put(p->d_tiles, p->h_tiles.data(), p->h_tiles.size() * sizeof(SortTile));
+    if (e != hipSuccess) {
+        (void)hipFree(p->dev);
+        p->dev = nullptr;
+        return set_error(BS_ERR_HIP, "plan arrays: %s", hipGetErrorString(e));
+    }
+    return BS_OK;
+}
+
+int batch_plan_execute(BatchPlan* p, const float* pts, int32_t* out_order, float* out_radius, void* ws,
+                       size_t ws_bytes, hipStream_t st) {
+    if (!p) return set_error(BS_ERR_INVALID_ARG, "null plan");
+    if (p->mwork == 0) return BS_OK;
+    std::lock_guard<std::mutex> lk(p->mu);
+    if (!p->use_graph || !p->dev) return enqueue_execute(p, pts, out_order, out_radius, ws, ws_bytes, st);
+    // host checks first: nothing may fail inside the capture
+    if (!pts || !out_order) return set_error(BS_ERR_INVALID_ARG, "null points or output");
+    if (!ws || ws_bytes < p->ws_bytes)
+        return set_error(BS_ERR_INVALID_ARG, "workspace %zu bytes < %zu needed", ws_bytes, p->ws_bytes);
+    if (reinterpret_cast<uintptr_t>(ws) % kAlign)
+        return set_error(BS_ERR_INVALID_ARG, "workspace not %zu-byte aligned", kAlign);
+    const void* key[4] = {ws, pts, out_order, out_radius};
+    if (!p->exec || !std::equal(key, key + 4, p->graph_key)) {
+        // one graph for the whole execute: a capture stream forks the side
+        // stream for the wide kernel and joins it back
+        drop_graph(p);
+        hipStream_t cap = nullptr;
+        hipError_t e = hipStreamCreateWithFlags(&cap, hipStreamNonBlocking);
+        if (e != hipSuccess) return set_error(BS_ERR_HIP, "graph capture: %s", hipGetErrorString(e));
+        e = hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal);
+        int rc = BS_OK;
+        if (e == hipSuccess) {
+            rc = enqueue_execute(p, pts, out_order, out_radius, ws, ws_bytes, cap);
+            const hipError_t e2 = hipStreamEndCapture(cap, &p->graph);
+            if (e2 != hipSuccess) e = e2;
+        }
+        if (e == hipSuccess && rc == BS_OK) e = hipGraphInstantiate(&p->exec, p->graph, nullptr, nullptr, 0);
+        (void)hipStreamDestroy(cap);
+        if (rc != BS_OK || e != hipSuccess) {
+            drop_graph(p);
+            return rc != BS_OK ? rc : set_error(BS_ERR_HIP, "graph capture: %s", hipGetErrorString(e));
+        }
+        std::copy(key, key + 4, p->graph_key);
+    }
+    const hipError_t e = hipGraphLaunch(p->exec, st);
+    if (e != hipSuccess) return set_error(BS_ERR_HIP, "graph launch: %s", hipGetErrorString(e));
     return BS_OK;
 }
 
@@ -1071,9 +1154,11 @@ int batch_plan_execute_sample(BatchPlan* p, int S, int K, float vicinity, const 
     const int rc = batch_preprocess(p, pts, out_order, out_radius, ws, ws_bytes, st, w);
     if (rc != BS_OK) return rc;
     const int m = p->m, N = p->N, tb = 256;
-    e = hipMemcpyAsync(w.seeds, p->h_seed.data(), size_t(m) * 8, hipMemcpyHostToDevice, st);
-    if (e == hipSuccess) e = hipMemcpyAsync(w.kept, p->h_kept.data(), size_t(m) * 4, hipMemcpyHostToDevice, st);
-    if (e != hipSuccess) return set_error(BS_ERR_HIP, "sampler upload: %s", hipGetErrorString(e));
+    if (!p->dev) {  // otherwise w.seeds and w.kept are the plan's device copies
+        e = hipMemcpyAsync(w.seeds, p->h_seed.data(), size_t(m) * 8, hipMemcpyHostToDevice, st);
+        if (e == hipSuccess) e = hipMemcpyAsync(w.kept, p->h_kept.data(), size_t(m) * 4, hipMemcpyHostToDevice, st);
+        if (e != hipSuccess) return set_error(BS_ERR_HIP, "sampler upload: %s", hipGetErrorString(e));
+    }
     hipLaunchKernelGGL(bpos_kernel, dim3((N + tb - 1) / tb), dim3(tb), 0, st, w.keys_s, w.ids, N, w.offs, w.pos_of);
     SampleParams prm{S, K, vicinity, 0};
     hipLaunchKernelGGL(bsdesc_kernel, dim3((m + tb - 1) / tb), dim3(tb), 0, st, m, w.hd, w.offs, w.seeds, w.kept,

@@ -89,6 +89,9 @@ struct BatchPlan;
 int batch_plan_create(const int64_t* h_offsets, const int64_t* h_k, const uint64_t* h_seed, int32_t m,
                       float target, int wide, int wide_groups, BatchPlan** out);
 void batch_plan_free(BatchPlan* p);
+// Device copies of the plan's arrays (synchronous; batch and hierarchy
+// plans: their executes then upload nothing and run as one captured graph).
+int batch_plan_upload(BatchPlan* p);
 size_t batch_workspace_bytes(const BatchPlan* p);
 int64_t batch_total_k(const BatchPlan* p);
 // Each object's candidates in Morton order (indices within the object), at

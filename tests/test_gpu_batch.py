@@ -71,12 +71,33 @@ def test_batch_replay_and_nonfinite(hip):
         objs[3][0, 1] = np.nan
     plan = hip.BatchPlan(offs, ks, seeds)
     allp = torch.from_numpy(np.concatenate(objs)).cuda()
-    first = [x.cpu().numpy().copy() for x in plan.execute(allp)]
+    # fixed outputs and workspace: the first execute captures the graph of
+    # the whole execute, the others replay it (with the program's own work
+    # and synchronisations between them)
+    oo = torch.empty(plan.total_k, dtype=torch.int32, device="cuda")
+    rr = torch.empty(plan.total_k, dtype=torch.float32, device="cuda")
+    first = [x.cpu().numpy().copy() for x in plan.execute(allp, oo, rr)]
+    junk = torch.zeros(1 << 20, device="cuda")
     for rep in range(3):
-        o, r = plan.execute(allp)
+        oo.fill_(-7)
+        junk.add_(1.0)
+        torch.cuda.synchronize()
+        o, r = plan.execute(allp, oo, rr)
         torch.cuda.synchronize()
         assert np.array_equal(o.cpu().numpy(), first[0]), "replay %d order" % rep
         assert pins.same_f32(r.cpu().numpy(), first[1]), "replay %d radius" % rep
+    # a replay reads the points' current contents: swapping two objects'
+    # coordinates within the buffer changes only those objects' outputs
+    saved = allp.clone()
+    a0, a1 = int(offs[0]), int(offs[1])
+    allp[a0:a1] = allp[a0:a1].flip(0)
+    o2, _ = plan.execute(allp, oo, rr)
+    torch.cuda.synchronize()
+    P0 = allp[a0:a1].cpu().numpy()
+    if ks[0] > 0:
+        eo0, _ = oracle.greedy32_grid(P0, ks[0], oracle.start_index(seeds[0], P0.shape[0]))
+        assert np.array_equal(o2.cpu().numpy()[plan.out_offsets[0]:plan.out_offsets[1]], eo0)
+    allp.copy_(saved)
     for j, P in enumerate(objs):
         a, b = plan.out_offsets[j], plan.out_offsets[j + 1]
         if ks[j] == 0:
@@ -150,8 +171,11 @@ def test_batch_wide_workgroups(hip, wide):
     offs = np.concatenate([[0], np.cumsum([o.shape[0] for o in objs])]).astype(np.int64)
     plan = hip.BatchPlan(offs, ks, seeds, tune=hip.tuning(batch_wide=wide))
     allp = torch.from_numpy(np.concatenate(objs)).cuda()
-    for rep in range(2):
-        o, r = plan.execute(allp)
+    oo = torch.empty(plan.total_k, dtype=torch.int32, device="cuda")
+    rr = torch.empty(plan.total_k, dtype=torch.float32, device="cuda")
+    for rep in range(2):  # capture, then a replay of the forked graph
+        oo.fill_(-7)
+        o, r = plan.execute(allp, oo, rr)
         torch.cuda.synchronize()
         o = o.cpu().numpy()
         r = r.cpu().numpy()
