@@ -46,8 +46,13 @@ namespace bs {
 namespace {
 
 constexpr int kMpEntries = 3;                 // entries a workgroup offers per step
-constexpr int kMpWords = 6 * kMpEntries + 1;  // per entry: key hi, lo, x, y, z, pos; then R
-constexpr int kMpRecStride = 32;              // words per exchange record
+// An exchange record: three packed words per entry, then R, each word with a
+// 2-bit step tag above 62 payload bits; one 128-byte line per record.
+constexpr int kMpEntryWords = 3;
+constexpr int kMpWords = kMpEntryWords * kMpEntries + 1;
+constexpr int kMpRecStride = 16;  // words per exchange record
+constexpr uint64_t kMpPayload = (uint64_t(1) << 62) - 1u;
+constexpr uint32_t kMpMaxPos = 1u << 22;  // sorted positions fit 22 bits (n <= 2^22)
 constexpr int kMpMaxPicks = 128;  // two passes of one lane per pick in the reach test
 constexpr int kMpMaxGroups = 256;
 
@@ -133,14 +138,37 @@ __device__ __forceinline__ int lanes_below(uint64_t m) {
     return int(__builtin_amdgcn_mbcnt_hi(uint32_t(m >> 32), __builtin_amdgcn_mbcnt_lo(uint32_t(m), 0u)));
 }
 
-// Entry e of the records (workgroup e / kMpEntries, slot e % kMpEntries):
-// its key, and its x, y, z, sorted position.
-__device__ __forceinline__ const uint32_t* rec_entry(const uint32_t* rw, int e) {
-    return rw + (e / kMpEntries) * kMpWords + 6 * (e % kMpEntries);
+// Entry e of the records (workgroup e / kMpEntries, slot e % kMpEntries),
+// three packed words (payload bits only):
+//   w0: value bits 0..30 of the key (m >= 0: the sign bit is 0), then the
+//       31 bits of its complemented index;
+//   w1: x, the sorted position (22 bits) from bit 32, z bits 0..7 from bit 54;
+//   w2: y, z bits 8..31 from bit 32.
+// Word kMpWords - 1 of a workgroup's record is R.
+__device__ __forceinline__ const uint64_t* rec_entry(const uint64_t* rw, int e) {
+    return rw + (e / kMpEntries) * kMpWords + kMpEntryWords * (e % kMpEntries);
 }
-__device__ __forceinline__ uint64_t rec_key(const uint32_t* rw, int e) {
-    const uint32_t* p = rec_entry(rw, e);
-    return (uint64_t(p[0]) << 32) | p[1];
+__device__ __forceinline__ uint64_t rec_key(const uint64_t* rw, int e) {
+    const uint64_t w0 = rec_entry(rw, e)[0];
+    return ((w0 & 0x7FFFFFFFull) << 32) | ((w0 >> 31) & 0x7FFFFFFFull);
+}
+// x, y, z and the sorted position (as the bits of w) of entry e.
+__device__ __forceinline__ float4 rec_coords(const uint64_t* rw, int e) {
+    const uint64_t* p = rec_entry(rw, e);
+    const uint64_t w1 = p[1], w2 = p[2];
+    const uint32_t z = uint32_t((w1 >> 54) & 0xFFu) | (uint32_t(w2 >> 32) << 8);
+    return make_float4(__uint_as_float(uint32_t(w1)), __uint_as_float(uint32_t(w2)), __uint_as_float(z),
+                       __int_as_float(int((w1 >> 32) & (kMpMaxPos - 1u))));
+}
+__device__ __forceinline__ uint32_t rec_bound(const uint64_t* rw, int g) {
+    return uint32_t(rw[g * kMpWords + kMpEntryWords * kMpEntries]);
+}
+// Word f of an entry from its key, coordinates and position (32-bit fields).
+__device__ __forceinline__ uint64_t pack_entry_word(int f, uint32_t key_hi, uint32_t key_lo, uint32_t x, uint32_t y,
+                                                    uint32_t z, uint32_t pos) {
+    if (f == 0) return uint64_t(key_hi & 0x7FFFFFFFu) | (uint64_t(key_lo & 0x7FFFFFFFu) << 31);
+    if (f == 1) return uint64_t(x) | (uint64_t(pos & (kMpMaxPos - 1u)) << 32) | (uint64_t(z & 0xFFu) << 54);
+    return uint64_t(y) | (uint64_t(z >> 8) << 32);
 }
 
 __device__ __forceinline__ void st_rec(uint64_t* p, uint64_t v) {
@@ -216,7 +244,7 @@ __global__ void __launch_bounds__(BLOCK)
     __shared__ uint32_t s_c3[NW];                  // and the bound after them (value bits)
     __shared__ uint32_t s_ent[6 * kMpEntries];     // the record's entry words, staged by rank
     __shared__ float4 s_wc[NW][2];                 // x, y, z, sorted position of each chain key
-    __shared__ uint32_t s_rw[kMpMaxGroups * kMpWords];  // every workgroup's record (low words)
+    __shared__ uint64_t s_rw[kMpMaxGroups * kMpWords];  // every workgroup's record (payload bits)
     __shared__ __align__(16) uint64_t s_mk[kMpEntries * kMpMaxGroups + 2];  // members: keys
     __shared__ int s_mi[kMpEntries * kMpMaxGroups];  // members: entry index
     __shared__ float4 s_pk[kMpMaxPicks];           // picks by rank: x, y, z, m
@@ -554,7 +582,7 @@ __global__ void __launch_bounds__(BLOCK)
         // 2. wavefront 0: the workgroup's three best chain keys become its
         // entries, with their data from the wavefronts that hold them, and R
         // bounds every value it does not offer; its record is one word a lane
-        const uint64_t tag = uint64_t(step) << 32;
+        const uint64_t tag = uint64_t(step & 3u) << 62;
         if (wave == 0) {
             // chain key i of wavefront w on lane 2 w + i, ranked among all
             // listed keys by counting the larger ones (keys are unique, 0 =
@@ -590,10 +618,14 @@ __global__ void __launch_bounds__(BLOCK)
                 e[5] = __float_as_uint(c.w);
             }
             __builtin_amdgcn_wave_barrier();  // LDS in program order within the wavefront
-            // lane 6 e + f carries word f of entry e (zero past the listed
-            // keys); lane 18 carries R
-            uint32_t wv = rg;
-            if (lane < 6 * kMpEntries) wv = lane / 6 < nz ? s_ent[lane] : 0u;
+            // lane 3 e + f carries packed word f of entry e (zero past the
+            // listed keys); lane 9 carries R
+            uint64_t wv = rg;
+            if (lane < kMpEntryWords * kMpEntries) {
+                const int e = lane / kMpEntryWords, f = lane - e * kMpEntryWords;
+                const uint32_t* q = s_ent + 6 * e;
+                wv = e < nz ? pack_entry_word(f, q[0], q[1], q[2], q[3], q[4], q[5]) : 0ull;
+            }
             if (lane < kMpWords) st_rec(slots + (size_t(buf) * G + g) * kMpRecStride + lane, tag | wv);
         }
         // 3. every record, a few words a thread, into s_rw (kMpWords per
@@ -621,7 +653,7 @@ __global__ void __launch_bounds__(BLOCK)
                 for (int c = 0; c < RW; ++c) {
                     const int i = tid + c * BLOCK;
                     if (i < nw) {
-                        if (uint32_t(v[c] >> 32) == step) s_rw[i] = uint32_t(v[c]);
+                        if ((v[c] >> 62) == (step & 3u)) s_rw[i] = v[c] & kMpPayload;
                         else pending = true;
                     }
                 }
@@ -658,7 +690,7 @@ __global__ void __launch_bounds__(BLOCK)
             for (int c = 0; c < kMpMaxGroups / 64; ++c) {
                 const int w = c * 64 + lane;
                 k1[c] = w < G ? rec_key(s_rw, kMpEntries * w) : 0ull;
-                rr[c] = w < G ? s_rw[w * kMpWords + 6 * kMpEntries] : 0u;
+                rr[c] = w < G ? rec_bound(s_rw, w) : 0u;
             }
             uint64_t top = 0;
             uint32_t topr = 0;
@@ -756,9 +788,7 @@ __global__ void __launch_bounds__(BLOCK)
                 for (int r = 1; r < MR; ++r) rank = part == r ? rk[r] : rank;
                 const int mi = m0 + part;
                 if (part < MR && mi < na && rank < cap) {
-                    const uint32_t* x = rec_entry(s_rw, s_mi[mi]) + 2;
-                    const float4 c = make_float4(__uint_as_float(x[0]), __uint_as_float(x[1]),
-                                                 __uint_as_float(x[2]), __uint_as_float(x[3]));
+                    const float4 c = rec_coords(s_rw, s_mi[mi]);
                     s_pk[rank] = make_float4(c.x, c.y, c.z, key_value(s_mk[mi]));
                     s_pid[rank] = key_id(s_mk[mi]);
                     s_ppos[rank] = __float_as_int(c.w);
@@ -835,6 +865,7 @@ hipError_t launch_scan_several(const ScanShape& s, const float* pts, int n, int 
     for (const MpEntry& e : kMpTable)
         if (e.block == s.block && e.per_thread == s.per_thread) fn = e.fn;
     if (!fn || !scan_several_supported(s)) return hipErrorInvalidValue;
+    if (uint32_t(n) > kMpMaxPos) return hipErrorInvalidValue;  // positions are packed in 22 bits
     // both record buffers must fit the exchange area the workspace reserves
     if (size_t(2) * size_t(s.groups) * kMpRecStride * sizeof(uint64_t) > scan_slot_bytes(kMaxCoopGroups))
         return hipErrorInvalidValue;
