@@ -83,7 +83,8 @@ const char* bs_version(void);
 typedef enum {
     BS_KERNEL_AUTO = 0,  /* library picks (autotuned table; without one: up to 4,096
                             candidates BS_KERNEL_WG, from 4,097 (two workgroups) to
-                            4,194,304 BS_KERNEL_COOP with 128 picks per step, above
+                            4,194,304 BS_KERNEL_COOP with 256 picks per step (128 below
+                            64 workgroups), above
                             that BS_KERNEL_GRID) */
     BS_KERNEL_WG = 1,    /* one workgroup, candidates resident in registers */
     BS_KERNEL_COOP = 2,  /* cooperative workgroups, resident, full scan (several picks
@@ -102,7 +103,7 @@ typedef struct {
                               result; see bs_order_ex).  Cooperative full scan
                               (BS_KERNEL_COOP; 1024-thread workgroups with 1, 2, 4, 8, 12 or
                               16 per thread, or 512-thread with 24 or 32; 2..256
-                              workgroups): 2..128 = several exact picks per step over
+                              workgroups): 2..256 = several exact picks per step over
                               the candidates in Morton order, every workgroup a bucket
                               offering its three best keys */
     int32_t lead_picks;    /* grid kernel with several picks per round: the first picks

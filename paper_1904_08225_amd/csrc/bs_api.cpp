@@ -35,7 +35,7 @@ int device_cus() {
 }
 
 constexpr int kMaxGridPicks = 32;     // picks per round of the grid kernel
-constexpr int kMaxScanPicks = 128;    // picks per step of the cooperative full scan
+constexpr int kMaxScanPicks = 256;    // picks per step of the cooperative full scan
 constexpr int kDefaultGridPicks = 16;
 
 bool tuning_clean(const bs_tuning* t) {
@@ -58,7 +58,7 @@ constexpr int64_t kAutoLeadDiv = 1024;
 // Automatic several-picks cooperative scan: at most this many picks per step,
 // and only above this many candidates (below, the one resident workgroup is
 // as fast: 4,096 in 2.97 ms against 3.12 ms on four workgroups).
-constexpr int kAutoScanPicks = 128;
+constexpr int kAutoScanPicks = 256;
 constexpr int64_t kAutoSeveralMin = 4096;
 
 struct Plan {
@@ -112,7 +112,9 @@ int plan_single(int64_t n, int64_t k, const bs_tuning* t, Plan* p) {
     const int wb = t ? t->block : 0, wp = t ? t->per_thread : 0, wg = t ? t->groups : 0;
     if (want == BS_KERNEL_AUTO && n > kAutoSeveralMin && choose_several_shape(n, cus, wb, wp, wg, &p->shape)) {
         p->kernel = BS_KERNEL_COOP;
-        p->scan_picks = (t && t->picks > 1) ? t->picks : kAutoScanPicks;
+        // 256 picks per step where the entries can exceed 128 (three a
+        // workgroup); the 128-pick kernel's step is cheaper otherwise
+        p->scan_picks = (t && t->picks > 1) ? t->picks : (p->shape.groups >= 64 ? kAutoScanPicks : 128);
         return BS_OK;
     }
     if (want == BS_KERNEL_GRID || (want == BS_KERNEL_AUTO && n > kAutoResidentMax)) {

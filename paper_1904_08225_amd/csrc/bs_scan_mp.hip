@@ -53,7 +53,10 @@ constexpr int kMpWords = kMpEntryWords * kMpEntries + 1;
 constexpr int kMpRecStride = 16;  // words per exchange record
 constexpr uint64_t kMpPayload = (uint64_t(1) << 62) - 1u;
 constexpr uint32_t kMpMaxPos = 1u << 22;  // sorted positions fit 22 bits (n <= 2^22)
-constexpr int kMpMaxPicks = 128;  // two passes of one lane per pick in the reach test
+// Most picks per step: 256, or 128 for a kernel with fewer passes of one
+// lane per pick in the reach test and wider conflict columns (a step's fixed
+// cost is lower; with few workgroups, and so few entries, 128 never binds).
+constexpr int kMpMaxPicks = 256;
 constexpr int kMpMaxGroups = 256;
 
 // A workgroup barrier ordering LDS only: within a step the workgroup's
@@ -231,7 +234,7 @@ __device__ __forceinline__ BestKey wave_best(uint32_t vm, int jm, bool tie, cons
 
 // Points: lane l of wavefront w in workgroup g holds sorted positions
 // g*BLOCK*P + w*64*P + j*64 + l, j < P.
-template <int BLOCK, int P>
+template <int BLOCK, int P, int MAXPICKS>
 __global__ void __launch_bounds__(BLOCK)
     scan_mp_kernel(const float4* __restrict__ xyzm, const uint32_t* __restrict__ ids,
                    const uint32_t* __restrict__ codes, const int32_t* __restrict__ start_pos, int n, int k, int start, int32_t* __restrict__ order,
@@ -239,7 +242,9 @@ __global__ void __launch_bounds__(BLOCK)
                    uint64_t* __restrict__ slots, uint64_t* __restrict__ ticks, int max_picks,
                    uint32_t spin_limit) {
     constexpr int NW = BLOCK / 64;
-    static_assert(kMpMaxPicks <= 128, "two passes of one lane per pick");
+    constexpr int kMpPickWords = MAXPICKS / 64;  // reach-test passes of 64 picks
+    static_assert(MAXPICKS % 64 == 0 && MAXPICKS <= kMpMaxPicks && MAXPICKS <= BLOCK,
+                  "passes of 64 picks; one emitting thread a pick");
     __shared__ __align__(16) uint64_t s_w[NW][2];  // per wavefront: its chain's two keys (cached)
     __shared__ uint32_t s_c3[NW];                  // and the bound after them (value bits)
     __shared__ uint32_t s_ent[6 * kMpEntries];     // the record's entry words, staged by rank
@@ -247,9 +252,9 @@ __global__ void __launch_bounds__(BLOCK)
     __shared__ uint64_t s_rw[kMpMaxGroups * kMpWords];  // every workgroup's record (payload bits)
     __shared__ __align__(16) uint64_t s_mk[kMpEntries * kMpMaxGroups + 2];  // members: keys
     __shared__ int s_mi[kMpEntries * kMpMaxGroups];  // members: entry index
-    __shared__ float4 s_pk[kMpMaxPicks];           // picks by rank: x, y, z, m
-    __shared__ uint32_t s_pid[kMpMaxPicks];        // original index
-    __shared__ int s_ppos[kMpMaxPicks];            // sorted position
+    __shared__ float4 s_pk[MAXPICKS];           // picks by rank: x, y, z, m
+    __shared__ uint32_t s_pid[MAXPICKS];        // original index
+    __shared__ int s_ppos[MAXPICKS];            // sorted position
     __shared__ uint32_t s_id[P * BLOCK];           // original index of each held candidate
     __shared__ float4 s_slo[NW][P], s_shi[NW][P];  // box of each slab of 64 (x, y, z; w unused)
     __shared__ float4 s_gb[NW][4];                 // boxes of the wavefront's two groups (lo, hi each)
@@ -268,7 +273,7 @@ __global__ void __launch_bounds__(BLOCK)
         }
         return;
     }
-    const int cap_picks = max_picks < kMpMaxPicks ? max_picks : kMpMaxPicks;
+    const int cap_picks = max_picks < MAXPICKS ? max_picks : MAXPICKS;
     const int wbase = g * BLOCK * P + wave * 64 * P;
 
     float px[P], py[P], pz[P], m[P];
@@ -403,9 +408,10 @@ __global__ void __launch_bounds__(BLOCK)
         const int buf = step & 1;
         // 1. the previous step's picks: the ones whose ball reaches a group's
         // box lower m in that group's slabs of 64; the ones it owns become chosen
-        uint64_t ra[2], rb[2], om[2];  // picks 0-63 and 64-127
+        uint64_t ra[kMpPickWords], rb[kMpPickWords], om[kMpPickWords];  // picks 64 h .. 64 h + 63
+        uint64_t any_reach = 0ull, any_own = 0ull;
 #pragma unroll
-        for (int h = 0; h < 2; ++h) {
+        for (int h = 0; h < kMpPickWords; ++h) {
             const int qi = h * 64 + lane;
             bool reach_a = false, reach_b = false, own = false;
             if (qi < K) {
@@ -419,8 +425,10 @@ __global__ void __launch_bounds__(BLOCK)
             ra[h] = __ballot(reach_a);
             rb[h] = __ballot(reach_b);
             om[h] = __ballot(own);
+            any_reach |= ra[h] | rb[h];
+            any_own |= om[h];
         }
-        if ((ra[0] | ra[1] | rb[0] | rb[1] | om[0] | om[1]) != 0ull || step == 1) {  // step 1 fills every cache
+        if ((any_reach | any_own) != 0ull || step == 1) {  // step 1 fills every cache
             // slots of this lane holding one of the wavefront's two chain
             // keys (their sorted positions are cached with them): only a
             // lowered m there can change the chain; any other m only drops,
@@ -434,7 +442,7 @@ __global__ void __launch_bounds__(BLOCK)
             }
             uint32_t lowm = 0u;  // slots of this lane whose m dropped
 #pragma unroll
-            for (int h = 0; h < 2; ++h)
+            for (int h = 0; h < kMpPickWords; ++h)
                 for (uint64_t mm = ra[h] | rb[h]; mm; mm &= mm - 1) {
                     const int bq = __builtin_ctzll(mm);
                     const float4 q = s_pk[h * 64 + bq];
@@ -458,7 +466,7 @@ __global__ void __launch_bounds__(BLOCK)
                     }
                 }
 #pragma unroll
-            for (int h = 0; h < 2; ++h)
+            for (int h = 0; h < kMpPickWords; ++h)
                 for (uint64_t mm = om[h]; mm; mm &= mm - 1) {
                     const int off = s_ppos[h * 64 + __builtin_ctzll(mm)] - wbase;
 #pragma unroll
@@ -469,7 +477,7 @@ __global__ void __launch_bounds__(BLOCK)
             // dropped or a pick (always one of them) was taken here: all of
             // it is rebuilt when a pick was taken here or c1's m dropped
             // (step 1 fills every cache), from c2 on when only c2's m did
-            const bool redo1 = (om[0] | om[1]) != 0ull || step == 1 || __ballot((lowm & topm[0]) != 0u) != 0ull;
+            const bool redo1 = any_own != 0ull || step == 1 || __ballot((lowm & topm[0]) != 0u) != 0ull;
             if (redo1 || __ballot((lowm & topm[1]) != 0u) != 0ull) {
                 const uint32_t* ids = s_id + (tid - lane);  // this wavefront's column of s_id
                 uint64_t c1;
@@ -667,7 +675,7 @@ __global__ void __launch_bounds__(BLOCK)
             if (aborted && lane == 0) s_abort = 1;
         }
         if (tid == 0) {
-            s_kfail = kMpMaxPicks;
+            s_kfail = MAXPICKS;
             s_na = 0;
         }
         lds_barrier();
@@ -802,9 +810,9 @@ __global__ void __launch_bounds__(BLOCK)
         // or more consecutive columns give their lowest lowered j by ballot,
         // and that goes to LDS in one atomic
         {
-            constexpr int TPC = BLOCK / kMpMaxPicks;  // threads per column
+            constexpr int TPC = BLOCK / MAXPICKS;  // threads per column
             static_assert(TPC >= 1 && (TPC & (TPC - 1)) == 0 && 64 % TPC == 0, "conflict tiling");
-            const int j = tid / TPC, part = tid % TPC;  // j < kMpMaxPicks
+            const int j = tid / TPC, part = tid % TPC;  // j < MAXPICKS
             bool low = false;
             if (j < nr) {
                 const float4 cj = s_pk[j];
@@ -835,15 +843,15 @@ using ScanMpFn = void (*)(const float4*, const uint32_t*, const uint32_t*, const
 struct MpEntry {
     int block;
     int per_thread;
-    ScanMpFn fn;
+    ScanMpFn fn128, fn256;  // at most 128 / 256 picks per step
 };
 
+#define BS_MP_ENTRY(B, P) {B, P, scan_mp_kernel<B, P, 128>, scan_mp_kernel<B, P, 256>}
 const MpEntry kMpTable[] = {
-    {1024, 1, scan_mp_kernel<1024, 1>},   {1024, 2, scan_mp_kernel<1024, 2>},
-    {1024, 4, scan_mp_kernel<1024, 4>},   {1024, 8, scan_mp_kernel<1024, 8>},
-    {1024, 12, scan_mp_kernel<1024, 12>}, {1024, 16, scan_mp_kernel<1024, 16>},
-    {512, 24, scan_mp_kernel<512, 24>},   {512, 32, scan_mp_kernel<512, 32>},
+    BS_MP_ENTRY(1024, 1),  BS_MP_ENTRY(1024, 2),  BS_MP_ENTRY(1024, 4), BS_MP_ENTRY(1024, 8),
+    BS_MP_ENTRY(1024, 12), BS_MP_ENTRY(1024, 16), BS_MP_ENTRY(512, 24), BS_MP_ENTRY(512, 32),
 };
+#undef BS_MP_ENTRY
 
 __global__ void clear_mp_slots_kernel(uint64_t* slots, int nwords) {
     for (int i = threadIdx.x; i < nwords; i += blockDim.x) st_rec(slots + i, 0);
@@ -863,7 +871,7 @@ hipError_t launch_scan_several(const ScanShape& s, const float* pts, int n, int 
                                const LaunchOpts* ev) {
     ScanMpFn fn = nullptr;
     for (const MpEntry& e : kMpTable)
-        if (e.block == s.block && e.per_thread == s.per_thread) fn = e.fn;
+        if (e.block == s.block && e.per_thread == s.per_thread) fn = picks > 128 ? e.fn256 : e.fn128;
     if (!fn || !scan_several_supported(s)) return hipErrorInvalidValue;
     if (uint32_t(n) > kMpMaxPos) return hipErrorInvalidValue;  // positions are packed in 22 bits
     // both record buffers must fit the exchange area the workspace reserves

@@ -62,7 +62,7 @@ std::vector<bs_tuning> single_candidates(int64_t n) {
         // workgroups offer more entries per step), the most picks per step
         // (a lower cap only binds late in the ordering, beyond the prefixes
         // timed here, and is never faster there)
-        for (int pt : {1, 2, 4, 8, 12, 16}) c.push_back(make_tuning(BS_KERNEL_COOP, 1024, pt, 0.f, 128));
+        for (int pt : {1, 2, 4, 8, 12, 16}) c.push_back(make_tuning(BS_KERNEL_COOP, 1024, pt, 0.f, 256));
     }
     for (int block : {512, 1024})
         for (float cp : {8.f, 16.f}) c.push_back(make_tuning(BS_KERNEL_GRID, block, 0, cp, 16));
@@ -202,7 +202,7 @@ int forced_tuning(bs_tuning* out) {
     const std::string v = env;
     if (v == "wg") *out = make_tuning(BS_KERNEL_WG, 0, 0, 0.f, 0);
     else if (v == "scan") *out = make_tuning(BS_KERNEL_COOP, 0, 0, 0.f, 1);
-    else if (v == "several") *out = make_tuning(BS_KERNEL_COOP, 1024, 0, 0.f, 128);
+    else if (v == "several") *out = make_tuning(BS_KERNEL_COOP, 1024, 0, 0.f, 256);
     else if (v == "grid") *out = make_tuning(BS_KERNEL_GRID, 0, 0, 0.f, 0);
     else return -1;
     return 1;

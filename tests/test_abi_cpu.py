@@ -121,15 +121,15 @@ def test_lead_picks_validation(lib):
 
 def test_plan_describe(lib):
     """Automatic choices resolved: up to 256 workgroups of 1024 threads, the
-    several-picks cooperative scan with 128 picks per step on the most
+    several-picks cooperative scan with 256 picks per step on the most
     workgroups that fit (fewest candidates per thread); above 4,194,304 the
     grid kernel with 16 picks per round (asked for at 4,194,304: with a
     leading scan of n / 1024 picks); up to 4,096 the resident workgroup."""
     lib.bs_autotune_clear()
     p = bs.plan_describe(4194304, 262144)
-    assert (p.kernel, p.block, p.per_thread, p.groups, p.picks) == (bs.KERNEL_COOP, 1024, 16, 256, 128)
+    assert (p.kernel, p.block, p.per_thread, p.groups, p.picks) == (bs.KERNEL_COOP, 1024, 16, 256, 256)
     p = bs.plan_describe(2097152, 1000)
-    assert (p.kernel, p.per_thread, p.groups, p.picks) == (bs.KERNEL_COOP, 8, 256, 128)
+    assert (p.kernel, p.per_thread, p.groups, p.picks) == (bs.KERNEL_COOP, 8, 256, 256)
     p = bs.plan_describe(100000, 1000)
     assert (p.kernel, p.per_thread, p.groups) == (bs.KERNEL_COOP, 1, 98)
     p = bs.plan_describe(500000, 1000)
@@ -146,7 +146,7 @@ def test_plan_describe(lib):
     p = bs.plan_describe(4194304, 2000, bs.tuning(kernel=3, picks=16))
     assert p.lead_picks == 2000  # capped at k
     p = bs.plan_describe(10000, 100)  # from two workgroups on, the several-picks scan
-    assert (p.kernel, p.per_thread, p.groups, p.picks) == (bs.KERNEL_COOP, 1, 10, 128)
+    assert (p.kernel, p.per_thread, p.groups, p.picks) == (bs.KERNEL_COOP, 1, 10, 128)  # few workgroups: 128
     p = bs.plan_describe(4096, 100)
     assert p.kernel == bs.KERNEL_WG and p.groups == 1
     # several picks per step need two workgroups at least
@@ -162,7 +162,7 @@ def test_forced_kernel_override(lib, monkeypatch):
     tuning; an explicit tuning still wins, and an unknown value is an error."""
     lib.bs_autotune_clear()
     for name, kernel, picks in (("wg", bs.KERNEL_WG, None), ("scan", bs.KERNEL_COOP, 1),
-                                ("several", bs.KERNEL_COOP, 128), ("grid", bs.KERNEL_GRID, 16)):
+                                ("several", bs.KERNEL_COOP, 256), ("grid", bs.KERNEL_GRID, 16)):
         monkeypatch.setenv("BS_FORCE_KERNEL", name)
         n = 4000 if name == "wg" else 100000
         p = bs.plan_describe(n, 1000)

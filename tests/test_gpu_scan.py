@@ -156,7 +156,7 @@ def test_cooperative_cad_part_full_size(hip):
     assert_parity(o, r, eo, er, "cad_part full")
 
 
-@pytest.mark.parametrize("picks", [2, 8, 32, 64, 128])
+@pytest.mark.parametrize("picks", [2, 8, 32, 64, 128, 256])
 def test_cooperative_several_picks(hip, picks):
     """Several exact picks per step of the cooperative full scan (every
     workgroup a bucket with three entries and a bound on the rest): the
@@ -179,12 +179,12 @@ def test_cooperative_several_picks(hip, picks):
 
 
 def test_cooperative_several_picks_full_size(hip):
-    """4,194,304 candidates to k = 262,144, at most 32 and 128 picks per step."""
+    """4,194,304 candidates to k = 262,144, at most 32, 128 and 256 picks per step."""
     n, k = 4194304, 262144
     P = synth.cad_part(n, seed=2).points.numpy()
     st = oracle.start_index(2, n)
     eo, er = oracle.greedy32_grid(P, k, st)
-    for picks in (32, 128):
+    for picks in (32, 128, 256):
         o, r = run(hip, P, k, seed=2,
                    tune=hip.tuning(kernel=hip.KERNEL_COOP, block=1024, per_thread=16, picks=picks))
         assert_parity(o, r, eo, er, "cooperative several picks, full size, picks=%d" % picks)
@@ -198,7 +198,8 @@ def test_several_picks_automatic_plan(hip, n, k):
     (every candidate chosen, the last steps with fewer live candidates than
     picks), and ragged sizes spanning many workgroups."""
     plan = hip.plan_describe(n, k)
-    assert plan.kernel == hip.KERNEL_COOP and plan.picks == 128 and plan.groups >= 2
+    assert plan.kernel == hip.KERNEL_COOP and plan.groups >= 2
+    assert plan.picks == (256 if plan.groups >= 64 else 128)
     P = synth.cad_part(n, seed=13).points.numpy()
     st = oracle.start_index(4, n)
     eo, er = oracle.greedy32_grid(P, k, st)
