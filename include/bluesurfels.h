@@ -105,7 +105,8 @@ typedef struct {
                               16 per thread, or 512-thread with 24 or 32; 2..256
                               workgroups): 2..256 = several exact picks per step over
                               the candidates in Morton order, every workgroup a bucket
-                              offering its three best keys */
+                              offering its four best keys, five in the 128-pick
+                              kernel */
     int32_t lead_picks;    /* grid kernel with several picks per round: the first picks
                               come from the cooperative full scan over all CUs, which
                               then hands every candidate's distance to the grid kernel

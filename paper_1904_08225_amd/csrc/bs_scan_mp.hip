@@ -14,7 +14,7 @@
 // wavefront keeps a chain: c1, its best key; c2, its best key once c1's ball
 // has lowered the others (the value in c2's key includes that update); and
 // the bound of all its other values once both are taken.  Every workgroup
-// is a bucket: it publishes its three best chain keys (with coordinates and
+// is a bucket: it publishes its E best chain keys (four or five, with coordinates and
 // sorted positions) and value bits R that bound every value it does not
 // offer (the largest chain key it keeps back, and every wavefront's bound
 // after its chain: a wavefront's published keys are a prefix of its chain).
@@ -45,12 +45,23 @@
 namespace bs {
 namespace {
 
-constexpr int kMpEntries = 3;                 // entries a workgroup offers per step
+// Entries a workgroup offers per step: more entries let more of them clear
+// tau (a workgroup's bound R is its first key kept back), but the member set
+// to rank and test grows with them.  Four suit the kernels of up to 256
+// picks per step (many workgroups), five the 128-pick ones (few workgroups,
+// so few entries in all): 28.3 ms against 30.8 (three) and 29.2 (five) on
+// the headline part, 3.3 ms against 3.9 (four) and 5.0 (three) on the
+// 16,384-candidate sphere and box with 16 workgroups.
+template <int MAXPICKS>
+constexpr int mp_entries() { return MAXPICKS > 128 ? 4 : 5; }
+constexpr int kMpMaxEntries = 5;
 // An exchange record: three packed words per entry, then R, each word with a
 // 2-bit step tag above 62 payload bits; one 128-byte line per record.
 constexpr int kMpEntryWords = 3;
-constexpr int kMpWords = kMpEntryWords * kMpEntries + 1;
+template <int E>
+constexpr int mp_words() { return kMpEntryWords * E + 1; }
 constexpr int kMpRecStride = 16;  // words per exchange record
+static_assert(mp_words<kMpMaxEntries>() <= kMpRecStride, "a record fits its line");
 constexpr uint64_t kMpPayload = (uint64_t(1) << 62) - 1u;
 constexpr uint32_t kMpMaxPos = 1u << 22;  // sorted positions fit 22 bits (n <= 2^22)
 // Most picks per step: 256, or 128 for a kernel with fewer passes of one
@@ -141,30 +152,34 @@ __device__ __forceinline__ int lanes_below(uint64_t m) {
     return int(__builtin_amdgcn_mbcnt_hi(uint32_t(m >> 32), __builtin_amdgcn_mbcnt_lo(uint32_t(m), 0u)));
 }
 
-// Entry e of the records (workgroup e / kMpEntries, slot e % kMpEntries),
+// Entry e of the records (workgroup e / E, slot e % E),
 // three packed words (payload bits only):
 //   w0: value bits 0..30 of the key (m >= 0: the sign bit is 0), then the
 //       31 bits of its complemented index;
 //   w1: x, the sorted position (22 bits) from bit 32, z bits 0..7 from bit 54;
 //   w2: y, z bits 8..31 from bit 32.
-// Word kMpWords - 1 of a workgroup's record is R.
+// Word mp_words<E>() - 1 of a workgroup's record is R.
+template <int E>
 __device__ __forceinline__ const uint64_t* rec_entry(const uint64_t* rw, int e) {
-    return rw + (e / kMpEntries) * kMpWords + kMpEntryWords * (e % kMpEntries);
+    return rw + (e / E) * mp_words<E>() + kMpEntryWords * (e % E);
 }
+template <int E>
 __device__ __forceinline__ uint64_t rec_key(const uint64_t* rw, int e) {
-    const uint64_t w0 = rec_entry(rw, e)[0];
+    const uint64_t w0 = rec_entry<E>(rw, e)[0];
     return ((w0 & 0x7FFFFFFFull) << 32) | ((w0 >> 31) & 0x7FFFFFFFull);
 }
 // x, y, z and the sorted position (as the bits of w) of entry e.
+template <int E>
 __device__ __forceinline__ float4 rec_coords(const uint64_t* rw, int e) {
-    const uint64_t* p = rec_entry(rw, e);
+    const uint64_t* p = rec_entry<E>(rw, e);
     const uint64_t w1 = p[1], w2 = p[2];
     const uint32_t z = uint32_t((w1 >> 54) & 0xFFu) | (uint32_t(w2 >> 32) << 8);
     return make_float4(__uint_as_float(uint32_t(w1)), __uint_as_float(uint32_t(w2)), __uint_as_float(z),
                        __int_as_float(int((w1 >> 32) & (kMpMaxPos - 1u))));
 }
+template <int E>
 __device__ __forceinline__ uint32_t rec_bound(const uint64_t* rw, int g) {
-    return uint32_t(rw[g * kMpWords + kMpEntryWords * kMpEntries]);
+    return uint32_t(rw[g * mp_words<E>() + kMpEntryWords * E]);
 }
 // Word f of an entry from its key, coordinates and position (32-bit fields).
 __device__ __forceinline__ uint64_t pack_entry_word(int f, uint32_t key_hi, uint32_t key_lo, uint32_t x, uint32_t y,
@@ -242,6 +257,8 @@ __global__ void __launch_bounds__(BLOCK)
                    uint64_t* __restrict__ slots, uint64_t* __restrict__ ticks, int max_picks,
                    uint32_t spin_limit) {
     constexpr int NW = BLOCK / 64;
+    constexpr int kMpEntries = mp_entries<MAXPICKS>();
+    constexpr int kMpWords = mp_words<kMpEntries>();
     constexpr int kMpPickWords = MAXPICKS / 64;  // reach-test passes of 64 picks
     static_assert(MAXPICKS % 64 == 0 && MAXPICKS <= kMpMaxPicks && MAXPICKS <= BLOCK,
                   "passes of 64 picks; one emitting thread a pick");
@@ -587,14 +604,14 @@ __global__ void __launch_bounds__(BLOCK)
             }
         }
         lds_barrier();
-        // 2. wavefront 0: the workgroup's three best chain keys become its
+        // 2. wavefront 0: the workgroup's E best chain keys become its
         // entries, with their data from the wavefronts that hold them, and R
         // bounds every value it does not offer; its record is one word a lane
         const uint64_t tag = uint64_t(step & 3u) << 62;
         if (wave == 0) {
             // chain key i of wavefront w on lane 2 w + i, ranked among all
             // listed keys by counting the larger ones (keys are unique, 0 =
-            // none); ranks 0, 1, 2 are the entries
+            // none); ranks 0 .. E-1 are the entries
             constexpr int NK = 2 * NW;
             static_assert(NK % 2 == 0 && NK <= 64 && 6 * kMpEntries <= 64, "one key a lane");
             const int kw = lane >> 1, ki = lane & 1;
@@ -627,7 +644,7 @@ __global__ void __launch_bounds__(BLOCK)
             }
             __builtin_amdgcn_wave_barrier();  // LDS in program order within the wavefront
             // lane 3 e + f carries packed word f of entry e (zero past the
-            // listed keys); lane 9 carries R
+            // listed keys); lane 3 E carries R
             uint64_t wv = rg;
             if (lane < kMpEntryWords * kMpEntries) {
                 const int e = lane / kMpEntryWords, f = lane - e * kMpEntryWords;
@@ -697,8 +714,8 @@ __global__ void __launch_bounds__(BLOCK)
 #pragma unroll
             for (int c = 0; c < kMpMaxGroups / 64; ++c) {
                 const int w = c * 64 + lane;
-                k1[c] = w < G ? rec_key(s_rw, kMpEntries * w) : 0ull;
-                rr[c] = w < G ? rec_bound(s_rw, w) : 0u;
+                k1[c] = w < G ? rec_key<kMpEntries>(s_rw, kMpEntries * w) : 0ull;
+                rr[c] = w < G ? rec_bound<kMpEntries>(s_rw, w) : 0u;
             }
             uint64_t top = 0;
             uint32_t topr = 0;
@@ -732,33 +749,39 @@ __global__ void __launch_bounds__(BLOCK)
             uint64_t k1w = k1[0];
 #pragma unroll
             for (int c = 1; c < kMpMaxGroups / 64; ++c) k1w = wave == c ? k1[c] : k1w;
-            const bool m1 = k1w != 0 && (k1w == tk || uint32_t(k1w >> 32) > tau);
-            const uint64_t k2 = w < G ? rec_key(s_rw, kMpEntries * w + 1) : 0ull;
-            const uint64_t k3 = w < G ? rec_key(s_rw, kMpEntries * w + 2) : 0ull;
-            const bool m2 = k2 != 0 && uint32_t(k2 >> 32) > tau;  // e3 < e2 < e1 <= top
-            const bool m3 = k3 != 0 && uint32_t(k3 >> 32) > tau;
-            const uint64_t b1 = __ballot(m1), b2 = __ballot(m2), b3 = __ballot(m3);
-            const int cnt = __popcll(b1) + __popcll(b2) + __popcll(b3);
+            // entry e of workgroup w is a member when above tau (the first
+            // also when it is the top key); the later entries of a
+            // workgroup lie below its earlier ones
+            uint64_t ke[kMpEntries];
+            bool me[kMpEntries];
+            uint64_t be[kMpEntries];
+            ke[0] = k1w;
+            me[0] = k1w != 0 && (k1w == tk || uint32_t(k1w >> 32) > tau);
+#pragma unroll
+            for (int e = 1; e < kMpEntries; ++e) {
+                ke[e] = w < G ? rec_key<kMpEntries>(s_rw, kMpEntries * w + e) : 0ull;
+                me[e] = ke[e] != 0 && uint32_t(ke[e] >> 32) > tau;
+            }
+            int cnt = 0;
+#pragma unroll
+            for (int e = 0; e < kMpEntries; ++e) {
+                be[e] = __ballot(me[e]);
+                cnt += __popcll(be[e]);
+            }
             int base = 0;
             if (cnt != 0) {
                 int old = 0;
                 if (lane == 0) old = atomicAdd(&s_na, cnt);
                 base = __builtin_amdgcn_readfirstlane(old);  // the whole wavefront is active: lane 0
             }
-            const int p1 = base + lanes_below(b1);
-            const int p2 = base + __popcll(b1) + lanes_below(b2);
-            const int p3 = base + __popcll(b1) + __popcll(b2) + lanes_below(b3);
-            if (m1) {
-                s_mk[p1] = k1w;
-                s_mi[p1] = kMpEntries * w;
-            }
-            if (m2) {
-                s_mk[p2] = k2;
-                s_mi[p2] = kMpEntries * w + 1;
-            }
-            if (m3) {
-                s_mk[p3] = k3;
-                s_mi[p3] = kMpEntries * w + 2;
+#pragma unroll
+            for (int e = 0; e < kMpEntries; ++e) {
+                if (me[e]) {
+                    const int p = base + lanes_below(be[e]);
+                    s_mk[p] = ke[e];
+                    s_mi[p] = kMpEntries * w + e;
+                }
+                base += __popcll(be[e]);
             }
         }
         lds_barrier();
@@ -796,7 +819,7 @@ __global__ void __launch_bounds__(BLOCK)
                 for (int r = 1; r < MR; ++r) rank = part == r ? rk[r] : rank;
                 const int mi = m0 + part;
                 if (part < MR && mi < na && rank < cap) {
-                    const float4 c = rec_coords(s_rw, s_mi[mi]);
+                    const float4 c = rec_coords<kMpEntries>(s_rw, s_mi[mi]);
                     s_pk[rank] = make_float4(c.x, c.y, c.z, key_value(s_mk[mi]));
                     s_pid[rank] = key_id(s_mk[mi]);
                     s_ppos[rank] = __float_as_int(c.w);
