@@ -828,25 +828,42 @@ __global__ void __launch_bounds__(BLOCK)
         }
         const int nr = min(na, cap);
         lds_barrier();
-        // 5. distance conflicts: TPC threads per member j test it against the
-        // earlier members i < j (every TPC-th one each); a wavefront's eight
-        // or more consecutive columns give their lowest lowered j by ballot,
-        // and that goes to LDS in one atomic
+        // 5. distance conflicts: member j is tested against the earlier
+        // members i < j.  Columns are paired, c with nr - 1 - c, so that
+        // every pair holds nr - 1 tests; TPP threads share a pair, each
+        // taking every TPP-th test of column c, then of column nr - 1 - c.
+        // Per wavefront the lowest lowered column of each kind comes from a
+        // ballot (c grows with the lane, nr - 1 - c falls), and the lower
+        // goes to LDS in one atomic
         {
-            constexpr int TPC = BLOCK / MAXPICKS;  // threads per column
-            static_assert(TPC >= 1 && (TPC & (TPC - 1)) == 0 && 64 % TPC == 0, "conflict tiling");
-            const int j = tid / TPC, part = tid % TPC;  // j < MAXPICKS
-            bool low = false;
-            if (j < nr) {
-                const float4 cj = s_pk[j];
+            constexpr int TPP = BLOCK / (MAXPICKS / 2);  // threads per column pair
+            static_assert(TPP >= 1 && (TPP & (TPP - 1)) == 0 && 64 % TPP == 0, "conflict tiling");
+            const int c = tid / TPP, part = tid % TPP;  // c < MAXPICKS / 2
+            bool low1 = false, low2 = false;
+            if (c < (nr + 1) / 2) {
+                const int j2 = nr - 1 - c;  // == c only for the middle column of an odd nr
+                const float4 c1 = s_pk[c];
 #pragma unroll 2
-                for (int i = part; i < j; i += TPC) {
+                for (int i = part; i < c; i += TPP) {
                     const float4 ci = s_pk[i];
-                    if (dist2(cj.x, cj.y, cj.z, ci.x, ci.y, ci.z) < cj.w) low = true;
+                    if (dist2(c1.x, c1.y, c1.z, ci.x, ci.y, ci.z) < c1.w) low1 = true;
+                }
+                if (j2 > c) {
+                    const float4 c2 = s_pk[j2];
+#pragma unroll 2
+                    for (int i = part; i < j2; i += TPP) {
+                        const float4 ci = s_pk[i];
+                        if (dist2(c2.x, c2.y, c2.z, ci.x, ci.y, ci.z) < c2.w) low2 = true;
+                    }
                 }
             }
-            const uint64_t b = __ballot(low);
-            if (b != 0 && lane == 0) atomicMin(&s_kfail, (wave * 64 + __builtin_ctzll(b)) / TPC);
+            const uint64_t b1 = __ballot(low1), b2 = __ballot(low2);
+            if (lane == 0 && (b1 | b2) != 0ull) {
+                int f = MAXPICKS;
+                if (b1) f = min(f, (wave * 64 + __builtin_ctzll(b1)) / TPP);
+                if (b2) f = min(f, nr - 1 - (wave * 64 + 63 - __builtin_clzll(b2)) / TPP);
+                atomicMin(&s_kfail, f);
+            }
         }
         lds_barrier();
         K = min(s_kfail, nr);
