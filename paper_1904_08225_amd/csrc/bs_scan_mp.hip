@@ -49,9 +49,9 @@ namespace {
 // tau (a workgroup's bound R is its first key kept back), but the member set
 // to rank and test grows with them.  Four suit the kernels of up to 256
 // picks per step (many workgroups), five the 128-pick ones (few workgroups,
-// so few entries in all): 28.3 ms against 30.8 (three) and 29.2 (five) on
-// the headline part, 3.3 ms against 3.9 (four) and 5.0 (three) on the
-// 16,384-candidate sphere and box with 16 workgroups.
+// so few entries in all): 26.6 ms against 27.7 (five) and 30.8 before (three)
+// on the 4,194,304-candidate part to 262,144; 3.3 ms against 3.9 (four) and
+// 5.0 (three) on the 16,384-candidate sphere and box with 16 workgroups.
 template <int MAXPICKS>
 constexpr int mp_entries() { return MAXPICKS > 128 ? 4 : 5; }
 constexpr int kMpMaxEntries = 5;
