@@ -648,7 +648,8 @@ typedef struct {
     int32_t poll_us;             /* dispatcher polling period while busy; 0 = 50 */
     float cell_points;           /* grid cell target, 0 = 8 */
     int32_t workgroups;          /* resident 1024-thread ordering workers (each holds a whole
-                                    compute unit), 0 = half the compute units */
+                                    compute unit), 0 = three quarters of the compute units;
+                                    at most seven eighths (the rest run the preprocessing) */
     int32_t stall_us;            /* a micro-batch whose preprocessing has not begun on the device
                                     this long after every earlier micro-batch was published stops
                                     the workers (the device is then running it behind them on one

@@ -606,8 +606,8 @@ __global__ void publish_kernel(const ObjDesc* __restrict__ desc, const int32_t* 
 // orders that object and sets its completion flag.  A workgroup exits when
 // stop is set and nothing is left to claim, or after idle_polls empty polls.
 // Workers have 1024 threads: a worker then holds a whole CU (its waves take
-// most of each SIMD's registers), so as many workers as half the CUs leave
-// the other CUs free for the preprocessing kernels of later micro-batches.
+// most of each SIMD's registers), so the workers take at most seven eighths
+// of the CUs and leave the others to the preprocessing of later micro-batches.
 __global__ void __launch_bounds__(kWideBlock)
     serve_kernel(const ObjDesc* __restrict__ slots, uint32_t cap, uint32_t* head, const uint32_t* tail,
                  const uint32_t* stop, uint32_t idle_polls) {
