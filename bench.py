@@ -881,7 +881,8 @@ def main():
     if n_ball is not None:
         several = kernel == bs.KERNEL_COOP and tuned.picks > 1
         if several:
-            kname = "scan_mp_kernel<%d,%d> x %d workgroups" % (tuned.block, tuned.per_thread, tuned.groups)
+            kname = "scan_mp_kernel<%d, %d, %d> x %d workgroups" % (
+                tuned.block, tuned.per_thread, 256 if tuned.picks > 128 else 128, tuned.groups)
             which = "scan_mp"
         else:
             kname = {3: "grid_multi_kernel<%d,...>" % (tuned.block or 1024)}.get(kernel, "kernel %d" % kernel)

@@ -106,7 +106,10 @@ typedef struct {
                               workgroups): 2..256 = several exact picks per step over
                               the candidates in Morton order, every workgroup a bucket
                               offering its four best keys, five in the 128-pick
-                              kernel */
+                              kernel.  Batch plans: most exact picks per round of
+                              each object, 1..32 (same result); 0 = 24, or 16 for
+                              an object whose cells average more than 64
+                              candidates */
     int32_t lead_picks;    /* grid kernel with several picks per round: the first picks
                               come from the cooperative full scan over all CUs, which
                               then hands every candidate's distance to the grid kernel

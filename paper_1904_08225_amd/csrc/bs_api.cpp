@@ -431,10 +431,13 @@ int bs_batch_plan_create(const int64_t* h_offsets, const int64_t* h_k, const uin
     if (!out_plan) return set_error(BS_ERR_INVALID_ARG, "null plan pointer");
     *out_plan = nullptr;
     if (!tuning_clean(tuning) || (tuning && tuning->groups < 0)) return set_error(BS_ERR_INVALID_ARG, "bad tuning struct");
+    if (tuning && tuning->picks > kMaxGridPicks)
+        return set_error(BS_ERR_UNSUPPORTED, "batch plans: at most %d picks per round", kMaxGridPicks);
     const float target = (tuning && tuning->cell_points > 0.f) ? tuning->cell_points : kDefaultCellPointsMulti;
     bs::BatchPlan* p = nullptr;
     int rc = batch_plan_create(h_offsets, h_k, h_seed, m, target, tuning ? tuning->batch_wide : 0,
                                tuning ? tuning->groups : 0, &p);
+    if (rc == BS_OK) batch_set_picks(p, tuning ? tuning->picks : 0);
     if (rc == BS_OK) rc = batch_plan_upload(p);
     if (rc != BS_OK) {
         batch_plan_free(p);

@@ -100,6 +100,8 @@ int batch_morton_order(BatchPlan* p, const float* pts, int32_t* out_perm, void* 
                        hipStream_t st);
 // Objects ordered by the 1024-thread workgroups.
 int batch_wide_count(const BatchPlan* p);
+// Most exact picks per round of every object (1..32; 0 = by mean cell size).
+void batch_set_picks(BatchPlan* p, int picks);
 const int64_t* batch_out_offsets(const BatchPlan* p);
 int batch_slots(const BatchPlan* p);
 void batch_set_job_io(BatchPlan* p, const std::vector<int32_t*>& order, const std::vector<float*>& radius,

@@ -74,6 +74,10 @@ def test_batch_plan_validation_without_device(lib):
     rc = lib.bs_batch_plan_create(offs.ctypes.data_as(vp), ks.ctypes.data_as(vp), None, 1, ctypes.byref(t),
                                   ctypes.byref(plan))
     assert rc == bs.BS_ERR_INVALID_ARG
+    t = bs.tuning(picks=33)                       # more picks per round than the grid kernel takes
+    rc = lib.bs_batch_plan_create(offs.ctypes.data_as(vp), ks.ctypes.data_as(vp), None, 1, ctypes.byref(t),
+                                  ctypes.byref(plan))
+    assert rc == bs.BS_ERR_UNSUPPORTED and "picks" in bs.last_error()
 
 
 def test_server_config_validation_without_device(lib):

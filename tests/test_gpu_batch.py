@@ -190,3 +190,29 @@ def test_batch_wide_workgroups(hip, wide):
             assert_parity(o[a:b], r[a:b], eo, er, "wide=%d object %d (n=%d k=%d) rep %d"
                           % (wide, j, P.shape[0], ks[j], rep))
     plan.close()
+
+
+@pytest.mark.parametrize("picks", [1, 2, 16, 32])
+def test_batch_picks_per_round(hip, picks):
+    """Every cap on the picks per round (by default 24, 16 for large cells) orders each
+    object exactly as the oracle does, wide objects included."""
+    import torch
+    objs, ks, seeds, offs = make_batch(11 + picks, count=20)
+    big = [np.ascontiguousarray(synth.cad_part(n, seed=950 + n % 97, count=30).points.numpy())
+           for n in (70000, 140000)]
+    objs += big
+    ks += [b.shape[0] // 3 for b in big]
+    seeds += [picks * 1000 + 1, picks * 1000 + 2]
+    offs = np.concatenate([[0], np.cumsum([o.shape[0] for o in objs])]).astype(np.int64)
+    plan = hip.BatchPlan(offs, ks, seeds, tune=hip.tuning(picks=picks, batch_wide=2))
+    o, r = plan.execute(torch.from_numpy(np.concatenate(objs)).cuda())
+    torch.cuda.synchronize()
+    o = o.cpu().numpy()
+    r = r.cpu().numpy()
+    for j, P in enumerate(objs):
+        a, b = plan.out_offsets[j], plan.out_offsets[j + 1]
+        if ks[j] == 0:
+            continue
+        eo, er = oracle.greedy32_grid(P, ks[j], oracle.start_index(seeds[j], P.shape[0]))
+        assert_parity(o[a:b], r[a:b], eo, er, "picks=%d object %d (n=%d k=%d)" % (picks, j, P.shape[0], ks[j]))
+    plan.close()
