@@ -15,6 +15,10 @@
 // sample members near the chosen surfels when asked) mark m = -1 and
 // refresh their cell's best key, so the hierarchy's top key stays the exact
 // farthest remaining candidate: a round whose draws all miss takes it.
+// Nothing in a round reads the m held in memory after its draws (its later
+// picks come from the sampled values in registers), so the round's picks
+// are applied to memory together, in one grid pass of up to 32 picks: every
+// m becomes the minimum over all of them, as after one pass per pick.
 #pragma once
 #pragma clang fp contract(off)
 
@@ -26,11 +30,13 @@
 
 #include "bs_grid.h"
 #include "bs_grid_device.h"
+#include "bs_grid_multi.h"
 
 namespace bs {
 
 constexpr int kSampleMaxSlots = 256;  // sample slots per round (one per thread)
 constexpr int kSampleAttempts = 16;   // draws a slot makes before it stays empty
+constexpr int kSamplePassPicks = 32;  // picks applied by one grid pass (bits of a 32-bit mask)
 
 // Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC 2011): the first output word
 // for counter (c0, c1, c2, c3) and key (k0, k1).  Ten rounds; each multiplies
@@ -73,11 +79,104 @@ struct SampleSpec {
 template <int NW>
 struct SampleLds {
     uint64_t wkey[NW];
-    float4 win;                     // x, y, z, sorted position of the chosen slot
     int wcnt[NW];
     int nrem;
     int2 rem[kSampleMaxSlots];      // removed sample members: (sorted position, cell)
+    float4 pk[kSamplePassPicks];    // picks not yet applied to memory: x, y, z (w unused)
+    int pkpos[kSamplePassPicks];    // their sorted positions
+    int pkcell[kSamplePassPicks];   // their cells
+    uint32_t hmask[NW][64];         // per wavefront: the picks reaching each hit cell of its block
+    // a pick's selection from the sample (two alternating sets, so that one
+    // barrier per pick suffices): each wavefront's best sampled key, its
+    // x, y, z and sorted position, and its cell
+    uint64_t skey[2][NW];
+    float4 swin[2][NW];
+    int scell[2][NW];
 };
+
+// One wavefront applies the picks in pm (bits of SL.pk) to every candidate of
+// block b they can reach -- a cell is hit by pick j when it is the pick's
+// cell or its box lower bound lies below mc, the largest m left -- marks the
+// picks taken, and rewrites the hit cells' best keys and the block's best in
+// LDS.  The hit cells each get an aligned group of lanes, as in
+// process_block.  Wave-local: no barrier.
+template <int NW, int MAXB>
+__device__ inline void sample_block_update(const GridObject& o, GridLds<NW, MAXB>& L, SampleLds<NW>& SL, int b,
+                                           uint32_t pm, float mc) {
+    const int lane = threadIdx.x & 63;
+    const int wave = threadIdx.x >> 6;
+    WaveScratch& W = L.ws[wave];
+    const int cell = b * 64 + lane;
+    const bool valid = cell < o.C;
+    const int ci = valid ? cell : o.C - 1;
+    const float4 lo = o.cstat[2 * ci], hi = o.cstat[2 * ci + 1];
+    const uint4 d0 = o.cdyn[2 * ci], d1 = o.cdyn[2 * ci + 1];
+    uint64_t ckey = valid ? ((uint64_t(d0.y) << 32) | d0.x) : 0ull;
+    float4 cwin = make_float4(__uint_as_float(d1.x), __uint_as_float(d1.y), __uint_as_float(d1.z),
+                              __int_as_float(int(d0.z)));
+    uint32_t cm = 0u;
+    for (uint32_t mm = pm; mm; mm &= mm - 1) {
+        const int j = __builtin_ctz(mm);
+        const float4 q = SL.pk[j];
+        const bool h = valid && (cell == SL.pkcell[j] ||
+                                 box_lower(lo.x, lo.y, lo.z, hi.x, hi.y, hi.z, q.x, q.y, q.z) < mc);
+        cm |= h ? (1u << j) : 0u;
+    }
+    const bool hit = cm != 0u;
+    const uint64_t hm = __ballot(hit);
+    const int nh = __popcll(hm);
+    if (nh == 0) return;  // nothing in reach: the block's best is unchanged
+    // lanes -> (hit cell r, sub-lane s)
+    const int rank = __popcll(hm & ((1ull << lane) - 1));
+    if (hit) {
+        W.tab[rank] = make_int2(__float_as_int(lo.w), __float_as_int(hi.w));
+        SL.hmask[wave][rank] = cm;
+    }
+    int steps = 0;
+    while ((1 << steps) < nh) ++steps;
+    const int gshift = 6 - steps;
+    const int G = 1 << gshift;
+    const int r = lane >> gshift;
+    wave_lds_sync();
+    const int2 my = W.tab[r < nh ? r : 0];
+    const uint32_t rm = r < nh ? SL.hmask[wave][r] : 0u;
+    const int start = my.x;
+    const int count = r < nh ? my.y : 0;
+    const int s = lane & (G - 1);
+    const bool single = __popc(rm) == 1;
+    const int j0 = __builtin_ctz(rm | 0x80000000u) & (kSamplePassPicks - 1);
+    const float4 q0 = SL.pk[j0];
+    const int qpos0 = SL.pkpos[j0];
+    uint64_t lk = 0, l2 = 0;
+    float4 lw = make_float4(0.f, 0.f, 0.f, 0.f);
+    const int per = count > s ? (count - s + G - 1) >> gshift : 0;
+    const int maxper = __builtin_amdgcn_readfirstlane(int(wave_max_key(uint64_t(per) << 32) >> 32));
+    constexpr int U = NW >= 16 ? 2 : 4;  // member loads in flight per lane
+    if (maxper <= 1)
+        member_batches_mp<1>(o, SL, start, count, s, G, rm, single, q0.x, q0.y, q0.z, qpos0, lk, l2, lw);
+    else
+        member_batches_mp<U>(o, SL, start, count, s, G, rm, single, q0.x, q0.y, q0.z, qpos0, lk, l2, lw);
+    // each hit cell's new best, then the block's
+    const uint64_t gm = group_max_u64(lk, gshift);
+    if (s == G - 1 && r < nh) W.gkey[r] = gm;
+    wave_lds_sync();
+    if (r < nh && lk != 0 && lk == W.gkey[r]) W.gwin[r] = lw;
+    wave_lds_sync();
+    if (hit) {
+        ckey = W.gkey[rank];
+        cwin = W.gwin[rank];
+        o.cdyn[2 * cell + 0] = make_uint4(uint32_t(ckey), uint32_t(ckey >> 32), uint32_t(__float_as_int(cwin.w)), 0u);
+        o.cdyn[2 * cell + 1] = make_uint4(__float_as_uint(cwin.x), __float_as_uint(cwin.y),
+                                          __float_as_uint(cwin.z), 0u);
+    }
+    const uint64_t bk = wave_max_key(ckey);
+    if (bk != 0 && ckey == bk) {
+        L.bwin[b] = cwin;
+        L.bcell[b] = cell;
+    }
+    if (lane == 0) L.bkey[b] = bk;
+    wave_lds_sync();
+}
 
 // Workgroup maximum of a 64-bit key (uniform result); two barriers.
 template <int NW>
@@ -212,6 +311,72 @@ __device__ inline void sample_object(const GridObject& o, const SampleSpec& sp, 
     using Upd = std::integral_constant<bool, true>;    // a pick: distances drop, it is marked
     using Mark = std::integral_constant<bool, false>;  // a removal: only marked
 
+    // One pass applying the np picks held in SL.pk (every m below mc, the
+    // largest m left, may drop): superblocks, then blocks, each tested
+    // against the picks that reach its superblock; then the touched
+    // superblocks' bests.  Returns the top key left.
+    auto pass_set = [&](int np, float mc) -> uint64_t {
+        __syncthreads();  // the picks' LDS entries are written
+        uint32_t sm = 0u;  // lane = superblock: the picks that may reach it
+        if (lane < nsb) {
+            for (int j = 0; j < np; ++j) {
+                const float4 q = SL.pk[j];
+                const bool r = lane == (SL.pkcell[j] >> 12) ||  // its own superblock (64 blocks of 64 cells)
+                               box_lower(slx, sly, slz, shx, shy, shz, q.x, q.y, q.z) < mc;
+                sm |= r ? (1u << j) : 0u;
+            }
+        }
+        const uint64_t smask = __ballot(sm != 0u);
+#pragma unroll
+        for (int j = 0; j < BPT; ++j) {
+            const int sb = j * NW + wave;
+            uint64_t msk = 0;
+            if ((smask >> sb) & 1ull) {
+                const int b = j * BLOCK + tid;
+                const uint32_t bm = uint32_t(__builtin_amdgcn_readlane(int(sm), sb));
+                bool touch = false;
+                for (uint32_t mm = bm; mm; mm &= mm - 1) {
+                    const int jj = __builtin_ctz(mm);
+                    const float4 q = SL.pk[jj];
+                    touch = touch || b == (SL.pkcell[jj] >> 6) ||
+                            box_lower(blx[j], bly[j], blz[j], bhx[j], bhy[j], bhz[j], q.x, q.y, q.z) < mc;
+                }
+                msk = __ballot(touch);
+            }
+            if (lane == 0) L.mask[sb] = msk;
+        }
+        __syncthreads();
+        const uint64_t mword = lane < nsb ? L.mask[lane] : 0ull;
+        const uint64_t nz = __ballot(mword != 0);
+        int rank = 0;
+        for (uint64_t zs = nz; zs;) {
+            const int mi = __builtin_ctzll(zs);
+            zs &= zs - 1;
+            const uint32_t mlo = uint32_t(__builtin_amdgcn_readlane(int(uint32_t(mword)), mi));
+            const uint32_t mhi = uint32_t(__builtin_amdgcn_readlane(int(uint32_t(mword >> 32)), mi));
+            const uint32_t bm = uint32_t(__builtin_amdgcn_readlane(int(sm), mi));
+            for (uint64_t mk = (uint64_t(mhi) << 32) | mlo; mk;) {
+                const int b = mi * 64 + __builtin_ctzll(mk);
+                mk &= mk - 1;
+                if (rank % NW == wave) sample_block_update<NW, MAXB>(o, L, SL, b, bm, mc);
+                ++rank;
+            }
+        }
+        __syncthreads();
+        for (uint64_t zs = nz; zs;) {
+            const int mi = __builtin_ctzll(zs);
+            zs &= zs - 1;
+            uint64_t kk;
+            int bb;
+            superblock_best(L, mi, kk, bb);
+            if (lane == mi) {
+                sbk = kk;
+                sbb = bb;
+            }
+        }
+        return wave_max_key(sbk);
+    };
+
     // the start's update (every candidate's m is +inf before it)
     uint64_t top = pass(Upd{}, INFINITY);
 
@@ -223,8 +388,9 @@ __device__ inline void sample_object(const GridObject& o, const SampleSpec& sp, 
     // this thread's sample slot
     bool live = false;
     float val = 0.f, px = 0.f, py = 0.f, pz = 0.f;
-    int ppos = 0;
+    int ppos = 0, pcell = 0;
     uint32_t pid = 0;
+    uint32_t sel = 0;  // selections from the sample so far (alternate LDS sets)
     while (t < k && remaining > 0) {
         // --- a new round: draw the sample
         bool whole = S == 0;
@@ -243,6 +409,7 @@ __device__ inline void sample_object(const GridObject& o, const SampleSpec& sp, 
                         py = p.y;
                         pz = p.z;
                         ppos = pos;
+                        pcell = int(sp.cellidx[pos]) - 1 - sp.cell_base;
                         pid = idx;
                         break;
                     }
@@ -254,6 +421,7 @@ __device__ inline void sample_object(const GridObject& o, const SampleSpec& sp, 
         int q = sp.K < 0 ? 1 : 1 + int(round / uint32_t(sp.K));
         if (whole && S > 0) q = 1;
         float d_first = 0.f;
+        int np = 0;  // picks of this round not yet applied to memory
         for (int p = 0; p < q && t < k && remaining > 0; ++p) {
             uint64_t best;
             if (whole) {
@@ -271,18 +439,34 @@ __device__ inline void sample_object(const GridObject& o, const SampleSpec& sp, 
                 cy = win.y;
                 cz = win.z;
             } else {
-                best = block_max_key(live ? make_key(val, pid) : 0ull, SL);
-                if (best == 0) break;  // the sample is used up
-                if (live && make_key(val, pid) == best)
-                    SL.win = make_float4(px, py, pz, __int_as_float(ppos));
+                // the largest sampled key: per wavefront, then over the
+                // wavefronts' entries (lanes holding the same key hold the
+                // same candidate, so any of them may write its data)
+                const uint64_t mine = live ? make_key(val, pid) : 0ull;
+                const uint64_t wk = wave_max_key(mine);
+                const int par = int(sel & 1u);
+                ++sel;
+                if (lane == 0) SL.skey[par][wave] = wk;
+                if (wk != 0 && mine == wk) {
+                    SL.swin[par][wave] = make_float4(px, py, pz, __int_as_float(ppos));
+                    SL.scell[par][wave] = pcell;
+                }
                 __syncthreads();
-                const float4 win = SL.win;
+                best = 0;
+                int bw = 0;
+#pragma unroll
+                for (int w = 0; w < NW; ++w) {
+                    const uint64_t kw = SL.skey[par][w];
+                    bw = kw > best ? w : bw;
+                    best = kw > best ? kw : best;
+                }
+                if (best == 0) break;  // the sample is used up
+                const float4 win = SL.swin[par][bw];
                 c_pos = __float_as_int(win.w);
-                c_cell = int(sp.cellidx[c_pos]) - 1 - sp.cell_base;
+                c_cell = SL.scell[par][bw];
                 cx = win.x;
                 cy = win.y;
                 cz = win.z;
-                __syncthreads();
             }
             const float mv = key_value(best);
             if (p == 0) d_first = mv;
@@ -298,8 +482,20 @@ __device__ inline void sample_object(const GridObject& o, const SampleSpec& sp, 
                 if (pid == key_id(best)) live = false;
                 else val = fminf(val, dist2(px, py, pz, cx, cy, cz));
             }
-            top = pass(Upd{}, key_value(top));
+            if (tid == 0) {
+                SL.pk[np] = make_float4(cx, cy, cz, 0.f);
+                SL.pkpos[np] = c_pos;
+                SL.pkcell[np] = c_cell;
+            }
+            ++np;
+            // a pick taken from the top key needs memory up to date for the
+            // next one (the whole remaining set as the sample)
+            if (whole || np == kSamplePassPicks) {
+                top = pass_set(np, key_value(top));
+                np = 0;
+            }
         }
+        if (np > 0) top = pass_set(np, key_value(top));
         // --- removal of sample members near the chosen surfels
         if (sp.vicinity > 0.f && !whole) {
             const float thr = (sp.vicinity * sp.vicinity) * d_first;
