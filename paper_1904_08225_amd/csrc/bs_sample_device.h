@@ -38,6 +38,17 @@ constexpr int kSampleMaxSlots = 256;  // sample slots per round (one per thread)
 constexpr int kSampleAttempts = 16;   // draws a slot makes before it stays empty
 constexpr int kSamplePassPicks = 32;  // picks applied by one grid pass (bits of a 32-bit mask)
 
+// A workgroup barrier ordering LDS only.  __syncthreads() also waits for the
+// wavefront's global stores in flight (the picks just emitted, say), which
+// a barrier that only hands LDS data to the other wavefronts need not do.
+// Global data one wavefront writes and another reads is still ordered by a
+// __syncthreads() between the two.
+__device__ __forceinline__ void barrier_lds() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+    __builtin_amdgcn_s_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
+
 // Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC 2011): the first output word
 // for counter (c0, c1, c2, c3) and key (k0, k1).  Ten rounds; each multiplies
 // words 0 and 2 by 0xD2511F53 and 0xCD9E8D57 into 64-bit products and mixes
@@ -96,13 +107,14 @@ struct SampleLds {
 
 // One wavefront applies the picks in pm (bits of SL.pk) to every candidate of
 // block b they can reach -- a cell is hit by pick j when it is the pick's
-// cell or its box lower bound lies below mc, the largest m left -- marks the
+// cell or its box lower bound from the pick lies below the cell's largest m
+// (its best key's value: no member with a smaller m can drop) -- marks the
 // picks taken, and rewrites the hit cells' best keys and the block's best in
 // LDS.  The hit cells each get an aligned group of lanes, as in
 // process_block.  Wave-local: no barrier.
 template <int NW, int MAXB>
 __device__ inline void sample_block_update(const GridObject& o, GridLds<NW, MAXB>& L, SampleLds<NW>& SL, int b,
-                                           uint32_t pm, float mc) {
+                                           uint32_t pm) {
     const int lane = threadIdx.x & 63;
     const int wave = threadIdx.x >> 6;
     WaveScratch& W = L.ws[wave];
@@ -114,12 +126,13 @@ __device__ inline void sample_block_update(const GridObject& o, GridLds<NW, MAXB
     uint64_t ckey = valid ? ((uint64_t(d0.y) << 32) | d0.x) : 0ull;
     float4 cwin = make_float4(__uint_as_float(d1.x), __uint_as_float(d1.y), __uint_as_float(d1.z),
                               __int_as_float(int(d0.z)));
+    const float cmax = key_value(ckey);  // 0 when no member is left
     uint32_t cm = 0u;
     for (uint32_t mm = pm; mm; mm &= mm - 1) {
         const int j = __builtin_ctz(mm);
         const float4 q = SL.pk[j];
         const bool h = valid && (cell == SL.pkcell[j] ||
-                                 box_lower(lo.x, lo.y, lo.z, hi.x, hi.y, hi.z, q.x, q.y, q.z) < mc);
+                                 box_lower(lo.x, lo.y, lo.z, hi.x, hi.y, hi.z, q.x, q.y, q.z) < cmax);
         cm |= h ? (1u << j) : 0u;
     }
     const bool hit = cm != 0u;
@@ -183,14 +196,14 @@ template <int NW>
 __device__ __forceinline__ uint64_t block_max_key(uint64_t v, SampleLds<NW>& S) {
     const uint64_t wk = wave_max_key(v);
     if ((threadIdx.x & 63) == 0) S.wkey[threadIdx.x >> 6] = wk;
-    __syncthreads();
+    barrier_lds();
     uint64_t best = 0;
 #pragma unroll
     for (int w = 0; w < NW; ++w) {
         const uint64_t k = S.wkey[w];
         best = k > best ? k : best;
     }
-    __syncthreads();
+    barrier_lds();
     return best;
 }
 
@@ -311,18 +324,21 @@ __device__ inline void sample_object(const GridObject& o, const SampleSpec& sp, 
     using Upd = std::integral_constant<bool, true>;    // a pick: distances drop, it is marked
     using Mark = std::integral_constant<bool, false>;  // a removal: only marked
 
-    // One pass applying the np picks held in SL.pk (every m below mc, the
-    // largest m left, may drop): superblocks, then blocks, each tested
-    // against the picks that reach its superblock; then the touched
-    // superblocks' bests.  Returns the top key left.
-    auto pass_set = [&](int np, float mc) -> uint64_t {
-        __syncthreads();  // the picks' LDS entries are written
+    // One pass applying the np picks held in SL.pk: superblocks, then
+    // blocks, then cells, each tested against the picks that reach the level
+    // above, a pick reaching a box when the box's lower bound from it lies
+    // below the largest m held in the box (its best key's value), or when it
+    // lies in the box; then the touched superblocks' bests.  Returns the top
+    // key left.
+    auto pass_set = [&](int np) -> uint64_t {
+        barrier_lds();  // the picks' LDS entries are written
         uint32_t sm = 0u;  // lane = superblock: the picks that may reach it
         if (lane < nsb) {
+            const float smax = key_value(sbk);
             for (int j = 0; j < np; ++j) {
                 const float4 q = SL.pk[j];
                 const bool r = lane == (SL.pkcell[j] >> 12) ||  // its own superblock (64 blocks of 64 cells)
-                               box_lower(slx, sly, slz, shx, shy, shz, q.x, q.y, q.z) < mc;
+                               box_lower(slx, sly, slz, shx, shy, shz, q.x, q.y, q.z) < smax;
                 sm |= r ? (1u << j) : 0u;
             }
         }
@@ -334,18 +350,19 @@ __device__ inline void sample_object(const GridObject& o, const SampleSpec& sp, 
             if ((smask >> sb) & 1ull) {
                 const int b = j * BLOCK + tid;
                 const uint32_t bm = uint32_t(__builtin_amdgcn_readlane(int(sm), sb));
+                const float bmax = key_value(L.bkey[b]);
                 bool touch = false;
                 for (uint32_t mm = bm; mm; mm &= mm - 1) {
                     const int jj = __builtin_ctz(mm);
                     const float4 q = SL.pk[jj];
                     touch = touch || b == (SL.pkcell[jj] >> 6) ||
-                            box_lower(blx[j], bly[j], blz[j], bhx[j], bhy[j], bhz[j], q.x, q.y, q.z) < mc;
+                            box_lower(blx[j], bly[j], blz[j], bhx[j], bhy[j], bhz[j], q.x, q.y, q.z) < bmax;
                 }
                 msk = __ballot(touch);
             }
             if (lane == 0) L.mask[sb] = msk;
         }
-        __syncthreads();
+        barrier_lds();
         const uint64_t mword = lane < nsb ? L.mask[lane] : 0ull;
         const uint64_t nz = __ballot(mword != 0);
         int rank = 0;
@@ -358,11 +375,11 @@ __device__ inline void sample_object(const GridObject& o, const SampleSpec& sp, 
             for (uint64_t mk = (uint64_t(mhi) << 32) | mlo; mk;) {
                 const int b = mi * 64 + __builtin_ctzll(mk);
                 mk &= mk - 1;
-                if (rank % NW == wave) sample_block_update<NW, MAXB>(o, L, SL, b, bm, mc);
+                if (rank % NW == wave) sample_block_update<NW, MAXB>(o, L, SL, b, bm);
                 ++rank;
             }
         }
-        __syncthreads();
+        __syncthreads();  // also orders the member and cell stores for later passes and draws
         for (uint64_t zs = nz; zs;) {
             const int mi = __builtin_ctzll(zs);
             zs &= zs - 1;
@@ -451,7 +468,7 @@ __device__ inline void sample_object(const GridObject& o, const SampleSpec& sp, 
                     SL.swin[par][wave] = make_float4(px, py, pz, __int_as_float(ppos));
                     SL.scell[par][wave] = pcell;
                 }
-                __syncthreads();
+                barrier_lds();  // the emitted picks' stores need not complete here
                 best = 0;
                 int bw = 0;
 #pragma unroll
@@ -491,11 +508,11 @@ __device__ inline void sample_object(const GridObject& o, const SampleSpec& sp, 
             // a pick taken from the top key needs memory up to date for the
             // next one (the whole remaining set as the sample)
             if (whole || np == kSamplePassPicks) {
-                top = pass_set(np, key_value(top));
+                top = pass_set(np);
                 np = 0;
             }
         }
-        if (np > 0) top = pass_set(np, key_value(top));
+        if (np > 0) top = pass_set(np);
         // --- removal of sample members near the chosen surfels
         if (sp.vicinity > 0.f && !whole) {
             const float thr = (sp.vicinity * sp.vicinity) * d_first;
