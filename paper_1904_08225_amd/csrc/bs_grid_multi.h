@@ -282,13 +282,14 @@ __device__ inline int process_block_mp(const GridObject& o, Lds& L, int b, const
                                  box_lower(blo.x, blo.y, blo.z, bhi.x, bhi.y, bhi.z, px, py, pz) < pm);
     uint32_t bm = uint32_t(__ballot(bt));
     // per cell: which of those picks reach it
+    const float cmax = __uint_as_float(d0.y);  // no member's m exceeds the cell's best key's value
     uint32_t cm = 0, um = 0;
     for (uint32_t mm = bm; mm; mm &= mm - 1) {
         const int j = __builtin_ctz(mm);
         const float qx = rl(px, j), qy = rl(py, j), qz = rl(pz, j), qm = rl(pm, j);
         const int qc = __builtin_amdgcn_readlane(pcell, j);
         const bool h = valid && (cell == qc ||
-                                 box_lower(lo.x, lo.y, lo.z, hi.x, hi.y, hi.z, qx, qy, qz) < qm);
+                                 box_lower(lo.x, lo.y, lo.z, hi.x, hi.y, hi.z, qx, qy, qz) < fminf(qm, cmax));
         cm |= h ? (1u << j) : 0u;
         um |= __ballot(h) ? (1u << j) : 0u;
     }
@@ -401,13 +402,14 @@ __device__ inline void collect_block(const GridObject& o, Lds& L, int b, const B
     const float4 blo = load_vec(o.bstat + 2 * b), bhi = load_vec(o.bstat + 2 * b + 1);
     const bool bt = lane < K && ((pcell >> 6) == b ||
                                  box_lower(blo.x, blo.y, blo.z, bhi.x, bhi.y, bhi.z, px, py, pz) < pm);
+    const float cmax = __uint_as_float(d0.y);  // no member's m exceeds the cell's best key's value
     uint32_t cm = 0;
     for (uint32_t mm = uint32_t(__ballot(bt)); mm; mm &= mm - 1) {
         const int j = __builtin_ctz(mm);
         const float qx = rl(px, j), qy = rl(py, j), qz = rl(pz, j), qm = rl(pm, j);
         const int qc = __builtin_amdgcn_readlane(pcell, j);
         const bool h = valid && (cell == qc ||
-                                 box_lower(lo.x, lo.y, lo.z, hi.x, hi.y, hi.z, qx, qy, qz) < qm);
+                                 box_lower(lo.x, lo.y, lo.z, hi.x, hi.y, hi.z, qx, qy, qz) < fminf(qm, cmax));
         cm |= h ? (1u << j) : 0u;
     }
     const bool hit = cm != 0;
@@ -706,6 +708,8 @@ __device__ inline void grid_order_object_mp(const GridObject& o, GridLdsMP<BLOCK
             const uint32_t mine = b < NB ? (L.spm[sb] & kmask) : 0u;
             uint32_t wm = 0;
             for (int j = 0; j < K; ++j) wm |= __ballot((mine >> j) & 1u) ? (1u << j) : 0u;
+            // no m in the block exceeds its best key's value (0 past NB)
+            const float bmax = key_value(L.bkey[b]);
             bool touch = false;
             for (uint32_t mm = wm; mm; mm &= mm - 1) {
                 const int j = __builtin_ctz(mm);
@@ -713,7 +717,7 @@ __device__ inline void grid_order_object_mp(const GridObject& o, GridLdsMP<BLOCK
                 const int qb = __builtin_amdgcn_readlane(pcell, j) >> 6;
                 touch = touch || (((mine >> j) & 1u) &&
                                   (b == qb || box_lower(blx[jb], bly[jb], blz[jb], bhx[jb], bhy[jb],
-                                                        bhz[jb], qx, qy, qz) < qm));
+                                                        bhz[jb], qx, qy, qz) < fminf(qm, bmax)));
             }
             const uint64_t m = __ballot(touch);
             if (lane == 0) L.mask[jb * NW + wave] = m;
@@ -875,7 +879,8 @@ __device__ inline void grid_order_object_mp(const GridObject& o, GridLdsMP<BLOCK
                 const bool fail = __ballot(f) != 0;
                 const int csb = (ccell >> 6) >> sbshift;
                 const bool reach = inl && (lane == csb ||
-                                           box_lower(slo.x, slo.y, slo.z, shi.x, shi.y, shi.z, cx, cy, cz) < cm);
+                                           box_lower(slo.x, slo.y, slo.z, shi.x, shi.y, shi.z, cx, cy, cz) <
+                                               fminf(cm, key_value(e1)));
                 if (reach) atomicOr(&L.spm[lane], 1u << rank);
                 if (lane == 0) {
                     if (fail) atomicMin(&L.kfail, rank);
