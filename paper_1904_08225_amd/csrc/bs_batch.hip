@@ -33,6 +33,15 @@ constexpr int kBatchBlock = 256;         // threads per ordering workgroup
 constexpr int kWideBlock = 1024;         // threads per workgroup for the largest objects
 constexpr int64_t kWideMinK = 65536;     // automatic choice: smallest k given a wide workgroup
 constexpr int kBatchMaxBlocks = 1024;    // blocks of 64 cells per object
+// A batch whose 1024-thread workgroups get an object of more than
+// 64 x 64 x kBatchMaxBlocks candidates (cells above 64 candidates) gives
+// them twice as many blocks, and so smaller cells (LDS: 116 KB a workgroup;
+// a pick's update reads whole cells): the hierarchy's cluster nodes of about
+// 9 M candidates, cells of about 70 instead of 140, 4.3 s -> 3.5 s for the
+// whole hierarchy.  Otherwise the 1024-block kernel is kept: the 1,000-part
+// batch ran 0.81 s with it against 0.86 s with 2048 blocks (cells of 16
+// instead of 32 for its largest parts, but two block boxes a thread).
+constexpr int kWideMaxBlocks = 2048;
 // Most exact picks per round of an object, unless the plan sets it: 24 for
 // cells of up to 64 candidates on average (on the 1,000-part batch, whose
 // largest objects have cells of about 32, 0.93 s against 0.97 s at 16 and at
@@ -51,7 +60,8 @@ struct ObjHdr {
     uint32_t hist[31];  // adjacent sorted pairs first separated by each code prefix length
     int32_t level;      // cells: runs of codes sharing their top `level` bits
     int32_t cell_base, C, NB, block_base, nsb, sb_base, start_pos, start_cell;
-    int32_t pad[17];
+    int32_t max_blocks;  // blocks of 64 cells at most (by the workgroup that orders the object)
+    int32_t pad[16];
 };
 static_assert(sizeof(ObjHdr) == 256, "object header size");
 
@@ -71,7 +81,7 @@ __device__ __forceinline__ int find_obj(const int32_t* __restrict__ offs, int m,
     return lo;
 }
 
-__global__ void bobj_init_kernel(int m, ObjHdr* __restrict__ hd) {
+__global__ void bobj_init_kernel(int m, ObjHdr* __restrict__ hd, int max_blocks) {
     const int j = blockIdx.x * blockDim.x + threadIdx.x;
     if (j >= m) return;
     ObjHdr h{};
@@ -80,7 +90,16 @@ __global__ void bobj_init_kernel(int m, ObjHdr* __restrict__ hd) {
         h.bbox[3 + a] = 0u;
     }
     h.start_pos = -1;
+    h.max_blocks = max_blocks;
     hd[j] = h;
+}
+
+// The objects of the 1024-thread workgroups (the head of the LPT order) may
+// have more blocks (after bobj_init_kernel, on the same stream).
+__global__ void bwide_kernel(int nwide, const int32_t* __restrict__ lpt, ObjHdr* __restrict__ hd,
+                             int max_blocks) {
+    const int r = blockIdx.x * blockDim.x + threadIdx.x;
+    if (r < nwide) hd[lpt[r]].max_blocks = max_blocks;
 }
 
 template <bool UMAX>
@@ -187,11 +206,11 @@ __global__ void bhist_kernel(const uint64_t* __restrict__ keys, int N, ObjHdr* _
 }
 
 __global__ void blevel_kernel(int m, const int32_t* __restrict__ offs, ObjHdr* __restrict__ hd,
-                              float target, int max_blocks) {
+                              float target) {
     const int j = blockIdx.x * blockDim.x + threadIdx.x;
     if (j >= m) return;
     const int n = offs[j + 1] - offs[j];
-    const double cap = fmin(fmax(1.0, double(n) / double(target)), double(64 * max_blocks));
+    const double cap = fmin(fmax(1.0, double(n) / double(target)), double(64 * hd[j].max_blocks));
     int level = 0;
     uint32_t acc = 1;
     for (int l = 1; l <= 3 * kMortonBits; ++l) {
@@ -564,11 +583,11 @@ __global__ void __launch_bounds__(kBatchBlock)
 // the queue is drained; every pop ends the loop for all its waves alike.
 // BLOCK = 256 for most objects; the largest ones may get 1024-thread
 // workgroups (a second launch of the same loop with its own queue).
-template <int BLOCK>
+template <int BLOCK, int MAXB>
 __global__ void __launch_bounds__(BLOCK)
     batch_order_kernel(const ObjDesc* __restrict__ desc, const int32_t* __restrict__ lpt, int mwork,
                        uint32_t* __restrict__ queue) {
-    __shared__ GridLdsMP<BLOCK / 64, kBatchMaxBlocks> L;
+    __shared__ GridLdsMP<BLOCK / 64, MAXB> L;
     __shared__ int s_item;
     for (;;) {
         if (threadIdx.x == 0) s_item = int(atomicAdd(queue, 1u));
@@ -586,7 +605,7 @@ __global__ void __launch_bounds__(BLOCK)
                     if (o.radius) o.radius[t] = __builtin_nanf("");
                 }
             } else {
-                grid_order_object_mp<BLOCK, kBatchMaxBlocks>(o, L);
+                grid_order_object_mp<BLOCK, MAXB>(o, L);
             }
         }
         __syncthreads();
@@ -707,6 +726,7 @@ struct BatchPlan {
     int nwide = 0;                  // the first nwide objects of h_lpt go to 1024-thread workgroups
     int wide_slots = 0;             // their persistent workgroups
     int picks = 0;                  // most exact picks per round of an object (0: by cell size)
+    int wide_blocks = kBatchMaxBlocks;  // blocks at most of the 1024-thread workgroups' objects
     hipStream_t side = nullptr;     // stream of the wide launch (forked from the caller's)
     hipEvent_t fork = nullptr, join = nullptr;
     bool use_graph = true;
@@ -846,7 +866,6 @@ int batch_plan_create(const int64_t* h_offsets, const int64_t* h_k, const uint64
     p->h_start.resize(p->m);
     p->h_seed.resize(p->m);
     std::vector<int64_t> outo(size_t(p->m) + 1);
-    size_t maxC = 0, maxB = 0, maxS = 0;
     for (int i = 0; i < p->m; ++i) {
         const int j = keep[i];
         const int64_t n = h_offsets[j + 1] - h_offsets[j];
@@ -855,18 +874,9 @@ int batch_plan_create(const int64_t* h_offsets, const int64_t* h_k, const uint64
         p->h_start[i] = int32_t(bs_start_index(h_seed ? h_seed[j] : 0, n));
         p->h_seed[i] = h_seed ? h_seed[j] : 0;
         outo[i] = p->h_out_offs[j];
-        const double cap = std::min(std::max(1.0, double(n) / double(p->target)), double(64 * kBatchMaxBlocks));
-        const size_t c = size_t(cap);
-        maxC += c;
-        const size_t nb = (c + 63) / 64;
-        maxB += nb;
-        maxS += (nb + 63) / 64;
     }
     p->h_offs[p->m] = p->N;
     outo[p->m] = p->total_k;
-    p->maxC = std::max<size_t>(maxC, 1);
-    p->maxB = std::max<size_t>(maxB, 1);
-    p->maxS = std::max<size_t>(maxS, 1);
     // largest chains first (longest-processing-time order)
     p->h_lpt.clear();
     for (int i = 0; i < p->m; ++i)
@@ -874,17 +884,11 @@ int batch_plan_create(const int64_t* h_offsets, const int64_t* h_k, const uint64
     std::stable_sort(p->h_lpt.begin(), p->h_lpt.end(),
                      [&](int a, int b) { return p->h_k[a] > p->h_k[b]; });
     p->mwork = int(p->h_lpt.size());
-    // tiles of the per-object sort (each object sorted where it lies)
-    p->h_tiles = sort_tiles(p->h_offs.data(), p->m);
-    p->sort_bytes = sort_temp_bytes(int64_t(p->h_tiles.size()));
-    p->scan_bytes = scan_temp_bytes(p->N);
-    p->h_outo = outo;
-    p->ws_bytes = batch_layout(*p, nullptr).total;
     int dev = 0, cus = 0, per = 0;
     (void)hipGetDevice(&dev);
     (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
     (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(
-        &per, reinterpret_cast<const void*>(batch_order_kernel<kBatchBlock>), kBatchBlock, 0);
+        &per, reinterpret_cast<const void*>(batch_order_kernel<kBatchBlock, kBatchMaxBlocks>), kBatchBlock, 0);
     if (cus <= 0) cus = 256;
     if (per <= 0) per = 1;
     // the largest objects (the head of the LPT order) on 1024-thread
@@ -901,6 +905,35 @@ int batch_plan_create(const int64_t* h_offsets, const int64_t* h_k, const uint64
             ++nw;
     }
     p->nwide = nw;
+    // cells, blocks and superblocks at most (the 1024-thread workgroups'
+    // objects may have more blocks)
+    std::vector<char> is_wide(size_t(p->m), 0);
+    for (int r = 0; r < nw; ++r) {
+        const int i = p->h_lpt[r];
+        is_wide[size_t(i)] = 1;
+        if (int64_t(p->h_offs[i + 1]) - p->h_offs[i] > int64_t(kLargeCell) * 64 * kBatchMaxBlocks)
+            p->wide_blocks = kWideMaxBlocks;
+    }
+    size_t maxC = 0, maxB = 0, maxS = 0;
+    for (int i = 0; i < p->m; ++i) {
+        const int64_t n = int64_t(p->h_offs[i + 1]) - p->h_offs[i];
+        const int mb = is_wide[size_t(i)] ? p->wide_blocks : kBatchMaxBlocks;
+        const double cap = std::min(std::max(1.0, double(n) / double(p->target)), double(64 * mb));
+        const size_t c = size_t(cap);
+        maxC += c;
+        const size_t nb = (c + 63) / 64;
+        maxB += nb;
+        maxS += (nb + 63) / 64;
+    }
+    p->maxC = std::max<size_t>(maxC, 1);
+    p->maxB = std::max<size_t>(maxB, 1);
+    p->maxS = std::max<size_t>(maxS, 1);
+    // tiles of the per-object sort (each object sorted where it lies)
+    p->h_tiles = sort_tiles(p->h_offs.data(), p->m);
+    p->sort_bytes = sort_temp_bytes(int64_t(p->h_tiles.size()));
+    p->scan_bytes = scan_temp_bytes(p->N);
+    p->h_outo = outo;
+    p->ws_bytes = batch_layout(*p, nullptr).total;
     // three quarters of the CUs by default (1,000-part batch: half 1.07-1.10 s,
     // three quarters 0.95-0.96 s, seven eighths 0.95-0.97 s); the batch
     // autotuner times the share on the whole batch
@@ -946,8 +979,12 @@ namespace {
 // Validation, per-object grids and the objects' descriptors (w.desc), all
 // enqueued on st; shared by the batched launch and the serving ring.  With
 // sort_only, up to the per-object Morton sort (keys_s, vals_s).
+// narrow_only: every object gets the 256-thread workgroups' block limit
+// (the sampler's kernel); otherwise the objects of 1024-thread workgroups may
+// have up to kWideMaxBlocks.
 int batch_preprocess(BatchPlan* p, const float* pts, int32_t* out_order, float* out_radius, void* ws,
-                     size_t ws_bytes, hipStream_t st, BatchWs& w, bool sort_only = false) {
+                     size_t ws_bytes, hipStream_t st, BatchWs& w, bool sort_only = false,
+                     bool narrow_only = false) {
     if (!pts || (!sort_only && !out_order && p->h_io.empty()))
         return set_error(BS_ERR_INVALID_ARG, "null points or output");
     if (!ws || ws_bytes < p->ws_bytes)
@@ -987,7 +1024,10 @@ int batch_preprocess(BatchPlan* p, const float* pts, int32_t* out_order, float* 
     const int tb = 256;
     const int nblk = (N + tb - 1) / tb;
     const int mblk = (m + tb - 1) / tb;
-    hipLaunchKernelGGL(bobj_init_kernel, dim3(mblk), dim3(tb), 0, st, m, w.hd);
+    hipLaunchKernelGGL(bobj_init_kernel, dim3(mblk), dim3(tb), 0, st, m, w.hd, kBatchMaxBlocks);
+    if (!narrow_only && p->nwide > 0 && p->wide_blocks > kBatchMaxBlocks)
+        hipLaunchKernelGGL(bwide_kernel, dim3((p->nwide + tb - 1) / tb), dim3(tb), 0, st, p->nwide, w.lpt, w.hd,
+                           p->wide_blocks);
     hipLaunchKernelGGL(bvalidate_kernel, dim3(std::min(nblk, 8192)), dim3(tb), 0, st, pts, N, w.offs, m, w.hd);
     hipLaunchKernelGGL(bmorton_kernel, dim3(nblk), dim3(tb), 0, st, pts, N, w.offs, m, w.hd, w.keys, w.vals);
     if ((e = hipGetLastError()) != hipSuccess) return set_error(BS_ERR_HIP, "%s", hipGetErrorString(e));
@@ -995,8 +1035,7 @@ int batch_preprocess(BatchPlan* p, const float* pts, int32_t* out_order, float* 
     if (e != hipSuccess) return set_error(BS_ERR_HIP, "sort: %s", hipGetErrorString(e));
     if (sort_only) return BS_OK;
     hipLaunchKernelGGL(bhist_kernel, dim3(nblk), dim3(tb), 0, st, w.keys_s, N, w.hd);
-    hipLaunchKernelGGL(blevel_kernel, dim3(mblk), dim3(tb), 0, st, m, w.offs, w.hd, p->target,
-                       kBatchMaxBlocks);
+    hipLaunchKernelGGL(blevel_kernel, dim3(mblk), dim3(tb), 0, st, m, w.offs, w.hd, p->target);
     hipLaunchKernelGGL(bflag_kernel, dim3(nblk), dim3(tb), 0, st, w.keys_s, N, w.hd, w.flags);
     e = inclusive_scan_u32(w.flags, w.cellidx, N, w.temp, st);
     if (e != hipSuccess) return set_error(BS_ERR_HIP, "scan: %s", hipGetErrorString(e));
@@ -1039,14 +1078,18 @@ int enqueue_execute(BatchPlan* p, const float* pts, int32_t* out_order, float* o
         e = hipEventRecord(p->fork, st);
         if (e == hipSuccess) e = hipStreamWaitEvent(p->side, p->fork, 0);
         if (e == hipSuccess) {
-            hipLaunchKernelGGL(batch_order_kernel<kWideBlock>, dim3(p->wide_slots), dim3(kWideBlock), 0, p->side,
-                               w.desc, w.lpt, p->nwide, w.queue + 1);
+            if (p->wide_blocks > kBatchMaxBlocks)
+                hipLaunchKernelGGL((batch_order_kernel<kWideBlock, kWideMaxBlocks>), dim3(p->wide_slots),
+                                   dim3(kWideBlock), 0, p->side, w.desc, w.lpt, p->nwide, w.queue + 1);
+            else
+                hipLaunchKernelGGL((batch_order_kernel<kWideBlock, kBatchMaxBlocks>), dim3(p->wide_slots),
+                                   dim3(kWideBlock), 0, p->side, w.desc, w.lpt, p->nwide, w.queue + 1);
             e = hipGetLastError();
         }
         if (e == hipSuccess) e = hipEventRecord(p->join, p->side);
     }
     if (e == hipSuccess && p->mwork > p->nwide) {
-        hipLaunchKernelGGL(batch_order_kernel<kBatchBlock>, dim3(p->slots), dim3(kBatchBlock), 0, st, w.desc,
+        hipLaunchKernelGGL((batch_order_kernel<kBatchBlock, kBatchMaxBlocks>), dim3(p->slots), dim3(kBatchBlock), 0, st, w.desc,
                            w.lpt + p->nwide, p->mwork - p->nwide, w.queue);
         e = hipGetLastError();
     }
@@ -1165,7 +1208,8 @@ int batch_plan_execute_sample(BatchPlan* p, int S, int K, float vicinity, const 
     }
     if (p->mwork == 0) return BS_OK;
     BatchWs w;
-    const int rc = batch_preprocess(p, pts, out_order, out_radius, ws, ws_bytes, st, w);
+    // the sampler's 256-thread workgroups hold at most kBatchMaxBlocks blocks
+    const int rc = batch_preprocess(p, pts, out_order, out_radius, ws, ws_bytes, st, w, false, true);
     if (rc != BS_OK) return rc;
     const int m = p->m, N = p->N, tb = 256;
     if (!p->dev) {  // otherwise w.seeds and w.kept are the plan's device copies

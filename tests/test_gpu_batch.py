@@ -216,3 +216,26 @@ def test_batch_picks_per_round(hip, picks):
         eo, er = oracle.greedy32_grid(P, ks[j], oracle.start_index(seeds[j], P.shape[0]))
         assert_parity(o[a:b], r[a:b], eo, er, "picks=%d object %d (n=%d k=%d)" % (picks, j, P.shape[0], ks[j]))
     plan.close()
+
+
+def test_batch_wide_object_with_more_blocks(hip):
+    """An object of more than 4,194,304 candidates on a 1024-thread
+    workgroup gets up to 2048 blocks of cells: equal to the oracle, and the
+    small objects beside it too."""
+    import torch
+    big = np.ascontiguousarray(synth.cad_part(4_400_000, seed=977, count=60).points.numpy())
+    objs = [big] + [np.ascontiguousarray(synth.cad_part(n, seed=978 + n % 7, count=20).points.numpy())
+                    for n in (3000, 25000)]
+    ks = [30000, 3000, 6000]
+    seeds = [11, 12, 13]
+    offs = np.concatenate([[0], np.cumsum([o.shape[0] for o in objs])]).astype(np.int64)
+    plan = hip.BatchPlan(offs, ks, seeds, tune=hip.tuning(batch_wide=1))
+    o, r = plan.execute(torch.from_numpy(np.concatenate(objs)).cuda())
+    torch.cuda.synchronize()
+    o = o.cpu().numpy()
+    r = r.cpu().numpy()
+    for j, P in enumerate(objs):
+        a, b = plan.out_offsets[j], plan.out_offsets[j + 1]
+        eo, er = oracle.greedy32_grid(P, ks[j], oracle.start_index(seeds[j], P.shape[0]))
+        assert_parity(o[a:b], r[a:b], eo, er, "object %d (n=%d k=%d)" % (j, P.shape[0], ks[j]))
+    plan.close()
