@@ -22,7 +22,9 @@
 // m_i <- min(m_i, d2(p_i, q_1), ..., d2(p_i, q_K)), which equals the
 // sequential updates because min is exact and order-free; a candidate or box
 // is skipped for pick q_j when its binary32 box lower bound is >= m(q_j),
-// which bounds its value at step j (see bs_grid.hip).
+// which bounds its value at step j (see bs_grid.hip), or >= the largest m
+// the box held before the round (its best key's value): either way no m in
+// it can drop.
 //
 // Levels: cells keep their best key, its position/coordinates and their
 // exact second key (cdyn); blocks of 64 cells keep best key, coordinates,

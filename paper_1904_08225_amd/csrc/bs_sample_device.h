@@ -7,9 +7,10 @@
 // far.  Its "distance to all chosen surfels" is each candidate's m (squared
 // distance to the nearest chosen surfel), kept exact for every candidate the
 // same way as the grid-pruned exact ordering keeps it: a pick lowers m only
-// inside its reach, and a cell whose box lower bound is at least the largest
-// m still held anywhere (the hierarchy's top key) cannot contain a candidate
-// the pick lowers.  So a sample member's m is read from memory when it is
+// inside its reach, and a superblock, block or cell whose box lower bound
+// from the pick is at least the largest m it holds (its best key's value)
+// cannot contain a candidate the pick lowers.  So a sample member's m is
+// read from memory when it is
 // drawn, and every later pick of the same round is folded into the sampled
 // values in registers (min is exact and order-free).  Removals (picks, and
 // sample members near the chosen surfels when asked) mark m = -1 and
