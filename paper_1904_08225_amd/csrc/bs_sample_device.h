@@ -400,6 +400,7 @@ __device__ inline void sample_object(const GridObject& o, const SampleSpec& sp, 
 
     const int S = sp.S;
     const bool has_slot = tid < S;
+    const int slot_waves = (S + 63) / 64;  // wavefronts holding sample slots (S <= kSampleMaxSlots)
     int t = 1;
     int remaining = sp.n - 1;
     uint32_t round = 0;
@@ -457,24 +458,27 @@ __device__ inline void sample_object(const GridObject& o, const SampleSpec& sp, 
                 cy = win.y;
                 cz = win.z;
             } else {
-                // the largest sampled key: per wavefront, then over the
-                // wavefronts' entries (lanes holding the same key hold the
-                // same candidate, so any of them may write its data)
-                const uint64_t mine = live ? make_key(val, pid) : 0ull;
-                const uint64_t wk = wave_max_key(mine);
+                // the largest sampled key: per wavefront holding slots, then
+                // over those wavefronts' entries (lanes holding the same key
+                // hold the same candidate, so any of them may write its data);
+                // the other wavefronts only read the result
                 const int par = int(sel & 1u);
                 ++sel;
-                if (lane == 0) SL.skey[par][wave] = wk;
-                if (wk != 0 && mine == wk) {
-                    SL.swin[par][wave] = make_float4(px, py, pz, __int_as_float(ppos));
-                    SL.scell[par][wave] = pcell;
+                if (wave < slot_waves) {
+                    const uint64_t mine = live ? make_key(val, pid) : 0ull;
+                    const uint64_t wk = wave_max_key(mine);
+                    if (lane == 0) SL.skey[par][wave] = wk;
+                    if (wk != 0 && mine == wk) {
+                        SL.swin[par][wave] = make_float4(px, py, pz, __int_as_float(ppos));
+                        SL.scell[par][wave] = pcell;
+                    }
                 }
                 barrier_lds();  // the emitted picks' stores need not complete here
                 best = 0;
                 int bw = 0;
 #pragma unroll
-                for (int w = 0; w < NW; ++w) {
-                    const uint64_t kw = SL.skey[par][w];
+                for (int w = 0; w < kSampleMaxSlots / 64 && w < NW; ++w) {
+                    const uint64_t kw = w < slot_waves ? SL.skey[par][w] : 0ull;
                     bw = kw > best ? w : bw;
                     best = kw > best ? kw : best;
                 }
