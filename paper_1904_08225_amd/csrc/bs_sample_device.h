@@ -113,17 +113,33 @@ struct SampleLds {
 // picks taken, and rewrites the hit cells' best keys and the block's best in
 // LDS.  The hit cells each get an aligned group of lanes, as in
 // process_block.  Wave-local: no barrier.
+// Cell records of one block as one wavefront holds them (lane = cell).
+struct SampleCells {
+    float4 lo, hi;  // cell box, first member / member count
+    uint4 d0, d1;   // best key, its position; its coordinates
+};
+
+__device__ __forceinline__ SampleCells sample_cells_load(const GridObject& o, int b) {
+    const int cell = b * 64 + int(threadIdx.x & 63);
+    const int ci = cell < o.C ? cell : o.C - 1;
+    SampleCells r;
+    r.lo = o.cstat[2 * ci];
+    r.hi = o.cstat[2 * ci + 1];
+    r.d0 = o.cdyn[2 * ci];
+    r.d1 = o.cdyn[2 * ci + 1];
+    return r;
+}
+
 template <int NW, int MAXB>
 __device__ inline void sample_block_update(const GridObject& o, GridLds<NW, MAXB>& L, SampleLds<NW>& SL, int b,
-                                           uint32_t pm) {
+                                           uint32_t pm, const SampleCells& rec) {
     const int lane = threadIdx.x & 63;
     const int wave = threadIdx.x >> 6;
     WaveScratch& W = L.ws[wave];
     const int cell = b * 64 + lane;
     const bool valid = cell < o.C;
-    const int ci = valid ? cell : o.C - 1;
-    const float4 lo = o.cstat[2 * ci], hi = o.cstat[2 * ci + 1];
-    const uint4 d0 = o.cdyn[2 * ci], d1 = o.cdyn[2 * ci + 1];
+    const float4 lo = rec.lo, hi = rec.hi;
+    const uint4 d0 = rec.d0, d1 = rec.d1;
     uint64_t ckey = valid ? ((uint64_t(d0.y) << 32) | d0.x) : 0ull;
     float4 cwin = make_float4(__uint_as_float(d1.x), __uint_as_float(d1.y), __uint_as_float(d1.z),
                               __int_as_float(int(d0.z)));
@@ -366,7 +382,11 @@ __device__ inline void sample_object(const GridObject& o, const SampleSpec& sp, 
         barrier_lds();
         const uint64_t mword = lane < nsb ? L.mask[lane] : 0ull;
         const uint64_t nz = __ballot(mword != 0);
-        int rank = 0;
+        // this wavefront's blocks (ranks wave, wave + NW, ...): the next
+        // one's cell records load while the current one is updated
+        int rank = 0, pb = -1;
+        uint32_t ppm = 0u;
+        SampleCells cur;
         for (uint64_t zs = nz; zs;) {
             const int mi = __builtin_ctzll(zs);
             zs &= zs - 1;
@@ -376,10 +396,17 @@ __device__ inline void sample_object(const GridObject& o, const SampleSpec& sp, 
             for (uint64_t mk = (uint64_t(mhi) << 32) | mlo; mk;) {
                 const int b = mi * 64 + __builtin_ctzll(mk);
                 mk &= mk - 1;
-                if (rank % NW == wave) sample_block_update<NW, MAXB>(o, L, SL, b, bm);
+                if (rank % NW == wave) {
+                    const SampleCells nxt = sample_cells_load(o, b);
+                    if (pb >= 0) sample_block_update<NW, MAXB>(o, L, SL, pb, ppm, cur);
+                    cur = nxt;
+                    pb = b;
+                    ppm = bm;
+                }
                 ++rank;
             }
         }
+        if (pb >= 0) sample_block_update<NW, MAXB>(o, L, SL, pb, ppm, cur);
         __syncthreads();  // also orders the member and cell stores for later passes and draws
         for (uint64_t zs = nz; zs;) {
             const int mi = __builtin_ctzll(zs);
