@@ -43,11 +43,11 @@ constexpr int kBatchMaxBlocks = 1024;    // blocks of 64 cells per object
 // instead of 32 for its largest parts, but two block boxes a thread).
 constexpr int kWideMaxBlocks = 2048;
 // Most exact picks per round of an object, unless the plan sets it: 24 for
-// cells of up to 64 candidates on average (on the 1,000-part batch, whose
-// largest objects have cells of about 32, 0.93 s against 0.97 s at 16 and at
-// 32), 16 for larger cells (a pick's update of a large cell costs more than
-// a round's fixed cost; the hierarchy's cluster nodes, cells of about 140:
-// 6.1 s at 16 against 6.5 s at 24).
+// cells of up to 64 candidates on average (the 1,000-part batch, whose
+// largest objects have cells of about 32: 0.86, 0.83, 0.81, 0.82 and 0.85 s
+// at 16, 20, 24, 28 and 32), 16 for larger cells (a pick's update of a large
+// cell costs more than a round's fixed cost; the hierarchy with its cluster
+// nodes' cells of about 140: 4.3 s at 16 against 4.7 s at 24).
 constexpr int kBatchPicks = 24;
 constexpr int kBatchPicksLargeCells = 16;
 constexpr int kLargeCell = 64;
