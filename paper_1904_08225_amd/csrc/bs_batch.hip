@@ -548,12 +548,14 @@ __global__ void fill_i32_kernel(int32_t* p, int n, int32_t v) {
 }
 
 // Persistent work queue of sampler runs (largest k first), one object per
-// 256-thread workgroup.
-__global__ void __launch_bounds__(kBatchBlock)
+// 256-thread workgroup; the batch's largest objects may get 1024-thread
+// workgroups (a second launch with its own queue), as in the exact ordering.
+template <int BLOCK>
+__global__ void __launch_bounds__(BLOCK)
     sample_batch_kernel(const ObjDesc* __restrict__ desc, const SampleSpec* __restrict__ sdesc,
                         const int32_t* __restrict__ lpt, int mwork, uint32_t* __restrict__ queue) {
-    __shared__ GridLds<kBatchBlock / 64, kBatchMaxBlocks> L;
-    __shared__ SampleLds<kBatchBlock / 64> SL;
+    __shared__ GridLds<BLOCK / 64, kBatchMaxBlocks> L;
+    __shared__ SampleLds<BLOCK / 64> SL;
     __shared__ int s_item;
     for (;;) {
         if (threadIdx.x == 0) s_item = int(atomicAdd(queue, 1u));
@@ -566,13 +568,13 @@ __global__ void __launch_bounds__(kBatchBlock)
         const SampleSpec sp = sdesc[j];
         if (o.k > 0) {
             if (desc[j].nonfinite) {
-                for (int t = threadIdx.x; t < o.k; t += kBatchBlock) {
+                for (int t = threadIdx.x; t < o.k; t += BLOCK) {
                     o.order[t] = -1;
                     if (o.radius) o.radius[t] = __builtin_nanf("");
                 }
                 if (threadIdx.x == 0 && sp.count) *sp.count = 0;
             } else {
-                sample_object<kBatchBlock, kBatchMaxBlocks>(o, sp, L, SL);
+                sample_object<BLOCK, kBatchMaxBlocks>(o, sp, L, SL);
             }
         }
         __syncthreads();
@@ -1225,14 +1227,32 @@ int batch_plan_execute_sample(BatchPlan* p, int S, int K, float vicinity, const 
     int dev = 0, cus = 0, per = 0;
     (void)hipGetDevice(&dev);
     (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
-    (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, reinterpret_cast<const void*>(sample_batch_kernel),
-                                                       kBatchBlock, 0);
+    (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(
+        &per, reinterpret_cast<const void*>(sample_batch_kernel<kBatchBlock>), kBatchBlock, 0);
     if (cus <= 0) cus = 256;
     if (per <= 0) per = 1;
-    const int slots = std::max(1, std::min(cus * per, p->mwork));
-    hipLaunchKernelGGL(sample_batch_kernel, dim3(slots), dim3(kBatchBlock), 0, st, w.desc, w.sdesc, w.lpt, p->mwork,
-                       w.queue);
-    if ((e = hipGetLastError()) != hipSuccess) return set_error(BS_ERR_HIP, "sampler launch: %s", hipGetErrorString(e));
+    if ((e = hipGetLastError()) != hipSuccess) return set_error(BS_ERR_HIP, "sampler setup: %s", hipGetErrorString(e));
+    // the largest objects on 1024-thread workgroups, launched first on the
+    // plan's side stream (as the exact ordering does), the others beside
+    const int nw = p->nwide;
+    if (nw > 0) {
+        e = hipEventRecord(p->fork, st);
+        if (e == hipSuccess) e = hipStreamWaitEvent(p->side, p->fork, 0);
+        if (e == hipSuccess) {
+            hipLaunchKernelGGL(sample_batch_kernel<kWideBlock>, dim3(p->wide_slots), dim3(kWideBlock), 0, p->side,
+                               w.desc, w.sdesc, w.lpt, nw, w.queue + 1);
+            e = hipGetLastError();
+        }
+        if (e == hipSuccess) e = hipEventRecord(p->join, p->side);
+    }
+    if (e == hipSuccess && p->mwork > nw) {
+        const int slots = std::max(1, std::min((cus - (nw > 0 ? p->wide_slots : 0)) * per, p->mwork - nw));
+        hipLaunchKernelGGL(sample_batch_kernel<kBatchBlock>, dim3(slots), dim3(kBatchBlock), 0, st, w.desc, w.sdesc,
+                           w.lpt + nw, p->mwork - nw, w.queue);
+        e = hipGetLastError();
+    }
+    if (e == hipSuccess && nw > 0) e = hipStreamWaitEvent(st, p->join, 0);
+    if (e != hipSuccess) return set_error(BS_ERR_HIP, "sampler launch: %s", hipGetErrorString(e));
     return BS_OK;
 }
 
