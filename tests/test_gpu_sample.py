@@ -151,3 +151,27 @@ def test_prefix_nn_matches_oracle(hip):
     bad = od.clone()
     bad[3] = -1
     assert np.isnan(hip.prefix_nn(pts, bad, 100).cpu().numpy()).all()
+
+
+def test_sampler_batch_wide_workgroups(hip):
+    """The batch's largest objects sampled by 1024-thread workgroups beside
+    the 256-thread ones (forced for two objects): every object equals the
+    sampler oracle."""
+    import torch
+    sizes = [40000, 60000, 3000, 500, 9000]
+    ks = [10000, 15000, 3000, 100, 2000]
+    seeds = [41, 42, 43, 44, 45]
+    pts, offs = synth.cad_parts_batch(sizes, seed=37, count=40, device="cuda")
+    P = pts.cpu().numpy()
+    expect = [oracle.sample32(P[offs[j]:offs[j + 1]], ks[j], seeds[j], oracle.start_index(seeds[j], sizes[j]))
+              for j in range(len(sizes))]
+    plan = hip.BatchPlan(offs, ks, seeds, tune=hip.tuning(batch_wide=2))
+    for rep in range(2):
+        o, r, c = plan.execute_sample(pts)
+        torch.cuda.synchronize()
+        o, r, c = o.cpu().numpy(), r.cpu().numpy(), c.cpu().numpy()
+        for j in range(len(sizes)):
+            a, b = plan.out_offsets[j], plan.out_offsets[j + 1]
+            eo, er, ec = expect[j]
+            _same(o[a:b], r[a:b], int(c[j]), eo, er, ec, "object %d rep %d" % (j, rep))
+    plan.close()
