@@ -464,7 +464,7 @@ def bench_batched(bs, torch, np, cpu=True):
     log("batched sampler: %.3f s for sum k = %d" % (sample_s, int(sc.sum())))
     sampler_rec = {"seconds": sample_s, "ordered_surfels_per_s": int(sc.sum()) / sample_s,
                    "params": {"sample_size": 200, "growth_rounds": 500, "vicinity": 0.0},
-                   "kernel": "sample_batch_kernel: 256-thread workgroups, objects largest k first"}
+                   "kernel": "sample_batch_kernel: objects largest k first, the longest chains on 1024-thread workgroups, the others on 256-thread ones"}
     del so, sr, sc
     # plain loop: one ordering launch per object, sampled across the size range
     order_idx = sorted(range(m), key=lambda j: sizes[j])
