@@ -61,7 +61,8 @@ struct ObjHdr {
     int32_t level;      // cells: runs of codes sharing their top `level` bits
     int32_t cell_base, C, NB, block_base, nsb, sb_base, start_pos, start_cell;
     int32_t max_blocks;  // blocks of 64 cells at most (by the workgroup that orders the object)
-    int32_t pad[16];
+    int32_t split;       // cells split into runs of at most `split` candidates (0: not split)
+    int32_t pad[15];
 };
 static_assert(sizeof(ObjHdr) == 256, "object header size");
 
@@ -205,12 +206,19 @@ __global__ void bhist_kernel(const uint64_t* __restrict__ keys, int N, ObjHdr* _
     if (threadIdx.x <= kBits && h[threadIdx.x]) atomicAdd(&hd[obj0].hist[threadIdx.x], h[threadIdx.x]);
 }
 
+// Cells at most of object j (the workspace is sized for it).
+__device__ __forceinline__ double cell_cap(int n, float target, int max_blocks) {
+    return fmin(fmax(1.0, double(n) / double(target)), double(64 * max_blocks));
+}
+
+// halve: leave room for splitting cells (the level takes at most half the cells)
 __global__ void blevel_kernel(int m, const int32_t* __restrict__ offs, ObjHdr* __restrict__ hd,
-                              float target) {
+                              float target, int halve) {
     const int j = blockIdx.x * blockDim.x + threadIdx.x;
     if (j >= m) return;
     const int n = offs[j + 1] - offs[j];
-    const double cap = fmin(fmax(1.0, double(n) / double(target)), double(64 * hd[j].max_blocks));
+    const double full = cell_cap(n, target, hd[j].max_blocks);
+    const double cap = halve ? fmax(1.0, floor(full / 2.0)) : full;
     int level = 0;
     uint32_t acc = 1;
     for (int l = 1; l <= 3 * kMortonBits; ++l) {
@@ -234,6 +242,40 @@ __global__ void bflag_kernel(const uint64_t* __restrict__ keys, int N, const Obj
     const int s = 3 * kMortonBits - hd[obj].level;
     const uint32_t ca = uint32_t(a) & ((1u << kObjBits) - 1u), cb = uint32_t(b) & ((1u << kObjBits) - 1u);
     flags[i] = ((a >> kObjBits) != (b >> kObjBits) || (ca >> s) != (cb >> s)) ? 1u : 0u;
+}
+
+// Splitting uneven cells (candidate sets made of compact groups, such as a
+// hierarchy node's children's surfels, give Morton-prefix cells far above
+// the mean where the groups lie): every run of a cell's candidates is cut
+// into pieces of at most S, with S per object the smallest that keeps the
+// cells within the object's limit.  Cells stay runs of consecutive sorted
+// candidates; their boxes come from their members.
+__global__ void bcstart_kernel(const uint32_t* __restrict__ flags, const uint32_t* __restrict__ cellidx, int N,
+                               int32_t* __restrict__ cstart) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < N && flags[i]) cstart[cellidx[i] - 1] = i;
+}
+
+__global__ void bsplit_prep_kernel(int m, const int32_t* __restrict__ offs, const uint32_t* __restrict__ cellidx,
+                                   ObjHdr* __restrict__ hd, float target) {
+    const int j = blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= m) return;
+    const int a = offs[j], b = offs[j + 1], n = b - a;
+    hd[j].split = 0;
+    if (n <= 0) return;
+    const int cells = int(cellidx[b - 1]) - (a > 0 ? int(cellidx[a - 1]) : 0);
+    const int cap = int(cell_cap(n, target, hd[j].max_blocks));
+    // pieces beyond the first of each cell number at most n / S <= cap - cells
+    if (cap > cells) hd[j].split = max(1, (n + (cap - cells) - 1) / (cap - cells));
+}
+
+__global__ void bsplit_kernel(const uint64_t* __restrict__ keys, const uint32_t* __restrict__ cellidx, int N,
+                              const int32_t* __restrict__ cstart, const ObjHdr* __restrict__ hd,
+                              uint32_t* __restrict__ flags) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= N) return;
+    const int S = hd[int(keys[i] >> kObjBits)].split;
+    if (S > 0 && (i - cstart[cellidx[i] - 1]) % S == 0) flags[i] = 1u;
 }
 
 __global__ void bgather_kernel(const float* __restrict__ pts, const uint64_t* __restrict__ keys,
@@ -729,6 +771,7 @@ struct BatchPlan {
     int wide_slots = 0;             // their persistent workgroups
     int picks = 0;                  // most exact picks per round of an object (0: by cell size)
     int wide_blocks = kBatchMaxBlocks;  // blocks at most of the 1024-thread workgroups' objects
+    bool split_cells = false;       // cut uneven cells into runs (see bsplit_kernel)
     hipStream_t side = nullptr;     // stream of the wide launch (forked from the caller's)
     hipEvent_t fork = nullptr, join = nullptr;
     bool use_graph = true;
@@ -970,6 +1013,9 @@ void batch_set_job_io(BatchPlan* p, const std::vector<int32_t*>& order, const st
 size_t batch_workspace_bytes(const BatchPlan* p) { return p ? p->ws_bytes : 0; }
 int64_t batch_total_k(const BatchPlan* p) { return p ? p->total_k : 0; }
 int batch_wide_count(const BatchPlan* p) { return p ? p->nwide : 0; }
+void batch_set_split_cells(BatchPlan* p, bool split) {
+    if (p) p->split_cells = split;
+}
 void batch_set_picks(BatchPlan* p, int picks) {
     if (p) p->picks = picks > 0 ? picks : 0;
 }
@@ -1037,10 +1083,19 @@ int batch_preprocess(BatchPlan* p, const float* pts, int32_t* out_order, float* 
     if (e != hipSuccess) return set_error(BS_ERR_HIP, "sort: %s", hipGetErrorString(e));
     if (sort_only) return BS_OK;
     hipLaunchKernelGGL(bhist_kernel, dim3(nblk), dim3(tb), 0, st, w.keys_s, N, w.hd);
-    hipLaunchKernelGGL(blevel_kernel, dim3(mblk), dim3(tb), 0, st, m, w.offs, w.hd, p->target);
+    hipLaunchKernelGGL(blevel_kernel, dim3(mblk), dim3(tb), 0, st, m, w.offs, w.hd, p->target,
+                       p->split_cells ? 1 : 0);
     hipLaunchKernelGGL(bflag_kernel, dim3(nblk), dim3(tb), 0, st, w.keys_s, N, w.hd, w.flags);
     e = inclusive_scan_u32(w.flags, w.cellidx, N, w.temp, st);
     if (e != hipSuccess) return set_error(BS_ERR_HIP, "scan: %s", hipGetErrorString(e));
+    if (p->split_cells) {
+        hipLaunchKernelGGL(bcstart_kernel, dim3(nblk), dim3(tb), 0, st, w.flags, w.cellidx, N, w.cstart);
+        hipLaunchKernelGGL(bsplit_prep_kernel, dim3(mblk), dim3(tb), 0, st, m, w.offs, w.cellidx, w.hd, p->target);
+        hipLaunchKernelGGL(bsplit_kernel, dim3(nblk), dim3(tb), 0, st, w.keys_s, w.cellidx, N, w.cstart, w.hd,
+                           w.flags);
+        e = inclusive_scan_u32(w.flags, w.cellidx, N, w.temp, st);
+        if (e != hipSuccess) return set_error(BS_ERR_HIP, "scan: %s", hipGetErrorString(e));
+    }
     hipLaunchKernelGGL(bgather_kernel, dim3(nblk), dim3(tb), 0, st, pts, w.keys_s, w.vals_s, w.flags,
                        w.cellidx, N, w.offs, w.starts, w.hd, w.xyzm, w.ids, w.cstart);
     hipLaunchKernelGGL(bobj_fin_kernel, dim3(1), dim3(1024), 0, st, m, w.cellidx, N, w.hd, w.totals);

@@ -279,6 +279,9 @@ int bs_hier_plan_create(int32_t m, const int32_t* h_parent, const int64_t* h_lea
                 free_plan(p);
                 return rc;
             }
+            // an inner node's candidates are its children's surfels, compact
+            // groups whose Morton-prefix cells are uneven: cut them
+            if (&L != &p->levels.front()) batch_set_split_cells(L.plan, true);
             need = batch_workspace_bytes(L.plan);
         }
         p->order_ws = std::max(p->order_ws, need);

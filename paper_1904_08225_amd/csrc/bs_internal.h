@@ -102,6 +102,9 @@ int batch_morton_order(BatchPlan* p, const float* pts, int32_t* out_perm, void* 
 int batch_wide_count(const BatchPlan* p);
 // Most exact picks per round of every object (1..32; 0 = by mean cell size).
 void batch_set_picks(BatchPlan* p, int picks);
+// Cut each object's Morton-prefix cells into runs of bounded length (for
+// candidate sets made of compact groups, whose prefix cells are uneven).
+void batch_set_split_cells(BatchPlan* p, bool split);
 const int64_t* batch_out_offsets(const BatchPlan* p);
 int batch_slots(const BatchPlan* p);
 void batch_set_job_io(BatchPlan* p, const std::vector<int32_t*>& order, const std::vector<float*>& radius,
