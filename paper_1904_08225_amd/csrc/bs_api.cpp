@@ -438,6 +438,9 @@ int bs_batch_plan_create(const int64_t* h_offsets, const int64_t* h_k, const uin
     int rc = batch_plan_create(h_offsets, h_k, h_seed, m, target, tuning ? tuning->batch_wide : 0,
                                tuning ? tuning->groups : 0, &p);
     if (rc == BS_OK) batch_set_picks(p, tuning ? tuning->picks : 0);
+    // bounded cells (same result): on the 1,000-part batch 0.804-0.808 s
+    // against 0.811-0.817 s with plain Morton-prefix cells
+    if (rc == BS_OK) batch_set_split_cells(p, true);
     if (rc == BS_OK) rc = batch_plan_upload(p);
     if (rc != BS_OK) {
         batch_plan_free(p);
