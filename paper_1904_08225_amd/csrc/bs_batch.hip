@@ -266,7 +266,10 @@ __global__ void bsplit_prep_kernel(int m, const int32_t* __restrict__ offs, cons
     const int cells = int(cellidx[b - 1]) - (a > 0 ? int(cellidx[a - 1]) : 0);
     const int cap = int(cell_cap(n, target, hd[j].max_blocks));
     // pieces beyond the first of each cell number at most n / S <= cap - cells
-    if (cap > cells) hd[j].split = max(1, (n + (cap - cells) - 1) / (cap - cells));
+    if (cap > cells) {
+        const int64_t room = int64_t(cap) - cells;
+        hd[j].split = int(max(int64_t(1), (int64_t(n) + room - 1) / room));
+    }
 }
 
 __global__ void bsplit_kernel(const uint64_t* __restrict__ keys, const uint32_t* __restrict__ cellidx, int N,
