@@ -111,6 +111,8 @@ public:
             delete b;
             return rc;
         }
+        // bounded cells: the largest jobs' Morton-prefix cells are uneven
+        batch_set_split_cells(b->plan, true);
         b->candidates = offs.back();
         *bytes = batch_workspace_bytes(b->plan) + align_up(size_t(offs.back()) * 12);
         *batch = b;
